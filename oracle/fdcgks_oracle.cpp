@@ -1,0 +1,1085 @@
+// FD-CGKS oracle: a plain, slow FP64 CPU reference of one S2O4 stage of the
+// finite-difference compact gas-kinetic scheme (Zhao, Chen & Xu, "Finite
+// difference implementation of a high-order space-time coupled compact
+// gas-kinetic scheme").
+//
+// TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+// cpu_baseline leg of bench.py load this library.  It shares no code, header,
+// table or helper with the HIP library; the product path never calls it.
+//
+// Written to be checked against the paper by eye:
+//   * 2D work is done on the half-spacing lattice: a point (I, J) sits at
+//     (x0 + I h/2, y0 + J h/2).  I+J even are nodes (I odd: primary grid,
+//     I even: dual grid), I+J odd are virtual interfaces.  Every line stencil
+//     is then "offsets -3,-1,+1,+3" (interface) or "-2,0,+2" (node) along an
+//     axis, whatever the grid (Sec. 4, dual-grid topology).
+//   * Maxwellian moments are taken monomial by monomial from the moment
+//     recursion (App. A); slopes come from solving the 4x4 (3x3 in 1D) moment
+//     system by Gaussian elimination, not from a closed form.
+//   * The interface distribution f^n is kept as an explicit list of terms
+//     (equilibrium part, non-equilibrium left/right parts) and every macroscopic
+//     quantity is the moment of that list.
+// Readings of passages the paper leaves open are the numbered "D" decisions
+// listed in the design notes; each use below names the decision.
+//
+// The scalar type is a template parameter: double for the reference, Dual for
+// the forward-mode (tangent) reference used to check the adjoint step.
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+namespace orc {
+
+// ---------------------------------------------------------------- scalars
+struct Dual {
+  double v, d;
+  Dual() : v(0), d(0) {}
+  Dual(double a) : v(a), d(0) {}
+  Dual(double a, double b) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+inline Dual& operator*=(Dual& a, Dual b) { a = a * b; return a; }
+inline bool operator<(Dual a, Dual b) { return a.v < b.v; }
+inline bool operator>(Dual a, Dual b) { return a.v > b.v; }
+inline bool operator<=(Dual a, Dual b) { return a.v <= b.v; }
+inline double val(double a) { return a; }
+inline double val(Dual a) { return a.v; }
+inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return Dual(s, a.d / (2 * s)); }
+inline Dual exp(Dual a) { double e = std::exp(a.v); return Dual(e, e * a.d); }
+inline Dual erfc(Dual a) {
+  return Dual(std::erfc(a.v), -2.0 / std::sqrt(M_PI) * std::exp(-a.v * a.v) * a.d);
+}
+inline Dual tanh(Dual a) { double t = std::tanh(a.v); return Dual(t, (1 - t * t) * a.d); }
+// |x|: derivative sign(x), taken as 0 at x == 0 (adjoint convention for ties)
+inline Dual fabs(Dual a) {
+  if (a.v > 0) return a;
+  if (a.v < 0) return -a;
+  return Dual(0.0, 0.0);
+}
+using std::erfc;
+using std::exp;
+using std::fabs;
+using std::sqrt;
+using std::tanh;
+
+template <class T> inline T sq(T a) { return a * a; }
+
+// ------------------------------------------------------------- parameters
+// Field meanings match the library's problem description; the layout is this
+// file's own and is mirrored only by oracle/oracle.py.
+struct Par {
+  int32_t dim, nx, ny, bc, dual_1d, variant, r, grad_carried;
+  double x0, lx, y0, ly;
+  double gamma, mu, prandtl;
+  double C, eps, eps_a, d_central, d_side;
+  double tau_c1, tau_c2;
+};
+enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1 };
+enum { VAR_6_4 = 0, VAR_6_2 = 1, VAR_LINEAR = 2 };
+
+// ------------------------------------------------ GENO reconstruction, Sec. 3
+// GENO blend (Eqs. GENO-nonlinear, GENO-IS-linear, GENO-1d-IS-HL; the
+// low-order weights of Sec. 3.2; App. D).  IS^tau compares the two "other"
+// indicators with IS[ref]:  IS^tau = |(IS_a + IS_b)/2 - IS_ref| written as
+// 0.5 |IS_a + IS_b - 2 IS_ref|.  r and eps are D3/D4, d is D5.
+template <class T>
+void geno_blend(const Par& p, const T IS[3], int ref, const double d[3], const T q[3],
+                const T dq[3], T PH, T PHx, T& val_out, T& der_out, T& chi_out) {
+  int a = (ref + 1) % 3, b = (ref + 2) % 3;
+  T tau = 0.5 * fabs((IS[a] + IS[b]) - 2.0 * IS[ref]);
+  T ISH = IS[0], ISL = IS[0];
+  for (int k = 1; k < 3; ++k) {
+    if (IS[k] > ISH) ISH = IS[k];
+    if (IS[k] < ISL) ISL = IS[k];
+  }
+  T xH = tau / (ISH + p.eps), xL = tau / (ISL + p.eps);
+  T aH = 1.0, aL = 1.0;
+  T pH = 1.0, pL = 1.0;
+  for (int k = 0; k < p.r; ++k) { pH = pH * xH; pL = pL * xL; }
+  aH = aH + pH;
+  aL = aL + pL;
+  T alpha = 2.0 * aH / (aH + aL);
+  T chi = tanh(p.C * alpha) / std::tanh(p.C);
+  T wt[3], s = 0.0;
+  for (int k = 0; k < 3; ++k) { wt[k] = d[k] / sq(IS[k] + p.eps_a); s = s + wt[k]; }
+  T PL = 0.0, PLx = 0.0;
+  for (int k = 0; k < 3; ++k) { PL = PL + (wt[k] / s) * q[k]; PLx = PLx + (wt[k] / s) * dq[k]; }
+  val_out = chi * PH + (1.0 - chi) * PL;
+  der_out = chi * PHx + (1.0 - chi) * PLx;  // same weights for the derivative (D17)
+  chi_out = chi;
+}
+
+// Interface j+1/2 from a line of four nodes.  Q[0..3] = Q_{j-1..j+2} (values),
+// X[0..3] = averaged derivatives Q_{x,j-1..j+2} along the line.
+// High order: Eq. 7th-compact-recons.  Sub-stencils and IS: App. C1 (left),
+// App. C2 (right, whose formulas are for j+1/2: D7).
+template <class T>
+void recon_interface(const Par& p, const T Q[4], const T X[4], double h, T& vl, T& dl, T& cl,
+                     T& vr, T& dr, T& cr) {
+  T PHl = ((7.0 * Q[0] + 35.0 * Q[1] + 21.0 * Q[2] + Q[3]) + (X[0] + 22.0 * X[1] - 7.0 * X[2]) * h) / 64.0;
+  T PHr = ((Q[0] + 21.0 * Q[1] + 35.0 * Q[2] + 7.0 * Q[3]) + (7.0 * X[1] - 22.0 * X[2] - X[3]) * h) / 64.0;
+  T PHx = -((Q[0] + 45.0 * Q[1] - 45.0 * Q[2] - Q[3]) + 9.0 * (X[1] + X[2]) * h) / (30.0 * h);
+  if (p.variant == VAR_LINEAR) {
+    vl = PHl; dl = PHx; cl = 1.0;
+    vr = PHr; dr = PHx; cr = 1.0;
+    return;
+  }
+  // App. C1, left state
+  T ql[3] = {(-5.0 * Q[0] + 9.0 * Q[1] - 3.0 * X[0] * h) / 4.0,
+             (-Q[0] + 6.0 * Q[1] + 3.0 * Q[2]) / 8.0,
+             (3.0 * Q[1] + 6.0 * Q[2] - Q[3]) / 8.0};
+  T dql[3] = {(-3.0 * Q[0] + 3.0 * Q[1] - 2.0 * X[0] * h) / h,
+              (Q[2] - Q[1]) / h,
+              (Q[2] - Q[1]) / h};
+  T ISl[3] = {13.0 / 3.0 * sq(Q[1] - Q[0] - X[0] * h) + sq(2.0 * (Q[1] - Q[0]) - X[0] * h),
+              13.0 / 12.0 * sq(Q[0] - 2.0 * Q[1] + Q[2]) + 0.25 * sq(Q[2] - Q[0]),
+              13.0 / 12.0 * sq(Q[1] - 2.0 * Q[2] + Q[3]) + 0.25 * sq(3.0 * Q[1] - 4.0 * Q[2] + Q[3])};
+  // App. C2, right state
+  T qr[3] = {(-5.0 * Q[3] + 9.0 * Q[2] + 3.0 * X[3] * h) / 4.0,
+             (-Q[3] + 6.0 * Q[2] + 3.0 * Q[1]) / 8.0,
+             (-Q[0] + 6.0 * Q[1] + 3.0 * Q[2]) / 8.0};
+  T dqr[3] = {(-3.0 * Q[2] + 3.0 * Q[3] - 2.0 * X[3] * h) / h,
+              (Q[2] - Q[1]) / h,
+              (Q[2] - Q[1]) / h};
+  T ISr[3] = {13.0 / 3.0 * sq(Q[2] - Q[3] + X[3] * h) + sq(2.0 * (Q[3] - Q[2]) - X[3] * h),
+              13.0 / 12.0 * sq(Q[1] - 2.0 * Q[2] + Q[3]) + 0.25 * sq(Q[3] - Q[1]),
+              13.0 / 12.0 * sq(Q[0] - 2.0 * Q[1] + Q[2]) + 0.25 * sq(3.0 * Q[2] - 4.0 * Q[1] + Q[0])};
+  // D5: App. C numbering at the interface: weight d_central on q_2, IS^tau
+  // referenced to IS_1 (the compact one-sided sub-stencil).
+  const double d[3] = {p.d_side, p.d_central, p.d_side};
+  geno_blend(p, ISl, 0, d, ql, dql, PHl, PHx, vl, dl, cl);
+  geno_blend(p, ISr, 0, d, qr, dqr, PHr, PHx, vr, dr, cr);
+}
+
+// Node j derivative from Q_{j-1..j+1}, X_{j-1..j+1} (Eq. 6th-compact-recons,
+// App. C3).  D5: the central sub-stencil q_3^N carries d_central and is the
+// IS^tau reference.
+template <class T>
+T recon_node(const Par& p, const T Q[3], const T X[3], double h) {
+  T PHx = (9.0 * (Q[0] - Q[2]) + h * (X[0] + 46.0 * X[1] + X[2])) / (30.0 * h);
+  if (p.variant == VAR_LINEAR) return PHx;
+  T dq[3] = {(-2.0 * Q[0] + 2.0 * Q[1] - X[0] * h) / h,
+             (-2.0 * Q[1] + 2.0 * Q[2] - X[2] * h) / h,
+             (Q[2] - Q[0]) / (2.0 * h)};
+  T IS[3] = {13.0 / 3.0 * sq(Q[1] - Q[0] - X[0] * h) + sq(2.0 * (Q[1] - Q[0]) - X[0] * h),
+             13.0 / 3.0 * sq(Q[2] - Q[1] - X[2] * h) + sq(2.0 * (Q[2] - Q[1]) - X[2] * h),
+             13.0 / 12.0 * sq(Q[0] - 2.0 * Q[1] + Q[2]) + 0.25 * sq(Q[2] - Q[0])};
+  const double d[3] = {p.d_side, p.d_side, p.d_central};
+  T q0[3] = {Q[1], Q[1], Q[1]};  // values are not reconstructed at nodes (P^5(x_j) = Q_j)
+  T v, der, chi;
+  geno_blend(p, IS, 2, d, q0, dq, Q[1], PHx, v, der, chi);
+  return der;
+}
+
+// ----------------------------------------------- Maxwellian moments, App. A
+// Polynomials in (u, v, xi^2): sum of k * u^a v^b (xi^2)^c.
+template <class T> struct Poly {
+  int n = 0;
+  int a[96], b[96], c[96];
+  T k[96];
+  void add(int aa, int bb, int cc, T kk) {
+    for (int i = 0; i < n; ++i)
+      if (a[i] == aa && b[i] == bb && c[i] == cc) { k[i] = k[i] + kk; return; }
+    a[n] = aa; b[n] = bb; c[n] = cc; k[n] = kk; ++n;
+  }
+};
+template <class T> Poly<T> pmul(const Poly<T>& P, const Poly<T>& Q) {
+  Poly<T> R;
+  for (int i = 0; i < P.n; ++i)
+    for (int j = 0; j < Q.n; ++j) R.add(P.a[i] + Q.a[j], P.b[i] + Q.b[j], P.c[i] + Q.c[j], P.k[i] * Q.k[j]);
+  return R;
+}
+template <class T> Poly<T> padd(const Poly<T>& P, const Poly<T>& Q, T sq_ = T(1.0)) {
+  Poly<T> R = P;
+  for (int j = 0; j < Q.n; ++j) R.add(Q.a[j], Q.b[j], Q.c[j], sq_ * Q.k[j]);
+  return R;
+}
+template <class T> Poly<T> pconst(T k) { Poly<T> R; R.add(0, 0, 0, k); return R; }
+template <class T> Poly<T> pmono(int a, int b, int c, T k) { Poly<T> R; R.add(a, b, c, k); return R; }
+
+// Collision invariants psi (App. A1): 2D (1, u, v, (u^2+v^2+xi^2)/2);
+// 1D (1, u, (u^2+xi^2)/2).
+template <class T> Poly<T> ppsi(int i, int dim) {
+  Poly<T> R;
+  int last = dim + 1;
+  if (i == 0) R.add(0, 0, 0, T(1.0));
+  else if (i == 1) R.add(1, 0, 0, T(1.0));
+  else if (i == 2 && dim == 2) R.add(0, 1, 0, T(1.0));
+  else if (i == last) {
+    R.add(2, 0, 0, T(0.5));
+    if (dim == 2) R.add(0, 2, 0, T(0.5));
+    R.add(0, 0, 1, T(0.5));
+  }
+  return R;
+}
+// s . psi
+template <class T> Poly<T> pslope(const T* s, int dim) {
+  Poly<T> R;
+  for (int i = 0; i < dim + 2; ++i) R = padd(R, ppsi<T>(i, dim), s[i]);
+  return R;
+}
+
+// Normalised moments of a Maxwellian (per unit density): <u^n> over the full
+// line or a half line, <v^n> over the full line, <xi^(2k)>.
+template <class T> struct Maxw {
+  T mu[10], mv[10], mx[3];
+};
+template <class T> Maxw<T> maxwell(T U, T V, T lam, double K, int half, int dim) {
+  Maxw<T> m;
+  T sl = sqrt(lam);
+  if (half == 0) {
+    m.mu[0] = 1.0;
+    m.mu[1] = U;
+  } else {
+    T e = exp(-lam * U * U) / (2.0 * sqrt(M_PI * lam));
+    if (half > 0) { m.mu[0] = 0.5 * erfc(-sl * U); m.mu[1] = U * m.mu[0] + e; }
+    else { m.mu[0] = 0.5 * erfc(sl * U); m.mu[1] = U * m.mu[0] - e; }
+  }
+  for (int k = 0; k + 2 < 10; ++k) m.mu[k + 2] = U * m.mu[k + 1] + (k + 1) / (2.0 * lam) * m.mu[k];
+  m.mv[0] = 1.0;
+  m.mv[1] = (dim == 2) ? V : T(0.0);
+  for (int k = 0; k + 2 < 10; ++k) m.mv[k + 2] = m.mv[1] * m.mv[k + 1] + (k + 1) / (2.0 * lam) * m.mv[k];
+  if (dim == 1) for (int k = 1; k < 10; ++k) m.mv[k] = 0.0;  // no v in 1D: only b = 0 occurs
+  m.mx[0] = 1.0;
+  m.mx[1] = K / (2.0 * lam);
+  m.mx[2] = K * (K + 2.0) / (4.0 * lam * lam);
+  return m;
+}
+template <class T> T avg(const Maxw<T>& m, const Poly<T>& P) {
+  T s = 0.0;
+  for (int i = 0; i < P.n; ++i) s = s + P.k[i] * m.mu[P.a[i]] * m.mv[P.b[i]] * m.mx[P.c[i]];
+  return s;
+}
+
+// Internal degrees of freedom from gamma (D22).
+inline double kdof(double gamma, int dim) {
+  return dim == 2 ? (4.0 - 2.0 * gamma) / (gamma - 1.0) : (3.0 - gamma) / (gamma - 1.0);
+}
+
+template <class T> struct Prim { T rho, U, V, p, lam; };
+template <class T> Prim<T> prim(const T* W, int dim, double gamma) {
+  Prim<T> s;
+  s.rho = W[0];
+  s.U = W[1] / W[0];
+  s.V = dim == 2 ? W[2] / W[0] : T(0.0);
+  T rE = W[dim + 1];
+  s.p = (gamma - 1.0) * (rE - 0.5 * s.rho * (s.U * s.U + s.V * s.V));
+  s.lam = s.rho / (2.0 * s.p);
+  return s;
+}
+
+// Solve the moment system  <psi_i (s . psi)> = D_i / rho  for the micro slope s
+// (App. A; Xu's BGK-NS scheme), by Gaussian elimination with partial pivoting.
+template <class T> void slope(const Maxw<T>& full, T rho, const T* D, int dim, T* s) {
+  int n = dim + 2;
+  T A[4][5];
+  for (int i = 0; i < n; ++i) {
+    for (int k = 0; k < n; ++k) A[i][k] = avg(full, pmul(ppsi<T>(i, dim), ppsi<T>(k, dim)));
+    A[i][n] = D[i] / rho;
+  }
+  for (int c = 0; c < n; ++c) {
+    int piv = c;
+    for (int r2 = c + 1; r2 < n; ++r2)
+      if (std::fabs(val(A[r2][c])) > std::fabs(val(A[piv][c]))) piv = r2;
+    if (piv != c) for (int k = 0; k <= n; ++k) std::swap(A[c][k], A[piv][k]);
+    for (int r2 = c + 1; r2 < n; ++r2) {
+      T f = A[r2][c] / A[c][c];
+      for (int k = c; k <= n; ++k) A[r2][k] = A[r2][k] - f * A[c][k];
+    }
+  }
+  for (int c = n - 1; c >= 0; --c) {
+    T acc = A[c][n];
+    for (int k = c + 1; k < n; ++k) acc = acc - A[c][k] * s[k];
+    s[c] = acc / A[c][c];
+  }
+}
+
+// ------------------------------------------- gas-kinetic interface solver
+// One interface in its local frame: the normal velocity is u; in 2D the
+// tangential velocity is v.  Inputs: reconstructed left/right states, their
+// normal slopes, the tangential slope (2D), the step dt.  App. A1-A2 and the
+// BGK-NS solution it cites, with decisions D10-D14, D21.
+template <class T> struct GksOut {
+  T F[4], Ft[4], We[4], Wet[4], Wl[4], Wr[4], Wlt[4], Wrt[4];
+  T tau;
+};
+
+// Integrated time coefficients of the BGK integral solution over [0, T]
+// (equilibrium g0, its spatial slope term, its time slope term, the initial
+// non-equilibrium part, and its slope term).
+template <class T> void qcoef(T Tt, T tau, T q[5]) {
+  T E = exp(-Tt / tau);
+  q[0] = Tt - tau * (1.0 - E);
+  q[1] = tau * ((2.0 * tau - Tt) - (Tt + 2.0 * tau) * E);
+  q[2] = 0.5 * Tt * Tt - tau * Tt + tau * tau * (1.0 - E);
+  q[3] = tau * (1.0 - E);
+  q[4] = tau * ((Tt + 2.0 * tau) * E - 2.0 * tau);
+}
+
+template <class T> struct Term { int state; int k; Poly<T> P; };
+
+template <class T>
+void gks_interface(const Par& p, int dim, const T* WL, const T* WR, const T* WnL, const T* WnR,
+                   const T* Wt, double dt, GksOut<T>& o) {
+  const int n = dim + 2;
+  const double g = p.gamma, K = kdof(g, dim);
+  Prim<T> sl = prim(WL, dim, g), sr = prim(WR, dim, g);
+  Maxw<T> mlh = maxwell(sl.U, sl.V, sl.lam, K, +1, dim), mlf = maxwell(sl.U, sl.V, sl.lam, K, 0, dim);
+  Maxw<T> mrh = maxwell(sr.U, sr.V, sr.lam, K, -1, dim), mrf = maxwell(sr.U, sr.V, sr.lam, K, 0, dim);
+  // compatibility (equilibrium) state at the interface
+  T W0[4];
+  for (int i = 0; i < n; ++i)
+    W0[i] = sl.rho * avg(mlh, ppsi<T>(i, dim)) + sr.rho * avg(mrh, ppsi<T>(i, dim));
+  Prim<T> s0 = prim(W0, dim, g);
+  Maxw<T> m0 = maxwell(s0.U, s0.V, s0.lam, K, 0, dim);
+  // spatial micro slopes (normal a, tangential b); D12 for the equilibrium
+  T zero[4] = {0, 0, 0, 0};
+  T aL[4], aR[4], bL[4] = {0, 0, 0, 0}, bR[4] = {0, 0, 0, 0}, a0[4], b0[4] = {0, 0, 0, 0};
+  slope(mlf, sl.rho, WnL, dim, aL);
+  slope(mrf, sr.rho, WnR, dim, aR);
+  T Wn0[4];
+  for (int i = 0; i < n; ++i) Wn0[i] = 0.5 * (WnL[i] + WnR[i]);
+  slope(m0, s0.rho, Wn0, dim, a0);
+  if (dim == 2) {
+    slope(mlf, sl.rho, Wt, dim, bL);
+    slope(mrf, sr.rho, Wt, dim, bR);
+    slope(m0, s0.rho, Wt, dim, b0);
+  }
+  (void)zero;
+  Poly<T> u1 = pmono<T>(1, 0, 0, 1.0), v1 = pmono<T>(0, 1, 0, 1.0);
+  auto transport = [&](const T* a, const T* b) {  // (a.psi) u + (b.psi) v
+    Poly<T> P = pmul(pslope(a, dim), u1);
+    if (dim == 2) P = padd(P, pmul(pslope(b, dim), v1));
+    return P;
+  };
+  Poly<T> trL = transport(aL, bL), trR = transport(aR, bR), tr0 = transport(a0, b0);
+  // time slopes from compatibility: <psi (A.psi)> = -<psi ((a.psi)u + (b.psi)v)>
+  T AL[4], AR[4], A0[4], rhsL[4], rhsR[4], rhs0[4];
+  for (int i = 0; i < n; ++i) {
+    rhsL[i] = -sl.rho * avg(mlf, pmul(ppsi<T>(i, dim), trL));
+    rhsR[i] = -sr.rho * avg(mrf, pmul(ppsi<T>(i, dim), trR));
+    rhs0[i] = -s0.rho * avg(m0, pmul(ppsi<T>(i, dim), tr0));
+  }
+  slope(mlf, sl.rho, rhsL, dim, AL);
+  slope(mrf, sr.rho, rhsR, dim, AR);
+  slope(m0, s0.rho, rhs0, dim, A0);
+  // collision time (D11) and the f^n, f_t^n fit of App. A1
+  T tau = (p.mu > 0 ? T(p.mu) / s0.p : T(p.tau_c1 * dt)) +
+          p.tau_c2 * dt * fabs(sl.p - sr.p) / (sl.p + sr.p);
+  T qh[5], qf[5], c[5], ct[5];
+  qcoef(T(0.5 * dt), tau, qh);
+  qcoef(T(dt), tau, qf);
+  for (int k = 0; k < 5; ++k) {
+    c[k] = (4.0 * qh[k] - qf[k]) / dt;
+    ct[k] = 4.0 * (qf[k] - 2.0 * qh[k]) / (dt * dt);
+  }
+  // the terms of f^n (coefficient index k into c / ct)
+  std::vector<Term<T>> terms;
+  terms.push_back({0, 0, pconst<T>(1.0)});
+  terms.push_back({0, 1, tr0});
+  terms.push_back({0, 2, pslope(A0, dim)});
+  terms.push_back({1, 3, padd(pconst<T>(1.0), pslope(AL, dim), -tau)});
+  terms.push_back({1, 4, trL});
+  terms.push_back({2, 3, padd(pconst<T>(1.0), pslope(AR, dim), -tau)});
+  terms.push_back({2, 4, trR});
+  auto moment = [&](const Poly<T>& phi, const T* coef) {
+    T s = 0.0;
+    for (auto& t : terms) {
+      const Maxw<T>& m = t.state == 0 ? m0 : (t.state == 1 ? mlh : mrh);
+      T rho = t.state == 0 ? s0.rho : (t.state == 1 ? sl.rho : sr.rho);
+      s = s + coef[t.k] * rho * avg(m, pmul(phi, t.P));
+    }
+    return s;
+  };
+  for (int i = 0; i < n; ++i) {
+    Poly<T> psi = ppsi<T>(i, dim), upsi = pmul(u1, psi);
+    o.F[i] = moment(upsi, c);
+    o.Ft[i] = moment(upsi, ct);
+    o.We[i] = moment(psi, c);
+    o.Wet[i] = moment(psi, ct);
+  }
+  // Prandtl-number fix of the energy flux (D21): (1/Pr - 1) times the heat
+  // flux 1/2 <(u-U0)((u-U0)^2 + (v-V0)^2 + xi^2)> of the same distribution.
+  if (p.mu > 0) {
+    Poly<T> du = padd(u1, pconst<T>(-s0.U)), c2 = pmul(du, du);
+    if (dim == 2) { Poly<T> dv = padd(v1, pconst<T>(-s0.V)); c2 = padd(c2, pmul(dv, dv)); }
+    c2 = padd(c2, pmono<T>(0, 0, 1, 1.0));
+    Poly<T> hq = pmul(pmul(du, c2), pconst<T>(0.5));
+    double f = 1.0 / p.prandtl - 1.0;
+    o.F[n - 1] = o.F[n - 1] + f * moment(hq, c);
+    o.Ft[n - 1] = o.Ft[n - 1] + f * moment(hq, ct);
+  }
+  // interface values for the gradient update (Eq. W-model, D10, D13)
+  T e = exp(-T(dt) / tau);
+  for (int i = 0; i < n; ++i) {
+    T WtL = rhsL[i], WtR = rhsR[i];  // one-sided Euler time derivatives (D13)
+    o.Wl[i] = (1.0 - e) * o.We[i] + e * WL[i];
+    o.Wr[i] = (1.0 - e) * o.We[i] + e * WR[i];
+    o.Wlt[i] = (1.0 - e) * o.Wet[i] + e * WtL;
+    o.Wrt[i] = (1.0 - e) * o.Wet[i] + e * WtR;
+  }
+  o.tau = tau;
+}
+
+// Smooth nodal flux (Sec. 2.1: smooth nodal values; D11: tau_N = mu/p):
+// f^n = g [1 - tau_N ((a.psi)u + (b.psi)v + A.psi)], f_t^n = (A.psi) g.
+// Outputs the x- (and in 2D y-) flux and their time derivatives.
+template <class T>
+void gks_node(const Par& p, int dim, const T* W, const T* Wx, const T* Wy, T* F, T* Ft, T* G, T* Gt) {
+  const int n = dim + 2;
+  const double g = p.gamma, K = kdof(g, dim);
+  Prim<T> s = prim(W, dim, g);
+  Maxw<T> m = maxwell(s.U, s.V, s.lam, K, 0, dim);
+  T a[4], b[4] = {0, 0, 0, 0}, A[4], rhs[4];
+  slope(m, s.rho, Wx, dim, a);
+  if (dim == 2) slope(m, s.rho, Wy, dim, b);
+  Poly<T> u1 = pmono<T>(1, 0, 0, 1.0), v1 = pmono<T>(0, 1, 0, 1.0);
+  Poly<T> tr = pmul(pslope(a, dim), u1);
+  if (dim == 2) tr = padd(tr, pmul(pslope(b, dim), v1));
+  for (int i = 0; i < n; ++i) rhs[i] = -s.rho * avg(m, pmul(ppsi<T>(i, dim), tr));
+  slope(m, s.rho, rhs, dim, A);
+  T tauN = p.mu > 0 ? T(p.mu) / s.p : T(0.0);
+  Poly<T> fn = padd(pconst<T>(1.0), padd(tr, pslope(A, dim)), -tauN);
+  Poly<T> ft = pslope(A, dim);
+  for (int i = 0; i < n; ++i) {
+    Poly<T> psi = ppsi<T>(i, dim);
+    F[i] = s.rho * avg(m, pmul(pmul(u1, psi), fn));
+    Ft[i] = s.rho * avg(m, pmul(pmul(u1, psi), ft));
+    if (dim == 2) {
+      G[i] = s.rho * avg(m, pmul(pmul(v1, psi), fn));
+      Gt[i] = s.rho * avg(m, pmul(pmul(v1, psi), ft));
+    }
+  }
+  if (p.mu > 0) {  // Prandtl fix (D21) with the node's own velocity
+    double f = 1.0 / p.prandtl - 1.0;
+    Poly<T> du = padd(u1, pconst<T>(-s.U)), dv = padd(v1, pconst<T>(-s.V));
+    Poly<T> c2 = pmul(du, du);
+    if (dim == 2) c2 = padd(c2, pmul(dv, dv));
+    c2 = padd(c2, pmono<T>(0, 0, 1, 1.0));
+    Poly<T> qx = pmul(pmul(du, c2), pconst<T>(0.5));
+    F[n - 1] = F[n - 1] + f * s.rho * avg(m, pmul(qx, fn));
+    Ft[n - 1] = Ft[n - 1] + f * s.rho * avg(m, pmul(qx, ft));
+    if (dim == 2) {
+      Poly<T> qy = pmul(pmul(dv, c2), pconst<T>(0.5));
+      G[n - 1] = G[n - 1] + f * s.rho * avg(m, pmul(qy, fn));
+      Gt[n - 1] = Gt[n - 1] + f * s.rho * avg(m, pmul(qy, ft));
+    }
+  }
+}
+
+// --------------------------------------------- compact flux, Sec. 2.1-2.2
+// Fm, Fc, Fp: interface fluxes at j-1/2, j+1/2, j+3/2; N0, N1: nodal fluxes at
+// j, j+1; chi: the interface path function.  Eq. fd-conservative-flux, and
+// (6-4) with the low-order term divided by 6 (D1) or (6-2).
+template <class T> T compact_flux(const Par& p, T Fm, T Fc, T Fp, T N0, T N1, T chi) {
+  T Fbar = ((Fm + 46.0 * Fc + Fp) - 9.0 * (N0 + N1)) / 30.0;
+  if (p.variant == VAR_LINEAR) return Fbar;
+  if (p.variant == VAR_6_2) return (1.0 - chi) * Fc + chi * Fbar;
+  return (1.0 - chi) * ((8.0 * Fc - N0 - N1) / 6.0) + chi * Fbar;
+}
+
+// ================================================================ 2D grids
+// State arrays: 12 planes of ny*nx doubles per grid, fields W[0..3],
+// Wx[0..3], Wy[0..3], x fastest.  P[j][i] at (x0+(i+1/2)h, y0+(j+1/2)h);
+// D[j][i] at (x0+(i+1)h, y0+(j+1)h); both periodic.
+template <class T> struct Grid2 {
+  int nx, ny;
+  const T* P;
+  const T* D;
+  long plane() const { return (long)nx * ny; }
+  static int md(int a, int m) { return ((a % m) + m) % m; }
+  // node at lattice point (I, J) with I+J even: grid and flat index
+  const T* node(int I, int J, long& k) const {
+    I = md(I, 2 * nx); J = md(J, 2 * ny);
+    if (I & 1) { k = (long)((J - 1) / 2) * nx + (I - 1) / 2; return P; }
+    int i = md(I / 2 - 1, nx), j = md(J / 2 - 1, ny);
+    k = (long)j * nx + i;
+    return D;
+  }
+  T W(int I, int J, int c) const { long k; const T* b = node(I, J, k); return b[c * plane() + k]; }
+  T Wx(int I, int J, int c) const { long k; const T* b = node(I, J, k); return b[(4 + c) * plane() + k]; }
+  T Wy(int I, int J, int c) const { long k; const T* b = node(I, J, k); return b[(8 + c) * plane() + k]; }
+};
+
+// What one virtual interface gives, per normal axis (0: x, 1: y).
+template <class T> struct EdgeRes {
+  T F[2][4], Ft[2][4], chi[2];
+  T Wtl[2][4], Wtr[2][4], Wtlt[2][4], Wtrt[2][4];  // blended interface values (Eq. W-model-2d)
+};
+
+// Everything at interface point (I, J), I+J odd.  Sec. 4 items 1(a)-(b),
+// App. A3, D30.
+template <class T> EdgeRes<T> edge2d(const Par& p, const Grid2<T>& G, int I, int J, double h, double dt) {
+  EdgeRes<T> E;
+  // line reconstructions: along x (nodes I-3, I-1, I+1, I+3) and along y
+  T Wl[2][4], Wr[2][4], Dl[2][4], Dr[2][4], cl[2][4], cr[2][4];
+  for (int ax = 0; ax < 2; ++ax)
+    for (int c = 0; c < 4; ++c) {
+      T Q[4], X[4];
+      for (int m = 0; m < 4; ++m) {
+        int o = 2 * m - 3;
+        int Ii = ax == 0 ? I + o : I, Jj = ax == 0 ? J : J + o;
+        Q[m] = G.W(Ii, Jj, c);
+        X[m] = ax == 0 ? G.Wx(Ii, Jj, c) : G.Wy(Ii, Jj, c);
+      }
+      recon_interface(p, Q, X, h, Wl[ax][c], Dl[ax][c], cl[ax][c], Wr[ax][c], Dr[ax][c], cr[ax][c]);
+    }
+  GksOut<T> o[2];
+  for (int ax = 0; ax < 2; ++ax) {
+    int bx = 1 - ax;
+    // tangential slope: average of the other line's l/r derivatives (Sec. 4
+    // item 1(b) for one normal; D30 for the other)
+    T Wt[4];
+    for (int c = 0; c < 4; ++c) Wt[c] = 0.5 * (Dl[bx][c] + Dr[bx][c]);
+    // local frame: the normal momentum is component 1 (swap rho U, rho V for y)
+    T L[4], R[4], nL[4], nR[4], tt[4];
+    int perm[4] = {0, 1, 2, 3};
+    if (ax == 1) { perm[1] = 2; perm[2] = 1; }
+    for (int c = 0; c < 4; ++c) {
+      L[c] = Wl[ax][perm[c]]; R[c] = Wr[ax][perm[c]];
+      nL[c] = Dl[ax][perm[c]]; nR[c] = Dr[ax][perm[c]]; tt[c] = Wt[perm[c]];
+    }
+    GksOut<T> loc;
+    gks_interface(p, 2, L, R, nL, nR, tt, dt, loc);
+    for (int c = 0; c < 4; ++c) {
+      int q = perm[c];
+      o[ax].F[q] = loc.F[c]; o[ax].Ft[q] = loc.Ft[c];
+      o[ax].Wl[q] = loc.Wl[c]; o[ax].Wr[q] = loc.Wr[c];
+      o[ax].Wlt[q] = loc.Wlt[c]; o[ax].Wrt[q] = loc.Wrt[c];
+    }
+    E.chi[ax] = std::min(val(cl[ax][0]), val(cr[ax][0])) == val(cl[ax][0]) ? cl[ax][0] : cr[ax][0];
+  }
+  for (int ax = 0; ax < 2; ++ax) {
+    int bx = 1 - ax;
+    for (int c = 0; c < 4; ++c) {
+      E.F[ax][c] = o[ax].F[c];
+      E.Ft[ax][c] = o[ax].Ft[c];
+      T s = o[bx].Wl[c] + o[bx].Wr[c], st = o[bx].Wlt[c] + o[bx].Wrt[c];
+      E.Wtl[ax][c] = 0.5 * o[ax].Wl[c] + 0.25 * s;
+      E.Wtr[ax][c] = 0.5 * o[ax].Wr[c] + 0.25 * s;
+      E.Wtlt[ax][c] = 0.5 * o[ax].Wlt[c] + 0.25 * st;
+      E.Wtrt[ax][c] = 0.5 * o[ax].Wrt[c] + 0.25 * st;
+    }
+  }
+  return E;
+}
+
+// Nodal fluxes at node (I, J): 3-point derivative reconstructions along x and
+// y (Sec. 4 item 2, App. C3), then the smooth nodal GKS.
+template <class T> struct NodeRes { T F[4], Ft[4], G[4], Gt[4]; };
+template <class T> NodeRes<T> node2d(const Par& p, const Grid2<T>& G, int I, int J, double h) {
+  T W[4], Wx[4], Wy[4];
+  for (int c = 0; c < 4; ++c) {
+    T Q[3], X[3];
+    for (int m = 0; m < 3; ++m) { Q[m] = G.W(I + 2 * m - 2, J, c); X[m] = G.Wx(I + 2 * m - 2, J, c); }
+    Wx[c] = recon_node(p, Q, X, h);
+    for (int m = 0; m < 3; ++m) { Q[m] = G.W(I, J + 2 * m - 2, c); X[m] = G.Wy(I, J + 2 * m - 2, c); }
+    Wy[c] = recon_node(p, Q, X, h);
+    W[c] = G.W(I, J, c);
+  }
+  NodeRes<T> R;
+  gks_node(p, 2, W, Wx, Wy, R.F, R.Ft, R.G, R.Gt);
+  return R;
+}
+
+// Edge / node result storage indexed by lattice point.
+template <class T> struct Store2 {
+  int nx, ny;
+  std::vector<EdgeRes<T>> X, Y;  // X[j][i] at (2i+2, 2j+1); Y[j][i] at (2i+1, 2j+2)
+  std::vector<NodeRes<T>> P, D;
+  static int md(int a, int m) { return ((a % m) + m) % m; }
+  const EdgeRes<T>& edge(int I, int J) const {
+    I = md(I, 2 * nx); J = md(J, 2 * ny);
+    if ((I & 1) == 0) return X[(long)((J - 1) / 2) * nx + md(I / 2 - 1, nx)];
+    return Y[(long)md(J / 2 - 1, ny) * nx + (I - 1) / 2];
+  }
+  const NodeRes<T>& nodeR(int I, int J) const {
+    I = md(I, 2 * nx); J = md(J, 2 * ny);
+    if (I & 1) return P[(long)((J - 1) / 2) * nx + (I - 1) / 2];
+    return D[(long)md(J / 2 - 1, ny) * nx + md(I / 2 - 1, nx)];
+  }
+};
+
+// Stage operator at node (I, J): L, L_t (Eq. eq-conservation-law-2d with the
+// compact flux) and the re-evaluated averaged gradients and their time
+// derivatives (Eq. define-averaged-gradient with the blended interface values,
+// D15).
+template <class T> struct NodeOp { T L[4], Lt[4], Gx[4], Gy[4], Gxt[4], Gyt[4]; };
+
+template <class T, class EdgeF, class NodeF>
+NodeOp<T> node_operator(const Par& p, int I, int J, double h, EdgeF edge, NodeF nodef) {
+  NodeOp<T> r;
+  for (int c = 0; c < 4; ++c) { r.L[c] = 0.0; r.Lt[c] = 0.0; }
+  for (int ax = 0; ax < 2; ++ax) {
+    int dI = ax == 0 ? 1 : 0, dJ = ax == 0 ? 0 : 1;
+    const EdgeRes<T>& em3 = edge(I - 3 * dI, J - 3 * dJ);
+    const EdgeRes<T>& em1 = edge(I - dI, J - dJ);
+    const EdgeRes<T>& ep1 = edge(I + dI, J + dJ);
+    const EdgeRes<T>& ep3 = edge(I + 3 * dI, J + 3 * dJ);
+    const NodeRes<T>& nm = nodef(I - 2 * dI, J - 2 * dJ);
+    const NodeRes<T>& n0 = nodef(I, J);
+    const NodeRes<T>& np = nodef(I + 2 * dI, J + 2 * dJ);
+    for (int c = 0; c < 4; ++c) {
+      T Nm = ax == 0 ? nm.F[c] : nm.G[c], N0 = ax == 0 ? n0.F[c] : n0.G[c], Np = ax == 0 ? np.F[c] : np.G[c];
+      T Nmt = ax == 0 ? nm.Ft[c] : nm.Gt[c], N0t = ax == 0 ? n0.Ft[c] : n0.Gt[c], Npt = ax == 0 ? np.Ft[c] : np.Gt[c];
+      T FR = compact_flux(p, em1.F[ax][c], ep1.F[ax][c], ep3.F[ax][c], N0, Np, ep1.chi[ax]);
+      T FL = compact_flux(p, em3.F[ax][c], em1.F[ax][c], ep1.F[ax][c], Nm, N0, em1.chi[ax]);
+      T FRt = compact_flux(p, em1.Ft[ax][c], ep1.Ft[ax][c], ep3.Ft[ax][c], N0t, Npt, ep1.chi[ax]);
+      T FLt = compact_flux(p, em3.Ft[ax][c], em1.Ft[ax][c], ep1.Ft[ax][c], Nmt, N0t, em1.chi[ax]);
+      r.L[c] = r.L[c] - (FR - FL) / h;
+      r.Lt[c] = r.Lt[c] - (FRt - FLt) / h;
+      T g = (ep1.Wtl[ax][c] - em1.Wtr[ax][c]) / h;
+      T gt = (ep1.Wtlt[ax][c] - em1.Wtrt[ax][c]) / h;
+      if (ax == 0) { r.Gx[c] = g; r.Gxt[c] = gt; } else { r.Gy[c] = g; r.Gyt[c] = gt; }
+    }
+  }
+  return r;
+}
+
+// S2O4 (Eqs. eq-nodal-update, eq-interface-update; D8, D9).  Stage 1 returns
+// W*, grad W*, and the accumulators acc_W = W + dt L + dt^2/6 L_t and
+// acc_grad = grad W^n (re-evaluated); stage 2 returns W^{n+1}, grad W^{n+1}.
+// st: 12 state values (W, Wx, Wy); acc: 12 accumulator values.
+// With grad_carried the stored gradient replaces the re-evaluated one as the
+// base of the gradient update (the alternative reading of D9).
+template <class T>
+void s2o4(int stage, double dt, const NodeOp<T>& op, const T* st, const T* acc, T* out, T* acc_out,
+          int carried = 0) {
+  for (int c = 0; c < 4; ++c) {
+    if (stage == 1) {
+      T gx = carried ? st[4 + c] : op.Gx[c], gy = carried ? st[8 + c] : op.Gy[c];
+      out[c] = st[c] + 0.5 * dt * op.L[c] + 0.125 * dt * dt * op.Lt[c];
+      out[4 + c] = gx + 0.5 * dt * op.Gxt[c];
+      out[8 + c] = gy + 0.5 * dt * op.Gyt[c];
+      acc_out[c] = st[c] + dt * op.L[c] + dt * dt / 6.0 * op.Lt[c];
+      acc_out[4 + c] = gx;
+      acc_out[8 + c] = gy;
+    } else {
+      out[c] = acc[c] + dt * dt / 3.0 * op.Lt[c];
+      out[4 + c] = acc[4 + c] + dt * op.Gxt[c];
+      out[8 + c] = acc[8 + c] + dt * op.Gyt[c];
+    }
+  }
+}
+
+template <class T>
+void stage2d(const Par& p, int stage, double dt, const T* P, const T* D, const T* accP, const T* accD,
+             T* outP, T* outD, T* outAccP, T* outAccD, Store2<T>* keep = nullptr) {
+  const int nx = p.nx, ny = p.ny;
+  const double h = p.lx / nx;
+  Grid2<T> G{nx, ny, P, D};
+  Store2<T> S;
+  S.nx = nx; S.ny = ny;
+  S.X.resize((size_t)nx * ny); S.Y.resize((size_t)nx * ny);
+  S.P.resize((size_t)nx * ny); S.D.resize((size_t)nx * ny);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      long k = (long)j * nx + i;
+      S.X[k] = edge2d(p, G, 2 * i + 2, 2 * j + 1, h, dt);
+      S.Y[k] = edge2d(p, G, 2 * i + 1, 2 * j + 2, h, dt);
+      S.P[k] = node2d(p, G, 2 * i + 1, 2 * j + 1, h);
+      S.D[k] = node2d(p, G, 2 * i + 2, 2 * j + 2, h);
+    }
+  const long pl = (long)nx * ny;
+  auto edgef = [&](int I, int J) -> const EdgeRes<T>& { return S.edge(I, J); };
+  auto nodef = [&](int I, int J) -> const NodeRes<T>& { return S.nodeR(I, J); };
+#pragma omp parallel for schedule(static)
+  for (int j = 0; j < ny; ++j)
+    for (int i = 0; i < nx; ++i) {
+      long k = (long)j * nx + i;
+      for (int g = 0; g < 2; ++g) {
+        int I = g == 0 ? 2 * i + 1 : 2 * i + 2, J = g == 0 ? 2 * j + 1 : 2 * j + 2;
+        NodeOp<T> op = node_operator<T>(p, I, J, h, edgef, nodef);
+        const T* src = g == 0 ? P : D;
+        const T* acc = g == 0 ? accP : accD;
+        T st[12], ac[12], out[12], aout[12];
+        for (int f = 0; f < 12; ++f) { st[f] = src[f * pl + k]; ac[f] = acc ? acc[f * pl + k] : T(0.0); }
+        s2o4(stage, dt, op, st, ac, out, aout, p.grad_carried);
+        T* o = g == 0 ? outP : outD;
+        T* ao = g == 0 ? outAccP : outAccD;
+        for (int f = 0; f < 12; ++f) {
+          o[f * pl + k] = out[f];
+          if (stage == 1 && ao) ao[f * pl + k] = aout[f];
+        }
+      }
+    }
+  if (keep) *keep = std::move(S);
+}
+
+// CFL time step (Sec. 5, D20): dt = CFL h / max(max(|U|,|V|) + c); with
+// viscosity also dt <= CFL h^2 / (8 nu_max), nu_max = mu / rho_min.
+inline double dt_from(const Par& p, double smax, double rmin, double h, double cfl) {
+  double dt = cfl * h / smax;
+  if (p.mu > 0) dt = std::min(dt, cfl * h * h / (8.0 * p.mu / rmin));
+  return dt;
+}
+inline void speed_scan(const Par& p, int dim, const double* W, long plane, long n, double& smax, double& rmin) {
+  for (long k = 0; k < n; ++k) {
+    double w[4];
+    for (int c = 0; c < dim + 2; ++c) w[c] = W[c * plane + k];
+    Prim<double> s = prim(w, dim, p.gamma);
+    double cs = std::sqrt(p.gamma * s.p / s.rho);
+    double vmax = dim == 2 ? std::max(std::fabs(s.U), std::fabs(s.V)) : std::fabs(s.U);
+    smax = std::max(smax, vmax + cs);
+    rmin = std::min(rmin, s.rho);
+  }
+}
+
+// ================================================================ 1D lines
+// A line holds 2*N planes... fields W[0..2], Wx[0..2] of N nodes at
+// x0 + (j + 1/2) h (primary) or x0 + (j + 1) h (the shifted copy, D24).
+// Ghosts: 3 per side, periodic or zero-gradient (D29).
+template <class T> struct Line1 {
+  int N, bc;
+  std::vector<T> W[3], X[3];  // with 3 ghosts on each side: index j + 3
+  void load(const T* S, int n, int bcond) {
+    N = n; bc = bcond;
+    for (int c = 0; c < 3; ++c) {
+      W[c].assign(N + 6, T(0.0)); X[c].assign(N + 6, T(0.0));
+      for (int j = 0; j < N; ++j) { W[c][j + 3] = S[c * N + j]; X[c][j + 3] = S[(3 + c) * N + j]; }
+      for (int g = 1; g <= 3; ++g) {
+        if (bc == BC_PERIODIC) {
+          W[c][3 - g] = W[c][3 + N - g]; X[c][3 - g] = X[c][3 + N - g];
+          W[c][N + 2 + g] = W[c][2 + g]; X[c][N + 2 + g] = X[c][2 + g];
+        } else {
+          W[c][3 - g] = W[c][3]; X[c][3 - g] = 0.0;
+          W[c][N + 2 + g] = W[c][N + 2]; X[c][N + 2 + g] = 0.0;
+        }
+      }
+    }
+  }
+};
+
+template <class T> struct Edge1 { T F[3], Ft[3], chi, Wl[3], Wr[3], Wlt[3], Wrt[3]; };
+template <class T> struct Node1 { T F[3], Ft[3]; };
+
+// Interface between nodes j and j+1 (j from -2 to N).
+template <class T> Edge1<T> edge1d(const Par& p, const Line1<T>& L, int j, double h, double dt) {
+  T Wl[3], Wr[3], Dl[3], Dr[3], cl[3], cr[3];
+  for (int c = 0; c < 3; ++c) {
+    T Q[4], X[4];
+    for (int m = 0; m < 4; ++m) { Q[m] = L.W[c][j - 1 + m + 3]; X[m] = L.X[c][j - 1 + m + 3]; }
+    recon_interface(p, Q, X, h, Wl[c], Dl[c], cl[c], Wr[c], Dr[c], cr[c]);
+  }
+  GksOut<T> o;
+  gks_interface(p, 1, Wl, Wr, Dl, Dr, (const T*)nullptr, dt, o);
+  Edge1<T> E;
+  for (int c = 0; c < 3; ++c) {
+    E.F[c] = o.F[c]; E.Ft[c] = o.Ft[c];
+    E.Wl[c] = o.Wl[c]; E.Wr[c] = o.Wr[c]; E.Wlt[c] = o.Wlt[c]; E.Wrt[c] = o.Wrt[c];
+  }
+  E.chi = std::min(val(cl[0]), val(cr[0])) == val(cl[0]) ? cl[0] : cr[0];
+  return E;
+}
+template <class T> Node1<T> node1d(const Par& p, const Line1<T>& L, int j, double h) {
+  T W[3], Wx[3];
+  for (int c = 0; c < 3; ++c) {
+    T Q[3], X[3];
+    for (int m = 0; m < 3; ++m) { Q[m] = L.W[c][j - 1 + m + 3]; X[m] = L.X[c][j - 1 + m + 3]; }
+    Wx[c] = recon_node(p, Q, X, h);
+    W[c] = L.W[c][j + 3];
+  }
+  Node1<T> R;
+  gks_node(p, 1, W, Wx, (const T*)nullptr, R.F, R.Ft, (T*)nullptr, (T*)nullptr);
+  return R;
+}
+
+// One stage on one line: S = 6 planes of N (W, Wx); acc likewise.
+template <class T>
+void stage1d_line(const Par& p, int N, int stage, double dt, const T* S, const T* acc, T* out, T* acc_out,
+                  std::vector<Edge1<T>>* keepE = nullptr, std::vector<Node1<T>>* keepN = nullptr) {
+  const double h = p.lx / N;
+  Line1<T> L;
+  L.load(S, N, p.bc);
+  std::vector<Edge1<T>> E(N + 3);  // interface j+1/2 for j = -2..N  ->  E[j + 2]
+  std::vector<Node1<T>> Nd(N + 2);  // node j = -1..N  ->  Nd[j + 1]
+  for (int j = -2; j <= N; ++j) E[j + 2] = edge1d(p, L, j, h, dt);
+  for (int j = -1; j <= N; ++j) Nd[j + 1] = node1d(p, L, j, h);
+  for (int j = 0; j < N; ++j) {
+    const Edge1<T>&em3 = E[j - 2 + 2], &em1 = E[j - 1 + 2], &ep1 = E[j + 2], &ep3 = E[j + 1 + 2];
+    const Node1<T>&nm = Nd[j - 1 + 1], &n0 = Nd[j + 1], &np = Nd[j + 1 + 1];
+    for (int c = 0; c < 3; ++c) {
+      T FR = compact_flux(p, em1.F[c], ep1.F[c], ep3.F[c], n0.F[c], np.F[c], ep1.chi);
+      T FL = compact_flux(p, em3.F[c], em1.F[c], ep1.F[c], nm.F[c], n0.F[c], em1.chi);
+      T FRt = compact_flux(p, em1.Ft[c], ep1.Ft[c], ep3.Ft[c], n0.Ft[c], np.Ft[c], ep1.chi);
+      T FLt = compact_flux(p, em3.Ft[c], em1.Ft[c], ep1.Ft[c], nm.Ft[c], n0.Ft[c], em1.chi);
+      T Lc = -(FR - FL) / h, Ltc = -(FRt - FLt) / h;
+      T g = (ep1.Wl[c] - em1.Wr[c]) / h, gt = (ep1.Wlt[c] - em1.Wrt[c]) / h;
+      if (p.grad_carried) g = S[(3 + c) * N + j];
+      if (stage == 1) {
+        out[c * N + j] = S[c * N + j] + 0.5 * dt * Lc + 0.125 * dt * dt * Ltc;
+        out[(3 + c) * N + j] = g + 0.5 * dt * gt;
+        if (acc_out) {
+          acc_out[c * N + j] = S[c * N + j] + dt * Lc + dt * dt / 6.0 * Ltc;
+          acc_out[(3 + c) * N + j] = g;
+        }
+      } else {
+        out[c * N + j] = acc[c * N + j] + dt * dt / 3.0 * Ltc;
+        out[(3 + c) * N + j] = acc[(3 + c) * N + j] + dt * gt;
+      }
+    }
+  }
+  if (keepE) *keepE = E;
+  if (keepN) *keepN = Nd;
+}
+
+}  // namespace orc
+
+using namespace orc;
+
+// =================================================================== C API
+// All arrays are caller-owned, contiguous, little-endian doubles.
+extern "C" {
+
+int orc_abi_version() { return 1; }
+
+// --- unit-level entry points (pins) ---------------------------------------
+// out: vl, dl, cl, vr, dr, cr
+void orc_recon_interface(const Par* p, const double* Q, const double* X, double h, double* out) {
+  recon_interface(*p, Q, X, h, out[0], out[1], out[2], out[3], out[4], out[5]);
+}
+double orc_recon_node(const Par* p, const double* Q, const double* X, double h) {
+  return recon_node(*p, Q, X, h);
+}
+void orc_geno_blend(const Par* p, const double* IS, int ref, const double* d, const double* q,
+                    const double* dq, double PH, double PHx, double* out3) {
+  geno_blend(*p, IS, ref, d, q, dq, PH, PHx, out3[0], out3[1], out3[2]);
+}
+// out: mu[10], mv[10], mx[3]
+void orc_maxwell(double U, double V, double lam, double K, int half, int dim, double* out) {
+  Maxw<double> m = maxwell(U, V, lam, K, half, dim);
+  for (int k = 0; k < 10; ++k) { out[k] = m.mu[k]; out[10 + k] = m.mv[k]; }
+  for (int k = 0; k < 3; ++k) out[20 + k] = m.mx[k];
+}
+void orc_slope(const double* W, const double* D, int dim, double gamma, double* s) {
+  Prim<double> q = prim(W, dim, gamma);
+  Maxw<double> m = maxwell(q.U, q.V, q.lam, kdof(gamma, dim), 0, dim);
+  slope(m, q.rho, D, dim, s);
+}
+void orc_qcoef(double T_, double tau, double* q) { qcoef(T_, tau, q); }
+// out: F, Ft, We, Wet, Wl, Wr, Wlt, Wrt (each dim+2), then tau
+void orc_gks_interface(const Par* p, int dim, const double* WL, const double* WR, const double* WnL,
+                       const double* WnR, const double* Wt, double dt, double* out) {
+  GksOut<double> o;
+  gks_interface(*p, dim, WL, WR, WnL, WnR, Wt, dt, o);
+  int n = dim + 2;
+  const double* src[8] = {o.F, o.Ft, o.We, o.Wet, o.Wl, o.Wr, o.Wlt, o.Wrt};
+  for (int s = 0; s < 8; ++s) for (int i = 0; i < n; ++i) out[s * n + i] = src[s][i];
+  out[8 * n] = o.tau;
+}
+// out: F, Ft, G, Gt (each dim+2)
+void orc_gks_node(const Par* p, int dim, const double* W, const double* Wx, const double* Wy, double* out) {
+  int n = dim + 2;
+  gks_node(*p, dim, W, Wx, Wy, out, out + n, out + 2 * n, out + 3 * n);
+}
+double orc_compact_flux(const Par* p, double Fm, double Fc, double Fp, double N0, double N1, double chi) {
+  return compact_flux(*p, Fm, Fc, Fp, N0, N1, chi);
+}
+// The S2O4 combination applied to one scalar with caller-given L and L_t
+// (stage 2 also takes the stage-1 accumulator).  out2: stage value, accumulator.
+void orc_s2o4_scalar(int stage, double dt, double W, double L, double Lt, double acc, double* out2) {
+  NodeOp<double> op;
+  for (int c = 0; c < 4; ++c) op.L[c] = op.Lt[c] = op.Gx[c] = op.Gy[c] = op.Gxt[c] = op.Gyt[c] = 0.0;
+  op.L[0] = L;
+  op.Lt[0] = Lt;
+  double st[12] = {W}, ac[12] = {acc}, o[12], a[12];
+  s2o4(stage, dt, op, st, ac, o, a);
+  out2[0] = o[0];
+  out2[1] = stage == 1 ? a[0] : 0.0;
+}
+
+// --- 2D ------------------------------------------------------------------
+// P, D: 12 planes (W, Wx, Wy) of ny*nx each.  Stage 2 needs accP/accD.
+void orc_stage2d(const Par* p, int stage, double dt, const double* P, const double* D, const double* accP,
+                 const double* accD, double* outP, double* outD, double* outAccP, double* outAccD) {
+  stage2d<double>(*p, stage, dt, P, D, accP, accD, outP, outD, outAccP, outAccD);
+}
+
+double orc_dt2d(const Par* p, const double* P, const double* D, double cfl) {
+  long pl = (long)p->nx * p->ny;
+  double smax = 0, rmin = 1e300;
+  speed_scan(*p, 2, P, pl, pl, smax, rmin);
+  speed_scan(*p, 2, D, pl, pl, smax, rmin);
+  return dt_from(*p, smax, rmin, p->lx / p->nx, cfl);
+}
+
+// Advance nsteps (dt_fixed > 0: fixed step, else CFL); stops at t_end when
+// t_end > 0.  P, D updated in place; t in/out; returns steps taken.
+int orc_step2d(const Par* p, double* P, double* D, int nsteps, double dt_fixed, double cfl, double t_end,
+               double* t) {
+  long n12 = 12L * p->nx * p->ny;
+  std::vector<double> sP(n12), sD(n12), aP(n12), aD(n12);
+  int k = 0;
+  for (; k < nsteps; ++k) {
+    if (t_end > 0 && *t >= t_end) break;
+    double dt = dt_fixed > 0 ? dt_fixed : orc_dt2d(p, P, D, cfl);
+    if (t_end > 0 && *t + dt > t_end) dt = t_end - *t;
+    stage2d<double>(*p, 1, dt, P, D, nullptr, nullptr, sP.data(), sD.data(), aP.data(), aD.data());
+    stage2d<double>(*p, 2, dt, sP.data(), sD.data(), aP.data(), aD.data(), P, D, nullptr, nullptr);
+    *t += dt;
+  }
+  return k;
+}
+
+// Per-interface and per-node intermediates of one stage, for kernel-level
+// comparison.  Xo, Yo: 50 planes each (per normal axis a = x, y: F[4], Ft[4],
+// chi, Wtl[4], Wtr[4], Wtlt[4], Wtrt[4]); Po, Do: 16 planes (F, Ft, G, Gt).
+void orc_intermediates2d(const Par* p, double dt, const double* P, const double* D, double* Xo, double* Yo,
+                         double* Po, double* Do) {
+  const int nx = p->nx, ny = p->ny;
+  long n12 = 12L * nx * ny, pl = (long)nx * ny;
+  std::vector<double> a(n12), b(n12), c(n12), d(n12);
+  Store2<double> S;
+  stage2d<double>(*p, 1, dt, P, D, nullptr, nullptr, a.data(), b.data(), c.data(), d.data(), &S);
+  for (long k = 0; k < pl; ++k) {
+    for (int fam = 0; fam < 2; ++fam) {
+      const EdgeRes<double>& E = fam == 0 ? S.X[k] : S.Y[k];
+      double* o = fam == 0 ? Xo : Yo;
+      for (int ax = 0; ax < 2; ++ax) {
+        double* q = o + (long)ax * 25 * pl;
+        for (int cc = 0; cc < 4; ++cc) {
+          q[(0 + cc) * pl + k] = E.F[ax][cc];
+          q[(4 + cc) * pl + k] = E.Ft[ax][cc];
+          q[(9 + cc) * pl + k] = E.Wtl[ax][cc];
+          q[(13 + cc) * pl + k] = E.Wtr[ax][cc];
+          q[(17 + cc) * pl + k] = E.Wtlt[ax][cc];
+          q[(21 + cc) * pl + k] = E.Wtrt[ax][cc];
+        }
+        q[8 * pl + k] = E.chi[ax];
+      }
+    }
+    for (int g = 0; g < 2; ++g) {
+      const NodeRes<double>& R = g == 0 ? S.P[k] : S.D[k];
+      double* o = g == 0 ? Po : Do;
+      for (int cc = 0; cc < 4; ++cc) {
+        o[cc * pl + k] = R.F[cc]; o[(4 + cc) * pl + k] = R.Ft[cc];
+        o[(8 + cc) * pl + k] = R.G[cc]; o[(12 + cc) * pl + k] = R.Gt[cc];
+      }
+    }
+  }
+}
+
+// One stage evaluated at a sample of nodes only (for grids too large for a
+// full oracle sweep).  grid[s] (0: P, 1: D), jj[s], ii[s] name the nodes;
+// out[s*24 .. +12]: the stage output state, out[s*24+12 .. +12]: the stage-1
+// accumulators (zero for stage 2).
+void orc_stage2d_sample(const Par* p, int stage, double dt, const double* P, const double* D, const double* accP,
+                        const double* accD, int ns, const int* grid, const int* jj, const int* ii, double* out) {
+  const int nx = p->nx, ny = p->ny;
+  const double h = p->lx / nx;
+  const long pl = (long)nx * ny;
+  Grid2<double> G{nx, ny, P, D};
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int s = 0; s < ns; ++s) {
+    int I = grid[s] == 0 ? 2 * ii[s] + 1 : 2 * ii[s] + 2;
+    int J = grid[s] == 0 ? 2 * jj[s] + 1 : 2 * jj[s] + 2;
+    // the 8 interfaces and 5 nodes the operator reads
+    EdgeRes<double> E[2][4];
+    NodeRes<double> Nn[2][3];
+    for (int ax = 0; ax < 2; ++ax) {
+      int dI = ax == 0 ? 1 : 0, dJ = ax == 0 ? 0 : 1;
+      for (int m = 0; m < 4; ++m) E[ax][m] = edge2d(*p, G, I + (2 * m - 3) * dI, J + (2 * m - 3) * dJ, h, dt);
+      for (int m = 0; m < 3; ++m) Nn[ax][m] = node2d(*p, G, I + (2 * m - 2) * dI, J + (2 * m - 2) * dJ, h);
+    }
+    auto edgef = [&](int I2, int J2) -> const EdgeRes<double>& {
+      int ax = (J2 == J) ? 0 : 1;
+      int o = ax == 0 ? I2 - I : J2 - J;
+      return E[ax][(o + 3) / 2];
+    };
+    auto nodef = [&](int I2, int J2) -> const NodeRes<double>& {
+      if (I2 == I && J2 == J) return Nn[0][1];
+      int ax = (J2 == J) ? 0 : 1;
+      int o = ax == 0 ? I2 - I : J2 - J;
+      return Nn[ax][(o + 2) / 2];
+    };
+    NodeOp<double> op = node_operator<double>(*p, I, J, h, edgef, nodef);
+    long k = (long)jj[s] * nx + ii[s];
+    const double* src = grid[s] == 0 ? P : D;
+    const double* acc = grid[s] == 0 ? accP : accD;
+    double st[12], ac[12], o12[12], a12[12];
+    for (int f = 0; f < 12; ++f) { st[f] = src[f * pl + k]; ac[f] = acc ? acc[f * pl + k] : 0.0; }
+    s2o4(stage, dt, op, st, ac, o12, a12, p->grad_carried);
+    for (int f = 0; f < 12; ++f) { out[s * 24 + f] = o12[f]; out[s * 24 + 12 + f] = stage == 1 ? a12[f] : 0.0; }
+  }
+}
+
+// Tangent (forward-mode) of one full step at fixed dt: given state and a
+// direction (dP, dD), returns the stepped state and its directional
+// derivative.  Ties in min/max and |0| follow the adjoint's convention.
+void orc_step2d_tangent(const Par* p, double dt, const double* P, const double* D, const double* dP,
+                        const double* dD, double* outP, double* outD, double* outdP, double* outdD) {
+  long n12 = 12L * p->nx * p->ny;
+  std::vector<Dual> xP(n12), xD(n12), sP(n12), sD(n12), aP(n12), aD(n12), yP(n12), yD(n12);
+  for (long k = 0; k < n12; ++k) { xP[k] = Dual(P[k], dP[k]); xD[k] = Dual(D[k], dD[k]); }
+  stage2d<Dual>(*p, 1, dt, xP.data(), xD.data(), nullptr, nullptr, sP.data(), sD.data(), aP.data(), aD.data());
+  stage2d<Dual>(*p, 2, dt, sP.data(), sD.data(), aP.data(), aD.data(), yP.data(), yD.data(), nullptr, nullptr);
+  for (long k = 0; k < n12; ++k) { outP[k] = yP[k].v; outD[k] = yD[k].v; outdP[k] = yP[k].d; outdD[k] = yD[k].d; }
+}
+
+// --- 1D --------------------------------------------------------------------
+// S: 6 planes of N (W[3], Wx[3]) per line; nl lines (1, or 2 with the shifted
+// copy) stored one after another.
+void orc_stage1d(const Par* p, int stage, double dt, const double* S, const double* acc, double* out,
+                 double* acc_out) {
+  int N = p->nx, nl = p->dual_1d ? 2 : 1;
+  for (int l = 0; l < nl; ++l)
+    stage1d_line<double>(*p, N, stage, dt, S + 6L * N * l, acc ? acc + 6L * N * l : nullptr, out + 6L * N * l,
+                         acc_out ? acc_out + 6L * N * l : nullptr);
+}
+double orc_dt1d(const Par* p, const double* S, double cfl) {
+  int N = p->nx, nl = p->dual_1d ? 2 : 1;
+  double smax = 0, rmin = 1e300;
+  for (int l = 0; l < nl; ++l) speed_scan(*p, 1, S + 6L * N * l, N, N, smax, rmin);
+  return dt_from(*p, smax, rmin, p->lx / N, cfl);
+}
+int orc_step1d(const Par* p, double* S, int nsteps, double dt_fixed, double cfl, double t_end, double* t) {
+  int N = p->nx, nl = p->dual_1d ? 2 : 1;
+  long n = 6L * N * nl;
+  std::vector<double> s(n), a(n);
+  int k = 0;
+  for (; k < nsteps; ++k) {
+    if (t_end > 0 && *t >= t_end) break;
+    double dt = dt_fixed > 0 ? dt_fixed : orc_dt1d(p, S, cfl);
+    if (t_end > 0 && *t + dt > t_end) dt = t_end - *t;
+    orc_stage1d(p, 1, dt, S, nullptr, s.data(), a.data());
+    orc_stage1d(p, 2, dt, s.data(), a.data(), S, nullptr);
+    *t += dt;
+  }
+  return k;
+}
+// Intermediates of one 1D line: E: 19 planes of N+3 interfaces (j = -2..N):
+// F[3], Ft[3], chi, Wl[3], Wr[3], Wlt[3], Wrt[3]; Nn: 6 planes of N+2 nodes
+// (j = -1..N): F[3], Ft[3].
+void orc_intermediates1d(const Par* p, double dt, const double* S, double* E, double* Nn) {
+  int N = p->nx;
+  std::vector<double> o(6L * N), a(6L * N);
+  std::vector<Edge1<double>> Ev;
+  std::vector<Node1<double>> Nv;
+  stage1d_line<double>(*p, N, 1, dt, S, nullptr, o.data(), a.data(), &Ev, &Nv);
+  long ne = N + 3, nn = N + 2;
+  for (long k = 0; k < ne; ++k) {
+    for (int c = 0; c < 3; ++c) {
+      E[c * ne + k] = Ev[k].F[c]; E[(3 + c) * ne + k] = Ev[k].Ft[c];
+      E[(7 + c) * ne + k] = Ev[k].Wl[c]; E[(10 + c) * ne + k] = Ev[k].Wr[c];
+      E[(13 + c) * ne + k] = Ev[k].Wlt[c]; E[(16 + c) * ne + k] = Ev[k].Wrt[c];
+    }
+    E[6 * ne + k] = Ev[k].chi;
+  }
+  for (long k = 0; k < nn; ++k)
+    for (int c = 0; c < 3; ++c) { Nn[c * nn + k] = Nv[k].F[c]; Nn[(3 + c) * nn + k] = Nv[k].Ft[c]; }
+}
+
+}  // extern "C"

@@ -1,0 +1,277 @@
+"""ctypes front end of the FD-CGKS oracle (``fdcgks_oracle.cpp``).
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py``.  It never imports the product package
+and the product package never imports it.
+
+Arrays cross the boundary as contiguous float64 numpy arrays.  2D state: one
+array per grid of shape (12, ny, nx) holding W[0..3], Wx[0..3], Wy[0..3].  1D
+state: (lines, 6, N) holding W[0..2], Wx[0..2] per line.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "fdcgks_oracle.cpp")
+LIB = os.path.join(HERE, "liboracle_fdcgks.so")
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with g++ (FP contraction off so the arithmetic is the
+    written one, OpenMP over grid rows)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp"
+        cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               SRC, "-o", tmp]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Par(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32),
+        ("dual_1d", C.c_int32), ("variant", C.c_int32), ("r", C.c_int32), ("grad_carried", C.c_int32),
+        ("x0", C.c_double), ("lx", C.c_double), ("y0", C.c_double), ("ly", C.c_double),
+        ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
+        ("C", C.c_double), ("eps", C.c_double), ("eps_a", C.c_double),
+        ("d_central", C.c_double), ("d_side", C.c_double),
+        ("tau_c1", C.c_double), ("tau_c2", C.c_double),
+    ]
+
+
+VARIANTS = {"6-4": 0, "6-2": 1, "linear": 2}
+BCS = {"periodic": 0, "zero_gradient": 1}
+
+
+def make_par(*, dim=2, nx=16, ny=16, x0=0.0, lx=1.0, y0=0.0, ly=None, bc="periodic", dual_1d=0,
+             gamma=1.4, mu=0.0, prandtl=1.0, variant="6-4", geno_C=20.0, geno_r=3,
+             geno_eps=1e-15, geno_eps_a=1e-6, d_central=8.0, d_side=1.0, tau_c1=0.0,
+             tau_c2=1.0, grad_carried=0, **_ignored) -> Par:
+    """Problem description with the oracle's own field layout.  Defaults are the
+    readings of the paper (C = 20, r = 3, eps = 1e-15, eps_a = 1e-6, d = 8/1,
+    tau = 0 * dt + dt |dp|/(p_l+p_r) for Euler: D11 as amended)."""
+    p = Par()
+    p.dim, p.nx, p.ny = dim, nx, (ny if dim == 2 else 1)
+    p.bc = BCS[bc] if isinstance(bc, str) else int(bc)
+    p.dual_1d = int(dual_1d)
+    p.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
+    p.r = int(geno_r)
+    p.x0, p.lx, p.y0 = x0, lx, y0
+    p.ly = lx * p.ny / nx if ly is None else ly
+    p.gamma, p.mu, p.prandtl = gamma, mu, prandtl
+    p.C, p.eps, p.eps_a, p.d_central, p.d_side = geno_C, geno_eps, geno_eps_a, d_central, d_side
+    p.tau_c1, p.tau_c2 = tau_c1, tau_c2
+    p.grad_carried = int(grad_carried)
+    return p
+
+
+_lib = None
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB)
+        P = C.POINTER(Par)
+        d, i = C.c_double, C.c_int
+        sig = {
+            "orc_abi_version": (i, []),
+            "orc_recon_interface": (None, [P, _dp, _dp, d, _dp]),
+            "orc_recon_node": (d, [P, _dp, _dp, d]),
+            "orc_geno_blend": (None, [P, _dp, i, _dp, _dp, _dp, d, d, _dp]),
+            "orc_maxwell": (None, [d, d, d, d, i, i, _dp]),
+            "orc_slope": (None, [_dp, _dp, i, d, _dp]),
+            "orc_qcoef": (None, [d, d, _dp]),
+            "orc_gks_interface": (None, [P, i, _dp, _dp, _dp, _dp, _dp, d, _dp]),
+            "orc_gks_node": (None, [P, i, _dp, _dp, _dp, _dp]),
+            "orc_compact_flux": (d, [P, d, d, d, d, d, d]),
+            "orc_s2o4_scalar": (None, [i, d, d, d, d, d, _dp]),
+            "orc_stage2d": (None, [P, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+            "orc_dt2d": (d, [P, _dp, _dp, d]),
+            "orc_step2d": (i, [P, _dp, _dp, i, d, d, d, _dp]),
+            "orc_intermediates2d": (None, [P, d, _dp, _dp, _dp, _dp, _dp, _dp]),
+            "orc_stage2d_sample": (None, [P, i, d, _dp, _dp, _dp, _dp, i, _ip, _ip, _ip, _dp]),
+            "orc_step2d_tangent": (None, [P, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+            "orc_stage1d": (None, [P, i, d, _dp, _dp, _dp, _dp]),
+            "orc_dt1d": (d, [P, _dp, d]),
+            "orc_step1d": (i, [P, _dp, i, d, d, d, _dp]),
+            "orc_intermediates1d": (None, [P, d, _dp, _dp, _dp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    if a is None:
+        return None
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(_dp)
+
+
+def _arr(x, n=None):
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+    if n is not None:
+        assert a.size == n
+    return a
+
+
+# ---------------------------------------------------------------- unit level
+def recon_interface(par, Q, X, h):
+    """(v_l, d_l, chi_l, v_r, d_r, chi_r) at j+1/2 from Q_{j-1..j+2}, Q_{x,j-1..j+2}."""
+    out = np.zeros(6)
+    lib().orc_recon_interface(C.byref(par), _p(_arr(Q, 4)), _p(_arr(X, 4)), h, _p(out))
+    return out
+
+
+def recon_node(par, Q, X, h):
+    return lib().orc_recon_node(C.byref(par), _p(_arr(Q, 3)), _p(_arr(X, 3)), h)
+
+
+def geno_blend(par, IS, ref, d, q, dq, PH, PHx):
+    out = np.zeros(3)
+    lib().orc_geno_blend(C.byref(par), _p(_arr(IS, 3)), ref, _p(_arr(d, 3)), _p(_arr(q, 3)),
+                         _p(_arr(dq, 3)), PH, PHx, _p(out))
+    return out  # value, derivative, chi
+
+
+def maxwell(U, V, lam, K, half, dim):
+    out = np.zeros(23)
+    lib().orc_maxwell(U, V, lam, K, half, dim, _p(out))
+    return out[:10], out[10:20], out[20:23]
+
+
+def slope(W, D, dim, gamma):
+    s = np.zeros(dim + 2)
+    lib().orc_slope(_p(_arr(W, dim + 2)), _p(_arr(D, dim + 2)), dim, gamma, _p(s))
+    return s
+
+
+def qcoef(T, tau):
+    q = np.zeros(5)
+    lib().orc_qcoef(T, tau, _p(q))
+    return q
+
+
+def gks_interface(par, dim, WL, WR, WnL, WnR, Wt, dt):
+    n = dim + 2
+    out = np.zeros(8 * n + 1)
+    wt = _arr(Wt if Wt is not None else np.zeros(n), n)
+    lib().orc_gks_interface(C.byref(par), dim, _p(_arr(WL, n)), _p(_arr(WR, n)), _p(_arr(WnL, n)),
+                            _p(_arr(WnR, n)), _p(wt), dt, _p(out))
+    keys = ["F", "Ft", "We", "Wet", "Wl", "Wr", "Wlt", "Wrt"]
+    r = {k: out[i * n:(i + 1) * n].copy() for i, k in enumerate(keys)}
+    r["tau"] = out[8 * n]
+    return r
+
+
+def gks_node(par, dim, W, Wx, Wy=None):
+    n = dim + 2
+    out = np.zeros(4 * n)
+    wy = _arr(Wy if Wy is not None else np.zeros(n), n)
+    lib().orc_gks_node(C.byref(par), dim, _p(_arr(W, n)), _p(_arr(Wx, n)), _p(wy), _p(out))
+    return {"F": out[:n], "Ft": out[n:2 * n], "G": out[2 * n:3 * n], "Gt": out[3 * n:]}
+
+
+def compact_flux(par, Fm, Fc, Fp, N0, N1, chi):
+    return lib().orc_compact_flux(C.byref(par), Fm, Fc, Fp, N0, N1, chi)
+
+
+def s2o4_scalar(stage, dt, W, L, Lt, acc=0.0):
+    out = np.zeros(2)
+    lib().orc_s2o4_scalar(stage, dt, W, L, Lt, acc, _p(out))
+    return out
+
+
+# ---------------------------------------------------------------------- 2D
+def stage2d(par, stage, dt, P, D, accP=None, accD=None):
+    P, D = _arr(P), _arr(D)
+    oP, oD = np.zeros_like(P), np.zeros_like(D)
+    aP = np.zeros_like(P) if stage == 1 else None
+    aD = np.zeros_like(D) if stage == 1 else None
+    lib().orc_stage2d(C.byref(par), stage, dt, _p(P), _p(D), _p(None if accP is None else _arr(accP)),
+                      _p(None if accD is None else _arr(accD)), _p(oP), _p(oD), _p(aP), _p(aD))
+    return (oP, oD, aP, aD) if stage == 1 else (oP, oD)
+
+
+def dt2d(par, P, D, cfl):
+    return lib().orc_dt2d(C.byref(par), _p(_arr(P)), _p(_arr(D)), cfl)
+
+
+def step2d(par, P, D, nsteps, dt=0.0, cfl=0.5, t_end=0.0, t=0.0):
+    """Advance; returns (P, D, t, steps)."""
+    P, D = _arr(P).copy(), _arr(D).copy()
+    tt = C.c_double(t)
+    k = lib().orc_step2d(C.byref(par), _p(P), _p(D), nsteps, dt, cfl, t_end, C.byref(tt))
+    return P, D, tt.value, k
+
+
+def intermediates2d(par, dt, P, D):
+    """Per-interface (X, Y: (2 normals, 25, ny, nx)) and per-node (P, D:
+    (16, ny, nx)) intermediates of stage 1."""
+    ny, nx = par.ny, par.nx
+    X = np.zeros((2, 25, ny, nx)); Y = np.zeros((2, 25, ny, nx))
+    NP = np.zeros((16, ny, nx)); ND = np.zeros((16, ny, nx))
+    lib().orc_intermediates2d(C.byref(par), dt, _p(_arr(P)), _p(_arr(D)), _p(X), _p(Y), _p(NP), _p(ND))
+    return X, Y, NP, ND
+
+
+def stage2d_sample(par, stage, dt, P, D, grid, jj, ii, accP=None, accD=None):
+    """Stage output at the listed nodes only: (ns, 12) state and (ns, 12) accumulators."""
+    grid = np.ascontiguousarray(grid, dtype=np.int32)
+    jj = np.ascontiguousarray(jj, dtype=np.int32)
+    ii = np.ascontiguousarray(ii, dtype=np.int32)
+    ns = grid.size
+    out = np.zeros((ns, 24))
+    ip = lambda a: a.ctypes.data_as(_ip)  # noqa: E731
+    lib().orc_stage2d_sample(C.byref(par), stage, dt, _p(_arr(P)), _p(_arr(D)),
+                             _p(None if accP is None else _arr(accP)), _p(None if accD is None else _arr(accD)),
+                             ns, ip(grid), ip(jj), ip(ii), _p(out))
+    return out[:, :12], out[:, 12:]
+
+
+def step2d_tangent(par, dt, P, D, dP, dD):
+    P, D, dP, dD = _arr(P), _arr(D), _arr(dP), _arr(dD)
+    oP, oD, odP, odD = (np.zeros_like(P) for _ in range(4))
+    lib().orc_step2d_tangent(C.byref(par), dt, _p(P), _p(D), _p(dP), _p(dD), _p(oP), _p(oD), _p(odP), _p(odD))
+    return oP, oD, odP, odD
+
+
+# ---------------------------------------------------------------------- 1D
+def stage1d(par, stage, dt, S, acc=None):
+    S = _arr(S)
+    out = np.zeros_like(S)
+    a = np.zeros_like(S) if stage == 1 else None
+    lib().orc_stage1d(C.byref(par), stage, dt, _p(S), _p(None if acc is None else _arr(acc)), _p(out), _p(a))
+    return (out, a) if stage == 1 else out
+
+
+def dt1d(par, S, cfl):
+    return lib().orc_dt1d(C.byref(par), _p(_arr(S)), cfl)
+
+
+def step1d(par, S, nsteps, dt=0.0, cfl=0.5, t_end=0.0, t=0.0):
+    S = _arr(S).copy()
+    tt = C.c_double(t)
+    k = lib().orc_step1d(C.byref(par), _p(S), nsteps, dt, cfl, t_end, C.byref(tt))
+    return S, tt.value, k
+
+
+def intermediates1d(par, dt, S):
+    """Interfaces j+1/2 for j = -2..N: (19, N+3); nodes j = -1..N: (6, N+2)."""
+    N = par.nx
+    E = np.zeros((19, N + 3)); Nn = np.zeros((6, N + 2))
+    lib().orc_intermediates1d(C.byref(par), dt, _p(_arr(S)), _p(E), _p(Nn))
+    return E, Nn

@@ -1,0 +1,110 @@
+"""Shared test helpers: parameter mapping and error measures (no method
+arithmetic)."""
+import numpy as np
+
+DEFAULTS = dict(gamma=1.4, mu=0.0, prandtl=1.0, variant="6-4", geno_C=20.0, geno_r=3, geno_eps=1e-15,
+                geno_eps_a=1e-6, d_central=8.0, d_side=1.0, tau_c1=0.0, tau_c2=1.0, bc="periodic")
+
+# max-relative parity bar for FP64 (per plane: max |gpu - oracle| / max |oracle|)
+TOL = 1e-12
+
+
+def settings(**kw):
+    s = dict(DEFAULTS)
+    s.update(kw)
+    return s
+
+
+def oracle_par(O, s):
+    return O.make_par(**s)
+
+
+def gpu_params(s):
+    from paper_2606_17772_amd import make_params
+    kw = dict(dim=s["dim"], nx=s["nx"], ny=s.get("ny", 1), lx=s["lx"], gamma=s["gamma"], mu=s["mu"],
+              prandtl=s["prandtl"], variant=s["variant"], geno_C=s["geno_C"], geno_r=s["geno_r"],
+              geno_eps=s["geno_eps"], geno_eps_a=s["geno_eps_a"], geno_d_central=s["d_central"],
+              geno_d_side=s["d_side"], tau_c1=s["tau_c1"], tau_c2=s["tau_c2"], bc=s["bc"],
+              fp32_flux=s.get("fp32_flux", False), grad_carried=s.get("grad_carried", 0))
+    if s["dim"] == 2:
+        kw["ly"] = s.get("ly", s["lx"] * s["ny"] / s["nx"])
+    else:
+        kw["dual_1d"] = s.get("dual_1d", 0)
+    return make_params(**kw)
+
+
+def maxrel(g, o, floor=1e-6, axes=None):
+    """Largest per-plane relative error; planes are the leading axes up to the
+    last two (2D) / last one (1D)."""
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    assert g.shape == o.shape, (g.shape, o.shape)
+    if axes is None:
+        axes = (-2, -1) if g.ndim >= 3 else (-1,)
+    num = np.abs(g - o).max(axis=axes)
+    den = np.maximum(np.abs(o).max(axis=axes), floor)
+    return float((num / den).max())
+
+
+def worst_plane(g, o, floor=1e-6):
+    num = np.abs(g - o).max(axis=(-2, -1))
+    den = np.maximum(np.abs(o).max(axis=(-2, -1)), floor)
+    r = num / den
+    return np.unravel_index(np.argmax(r), r.shape), float(r.max())
+
+
+# ------------------------------------------------------------------ scales
+# A plane whose exact values vanish (e.g. rho_t of a shear layer) has no
+# meaningful relative error; its denominator is floored by the dimensional
+# reference scale of the field: rho0, rho0 a, rho0 a^2 for rho, momentum,
+# energy (a = largest wave speed |u| + c), divided by the domain length L for
+# spatial derivatives, times a/L for time derivatives.
+def ref_scales(states, gamma, L, dim=2):
+    rho = U = V = None
+    rmax, amax = 0.0, 0.0
+    for S in states:
+        W = np.asarray(S)[: dim + 2]
+        rho = W[0]
+        U = W[1] / rho
+        V = W[2] / rho if dim == 2 else 0.0 * U
+        p = (gamma - 1.0) * (W[dim + 1] - 0.5 * rho * (U * U + V * V))
+        c = np.sqrt(gamma * p / rho)
+        rmax = max(rmax, float(rho.max()))
+        amax = max(amax, float((np.maximum(abs(U), abs(V)) + c).max()))
+    Wr = [rmax] + [rmax * amax] * dim + [rmax * amax * amax]
+    Wr = np.array(Wr)
+    return {"W": Wr, "grad": Wr / L, "flux": Wr * amax, "flux_t": Wr * amax * amax / L, "Wt": Wr * amax / L}
+
+
+def floors_state(sc, dim=2):
+    return np.concatenate([sc["W"], sc["grad"], sc["grad"]] if dim == 2 else [sc["W"], sc["grad"]])
+
+
+def floors_state_interval(sc, h, dim=2):
+    """Floors for comparing the averaged gradients in the units the scheme
+    forms them in: the Gauss difference h * grad W of two interface values of
+    size |W| (Eq. define-averaged-gradient), i.e. floor |W| / h."""
+    g = sc["W"] / h
+    return np.concatenate([sc["W"], g, g] if dim == 2 else [sc["W"], g])
+
+
+def floors_edge(sc):
+    one = np.concatenate([sc["flux"], sc["flux_t"], [1.0], sc["W"], sc["W"], sc["Wt"], sc["Wt"]])
+    return np.stack([one, one])  # (2 normals, 25)
+
+
+def floors_node(sc):
+    return np.concatenate([sc["flux"], sc["flux_t"], sc["flux"], sc["flux_t"]])
+
+
+def relerr(g, o, floors, ndim_plane=2):
+    """Largest per-plane max|g-o| / max(max|o|, floor); floors broadcast over
+    the plane index axes."""
+    g = np.asarray(g, dtype=np.float64)
+    o = np.asarray(o, dtype=np.float64)
+    assert g.shape == o.shape, (g.shape, o.shape)
+    axes = tuple(range(-ndim_plane, 0))
+    num = np.abs(g - o).max(axis=axes)
+    den = np.maximum(np.abs(o).max(axis=axes), floors)
+    r = num / den
+    return float(r.max()), np.unravel_index(int(np.argmax(r)), r.shape)

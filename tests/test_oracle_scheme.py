@@ -1,0 +1,217 @@
+"""Scheme-level pins of the oracle: invariants (free stream, conservation,
+symmetries, shift equivariance), the paper's accuracy tables (Sec. 5.1,
+tests/golden/) and exact Riemann solutions for shock tubes.  CPU only."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as WL
+from tests import riemann_exact as RE
+from tests.helpers import settings
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def _p2(oracle, n, ny=None, lx=1.0, **kw):
+    return oracle.make_par(**settings(dim=2, nx=n, ny=ny or n, lx=lx, **kw))
+
+
+# ---------------------------------------------------------------- 2D invariants
+def test_free_stream_is_preserved_exactly(oracle):
+    n = 9
+    W = WL.conservative(1.3, 0.4, -0.7, 2.0)
+    P = np.zeros((12, n, n))
+    P[0:4] = W[:, None, None]
+    D = P.copy()
+    par = _p2(oracle, n)
+    oP, oD, t, k = oracle.step2d(par, P, D, 2, dt=0.01)
+    assert np.abs(oP - P).max() < 1e-14 and np.abs(oD - D).max() < 1e-14
+
+
+@pytest.mark.parametrize("case", ["rough", "riemann"])
+def test_conservation_on_both_grids(oracle, case):
+    pr = WL.random_rough2d(12, 10, seed=1) if case == "rough" else WL.riemann2d(12, seed=2)
+    par = _p2(oracle, pr.nx, pr.ny, lx=pr.lx)
+    oP, oD, t, k = oracle.step2d(par, pr.P, pr.D, 2, dt=0.2 * pr.h / 3)
+    for A, B in ((pr.P, oP), (pr.D, oD)):
+        for c in range(4):
+            scale = np.abs(A[c]).sum()
+            assert abs(B[c].sum() - A[c].sum()) <= 1e-13 * scale, c
+
+
+def _transpose(S):
+    T = np.ascontiguousarray(np.swapaxes(S, 1, 2))
+    T = T[[0, 2, 1, 3, 8, 10, 9, 11, 4, 6, 5, 7]]  # rho V <-> rho U, Wx <-> Wy
+    return np.ascontiguousarray(T)
+
+
+def test_transpose_symmetry(oracle):
+    pr = WL.random_rough2d(11, 11, seed=3)
+    par = _p2(oracle, 11)
+    dt = 0.02
+    a = oracle.stage2d(par, 1, dt, pr.P, pr.D)
+    b = oracle.stage2d(par, 1, dt, _transpose(pr.P), _transpose(pr.D))
+    for k in range(4):
+        assert np.allclose(_transpose(a[k]), b[k], rtol=1e-13, atol=1e-13)
+
+
+def _mirror_x(S, grid):
+    n = S.shape[2]
+    idx = (n - 1 - np.arange(n)) if grid == 0 else (n - 2 - np.arange(n)) % n
+    M = S[:, :, idx].copy()
+    sgn = np.array([1, -1, 1, 1, -1, 1, -1, -1, 1, -1, 1, 1], float)  # W, Wx, Wy with rho U odd
+    return np.ascontiguousarray(M * sgn[:, None, None])
+
+
+def test_mirror_symmetry(oracle):
+    pr = WL.random_rough2d(10, 7, seed=5)
+    par = _p2(oracle, 10, 7)
+    dt = 0.02
+    a = oracle.stage2d(par, 1, dt, pr.P, pr.D)
+    b = oracle.stage2d(par, 1, dt, _mirror_x(pr.P, 0), _mirror_x(pr.D, 1))
+    for k, g in ((0, 0), (1, 1), (2, 0), (3, 1)):
+        assert np.allclose(_mirror_x(a[k], g), b[k], rtol=1e-12, atol=1e-12), k
+
+
+def test_shift_equivariance(oracle):
+    pr = WL.random_rough2d(9, 8, seed=6)
+    par = _p2(oracle, 9, 8)
+    a = oracle.stage2d(par, 1, 0.02, pr.P, pr.D)
+    r = lambda S: np.ascontiguousarray(np.roll(np.roll(S, 2, axis=2), -3, axis=1))  # noqa: E731
+    b = oracle.stage2d(par, 1, 0.02, r(pr.P), r(pr.D))
+    for k in range(4):
+        assert np.array_equal(r(a[k]), b[k])
+
+
+def test_vortex_translates(oracle):
+    """Isentropic vortex advected by the free stream for a short time stays
+    close to the exact translated vortex (both grids)."""
+    pr = WL.vortex(64, seed=0)
+    par = _p2(oracle, 64, lx=10.0)
+    T = 0.5
+    oP, oD, t, k = oracle.step2d(par, pr.P, pr.D, 1000, cfl=0.5, t_end=T)
+    eP, eD = WL.vortex_exact(pr, T)
+    assert abs(t - T) < 1e-14
+    assert np.abs(oP[0] - eP[0]).max() < 6e-3 and np.abs(oD[0] - eD[0]).max() < 6e-3
+
+
+# ---------------------------------------------------------- accuracy, Sec. 5.1
+def _table(name):
+    rows = [l.split()
+            for l in open(os.path.join(HERE, "golden", name)) if l.strip() and not l.startswith("#")]
+    return {float(r[0]): (float(r[1]), float(r[3])) for r in rows}
+
+
+def test_1d_accuracy_against_table_1(oracle):
+    """Design order 6 on the smooth advection test at the paper's meshes, with
+    errors within 3x of Table 1 (dt = 0.1 h (h / h_coarsest) / max(|U|+c),
+    t = 2: readings D25, D26)."""
+    tab = _table("table1_1d_accuracy.txt")
+    errs = []
+    for N in (8, 16, 32):
+        h = 2.0 / N
+        pr = WL.advection1d(N, noise=0, dual=False)
+        par = oracle.make_par(**settings(dim=1, nx=N, lx=2.0, variant="6-2"))
+        dt = 0.1 * h * (h / 0.25) / (1 + np.sqrt(1.4 / 0.8))
+        nst = int(np.ceil(2.0 / dt))
+        S, t, k = oracle.step1d(par, pr.S, nst, dt=2.0 / nst)
+        e = np.abs(S[0, 0] - WL.advection1d_exact(N, 2.0)[0])
+        L1, Li = e.mean(), e.max()
+        errs.append((L1, Li))
+        ref = tab[h]
+        assert ref[0] / 3 < L1 < ref[0] * 3 and ref[1] / 3 < Li < ref[1] * 3, (N, L1, Li, ref)
+    for (a, b), (c, d) in zip(errs, errs[1:]):
+        assert np.log2(a / c) > 5.5 and np.log2(b / d) > 5.5
+
+
+def test_2d_accuracy_against_table_2(oracle):
+    tab = _table("table2_2d_accuracy.txt")
+    errs = []
+    for N in (5, 10):
+        h = 2.0 / N
+        pr = WL.advection2d(N)
+        par = _p2(oracle, N, lx=2.0, variant="6-2")
+        dt = 0.1 * h * (h / 0.4) / (1 + np.sqrt(1.4 / 0.8))
+        nst = int(np.ceil(2.0 / dt))
+        P, D, t, k = oracle.step2d(par, pr.P, pr.D, nst, dt=2.0 / nst)
+        eP, eD = WL.advection2d_exact(N, 2.0)
+        e = np.abs(P[0] - eP[0])
+        L1, Li = e.sum() * h * h, e.max()
+        errs.append((L1, Li))
+        ref = tab[h]
+        assert ref[0] / 3 < L1 < ref[0] * 3 and ref[1] / 3 < Li < ref[1] * 3, (N, L1, Li, ref)
+        assert np.abs(D[0] - eD[0]).max() < 3 * ref[1]
+    (a, b), (c, d) = errs
+    assert np.log2(a / c) > 5.5 and np.log2(b / d) > 5.5
+
+
+def test_1d_primary_and_shifted_copy_agree(oracle):
+    """The shifted copy (reading D24) solves the same problem on nodes offset
+    by h/2: both converge to the exact solution, so they agree to
+    discretisation error."""
+    N = 40
+    pr = WL.advection1d(N, noise=0, dual=True)
+    par = oracle.make_par(**settings(dim=1, nx=N, lx=2.0, dual_1d=1))
+    S, t, k = oracle.step1d(par, pr.S, 100000, cfl=0.3, t_end=0.5)
+    for line, shifted in ((0, False), (1, True)):
+        ex = WL.advection1d_exact(N, 0.5, shifted=shifted)
+        assert np.abs(S[line, 0] - ex[0]).max() < 1e-6
+
+
+def test_1d_conservation_periodic(oracle):
+    pr = WL.advection1d(50, seed=3, noise=1e-2)
+    par = oracle.make_par(**settings(dim=1, nx=50, lx=2.0, dual_1d=1))
+    S, t, k = oracle.step1d(par, pr.S, 5, cfl=0.5)
+    for l in range(2):
+        for c in range(3):
+            assert abs(S[l, c].sum() - pr.S[l, c].sum()) <= 1e-13 * np.abs(pr.S[l, c]).sum()
+
+
+# ------------------------------------------------------------- shock tubes
+def _run_tube(oracle, pr, T, variant="6-4"):
+    par = oracle.make_par(**settings(dim=1, nx=pr.N, lx=pr.lx, bc="zero_gradient", variant=variant))
+    S, t, k = oracle.step1d(par, pr.S, 100000, cfl=0.5, t_end=T)
+    assert abs(t - T) < 1e-14
+    x = (np.arange(pr.N) + 0.5) * pr.h
+    rho = S[0, 0]
+    u = S[0, 1] / rho
+    p = 0.4 * (S[0, 2] - 0.5 * rho * u * u)
+    ex = RE.sample(pr.params["left"], pr.params["right"], (x - 0.5) / T)
+    return x, rho, u, p, ex
+
+
+@pytest.mark.parametrize("variant", ["6-4", "6-2"])
+def test_sod(oracle, variant):
+    pr = WL.sod(100)
+    x, rho, u, p, ex = _run_tube(oracle, pr, 0.2, variant)
+    assert np.abs(rho - ex[0]).mean() < 0.01
+    assert rho.max() <= 1.0 + 1e-3 and rho.min() >= 0.125 - 1e-3     # essentially non-oscillatory
+    ps, us = RE.star_state(pr.params["left"], pr.params["right"])
+    mid = (x > 0.55) & (x < 0.65)                                        # between contact and shock at t = 0.2
+    assert abs(p[mid].mean() - ps) < 0.01 * ps and abs(u[mid].mean() - us) < 0.01 * us
+
+
+def test_lax(oracle):
+    pr = WL.lax(100)
+    x, rho, u, p, ex = _run_tube(oracle, pr, 0.16)
+    assert np.abs(rho - ex[0]).mean() < 0.03
+    assert rho.max() <= ex[0].max() + 0.05
+
+
+@pytest.mark.parametrize("seed", [0, 2])
+def test_seeded_shock_tubes(oracle, seed):
+    """Config-2 shock tubes (N = 400): the density converges to the exact
+    Riemann solution; star pressure recovered on the plateau."""
+    pr = WL.seeded_shock_tube(400, seed)
+    x, rho, u, p, ex = _run_tube(oracle, pr, 0.2)
+    sl, sr = RE.wave_speeds(pr.params["left"], pr.params["right"])
+    inside = (x > 0.5 + sl * 0.2 - 0.3) & (x < 0.5 + sr * 0.2 + 0.3)  # away from boundary-influenced ends
+    assert np.abs(rho - ex[0])[inside].mean() < 0.01
+    jump = max(pr.params["left"][0], pr.params["right"][0]) - min(pr.params["left"][0], pr.params["right"][0])
+    assert rho.max() <= ex[0].max() + 0.2 * jump   # bounded overshoot (conservative-variable GENO)
+    ps, us = RE.star_state(pr.params["left"], pr.params["right"])
+    near = np.abs(ex[2] - ps) < 1e-12
+    core = near & (np.abs(x - 0.5 - us * 0.2) > 0.03)
+    if core.sum() > 5:
+        assert np.median(np.abs(p[core] - ps)) < 0.01 * ps

@@ -1,0 +1,306 @@
+"""Seeded synthetic inputs shaped like the paper's test problems.
+
+This module holds no arithmetic of the method: it only samples analytic
+initial conditions and turns samples into the scheme's input state (nodal
+conservative values and interval-averaged derivatives).  Both the oracle tests
+and the HIP path take their inputs from here; nothing else is shared.
+
+Conventions
+-----------
+Mesh size h.  Samples live on the half-spacing lattice: point (I, J) at
+(x0 + I h/2, y0 + J h/2).  Primary node P[j][i] is lattice (2i+1, 2j+1), dual
+node D[j][i] is (2i+2, 2j+2) (periodic wrap).  The interval-averaged
+derivative of a node is the difference of the exact values at its two bounding
+interfaces divided by h (the Gauss form of the averaged gradient); for initial
+data with jumps placed on interfaces the derivative is set to zero.
+
+2D state per grid: float64 array (12, ny, nx) = W[0..3], Wx[0..3], Wy[0..3],
+W = (rho, rho U, rho V, rho E).  1D state per line: (6, N) = W[0..2], Wx[0..2].
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def conservative(rho, U, V, p, gamma=GAMMA):
+    rho, U, V, p = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64) for a in (rho, U, V, p)))
+    return np.stack([rho, rho * U, rho * V, p / (gamma - 1.0) + 0.5 * rho * (U * U + V * V)])
+
+
+def conservative1d(rho, U, p, gamma=GAMMA):
+    rho, U, p = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64) for a in (rho, U, p)))
+    return np.stack([rho, rho * U, p / (gamma - 1.0) + 0.5 * rho * U * U])
+
+
+# --------------------------------------------------------------------- 2D
+def state_from_samples(S, h):
+    """S: (4, 2ny, 2nx) conservative samples on the half lattice -> (P, D)."""
+    _, JJ, II = S.shape
+    ny, nx = JJ // 2, II // 2
+    j = np.arange(ny)[:, None]
+    i = np.arange(nx)[None, :]
+
+    def at(J, I):
+        return S[:, J % JJ, I % II]
+
+    P = np.empty((12, ny, nx))
+    D = np.empty((12, ny, nx))
+    P[0:4] = at(2 * j + 1, 2 * i + 1)
+    P[4:8] = (at(2 * j + 1, 2 * i + 2) - at(2 * j + 1, 2 * i)) / h
+    P[8:12] = (at(2 * j + 2, 2 * i + 1) - at(2 * j, 2 * i + 1)) / h
+    D[0:4] = at(2 * j + 2, 2 * i + 2)
+    D[4:8] = (at(2 * j + 2, 2 * i + 3) - at(2 * j + 2, 2 * i + 1)) / h
+    D[8:12] = (at(2 * j + 3, 2 * i + 2) - at(2 * j + 1, 2 * i + 2)) / h
+    return np.ascontiguousarray(P), np.ascontiguousarray(D)
+
+
+def lattice(nx, ny, x0, y0, h):
+    I = np.arange(2 * nx)
+    J = np.arange(2 * ny)
+    X = x0 + I[None, :] * h / 2
+    Y = y0 + J[:, None] * h / 2
+    return np.broadcast_arrays(X, Y)
+
+
+@dataclass
+class Problem2D:
+    name: str
+    nx: int
+    ny: int
+    x0: float
+    lx: float
+    y0: float
+    ly: float
+    P: np.ndarray
+    D: np.ndarray
+    params: dict = field(default_factory=dict)
+
+    @property
+    def h(self):
+        return self.lx / self.nx
+
+
+def advection2d(n, lx=2.0):
+    """Smooth density wave rho = 1 + 0.2 sin(pi (x+y)), U = V = p = 1 on
+    [0, 2]^2 (Sec. 5.1 accuracy test)."""
+    h = lx / n
+    X, Y = lattice(n, n, 0.0, 0.0, h)
+    S = conservative(1.0 + 0.2 * np.sin(np.pi * (X + Y)), 1.0, 1.0, 1.0)
+    P, D = state_from_samples(S, h)
+    return Problem2D("advection2d", n, n, 0.0, lx, 0.0, lx, P, D, {"gamma": GAMMA, "mu": 0.0})
+
+
+def advection2d_exact(n, t, lx=2.0):
+    h = lx / n
+    X, Y = lattice(n, n, 0.0, 0.0, h)
+    S = conservative(1.0 + 0.2 * np.sin(np.pi * (X + Y - 2 * t)), 1.0, 1.0, 1.0)
+    return state_from_samples(S, h)
+
+
+def vortex(n, seed=0, L=10.0, beta=5.0, gamma=GAMMA):
+    """Isentropic vortex (strength beta) in a (1,1,1,1) free stream on a
+    periodic [0, L]^2, centre L/2 plus a seeded offset in [-0.5, 0.5]^2."""
+    rng = np.random.default_rng(seed)
+    xc, yc = L / 2 + rng.uniform(-0.5, 0.5, size=2)
+    h = L / n
+    X, Y = lattice(n, n, 0.0, 0.0, h)
+    S = _vortex_samples(X, Y, xc, yc, beta, gamma, L)
+    P, D = state_from_samples(S, h)
+    return Problem2D("vortex", n, n, 0.0, L, 0.0, L, P, D,
+                     {"gamma": gamma, "mu": 0.0, "center": (xc, yc), "beta": beta})
+
+
+def _vortex_samples(X, Y, xc, yc, beta, gamma, L):
+    # nearest periodic image of the centre
+    xb = (X - xc + L / 2) % L - L / 2
+    yb = (Y - yc + L / 2) % L - L / 2
+    r2 = xb * xb + yb * yb
+    dT = -(gamma - 1.0) * beta ** 2 / (8.0 * gamma * math.pi ** 2) * np.exp(1.0 - r2)
+    du = beta / (2 * math.pi) * np.exp(0.5 * (1.0 - r2))
+    T = 1.0 + dT
+    rho = T ** (1.0 / (gamma - 1.0))
+    return conservative(rho, 1.0 - du * yb, 1.0 + du * xb, rho * T, gamma)
+
+
+def vortex_exact(prob, t):
+    xc, yc = prob.params["center"]
+    L = prob.lx
+    X, Y = lattice(prob.nx, prob.ny, 0.0, 0.0, prob.h)
+    S = _vortex_samples(X, Y, (xc + t) % L, (yc + t) % L, prob.params["beta"], prob.params["gamma"], L)
+    return state_from_samples(S, prob.h)
+
+
+def shear_layer(n, seed=0, k=80.0, delta=0.05, Ma=0.15, gamma=GAMMA, mu=1e-4, prandtl=0.72):
+    """Doubly periodic double shear layer on [0,1]^2: U = tanh(k(y-1/4)) below
+    y = 1/2, tanh(k(3/4-y)) above; V = delta sin(2 pi (x + phi)), phi seeded;
+    rho = 1, p = 1/(gamma Ma^2) (Sec. 5.7 shape; k = 80 <-> thickness 1/80)."""
+    rng = np.random.default_rng(seed)
+    phi = rng.uniform(0.0, 1.0)
+    h = 1.0 / n
+    X, Y = lattice(n, n, 0.0, 0.0, h)
+    U = np.where(Y <= 0.5, np.tanh(k * (Y - 0.25)), np.tanh(k * (0.75 - Y)))
+    V = delta * np.sin(2 * math.pi * (X + phi))
+    S = conservative(1.0, U, V, 1.0 / (gamma * Ma * Ma), gamma)
+    P, D = state_from_samples(S, h)
+    return Problem2D("shear_layer", n, n, 0.0, 1.0, 0.0, 1.0, P, D,
+                     {"gamma": gamma, "mu": mu, "prandtl": prandtl, "phi": phi})
+
+
+def riemann2d(n, seed=0, gamma=GAMMA):
+    """Four-quadrant Riemann data on a periodic [0,1]^2 (quadrant states seeded
+    from rho in [0.1,1], u, v in [-1,1], p in [0.1,1]); jumps on interfaces,
+    zero initial derivatives."""
+    rng = np.random.default_rng(seed)
+    q = [(rng.uniform(0.1, 1), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.1, 1)) for _ in range(4)]
+    h = 1.0 / n
+    X, Y = lattice(n, n, 0.0, 0.0, h)
+    quad = (X >= 0.5).astype(int) + 2 * (Y >= 0.5).astype(int)
+    rho = np.choose(quad, [s[0] for s in q])
+    U = np.choose(quad, [s[1] for s in q])
+    V = np.choose(quad, [s[2] for s in q])
+    p = np.choose(quad, [s[3] for s in q])
+    S = conservative(rho, U, V, p, gamma)
+    P, D = state_from_samples(S, h)
+    P[4:] = 0.0
+    D[4:] = 0.0
+    return Problem2D("riemann2d", n, n, 0.0, 1.0, 0.0, 1.0, P, D, {"gamma": gamma, "mu": 0.0, "states": q})
+
+
+def random_smooth2d(nx, ny, seed=0, amp=0.1, modes=3, lx=1.0):
+    """A seeded smooth periodic flow (sums of low Fourier modes) for parity
+    tests on non-square grids."""
+    rng = np.random.default_rng(seed)
+    h = lx / nx
+    X, Y = lattice(nx, ny, 0.0, 0.0, h)
+    ly = h * ny
+
+    def field(base):
+        f = np.full_like(X, base)
+        for _ in range(modes):
+            kx, ky = rng.integers(1, 3, size=2)
+            ph = rng.uniform(0, 2 * math.pi)
+            f = f + amp * rng.uniform(-1, 1) * np.sin(2 * math.pi * (kx * X / lx + ky * Y / ly) + ph)
+        return f
+
+    S = conservative(field(1.0), field(0.3), field(-0.2), field(1.0))
+    P, D = state_from_samples(S, h)
+    return Problem2D("random_smooth2d", nx, ny, 0.0, lx, 0.0, ly, P, D, {"gamma": GAMMA, "mu": 0.0})
+
+
+def random_rough2d(nx, ny, seed=0, lx=1.0):
+    """Seeded noisy data (independent random nodal values and derivatives)
+    that drive every GENO branch; for parity tests only."""
+    rng = np.random.default_rng(seed)
+    P = np.empty((12, ny, nx))
+    D = np.empty((12, ny, nx))
+    for A in (P, D):
+        rho = rng.uniform(0.5, 1.5, size=(ny, nx))
+        U = rng.uniform(-0.5, 0.5, size=(ny, nx))
+        V = rng.uniform(-0.5, 0.5, size=(ny, nx))
+        p = rng.uniform(0.5, 1.5, size=(ny, nx))
+        A[0:4] = conservative(rho, U, V, p)
+        A[4:12] = rng.normal(0.0, 0.5, size=(8, ny, nx))
+    return Problem2D("random_rough2d", nx, ny, 0.0, lx, 0.0, lx * ny / nx, P, D, {"gamma": GAMMA, "mu": 0.0})
+
+
+def batch_sizes(count=64, lo=64, hi=512, seed=0):
+    rng = np.random.default_rng(seed)
+    return [int(v) for v in rng.integers(lo, hi + 1, size=count)]
+
+
+def batch_problems(count=64, lo=64, hi=512, seed=0):
+    """Batched workload: even members isentropic vortices, odd members
+    four-quadrant Riemann problems, sides seeded in [lo, hi]."""
+    out = []
+    for b, n in enumerate(batch_sizes(count, lo, hi, seed)):
+        out.append(vortex(n, seed=seed * 1000 + b) if b % 2 == 0 else riemann2d(n, seed=seed * 1000 + b))
+    return out
+
+
+# --------------------------------------------------------------------- 1D
+@dataclass
+class Problem1D:
+    name: str
+    N: int
+    x0: float
+    lx: float
+    S: np.ndarray           # (lines, 6, N)
+    bc: str = "periodic"
+    params: dict = field(default_factory=dict)
+
+    @property
+    def h(self):
+        return self.lx / self.N
+
+
+def line_from_samples(S, h, shifted=False):
+    """S: (3, 2N) samples at x0 + I h/2 (periodic) -> (6, N) state of the
+    primary line (nodes at odd I) or of the shifted copy (even I)."""
+    N = S.shape[1] // 2
+    j = np.arange(N)
+    c = 2 * j + (2 if shifted else 1)
+    out = np.empty((6, N))
+    out[0:3] = S[:, c % (2 * N)]
+    out[3:6] = (S[:, (c + 1) % (2 * N)] - S[:, (c - 1) % (2 * N)]) / h
+    return out
+
+
+def advection1d(N, seed=0, noise=1e-3, lx=2.0, dual=True):
+    """rho = 1 + 0.2 sin(pi x) (+ seeded N(0,1) noise of size `noise` on node
+    values only), U = p = 1, periodic [0, 2]; derivatives from the smooth part."""
+    rng = np.random.default_rng(seed)
+    h = lx / N
+    x = np.arange(2 * N) * h / 2
+    S = conservative1d(1.0 + 0.2 * np.sin(np.pi * x), 1.0, 1.0)
+    lines = [line_from_samples(S, h, False)]
+    if dual:
+        lines.append(line_from_samples(S, h, True))
+    for L in lines:
+        if noise:
+            d = noise * rng.standard_normal(N)
+            L[0] += d
+            L[1] += d      # U = 1 kept: rho U moves with rho
+            L[2] += 0.5 * d  # p kept: rho E = p/(g-1) + rho/2
+    return Problem1D("advection1d", N, 0.0, lx, np.ascontiguousarray(np.stack(lines)), "periodic",
+                     {"gamma": GAMMA, "mu": 0.0})
+
+
+def advection1d_exact(N, t, lx=2.0, shifted=False):
+    h = lx / N
+    x = np.arange(2 * N) * h / 2
+    S = conservative1d(1.0 + 0.2 * np.sin(np.pi * (x - t)), 1.0, 1.0)
+    return line_from_samples(S, h, shifted)
+
+
+def shock_tube(N, left, right, x_jump=0.5, lx=1.0, gamma=GAMMA):
+    """Piecewise-constant (rho, u, p) data, jump at an interface, zero
+    derivatives, zero-gradient ends.  Nodes at (j + 1/2) h."""
+    h = lx / N
+    x = (np.arange(N) + 0.5) * h
+    L = conservative1d(*left, gamma=gamma)
+    R = conservative1d(*right, gamma=gamma)
+    W = np.where(x[None, :] < x_jump, L[:, None], R[:, None])
+    S = np.zeros((1, 6, N))
+    S[0, 0:3] = W
+    return Problem1D("shock_tube", N, 0.0, lx, S, "zero_gradient",
+                     {"gamma": gamma, "mu": 0.0, "left": left, "right": right, "x_jump": x_jump})
+
+
+def seeded_shock_tube(N=400, seed=0):
+    rng = np.random.default_rng(seed)
+    left = (rng.uniform(0.1, 1), rng.uniform(-1, 1), rng.uniform(0.1, 1))
+    right = (rng.uniform(0.1, 1), rng.uniform(-1, 1), rng.uniform(0.1, 1))
+    return shock_tube(N, left, right)
+
+
+def sod(N=100):
+    return shock_tube(N, (1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+
+
+def lax(N=100):
+    return shock_tube(N, (0.445, 0.698, 3.528), (0.5, 0.0, 0.571))
