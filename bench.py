@@ -1,0 +1,158 @@
+"""Benchmark: FD-CGKS S2O4 steps on one MI355X.
+
+Workload: 2D Navier-Stokes doubly periodic double shear layer, 2048 x 2048
+primary + 2048 x 2048 dual nodes, Re = 1e4 (mu = 1e-4), Pr = 0.72,
+gamma = 1.4, Ma = 0.15, tanh profile of thickness 1/80 with a seeded 5 %
+sinusoidal perturbation, CFL 0.5 (time step reduced on the device every
+step), FP64 throughout.  A step is two S2O4 stages, each a full pass of the
+hot path (halo fill, interface sweep, node sweep, assemble + update) over
+both grids.
+
+Prints one JSON line.  value = node-updates per second per stage =
+(N_primary + N_dual) * 2 stages * steps / seconds, inputs resident in HBM.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N = 2048
+CFL = 0.5
+MU, PR = 1e-4, 0.72
+PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector peak
+PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
+HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doubles, stage 2 reads 24 / writes 12
+# FP64 operations executed per interface point by the stage-1 interface sweep
+# (two GENO line reconstructions and two gas-kinetic solves), from the
+# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters of the same kernel; see the
+# profiles/ summary of that run.
+FLOPS_PER_IFACE_POINT_STAGE1 = None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=N)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-n", type=int, default=256, help="side of the oracle's timed sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(n):
+    """The oracle, unmodified, timed on this host: one full S2O4 step of the
+    same workload at n x n (same scheme and per-node work)."""
+    import ctypes
+
+    import numpy as np
+
+    import workloads as WL
+    from oracle import oracle as O
+    pr = WL.shear_layer(n, seed=0, mu=MU, prandtl=PR)
+    par = O.make_par(dim=2, nx=n, ny=n, lx=1.0, mu=MU, prandtl=PR)
+    dt = O.dt2d(par, pr.P, pr.D, CFL)
+    t0 = time.perf_counter()
+    O.step2d(par, pr.P, pr.D, 1, dt=dt)
+    sec = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    try:
+        lib = ctypes.CDLL(None)
+        f = getattr(lib, "omp_get_max_threads", None)
+        if f:
+            threads = int(f())
+    except OSError:
+        pass
+    del np
+    return {"value": 2 * n * n * 2 / sec, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"one S2O4 step (2 stages) of the {n}x{n} double shear layer (same parameters and per-node "
+                      f"work as the {N}x{N} workload), {sec:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU decomposition is described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workloads as WL
+    from paper_2606_17772_amd import Problem, make_params
+
+    torch.cuda.set_device(0)
+    n = args.n
+    pr = WL.shear_layer(n, seed=0, mu=MU, prandtl=PR)
+    prm = make_params(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, mu=MU, prandtl=PR)
+    pb = Problem(prm)
+    dev = torch.device("cuda:0")
+    # inputs resident in HBM before timing
+    for g, S in ((0, pr.P), (1, pr.D)):
+        T = torch.from_numpy(S).to(dev)
+        pb.set_state(g, T[0:4].contiguous(), T[4:8].contiguous(), T[8:12].contiguous())
+    torch.cuda.synchronize()
+    t = 0.0
+    if args.warmup:
+        t, _ = pb.step(nsteps=args.warmup, cfl=CFL, t=t)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    t, k = pb.step(nsteps=args.steps, cfl=CFL, t=t)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    assert k == args.steps
+    nodes = 2 * n * n
+    value = nodes * 2 * args.steps / (ms * 1e-3)
+    # per-kernel breakdown on the same stream (separate, untimed-for-value run)
+    _, _, kms = pb.step_timed(nsteps=max(2, args.steps // 4), cfl=CFL, t=t)
+    kn = max(2, args.steps // 4)
+    edge1_ms = kms["edge1"] / kn
+    iface_points = 2 * (n + 3) * (n + 3)
+    if FLOPS_PER_IFACE_POINT_STAGE1:
+        flops = FLOPS_PER_IFACE_POINT_STAGE1 * iface_points
+        achieved = flops / (edge1_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None}
+    else:
+        roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": None,
+                "traffic": None}
+    roof["kernel"] = "k_edges2d<1,double> (stage-1 interface sweep)"
+    roof["avg_launch_ms"] = round(edge1_ms, 4)
+    hbm_gbs = value * HBM_BYTES_PER_NODE_STAGE / 1e9
+    out = {
+        "metric": "node-updates/s per stage (FP64, 1 GPU)",
+        "value": value,
+        "unit": "node-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"2D Navier-Stokes double shear layer {n}x{n} primary + dual, Re=1e4, Pr=0.72, "
+                               "CFL 0.5, (6-4) GENO, FP64", "nodes_per_stage": nodes, "stages_per_step": 2},
+        "roofline": roof,
+        "hbm_roofline": {"algorithmic_bytes_per_node_stage": HBM_BYTES_PER_NODE_STAGE,
+                         "achieved_GBs": round(hbm_gbs, 1), "peak_GBs": PEAK_HBM_GBS,
+                         "frac": round(hbm_gbs / PEAK_HBM_GBS, 4)},
+        "kernel_ms_per_step": {k2: round(v / kn, 4) for k2, v in kms.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

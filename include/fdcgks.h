@@ -1,0 +1,171 @@
+/* fdcgks.h - C ABI of the MI355X (gfx950) FD-CGKS library (libfdcgks.so).
+ *
+ * The library advances the compressible Euler / Navier-Stokes equations with
+ * the finite-difference compact gas-kinetic scheme of Zhao, Chen & Xu,
+ * "Finite difference implementation of a high-order space-time coupled compact
+ * gas-kinetic scheme":
+ *   - conservative compact finite differences, Eq. (fd-conservative-form) and
+ *     (eq-conservation-law-2d), with the compact numerical flux of
+ *     Eq. (fd-conservative-flux) and its nonlinear (6-4) / (6-2) forms,
+ *     Eqs. (fd-conservative-flux-2) / (fd-conservative-flux-1);
+ *   - nodal values and interval-averaged derivatives evolved on a primary
+ *     grid and a dual grid offset by half a mesh size (Sec. 4);
+ *   - compact GENO reconstruction at virtual interfaces and nodes (Sec. 3,
+ *     App. C, App. D);
+ *   - the space-time coupled BGK gas-kinetic interface and nodal solver
+ *     (App. A), giving fluxes, their time derivatives and time-accurate
+ *     interface values;
+ *   - the two-stage fourth-order (S2O4) update of values and averaged
+ *     gradients, Eqs. (eq-nodal-update) and (eq-interface-update).
+ *
+ * Every call returns an fdcgks_status; no call aborts the process.  Pointers
+ * passed in are only read or written during the call (the library keeps no
+ * reference to caller memory).  All floating-point data are IEEE binary64.
+ *
+ * State layout at the boundary.  For one grid, W, Wx, Wy are each
+ * ncomp contiguous planes of ny*nx doubles, x fastest:
+ *   element (c, j, i) at  c*ny*nx + j*nx + i,
+ * with ncomp = 4 in 2D (rho, rho U, rho V, rho E) and 3 in 1D (rho, rho U,
+ * rho E).  Wx (Wy) holds the derivative averaged over the interval between
+ * the node's two x (y) interfaces, i.e. the Gauss difference of the interface
+ * values divided by the mesh size (Eq. define-averaged-gradient).
+ * Grid 0 is the primary grid: node (i, j) at (x0+(i+1/2)h, y0+(j+1/2)h).
+ * Grid 1 is the dual grid:    node (i, j) at (x0+(i+1)h,   y0+(j+1)h).
+ * In 1D grid 1 is an independent copy on the shifted nodes, advanced only when
+ * dual_1d is set.
+ */
+#ifndef FDCGKS_H
+#define FDCGKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FDCGKS_OK = 0,
+  FDCGKS_EINVAL = -1,   /* bad argument: sizes, NULL pointers, parameters out of range */
+  FDCGKS_ENOMEM = -2,   /* device allocation failed */
+  FDCGKS_EHIP = -3,     /* a HIP runtime call failed (message in fdcgks_last_error) */
+  FDCGKS_ENONPHYS = -4, /* a stage produced rho <= 0, p <= 0 or a NaN; state rolled back */
+  FDCGKS_ESTATE = -5    /* call out of order (e.g. step before set_state) */
+} fdcgks_status;
+
+enum { FDCGKS_BC_PERIODIC = 0, FDCGKS_BC_ZERO_GRADIENT = 1 };
+/* Numerical flux: (6-4) = Eq. fd-conservative-flux-2 with its low-order term
+ * divided by 6; (6-2) = Eq. fd-conservative-flux-1; LINEAR = linear compact
+ * flux and linear reconstruction (no GENO). */
+enum { FDCGKS_FLUX_6_4 = 0, FDCGKS_FLUX_6_2 = 1, FDCGKS_FLUX_LINEAR = 2 };
+/* Precision of the gas-kinetic solver; reconstruction and update stay FP64. */
+enum { FDCGKS_FP64 = 0, FDCGKS_FP32_FLUX = 1 };
+/* Base of the averaged-gradient update (Eq. eq-interface-update): the gradient
+ * re-evaluated from the stage-1 interface values (default) or the stored one. */
+enum { FDCGKS_GRAD_REEVAL = 0, FDCGKS_GRAD_CARRIED = 1 };
+
+typedef struct fdcgks_params {
+  int32_t dim;            /* 1 or 2 */
+  int32_t nx, ny;         /* primary nodes per axis (ny = 1 in 1D); 2D needs nx, ny >= 4 */
+  int32_t bc;             /* FDCGKS_BC_*: 1D periodic or zero-gradient; 2D periodic only */
+  int32_t dual_1d;        /* 1D: also advance the shifted copy (grid 1) */
+  int32_t flux_variant;   /* FDCGKS_FLUX_* */
+  int32_t flux_precision; /* FDCGKS_FP64 | FDCGKS_FP32_FLUX */
+  int32_t grad_update;    /* FDCGKS_GRAD_* */
+  int32_t geno_r;         /* exponent r of the GENO smoothness ratio, 1..8 (default 3) */
+  int32_t reserved;       /* must be 0 */
+  double x0, lx, y0, ly;  /* domain origin and lengths; 2D needs lx/nx == ly/ny */
+  double gamma;           /* ratio of specific heats, > 1 and < 5/3 (2D) or < 3 (1D) */
+  double mu;              /* dynamic viscosity; 0 = Euler */
+  double prandtl;         /* Prandtl number (used when mu > 0) */
+  double geno_C;          /* path-function constant C (20) */
+  double geno_eps;        /* epsilon of the GENO smoothness ratio (1e-15) */
+  double geno_eps_a;      /* epsilon of the low-order weights (1e-6) */
+  double geno_d_central;  /* ideal weight of the central sub-stencil (8) */
+  double geno_d_side;     /* ideal weight of the other two sub-stencils (1) */
+  double tau_c1;          /* Euler collision time tau = c1 dt + c2 dt |p_l-p_r|/(p_l+p_r) */
+  double tau_c2;          /*   (defaults c1 = 0, c2 = 1; with mu > 0 the first term is mu/p) */
+} fdcgks_params;
+
+typedef struct fdcgks_problem fdcgks_problem; /* opaque, owned by the library */
+
+/* Fill *p with the defaults (2D, 64x64 on [0,1]^2, periodic, gamma 1.4, Euler,
+ * (6-4) flux, FP64, GENO constants above). */
+void fdcgks_default_params(fdcgks_params* p);
+
+/* Validate *p, allocate the device planes on the current HIP device and bind
+ * the problem to `hip_stream` (a hipStream_t; NULL = the null stream).  All
+ * later work of the problem is enqueued on that stream.  *out receives the
+ * handle; on error *out is NULL and nothing is allocated. */
+fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_problem** out);
+
+/* Copy one grid's state in.  W, Wx must be non-NULL; Wy must be non-NULL in 2D
+ * and is ignored in 1D.  on_device = 1: device pointers (read on the problem's
+ * stream, no host synchronisation); 0: host pointers (synchronous).  Values
+ * with rho <= 0, p <= 0 or NaN are accepted here and reported by the first
+ * step as FDCGKS_ENONPHYS. */
+fdcgks_status fdcgks_set_state(fdcgks_problem* pb, int32_t grid, const double* W, const double* Wx,
+                               const double* Wy, int32_t on_device);
+
+/* Copy one grid's state out (same layout and on_device rule as set_state;
+ * with on_device = 0 the call waits for the stream). */
+fdcgks_status fdcgks_get_state(const fdcgks_problem* pb, int32_t grid, double* W, double* Wx, double* Wy,
+                               int32_t on_device);
+
+/* CFL time step of the current state (Sec. 5): dt = cfl h / max over all
+ * nodes of (max(|U|,|V|) + c); with mu > 0 also dt <= cfl h^2 / (8 mu/rho_min).
+ * Synchronous. */
+fdcgks_status fdcgks_compute_dt(fdcgks_problem* pb, double cfl, double* dt_out);
+
+/* Advance up to nsteps S2O4 steps.  dt > 0: fixed step; dt <= 0: CFL step
+ * recomputed on the device before every step.  t_end > 0 clips the last step
+ * so that t does not pass t_end and stops there.  *t_inout is the time before
+ * and after; *steps_done (may be NULL) the number of steps taken.  On
+ * FDCGKS_ENONPHYS the state is the one after the last good step and *t_inout,
+ * *steps_done describe it. */
+fdcgks_status fdcgks_step(fdcgks_problem* pb, double dt, double cfl, int32_t nsteps, double t_end,
+                          double* t_inout, int32_t* steps_done);
+
+/* fdcgks_step with a per-kernel device-time breakdown: a HIP event is
+ * recorded on the problem's stream after every kernel, and kernel_ms[8]
+ * receives the summed milliseconds between consecutive events for: halo fill,
+ * interface sweep (stage 1), node sweep (1), assemble+update (1), interface
+ * sweep (2), node sweep (2), assemble+update (2), step bookkeeping (CFL
+ * reduction, dt, time advance).  Synchronous. */
+fdcgks_status fdcgks_step_timed(fdcgks_problem* pb, double dt, double cfl, int32_t nsteps, double t_end,
+                                double* t_inout, int32_t* steps_done, double* kernel_ms);
+
+/* Free all device memory of the problem.  NULL is accepted. */
+fdcgks_status fdcgks_destroy(fdcgks_problem* pb);
+
+/* Message of the last failed call on this problem (or of the last failed
+ * create when pb is NULL).  Valid until the next call on the same problem. */
+const char* fdcgks_last_error(const fdcgks_problem* pb);
+
+/* ------------------------------------------------------------ diagnostics
+ * One stage without committing it, for stage-level comparison.  Stage 1
+ * starts from the current state, stage 2 from the internal stage-1 buffers
+ * left by the previous fdcgks_debug_stage(.., 1, ..) call, with the same dt.
+ * Host outputs: out_state[grid][12][ny][nx] (2D; 1D: [grid][6][nx]) holds the
+ * stage result (W*, grad W* after stage 1; W^{n+1}, grad W^{n+1} after stage
+ * 2); out_acc (stage 1 only, may be NULL) the accumulators
+ * W + dt L + dt^2/6 L_t and the base gradient.  Grids not present are not
+ * written. */
+fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, double* out_state,
+                                 double* out_acc);
+
+/* Per-interface and per-node intermediates of stage 1 at step dt from the
+ * current state (2D only).  Host outputs, each plane ny*nx:
+ *   edge_x, edge_y: [2 normals][25] planes for the interface families
+ *     X(i,j) at (x0+(i+1)h, y0+(j+1/2)h) and Y(i,j) at (x0+(i+1/2)h, y0+(j+1)h);
+ *     normal 0 = x, 1 = y; per normal: flux F[4], F_t[4], chi (path function
+ *     of rho, min of left/right), blended interface values Wl[4], Wr[4],
+ *     Wl_t[4], Wr_t[4] (Eq. W-model-2d);
+ *   node_p, node_d: [16] planes: nodal x-flux F[4], F_t[4], y-flux G[4], G_t[4]. */
+fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* edge_x, double* edge_y,
+                                         double* node_p, double* node_d);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDCGKS_H */

@@ -1,0 +1,199 @@
+"""FD-CGKS on MI355X: Python binding of libfdcgks.so.
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI (include/fdcgks.h).  PyTorch provides device memory and the
+stream; numpy arrays are accepted for host-side state exchange.
+
+    from paper_2606_17772_amd import Problem
+    pb = Problem(dim=2, nx=512, ny=512, lx=10.0, ly=10.0)
+    pb.set_state(0, W, Wx, Wy); pb.set_state(1, Wd, Wxd, Wyd)
+    t, n = pb.step(cfl=0.5, nsteps=10)
+    W, Wx, Wy = pb.get_state(0)
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import (BC_PERIODIC, BC_ZERO_GRADIENT, FLUX_6_2, FLUX_6_4, FLUX_LINEAR, FP32_FLUX, FP64,  # noqa: F401
+                   GRAD_CARRIED, GRAD_REEVAL, FdcgksError, Params)
+
+__all__ = ["Problem", "Params", "FdcgksError", "default_params", "make_params"]
+
+_VARIANTS = {"6-4": FLUX_6_4, "6-2": FLUX_6_2, "linear": FLUX_LINEAR}
+_BCS = {"periodic": BC_PERIODIC, "zero_gradient": BC_ZERO_GRADIENT}
+
+
+def default_params() -> Params:
+    p = Params()
+    _lib.load().fdcgks_default_params(C.byref(p))
+    return p
+
+
+def make_params(**kw) -> Params:
+    """fdcgks_params from keywords (names of the C struct; also
+    variant='6-4'|'6-2'|'linear', bc='periodic'|'zero_gradient',
+    fp32_flux=bool)."""
+    p = default_params()
+    kw = dict(kw)
+    if "variant" in kw:
+        v = kw.pop("variant")
+        p.flux_variant = _VARIANTS[v] if isinstance(v, str) else int(v)
+    if "bc" in kw and isinstance(kw["bc"], str):
+        kw["bc"] = _BCS[kw["bc"]]
+    if kw.pop("fp32_flux", False):
+        p.flux_precision = FP32_FLUX
+    if kw.pop("grad_carried", False):
+        p.grad_update = GRAD_CARRIED
+    if "dim" in kw and kw["dim"] == 1:
+        kw.setdefault("ny", 1)
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k!r}")
+        setattr(p, k, v)
+    if p.dim == 2 and "ly" not in kw:
+        p.ly = p.lx * p.ny / p.nx
+    return p
+
+
+def _torch():
+    import torch  # noqa: PLC0415
+    return torch
+
+
+def _current_stream():
+    try:
+        torch = _torch()
+        if torch.cuda.is_available():
+            return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    except ImportError:
+        pass
+    return C.c_void_p(None)
+
+
+def _ptr(a, writable=False):
+    """(pointer, on_device, keepalive) for a numpy array or torch tensor."""
+    if isinstance(a, np.ndarray):
+        if a.dtype != np.float64 or not a.flags.c_contiguous or (writable and not a.flags.writeable):
+            raise TypeError("numpy state arrays must be contiguous float64")
+        return C.c_void_p(a.ctypes.data), 0, a
+    torch = _torch()
+    if isinstance(a, torch.Tensor):
+        if a.dtype != torch.float64 or not a.is_contiguous():
+            raise TypeError("tensors must be contiguous float64")
+        return C.c_void_p(a.data_ptr()), (1 if a.is_cuda else 0), a
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+class Problem:
+    """One FD-CGKS problem on the current HIP device (see fdcgks_create)."""
+
+    def __init__(self, params: Params | None = None, stream=None, **kw):
+        self._L = _lib.load()
+        self.params = params if params is not None else make_params(**kw)
+        self._h = C.c_void_p()
+        s = _current_stream() if stream is None else C.c_void_p(stream)
+        _lib.check(self._L.fdcgks_create(C.byref(self.params), s, C.byref(self._h)))
+        p = self.params
+        self.ncomp = 4 if p.dim == 2 else 3
+        self.ngrid = 2 if (p.dim == 2 or p.dual_1d) else 1
+        self.shape = (self.ncomp, p.ny, p.nx)
+
+    # -- lifetime
+    def close(self):
+        if self._h:
+            self._L.fdcgks_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, st):
+        return _lib.check(st, self._h)
+
+    # -- state
+    def set_state(self, grid, W, Wx, Wy=None):
+        pw, dev, k1 = _ptr(W)
+        px, dev2, k2 = _ptr(Wx)
+        py, dev3, k3 = _ptr(Wy) if Wy is not None else (C.c_void_p(None), dev, None)
+        if len({dev, dev2, dev3}) != 1:
+            raise TypeError("W, Wx, Wy must all live on the host or all on the device")
+        for a in (W, Wx) + ((Wy,) if Wy is not None else ()):
+            if tuple(a.shape) not in (self.shape, (self.ncomp * self.params.ny * self.params.nx,)):
+                raise ValueError(f"state arrays must have shape {self.shape}")
+        self._chk(self._L.fdcgks_set_state(self._h, grid, pw, px, py, dev))
+
+    def set_state_stacked(self, grid, S):
+        """S: (12, ny, nx) (2D) or (6, N) (1D) stacked W, Wx[, Wy]."""
+        n = self.ncomp
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(-1, self.params.ny, self.params.nx)
+        self.set_state(grid, np.ascontiguousarray(S[:n]), np.ascontiguousarray(S[n:2 * n]),
+                       np.ascontiguousarray(S[2 * n:3 * n]) if self.params.dim == 2 else None)
+
+    def get_state(self, grid, device=None):
+        """Returns (W, Wx, Wy) as numpy (device=None) or torch tensors on `device`."""
+        if device is None:
+            out = [np.empty(self.shape) for _ in range(3 if self.params.dim == 2 else 2)]
+        else:
+            torch = _torch()
+            out = [torch.empty(self.shape, dtype=torch.float64, device=device)
+                   for _ in range(3 if self.params.dim == 2 else 2)]
+        ptrs = [_ptr(a, True) for a in out]
+        py = ptrs[2][0] if len(ptrs) == 3 else C.c_void_p(None)
+        self._chk(self._L.fdcgks_get_state(self._h, grid, ptrs[0][0], ptrs[1][0], py, ptrs[0][1]))
+        return tuple(out)
+
+    def get_state_stacked(self, grid):
+        return np.concatenate(self.get_state(grid), axis=0)
+
+    # -- time stepping
+    def compute_dt(self, cfl):
+        dt = C.c_double()
+        self._chk(self._L.fdcgks_compute_dt(self._h, cfl, C.byref(dt)))
+        return dt.value
+
+    def step(self, nsteps=1, dt=0.0, cfl=0.5, t_end=0.0, t=0.0):
+        """Advance up to nsteps; returns (t, steps_done)."""
+        tt = C.c_double(t)
+        n = C.c_int32()
+        self._chk(self._L.fdcgks_step(self._h, dt, cfl, nsteps, t_end, C.byref(tt), C.byref(n)))
+        return tt.value, n.value
+
+    KERNEL_CLASSES = ("halo", "edge1", "node1", "update1", "edge2", "node2", "update2", "step")
+
+    def step_timed(self, nsteps=1, dt=0.0, cfl=0.5, t_end=0.0, t=0.0):
+        """step() with per-kernel device milliseconds: returns (t, steps, {class: ms})."""
+        tt = C.c_double(t)
+        n = C.c_int32()
+        ms = (C.c_double * 8)()
+        self._chk(self._L.fdcgks_step_timed(self._h, dt, cfl, nsteps, t_end, C.byref(tt), C.byref(n), ms))
+        return tt.value, n.value, dict(zip(self.KERNEL_CLASSES, list(ms)))
+
+    # -- diagnostics
+    def debug_stage(self, stage, dt):
+        p = self.params
+        nf = 12 if p.dim == 2 else 6
+        out = np.zeros((self.ngrid, nf, p.ny, p.nx))
+        acc = np.zeros_like(out)
+        self._chk(self._L.fdcgks_debug_stage(self._h, stage, dt, C.c_void_p(out.ctypes.data),
+                                             C.c_void_p(acc.ctypes.data)))
+        return (out, acc) if stage == 1 else out
+
+    def debug_intermediates(self, dt):
+        p = self.params
+        ex = np.zeros((2, 25, p.ny, p.nx)); ey = np.zeros_like(ex)
+        npp = np.zeros((16, p.ny, p.nx)); nd = np.zeros_like(npp)
+        self._chk(self._L.fdcgks_debug_intermediates(self._h, dt, *(C.c_void_p(a.ctypes.data)
+                                                                   for a in (ex, ey, npp, nd))))
+        return ex, ey, npp, nd

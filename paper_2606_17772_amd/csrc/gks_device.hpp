@@ -1,0 +1,566 @@
+// Device arithmetic of the FD-CGKS stage for gfx950: compact GENO
+// reconstruction and the space-time coupled BGK gas-kinetic solver.
+//
+// Straight-line FP64 code (FP32 optional for the gas-kinetic part), fully
+// inlined so that every moment index is a compile-time constant and all
+// moment tables live in VGPRs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fdk {
+
+// Scheme constants, passed by value to every kernel.
+struct Consts {
+  double gamma;
+  double K;           // internal degrees of freedom: (4-2g)/(g-1) in 2D, (3-g)/(g-1) in 1D
+  double mu;          // dynamic viscosity (0: Euler)
+  double prfix;       // 1/Pr - 1 (applied when mu > 0)
+  double C, inv_tanhC, eps, eps_a, dc, ds;  // GENO (Sec. 3.2, App. D)
+  double tau_c1, tau_c2;
+  int r;              // GENO exponent
+  int variant;        // 0: (6-4), 1: (6-2), 2: linear
+  int grad_carried;
+  int pad;
+};
+
+// ---------------------------------------------------------------- math
+__device__ __forceinline__ double m_erfc(double x) { return erfc(x); }
+__device__ __forceinline__ float m_erfc(float x) { return erfcf(x); }
+__device__ __forceinline__ double m_exp(double x) { return exp(x); }
+__device__ __forceinline__ float m_exp(float x) { return expf(x); }
+__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
+__device__ __forceinline__ double m_abs(double x) { return fabs(x); }
+__device__ __forceinline__ float m_abs(float x) { return fabsf(x); }
+
+template <class T> __device__ __forceinline__ T sqr(T a) { return a * a; }
+
+__device__ __forceinline__ double ipow(double x, int r) {
+  double y = x;
+  for (int k = 1; k < r; ++k) y *= x;
+  return y;
+}
+
+// ----------------------------------------------------- GENO, Sec. 3 / App. C
+// Path function and blend of one side.  IS1 is the IS^tau reference;
+// d1, d2, d3 the ideal weights; q/dq the sub-stencil value/derivative
+// candidates; PH/PHx the high-order ones.  Normalised low-order weights are
+// d_k / t_k^2 (t_k = IS_k + eps_a) scaled by t1^2 t2^2 t3^2, so one division
+// normalises them.
+struct GenoOut {
+  double v, d, chi;
+};
+__device__ __forceinline__ GenoOut geno(const Consts& k, double IS1, double IS2, double IS3, double d1, double d2,
+                                        double d3, double q1, double q2, double q3, double dq1, double dq2,
+                                        double dq3, double PH, double PHx) {
+  double tau = 0.5 * fabs((IS2 + IS3) - 2.0 * IS1);
+  double ISH = fmax(IS1, fmax(IS2, IS3));
+  double ISL = fmin(IS1, fmin(IS2, IS3));
+  double eH = ISH + k.eps, eL = ISL + k.eps;
+  double inv = 1.0 / (eH * eL);
+  double xH = tau * eL * inv, xL = tau * eH * inv;
+  double aH = 1.0 + ipow(xH, k.r), aL = 1.0 + ipow(xL, k.r);
+  double alpha = 2.0 * aH / (aH + aL);
+  double chi = tanh(k.C * alpha) * k.inv_tanhC;
+  double t1 = sqr(IS1 + k.eps_a), t2 = sqr(IS2 + k.eps_a), t3 = sqr(IS3 + k.eps_a);
+  double w1 = d1 * t2 * t3, w2 = d2 * t1 * t3, w3 = d3 * t1 * t2;
+  double is = 1.0 / (w1 + w2 + w3);
+  double PL = (w1 * q1 + w2 * q2 + w3 * q3) * is;
+  double PLx = (w1 * dq1 + w2 * dq2 + w3 * dq3) * is;
+  GenoOut o;
+  o.v = chi * PH + (1.0 - chi) * PL;
+  o.d = chi * PHx + (1.0 - chi) * PLx;
+  o.chi = chi;
+  return o;
+}
+
+// Interface m+1/2 of a line q0..q3 = Q_{m-1..m+2}, x0..x3 = averaged
+// derivatives (Eq. 7th-compact-recons; App. C1, C2).
+struct IfaceRec {
+  double vl, dl, cl, vr, dr, cr;
+};
+__device__ __forceinline__ IfaceRec recon_iface(const Consts& k, double q0, double q1, double q2, double q3,
+                                                double x0, double x1, double x2, double x3, double h,
+                                                double invh) {
+  IfaceRec o;
+  double PHl = ((7.0 * q0 + 35.0 * q1 + 21.0 * q2 + q3) + (x0 + 22.0 * x1 - 7.0 * x2) * h) * (1.0 / 64.0);
+  double PHr = ((q0 + 21.0 * q1 + 35.0 * q2 + 7.0 * q3) + (7.0 * x1 - 22.0 * x2 - x3) * h) * (1.0 / 64.0);
+  double PHx = -((q0 + 45.0 * q1 - 45.0 * q2 - q3) + 9.0 * (x1 + x2) * h) * (invh * (1.0 / 30.0));
+  if (k.variant == 2) {
+    o.vl = PHl; o.dl = PHx; o.cl = 1.0;
+    o.vr = PHr; o.dr = PHx; o.cr = 1.0;
+    return o;
+  }
+  double hx0 = h * x0, hx3 = h * x3;
+  double D2 = sqr(q0 - 2.0 * q1 + q2), D3 = sqr(q1 - 2.0 * q2 + q3);
+  double dmid = (q2 - q1) * invh;
+  double qc = (-q0 + 6.0 * q1 + 3.0 * q2) * 0.125;  // q_2^l == q_3^r
+  // left (App. C1)
+  double ISl1 = (13.0 / 3.0) * sqr(q1 - q0 - hx0) + sqr(2.0 * (q1 - q0) - hx0);
+  double ISl2 = (13.0 / 12.0) * D2 + 0.25 * sqr(q2 - q0);
+  double ISl3 = (13.0 / 12.0) * D3 + 0.25 * sqr(3.0 * q1 - 4.0 * q2 + q3);
+  double ql1 = (-5.0 * q0 + 9.0 * q1 - 3.0 * hx0) * 0.25;
+  double ql3 = (3.0 * q1 + 6.0 * q2 - q3) * 0.125;
+  double dl1 = (-3.0 * q0 + 3.0 * q1 - 2.0 * hx0) * invh;
+  GenoOut L = geno(k, ISl1, ISl2, ISl3, k.ds, k.dc, k.ds, ql1, qc, ql3, dl1, dmid, dmid, PHl, PHx);
+  // right (App. C2)
+  double ISr1 = (13.0 / 3.0) * sqr(q2 - q3 + hx3) + sqr(2.0 * (q3 - q2) - hx3);
+  double ISr2 = (13.0 / 12.0) * D3 + 0.25 * sqr(q3 - q1);
+  double ISr3 = (13.0 / 12.0) * D2 + 0.25 * sqr(3.0 * q2 - 4.0 * q1 + q0);
+  double qr1 = (-5.0 * q3 + 9.0 * q2 + 3.0 * hx3) * 0.25;
+  double qr2 = (-q3 + 6.0 * q2 + 3.0 * q1) * 0.125;
+  double dr1 = (-3.0 * q2 + 3.0 * q3 - 2.0 * hx3) * invh;
+  GenoOut R = geno(k, ISr1, ISr2, ISr3, k.ds, k.dc, k.ds, qr1, qr2, qc, dr1, dmid, dmid, PHr, PHx);
+  o.vl = L.v; o.dl = L.d; o.cl = L.chi;
+  o.vr = R.v; o.dr = R.d; o.cr = R.chi;
+  return o;
+}
+
+// Node derivative from q0..q2 = Q_{j-1..j+1}, x0..x2 (Eq. 6th-compact-recons,
+// App. C3; the central sub-stencil is the IS^tau reference with weight dc).
+__device__ __forceinline__ double recon_node(const Consts& k, double q0, double q1, double q2, double x0, double x1,
+                                             double x2, double h, double invh) {
+  double PHx = (9.0 * (q0 - q2) + h * (x0 + 46.0 * x1 + x2)) * (invh * (1.0 / 30.0));
+  if (k.variant == 2) return PHx;
+  double hx0 = h * x0, hx2 = h * x2;
+  double IS1 = (13.0 / 3.0) * sqr(q1 - q0 - hx0) + sqr(2.0 * (q1 - q0) - hx0);
+  double IS2 = (13.0 / 3.0) * sqr(q2 - q1 - hx2) + sqr(2.0 * (q2 - q1) - hx2);
+  double IS3 = (13.0 / 12.0) * sqr(q0 - 2.0 * q1 + q2) + 0.25 * sqr(q2 - q0);
+  double dq1 = (-2.0 * q0 + 2.0 * q1 - hx0) * invh;
+  double dq2 = (-2.0 * q1 + 2.0 * q2 - hx2) * invh;
+  double dq3 = (q2 - q0) * (0.5 * invh);
+  GenoOut o = geno(k, IS3, IS1, IS2, k.dc, k.ds, k.ds, q1, q1, q1, dq3, dq1, dq2, q1, PHx);
+  return o.d;
+}
+
+// ------------------------------------------- Maxwellian moments (App. A)
+// Per unit density: mu[n] = <u^n> (full or half line), mv[n] = <v^n>,
+// x2 = <xi^2>, x4 = <xi^4>.
+template <class FT> struct Mom {
+  FT mu[7];
+  FT mv[7];
+  FT x2, x4;
+};
+
+template <class FT> __device__ __forceinline__ void mu_rec(FT* m, FT U, FT i2l) {
+#pragma unroll
+  for (int n = 0; n < 5; ++n) m[n + 2] = U * m[n + 1] + FT(n + 1) * i2l * m[n];
+}
+
+// <u^P v^Q xi^(2R) psi>, psi = (1, u, v, (u^2+v^2+xi^2)/2), R in {0, 1}
+template <int P, int Q, int R, class FT> __device__ __forceinline__ void muv(const Mom<FT>& m, FT o[4]) {
+  const FT xr = R == 0 ? FT(1) : m.x2;
+  const FT xr1 = R == 0 ? m.x2 : m.x4;
+  FT b = m.mu[P] * m.mv[Q];
+  o[0] = b * xr;
+  o[1] = m.mu[P + 1] * m.mv[Q] * xr;
+  o[2] = m.mu[P] * m.mv[Q + 1] * xr;
+  o[3] = FT(0.5) * ((m.mu[P + 2] * m.mv[Q] + m.mu[P] * m.mv[Q + 2]) * xr + b * xr1);
+}
+// <(s.psi) u^P v^Q psi>
+template <int P, int Q, class FT> __device__ __forceinline__ void ma(const FT s[4], const Mom<FT>& m, FT o[4]) {
+  FT t0[4], t1[4], t2[4], t3[4], t4[4], t5[4];
+  muv<P, Q, 0>(m, t0);
+  muv<P + 1, Q, 0>(m, t1);
+  muv<P, Q + 1, 0>(m, t2);
+  muv<P + 2, Q, 0>(m, t3);
+  muv<P, Q + 2, 0>(m, t4);
+  muv<P, Q, 1>(m, t5);
+  FT h3 = FT(0.5) * s[3];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) o[i] = s[0] * t0[i] + s[1] * t1[i] + s[2] * t2[i] + h3 * (t3[i] + t4[i] + t5[i]);
+}
+// 1D: psi = (1, u, (u^2+xi^2)/2)
+template <int P, int R, class FT> __device__ __forceinline__ void mu1(const Mom<FT>& m, FT o[3]) {
+  const FT xr = R == 0 ? FT(1) : m.x2;
+  const FT xr1 = R == 0 ? m.x2 : m.x4;
+  o[0] = m.mu[P] * xr;
+  o[1] = m.mu[P + 1] * xr;
+  o[2] = FT(0.5) * (m.mu[P + 2] * xr + m.mu[P] * xr1);
+}
+template <int P, class FT> __device__ __forceinline__ void ma1(const FT s[3], const Mom<FT>& m, FT o[3]) {
+  FT t0[3], t1[3], t2[3], t3[3];
+  mu1<P, 0>(m, t0);
+  mu1<P + 1, 0>(m, t1);
+  mu1<P + 2, 0>(m, t2);
+  mu1<P, 1>(m, t3);
+  FT h2 = FT(0.5) * s[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) o[i] = s[0] * t0[i] + s[1] * t1[i] + h2 * (t2[i] + t3[i]);
+}
+
+// Primitive variables and the shared v / xi moments of a state.
+template <class FT> struct Prim {
+  FT rho, irho, U, V, p, lam, i2l;
+};
+template <class FT, int DIM> __device__ __forceinline__ Prim<FT> prim(const FT* W, FT gamma) {
+  Prim<FT> s;
+  s.rho = W[0];
+  s.irho = FT(1) / W[0];
+  s.U = W[1] * s.irho;
+  s.V = DIM == 2 ? W[2] * s.irho : FT(0);
+  FT rE = W[DIM + 1];
+  s.p = (gamma - FT(1)) * (rE - FT(0.5) * s.rho * (s.U * s.U + s.V * s.V));
+  s.lam = s.rho / (FT(2) * s.p);
+  s.i2l = s.p * s.irho;  // 1/(2 lambda)
+  return s;
+}
+template <class FT, int DIM> __device__ __forceinline__ void mom_common(const Prim<FT>& s, FT K, Mom<FT>& m) {
+  m.mv[0] = FT(1);
+  m.mv[1] = s.V;
+  if (DIM == 2) mu_rec(m.mv, s.V, s.i2l);
+  m.x2 = K * s.i2l;
+  m.x4 = m.x2 * (K + FT(2)) * s.i2l;
+}
+template <class FT> __device__ __forceinline__ void mom_full(const Prim<FT>& s, Mom<FT>& m) {
+  m.mu[0] = FT(1);
+  m.mu[1] = s.U;
+  mu_rec(m.mu, s.U, s.i2l);
+}
+// half line: sgn = +1 (u > 0) or -1 (u < 0)
+template <class FT> __device__ __forceinline__ void mom_half(const Prim<FT>& s, FT sgn, Mom<FT>& m) {
+  FT sl = m_sqrt(s.lam);
+  m.mu[0] = FT(0.5) * m_erfc(-sgn * sl * s.U);
+  m.mu[1] = s.U * m.mu[0] + sgn * FT(0.5) * m_exp(-s.lam * s.U * s.U) / (sl * FT(1.7724538509055160273));
+  mu_rec(m.mu, s.U, s.i2l);
+}
+
+// Micro slope s with <psi (s.psi)> = d (d per unit density): closed-form
+// solution of the moment system.
+template <class FT, int DIM>
+__device__ __forceinline__ void slope(const Prim<FT>& q, FT K, const FT* d, FT* s) {
+  if (DIM == 2) {
+    FT e = q.U * q.U + q.V * q.V + (K + FT(2)) * q.i2l;
+    FT B = FT(2) * d[3] - e * d[0];
+    FT A = d[1] - q.U * d[0];
+    FT Cc = d[2] - q.V * d[0];
+    FT tl = FT(2) * q.lam;
+    s[3] = tl * tl / (K + FT(2)) * (B - FT(2) * q.U * A - FT(2) * q.V * Cc);
+    s[2] = tl * Cc - q.V * s[3];
+    s[1] = tl * A - q.U * s[3];
+    s[0] = d[0] - q.U * s[1] - q.V * s[2] - FT(0.5) * s[3] * e;
+  } else {
+    FT e = q.U * q.U + (K + FT(1)) * q.i2l;
+    FT B = FT(2) * d[2] - e * d[0];
+    FT A = d[1] - q.U * d[0];
+    FT tl = FT(2) * q.lam;
+    s[2] = tl * tl / (K + FT(1)) * (B - FT(2) * q.U * A);
+    s[1] = tl * A - q.U * s[2];
+    s[0] = d[0] - q.U * s[1] - FT(0.5) * s[2] * e;
+  }
+}
+
+// Integrated BGK time coefficients over [0, T] (equilibrium, its space and
+// time slope terms, non-equilibrium initial part, its slope term) and the
+// f^n / f_t^n fit of App. A1 from T = dt/2 and T = dt.
+template <class FT> struct TimeCoef {
+  FT c[5], ct[5], e1;  // e1 = exp(-dt/tau)
+};
+template <class FT> __device__ __forceinline__ TimeCoef<FT> time_coef(FT dt, FT tau) {
+  TimeCoef<FT> r;
+  FT Eh = m_exp(-FT(0.5) * dt / tau);
+  FT Ef = Eh * Eh;
+  FT Th = FT(0.5) * dt, Tf = dt;
+  FT qh[5], qf[5];
+  qh[0] = Th - tau * (FT(1) - Eh);
+  qf[0] = Tf - tau * (FT(1) - Ef);
+  qh[1] = tau * ((FT(2) * tau - Th) - (Th + FT(2) * tau) * Eh);
+  qf[1] = tau * ((FT(2) * tau - Tf) - (Tf + FT(2) * tau) * Ef);
+  qh[2] = FT(0.5) * Th * Th - tau * Th + tau * tau * (FT(1) - Eh);
+  qf[2] = FT(0.5) * Tf * Tf - tau * Tf + tau * tau * (FT(1) - Ef);
+  qh[3] = tau * (FT(1) - Eh);
+  qf[3] = tau * (FT(1) - Ef);
+  qh[4] = tau * ((Th + FT(2) * tau) * Eh - FT(2) * tau);
+  qf[4] = tau * ((Tf + FT(2) * tau) * Ef - FT(2) * tau);
+  FT idt = FT(1) / dt;
+  FT idt2 = FT(4) * idt * idt;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    r.c[k] = (FT(4) * qh[k] - qf[k]) * idt;
+    r.ct[k] = (qf[k] - FT(2) * qh[k]) * idt2;
+  }
+  r.e1 = Ef;
+  return r;
+}
+
+// ----------------------------------------- gas-kinetic interface solver
+// Local frame: the normal velocity is component 1 (u).  2D: W = (rho, rho u,
+// rho v, rho E), tangential slope Wt; 1D: W = (rho, rho u, rho E).
+// Outputs: flux F, its time derivative Ft, and the interface values
+// W-hat^{l,r} and their time derivatives (Eq. W-model).  VALUES = false skips
+// F and W-hat (stage 2 uses only the time derivatives).
+template <class FT, int DIM> struct GksIO {
+  FT WL[DIM + 2], WR[DIM + 2], nL[DIM + 2], nR[DIM + 2], Wt[DIM + 2];
+  FT F[DIM + 2], Ft[DIM + 2], Wl[DIM + 2], Wr[DIM + 2], Wlt[DIM + 2], Wrt[DIM + 2];
+};
+
+template <class FT, int DIM, bool VALUES>
+__device__ __forceinline__ void gks_iface(const Consts& k, FT dt, GksIO<FT, DIM>& io) {
+  constexpr int N = DIM + 2;
+  const FT K = FT(k.K), gam = FT(k.gamma);
+  Prim<FT> sL = prim<FT, DIM>(io.WL, gam), sR = prim<FT, DIM>(io.WR, gam);
+  Mom<FT> hL, fL, hR, fR;
+  mom_common<FT, DIM>(sL, K, hL);
+  mom_common<FT, DIM>(sR, K, hR);
+  mom_half(sL, FT(1), hL);
+  mom_half(sR, FT(-1), hR);
+  fL = hL;
+  mom_full(sL, fL);
+  fR = hR;
+  mom_full(sR, fR);
+  // <psi> over the half lines, and the compatibility state W0
+  FT pL[N], pR[N], W0[N];
+  if (DIM == 2) {
+    pL[0] = hL.mu[0]; pL[1] = hL.mu[1]; pL[2] = hL.mu[0] * hL.mv[1];
+    pL[3] = FT(0.5) * (hL.mu[2] + hL.mu[0] * (hL.mv[2] + hL.x2));
+    pR[0] = hR.mu[0]; pR[1] = hR.mu[1]; pR[2] = hR.mu[0] * hR.mv[1];
+    pR[3] = FT(0.5) * (hR.mu[2] + hR.mu[0] * (hR.mv[2] + hR.x2));
+  } else {
+    pL[0] = hL.mu[0]; pL[1] = hL.mu[1]; pL[2] = FT(0.5) * (hL.mu[2] + hL.mu[0] * hL.x2);
+    pR[0] = hR.mu[0]; pR[1] = hR.mu[1]; pR[2] = FT(0.5) * (hR.mu[2] + hR.mu[0] * hR.x2);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) W0[i] = sL.rho * pL[i] + sR.rho * pR[i];
+  Prim<FT> s0 = prim<FT, DIM>(W0, gam);
+  Mom<FT> m0;
+  mom_common<FT, DIM>(s0, K, m0);
+  mom_full(s0, m0);
+  // spatial micro slopes
+  FT aL[N], aR[N], a0[N], bL[N], bR[N], b0[N], d[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) d[i] = io.nL[i] * sL.irho;
+  slope<FT, DIM>(sL, K, d, aL);
+#pragma unroll
+  for (int i = 0; i < N; ++i) d[i] = io.nR[i] * sR.irho;
+  slope<FT, DIM>(sR, K, d, aR);
+#pragma unroll
+  for (int i = 0; i < N; ++i) d[i] = FT(0.5) * (io.nL[i] + io.nR[i]) * s0.irho;
+  slope<FT, DIM>(s0, K, d, a0);
+  if (DIM == 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = io.Wt[i] * sL.irho;
+    slope<FT, DIM>(sL, K, d, bL);
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = io.Wt[i] * sR.irho;
+    slope<FT, DIM>(sR, K, d, bR);
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = io.Wt[i] * s0.irho;
+    slope<FT, DIM>(s0, K, d, b0);
+  }
+  // transport moments <psi ((a.psi) u + (b.psi) v)> (full) and time slopes
+  FT tLf[N], tRf[N], t0[N], AL[N], AR[N], A0[N];
+  {
+    FT x[N], y[N];
+    if (DIM == 2) {
+      ma<1, 0>(aL, fL, x); ma<0, 1>(bL, fL, y);
+      for (int i = 0; i < N; ++i) tLf[i] = x[i] + y[i];
+      ma<1, 0>(aR, fR, x); ma<0, 1>(bR, fR, y);
+      for (int i = 0; i < N; ++i) tRf[i] = x[i] + y[i];
+      ma<1, 0>(a0, m0, x); ma<0, 1>(b0, m0, y);
+      for (int i = 0; i < N; ++i) t0[i] = x[i] + y[i];
+    } else {
+      ma1<1>(aL, fL, tLf);
+      ma1<1>(aR, fR, tRf);
+      ma1<1>(a0, m0, t0);
+    }
+    for (int i = 0; i < N; ++i) { x[i] = -tLf[i]; }
+    slope<FT, DIM>(sL, K, x, AL);
+    for (int i = 0; i < N; ++i) { x[i] = -tRf[i]; }
+    slope<FT, DIM>(sR, K, x, AR);
+    for (int i = 0; i < N; ++i) { x[i] = -t0[i]; }
+    slope<FT, DIM>(s0, K, x, A0);
+  }
+  // collision time and time coefficients
+  FT tau = (k.mu > 0 ? FT(k.mu) / s0.p : FT(k.tau_c1) * dt) +
+           FT(k.tau_c2) * dt * m_abs(sL.p - sR.p) / (sL.p + sR.p);
+  TimeCoef<FT> tc = time_coef(dt, tau);
+  // moments of every term of f^n against psi and u psi
+  FT u0[N], tu0[N], Ap0[N], Au0[N];                // equilibrium
+  FT uL[N], tLp[N], tLu[N], ApL[N], AuL[N];        // left half
+  FT uR[N], tRp[N], tRu[N], ApR[N], AuR[N];        // right half
+  FT p0[N];
+  if (DIM == 2) {
+    p0[0] = FT(1); p0[1] = s0.U; p0[2] = s0.V; p0[3] = FT(0.5) * (m0.mu[2] + m0.mv[2] + m0.x2);
+    muv<1, 0, 0>(m0, u0);
+    FT x[N], y[N];
+    ma<2, 0>(a0, m0, x); ma<1, 1>(b0, m0, y);
+    for (int i = 0; i < N; ++i) tu0[i] = x[i] + y[i];
+    ma<0, 0>(A0, m0, Ap0); ma<1, 0>(A0, m0, Au0);
+    muv<1, 0, 0>(hL, uL);
+    ma<1, 0>(aL, hL, x); ma<0, 1>(bL, hL, y);
+    for (int i = 0; i < N; ++i) tLp[i] = x[i] + y[i];
+    ma<2, 0>(aL, hL, x); ma<1, 1>(bL, hL, y);
+    for (int i = 0; i < N; ++i) tLu[i] = x[i] + y[i];
+    ma<0, 0>(AL, hL, ApL); ma<1, 0>(AL, hL, AuL);
+    muv<1, 0, 0>(hR, uR);
+    ma<1, 0>(aR, hR, x); ma<0, 1>(bR, hR, y);
+    for (int i = 0; i < N; ++i) tRp[i] = x[i] + y[i];
+    ma<2, 0>(aR, hR, x); ma<1, 1>(bR, hR, y);
+    for (int i = 0; i < N; ++i) tRu[i] = x[i] + y[i];
+    ma<0, 0>(AR, hR, ApR); ma<1, 0>(AR, hR, AuR);
+  } else {
+    p0[0] = FT(1); p0[1] = s0.U; p0[2] = FT(0.5) * (m0.mu[2] + m0.x2);
+    mu1<1, 0>(m0, u0);
+    ma1<2>(a0, m0, tu0);
+    ma1<0>(A0, m0, Ap0); ma1<1>(A0, m0, Au0);
+    mu1<1, 0>(hL, uL);
+    ma1<1>(aL, hL, tLp); ma1<2>(aL, hL, tLu);
+    ma1<0>(AL, hL, ApL); ma1<1>(AL, hL, AuL);
+    mu1<1, 0>(hR, uR);
+    ma1<1>(aR, hR, tRp); ma1<2>(aR, hR, tRu);
+    ma1<0>(AR, hR, ApR); ma1<1>(AR, hR, AuR);
+  }
+  // combine: coefficient index 0 g0, 1 slope term, 2 time-slope term,
+  // 3 (1 - tau A) g^s, 4 slope term of g^s
+  FT We[N], Wet[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    FT e0u = u0[i], e1u = tu0[i], e2u = Au0[i];
+    FT nLu = uL[i] - tau * AuL[i], nRu = uR[i] - tau * AuR[i];
+    FT e0p = p0[i], e1p = t0[i], e2p = Ap0[i];
+    FT nLp = pL[i] - tau * ApL[i], nRp = pR[i] - tau * ApR[i];
+    FT r0 = s0.rho, rl = sL.rho, rr = sR.rho;
+    io.Ft[i] = r0 * (tc.ct[0] * e0u + tc.ct[1] * e1u + tc.ct[2] * e2u) +
+               rl * (tc.ct[3] * nLu + tc.ct[4] * tLu[i]) + rr * (tc.ct[3] * nRu + tc.ct[4] * tRu[i]);
+    Wet[i] = r0 * (tc.ct[0] * e0p + tc.ct[1] * e1p + tc.ct[2] * e2p) +
+             rl * (tc.ct[3] * nLp + tc.ct[4] * tLp[i]) + rr * (tc.ct[3] * nRp + tc.ct[4] * tRp[i]);
+    if (VALUES || k.mu > 0) {
+      io.F[i] = r0 * (tc.c[0] * e0u + tc.c[1] * e1u + tc.c[2] * e2u) +
+                rl * (tc.c[3] * nLu + tc.c[4] * tLu[i]) + rr * (tc.c[3] * nRu + tc.c[4] * tRu[i]);
+      We[i] = r0 * (tc.c[0] * e0p + tc.c[1] * e1p + tc.c[2] * e2p) +
+              rl * (tc.c[3] * nLp + tc.c[4] * tLp[i]) + rr * (tc.c[3] * nRp + tc.c[4] * tRp[i]);
+    }
+  }
+  // Prandtl-number correction of the energy flux: (1/Pr - 1) times the heat
+  // flux 1/2 <(u-U0)((u-U0)^2 + (v-V0)^2 + xi^2)> of the same distribution,
+  // written with the moments of psi and u psi.
+  if (k.mu > 0) {
+    FT U = s0.U, V = s0.V, f = FT(k.prfix);
+    if (DIM == 2) {
+      FT a = FT(1.5) * U * U + FT(0.5) * V * V, b = FT(0.5) * U * (U * U + V * V);
+      FT q = io.F[3] - U * io.F[1] - V * io.F[2] + a * io.F[0] - U * We[3] + U * V * We[2] - b * We[0];
+      FT qt = io.Ft[3] - U * io.Ft[1] - V * io.Ft[2] + a * io.Ft[0] - U * Wet[3] + U * V * Wet[2] - b * Wet[0];
+      io.F[3] += f * q;
+      io.Ft[3] += f * qt;
+    } else {
+      FT a = FT(1.5) * U * U, b = FT(0.5) * U * U * U;
+      FT q = io.F[2] - U * io.F[1] + a * io.F[0] - U * We[2] - b * We[0];
+      FT qt = io.Ft[2] - U * io.Ft[1] + a * io.Ft[0] - U * Wet[2] - b * Wet[0];
+      io.F[2] += f * q;
+      io.Ft[2] += f * qt;
+    }
+  }
+  // interface values (Eq. W-model); one-sided time derivatives from the
+  // Euler transport of each side
+  FT e = tc.e1, oe = FT(1) - tc.e1;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    io.Wlt[i] = oe * Wet[i] - e * sL.rho * tLf[i];
+    io.Wrt[i] = oe * Wet[i] - e * sR.rho * tRf[i];
+    if (VALUES) {
+      io.Wl[i] = oe * We[i] + e * io.WL[i];
+      io.Wr[i] = oe * We[i] + e * io.WR[i];
+    }
+  }
+}
+
+// ------------------------------------------------ smooth nodal solver
+// f^n = g [1 - tauN ((a.psi) u + (b.psi) v + A.psi)], f_t = (A.psi) g.
+// Outputs x-flux F, Ft and (2D) y-flux G, Gt.  VALUES = false: F, G skipped.
+template <class FT, int DIM, bool VALUES>
+__device__ __forceinline__ void gks_node(const Consts& k, const FT* W, const FT* Wx, const FT* Wy, FT* F, FT* Ft,
+                                         FT* G, FT* Gt) {
+  constexpr int N = DIM + 2;
+  const FT K = FT(k.K);
+  Prim<FT> s = prim<FT, DIM>(W, FT(k.gamma));
+  Mom<FT> m;
+  mom_common<FT, DIM>(s, K, m);
+  mom_full(s, m);
+  FT a[N], b[N], A[N], d[N], tr[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) d[i] = Wx[i] * s.irho;
+  slope<FT, DIM>(s, K, d, a);
+  if (DIM == 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = Wy[i] * s.irho;
+    slope<FT, DIM>(s, K, d, b);
+    FT x[N], y[N];
+    ma<1, 0>(a, m, x); ma<0, 1>(b, m, y);
+    for (int i = 0; i < N; ++i) tr[i] = x[i] + y[i];
+  } else {
+    ma1<1>(a, m, tr);
+  }
+#pragma unroll
+  for (int i = 0; i < N; ++i) d[i] = -tr[i];
+  slope<FT, DIM>(s, K, d, A);
+  FT tauN = k.mu > 0 ? FT(k.mu) / s.p : FT(0);
+  const bool visc = k.mu > 0;
+  FT Fu[N], Gv[N];
+  if (DIM == 2) {
+    FT x[N], y[N], z[N];
+    ma<1, 0>(A, m, Fu);
+    ma<0, 1>(A, m, Gv);
+#pragma unroll
+    for (int i = 0; i < N; ++i) { Ft[i] = s.rho * Fu[i]; Gt[i] = s.rho * Gv[i]; }
+    if (VALUES || visc) {
+      FT u0[N], v0[N];
+      muv<1, 0, 0>(m, u0);
+      muv<0, 1, 0>(m, v0);
+      if (visc) {
+        ma<2, 0>(a, m, x); ma<1, 1>(b, m, y);
+        for (int i = 0; i < N; ++i) u0[i] -= tauN * (x[i] + y[i] + Fu[i]);
+        ma<1, 1>(a, m, x); ma<0, 2>(b, m, z);
+        for (int i = 0; i < N; ++i) v0[i] -= tauN * (x[i] + z[i] + Gv[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) { F[i] = s.rho * u0[i]; G[i] = s.rho * v0[i]; }
+    }
+    if (visc) {  // Prandtl correction with the node's velocity; W^e = W, W^e_t = -rho tr
+      FT U = s.U, V = s.V, f = FT(k.prfix);
+      FT ax = FT(1.5) * U * U + FT(0.5) * V * V, ay = FT(1.5) * V * V + FT(0.5) * U * U;
+      FT bx = FT(0.5) * U * (U * U + V * V), by = FT(0.5) * V * (U * U + V * V);
+      FT Wt0 = -s.rho * tr[0], Wt1 = -s.rho * tr[1], Wt2 = -s.rho * tr[2], Wt3 = -s.rho * tr[3];
+      FT qx = F[3] - U * F[1] - V * F[2] + ax * F[0] - U * W[3] + U * V * W[2] - bx * W[0];
+      FT qy = G[3] - V * G[2] - U * G[1] + ay * G[0] - V * W[3] + U * V * W[1] - by * W[0];
+      FT qxt = Ft[3] - U * Ft[1] - V * Ft[2] + ax * Ft[0] - U * Wt3 + U * V * Wt2 - bx * Wt0;
+      FT qyt = Gt[3] - V * Gt[2] - U * Gt[1] + ay * Gt[0] - V * Wt3 + U * V * Wt1 - by * Wt0;
+      F[3] += f * qx; G[3] += f * qy; Ft[3] += f * qxt; Gt[3] += f * qyt;
+    }
+  } else {
+    ma1<1>(A, m, Fu);
+#pragma unroll
+    for (int i = 0; i < N; ++i) Ft[i] = s.rho * Fu[i];
+    if (VALUES || visc) {
+      FT u0[N];
+      mu1<1, 0>(m, u0);
+      if (visc) {
+        FT x[N];
+        ma1<2>(a, m, x);
+        for (int i = 0; i < N; ++i) u0[i] -= tauN * (x[i] + Fu[i]);
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) F[i] = s.rho * u0[i];
+    }
+    if (visc) {
+      FT U = s.U, f = FT(k.prfix);
+      FT a1 = FT(1.5) * U * U, b1 = FT(0.5) * U * U * U;
+      FT Wt0 = -s.rho * tr[0], Wt2 = -s.rho * tr[2];
+      FT q = F[2] - U * F[1] + a1 * F[0] - U * W[2] - b1 * W[0];
+      FT qt = Ft[2] - U * Ft[1] + a1 * Ft[0] - U * Wt2 - b1 * Wt0;
+      F[2] += f * q; Ft[2] += f * qt;
+    }
+  }
+}
+
+// ---------------------------------------------------------- compact flux
+// Eq. fd-conservative-flux and its (6-4) / (6-2) nonlinear forms.
+__device__ __forceinline__ double compact_flux(int variant, double Fm, double Fc, double Fp, double N0, double N1,
+                                               double chi) {
+  double Fb = ((Fm + 46.0 * Fc + Fp) - 9.0 * (N0 + N1)) * (1.0 / 30.0);
+  if (variant == 2) return Fb;
+  double lo = variant == 1 ? Fc : (8.0 * Fc - N0 - N1) * (1.0 / 6.0);
+  return lo + chi * (Fb - lo);
+}
+
+}  // namespace fdk

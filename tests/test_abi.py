@@ -1,0 +1,73 @@
+"""The C-ABI library loads and exports every symbol include/fdcgks.h declares;
+argument validation happens before any device work (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "fdcgks.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdcgks_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    syms = header_symbols()
+    for s in ("fdcgks_create", "fdcgks_set_state", "fdcgks_get_state", "fdcgks_step", "fdcgks_compute_dt",
+              "fdcgks_destroy", "fdcgks_last_error", "fdcgks_default_params"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2606_17772_amd import _lib
+    L = _lib.load()
+    for s in header_symbols():
+        assert hasattr(L, s), s
+    assert set(header_symbols()) <= set(_lib.SIGNATURES), "binding must declare every ABI symbol"
+
+
+def test_params_struct_matches_header_size():
+    from paper_2606_17772_amd import Params
+    # 10 int32 + 14 doubles, naturally aligned
+    assert C.sizeof(Params) == 10 * 4 + 14 * 8
+
+
+def test_defaults():
+    from paper_2606_17772_amd import default_params
+    p = default_params()
+    assert (p.dim, p.nx, p.ny, p.geno_r) == (2, 64, 64, 3)
+    assert p.geno_C == 20.0 and p.geno_eps == 1e-15 and p.geno_eps_a == 1e-6
+    assert p.geno_d_central == 8.0 and p.geno_d_side == 1.0 and p.gamma == 1.4
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=3), dict(nx=3), dict(ny=2), dict(gamma=1.0), dict(gamma=1.7), dict(mu=-1.0),
+    dict(mu=1e-3, prandtl=0.0), dict(flux_variant=7), dict(flux_precision=5), dict(geno_r=0),
+    dict(geno_eps=0.0), dict(tau_c1=-1.0), dict(bc=1), dict(lx=0.0), dict(ly=2.0), dict(reserved=1),
+    dict(dim=1, nx=100, ny=2), dict(grad_update=3),
+])
+def test_create_rejects_bad_params(bad):
+    from paper_2606_17772_amd import _lib, default_params
+    L = _lib.load()
+    p = default_params()
+    for k, v in bad.items():
+        setattr(p, k, v)
+    h = C.c_void_p()
+    st = L.fdcgks_create(C.byref(p), None, C.byref(h))
+    assert st == _lib.EINVAL
+    assert not h.value
+    assert L.fdcgks_last_error(None)
+
+
+def test_null_arguments():
+    from paper_2606_17772_amd import _lib
+    L = _lib.load()
+    assert L.fdcgks_create(None, None, None) == _lib.EINVAL
+    assert L.fdcgks_destroy(None) == _lib.OK
+    t = C.c_double(0)
+    assert L.fdcgks_step(None, 0.1, 0.5, 1, 0.0, C.byref(t), None) == _lib.EINVAL
+    assert L.fdcgks_set_state(None, 0, None, None, None, 0) == _lib.EINVAL
