@@ -28,11 +28,16 @@ MU, PR = 1e-4, 0.72
 PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector peak
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doubles, stage 2 reads 24 / writes 12
-# FP64 operations executed per interface point by the stage-1 interface sweep
-# (two GENO line reconstructions and two gas-kinetic solves), from the
-# SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters of the same kernel; see the
-# profiles/ summary of that run.
-FLOPS_PER_IFACE_POINT_STAGE1 = None
+# Dominant kernel: the stage-1 interface sweep k_edges2d<1,double>.  Unit of
+# work: one interface point (two GENO line reconstructions, two gas-kinetic
+# solves, the blend); one launch processes 2 (n+3)^2 of them.  FP64 flops per
+# point and HBM bytes per launch are from the rocprofv3 counters of this
+# kernel (profiles/k_edges2d_shear2048.md: 64 x (ADD + MUL + 2 FMA + TRANS)
+# wave instructions; FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 after the
+# copy-kernel calibration).  Both are None whenever the kernel has changed
+# since the counters were taken.
+FLOPS_PER_IFACE_POINT_STAGE1 = 10412
+TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 5.392e9
 
 
 def parse():
@@ -42,7 +47,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=256, help="side of the oracle's timed sample")
+    ap.add_argument("--cpu-n", type=int, default=1024, help="side of the oracle's timed sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -87,6 +94,12 @@ def main():
     from paper_2606_17772_amd import Problem, make_params
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n = args.n
     pr = WL.shear_layer(n, seed=0, mu=MU, prandtl=PR)
     prm = make_params(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, mu=MU, prandtl=PR)
@@ -121,7 +134,7 @@ def main():
         flops = FLOPS_PER_IFACE_POINT_STAGE1 * iface_points
         achieved = flops / (edge1_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None}
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": TRAFFIC_BYTES_PER_LAUNCH_STAGE1}
     else:
         roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": None,
                 "traffic": None}
