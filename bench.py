@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -36,8 +38,8 @@ HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doub
 # wave instructions; FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 after the
 # copy-kernel calibration).  Both are None whenever the kernel has changed
 # since the counters were taken.
-FLOPS_PER_IFACE_POINT_STAGE1 = 10412
-TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 5.392e9
+FLOPS_PER_IFACE_POINT_STAGE1 = None
+TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = None
 
 
 def parse():
@@ -48,6 +50,8 @@ def parse():
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=1024, help="side of the oracle's timed sample")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-problem comparison")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -76,10 +80,49 @@ def cpu_baseline(n):
             threads = int(f())
     except OSError:
         pass
-    del np
     return {"value": 2 * n * n * 2 / sec, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"one S2O4 step (2 stages) of the {n}x{n} double shear layer (same parameters and per-node "
                       f"work as the {N}x{N} workload), {sec:.1f} s"}
+
+
+BATCH_CFL = 0.4  # the four-quadrant Riemann members need CFL <= 0.4 (the paper's tests use CFL >= 0.4)
+
+
+def batch_comparison(steps):
+    """64 independent 2D Euler problems (sides seeded in [64, 512]; vortex and
+    four-quadrant Riemann members, CFL 0.4) advanced by the batched persistent
+    launch and by a loop over single problems on the same GPU."""
+    import torch
+
+    import workloads as WL
+    from paper_2606_17772_amd import Batch, Problem, make_params
+    probs = WL.batch_problems(64, 64, 512, seed=0)
+    prms = [make_params(dim=2, nx=p.nx, ny=p.ny, lx=p.lx, ly=p.ly) for p in probs]
+    nodes = sum(2 * p.nx * p.ny for p in probs)
+    B = Batch(prms)
+    singles = [Problem(q) for q in prms]
+    for m, p in enumerate(probs):
+        for g, S in ((0, p.P), (1, p.D)):
+            B.set_state_stacked(m, g, S)
+            singles[m].set_state_stacked(g, S)
+    B.step(nsteps=1, cfl=BATCH_CFL)
+    for pb in singles:
+        pb.step(nsteps=1, cfl=BATCH_CFL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(nsteps=steps, cfl=BATCH_CFL)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for pb in singles:
+        pb.step(nsteps=steps, cfl=BATCH_CFL)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    same = all(np.array_equal(B.get_state_stacked(m, 0), singles[m].get_state_stacked(0)) for m in (0, 1, 63))
+    return {"members": len(probs), "nodes_per_stage": nodes, "steps": steps,
+            "batched_node_updates_per_s": nodes * 2 * steps / tb,
+            "per_problem_loop_node_updates_per_s": nodes * 2 * steps / ts,
+            "speedup": ts / tb, "bitwise_equal_sampled_members": bool(same)}
 
 
 def main():
@@ -162,6 +205,10 @@ def main():
                          "frac": round(hbm_gbs / PEAK_HBM_GBS, 4)},
         "kernel_ms_per_step": {k2: round(v / kn, 4) for k2, v in kms.items()},
     }
+    if not args.no_batch:
+        del pb
+        torch.cuda.empty_cache()
+        out["batched"] = batch_comparison(args.batch_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out), flush=True)

@@ -164,6 +164,29 @@ fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, d
 fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* edge_x, double* edge_y,
                                          double* node_p, double* node_d);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent periodic 2D problems of different sizes advanced together
+ * (same scheme constants, each member its own grid, mesh size and CFL time
+ * step): one cooperative persistent launch per S2O4 stage covers every
+ * member.  Same state layout and on_device rule as the single-problem calls. */
+typedef struct fdcgks_batch fdcgks_batch; /* opaque, owned by the library */
+
+/* params[count]: every member 2D periodic; members may differ only in nx, ny,
+ * x0, lx, y0, ly.  Allocates all device memory on the current device. */
+fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, void* hip_stream, fdcgks_batch** out);
+fdcgks_status fdcgks_batch_set_state(fdcgks_batch* b, int32_t member, int32_t grid, const double* W,
+                                     const double* Wx, const double* Wy, int32_t on_device);
+fdcgks_status fdcgks_batch_get_state(const fdcgks_batch* b, int32_t member, int32_t grid, double* W, double* Wx,
+                                     double* Wy, int32_t on_device);
+/* Advance every member nsteps steps with its own CFL time step.  Optional
+ * host outputs: t_out[count] (time since the batch was created), dt_out[count]
+ * (last step), *steps_done.  On FDCGKS_ENONPHYS every member is left after the
+ * last step all members completed. */
+fdcgks_status fdcgks_batch_step(fdcgks_batch* b, double cfl, int32_t nsteps, double* t_out, double* dt_out,
+                                int32_t* steps_done);
+fdcgks_status fdcgks_batch_destroy(fdcgks_batch* b);
+const char* fdcgks_batch_last_error(const fdcgks_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

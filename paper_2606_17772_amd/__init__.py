@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import (BC_PERIODIC, BC_ZERO_GRADIENT, FLUX_6_2, FLUX_6_4, FLUX_LINEAR, FP32_FLUX, FP64,  # noqa: F401
                    GRAD_CARRIED, GRAD_REEVAL, FdcgksError, Params)
 
-__all__ = ["Problem", "Params", "FdcgksError", "default_params", "make_params"]
+__all__ = ["Problem", "Batch", "Params", "FdcgksError", "default_params", "make_params"]
 
 _VARIANTS = {"6-4": FLUX_6_4, "6-2": FLUX_6_2, "linear": FLUX_LINEAR}
 _BCS = {"periodic": BC_PERIODIC, "zero_gradient": BC_ZERO_GRADIENT}
@@ -197,3 +197,59 @@ class Problem:
         self._chk(self._L.fdcgks_debug_intermediates(self._h, dt, *(C.c_void_p(a.ctypes.data)
                                                                    for a in (ex, ey, npp, nd))))
         return ex, ey, npp, nd
+
+
+class Batch:
+    """Many independent 2D problems advanced together (fdcgks_batch_*):
+    one cooperative persistent launch per stage for all members."""
+
+    def __init__(self, params_list, stream=None):
+        self._L = _lib.load()
+        n = len(params_list)
+        arr = (Params * n)(*params_list)
+        self.params = list(params_list)
+        self.count = n
+        self._h = C.c_void_p()
+        s = _current_stream() if stream is None else C.c_void_p(stream)
+        _lib.check(self._L.fdcgks_batch_create(n, arr, s, C.byref(self._h)), None, batch=True)
+
+    def close(self):
+        if self._h:
+            self._L.fdcgks_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def _chk(self, st):
+        return _lib.check(st, self._h, batch=True)
+
+    def set_state(self, member, grid, W, Wx, Wy):
+        pw, dev, _ = _ptr(W)
+        px, _, _ = _ptr(Wx)
+        py, _, _ = _ptr(Wy)
+        self._chk(self._L.fdcgks_batch_set_state(self._h, member, grid, pw, px, py, dev))
+
+    def set_state_stacked(self, member, grid, S):
+        p = self.params[member]
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape(12, p.ny, p.nx)
+        self.set_state(member, grid, np.ascontiguousarray(S[:4]), np.ascontiguousarray(S[4:8]),
+                       np.ascontiguousarray(S[8:12]))
+
+    def get_state_stacked(self, member, grid):
+        p = self.params[member]
+        out = [np.empty((4, p.ny, p.nx)) for _ in range(3)]
+        self._chk(self._L.fdcgks_batch_get_state(self._h, member, grid, *(C.c_void_p(a.ctypes.data) for a in out), 0))
+        return np.concatenate(out, axis=0)
+
+    def step(self, nsteps=1, cfl=0.5):
+        """Returns (t[count], dt_last[count], steps_done)."""
+        t = np.zeros(self.count)
+        dt = np.zeros(self.count)
+        n = C.c_int32()
+        self._chk(self._L.fdcgks_batch_step(self._h, cfl, nsteps, t.ctypes.data_as(C.POINTER(C.c_double)),
+                                            dt.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
+        return t, dt, n.value

@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfdcgks.so")
+# FDCGKS_LIB may point at another build of the same library (A/B timing).
+LIB_PATH = os.environ.get("FDCGKS_LIB") or os.path.join(HERE, "libfdcgks.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONPHYS, ESTATE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONPHYS", -5: "ESTATE"}
@@ -55,6 +56,12 @@ SIGNATURES = {
     "fdcgks_last_error": (C.c_char_p, [_vp]),
     "fdcgks_debug_stage": (C.c_int, [_vp, _i32, C.c_double, _vp, _vp]),
     "fdcgks_debug_intermediates": (C.c_int, [_vp, C.c_double, _vp, _vp, _vp, _vp]),
+    "fdcgks_batch_create": (C.c_int, [_i32, C.POINTER(Params), _vp, C.POINTER(_vp)]),
+    "fdcgks_batch_set_state": (C.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32]),
+    "fdcgks_batch_get_state": (C.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32]),
+    "fdcgks_batch_step": (C.c_int, [_vp, C.c_double, _i32, _dp, _dp, C.POINTER(_i32)]),
+    "fdcgks_batch_destroy": (C.c_int, [_vp]),
+    "fdcgks_batch_last_error": (C.c_char_p, [_vp]),
 }
 
 _lib = None
@@ -86,8 +93,9 @@ def load():
     return L
 
 
-def check(status, handle=None):
+def check(status, handle=None, batch=False):
     if status != OK:
-        msg = load().fdcgks_last_error(handle)
+        L = load()
+        msg = (L.fdcgks_batch_last_error if batch else L.fdcgks_last_error)(handle)
         raise FdcgksError(status, msg.decode() if msg else "")
     return status

@@ -19,8 +19,10 @@
 // sweep (nodal derivative GENO + smooth gas-kinetic flux) -> assemble+update.
 // The time step lives in device memory so steps never wait on the host.
 
+#include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -118,89 +120,108 @@ __device__ __forceinline__ void solve_dir(const Consts& k, FT dt, const fdk::Ifa
   }
 }
 
-// Everything at interface point (i, j) of family FAM (0: X, 1: Y).
-template <int STAGE, class FT, int FAM>
-__device__ __forceinline__ void edge_point(const double* __restrict__ S, double* __restrict__ E, const Geo& g,
-                                           const Consts& k, double dt, int i, int j) {
+// Reconstruction of one interface line.  Family FAM (0: X, 1: Y), grid G
+// (0: primary, 1: dual).  The line runs along y when FAM != G: X-primary
+// along x from P(i-1,j); X-dual along y from D(i,j-2); Y-primary along y
+// from P(i,j-1); Y-dual along x from D(i-2,j).
+template <int FAM, int G>
+__device__ __forceinline__ void edge_recon(const double* __restrict__ S, const Geo& g, const Consts& k, int i, int j,
+                                           fdk::IfaceRec (&rec)[4]) {
+  constexpr bool ALONG_Y = (FAM ^ G) != 0;
+  constexpr int back = G == 0 ? 1 : 2;
+  const long st = ALONG_Y ? g.pitch : 1;
+  const long o = ALONG_Y ? at(g, j - back, i) : at(g, j, i - back);
+  constexpr int f = ALONG_Y ? 2 : 1;  // derivative field along the line
   const long pl = g.plane;
-  // primary line: X along x from P(i-1,j); Y along y from P(i,j-1)
-  // dual line:    X along y from D(i,j-2); Y along x from D(i-2,j)
-  const long sP = FAM == 0 ? 1 : g.pitch, sD = FAM == 0 ? g.pitch : 1;
-  const long oP = FAM == 0 ? at(g, j, i - 1) : at(g, j - 1, i);
-  const long oD = FAM == 0 ? at(g, j - 2, i) : at(g, j, i - 2);
-  constexpr int fP = FAM == 0 ? 1 : 2, fD = FAM == 0 ? 2 : 1;  // derivative field along each line
-  fdk::IfaceRec rP[4], rD[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const double* w = S + (0 * 12 + c) * pl + oP;
-    const double* x = S + (0 * 12 + fP * 4 + c) * pl + oP;
-    rP[c] = fdk::recon_iface(k, w[0], w[sP], w[2 * sP], w[3 * sP], x[0], x[sP], x[2 * sP], x[3 * sP], g.h, g.invh);
-    const double* wd = S + (12 + c) * pl + oD;
-    const double* xd = S + (12 + fD * 4 + c) * pl + oD;
-    rD[c] = fdk::recon_iface(k, wd[0], wd[sD], wd[2 * sD], wd[3 * sD], xd[0], xd[sD], xd[2 * sD], xd[3 * sD], g.h,
-                             g.invh);
-  }
-  double tP[4], tD[4];  // tangential slopes: mean of the left/right line derivatives
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    tP[c] = 0.5 * (rP[c].dl + rP[c].dr);
-    tD[c] = 0.5 * (rD[c].dl + rD[c].dr);
-  }
-  double FPn[4], FPt[4], WPl[4], WPr[4], WPlt[4], WPrt[4];
-  double FDn[4], FDt[4], WDl[4], WDr[4], WDlt[4], WDrt[4];
-  solve_dir<FAM == 1, STAGE, FT>(k, (FT)dt, rP, tD, FPn, FPt, WPl, WPr, WPlt, WPrt);
-  solve_dir<FAM == 0, STAGE, FT>(k, (FT)dt, rD, tP, FDn, FDt, WDl, WDr, WDlt, WDrt);
-  // blend of the two directions (Eq. W-model-2d) and store
-  double* e = E + (long)FAM * 50 * pl + at(g, j, i);
-  e[8 * pl] = fmin(rP[0].cl, rP[0].cr);
-  e[(25 + 8) * pl] = fmin(rD[0].cl, rD[0].cr);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    double sPt = WPlt[c] + WPrt[c], sDt = WDlt[c] + WDrt[c];
-    e[(4 + c) * pl] = FPt[c];
-    e[(17 + c) * pl] = 0.5 * WPlt[c] + 0.25 * sDt;
-    e[(21 + c) * pl] = 0.5 * WPrt[c] + 0.25 * sDt;
-    e[(25 + 4 + c) * pl] = FDt[c];
-    e[(25 + 17 + c) * pl] = 0.5 * WDlt[c] + 0.25 * sPt;
-    e[(25 + 21 + c) * pl] = 0.5 * WDrt[c] + 0.25 * sPt;
-    if (STAGE == 1) {
-      double sP = WPl[c] + WPr[c], sD = WDl[c] + WDr[c];
-      e[(0 + c) * pl] = FPn[c];
-      e[(9 + c) * pl] = 0.5 * WPl[c] + 0.25 * sD;
-      e[(13 + c) * pl] = 0.5 * WPr[c] + 0.25 * sD;
-      e[(25 + 0 + c) * pl] = FDn[c];
-      e[(25 + 9 + c) * pl] = 0.5 * WDl[c] + 0.25 * sP;
-      e[(25 + 13 + c) * pl] = 0.5 * WDr[c] + 0.25 * sP;
-    }
+    const double* w = S + (G * 12 + c) * pl + o;
+    const double* x = S + (G * 12 + f * 4 + c) * pl + o;
+    rec[c] = fdk::recon_iface(k, w[0], w[st], w[2 * st], w[3 * st], x[0], x[st], x[2 * st], x[3 * st], g.h, g.invh);
   }
 }
 
-// One thread per interface point.  blockIdx.z = family: X over i in [-2, nx],
-// j in [-1, ny+1]; Y over i in [-1, nx+1], j in [-2, ny] (everything the
-// update of the interior reads).
+// One thread per (interface point, normal): blockDim (64, 4), threadIdx.y =
+// 2 * row + G, so every wave is one row of one line type and the partner
+// solve of the same point sits in the neighbouring wave.  fam: X covers
+// i in [-2, nx], j in [-1, ny+1]; Y covers i in [-1, nx+1], j in [-2, ny]
+// (everything the update of the interior reads); block (bx, by) covers 64
+// points in i and 2 in j.  The partners exchange tangential slopes and blend
+// sums through LDS.  Every thread of the block must call this.
 template <int STAGE, class FT>
-__global__ __launch_bounds__(256) void k_edges2d(const double* __restrict__ S, double* __restrict__ E, Geo g,
-                                                 Consts k, const Scal* __restrict__ sc) {
-  const int fam = blockIdx.z;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x + (fam == 0 ? -2 : -1);
-  const int j = blockIdx.y * blockDim.y + threadIdx.y + (fam == 0 ? -1 : -2);
-  if (i > (fam == 0 ? g.nx : g.nx + 1) || j > (fam == 0 ? g.ny + 1 : g.ny)) return;
-  if (sc->stop) return;
-  const double dt = sc->dt;
-  if (fam == 0) edge_point<STAGE, FT, 0>(S, E, g, k, dt, i, j);
-  else edge_point<STAGE, FT, 1>(S, E, g, k, dt, i, j);
+__device__ __forceinline__ void edge_block(const double* __restrict__ S, double* __restrict__ E, const Geo& g,
+                                           const Consts& k, double dt, int bx, int by, int fam) {
+  __shared__ double xch[4][8][64];
+  const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
+  const int i = bx * 64 + tx + (fam == 0 ? -2 : -1);
+  const int j = by * 2 + (ty >> 1) + (fam == 0 ? -1 : -2);
+  const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
+  fdk::IfaceRec rec[4];
+  if (valid) {
+    if (fam == 0) { if (G == 0) edge_recon<0, 0>(S, g, k, i, j, rec); else edge_recon<0, 1>(S, g, k, i, j, rec); }
+    else { if (G == 0) edge_recon<1, 0>(S, g, k, i, j, rec); else edge_recon<1, 1>(S, g, k, i, j, rec); }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) xch[ty][c][tx] = 0.5 * (rec[c].dl + rec[c].dr);
+  __syncthreads();
+  double tang[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) tang[c] = xch[ty ^ 1][c][tx];
+  double F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wl[4] = {0, 0, 0, 0}, Wr[4] = {0, 0, 0, 0};
+  double Wlt[4] = {0, 0, 0, 0}, Wrt[4] = {0, 0, 0, 0};
+  if (valid) {
+    // the normal is y when FAM != G (rho U and rho V swap in the local frame)
+    if (fam == G) solve_dir<false, STAGE, FT>(k, (FT)dt, rec, tang, F, Ft, Wl, Wr, Wlt, Wrt);
+    else solve_dir<true, STAGE, FT>(k, (FT)dt, rec, tang, F, Ft, Wl, Wr, Wlt, Wrt);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    xch[ty][c][tx] = Wlt[c] + Wrt[c];
+    if (STAGE == 1) xch[ty][4 + c][tx] = Wl[c] + Wr[c];
+  }
+  __syncthreads();
+  if (valid) {
+    // blend with the partner direction (Eq. W-model-2d) and store this normal's slot
+    double* e = E + ((long)fam * 50 + G * 25) * g.plane + at(g, j, i);
+    const long pl = g.plane;
+    e[8 * pl] = fmin(rec[0].cl, rec[0].cr);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double st = xch[ty ^ 1][c][tx];
+      e[(4 + c) * pl] = Ft[c];
+      e[(17 + c) * pl] = 0.5 * Wlt[c] + 0.25 * st;
+      e[(21 + c) * pl] = 0.5 * Wrt[c] + 0.25 * st;
+      if (STAGE == 1) {
+        const double sv = xch[ty ^ 1][4 + c][tx];
+        e[(0 + c) * pl] = F[c];
+        e[(9 + c) * pl] = 0.5 * Wl[c] + 0.25 * sv;
+        e[(13 + c) * pl] = 0.5 * Wr[c] + 0.25 * sv;
+      }
+    }
+  }
+  __syncthreads();  // the block may reuse xch for its next work item
+}
+
+template <int STAGE, class FT>
+__global__ __launch_bounds__(256, 2) void k_edges2d(const double* __restrict__ S, double* __restrict__ E, Geo g,
+                                                    Consts k, const Scal* __restrict__ sc) {
+  if (sc->stop) return;  // grid-uniform
+  edge_block<STAGE, FT>(S, E, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------ node sweep
-// Both grids (blockIdx.z), nodes i in [-1, nx], j in [-1, ny].
+// Nodes i in [-1, nx], j in [-1, ny] of grid `grid`; block (bx, by) of
+// 64 x 4 nodes.
 template <int STAGE, class FT>
-__global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, double* __restrict__ Nb, Geo g,
-                                                 Consts k, const Scal* __restrict__ sc) {
-  const int grid = blockIdx.z;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x - 1;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y - 1;
+__device__ __forceinline__ void node_block(const double* __restrict__ S, double* __restrict__ Nb, const Geo& g,
+                                           const Consts& k, int bx, int by, int grid) {
+  const int i = bx * 64 + threadIdx.x - 1;
+  const int j = by * 4 + threadIdx.y - 1;
   if (i > g.nx || j > g.ny) return;
-  if (sc->stop) return;
   const long pl = g.plane, o = at(g, j, i);
   const double* B = S + (long)grid * 12 * pl;
   FT W[4], Wx[4], Wy[4];
@@ -227,22 +248,30 @@ __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, d
   }
 }
 
+template <int STAGE, class FT>
+__global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, double* __restrict__ Nb, Geo g,
+                                                 Consts k, const Scal* __restrict__ sc) {
+  if (sc->stop) return;
+  node_block<STAGE, FT>(S, Nb, g, k, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
 // ------------------------------------------------------ assemble + update
 // Node (i, j) of grid `grid`, axis a: the interface family and normal slot
 // holding its a-fluxes, and the offset r of its right (upper) interface:
 // primary x -> X, slot 0, r = 0; primary y -> Y, slot 0, r = 0;
 // dual x -> Y, slot 1, r = 1;    dual y -> X, slot 1, r = 1.
+// Block (bx, by) of 64 x 4 interior nodes.  A non-physical result (rho <= 0,
+// p <= 0, NaN) sets the stop flag and records where (`member` names the
+// batch member, 0 for a single problem).
 template <int STAGE>
-__global__ __launch_bounds__(256) void k_update2d(const double* __restrict__ S, const double* __restrict__ E,
-                                                  const double* __restrict__ Nb, const double* __restrict__ Ain,
-                                                  double* __restrict__ Out, double* __restrict__ Aout, Geo g,
-                                                  Consts k, Scal* __restrict__ sc) {
-  const int grid = blockIdx.z;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j = blockIdx.y * blockDim.y + threadIdx.y;
+__device__ __forceinline__ void update_block(const double* __restrict__ S, const double* __restrict__ E,
+                                             const double* __restrict__ Nb, const double* __restrict__ Ain,
+                                             double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
+                                             const Consts& k, double dt, int bx, int by, int grid, Scal* sc,
+                                             int member) {
+  const int i = bx * 64 + threadIdx.x;
+  const int j = by * 4 + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
-  if (sc->stop) return;
-  const double dt = sc->dt;
   const long pl = g.plane, o = at(g, j, i);
   const int r = grid;
   double L[4] = {0, 0, 0, 0}, Lt[4] = {0, 0, 0, 0}, Gr[2][4], Grt[2][4];
@@ -303,12 +332,237 @@ __global__ __launch_bounds__(256) void k_update2d(const double* __restrict__ S, 
   double p = (k.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
   if (!(W[0] > 0.0) || !(p > 0.0)) {
     if (atomicCAS(&sc->stop, 0, 1) == 0) {
-      sc->fail_grid = grid;
+      sc->fail_grid = grid + 2 * member;
       sc->fail_i = i;
       sc->fail_j = j;
       sc->fail_stage = STAGE;
     }
   }
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_update2d(const double* __restrict__ S, const double* __restrict__ E,
+                                                  const double* __restrict__ Nb, const double* __restrict__ Ain,
+                                                  double* __restrict__ Out, double* __restrict__ Aout, Geo g,
+                                                  Consts k, Scal* __restrict__ sc) {
+  if (sc->stop) return;
+  update_block<STAGE>(S, E, Nb, Ain, Out, Aout, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z, sc, 0);
+}
+
+// ================================================================== 1D
+// A 1D problem is one line (grid 0) or two independent lines (grid 1 = the
+// copy on nodes shifted by h/2).  Planes have one interior row (j = 0):
+// state plane = line*6 + field*3 + comp (field 0 W, 1 Wx); interface buffer
+// plane = line*19 + q for the interface j+1/2 stored at column j, j in
+// [-2, N]: F[3], Ft[3], chi, Wl[3], Wr[3], Wlt[3], Wrt[3]; node buffer plane
+// = line*6 + q at column j in [-1, N]: F[3], Ft[3].
+// One workgroup advances every line of the problem through whole steps:
+// block barriers separate halo fill, interface and node sweeps, and update;
+// interface and node results stay in global memory (cache resident at these
+// sizes).
+
+// ghost cells: periodic, or zero-gradient (copy W, zero derivative)
+__device__ __forceinline__ void halo1d(double* __restrict__ S, const Geo& g, int lines, int bc) {
+  const long pl = g.plane;
+  for (int q = threadIdx.x; q < lines * 6 * 2 * HALO; q += blockDim.x) {
+    int gh = q % (2 * HALO), p = q / (2 * HALO);
+    int f = (p % 6) / 3;
+    int i = gh < HALO ? gh - HALO : g.nx + (gh - HALO);
+    double* P = S + p * pl;
+    if (bc == FDCGKS_BC_PERIODIC) P[at(g, 0, i)] = P[at(g, 0, imod(i, g.nx))];
+    else P[at(g, 0, i)] = f == 0 ? P[at(g, 0, i < 0 ? 0 : g.nx - 1)] : 0.0;
+  }
+}
+
+template <int STAGE, class FT>
+__device__ void stage1d_block(double* __restrict__ S, const double* __restrict__ Ain, double* __restrict__ Out,
+                              double* __restrict__ Aout, double* __restrict__ E, double* __restrict__ Nb,
+                              const Geo& g, const Consts& k, int lines, int bc, double dt, int* sfail,
+                              Scal* __restrict__ sc) {
+  const long pl = g.plane;
+  const int N = g.nx;
+  halo1d(S, g, lines, bc);
+  __syncthreads();
+  // interfaces j+1/2 for j in [-2, N]
+  for (int q = threadIdx.x; q < lines * (N + 3); q += blockDim.x) {
+    const int l = q / (N + 3), j = q % (N + 3) - 2;
+    const double* B = S + (long)l * 6 * pl;
+    fdk::GksIO<FT, 1> io;
+    double chi = 1.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double* w = B + c * pl + at(g, 0, j - 1);
+      const double* x = B + (3 + c) * pl + at(g, 0, j - 1);
+      fdk::IfaceRec r = fdk::recon_iface(k, w[0], w[1], w[2], w[3], x[0], x[1], x[2], x[3], g.h, g.invh);
+      io.WL[c] = (FT)r.vl; io.WR[c] = (FT)r.vr; io.nL[c] = (FT)r.dl; io.nR[c] = (FT)r.dr; io.Wt[c] = FT(0);
+      if (c == 0) chi = fmin(r.cl, r.cr);
+    }
+    fdk::gks_iface<FT, 1, STAGE == 1>(k, (FT)dt, io);
+    double* e = E + (long)l * 19 * pl + at(g, 0, j);
+    e[6 * pl] = chi;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      e[(3 + c) * pl] = (double)io.Ft[c];
+      e[(13 + c) * pl] = (double)io.Wlt[c];
+      e[(16 + c) * pl] = (double)io.Wrt[c];
+      if (STAGE == 1) {
+        e[c * pl] = (double)io.F[c];
+        e[(7 + c) * pl] = (double)io.Wl[c];
+        e[(10 + c) * pl] = (double)io.Wr[c];
+      }
+    }
+  }
+  // nodes j in [-1, N]
+  for (int q = threadIdx.x; q < lines * (N + 2); q += blockDim.x) {
+    const int l = q / (N + 2), j = q % (N + 2) - 1;
+    const double* B = S + (long)l * 6 * pl;
+    FT W[3], Wx[3], F[3], Ft[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double* w = B + c * pl + at(g, 0, j);
+      const double* x = B + (3 + c) * pl + at(g, 0, j);
+      W[c] = (FT)w[0];
+      Wx[c] = (FT)fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
+    }
+    fdk::gks_node<FT, 1, STAGE == 1>(k, W, Wx, (const FT*)nullptr, F, Ft, (FT*)nullptr, (FT*)nullptr);
+    double* n = Nb + (long)l * 6 * pl + at(g, 0, j);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      n[(3 + c) * pl] = (double)Ft[c];
+      if (STAGE == 1) n[c * pl] = (double)F[c];
+    }
+  }
+  __syncthreads();
+  // assemble + S2O4 update of the interior nodes
+  for (int q = threadIdx.x; q < lines * N; q += blockDim.x) {
+    const int l = q / N, j = q % N;
+    const double* e = E + (long)l * 19 * pl + at(g, 0, j);
+    const double* n = Nb + (long)l * 6 * pl + at(g, 0, j);
+    const double* s = S + (long)l * 6 * pl + at(g, 0, j);
+    double* out = Out + (long)l * 6 * pl + at(g, 0, j);
+    const double chiR = e[6 * pl], chiL = e[6 * pl - 1];
+    double W[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double* f = e + c * pl;
+      const double* ft = e + (3 + c) * pl;
+      const double* nf = n + c * pl;
+      const double* nft = n + (3 + c) * pl;
+      double FRt = fdk::compact_flux(k.variant, ft[-1], ft[0], ft[1], nft[0], nft[1], chiR);
+      double FLt = fdk::compact_flux(k.variant, ft[-2], ft[-1], ft[0], nft[-1], nft[0], chiL);
+      double Lt = -(FRt - FLt) * g.invh;
+      double Gt = (e[(13 + c) * pl] - e[(16 + c) * pl - 1]) * g.invh;
+      if (STAGE == 1) {
+        double FR = fdk::compact_flux(k.variant, f[-1], f[0], f[1], nf[0], nf[1], chiR);
+        double FL = fdk::compact_flux(k.variant, f[-2], f[-1], f[0], nf[-1], nf[0], chiL);
+        double L = -(FR - FL) * g.invh;
+        double G = (e[(7 + c) * pl] - e[(10 + c) * pl - 1]) * g.invh;
+        if (k.grad_carried) G = s[(3 + c) * pl];
+        double w = s[c * pl];
+        double* ao = Aout + (long)l * 6 * pl + at(g, 0, j);
+        W[c] = w + 0.5 * dt * L + 0.125 * dt * dt * Lt;
+        out[c * pl] = W[c];
+        out[(3 + c) * pl] = G + 0.5 * dt * Gt;
+        ao[c * pl] = w + dt * L + dt * dt / 6.0 * Lt;
+        ao[(3 + c) * pl] = G;
+      } else {
+        const double* ai = Ain + (long)l * 6 * pl + at(g, 0, j);
+        W[c] = ai[c * pl] + dt * dt / 3.0 * Lt;
+        out[c * pl] = W[c];
+        out[(3 + c) * pl] = ai[(3 + c) * pl] + dt * Gt;
+      }
+    }
+    double p = (k.gamma - 1.0) * (W[2] - 0.5 * W[1] * W[1] / W[0]);
+    if (!(W[0] > 0.0) || !(p > 0.0)) {
+      if (atomicCAS(sfail, 0, 1) == 0) {
+        sc->fail_grid = l;
+        sc->fail_i = j;
+        sc->fail_j = 0;
+        sc->fail_stage = STAGE;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Whole 1D run in one workgroup.  mode 0: up to nsteps steps, ping-pong
+// between S0 and S1 starting from S0; mode 1 / 2: one stage at sc->dt into
+// Sstar/Acc (1) or S1 (2), not committed.
+template <class FT>
+__global__ __launch_bounds__(256) void k_run1d(double* S0, double* S1, double* Sstar, double* Acc, double* E,
+                                               double* Nb, Geo g, Consts k, Scal* sc, int lines, int bc,
+                                               int nsteps, double cfl, int use_cfl, int mode) {
+  __shared__ double rmax[256], rmin[256];
+  __shared__ double sdt;
+  __shared__ int sfail, sstop;
+  if (threadIdx.x == 0) { sfail = 0; sstop = sc->stop; }
+  __syncthreads();
+  if (sstop) return;
+  if (mode == 1 || mode == 2) {
+    const double dt = sc->dt;
+    if (mode == 1) stage1d_block<1, FT>(S0, nullptr, Sstar, Acc, E, Nb, g, k, lines, bc, dt, &sfail, sc);
+    else stage1d_block<2, FT>(Sstar, Acc, S1, nullptr, E, Nb, g, k, lines, bc, dt, &sfail, sc);
+    if (threadIdx.x == 0 && sfail) sc->stop |= 1;
+    return;
+  }
+  double* cur = S0;
+  double* nxt = S1;
+  const long pl = g.plane;
+  for (int st = 0; st < nsteps; ++st) {
+    // time step: CFL over every node of every line (or the fixed dt), clipped to t_end
+    double vmax = 0.0, rm = 1e300;
+    if (use_cfl)
+      for (int q = threadIdx.x; q < lines * g.nx; q += blockDim.x) {
+        const int l = q / g.nx, j = q % g.nx;
+        const double* B = cur + (long)l * 6 * pl + at(g, 0, j);
+        double rho = B[0], U = B[pl] / rho, rE = B[2 * pl];
+        double p = (k.gamma - 1.0) * (rE - 0.5 * rho * U * U);
+        vmax = fmax(vmax, fabs(U) + sqrt(k.gamma * p / rho));
+        rm = fmin(rm, rho);
+      }
+    rmax[threadIdx.x] = vmax;
+    rmin[threadIdx.x] = rm;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) {
+        rmax[threadIdx.x] = fmax(rmax[threadIdx.x], rmax[threadIdx.x + w]);
+        rmin[threadIdx.x] = fmin(rmin[threadIdx.x], rmin[threadIdx.x + w]);
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      double dt = sc->dt_fixed;
+      if (use_cfl) {
+        dt = cfl * g.h / rmax[0];
+        if (k.mu > 0) dt = fmin(dt, cfl * g.h * g.h / (8.0 * k.mu / rmin[0]));
+      }
+      int stop = 0;
+      if (sc->t_end > 0) {
+        if (sc->t >= sc->t_end) stop = 2;
+        else if (sc->t + dt > sc->t_end) dt = sc->t_end - sc->t;
+      }
+      if (!stop && !(dt > 0.0)) { stop = 1; sc->fail_stage = 0; }
+      sc->stop |= stop;
+      sstop = stop;
+      sdt = dt;
+      sc->dt = dt;
+    }
+    __syncthreads();
+    if (sstop) break;
+    const double dt = sdt;
+    stage1d_block<1, FT>(cur, nullptr, Sstar, Acc, E, Nb, g, k, lines, bc, dt, &sfail, sc);
+    if (sfail) break;
+    stage1d_block<2, FT>(Sstar, Acc, nxt, nullptr, E, Nb, g, k, lines, bc, dt, &sfail, sc);
+    if (sfail) break;
+    if (threadIdx.x == 0) {
+      sc->t += dt;
+      sc->steps += 1;
+    }
+    double* tmp = cur;
+    cur = nxt;
+    nxt = tmp;
+  }
+  if (threadIdx.x == 0 && sfail) sc->stop |= 1;
 }
 
 // ------------------------------------------------------------ CFL / step
@@ -396,6 +650,167 @@ __global__ void k_step_end(Scal* __restrict__ sc) {
   if (sc->stop) return;
   sc->t += sc->dt;
   sc->steps += 1;
+}
+
+// ============================================================ batched 2D
+// Many independent periodic 2D problems of different sizes advanced together:
+// one cooperative persistent launch per stage.  Work items of every phase
+// are listed on the host (member, family/grid, block x, block y) and taken
+// round-robin by the resident workgroups; grid-wide barriers separate the
+// phases.  Each member keeps its own padded planes, mesh size and CFL time
+// step; all members share the scheme constants.
+struct BMember {
+  Geo g;
+  double* S[2];
+  double* Sstar;
+  double* Acc;
+  double* E;
+  double* Nb;
+};
+struct BItem {
+  int m, z, bx, by;
+};
+struct BArgs {
+  const BMember* mem;
+  int count;
+  const BItem* items;  // concatenated: cfl, halo, edges, nodes, updates
+  int n_cfl, n_halo, n_edge, n_node, n_upd;
+  double cfl;
+  int parity;          // step parity: selects the CFL slots of this step
+  int cur;             // which of S[0], S[1] holds the state at the start of the step
+  unsigned long long* slots;  // [2 parities][2: max speed, min rho][count] as ordered bit patterns
+  double* t;           // per-member time
+  double* dt_last;     // per-member last dt
+  Scal* sc;            // shared stop flag / failure record
+};
+
+__device__ __forceinline__ double member_dt(const BArgs& a, int m, const Consts& k) {
+  const unsigned long long* sl = a.slots + (long)a.parity * 2 * a.count;
+  double smax = __longlong_as_double((long long)sl[m]);
+  double rmin = __longlong_as_double((long long)sl[a.count + m]);
+  const Geo& g = a.mem[m].g;
+  double dt = a.cfl * g.h / smax;
+  if (k.mu > 0) dt = fmin(dt, a.cfl * g.h * g.h / (8.0 * k.mu / rmin));
+  return dt;
+}
+
+// CFL partial of one member over rows [16 by, 16 by + 16) of both grids.
+__device__ __forceinline__ void cfl_block(const BArgs& a, const Consts& k, const BItem& it, double* red) {
+  const BMember& M = a.mem[it.m];
+  const Geo& g = M.g;
+  const double* S = M.S[a.cur];
+  const int nthr = blockDim.x * blockDim.y, tid = threadIdx.y * blockDim.x + threadIdx.x;
+  double vmax = 0.0, rmin = 1e300;
+  const int j0 = it.by * 16, j1 = min(g.ny, j0 + 16);
+  for (int q = tid; q < 2 * (j1 - j0) * g.nx; q += nthr) {
+    int i = q % g.nx, r = q / g.nx, j = j0 + r % (j1 - j0), gr = r / (j1 - j0);
+    const double* B = S + (long)gr * 12 * g.plane + at(g, j, i);
+    double rho = B[0], U = B[g.plane] / rho, V = B[2 * g.plane] / rho;
+    double p = (k.gamma - 1.0) * (B[3 * g.plane] - 0.5 * rho * (U * U + V * V));
+    vmax = fmax(vmax, fmax(fabs(U), fabs(V)) + sqrt(k.gamma * p / rho));
+    rmin = fmin(rmin, rho);
+  }
+  red[tid] = vmax;
+  red[nthr + tid] = rmin;
+  __syncthreads();
+  for (int w = nthr / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[tid] = fmax(red[tid], red[tid + w]);
+      red[nthr + tid] = fmin(red[nthr + tid], red[nthr + tid + w]);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    unsigned long long* sl = a.slots + (long)a.parity * 2 * a.count;
+    // positive doubles order like their bit patterns
+    atomicMax(&sl[it.m], (unsigned long long)__double_as_longlong(red[0]));
+    atomicMin(&sl[a.count + it.m], (unsigned long long)__double_as_longlong(red[nthr]));
+  }
+  __syncthreads();
+}
+
+// Periodic halo of one state plane (rows, then whole columns).
+__device__ __forceinline__ void halo_plane_block(double* __restrict__ P, const Geo& g) {
+  const int nthr = blockDim.x * blockDim.y, tid = threadIdx.y * blockDim.x + threadIdx.x;
+  for (int q = tid; q < 2 * HALO * g.nx; q += nthr) {
+    int i = q % g.nx, hr = q / g.nx;
+    int j = hr < HALO ? hr - HALO : g.ny + (hr - HALO);
+    P[at(g, j, i)] = P[at(g, imod(j, g.ny), i)];
+  }
+  __syncthreads();
+  for (int q = tid; q < (g.ny + 2 * HALO) * 2 * HALO; q += nthr) {
+    int hc = q % (2 * HALO), j = q / (2 * HALO) - HALO;
+    int i = hc < HALO ? hc - HALO : g.nx + (hc - HALO);
+    P[at(g, j, i)] = P[at(g, j, imod(i, g.nx))];
+  }
+  __syncthreads();
+}
+
+template <int STAGE, class FT>
+__global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
+  namespace cg = cooperative_groups;
+  cg::grid_group grid = cg::this_grid();
+  __shared__ double red[512];
+  const BItem* it = a.items;
+  const int nb = gridDim.x;
+  // phase A: (stage 1) CFL partials of every member, reset of the next
+  // step's slots; halo of the stage input
+  if (STAGE == 1) {
+    if (blockIdx.x == 0)
+      for (int q = threadIdx.y * blockDim.x + threadIdx.x; q < a.count; q += blockDim.x * blockDim.y) {
+        unsigned long long* nx = a.slots + (long)(a.parity ^ 1) * 2 * a.count;
+        nx[q] = 0ull;
+        nx[a.count + q] = (unsigned long long)__double_as_longlong(1e300);
+      }
+    for (int q = blockIdx.x; q < a.n_cfl; q += nb) cfl_block(a, k, it[q], red);
+  }
+  it += a.n_cfl;
+  for (int q = blockIdx.x; q < a.n_halo; q += nb) {
+    const BMember& M = a.mem[it[q].m];
+    double* S = STAGE == 1 ? M.S[a.cur] : M.Sstar;
+    halo_plane_block(S + (long)it[q].z * M.g.plane, M.g);
+  }
+  it += a.n_halo;
+  grid.sync();
+  // phase B: interfaces and nodes
+  const bool stopped = a.sc->stop != 0;
+  if (!stopped) {
+    for (int q = blockIdx.x; q < a.n_edge; q += nb) {
+      const BItem& w = it[q];
+      const BMember& M = a.mem[w.m];
+      edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z);
+    }
+  }
+  it += a.n_edge;
+  if (!stopped) {
+    for (int q = blockIdx.x; q < a.n_node; q += nb) {
+      const BItem& w = it[q];
+      const BMember& M = a.mem[w.m];
+      node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z);
+    }
+  }
+  it += a.n_node;
+  grid.sync();
+  // phase C: assemble + update
+  if (!stopped) {
+    for (int q = blockIdx.x; q < a.n_upd; q += nb) {
+      const BItem& w = it[q];
+      const BMember& M = a.mem[w.m];
+      const double dt = member_dt(a, w.m, k);
+      if (STAGE == 1)
+        update_block<1>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
+      else
+        update_block<2>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
+    }
+  }
+  if (STAGE == 2 && blockIdx.x == 0 && !stopped) {
+    for (int q = threadIdx.y * blockDim.x + threadIdx.x; q < a.count; q += blockDim.x * blockDim.y) {
+      const double dt = member_dt(a, q, k);
+      a.t[q] += dt;
+      a.dt_last[q] = dt;
+    }
+    if (threadIdx.x == 0 && threadIdx.y == 0) a.sc->steps += 1;
+  }
 }
 
 // ================================================================== host
@@ -503,7 +918,7 @@ fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, 
   fdcgks_status st = halo2d(pb, const_cast<double*>(Sin));
   if (st) return st;
   dim3 blk(64, 4);
-  dim3 ge(ceil_div(g.nx + 3, 64), ceil_div(g.ny + 3, 4), 2);
+  dim3 ge(ceil_div(g.nx + 3, 64), ceil_div(g.ny + 3, 2), 2);
   if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
     hipLaunchKernelGGL((k_edges2d<STAGE, float>), ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc);
   else
@@ -537,6 +952,19 @@ fdcgks_status begin_step(fdcgks_problem* pb, double dt, double cfl) {
   hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, pb->stream, pb->part, pb->nparts, pb->sc, cfl, g.h,
                      pb->k.mu, use_cfl);
   return launch_check(pb, "step_begin");
+}
+
+fdcgks_status launch_run1d(fdcgks_problem* pb, int mode, int nsteps, double dt, double cfl) {
+  const int use_cfl = dt > 0 ? 0 : 1;
+  double* S0 = pb->S[pb->cur];
+  double* S1 = pb->S[1 - pb->cur];
+  if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
+    hipLaunchKernelGGL(k_run1d<float>, dim3(1), dim3(256), 0, pb->stream, S0, S1, pb->Sstar, pb->Acc, pb->E, pb->Nb,
+                       pb->g, pb->k, pb->sc, pb->ngrid, pb->prm.bc, nsteps, cfl, use_cfl, mode);
+  else
+    hipLaunchKernelGGL(k_run1d<double>, dim3(1), dim3(256), 0, pb->stream, S0, S1, pb->Sstar, pb->Acc, pb->E, pb->Nb,
+                       pb->g, pb->k, pb->sc, pb->ngrid, pb->prm.bc, nsteps, cfl, use_cfl, mode);
+  return launch_check(pb, "run1d");
 }
 
 fdcgks_status check_params(const fdcgks_params* p) {
@@ -620,6 +1048,7 @@ fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_pro
   Consts& k = pb->k;
   k.gamma = p->gamma;
   k.K = p->dim == 2 ? (4.0 - 2.0 * p->gamma) / (p->gamma - 1.0) : (3.0 - p->gamma) / (p->gamma - 1.0);
+  k.inv_Kd = 1.0 / (k.K + (p->dim == 2 ? 2.0 : 1.0));
   k.mu = p->mu;
   k.prfix = p->mu > 0 ? 1.0 / p->prandtl - 1.0 : 0.0;
   k.C = p->geno_C;
@@ -635,10 +1064,6 @@ fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_pro
   k.grad_carried = p->grad_update == FDCGKS_GRAD_CARRIED;
   pb->ngrid = p->dim == 2 ? 2 : (p->dual_1d ? 2 : 1);
   pb->nplanes = (int)state_planes(*p);
-  if (p->dim == 1) {
-    delete pb;
-    return fail(nullptr, FDCGKS_EINVAL, "1D problems are not available in this build");
-  }
   size_t sbytes = (size_t)pb->nplanes * g.plane * sizeof(double);
   size_t ebytes = (size_t)100 * g.plane * sizeof(double);
   size_t nbytes = (size_t)32 * g.plane * sizeof(double);
@@ -766,6 +1191,11 @@ fdcgks_status fdcgks_step(fdcgks_problem* pb, double dt, double cfl, int32_t nst
   int cur = cur0;
   pb->ev_used = 0;
   mark(pb, TK_STEP);
+  if (pb->prm.dim == 1 && nsteps > 0) {
+    st = launch_run1d(pb, 0, nsteps, dt, cfl);
+    mark(pb, TK_STEP);
+    nsteps = 0;
+  }
   for (int s = 0; s < nsteps; ++s) {
     pb->cur = cur;
     st = begin_step(pb, dt, cfl);
@@ -829,7 +1259,8 @@ fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, d
   fdcgks_status st = write_scal(pb);
   double* scratch = pb->S[1 - pb->cur];  // the next-state buffer is free between steps
   if (!st) {
-    if (stage == 1) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc);
+    if (pb->prm.dim == 1) st = launch_run1d(pb, stage, 0, dt, 0.0);
+    else if (stage == 1) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc);
     else st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr);
   }
   if (st) return st;
@@ -837,7 +1268,8 @@ fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, d
   const double* src = stage == 1 ? pb->Sstar : scratch;
   size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
   long n = (long)g.nx * g.ny;
-  for (int p = 0; p < pb->nplanes; ++p) {
+  const int nout = pb->ngrid * (pb->prm.dim == 2 ? 12 : 6);  // planes of the grids present
+  for (int p = 0; p < nout; ++p) {
     HIPCHK(pb, hipMemcpy2DAsync(out_state + p * n, row, src + p * g.plane + (long)OY * g.pitch + OX, pitchb, row,
                                 g.ny, hipMemcpyDeviceToHost, pb->stream));
     if (stage == 1 && out_acc)
@@ -879,5 +1311,310 @@ fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* 
                                   hipMemcpyDeviceToHost, pb->stream));
   return read_scal(pb);
 }
+
+}  // extern "C"
+
+// ============================================================ batch host
+struct fdcgks_batch {
+  int count = 0;
+  fdcgks_params prm0;
+  Consts k;
+  hipStream_t stream = nullptr;
+  std::vector<BMember> mem;
+  BMember* mem_d = nullptr;
+  std::vector<void*> allocs;
+  BItem* items_d = nullptr;
+  int n_cfl = 0, n_halo = 0, n_edge = 0, n_node = 0, n_upd = 0;
+  unsigned long long* slots = nullptr;
+  double* t = nullptr;
+  double* dt_last = nullptr;
+  Scal* sc = nullptr;
+  Scal* sc_host = nullptr;
+  int cur = 0, parity = 0;
+  int blocks = 0;
+  std::vector<char> have_state;
+  std::string err;
+};
+
+namespace {
+fdcgks_status bfail(fdcgks_batch* b, fdcgks_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (b) b->err = buf; else g_create_error = buf;
+  return st;
+}
+#define BHIPCHK(b, call)                                                                      \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return bfail(b, FDCGKS_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+void batch_free(fdcgks_batch* b) {
+  for (void* p : b->allocs) (void)hipFree(p);
+  b->allocs.clear();
+  if (b->sc_host) (void)hipHostFree(b->sc_host);
+  b->sc_host = nullptr;
+}
+
+bool same_scheme(const fdcgks_params& a, const fdcgks_params& b) {
+  return a.gamma == b.gamma && a.mu == b.mu && a.prandtl == b.prandtl && a.flux_variant == b.flux_variant &&
+         a.flux_precision == b.flux_precision && a.grad_update == b.grad_update && a.geno_r == b.geno_r &&
+         a.geno_C == b.geno_C && a.geno_eps == b.geno_eps && a.geno_eps_a == b.geno_eps_a &&
+         a.geno_d_central == b.geno_d_central && a.geno_d_side == b.geno_d_side && a.tau_c1 == b.tau_c1 &&
+         a.tau_c2 == b.tau_c2;
+}
+
+template <class FT> void* batch_kernel(int stage) {
+  return stage == 1 ? reinterpret_cast<void*>(k_batch_stage<1, FT>) : reinterpret_cast<void*>(k_batch_stage<2, FT>);
+}
+}  // namespace
+
+extern "C" {
+
+fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, void* hip_stream, fdcgks_batch** out) {
+  if (!out) return bfail(nullptr, FDCGKS_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || !params) return bfail(nullptr, FDCGKS_EINVAL, "need count >= 1 and a params array");
+  for (int m = 0; m < count; ++m) {
+    fdcgks_status st = check_params(&params[m]);
+    if (st) return bfail(nullptr, st, "member %d: %s", m, g_create_error.c_str());
+    if (params[m].dim != 2) return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches are 2D only", m);
+    if (!same_scheme(params[0], params[m]))
+      return bfail(nullptr, FDCGKS_EINVAL, "member %d: scheme constants differ from member 0", m);
+  }
+  int dev = 0, coop = 0, ncu = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return bfail(nullptr, FDCGKS_EHIP, "device query failed: %s", hipGetErrorString(e));
+  if (!coop) return bfail(nullptr, FDCGKS_EHIP, "device does not support cooperative launches");
+  fdcgks_batch* b = new fdcgks_batch();
+  b->count = count;
+  b->prm0 = params[0];
+  b->stream = (hipStream_t)hip_stream;
+  // scheme constants (shared)
+  const fdcgks_params& p = params[0];
+  Consts& k = b->k;
+  std::memset(&k, 0, sizeof k);
+  k.gamma = p.gamma;
+  k.K = (4.0 - 2.0 * p.gamma) / (p.gamma - 1.0);
+  k.inv_Kd = 1.0 / (k.K + 2.0);
+  k.mu = p.mu;
+  k.prfix = p.mu > 0 ? 1.0 / p.prandtl - 1.0 : 0.0;
+  k.C = p.geno_C;
+  k.inv_tanhC = 1.0 / std::tanh(p.geno_C);
+  k.eps = p.geno_eps;
+  k.eps_a = p.geno_eps_a;
+  k.dc = p.geno_d_central;
+  k.ds = p.geno_d_side;
+  k.tau_c1 = p.tau_c1;
+  k.tau_c2 = p.tau_c2;
+  k.r = p.geno_r;
+  k.variant = p.flux_variant;
+  k.grad_carried = p.grad_update == FDCGKS_GRAD_CARRIED;
+  // per-member buffers and work lists
+  std::vector<BItem> cfl, halo, edge, node, upd;
+  b->mem.resize(count);
+  b->have_state.assign(2 * count, 0);
+  auto alloc = [&](size_t bytes) -> double* {
+    void* ptr = nullptr;
+    if (e == hipSuccess) e = hipMalloc(&ptr, bytes);
+    if (e == hipSuccess) {
+      b->allocs.push_back(ptr);
+      e = hipMemsetAsync(ptr, 0, bytes, b->stream);
+    }
+    return (double*)ptr;
+  };
+  for (int m = 0; m < count && e == hipSuccess; ++m) {
+    Geo& g = b->mem[m].g;
+    g.nx = params[m].nx;
+    g.ny = params[m].ny;
+    g.pitch = ((params[m].nx + 2 * OX) + 15) / 16 * 16;
+    g.rows = params[m].ny + 2 * OY;
+    g.plane = (long)g.pitch * g.rows;
+    g.h = params[m].lx / params[m].nx;
+    g.invh = 1.0 / g.h;
+    size_t sb = (size_t)24 * g.plane * sizeof(double);
+    b->mem[m].S[0] = alloc(sb);
+    b->mem[m].S[1] = alloc(sb);
+    b->mem[m].Sstar = alloc(sb);
+    b->mem[m].Acc = alloc(sb);
+    b->mem[m].E = alloc((size_t)100 * g.plane * sizeof(double));
+    b->mem[m].Nb = alloc((size_t)32 * g.plane * sizeof(double));
+    for (int by = 0; by < ceil_div(g.ny, 16); ++by) cfl.push_back({m, 0, 0, by});
+    for (int pl = 0; pl < 24; ++pl) halo.push_back({m, pl, 0, 0});
+    for (int z = 0; z < 2; ++z)
+      for (int by = 0; by < ceil_div(g.ny + 3, 2); ++by)
+        for (int bx = 0; bx < ceil_div(g.nx + 3, 64); ++bx) edge.push_back({m, z, bx, by});
+    for (int z = 0; z < 2; ++z)
+      for (int by = 0; by < ceil_div(g.ny + 2, 4); ++by)
+        for (int bx = 0; bx < ceil_div(g.nx + 2, 64); ++bx) node.push_back({m, z, bx, by});
+    for (int z = 0; z < 2; ++z)
+      for (int by = 0; by < ceil_div(g.ny, 4); ++by)
+        for (int bx = 0; bx < ceil_div(g.nx, 64); ++bx) upd.push_back({m, z, bx, by});
+  }
+  b->n_cfl = (int)cfl.size();
+  b->n_halo = (int)halo.size();
+  b->n_edge = (int)edge.size();
+  b->n_node = (int)node.size();
+  b->n_upd = (int)upd.size();
+  std::vector<BItem> all;
+  for (auto* v : {&cfl, &halo, &edge, &node, &upd}) all.insert(all.end(), v->begin(), v->end());
+  b->mem_d = (BMember*)alloc(sizeof(BMember) * count);
+  b->items_d = (BItem*)alloc(sizeof(BItem) * all.size());
+  b->slots = (unsigned long long*)alloc(sizeof(unsigned long long) * 4 * count);
+  b->t = alloc(sizeof(double) * count);
+  b->dt_last = alloc(sizeof(double) * count);
+  b->sc = (Scal*)alloc(sizeof(Scal));
+  if (e == hipSuccess) e = hipHostMalloc((void**)&b->sc_host, sizeof(Scal), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->mem_d, b->mem.data(), sizeof(BMember) * count, hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->items_d, all.data(), sizeof(BItem) * all.size(), hipMemcpyHostToDevice, b->stream);
+  // CFL slots of both parities: max speed 0, min rho +big
+  std::vector<unsigned long long> sl(4 * count, 0ull);
+  double big = 1e300;
+  unsigned long long bigbits;
+  std::memcpy(&bigbits, &big, sizeof big);
+  for (int q = 0; q < 2; ++q)
+    for (int m = 0; m < count; ++m) sl[(2 * q + 1) * count + m] = bigbits;
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->slots, sl.data(), sizeof(unsigned long long) * sl.size(), hipMemcpyHostToDevice,
+                       b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  // resident workgroups of the cooperative grid
+  if (e == hipSuccess) {
+    int nb1 = 0, nb2 = 0;
+    bool fp32 = p.flux_precision == FDCGKS_FP32_FLUX;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, fp32 ? batch_kernel<float>(1) : batch_kernel<double>(1),
+                                                     256, 0);
+    if (e == hipSuccess)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, fp32 ? batch_kernel<float>(2) : batch_kernel<double>(2),
+                                                       256, 0);
+    b->blocks = std::max(1, std::min(nb1, nb2)) * ncu;
+  }
+  if (e != hipSuccess) {
+    fdcgks_status code = (e == hipErrorOutOfMemory) ? FDCGKS_ENOMEM : FDCGKS_EHIP;
+    bfail(nullptr, code, "batch setup failed: %s", hipGetErrorString(e));
+    batch_free(b);
+    delete b;
+    return code;
+  }
+  *out = b;
+  return FDCGKS_OK;
+}
+
+static fdcgks_status batch_copy(fdcgks_batch* b, int m, int grid, double* const* ptrs, int to_dev, int on_device) {
+  const Geo& g = b->mem[m].g;
+  double* base = b->mem[m].S[b->cur] + (long)grid * 12 * g.plane;
+  size_t row = (size_t)g.nx * sizeof(double);
+  hipMemcpyKind kind = to_dev ? (on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
+                              : (on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
+  for (int f = 0; f < 3; ++f)
+    for (int c = 0; c < 4; ++c) {
+      double* dev = base + (long)(f * 4 + c) * g.plane + (long)OY * g.pitch + OX;
+      double* usr = ptrs[f] + (long)c * g.nx * g.ny;
+      if (to_dev)
+        BHIPCHK(b, hipMemcpy2DAsync(dev, (size_t)g.pitch * sizeof(double), usr, row, row, g.ny, kind, b->stream));
+      else
+        BHIPCHK(b, hipMemcpy2DAsync(usr, row, dev, (size_t)g.pitch * sizeof(double), row, g.ny, kind, b->stream));
+    }
+  if (!on_device) BHIPCHK(b, hipStreamSynchronize(b->stream));
+  return FDCGKS_OK;
+}
+
+fdcgks_status fdcgks_batch_set_state(fdcgks_batch* b, int32_t member, int32_t grid, const double* W, const double* Wx,
+                                     const double* Wy, int32_t on_device) {
+  if (!b) return bfail(nullptr, FDCGKS_EINVAL, "batch is NULL");
+  if (member < 0 || member >= b->count || grid < 0 || grid > 1)
+    return bfail(b, FDCGKS_EINVAL, "member %d / grid %d out of range", member, grid);
+  if (!W || !Wx || !Wy) return bfail(b, FDCGKS_EINVAL, "state pointer is NULL");
+  double* ptrs[3] = {const_cast<double*>(W), const_cast<double*>(Wx), const_cast<double*>(Wy)};
+  fdcgks_status st = batch_copy(b, member, grid, ptrs, 1, on_device);
+  if (!st) b->have_state[2 * member + grid] = 1;
+  return st;
+}
+
+fdcgks_status fdcgks_batch_get_state(const fdcgks_batch* cb, int32_t member, int32_t grid, double* W, double* Wx,
+                                     double* Wy, int32_t on_device) {
+  fdcgks_batch* b = const_cast<fdcgks_batch*>(cb);
+  if (!b) return bfail(nullptr, FDCGKS_EINVAL, "batch is NULL");
+  if (member < 0 || member >= b->count || grid < 0 || grid > 1)
+    return bfail(b, FDCGKS_EINVAL, "member %d / grid %d out of range", member, grid);
+  if (!W || !Wx || !Wy) return bfail(b, FDCGKS_EINVAL, "state pointer is NULL");
+  double* ptrs[3] = {W, Wx, Wy};
+  return batch_copy(b, member, grid, ptrs, 0, on_device);
+}
+
+fdcgks_status fdcgks_batch_step(fdcgks_batch* b, double cfl, int32_t nsteps, double* t_out, double* dt_out,
+                                int32_t* steps_done) {
+  if (!b) return bfail(nullptr, FDCGKS_EINVAL, "batch is NULL");
+  if (!(cfl > 0) || nsteps < 0) return bfail(b, FDCGKS_EINVAL, "need cfl > 0 and nsteps >= 0");
+  for (char c : b->have_state)
+    if (!c) return bfail(b, FDCGKS_ESTATE, "set_state has not been called for every member and grid");
+  std::memset(b->sc_host, 0, sizeof(Scal));
+  BHIPCHK(b, hipMemcpyAsync(b->sc, b->sc_host, sizeof(Scal), hipMemcpyHostToDevice, b->stream));
+  const int cur0 = b->cur, par0 = b->parity;
+  BArgs a;
+  a.mem = b->mem_d;
+  a.count = b->count;
+  a.items = b->items_d;
+  a.n_cfl = b->n_cfl;
+  a.n_halo = b->n_halo;
+  a.n_edge = b->n_edge;
+  a.n_node = b->n_node;
+  a.n_upd = b->n_upd;
+  a.cfl = cfl;
+  a.slots = b->slots;
+  a.t = b->t;
+  a.dt_last = b->dt_last;
+  a.sc = b->sc;
+  const bool fp32 = b->prm0.flux_precision == FDCGKS_FP32_FLUX;
+  for (int s = 0; s < nsteps; ++s) {
+    a.cur = cur0 ^ (s & 1);
+    a.parity = par0 ^ (s & 1);
+    void* args[2] = {&a, &b->k};
+    for (int stage = 1; stage <= 2; ++stage) {
+      void* fn = fp32 ? batch_kernel<float>(stage) : batch_kernel<double>(stage);
+      BHIPCHK(b, hipLaunchCooperativeKernel(fn, dim3(b->blocks), dim3(64, 4), args, 0, b->stream));
+    }
+  }
+  BHIPCHK(b, hipMemcpyAsync(b->sc_host, b->sc, sizeof(Scal), hipMemcpyDeviceToHost, b->stream));
+  if (t_out) BHIPCHK(b, hipMemcpyAsync(t_out, b->t, sizeof(double) * b->count, hipMemcpyDeviceToHost, b->stream));
+  if (dt_out)
+    BHIPCHK(b, hipMemcpyAsync(dt_out, b->dt_last, sizeof(double) * b->count, hipMemcpyDeviceToHost, b->stream));
+  BHIPCHK(b, hipStreamSynchronize(b->stream));
+  const int done = b->sc_host->steps;
+  b->cur = cur0 ^ (done & 1);
+  b->parity = par0 ^ (done & 1);
+  if (steps_done) *steps_done = done;
+  if (b->sc_host->stop & 1) {
+    // the failing step's input is intact; the next step must start from clean CFL slots
+    std::vector<unsigned long long> sl(4 * b->count, 0ull);
+    double big = 1e300;
+    unsigned long long bigbits;
+    std::memcpy(&bigbits, &big, sizeof big);
+    for (int q = 0; q < 2; ++q)
+      for (int m = 0; m < b->count; ++m) sl[(2 * q + 1) * b->count + m] = bigbits;
+    BHIPCHK(b, hipMemcpy(b->slots, sl.data(), sizeof(unsigned long long) * sl.size(), hipMemcpyHostToDevice));
+    return bfail(b, FDCGKS_ENONPHYS, "non-physical state in step %d stage %d: member %d grid %d node (%d, %d)",
+                 done + 1, b->sc_host->fail_stage, b->sc_host->fail_grid / 2, b->sc_host->fail_grid % 2,
+                 b->sc_host->fail_i, b->sc_host->fail_j);
+  }
+  return FDCGKS_OK;
+}
+
+fdcgks_status fdcgks_batch_destroy(fdcgks_batch* b) {
+  if (!b) return FDCGKS_OK;
+  (void)hipStreamSynchronize(b->stream);
+  batch_free(b);
+  delete b;
+  return FDCGKS_OK;
+}
+
+const char* fdcgks_batch_last_error(const fdcgks_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

@@ -14,6 +14,7 @@ namespace fdk {
 struct Consts {
   double gamma;
   double K;           // internal degrees of freedom: (4-2g)/(g-1) in 2D, (3-g)/(g-1) in 1D
+  double inv_Kd;      // 1/(K+2) in 2D, 1/(K+1) in 1D
   double mu;          // dynamic viscosity (0: Euler)
   double prfix;       // 1/Pr - 1 (applied when mu > 0)
   double C, inv_tanhC, eps, eps_a, dc, ds;  // GENO (Sec. 3.2, App. D)
@@ -202,8 +203,8 @@ template <class FT, int DIM> __device__ __forceinline__ Prim<FT> prim(const FT* 
   s.V = DIM == 2 ? W[2] * s.irho : FT(0);
   FT rE = W[DIM + 1];
   s.p = (gamma - FT(1)) * (rE - FT(0.5) * s.rho * (s.U * s.U + s.V * s.V));
-  s.lam = s.rho / (FT(2) * s.p);
-  s.i2l = s.p * s.irho;  // 1/(2 lambda)
+  s.i2l = s.p * s.irho;          // 1/(2 lambda) = p/rho
+  s.lam = FT(0.5) / s.i2l;
   return s;
 }
 template <class FT, int DIM> __device__ __forceinline__ void mom_common(const Prim<FT>& s, FT K, Mom<FT>& m) {
@@ -222,21 +223,22 @@ template <class FT> __device__ __forceinline__ void mom_full(const Prim<FT>& s, 
 template <class FT> __device__ __forceinline__ void mom_half(const Prim<FT>& s, FT sgn, Mom<FT>& m) {
   FT sl = m_sqrt(s.lam);
   m.mu[0] = FT(0.5) * m_erfc(-sgn * sl * s.U);
-  m.mu[1] = s.U * m.mu[0] + sgn * FT(0.5) * m_exp(-s.lam * s.U * s.U) / (sl * FT(1.7724538509055160273));
+  // 1/(2 sqrt(pi lambda)) = sqrt(1/(2 lambda)) / sqrt(2 pi)
+  m.mu[1] = s.U * m.mu[0] + sgn * m_exp(-s.lam * s.U * s.U) * m_sqrt(s.i2l) * FT(0.39894228040143267794);
   mu_rec(m.mu, s.U, s.i2l);
 }
 
 // Micro slope s with <psi (s.psi)> = d (d per unit density): closed-form
 // solution of the moment system.
 template <class FT, int DIM>
-__device__ __forceinline__ void slope(const Prim<FT>& q, FT K, const FT* d, FT* s) {
+__device__ __forceinline__ void slope(const Prim<FT>& q, FT K, FT iKd, const FT* d, FT* s) {
   if (DIM == 2) {
     FT e = q.U * q.U + q.V * q.V + (K + FT(2)) * q.i2l;
     FT B = FT(2) * d[3] - e * d[0];
     FT A = d[1] - q.U * d[0];
     FT Cc = d[2] - q.V * d[0];
     FT tl = FT(2) * q.lam;
-    s[3] = tl * tl / (K + FT(2)) * (B - FT(2) * q.U * A - FT(2) * q.V * Cc);
+    s[3] = tl * tl * iKd * (B - FT(2) * q.U * A - FT(2) * q.V * Cc);
     s[2] = tl * Cc - q.V * s[3];
     s[1] = tl * A - q.U * s[3];
     s[0] = d[0] - q.U * s[1] - q.V * s[2] - FT(0.5) * s[3] * e;
@@ -245,7 +247,7 @@ __device__ __forceinline__ void slope(const Prim<FT>& q, FT K, const FT* d, FT* 
     FT B = FT(2) * d[2] - e * d[0];
     FT A = d[1] - q.U * d[0];
     FT tl = FT(2) * q.lam;
-    s[2] = tl * tl / (K + FT(1)) * (B - FT(2) * q.U * A);
+    s[2] = tl * tl * iKd * (B - FT(2) * q.U * A);
     s[1] = tl * A - q.U * s[2];
     s[0] = d[0] - q.U * s[1] - FT(0.5) * s[2] * e;
   }
@@ -295,141 +297,142 @@ template <class FT, int DIM> struct GksIO {
   FT F[DIM + 2], Ft[DIM + 2], Wl[DIM + 2], Wr[DIM + 2], Wlt[DIM + 2], Wrt[DIM + 2];
 };
 
+// Moments of the transport and time-slope terms of one state:
+// tr = <psi ((a.psi) u + (b.psi) v)>, tru = <u psi (...)>, Ap = <psi A.psi>,
+// Au = <u psi A.psi> (2D; 1D drops the v terms).
+template <class FT, int DIM>
+__device__ __forceinline__ void transport(const FT* a, const FT* b, const Mom<FT>& m, FT* tr, FT* tru) {
+  if (DIM == 2) {
+    FT x[4], y[4];
+    ma<1, 0>(a, m, x); ma<0, 1>(b, m, y);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tr[i] = x[i] + y[i];
+    ma<2, 0>(a, m, x); ma<1, 1>(b, m, y);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) tru[i] = x[i] + y[i];
+  } else {
+    ma1<1>(a, m, tr);
+    ma1<2>(a, m, tru);
+  }
+}
+template <class FT, int DIM> __device__ __forceinline__ void tslope(const FT* A, const Mom<FT>& m, FT* Ap, FT* Au) {
+  if (DIM == 2) { ma<0, 0>(A, m, Ap); ma<1, 0>(A, m, Au); }
+  else { ma1<0>(A, m, Ap); ma1<1>(A, m, Au); }
+}
+// <psi> and <u psi> of a (half or full) state
+template <class FT, int DIM> __device__ __forceinline__ void psi_moms(const Mom<FT>& m, FT* p, FT* u) {
+  if (DIM == 2) {
+    p[0] = m.mu[0]; p[1] = m.mu[1]; p[2] = m.mu[0] * m.mv[1];
+    p[3] = FT(0.5) * (m.mu[2] + m.mu[0] * (m.mv[2] + m.x2));
+    muv<1, 0, 0>(m, u);
+  } else {
+    p[0] = m.mu[0]; p[1] = m.mu[1]; p[2] = FT(0.5) * (m.mu[2] + m.mu[0] * m.x2);
+    mu1<1, 0>(m, u);
+  }
+}
+
+// The contribution of one side s to the moments of f^n and f_t^n:
+// rho_s <phi [c3 (1 - tau A.psi) + c4 ((a.psi) u + (b.psi) v)]> over the half
+// line of s, for phi = psi (We, Wet) and u psi (F, Ft); also the one-sided
+// Euler time derivative Wt = -rho_s <psi (...)> over the full line.
+template <class FT, int DIM, bool VALUES>
+__device__ __forceinline__ void side_terms(const Prim<FT>& s, const Mom<FT>& h, const FT* n, const FT* t, FT K,
+                                           FT iKd, FT tau, const TimeCoef<FT>& tc, bool both, FT* F, FT* Ft, FT* We,
+                                           FT* Wet, FT* Wt) {
+  constexpr int N = DIM + 2;
+  Mom<FT> f = h;
+  mom_full(s, f);
+  FT a[N], b[N], A[N], d[N], tf[N], tuf[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) d[i] = n[i] * s.irho;
+  slope<FT, DIM>(s, K, iKd, d, a);
+  if (DIM == 2) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = t[i] * s.irho;
+    slope<FT, DIM>(s, K, iKd, d, b);
+  }
+  if (DIM == 2) { FT x[N], y[N]; ma<1, 0>(a, f, x); ma<0, 1>(b, f, y); for (int i = 0; i < N; ++i) tf[i] = x[i] + y[i]; }
+  else ma1<1>(a, f, tf);
+#pragma unroll
+  for (int i = 0; i < N; ++i) { d[i] = -tf[i]; Wt[i] = -s.rho * tf[i]; }
+  slope<FT, DIM>(s, K, iKd, d, A);
+  FT ph[N], uh[N], tp[N], tu[N], Ap[N], Au[N];
+  psi_moms<FT, DIM>(h, ph, uh);
+  transport<FT, DIM>(a, b, h, tp, tu);
+  tslope<FT, DIM>(A, h, Ap, Au);
+  (void)tuf;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    FT nu = uh[i] - tau * Au[i], np = ph[i] - tau * Ap[i];
+    Ft[i] += s.rho * (tc.ct[3] * nu + tc.ct[4] * tu[i]);
+    Wet[i] += s.rho * (tc.ct[3] * np + tc.ct[4] * tp[i]);
+    if (both) {
+      F[i] += s.rho * (tc.c[3] * nu + tc.c[4] * tu[i]);
+      We[i] += s.rho * (tc.c[3] * np + tc.c[4] * tp[i]);
+    }
+  }
+}
+
 template <class FT, int DIM, bool VALUES>
 __device__ __forceinline__ void gks_iface(const Consts& k, FT dt, GksIO<FT, DIM>& io) {
   constexpr int N = DIM + 2;
-  const FT K = FT(k.K), gam = FT(k.gamma);
+  const FT K = FT(k.K), gam = FT(k.gamma), iKd = FT(k.inv_Kd);
+  const bool both = VALUES || k.mu > 0;  // F and We are needed for the values or the Prandtl fix
   Prim<FT> sL = prim<FT, DIM>(io.WL, gam), sR = prim<FT, DIM>(io.WR, gam);
-  Mom<FT> hL, fL, hR, fR;
+  // half-line moments and the compatibility state W0
+  Mom<FT> hL, hR;
   mom_common<FT, DIM>(sL, K, hL);
-  mom_common<FT, DIM>(sR, K, hR);
   mom_half(sL, FT(1), hL);
+  mom_common<FT, DIM>(sR, K, hR);
   mom_half(sR, FT(-1), hR);
-  fL = hL;
-  mom_full(sL, fL);
-  fR = hR;
-  mom_full(sR, fR);
-  // <psi> over the half lines, and the compatibility state W0
-  FT pL[N], pR[N], W0[N];
-  if (DIM == 2) {
-    pL[0] = hL.mu[0]; pL[1] = hL.mu[1]; pL[2] = hL.mu[0] * hL.mv[1];
-    pL[3] = FT(0.5) * (hL.mu[2] + hL.mu[0] * (hL.mv[2] + hL.x2));
-    pR[0] = hR.mu[0]; pR[1] = hR.mu[1]; pR[2] = hR.mu[0] * hR.mv[1];
-    pR[3] = FT(0.5) * (hR.mu[2] + hR.mu[0] * (hR.mv[2] + hR.x2));
-  } else {
-    pL[0] = hL.mu[0]; pL[1] = hL.mu[1]; pL[2] = FT(0.5) * (hL.mu[2] + hL.mu[0] * hL.x2);
-    pR[0] = hR.mu[0]; pR[1] = hR.mu[1]; pR[2] = FT(0.5) * (hR.mu[2] + hR.mu[0] * hR.x2);
-  }
-#pragma unroll
-  for (int i = 0; i < N; ++i) W0[i] = sL.rho * pL[i] + sR.rho * pR[i];
-  Prim<FT> s0 = prim<FT, DIM>(W0, gam);
-  Mom<FT> m0;
-  mom_common<FT, DIM>(s0, K, m0);
-  mom_full(s0, m0);
-  // spatial micro slopes
-  FT aL[N], aR[N], a0[N], bL[N], bR[N], b0[N], d[N];
-#pragma unroll
-  for (int i = 0; i < N; ++i) d[i] = io.nL[i] * sL.irho;
-  slope<FT, DIM>(sL, K, d, aL);
-#pragma unroll
-  for (int i = 0; i < N; ++i) d[i] = io.nR[i] * sR.irho;
-  slope<FT, DIM>(sR, K, d, aR);
-#pragma unroll
-  for (int i = 0; i < N; ++i) d[i] = FT(0.5) * (io.nL[i] + io.nR[i]) * s0.irho;
-  slope<FT, DIM>(s0, K, d, a0);
-  if (DIM == 2) {
-#pragma unroll
-    for (int i = 0; i < N; ++i) d[i] = io.Wt[i] * sL.irho;
-    slope<FT, DIM>(sL, K, d, bL);
-#pragma unroll
-    for (int i = 0; i < N; ++i) d[i] = io.Wt[i] * sR.irho;
-    slope<FT, DIM>(sR, K, d, bR);
-#pragma unroll
-    for (int i = 0; i < N; ++i) d[i] = io.Wt[i] * s0.irho;
-    slope<FT, DIM>(s0, K, d, b0);
-  }
-  // transport moments <psi ((a.psi) u + (b.psi) v)> (full) and time slopes
-  FT tLf[N], tRf[N], t0[N], AL[N], AR[N], A0[N];
+  FT W0[N];
   {
-    FT x[N], y[N];
-    if (DIM == 2) {
-      ma<1, 0>(aL, fL, x); ma<0, 1>(bL, fL, y);
-      for (int i = 0; i < N; ++i) tLf[i] = x[i] + y[i];
-      ma<1, 0>(aR, fR, x); ma<0, 1>(bR, fR, y);
-      for (int i = 0; i < N; ++i) tRf[i] = x[i] + y[i];
-      ma<1, 0>(a0, m0, x); ma<0, 1>(b0, m0, y);
-      for (int i = 0; i < N; ++i) t0[i] = x[i] + y[i];
-    } else {
-      ma1<1>(aL, fL, tLf);
-      ma1<1>(aR, fR, tRf);
-      ma1<1>(a0, m0, t0);
-    }
-    for (int i = 0; i < N; ++i) { x[i] = -tLf[i]; }
-    slope<FT, DIM>(sL, K, x, AL);
-    for (int i = 0; i < N; ++i) { x[i] = -tRf[i]; }
-    slope<FT, DIM>(sR, K, x, AR);
-    for (int i = 0; i < N; ++i) { x[i] = -t0[i]; }
-    slope<FT, DIM>(s0, K, x, A0);
+    FT pL[N], pR[N], u[N];
+    psi_moms<FT, DIM>(hL, pL, u);
+    psi_moms<FT, DIM>(hR, pR, u);
+#pragma unroll
+    for (int i = 0; i < N; ++i) W0[i] = sL.rho * pL[i] + sR.rho * pR[i];
   }
+  Prim<FT> s0 = prim<FT, DIM>(W0, gam);
   // collision time and time coefficients
   FT tau = (k.mu > 0 ? FT(k.mu) / s0.p : FT(k.tau_c1) * dt) +
            FT(k.tau_c2) * dt * m_abs(sL.p - sR.p) / (sL.p + sR.p);
   TimeCoef<FT> tc = time_coef(dt, tau);
-  // moments of every term of f^n against psi and u psi
-  FT u0[N], tu0[N], Ap0[N], Au0[N];                // equilibrium
-  FT uL[N], tLp[N], tLu[N], ApL[N], AuL[N];        // left half
-  FT uR[N], tRp[N], tRu[N], ApR[N], AuR[N];        // right half
-  FT p0[N];
-  if (DIM == 2) {
-    p0[0] = FT(1); p0[1] = s0.U; p0[2] = s0.V; p0[3] = FT(0.5) * (m0.mu[2] + m0.mv[2] + m0.x2);
-    muv<1, 0, 0>(m0, u0);
-    FT x[N], y[N];
-    ma<2, 0>(a0, m0, x); ma<1, 1>(b0, m0, y);
-    for (int i = 0; i < N; ++i) tu0[i] = x[i] + y[i];
-    ma<0, 0>(A0, m0, Ap0); ma<1, 0>(A0, m0, Au0);
-    muv<1, 0, 0>(hL, uL);
-    ma<1, 0>(aL, hL, x); ma<0, 1>(bL, hL, y);
-    for (int i = 0; i < N; ++i) tLp[i] = x[i] + y[i];
-    ma<2, 0>(aL, hL, x); ma<1, 1>(bL, hL, y);
-    for (int i = 0; i < N; ++i) tLu[i] = x[i] + y[i];
-    ma<0, 0>(AL, hL, ApL); ma<1, 0>(AL, hL, AuL);
-    muv<1, 0, 0>(hR, uR);
-    ma<1, 0>(aR, hR, x); ma<0, 1>(bR, hR, y);
-    for (int i = 0; i < N; ++i) tRp[i] = x[i] + y[i];
-    ma<2, 0>(aR, hR, x); ma<1, 1>(bR, hR, y);
-    for (int i = 0; i < N; ++i) tRu[i] = x[i] + y[i];
-    ma<0, 0>(AR, hR, ApR); ma<1, 0>(AR, hR, AuR);
-  } else {
-    p0[0] = FT(1); p0[1] = s0.U; p0[2] = FT(0.5) * (m0.mu[2] + m0.x2);
-    mu1<1, 0>(m0, u0);
-    ma1<2>(a0, m0, tu0);
-    ma1<0>(A0, m0, Ap0); ma1<1>(A0, m0, Au0);
-    mu1<1, 0>(hL, uL);
-    ma1<1>(aL, hL, tLp); ma1<2>(aL, hL, tLu);
-    ma1<0>(AL, hL, ApL); ma1<1>(AL, hL, AuL);
-    mu1<1, 0>(hR, uR);
-    ma1<1>(aR, hR, tRp); ma1<2>(aR, hR, tRu);
-    ma1<0>(AR, hR, ApR); ma1<1>(AR, hR, AuR);
-  }
-  // combine: coefficient index 0 g0, 1 slope term, 2 time-slope term,
-  // 3 (1 - tau A) g^s, 4 slope term of g^s
-  FT We[N], Wet[N];
+  FT F[N], We[N], Wet[N], WtL[N], WtR[N];
 #pragma unroll
-  for (int i = 0; i < N; ++i) {
-    FT e0u = u0[i], e1u = tu0[i], e2u = Au0[i];
-    FT nLu = uL[i] - tau * AuL[i], nRu = uR[i] - tau * AuR[i];
-    FT e0p = p0[i], e1p = t0[i], e2p = Ap0[i];
-    FT nLp = pL[i] - tau * ApL[i], nRp = pR[i] - tau * ApR[i];
-    FT r0 = s0.rho, rl = sL.rho, rr = sR.rho;
-    io.Ft[i] = r0 * (tc.ct[0] * e0u + tc.ct[1] * e1u + tc.ct[2] * e2u) +
-               rl * (tc.ct[3] * nLu + tc.ct[4] * tLu[i]) + rr * (tc.ct[3] * nRu + tc.ct[4] * tRu[i]);
-    Wet[i] = r0 * (tc.ct[0] * e0p + tc.ct[1] * e1p + tc.ct[2] * e2p) +
-             rl * (tc.ct[3] * nLp + tc.ct[4] * tLp[i]) + rr * (tc.ct[3] * nRp + tc.ct[4] * tRp[i]);
-    if (VALUES || k.mu > 0) {
-      io.F[i] = r0 * (tc.c[0] * e0u + tc.c[1] * e1u + tc.c[2] * e2u) +
-                rl * (tc.c[3] * nLu + tc.c[4] * tLu[i]) + rr * (tc.c[3] * nRu + tc.c[4] * tRu[i]);
-      We[i] = r0 * (tc.c[0] * e0p + tc.c[1] * e1p + tc.c[2] * e2p) +
-              rl * (tc.c[3] * nLp + tc.c[4] * tLp[i]) + rr * (tc.c[3] * nRp + tc.c[4] * tRp[i]);
+  for (int i = 0; i < N; ++i) { F[i] = FT(0); io.Ft[i] = FT(0); We[i] = FT(0); Wet[i] = FT(0); }
+  // non-equilibrium initial parts of both sides
+  side_terms<FT, DIM, VALUES>(sL, hL, io.nL, io.Wt, K, iKd, tau, tc, both, F, io.Ft, We, Wet, WtL);
+  side_terms<FT, DIM, VALUES>(sR, hR, io.nR, io.Wt, K, iKd, tau, tc, both, F, io.Ft, We, Wet, WtR);
+  // equilibrium part: g0 with slopes from the averaged normal slope (D12) and
+  // the tangential slope, time slope from compatibility
+  {
+    Mom<FT> m0;
+    mom_common<FT, DIM>(s0, K, m0);
+    mom_full(s0, m0);
+    FT a0[N], b0[N], A0[N], d[N], t0[N], tu0[N], Ap0[N], Au0[N], p0[N], u0[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = FT(0.5) * (io.nL[i] + io.nR[i]) * s0.irho;
+    slope<FT, DIM>(s0, K, iKd, d, a0);
+    if (DIM == 2) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) d[i] = io.Wt[i] * s0.irho;
+      slope<FT, DIM>(s0, K, iKd, d, b0);
+    }
+    transport<FT, DIM>(a0, b0, m0, t0, tu0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) d[i] = -t0[i];
+    slope<FT, DIM>(s0, K, iKd, d, A0);
+    tslope<FT, DIM>(A0, m0, Ap0, Au0);
+    psi_moms<FT, DIM>(m0, p0, u0);
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      io.Ft[i] += s0.rho * (tc.ct[0] * u0[i] + tc.ct[1] * tu0[i] + tc.ct[2] * Au0[i]);
+      Wet[i] += s0.rho * (tc.ct[0] * p0[i] + tc.ct[1] * t0[i] + tc.ct[2] * Ap0[i]);
+      if (both) {
+        F[i] += s0.rho * (tc.c[0] * u0[i] + tc.c[1] * tu0[i] + tc.c[2] * Au0[i]);
+        We[i] += s0.rho * (tc.c[0] * p0[i] + tc.c[1] * t0[i] + tc.c[2] * Ap0[i]);
+      }
     }
   }
   // Prandtl-number correction of the energy flux: (1/Pr - 1) times the heat
@@ -439,26 +442,26 @@ __device__ __forceinline__ void gks_iface(const Consts& k, FT dt, GksIO<FT, DIM>
     FT U = s0.U, V = s0.V, f = FT(k.prfix);
     if (DIM == 2) {
       FT a = FT(1.5) * U * U + FT(0.5) * V * V, b = FT(0.5) * U * (U * U + V * V);
-      FT q = io.F[3] - U * io.F[1] - V * io.F[2] + a * io.F[0] - U * We[3] + U * V * We[2] - b * We[0];
+      FT q = F[3] - U * F[1] - V * F[2] + a * F[0] - U * We[3] + U * V * We[2] - b * We[0];
       FT qt = io.Ft[3] - U * io.Ft[1] - V * io.Ft[2] + a * io.Ft[0] - U * Wet[3] + U * V * Wet[2] - b * Wet[0];
-      io.F[3] += f * q;
+      F[3] += f * q;
       io.Ft[3] += f * qt;
     } else {
       FT a = FT(1.5) * U * U, b = FT(0.5) * U * U * U;
-      FT q = io.F[2] - U * io.F[1] + a * io.F[0] - U * We[2] - b * We[0];
+      FT q = F[2] - U * F[1] + a * F[0] - U * We[2] - b * We[0];
       FT qt = io.Ft[2] - U * io.Ft[1] + a * io.Ft[0] - U * Wet[2] - b * Wet[0];
-      io.F[2] += f * q;
+      F[2] += f * q;
       io.Ft[2] += f * qt;
     }
   }
-  // interface values (Eq. W-model); one-sided time derivatives from the
-  // Euler transport of each side
+  // interface values (Eq. W-model) with the one-sided Euler time derivatives
   FT e = tc.e1, oe = FT(1) - tc.e1;
 #pragma unroll
   for (int i = 0; i < N; ++i) {
-    io.Wlt[i] = oe * Wet[i] - e * sL.rho * tLf[i];
-    io.Wrt[i] = oe * Wet[i] - e * sR.rho * tRf[i];
+    io.Wlt[i] = oe * Wet[i] + e * WtL[i];
+    io.Wrt[i] = oe * Wet[i] + e * WtR[i];
     if (VALUES) {
+      io.F[i] = F[i];
       io.Wl[i] = oe * We[i] + e * io.WL[i];
       io.Wr[i] = oe * We[i] + e * io.WR[i];
     }
@@ -472,7 +475,7 @@ template <class FT, int DIM, bool VALUES>
 __device__ __forceinline__ void gks_node(const Consts& k, const FT* W, const FT* Wx, const FT* Wy, FT* F, FT* Ft,
                                          FT* G, FT* Gt) {
   constexpr int N = DIM + 2;
-  const FT K = FT(k.K);
+  const FT K = FT(k.K), iKd = FT(k.inv_Kd);
   Prim<FT> s = prim<FT, DIM>(W, FT(k.gamma));
   Mom<FT> m;
   mom_common<FT, DIM>(s, K, m);
@@ -480,11 +483,11 @@ __device__ __forceinline__ void gks_node(const Consts& k, const FT* W, const FT*
   FT a[N], b[N], A[N], d[N], tr[N];
 #pragma unroll
   for (int i = 0; i < N; ++i) d[i] = Wx[i] * s.irho;
-  slope<FT, DIM>(s, K, d, a);
+  slope<FT, DIM>(s, K, iKd, d, a);
   if (DIM == 2) {
 #pragma unroll
     for (int i = 0; i < N; ++i) d[i] = Wy[i] * s.irho;
-    slope<FT, DIM>(s, K, d, b);
+    slope<FT, DIM>(s, K, iKd, d, b);
     FT x[N], y[N];
     ma<1, 0>(a, m, x); ma<0, 1>(b, m, y);
     for (int i = 0; i < N; ++i) tr[i] = x[i] + y[i];
@@ -493,7 +496,7 @@ __device__ __forceinline__ void gks_node(const Consts& k, const FT* W, const FT*
   }
 #pragma unroll
   for (int i = 0; i < N; ++i) d[i] = -tr[i];
-  slope<FT, DIM>(s, K, d, A);
+  slope<FT, DIM>(s, K, iKd, d, A);
   FT tauN = k.mu > 0 ? FT(k.mu) / s.p : FT(0);
   const bool visc = k.mu > 0;
   FT Fu[N], Gv[N];

@@ -108,3 +108,18 @@ def relerr(g, o, floors, ndim_plane=2):
     den = np.maximum(np.abs(o).max(axis=axes), floors)
     r = num / den
     return float(r.max()), np.unravel_index(int(np.argmax(r)), r.shape)
+
+
+def ulp_sensitivity(run, P, D, floors, trials=2, seed=0):
+    """Largest relative change of the oracle's own output when its input is
+    perturbed by one ulp (random signs).  Over several steps near
+    discontinuities the nonlinear GENO weights amplify round-off, so two
+    correct FP64 implementations can only agree to about this level."""
+    rng = np.random.default_rng(seed)
+    a = run(P, D)
+    worst = 0.0
+    for _ in range(trials):
+        eps = np.finfo(np.float64).eps * rng.choice([-1.0, 1.0], size=P.shape)
+        b = run(P * (1 + eps), D * (1 - eps))
+        worst = max(worst, relerr(b[0], a[0], floors)[0], relerr(b[1], a[1], floors)[0])
+    return worst

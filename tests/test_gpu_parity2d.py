@@ -11,7 +11,7 @@ import pytest
 
 import workloads as WL
 from tests.helpers import (TOL, floors_edge, floors_node, floors_state, floors_state_interval, gpu_params,
-                           oracle_par, ref_scales, relerr, settings)
+                           oracle_par, ref_scales, relerr, settings, ulp_sensitivity)
 
 pytestmark = pytest.mark.gpu
 
@@ -76,8 +76,13 @@ def test_stages(oracle, name):
         assert err <= TOL, (where, err)
 
 
-@pytest.mark.parametrize("name,nsteps", [("vortex_40", 3), ("shear_ns_36", 3), ("riemann_33x20", 2)])
+@pytest.mark.parametrize("name,nsteps", [("vortex_40", 3), ("shear_ns_36", 3), ("riemann_33x20", 2),
+                                         ("smooth_70x37", 3)])
 def test_steps_cfl(oracle, name, nsteps):
+    """Several CFL steps.  Over several steps the nonlinear weights amplify
+    round-off (near discontinuities by ~20x per step), so the bar is
+    max(1e-12, 4 x the oracle's own change under a one-ulp input
+    perturbation), measured here on the same case."""
     s, pr = _case(name)
     par = oracle_par(oracle, s)
     dt0 = oracle.dt2d(par, pr.P, pr.D, 0.5)
@@ -88,9 +93,12 @@ def test_steps_cfl(oracle, name, nsteps):
     assert n == nsteps == ok
     assert abs(t - ot) <= 1e-13 * ot
     fl = floors_state(ref_scales([pr.P, pr.D], s["gamma"], s["lx"]))
+    sens = ulp_sensitivity(lambda P, D: oracle.step2d(par, P, D, nsteps, dt=0.0, cfl=0.5)[:2], pr.P, pr.D, fl)
+    bar = max(TOL, 4 * sens)
     for g, o in ((pb.get_state_stacked(0), oP), (pb.get_state_stacked(1), oD)):
         err, where = relerr(g, o, fl)
-        assert err <= TOL, (where, err)
+        print(f"{name} {nsteps} steps: gpu-oracle {err:.2e}, oracle 1-ulp sensitivity {sens:.2e}")
+        assert err <= bar, (where, err, sens)
 
 
 def test_t_end_clip(oracle):
