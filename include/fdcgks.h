@@ -164,6 +164,26 @@ fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, d
 fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* edge_x, double* edge_y,
                                          double* node_p, double* node_d);
 
+/* ---------------------------------------------------------------- adjoint
+ * Vector-Jacobian product of one S2O4 step (Sec. 2.3 stages with the
+ * interface and nodal solvers of Sec. 2, the compact flux of
+ * Eq. fd-conservative-flux and the GENO reconstructions of Sec. 3) taken at
+ * the current state with the time step dt held fixed (the CFL time step is
+ * not differentiated).  lam_out[grid][12][ny][nx] is the adjoint of the step
+ * output (W, Wx, Wy per grid, the get_state order); on return
+ * lam_in[grid][12][ny][nx] = J^T lam_out, where J is the Jacobian of the
+ * step map at the current state.  The state is not advanced (the step is
+ * recomputed internally; the next-state buffer is used as scratch).
+ * Non-smooth points take fixed one-sided derivatives: |x| has derivative 0
+ * at 0 and min/max ties select the first argument.  2D with FP64 fluxes only
+ * (EINVAL otherwise); ENONPHYS if the recomputed step is non-physical.
+ * on_device: both arrays are device pointers (1) or host pointers (0).
+ * The first call allocates an adjoint workspace of about 410 planes of
+ * (nx + 16) x (ny + 6) doubles, kept until fdcgks_destroy.  Calls on one
+ * problem must not overlap. */
+fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_out, double* lam_in,
+                              int32_t on_device);
+
 /* ---------------------------------------------------------------- batches
  * Many independent periodic 2D problems of different sizes advanced together
  * (same scheme constants, each member its own grid, mesh size and CFL time

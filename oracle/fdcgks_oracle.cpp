@@ -319,8 +319,11 @@ template <class T> struct GksOut {
 // Integrated time coefficients of the BGK integral solution over [0, T]
 // (equilibrium g0, its spatial slope term, its time slope term, the initial
 // non-equilibrium part, and its slope term).
+// With tau = 0 (p_l = p_r and no c1 term) the coefficients take their
+// tau -> 0+ limits: exp(-T/tau) = 0, so only the equilibrium terms remain
+// and derivatives with respect to tau stay finite.
 template <class T> void qcoef(T Tt, T tau, T q[5]) {
-  T E = exp(-Tt / tau);
+  T E = val(tau) > 0 ? exp(-Tt / tau) : T(0.0);
   q[0] = Tt - tau * (1.0 - E);
   q[1] = tau * ((2.0 * tau - Tt) - (Tt + 2.0 * tau) * E);
   q[2] = 0.5 * Tt * Tt - tau * Tt + tau * tau * (1.0 - E);
@@ -422,7 +425,7 @@ void gks_interface(const Par& p, int dim, const T* WL, const T* WR, const T* WnL
     o.Ft[n - 1] = o.Ft[n - 1] + f * moment(hq, ct);
   }
   // interface values for the gradient update (Eq. W-model, D10, D13)
-  T e = exp(-T(dt) / tau);
+  T e = val(tau) > 0 ? exp(-T(dt) / tau) : T(0.0);  // tau -> 0+ limit as in qcoef
   for (int i = 0; i < n; ++i) {
     T WtL = rhsL[i], WtR = rhsR[i];  // one-sided Euler time derivatives (D13)
     o.Wl[i] = (1.0 - e) * o.We[i] + e * WL[i];

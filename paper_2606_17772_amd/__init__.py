@@ -157,6 +157,43 @@ class Problem:
     def get_state_stacked(self, grid):
         return np.concatenate(self.get_state(grid), axis=0)
 
+    def set_state_all(self, S):
+        """S: (ngrid, 12, ny, nx) (2D) stacked W, Wx, Wy of every grid, as a
+        contiguous float64 numpy array or torch tensor (host or device)."""
+        n = self.ncomp
+        for g in range(self.ngrid):
+            if self.params.dim == 2:
+                self.set_state(g, S[g, :n], S[g, n:2 * n], S[g, 2 * n:3 * n])
+            else:
+                self.set_state(g, S[g, :n], S[g, n:2 * n])
+
+    def get_state_all(self, device=None):
+        """(ngrid, 3*ncomp, ny, nx) as numpy (device=None) or a torch tensor on `device`."""
+        parts = [self.get_state(g, device) for g in range(self.ngrid)]
+        if device is None:
+            return np.stack([np.concatenate(p, axis=0) for p in parts])
+        torch = _torch()
+        return torch.stack([torch.cat(p, dim=0) for p in parts])
+
+    def step_vjp(self, dt, lam_out):
+        """J^T lam_out for one step of size dt from the current state (the
+        state is not advanced).  lam_out: (2, 12, ny, nx) numpy array or
+        torch tensor; the result has the same type and device."""
+        p = self.params
+        shape = (self.ngrid, (3 if p.dim == 2 else 2) * self.ncomp, p.ny, p.nx)
+        if tuple(lam_out.shape) != shape:
+            raise ValueError(f"lam_out must have shape {shape}")
+        if isinstance(lam_out, np.ndarray):
+            lam_out = np.ascontiguousarray(lam_out, dtype=np.float64)
+            lam_in = np.empty(shape)
+        else:
+            lam_out = lam_out.contiguous()
+            lam_in = _torch().empty_like(lam_out)
+        po, dev, _ = _ptr(lam_out)
+        pi, dev2, _ = _ptr(lam_in, True)
+        self._chk(self._L.fdcgks_step_vjp(self._h, dt, po, pi, dev))
+        return lam_in
+
     # -- time stepping
     def compute_dt(self, cfl):
         dt = C.c_double()

@@ -56,6 +56,7 @@ SIGNATURES = {
     "fdcgks_last_error": (C.c_char_p, [_vp]),
     "fdcgks_debug_stage": (C.c_int, [_vp, _i32, C.c_double, _vp, _vp]),
     "fdcgks_debug_intermediates": (C.c_int, [_vp, C.c_double, _vp, _vp, _vp, _vp]),
+    "fdcgks_step_vjp": (C.c_int, [_vp, C.c_double, _vp, _vp, _i32]),
     "fdcgks_batch_create": (C.c_int, [_i32, C.POINTER(Params), _vp, C.POINTER(_vp)]),
     "fdcgks_batch_set_state": (C.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32]),
     "fdcgks_batch_get_state": (C.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32]),

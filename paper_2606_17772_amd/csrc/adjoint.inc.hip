@@ -1,0 +1,426 @@
+// Adjoint of one S2O4 step (vector-Jacobian product at a frozen time step).
+// Included by fdcgks.hip after the forward kernels, whose layouts it uses.
+//
+// Reverse of a stage, for every node and interface point:
+//   update^T     lambda of the stage outputs -> lambda of L, L_t, the averaged
+//                gradients and their time derivatives (and direct terms);
+//   assembly^T   -> lambda of the interface fluxes, path functions, blended
+//                interface values and nodal fluxes (compact flux of
+//                Eq. fd-conservative-flux with the (6-4)/(6-2) blend; Gauss
+//                gradients of Eq. define-averaged-gradient);
+//   blend^T      -> lambda of the interface values of each direction
+//                (Eq. W-model-2d);
+//   solver^T     local Jacobian-transpose products of the gas-kinetic
+//                interface and nodal solvers;
+//   GENO^T       of the line and nodal reconstructions, scattered to the
+//                nodes they read (atomic adds), then the periodic halo is
+//                folded back onto its images.
+// The local Jacobians of the two nonlinear pointwise maps come from running
+// the same templated device arithmetic on dual numbers, one input direction
+// per pass.  min/max ties take the first argument and d|x|/dx = 0 at 0.
+
+namespace {
+
+using fdk::DD;
+
+// Planes of the per-node operator adjoint: L[4], Lt[4], Gx[4], Gy[4],
+// Gxt[4], Gyt[4] per grid.
+constexpr int OPN = 24;
+
+// ---------------------------------------------------------- update^T
+// lam_out: adjoint of the stage output state (24 planes); lam_acc: adjoint
+// of the stage-1 accumulators (stage 1 only).  Writes lam_op (interior) and
+// the direct terms: stage 1 -> lam_in (W planes, and the gradient planes
+// when the stored gradient is carried); stage 2 -> lam_acc_out (copy).
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_adj_update(const double* __restrict__ lam_out,
+                                                    const double* __restrict__ lam_acc, double* __restrict__ lam_op,
+                                                    double* __restrict__ lam_direct, Geo g, Consts k, double dt) {
+  const int grid = blockIdx.z;
+  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
+  if (i >= g.nx || j >= g.ny) return;
+  const long pl = g.plane, o = at(g, j, i);
+  const double* lo = lam_out + (long)grid * 12 * pl + o;
+  double* op = lam_op + (long)grid * OPN * pl + o;
+  double* dir = lam_direct + (long)grid * 12 * pl + o;
+  for (int c = 0; c < 4; ++c) {
+    const double lW = lo[c * pl], lX = lo[(4 + c) * pl], lY = lo[(8 + c) * pl];
+    if (STAGE == 2) {
+      dir[c * pl] = lW;  // acc_W
+      dir[(4 + c) * pl] = lX;
+      dir[(8 + c) * pl] = lY;
+      op[c * pl] = 0.0;
+      op[(4 + c) * pl] = dt * dt / 3.0 * lW;
+      op[(8 + c) * pl] = 0.0;
+      op[(12 + c) * pl] = 0.0;
+      op[(16 + c) * pl] = dt * lX;
+      op[(20 + c) * pl] = dt * lY;
+    } else {
+      const double* la = lam_acc + (long)grid * 12 * pl + o;
+      const double aW = la[c * pl], aX = la[(4 + c) * pl], aY = la[(8 + c) * pl];
+      dir[c * pl] = lW + aW;
+      op[c * pl] = 0.5 * dt * lW + dt * aW;
+      op[(4 + c) * pl] = 0.125 * dt * dt * lW + dt * dt / 6.0 * aW;
+      op[(16 + c) * pl] = 0.5 * dt * lX;
+      op[(20 + c) * pl] = 0.5 * dt * lY;
+      if (k.grad_carried) {
+        dir[(4 + c) * pl] = lX + aX;
+        dir[(8 + c) * pl] = lY + aY;
+        op[(8 + c) * pl] = 0.0;
+        op[(12 + c) * pl] = 0.0;
+      } else {
+        dir[(4 + c) * pl] = 0.0;
+        dir[(8 + c) * pl] = 0.0;
+        op[(8 + c) * pl] = lX + aX;
+        op[(12 + c) * pl] = lY + aY;
+      }
+    }
+  }
+}
+
+// Partial derivatives of the compact flux CF(Fm, Fc, Fp, N0, N1, chi).
+struct CFd {
+  double dm, dc, dp, dn, dchi_lo;  // dchi = Fbar - lo needs the values
+};
+__device__ __forceinline__ CFd cf_partials(int variant, double chi) {
+  CFd d;
+  if (variant == 2) {
+    d.dm = d.dp = 1.0 / 30.0;
+    d.dc = 46.0 / 30.0;
+    d.dn = -9.0 / 30.0;
+  } else {
+    const double clo = variant == 1 ? 1.0 : 8.0 / 6.0, nlo = variant == 1 ? 0.0 : -1.0 / 6.0;
+    d.dm = d.dp = chi / 30.0;
+    d.dc = (1.0 - chi) * clo + chi * 46.0 / 30.0;
+    d.dn = (1.0 - chi) * nlo + chi * (-9.0 / 30.0);
+  }
+  d.dchi_lo = 0.0;
+  return d;
+}
+__device__ __forceinline__ double cf_dchi(int variant, double Fm, double Fc, double Fp, double N0, double N1) {
+  if (variant == 2) return 0.0;
+  double Fb = ((Fm + 46.0 * Fc + Fp) - 9.0 * (N0 + N1)) * (1.0 / 30.0);
+  double lo = variant == 1 ? Fc : (8.0 * Fc - N0 - N1) * (1.0 / 6.0);
+  return Fb - lo;
+}
+
+// ---------------------------------------------------------- assembly^T
+// One thread per (interface point, slot) over the forward interface ranges:
+// lambda of F, Ft, chi, Wl, Wr, Wlt, Wrt of the slot (25 planes, like E).
+// The slot's grid is G = slot; its axis is y when fam != G; the interface's
+// left / right nodes (along the axis, grid G) sit at offsets -G and 1-G.
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_adj_assemble(const double* __restrict__ lam_op, const double* __restrict__ E,
+                                                      const double* __restrict__ Nb, double* __restrict__ lamE, Geo g,
+                                                      Consts k) {
+  const int fam = blockIdx.z >> 1, G = blockIdx.z & 1;
+  const int i = blockIdx.x * 64 + threadIdx.x + (fam == 0 ? -2 : -1);
+  const int j = blockIdx.y * 4 + threadIdx.y + (fam == 0 ? -1 : -2);
+  if (i > (fam == 0 ? g.nx : g.nx + 1) || j > (fam == 0 ? g.ny + 1 : g.ny)) return;
+  const bool ay = (fam ^ G) != 0;
+  const long pl = g.plane, st = ay ? g.pitch : 1, o = at(g, j, i);
+  const double* e = E + ((long)fam * 50 + G * 25) * pl + o;
+  const double* op = lam_op + (long)G * OPN * pl + o;            // node planes, indexed at this interface
+  const double* nf = Nb + (long)G * 16 * pl + (ay ? 8 : 0) * pl + o;
+  double* le = lamE + ((long)fam * 50 + G * 25) * pl + o;
+  const long nL = -(long)G * st, nR = (long)(1 - G) * st;         // node offsets of interface e
+  const int gop = ay ? 12 : 8, gopt = ay ? 20 : 16;               // gradient planes of this axis in lam_op
+  double lchi = 0.0;
+  for (int c = 0; c < 4; ++c) {
+    for (int tpart = (STAGE == 1 ? 0 : 1); tpart < 2; ++tpart) {
+      const double* f = e + (tpart * 4 + c) * pl;
+      const double* n = nf + (tpart * 4 + c) * pl;
+      const double* lL = op + (tpart * 4 + c) * pl;
+      double lF = 0.0;
+      // interfaces e' = e - st, e, e + st; lambda of CF(e') = (lam L(right node) - lam L(left node)) / h
+      for (int q = -1; q <= 1; ++q) {
+        const long eo = q * st;
+        const double lcf = (lL[eo + nR] - lL[eo + nL]) * g.invh;
+        const double chi = e[8 * pl + eo];
+        const CFd d = cf_partials(k.variant, chi);
+        lF += (q == -1 ? d.dp : (q == 0 ? d.dc : d.dm)) * lcf;
+        if (q == 0)
+          lchi += cf_dchi(k.variant, f[-st], f[0], f[st], n[nL], n[nR]) * lcf;
+      }
+      le[(tpart * 4 + c) * pl] = lF;
+    }
+    // gradients: G(left node) uses Wl(e), G(right node) uses -Wr(e)
+    if (STAGE == 1) {
+      le[(9 + c) * pl] = op[(gop + c) * pl + nL] * g.invh;
+      le[(13 + c) * pl] = -op[(gop + c) * pl + nR] * g.invh;
+    } else {
+      le[c * pl] = 0.0;
+      le[(9 + c) * pl] = 0.0;
+      le[(13 + c) * pl] = 0.0;
+    }
+    le[(17 + c) * pl] = op[(gopt + c) * pl + nL] * g.invh;
+    le[(21 + c) * pl] = -op[(gopt + c) * pl + nR] * g.invh;
+  }
+  le[8 * pl] = lchi;
+}
+
+// Lambda of the nodal fluxes: node n is the left node (N0) of its right
+// interface e_R = n + G st and the right node (N1) of e_L = e_R - st.
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_adj_nodeflux(const double* __restrict__ lam_op, const double* __restrict__ E,
+                                                      double* __restrict__ lamN, Geo g, Consts k) {
+  const int G = blockIdx.z;
+  const int i = blockIdx.x * 64 + threadIdx.x - 1, j = blockIdx.y * 4 + threadIdx.y - 1;
+  if (i > g.nx || j > g.ny) return;
+  const long pl = g.plane, o = at(g, j, i);
+  const double* op = lam_op + (long)G * OPN * pl + o;
+  double* ln = lamN + (long)G * 16 * pl + o;
+  for (int a = 0; a < 2; ++a) {
+    const int fam = (G == 0) ? a : 1 - a;
+    const long st = a == 0 ? 1 : g.pitch;
+    const double* e = E + ((long)fam * 50 + G * 25) * pl + o;
+    const long eR = (long)G * st, eL = eR - st;
+    const double dR = cf_partials(k.variant, e[8 * pl + eR]).dn, dL = cf_partials(k.variant, e[8 * pl + eL]).dn;
+    for (int c = 0; c < 4; ++c)
+      for (int tpart = (STAGE == 1 ? 0 : 1); tpart < 2; ++tpart) {
+        const double* lL = op + (tpart * 4 + c) * pl;
+        // lambda of CF at e_R (left node n, right node n + st) and e_L (n - st, n)
+        const double lR = (lL[st] - lL[0]) * g.invh, lLf = (lL[0] - lL[-st]) * g.invh;
+        ln[(a * 8 + tpart * 4 + c) * pl] = dR * lR + dL * lLf;
+      }
+    if (STAGE == 2)
+      for (int c = 0; c < 4; ++c) ln[(a * 8 + c) * pl] = 0.0;
+  }
+}
+
+// ------------------------------------------------------- solver^T, GENO^T
+// GENO^T of one line: lam of (vl, dl, cl, vr, dr, cr) per component ->
+// scatter onto the line's nodes (W plane and derivative plane).
+template <int FAM, int G>
+__device__ __forceinline__ void line_adjoint(const double* __restrict__ S, double* __restrict__ lamS, const Geo& g,
+                                             const Consts& k, int i, int j, const double (&lv)[4][6]) {
+  constexpr bool ALONG_Y = (FAM ^ G) != 0;
+  constexpr int back = G == 0 ? 1 : 2;
+  const long st = ALONG_Y ? g.pitch : 1;
+  const long o = ALONG_Y ? at(g, j - back, i) : at(g, j, i - back);
+  constexpr int f = ALONG_Y ? 2 : 1;
+  const long pl = g.plane;
+  for (int c = 0; c < 4; ++c) {
+    const double* w = S + (G * 12 + c) * pl + o;
+    const double* x = S + (G * 12 + f * 4 + c) * pl + o;
+    double in[8] = {w[0], w[st], w[2 * st], w[3 * st], x[0], x[st], x[2 * st], x[3 * st]};
+    double* lw = lamS + (G * 12 + c) * pl + o;
+    double* lx = lamS + (G * 12 + f * 4 + c) * pl + o;
+    for (int q = 0; q < 8; ++q) {
+      DD a[8];
+      for (int r = 0; r < 8; ++r) a[r] = DD(in[r], r == q ? 1.0 : 0.0);
+      fdk::IfaceRecT<DD> R = fdk::recon_iface<DD>(k, a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], g.h, g.invh);
+      const double s = lv[c][0] * R.vl.d + lv[c][1] * R.dl.d + lv[c][2] * R.cl.d + lv[c][3] * R.vr.d +
+                       lv[c][4] * R.dr.d + lv[c][5] * R.cr.d;
+      if (s != 0.0) atomicAdd(q < 4 ? lw + q * st : lx + (q - 4) * st, s);
+    }
+  }
+}
+
+// Local Jacobian-transpose of one gas-kinetic interface solve: lam of the
+// outputs (local frame) -> lam of WL, WR, nL, nR, Wt (local frame).
+template <bool SWAP, int STAGE, class FT>
+__device__ __forceinline__ void solve_adjoint(const Consts& k, double dt, const fdk::IfaceRec (&rn)[4],
+                                              const double (&tang)[4], const double (&lF)[4], const double (&lFt)[4],
+                                              const double (&lWl)[4], const double (&lWr)[4],
+                                              const double (&lWlt)[4], const double (&lWrt)[4], double (&lin)[20]) {
+  double x0[20];
+  for (int c = 0; c < 4; ++c) {
+    const int q = SWAP ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+    x0[c] = rn[q].vl;
+    x0[4 + c] = rn[q].vr;
+    x0[8 + c] = rn[q].dl;
+    x0[12 + c] = rn[q].dr;
+    x0[16 + c] = tang[q];
+  }
+  for (int q = 0; q < 20; ++q) {
+    fdk::GksIO<DD, 2> io;
+    for (int c = 0; c < 4; ++c) {
+      io.WL[c] = DD(x0[c], q == c ? 1.0 : 0.0);
+      io.WR[c] = DD(x0[4 + c], q == 4 + c ? 1.0 : 0.0);
+      io.nL[c] = DD(x0[8 + c], q == 8 + c ? 1.0 : 0.0);
+      io.nR[c] = DD(x0[12 + c], q == 12 + c ? 1.0 : 0.0);
+      io.Wt[c] = DD(x0[16 + c], q == 16 + c ? 1.0 : 0.0);
+    }
+    fdk::gks_iface<DD, 2, true>(k, DD(dt), io);
+    double s = 0.0;
+    for (int c = 0; c < 4; ++c) {
+      const int gq = SWAP ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;  // global component of local slot c
+      s += lFt[gq] * io.Ft[c].d + lWlt[gq] * io.Wlt[c].d + lWrt[gq] * io.Wrt[c].d;
+      if (STAGE == 1) s += lF[gq] * io.F[c].d + lWl[gq] * io.Wl[c].d + lWr[gq] * io.Wr[c].d;
+    }
+    lin[q] = s;
+  }
+}
+
+// Reverse of the interface sweep: same thread layout as the forward sweep
+// (two threads per point, partners in neighbouring waves).
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_adj_edges(const double* __restrict__ S, const double* __restrict__ lamE,
+                                                   double* __restrict__ lamS, Geo g, Consts k, double dt) {
+  __shared__ double xch[4][4][64];
+  const int fam = blockIdx.z;
+  const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
+  const int i = blockIdx.x * 64 + tx + (fam == 0 ? -2 : -1);
+  const int j = blockIdx.y * 2 + (ty >> 1) + (fam == 0 ? -1 : -2);
+  const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
+  fdk::IfaceRec rec[4];
+  if (valid) {
+    if (fam == 0) { if (G == 0) edge_recon<0, 0>(S, g, k, i, j, rec); else edge_recon<0, 1>(S, g, k, i, j, rec); }
+    else { if (G == 0) edge_recon<1, 0>(S, g, k, i, j, rec); else edge_recon<1, 1>(S, g, k, i, j, rec); }
+  } else {
+    for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
+  }
+  for (int c = 0; c < 4; ++c) xch[ty][c][tx] = 0.5 * (rec[c].dl + rec[c].dr);
+  __syncthreads();
+  double tang[4];
+  for (int c = 0; c < 4; ++c) tang[c] = xch[ty ^ 1][c][tx];
+  __syncthreads();
+  double lin[20];
+  for (int q = 0; q < 20; ++q) lin[q] = 0.0;
+  double lchi = 0.0;
+  if (valid) {
+    const long pl = g.plane, o = at(g, j, i);
+    const double* le = lamE + ((long)fam * 50 + G * 25) * pl + o;
+    const double* lp = lamE + ((long)fam * 50 + (1 - G) * 25) * pl + o;  // partner slot
+    double lF[4], lFt[4], lWl[4], lWr[4], lWlt[4], lWrt[4];
+    for (int c = 0; c < 4; ++c) {
+      // blend^T: W~(own) = W^/2 + (partner W^l + W^r)/4 and W~(partner) = W^p/2 + (own W^l + W^r)/4
+      const double ps = lp[(9 + c) * pl] + lp[(13 + c) * pl], pst = lp[(17 + c) * pl] + lp[(21 + c) * pl];
+      lF[c] = le[c * pl];
+      lFt[c] = le[(4 + c) * pl];
+      lWl[c] = 0.5 * le[(9 + c) * pl] + 0.25 * ps;
+      lWr[c] = 0.5 * le[(13 + c) * pl] + 0.25 * ps;
+      lWlt[c] = 0.5 * le[(17 + c) * pl] + 0.25 * pst;
+      lWrt[c] = 0.5 * le[(21 + c) * pl] + 0.25 * pst;
+    }
+    lchi = le[8 * pl];
+    if (fam == G) solve_adjoint<false, STAGE, double>(k, dt, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
+    else solve_adjoint<true, STAGE, double>(k, dt, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
+  }
+  // the tangential slope of this solve came from the partner line: send its lambda
+  const bool swap = fam != G;
+  for (int c = 0; c < 4; ++c) {
+    const int lc = swap ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;  // local slot of global component c
+    xch[ty][c][tx] = lin[16 + lc];
+  }
+  __syncthreads();
+  if (valid) {
+    double lv[4][6];
+    for (int c = 0; c < 4; ++c) {
+      const int lc = swap ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+      const double lt = 0.5 * xch[ty ^ 1][c][tx];  // partner's tangential slope = mean of my dl, dr
+      lv[c][0] = lin[lc];
+      lv[c][1] = lin[8 + lc] + lt;
+      lv[c][2] = 0.0;
+      lv[c][3] = lin[4 + lc];
+      lv[c][4] = lin[12 + lc] + lt;
+      lv[c][5] = 0.0;
+    }
+    // chi = min(chi_l, chi_r) of the density line (ties: left)
+    if (rec[0].cr < rec[0].cl) lv[0][5] = lchi; else lv[0][2] = lchi;
+    if (fam == 0) { if (G == 0) line_adjoint<0, 0>(S, lamS, g, k, i, j, lv); else line_adjoint<0, 1>(S, lamS, g, k, i, j, lv); }
+    else { if (G == 0) line_adjoint<1, 0>(S, lamS, g, k, i, j, lv); else line_adjoint<1, 1>(S, lamS, g, k, i, j, lv); }
+  }
+}
+
+// Reverse of the node sweep: lambda of the nodal fluxes -> lambda of the
+// node's W and of the 3-point lines its derivative reconstructions read.
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S, const double* __restrict__ lamN,
+                                                   double* __restrict__ lamS, Geo g, Consts k) {
+  const int grid = blockIdx.z;
+  const int i = blockIdx.x * 64 + threadIdx.x - 1, j = blockIdx.y * 4 + threadIdx.y - 1;
+  if (i > g.nx || j > g.ny) return;
+  const long pl = g.plane, o = at(g, j, i);
+  const double* B = S + (long)grid * 12 * pl;
+  const double* ln = lamN + (long)grid * 16 * pl + o;
+  double W[4], Wx[4], Wy[4];
+  for (int c = 0; c < 4; ++c) {
+    const double* w = B + c * pl + o;
+    const double* x = B + (4 + c) * pl + o;
+    const double* y = B + (8 + c) * pl + o;
+    W[c] = w[0];
+    Wx[c] = fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
+    Wy[c] = fdk::recon_node(k, w[-g.pitch], w[0], w[g.pitch], y[-g.pitch], y[0], y[g.pitch], g.h, g.invh);
+  }
+  double lF[4], lFt[4], lG[4], lGt[4];
+  for (int c = 0; c < 4; ++c) {
+    lF[c] = ln[c * pl];
+    lFt[c] = ln[(4 + c) * pl];
+    lG[c] = ln[(8 + c) * pl];
+    lGt[c] = ln[(12 + c) * pl];
+  }
+  // nodal solver^T: 12 inputs (W, Wx^N, Wy^N)
+  double lin[12];
+  for (int q = 0; q < 12; ++q) {
+    DD a[4], bx[4], by[4], F[4], Ft[4], Gv[4], Gt[4];
+    for (int c = 0; c < 4; ++c) {
+      a[c] = DD(W[c], q == c ? 1.0 : 0.0);
+      bx[c] = DD(Wx[c], q == 4 + c ? 1.0 : 0.0);
+      by[c] = DD(Wy[c], q == 8 + c ? 1.0 : 0.0);
+    }
+    fdk::gks_node<DD, 2, true>(k, a, bx, by, F, Ft, Gv, Gt);
+    double s = 0.0;
+    for (int c = 0; c < 4; ++c) {
+      s += lFt[c] * Ft[c].d + lGt[c] * Gt[c].d;
+      if (STAGE == 1) s += lF[c] * F[c].d + lG[c] * Gv[c].d;
+    }
+    lin[q] = s;
+  }
+  double* lS = lamS + (long)grid * 12 * pl + o;
+  for (int c = 0; c < 4; ++c) {
+    if (lin[c] != 0.0) atomicAdd(lS + c * pl, lin[c]);
+    // derivative reconstructions along x and y (6 inputs each)
+    for (int a = 0; a < 2; ++a) {
+      const double la = lin[4 + 4 * a + c];
+      if (la == 0.0) continue;
+      const long st = a == 0 ? 1 : g.pitch;
+      const double* w = B + c * pl + o;
+      const double* x = B + ((a == 0 ? 4 : 8) + c) * pl + o;
+      double in[6] = {w[-st], w[0], w[st], x[-st], x[0], x[st]};
+      for (int q = 0; q < 6; ++q) {
+        DD v[6];
+        for (int r = 0; r < 6; ++r) v[r] = DD(in[r], r == q ? 1.0 : 0.0);
+        DD d = fdk::recon_node<DD>(k, v[0], v[1], v[2], v[3], v[4], v[5], g.h, g.invh);
+        const double s = la * d.d;
+        if (s != 0.0)
+          atomicAdd(lS + (q < 3 ? c : (a == 0 ? 4 : 8) + c) * pl + (q % 3 - 1) * st, s);
+      }
+    }
+  }
+}
+
+// Fold the periodic halo of the adjoint planes back onto their images:
+// columns first (all rows, halo rows included), then rows.
+__global__ void k_adj_fold_cols(double* __restrict__ L, int nplanes, Geo g) {
+  const int rows = g.ny + 2 * HALO;
+  const long n = (long)nplanes * rows * 2 * HALO;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const int hc = (int)(t % (2 * HALO));
+    const long r = t / (2 * HALO);
+    const int j = (int)(r % rows) - HALO;
+    const int p = (int)(r / rows);
+    const int i = hc < HALO ? hc - HALO : g.nx + (hc - HALO);
+    double* P = L + p * g.plane;
+    const double v = P[at(g, j, i)];
+    if (v != 0.0) atomicAdd(&P[at(g, j, imod(i, g.nx))], v);
+    P[at(g, j, i)] = 0.0;
+  }
+}
+__global__ void k_adj_fold_rows(double* __restrict__ L, int nplanes, Geo g) {
+  const long n = (long)nplanes * 2 * HALO * g.nx;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(t % g.nx);
+    const long r = t / g.nx;
+    const int hr = (int)(r % (2 * HALO));
+    const int p = (int)(r / (2 * HALO));
+    const int j = hr < HALO ? hr - HALO : g.ny + (hr - HALO);
+    double* P = L + p * g.plane;
+    const double v = P[at(g, j, i)];
+    if (v != 0.0) atomicAdd(&P[at(g, imod(j, g.ny), i)], v);
+    P[at(g, j, i)] = 0.0;
+  }
+}
+
+}  // namespace

@@ -813,6 +813,12 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
   }
 }
 
+}  // namespace
+
+#include "adjoint.inc.hip"
+
+namespace {
+
 // ================================================================== host
 thread_local std::string g_create_error;
 
@@ -846,6 +852,10 @@ struct fdcgks_problem {
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_kind;
   int ev_used = 0;
+  // adjoint workspace (fdcgks_step_vjp), allocated on first use
+  double* adj = nullptr;
+  double *E1 = nullptr, *Nb1 = nullptr, *Lo = nullptr, *Op = nullptr, *LE = nullptr, *LN = nullptr;
+  double *LSs = nullptr, *LAcc = nullptr, *LS0 = nullptr;
 };
 
 namespace {
@@ -872,6 +882,8 @@ void free_all(fdcgks_problem* pb) {
   for (double* b : bufs) if (b) (void)hipFree(b);
   if (pb->sc) (void)hipFree(pb->sc);
   if (pb->sc_host) (void)hipHostFree(pb->sc_host);
+  if (pb->adj) (void)hipFree(pb->adj);
+  pb->adj = nullptr;
   pb->S[0] = pb->S[1] = pb->Sstar = pb->Acc = pb->E = pb->Nb = pb->part = nullptr;
   pb->sc = nullptr;
   pb->sc_host = nullptr;
@@ -1000,6 +1012,69 @@ fdcgks_status check_params(const fdcgks_params* p) {
   if (!(p->tau_c1 >= 0) || !(p->tau_c2 >= 0)) return fail(nullptr, FDCGKS_EINVAL, "tau constants must be >= 0");
   if (p->reserved != 0) return fail(nullptr, FDCGKS_EINVAL, "reserved must be 0");
   return FDCGKS_OK;
+}
+
+
+// ---- adjoint of one step (2D, FP64 fluxes)
+constexpr int ADJ_PLANES = 100 + 32 + 24 + 48 + 100 + 32 + 24 + 24 + 24;
+
+fdcgks_status adj_alloc(fdcgks_problem* pb) {
+  if (pb->adj) return FDCGKS_OK;
+  const long pl = pb->g.plane;
+  size_t bytes = (size_t)ADJ_PLANES * pl * sizeof(double);
+  hipError_t e = hipMalloc((void**)&pb->adj, bytes);
+  if (e != hipSuccess) {
+    pb->adj = nullptr;
+    return fail(pb, e == hipErrorOutOfMemory ? FDCGKS_ENOMEM : FDCGKS_EHIP, "adjoint workspace: %s",
+                hipGetErrorString(e));
+  }
+  HIPCHK(pb, hipMemsetAsync(pb->adj, 0, bytes, pb->stream));
+  double* q = pb->adj;
+  auto take = [&](double*& dst, int planes) { dst = q; q += (long)planes * pl; };
+  take(pb->E1, 100);
+  take(pb->Nb1, 32);
+  take(pb->Lo, 24);
+  take(pb->Op, 48);
+  take(pb->LE, 100);
+  take(pb->LN, 32);
+  take(pb->LSs, 24);
+  take(pb->LAcc, 24);
+  take(pb->LS0, 24);
+  return FDCGKS_OK;
+}
+
+void adj_fold(fdcgks_problem* pb, double* L) {
+  const Geo& g = pb->g;
+  long nc = 24L * (g.ny + 2 * HALO) * 2 * HALO, nr = 24L * 2 * HALO * g.nx;
+  hipLaunchKernelGGL(k_adj_fold_cols, dim3(std::min(ceil_div(nc, 256), 4096)), dim3(256), 0, pb->stream, L, 24, g);
+  hipLaunchKernelGGL(k_adj_fold_rows, dim3(std::min(ceil_div(nr, 256), 4096)), dim3(256), 0, pb->stream, L, 24, g);
+}
+
+// Reverse of one stage.  Sin, E, Nb: the stage's input state and its
+// interface / node results; lam_out (and lam_acc for stage 1): adjoint of the
+// stage outputs; direct: receives the adjoint of the accumulators (stage 2)
+// or of Sin (stage 1); scatter: receives the adjoint of Sin through the
+// reconstructions and solvers (stage 2: LSs; stage 1: the same buffer as
+// direct).
+template <int STAGE>
+fdcgks_status adj_stage(fdcgks_problem* pb, double dt, const double* Sin, const double* E, const double* Nb,
+                        const double* lam_out, const double* lam_acc, double* direct, double* scatter) {
+  const Geo& g = pb->g;
+  const dim3 blk(64, 4);
+  if (STAGE == 2) HIPCHK(pb, hipMemsetAsync(scatter, 0, 24 * g.plane * sizeof(double), pb->stream));
+  else HIPCHK(pb, hipMemsetAsync(direct, 0, 24 * g.plane * sizeof(double), pb->stream));
+  hipLaunchKernelGGL((k_adj_update<STAGE>), dim3(ceil_div(g.nx, 64), ceil_div(g.ny, 4), 2), blk, 0, pb->stream,
+                     lam_out, lam_acc, pb->Op, direct, g, pb->k, dt);
+  hipLaunchKernelGGL((k_adj_assemble<STAGE>), dim3(ceil_div(g.nx + 3, 64), ceil_div(g.ny + 3, 4), 4), blk, 0,
+                     pb->stream, pb->Op, E, Nb, pb->LE, g, pb->k);
+  hipLaunchKernelGGL((k_adj_nodeflux<STAGE>), dim3(ceil_div(g.nx + 2, 64), ceil_div(g.ny + 2, 4), 2), blk, 0,
+                     pb->stream, pb->Op, E, pb->LN, g, pb->k);
+  hipLaunchKernelGGL((k_adj_edges<STAGE>), dim3(ceil_div(g.nx + 3, 64), ceil_div(g.ny + 3, 2), 2), blk, 0,
+                     pb->stream, Sin, pb->LE, scatter, g, pb->k, dt);
+  hipLaunchKernelGGL((k_adj_nodes<STAGE>), dim3(ceil_div(g.nx + 2, 64), ceil_div(g.ny + 2, 4), 2), blk, 0,
+                     pb->stream, Sin, pb->LN, scatter, g, pb->k);
+  adj_fold(pb, scatter);
+  return launch_check(pb, "adjoint stage");
 }
 
 }  // namespace
@@ -1310,6 +1385,54 @@ fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* 
                                   pb->Nb + ((long)gr * 16 + q) * g.plane + (long)OY * g.pitch + OX, pitchb, row, g.ny,
                                   hipMemcpyDeviceToHost, pb->stream));
   return read_scal(pb);
+}
+
+fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_out, double* lam_in,
+                              int32_t on_device) {
+  if (!pb || !lam_out || !lam_in) return fail(pb, FDCGKS_EINVAL, "NULL argument");
+  if (pb->prm.dim != 2) return fail(pb, FDCGKS_EINVAL, "the step adjoint is implemented for 2D problems");
+  if (pb->prm.flux_precision != FDCGKS_FP64) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs FP64 fluxes");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, FDCGKS_EINVAL, "dt must be finite and > 0");
+  if (!state_ready(pb)) return fail(pb, FDCGKS_ESTATE, "set_state has not been called for every grid");
+  fdcgks_status st = adj_alloc(pb);
+  if (st) return st;
+  const Geo& g = pb->g;
+  const size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
+  const long n = (long)g.nx * g.ny;
+  const long interior = (long)OY * g.pitch + OX;
+  // adjoint of the step output into the padded layout (halo stays zero)
+  const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  for (int p = 0; p < 24; ++p)
+    HIPCHK(pb, hipMemcpy2DAsync(pb->Lo + p * g.plane + interior, pitchb, lam_out + p * n, row, row, g.ny, kin,
+                                pb->stream));
+  // forward recompute at the frozen dt: stage-1 results into E1/Nb1, stage-2 into E/Nb
+  std::memset(pb->sc_host, 0, sizeof(Scal));
+  pb->sc_host->dt = dt;
+  st = write_scal(pb);
+  double* E0 = pb->E;
+  double* N0 = pb->Nb;
+  double* scratch = pb->S[1 - pb->cur];
+  pb->E = pb->E1;
+  pb->Nb = pb->Nb1;
+  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc);
+  pb->E = E0;
+  pb->Nb = N0;
+  if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr);
+  if (!st) st = read_scal(pb);
+  if (st) return st;
+  if (pb->sc_host->stop & 1)
+    return fail(pb, FDCGKS_ENONPHYS, "non-physical state in the forward step (stage %d, grid %d, node (%d, %d))",
+                pb->sc_host->fail_stage, pb->sc_host->fail_grid, pb->sc_host->fail_i, pb->sc_host->fail_j);
+  // reverse: stage 2 then stage 1
+  st = adj_stage<2>(pb, dt, pb->Sstar, pb->E, pb->Nb, pb->Lo, nullptr, pb->LAcc, pb->LSs);
+  if (!st) st = adj_stage<1>(pb, dt, pb->S[pb->cur], pb->E1, pb->Nb1, pb->LSs, pb->LAcc, pb->LS0, pb->LS0);
+  if (st) return st;
+  const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  for (int p = 0; p < 24; ++p)
+    HIPCHK(pb, hipMemcpy2DAsync(lam_in + p * n, row, pb->LS0 + p * g.plane + interior, pitchb, row, g.ny, kout,
+                                pb->stream));
+  if (!on_device) HIPCHK(pb, hipStreamSynchronize(pb->stream));
+  return FDCGKS_OK;
 }
 
 }  // extern "C"

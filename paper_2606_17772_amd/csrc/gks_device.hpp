@@ -37,11 +37,66 @@ __device__ __forceinline__ float m_abs(float x) { return fabsf(x); }
 
 template <class T> __device__ __forceinline__ T sqr(T a) { return a * a; }
 
-__device__ __forceinline__ double ipow(double x, int r) {
-  double y = x;
-  for (int k = 1; k < r; ++k) y *= x;
+template <class T> __device__ __forceinline__ T ipow(T x, int r) {
+  T y = x;
+  for (int k = 1; k < r; ++k) y = y * x;
   return y;
 }
+
+// Forward-mode dual number (value, one tangent): running the same templated
+// arithmetic on it gives directional derivatives, from which the adjoint
+// kernels assemble local Jacobian-transpose products.
+struct DD {
+  double v, d;
+  __device__ __forceinline__ DD() : v(0.0), d(0.0) {}
+  __device__ __forceinline__ DD(double a) : v(a), d(0.0) {}
+  __device__ __forceinline__ DD(double a, double b) : v(a), d(b) {}
+  __device__ __forceinline__ explicit operator double() const { return v; }
+};
+__device__ __forceinline__ DD operator+(DD a, DD b) { return DD(a.v + b.v, a.d + b.d); }
+__device__ __forceinline__ DD operator-(DD a, DD b) { return DD(a.v - b.v, a.d - b.d); }
+__device__ __forceinline__ DD operator-(DD a) { return DD(-a.v, -a.d); }
+__device__ __forceinline__ DD operator*(DD a, DD b) { return DD(a.v * b.v, a.d * b.v + a.v * b.d); }
+__device__ __forceinline__ DD operator/(DD a, DD b) {
+  double q = a.v / b.v;
+  return DD(q, (a.d - q * b.d) / b.v);
+}
+__device__ __forceinline__ DD operator+(DD a, double b) { return DD(a.v + b, a.d); }
+__device__ __forceinline__ DD operator+(double a, DD b) { return DD(a + b.v, b.d); }
+__device__ __forceinline__ DD operator-(DD a, double b) { return DD(a.v - b, a.d); }
+__device__ __forceinline__ DD operator-(double a, DD b) { return DD(a - b.v, -b.d); }
+__device__ __forceinline__ DD operator*(DD a, double b) { return DD(a.v * b, a.d * b); }
+__device__ __forceinline__ DD operator*(double a, DD b) { return DD(a * b.v, a * b.d); }
+__device__ __forceinline__ DD operator/(DD a, double b) { return DD(a.v / b, a.d / b); }
+__device__ __forceinline__ DD operator/(double a, DD b) {
+  double q = a / b.v;
+  return DD(q, -q * b.d / b.v);
+}
+__device__ __forceinline__ DD& operator+=(DD& a, DD b) { a = a + b; return a; }
+__device__ __forceinline__ DD& operator-=(DD& a, DD b) { a = a - b; return a; }
+__device__ __forceinline__ DD& operator*=(DD& a, DD b) { a = a * b; return a; }
+__device__ __forceinline__ bool operator>(DD a, DD b) { return a.v > b.v; }
+__device__ __forceinline__ bool operator<(DD a, DD b) { return a.v < b.v; }
+__device__ __forceinline__ bool operator>(DD a, double b) { return a.v > b; }
+__device__ __forceinline__ bool operator<(DD a, double b) { return a.v < b; }
+__device__ __forceinline__ DD m_erfc(DD a) { return DD(erfc(a.v), -1.1283791670955126 * exp(-a.v * a.v) * a.d); }
+__device__ __forceinline__ DD m_exp(DD a) { double e = exp(a.v); return DD(e, e * a.d); }
+__device__ __forceinline__ DD m_sqrt(DD a) { double q = sqrt(a.v); return DD(q, a.d / (2.0 * q)); }
+// |x| with derivative 0 at x == 0 (the adjoint's convention for ties)
+__device__ __forceinline__ DD m_abs(DD a) { return a.v > 0 ? a : (a.v < 0 ? -a : DD(0.0, 0.0)); }
+
+// scalar helpers shared by double and DD (ties keep the first argument)
+__device__ __forceinline__ double g_abs(double a) { return fabs(a); }
+__device__ __forceinline__ double g_max(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ double g_min(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ double g_tanh(double a) { return tanh(a); }
+__device__ __forceinline__ DD g_abs(DD a) { return m_abs(a); }
+__device__ __forceinline__ DD g_max(DD a, DD b) { return b.v > a.v ? b : a; }
+__device__ __forceinline__ DD g_min(DD a, DD b) { return b.v < a.v ? b : a; }
+__device__ __forceinline__ DD g_tanh(DD a) { double t = tanh(a.v); return DD(t, (1.0 - t * t) * a.d); }
+__device__ __forceinline__ double val(double a) { return a; }
+__device__ __forceinline__ float val(float a) { return a; }
+__device__ __forceinline__ double val(DD a) { return a.v; }
 
 // ----------------------------------------------------- GENO, Sec. 3 / App. C
 // Path function and blend of one side.  IS1 is the IS^tau reference;
@@ -49,27 +104,27 @@ __device__ __forceinline__ double ipow(double x, int r) {
 // candidates; PH/PHx the high-order ones.  Normalised low-order weights are
 // d_k / t_k^2 (t_k = IS_k + eps_a) scaled by t1^2 t2^2 t3^2, so one division
 // normalises them.
-struct GenoOut {
-  double v, d, chi;
+template <class R> struct GenoOutT {
+  R v, d, chi;
 };
-__device__ __forceinline__ GenoOut geno(const Consts& k, double IS1, double IS2, double IS3, double d1, double d2,
-                                        double d3, double q1, double q2, double q3, double dq1, double dq2,
-                                        double dq3, double PH, double PHx) {
-  double tau = 0.5 * fabs((IS2 + IS3) - 2.0 * IS1);
-  double ISH = fmax(IS1, fmax(IS2, IS3));
-  double ISL = fmin(IS1, fmin(IS2, IS3));
-  double eH = ISH + k.eps, eL = ISL + k.eps;
-  double inv = 1.0 / (eH * eL);
-  double xH = tau * eL * inv, xL = tau * eH * inv;
-  double aH = 1.0 + ipow(xH, k.r), aL = 1.0 + ipow(xL, k.r);
-  double alpha = 2.0 * aH / (aH + aL);
-  double chi = tanh(k.C * alpha) * k.inv_tanhC;
-  double t1 = sqr(IS1 + k.eps_a), t2 = sqr(IS2 + k.eps_a), t3 = sqr(IS3 + k.eps_a);
-  double w1 = d1 * t2 * t3, w2 = d2 * t1 * t3, w3 = d3 * t1 * t2;
-  double is = 1.0 / (w1 + w2 + w3);
-  double PL = (w1 * q1 + w2 * q2 + w3 * q3) * is;
-  double PLx = (w1 * dq1 + w2 * dq2 + w3 * dq3) * is;
-  GenoOut o;
+template <class R>
+__device__ __forceinline__ GenoOutT<R> geno(const Consts& k, R IS1, R IS2, R IS3, double d1, double d2, double d3,
+                                            R q1, R q2, R q3, R dq1, R dq2, R dq3, R PH, R PHx) {
+  R tau = 0.5 * g_abs((IS2 + IS3) - 2.0 * IS1);
+  R ISH = g_max(IS1, g_max(IS2, IS3));
+  R ISL = g_min(IS1, g_min(IS2, IS3));
+  R eH = ISH + k.eps, eL = ISL + k.eps;
+  R inv = 1.0 / (eH * eL);
+  R xH = tau * eL * inv, xL = tau * eH * inv;
+  R aH = 1.0 + ipow(xH, k.r), aL = 1.0 + ipow(xL, k.r);
+  R alpha = 2.0 * aH / (aH + aL);
+  R chi = g_tanh(k.C * alpha) * k.inv_tanhC;
+  R t1 = sqr(IS1 + k.eps_a), t2 = sqr(IS2 + k.eps_a), t3 = sqr(IS3 + k.eps_a);
+  R w1 = d1 * t2 * t3, w2 = d2 * t1 * t3, w3 = d3 * t1 * t2;
+  R is = 1.0 / (w1 + w2 + w3);
+  R PL = (w1 * q1 + w2 * q2 + w3 * q3) * is;
+  R PLx = (w1 * dq1 + w2 * dq2 + w3 * dq3) * is;
+  GenoOutT<R> o;
   o.v = chi * PH + (1.0 - chi) * PL;
   o.d = chi * PHx + (1.0 - chi) * PLx;
   o.chi = chi;
@@ -78,60 +133,61 @@ __device__ __forceinline__ GenoOut geno(const Consts& k, double IS1, double IS2,
 
 // Interface m+1/2 of a line q0..q3 = Q_{m-1..m+2}, x0..x3 = averaged
 // derivatives (Eq. 7th-compact-recons; App. C1, C2).
-struct IfaceRec {
-  double vl, dl, cl, vr, dr, cr;
+template <class R> struct IfaceRecT {
+  R vl, dl, cl, vr, dr, cr;
 };
-__device__ __forceinline__ IfaceRec recon_iface(const Consts& k, double q0, double q1, double q2, double q3,
-                                                double x0, double x1, double x2, double x3, double h,
-                                                double invh) {
-  IfaceRec o;
-  double PHl = ((7.0 * q0 + 35.0 * q1 + 21.0 * q2 + q3) + (x0 + 22.0 * x1 - 7.0 * x2) * h) * (1.0 / 64.0);
-  double PHr = ((q0 + 21.0 * q1 + 35.0 * q2 + 7.0 * q3) + (7.0 * x1 - 22.0 * x2 - x3) * h) * (1.0 / 64.0);
-  double PHx = -((q0 + 45.0 * q1 - 45.0 * q2 - q3) + 9.0 * (x1 + x2) * h) * (invh * (1.0 / 30.0));
+using IfaceRec = IfaceRecT<double>;
+template <class R>
+__device__ __forceinline__ IfaceRecT<R> recon_iface(const Consts& k, R q0, R q1, R q2, R q3, R x0, R x1, R x2, R x3,
+                                                    double h, double invh) {
+  IfaceRecT<R> o;
+  R PHl = ((7.0 * q0 + 35.0 * q1 + 21.0 * q2 + q3) + (x0 + 22.0 * x1 - 7.0 * x2) * h) * (1.0 / 64.0);
+  R PHr = ((q0 + 21.0 * q1 + 35.0 * q2 + 7.0 * q3) + (7.0 * x1 - 22.0 * x2 - x3) * h) * (1.0 / 64.0);
+  R PHx = -((q0 + 45.0 * q1 - 45.0 * q2 - q3) + 9.0 * (x1 + x2) * h) * (invh * (1.0 / 30.0));
   if (k.variant == 2) {
-    o.vl = PHl; o.dl = PHx; o.cl = 1.0;
-    o.vr = PHr; o.dr = PHx; o.cr = 1.0;
+    o.vl = PHl; o.dl = PHx; o.cl = R(1.0);
+    o.vr = PHr; o.dr = PHx; o.cr = R(1.0);
     return o;
   }
-  double hx0 = h * x0, hx3 = h * x3;
-  double D2 = sqr(q0 - 2.0 * q1 + q2), D3 = sqr(q1 - 2.0 * q2 + q3);
-  double dmid = (q2 - q1) * invh;
-  double qc = (-q0 + 6.0 * q1 + 3.0 * q2) * 0.125;  // q_2^l == q_3^r
+  R hx0 = h * x0, hx3 = h * x3;
+  R D2 = sqr(q0 - 2.0 * q1 + q2), D3 = sqr(q1 - 2.0 * q2 + q3);
+  R dmid = (q2 - q1) * invh;
+  R qc = (-q0 + 6.0 * q1 + 3.0 * q2) * 0.125;  // q_2^l == q_3^r
   // left (App. C1)
-  double ISl1 = (13.0 / 3.0) * sqr(q1 - q0 - hx0) + sqr(2.0 * (q1 - q0) - hx0);
-  double ISl2 = (13.0 / 12.0) * D2 + 0.25 * sqr(q2 - q0);
-  double ISl3 = (13.0 / 12.0) * D3 + 0.25 * sqr(3.0 * q1 - 4.0 * q2 + q3);
-  double ql1 = (-5.0 * q0 + 9.0 * q1 - 3.0 * hx0) * 0.25;
-  double ql3 = (3.0 * q1 + 6.0 * q2 - q3) * 0.125;
-  double dl1 = (-3.0 * q0 + 3.0 * q1 - 2.0 * hx0) * invh;
-  GenoOut L = geno(k, ISl1, ISl2, ISl3, k.ds, k.dc, k.ds, ql1, qc, ql3, dl1, dmid, dmid, PHl, PHx);
+  R ISl1 = (13.0 / 3.0) * sqr(q1 - q0 - hx0) + sqr(2.0 * (q1 - q0) - hx0);
+  R ISl2 = (13.0 / 12.0) * D2 + 0.25 * sqr(q2 - q0);
+  R ISl3 = (13.0 / 12.0) * D3 + 0.25 * sqr(3.0 * q1 - 4.0 * q2 + q3);
+  R ql1 = (-5.0 * q0 + 9.0 * q1 - 3.0 * hx0) * 0.25;
+  R ql3 = (3.0 * q1 + 6.0 * q2 - q3) * 0.125;
+  R dl1 = (-3.0 * q0 + 3.0 * q1 - 2.0 * hx0) * invh;
+  GenoOutT<R> L = geno<R>(k, ISl1, ISl2, ISl3, k.ds, k.dc, k.ds, ql1, qc, ql3, dl1, dmid, dmid, PHl, PHx);
   // right (App. C2)
-  double ISr1 = (13.0 / 3.0) * sqr(q2 - q3 + hx3) + sqr(2.0 * (q3 - q2) - hx3);
-  double ISr2 = (13.0 / 12.0) * D3 + 0.25 * sqr(q3 - q1);
-  double ISr3 = (13.0 / 12.0) * D2 + 0.25 * sqr(3.0 * q2 - 4.0 * q1 + q0);
-  double qr1 = (-5.0 * q3 + 9.0 * q2 + 3.0 * hx3) * 0.25;
-  double qr2 = (-q3 + 6.0 * q2 + 3.0 * q1) * 0.125;
-  double dr1 = (-3.0 * q2 + 3.0 * q3 - 2.0 * hx3) * invh;
-  GenoOut R = geno(k, ISr1, ISr2, ISr3, k.ds, k.dc, k.ds, qr1, qr2, qc, dr1, dmid, dmid, PHr, PHx);
+  R ISr1 = (13.0 / 3.0) * sqr(q2 - q3 + hx3) + sqr(2.0 * (q3 - q2) - hx3);
+  R ISr2 = (13.0 / 12.0) * D3 + 0.25 * sqr(q3 - q1);
+  R ISr3 = (13.0 / 12.0) * D2 + 0.25 * sqr(3.0 * q2 - 4.0 * q1 + q0);
+  R qr1 = (-5.0 * q3 + 9.0 * q2 + 3.0 * hx3) * 0.25;
+  R qr2 = (-q3 + 6.0 * q2 + 3.0 * q1) * 0.125;
+  R dr1 = (-3.0 * q2 + 3.0 * q3 - 2.0 * hx3) * invh;
+  GenoOutT<R> Rr = geno<R>(k, ISr1, ISr2, ISr3, k.ds, k.dc, k.ds, qr1, qr2, qc, dr1, dmid, dmid, PHr, PHx);
   o.vl = L.v; o.dl = L.d; o.cl = L.chi;
-  o.vr = R.v; o.dr = R.d; o.cr = R.chi;
+  o.vr = Rr.v; o.dr = Rr.d; o.cr = Rr.chi;
   return o;
 }
 
 // Node derivative from q0..q2 = Q_{j-1..j+1}, x0..x2 (Eq. 6th-compact-recons,
 // App. C3; the central sub-stencil is the IS^tau reference with weight dc).
-__device__ __forceinline__ double recon_node(const Consts& k, double q0, double q1, double q2, double x0, double x1,
-                                             double x2, double h, double invh) {
-  double PHx = (9.0 * (q0 - q2) + h * (x0 + 46.0 * x1 + x2)) * (invh * (1.0 / 30.0));
+template <class R>
+__device__ __forceinline__ R recon_node(const Consts& k, R q0, R q1, R q2, R x0, R x1, R x2, double h, double invh) {
+  R PHx = (9.0 * (q0 - q2) + h * (x0 + 46.0 * x1 + x2)) * (invh * (1.0 / 30.0));
   if (k.variant == 2) return PHx;
-  double hx0 = h * x0, hx2 = h * x2;
-  double IS1 = (13.0 / 3.0) * sqr(q1 - q0 - hx0) + sqr(2.0 * (q1 - q0) - hx0);
-  double IS2 = (13.0 / 3.0) * sqr(q2 - q1 - hx2) + sqr(2.0 * (q2 - q1) - hx2);
-  double IS3 = (13.0 / 12.0) * sqr(q0 - 2.0 * q1 + q2) + 0.25 * sqr(q2 - q0);
-  double dq1 = (-2.0 * q0 + 2.0 * q1 - hx0) * invh;
-  double dq2 = (-2.0 * q1 + 2.0 * q2 - hx2) * invh;
-  double dq3 = (q2 - q0) * (0.5 * invh);
-  GenoOut o = geno(k, IS3, IS1, IS2, k.dc, k.ds, k.ds, q1, q1, q1, dq3, dq1, dq2, q1, PHx);
+  R hx0 = h * x0, hx2 = h * x2;
+  R IS1 = (13.0 / 3.0) * sqr(q1 - q0 - hx0) + sqr(2.0 * (q1 - q0) - hx0);
+  R IS2 = (13.0 / 3.0) * sqr(q2 - q1 - hx2) + sqr(2.0 * (q2 - q1) - hx2);
+  R IS3 = (13.0 / 12.0) * sqr(q0 - 2.0 * q1 + q2) + 0.25 * sqr(q2 - q0);
+  R dq1 = (-2.0 * q0 + 2.0 * q1 - hx0) * invh;
+  R dq2 = (-2.0 * q1 + 2.0 * q2 - hx2) * invh;
+  R dq3 = (q2 - q0) * (0.5 * invh);
+  GenoOutT<R> o = geno<R>(k, IS3, IS1, IS2, k.dc, k.ds, k.ds, q1, q1, q1, dq3, dq1, dq2, q1, PHx);
   return o.d;
 }
 
@@ -261,7 +317,8 @@ template <class FT> struct TimeCoef {
 };
 template <class FT> __device__ __forceinline__ TimeCoef<FT> time_coef(FT dt, FT tau) {
   TimeCoef<FT> r;
-  FT Eh = m_exp(-FT(0.5) * dt / tau);
+  // tau = 0 (p_l = p_r without a c1 term): the tau -> 0+ limit, exp(-T/tau) = 0
+  FT Eh = val(tau) > 0 ? m_exp(-FT(0.5) * dt / tau) : FT(0);
   FT Ef = Eh * Eh;
   FT Th = FT(0.5) * dt, Tf = dt;
   FT qh[5], qf[5];

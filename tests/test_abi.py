@@ -71,3 +71,5 @@ def test_null_arguments():
     t = C.c_double(0)
     assert L.fdcgks_step(None, 0.1, 0.5, 1, 0.0, C.byref(t), None) == _lib.EINVAL
     assert L.fdcgks_set_state(None, 0, None, None, None, 0) == _lib.EINVAL
+    assert L.fdcgks_step_vjp(None, 0.1, None, None, 0) == _lib.EINVAL
+    assert L.fdcgks_batch_step(None, 0.5, 1, None, None, None) == _lib.EINVAL
