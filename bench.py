@@ -38,8 +38,8 @@ HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doub
 # wave instructions; FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 after the
 # copy-kernel calibration).  Both are None whenever the kernel has changed
 # since the counters were taken.
-FLOPS_PER_IFACE_POINT_STAGE1 = None
-TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = None
+FLOPS_PER_IFACE_POINT_STAGE1 = 10416
+TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 7.630e9
 
 
 def parse():
@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--cpu-n", type=int, default=1024, help="side of the oracle's timed sample")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-problem comparison")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -123,6 +124,44 @@ def batch_comparison(steps):
             "batched_node_updates_per_s": nodes * 2 * steps / tb,
             "per_problem_loop_node_updates_per_s": nodes * 2 * steps / ts,
             "speedup": ts / tb, "bitwise_equal_sampled_members": bool(same)}
+
+
+def adjoint_comparison(pb, n, reps=2):
+    """Vector-Jacobian product of one step (fdcgks_step_vjp: forward
+    recompute at the frozen dt, then the reverse sweep) on the same workload
+    and state, against the forward step at the same dt.  Also the adjoint of
+    the conserved dual-grid energy sum, whose exact value is the indicator
+    itself (deviation = round-off of the periodic cancellation)."""
+    import torch
+    dev = torch.device("cuda:0")
+    S = pb.get_state_all(device=dev)
+    dt = pb.compute_dt(CFL)
+    gen = torch.Generator(device=dev).manual_seed(0)
+    lam = torch.randn(S.shape, dtype=torch.float64, device=dev, generator=gen)
+    pb.step_vjp(dt, lam)  # first call allocates the adjoint workspace
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        pb.step_vjp(dt, lam)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    vjp_ms = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    pb.step(nsteps=reps, dt=dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1) / reps
+    pb.set_state_all(S)
+    ind = torch.zeros_like(S)
+    ind[1, 3] = 1.0
+    dev_ind = float((pb.step_vjp(dt, ind) - ind).abs().max())
+    return {"workload": f"one step of the {n}x{n} shear layer at its CFL dt, random adjoint seed",
+            "vjp_ms": round(vjp_ms, 3), "forward_step_ms": round(fwd_ms, 3),
+            "vjp_over_forward": round(vjp_ms / fwd_ms, 2),
+            "conserved_sum_adjoint_max_deviation": dev_ind}
 
 
 def main():
@@ -205,6 +244,8 @@ def main():
                          "frac": round(hbm_gbs / PEAK_HBM_GBS, 4)},
         "kernel_ms_per_step": {k2: round(v / kn, 4) for k2, v in kms.items()},
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_comparison(pb, n)
     if not args.no_batch:
         del pb
         torch.cuda.empty_cache()
