@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-problem comparison")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward comparison")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default 64x4 launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -126,6 +127,31 @@ def batch_comparison(steps):
             "speedup": ts / tb, "bitwise_equal_sampled_members": bool(same)}
 
 
+def graph_comparison(n=64, steps=400):
+    """Launch overhead: a small problem (n^2 isentropic vortex) stepped with
+    the captured-step graphs (16 steps per graph) and with separate kernel
+    launches."""
+    import torch
+
+    import workloads as WL
+    from paper_2606_17772_amd import Problem, make_params
+    pr = WL.vortex(n, seed=0)
+    res = {}
+    for mode in (True, False):
+        pb = Problem(make_params(dim=2, nx=n, ny=n, lx=10.0, ly=10.0))
+        pb.set_state_all(np.ascontiguousarray(np.stack([pr.P, pr.D])))
+        pb.graph_steps = 16 if mode else 0
+        pb.step(nsteps=16, cfl=CFL)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.step(nsteps=steps, cfl=CFL)
+        torch.cuda.synchronize()
+        res["graph" if mode else "separate"] = 2 * n * n * 2 * steps / (time.perf_counter() - t0)
+        del pb
+    return {"workload": f"{n}x{n} isentropic vortex, {steps} steps", "graph_node_updates_per_s": res["graph"],
+            "separate_launch_node_updates_per_s": res["separate"], "speedup": res["graph"] / res["separate"]}
+
+
 def adjoint_comparison(pb, n, reps=2):
     """Vector-Jacobian product of one step (fdcgks_step_vjp: forward
     recompute at the frozen dt, then the reverse sweep) on the same workload
@@ -192,6 +218,7 @@ def main():
         T = torch.from_numpy(S).to(dev)
         pb.set_state(g, T[0:4].contiguous(), T[4:8].contiguous(), T[8:12].contiguous())
     torch.cuda.synchronize()
+    tiles = pb.tiles() if args.no_autotune else pb.autotune(reps=5)
     t = 0.0
     if args.warmup:
         t, _ = pb.step(nsteps=args.warmup, cfl=CFL, t=t)
@@ -237,7 +264,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"2D Navier-Stokes double shear layer {n}x{n} primary + dual, Re=1e4, Pr=0.72, "
-                               "CFL 0.5, (6-4) GENO, FP64", "nodes_per_stage": nodes, "stages_per_step": 2},
+                               "CFL 0.5, (6-4) GENO, FP64", "nodes_per_stage": nodes, "stages_per_step": 2,
+                   "launch_shapes": {k2: f"{x}x{y}" for k2, (x, y) in tiles.items()}, "step_graphs": True},
         "roofline": roof,
         "hbm_roofline": {"algorithmic_bytes_per_node_stage": HBM_BYTES_PER_NODE_STAGE,
                          "achieved_GBs": round(hbm_gbs, 1), "peak_GBs": PEAK_HBM_GBS,
@@ -246,6 +274,7 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_comparison(pb, n)
+    out["graph_replay"] = graph_comparison()
     if not args.no_batch:
         del pb
         torch.cuda.empty_cache()

@@ -164,6 +164,31 @@ fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, d
 fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* edge_x, double* edge_y,
                                          double* node_p, double* node_d);
 
+/* ------------------------------------------------------- launch options
+ * FDCGKS_OPT_GRAPH = K in 0..64 (default 16): with K > 0, 2D fdcgks_step
+ * replays K whole steps at a time (dt reduction, both stages, step end)
+ * captured as one HIP graph per ping-pong parity, captured on first use on
+ * a private stream and launched on the problem's stream; the last nsteps mod
+ * K steps and K = 0 launch every kernel separately.
+ * fdcgks_step_timed always launches separately (it times every kernel).
+ * FDCGKS_OPT_TILE_EDGE / _NODE / _UPDATE: block shape of the interface
+ * sweep, node sweep and update kernels as x | (y << 16); x in {32, 64, 128,
+ * 256}, x*y a multiple of 64 and at most 256, y even for the interface
+ * sweep (its two normals per point are paired thread rows).  Default 64 x 4.
+ * The shape changes only the launch, never the arithmetic: results are
+ * bitwise identical for every valid shape.  EINVAL for an unknown option or
+ * an invalid value. */
+enum { FDCGKS_OPT_GRAPH = 0, FDCGKS_OPT_TILE_EDGE = 1, FDCGKS_OPT_TILE_NODE = 2, FDCGKS_OPT_TILE_UPDATE = 3 };
+fdcgks_status fdcgks_set_option(fdcgks_problem* pb, int32_t option, int64_t value);
+fdcgks_status fdcgks_get_option(const fdcgks_problem* pb, int32_t option, int64_t* value);
+
+/* Autotuner: times every valid candidate block shape of the three stage-1
+ * kernels (reps launches each, HIP events on the problem's stream) on the
+ * current state at its CFL 0.4 time step and keeps the fastest per kernel.
+ * The state is not advanced (the stage scratch buffers are overwritten).
+ * Synchronises the stream.  1D problems: nothing to tune, returns OK. */
+fdcgks_status fdcgks_autotune(fdcgks_problem* pb, int32_t reps);
+
 /* ---------------------------------------------------------------- adjoint
  * Vector-Jacobian product of one S2O4 step (Sec. 2.3 stages with the
  * interface and nodal solvers of Sec. 2, the compact flux of

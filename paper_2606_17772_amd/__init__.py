@@ -207,6 +207,45 @@ class Problem:
         self._chk(self._L.fdcgks_step(self._h, dt, cfl, nsteps, t_end, C.byref(tt), C.byref(n)))
         return tt.value, n.value
 
+    # -- launch options
+    _TILES = {"edge": _lib.OPT_TILE_EDGE, "node": _lib.OPT_TILE_NODE, "update": _lib.OPT_TILE_UPDATE}
+
+    @property
+    def graph_steps(self):
+        """Steps per captured HIP graph in fdcgks_step (0: separate launches)."""
+        v = C.c_int64()
+        self._chk(self._L.fdcgks_get_option(self._h, _lib.OPT_GRAPH, C.byref(v)))
+        return v.value
+
+    @graph_steps.setter
+    def graph_steps(self, k):
+        self._chk(self._L.fdcgks_set_option(self._h, _lib.OPT_GRAPH, int(k)))
+
+    @property
+    def use_graph(self):
+        return self.graph_steps > 0
+
+    @use_graph.setter
+    def use_graph(self, on):
+        self.graph_steps = max(1, self.graph_steps) if on else 0
+
+    def tiles(self):
+        """Block shapes {"edge": (x, y), "node": ..., "update": ...}."""
+        out = {}
+        for name, opt in self._TILES.items():
+            v = C.c_int64()
+            self._chk(self._L.fdcgks_get_option(self._h, opt, C.byref(v)))
+            out[name] = (v.value & 0xFFFF, (v.value >> 16) & 0xFFFF)
+        return out
+
+    def set_tile(self, kernel, x, y):
+        self._chk(self._L.fdcgks_set_option(self._h, self._TILES[kernel], int(x) | (int(y) << 16)))
+
+    def autotune(self, reps=5):
+        """Time the candidate block shapes and keep the fastest; returns tiles()."""
+        self._chk(self._L.fdcgks_autotune(self._h, reps))
+        return self.tiles()
+
     KERNEL_CLASSES = ("halo", "edge1", "node1", "update1", "edge2", "node2", "update2", "step")
 
     def step_timed(self, nsteps=1, dt=0.0, cfl=0.5, t_end=0.0, t=0.0):

@@ -18,6 +18,7 @@ BC_PERIODIC, BC_ZERO_GRADIENT = 0, 1
 FLUX_6_4, FLUX_6_2, FLUX_LINEAR = 0, 1, 2
 FP64, FP32_FLUX = 0, 1
 GRAD_REEVAL, GRAD_CARRIED = 0, 1
+OPT_GRAPH, OPT_TILE_EDGE, OPT_TILE_NODE, OPT_TILE_UPDATE = 0, 1, 2, 3
 
 
 class Params(C.Structure):
@@ -57,6 +58,9 @@ SIGNATURES = {
     "fdcgks_debug_stage": (C.c_int, [_vp, _i32, C.c_double, _vp, _vp]),
     "fdcgks_debug_intermediates": (C.c_int, [_vp, C.c_double, _vp, _vp, _vp, _vp]),
     "fdcgks_step_vjp": (C.c_int, [_vp, C.c_double, _vp, _vp, _i32]),
+    "fdcgks_set_option": (C.c_int, [_vp, _i32, C.c_int64]),
+    "fdcgks_get_option": (C.c_int, [_vp, _i32, C.POINTER(C.c_int64)]),
+    "fdcgks_autotune": (C.c_int, [_vp, _i32]),
     "fdcgks_batch_create": (C.c_int, [_i32, C.POINTER(Params), _vp, C.POINTER(_vp)]),
     "fdcgks_batch_set_state": (C.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32]),
     "fdcgks_batch_get_state": (C.c_int, [_vp, _i32, _i32, _vp, _vp, _vp, _i32]),

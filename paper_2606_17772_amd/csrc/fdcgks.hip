@@ -141,20 +141,24 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
   }
 }
 
-// One thread per (interface point, normal): blockDim (64, 4), threadIdx.y =
-// 2 * row + G, so every wave is one row of one line type and the partner
-// solve of the same point sits in the neighbouring wave.  fam: X covers
-// i in [-2, nx], j in [-1, ny+1]; Y covers i in [-1, nx+1], j in [-2, ny]
-// (everything the update of the interior reads); block (bx, by) covers 64
-// points in i and 2 in j.  The partners exchange tangential slopes and blend
-// sums through LDS.  Every thread of the block must call this.
+// One thread per (interface point, normal): blockDim (TX, TY) with TX a
+// multiple of 64 or 32 and TY even, threadIdx.y = 2 * row + G, so the two
+// solves of one point sit in neighbouring rows of threads (with TX >= 64,
+// neighbouring waves).  fam: X covers i in [-2, nx], j in [-1, ny+1]; Y
+// covers i in [-1, nx+1], j in [-2, ny] (everything the update of the
+// interior reads); block (bx, by) covers TX points in i and TY/2 in j.  The
+// partners exchange tangential slopes and blend sums through LDS.  Every
+// thread of the block must call this.
 template <int STAGE, class FT>
 __device__ __forceinline__ void edge_block(const double* __restrict__ S, double* __restrict__ E, const Geo& g,
                                            const Consts& k, double dt, int bx, int by, int fam) {
-  __shared__ double xch[4][8][64];
+  __shared__ double xch[8 * 256];
   const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
-  const int i = bx * 64 + tx + (fam == 0 ? -2 : -1);
-  const int j = by * 2 + (ty >> 1) + (fam == 0 ? -1 : -2);
+  const int TX = blockDim.x, TY = blockDim.y;
+  // slot c of thread row r
+#define XCH(c, r) xch[((c) * TY + (r)) * TX + tx]
+  const int i = bx * TX + tx + (fam == 0 ? -2 : -1);
+  const int j = by * (TY >> 1) + (ty >> 1) + (fam == 0 ? -1 : -2);
   const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
   fdk::IfaceRec rec[4];
   if (valid) {
@@ -165,11 +169,11 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
     for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
   }
 #pragma unroll
-  for (int c = 0; c < 4; ++c) xch[ty][c][tx] = 0.5 * (rec[c].dl + rec[c].dr);
+  for (int c = 0; c < 4; ++c) XCH(c, ty) = 0.5 * (rec[c].dl + rec[c].dr);
   __syncthreads();
   double tang[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) tang[c] = xch[ty ^ 1][c][tx];
+  for (int c = 0; c < 4; ++c) tang[c] = XCH(c, ty ^ 1);
   double F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wl[4] = {0, 0, 0, 0}, Wr[4] = {0, 0, 0, 0};
   double Wlt[4] = {0, 0, 0, 0}, Wrt[4] = {0, 0, 0, 0};
   if (valid) {
@@ -180,8 +184,8 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
   __syncthreads();
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    xch[ty][c][tx] = Wlt[c] + Wrt[c];
-    if (STAGE == 1) xch[ty][4 + c][tx] = Wl[c] + Wr[c];
+    XCH(c, ty) = Wlt[c] + Wrt[c];
+    if (STAGE == 1) XCH(4 + c, ty) = Wl[c] + Wr[c];
   }
   __syncthreads();
   if (valid) {
@@ -191,12 +195,12 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
     e[8 * pl] = fmin(rec[0].cl, rec[0].cr);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double st = xch[ty ^ 1][c][tx];
+      const double st = XCH(c, ty ^ 1);
       e[(4 + c) * pl] = Ft[c];
       e[(17 + c) * pl] = 0.5 * Wlt[c] + 0.25 * st;
       e[(21 + c) * pl] = 0.5 * Wrt[c] + 0.25 * st;
       if (STAGE == 1) {
-        const double sv = xch[ty ^ 1][4 + c][tx];
+        const double sv = XCH(4 + c, ty ^ 1);
         e[(0 + c) * pl] = F[c];
         e[(9 + c) * pl] = 0.5 * Wl[c] + 0.25 * sv;
         e[(13 + c) * pl] = 0.5 * Wr[c] + 0.25 * sv;
@@ -204,6 +208,7 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
     }
   }
   __syncthreads();  // the block may reuse xch for its next work item
+#undef XCH
 }
 
 template <int STAGE, class FT>
@@ -215,12 +220,12 @@ __global__ __launch_bounds__(256, 2) void k_edges2d(const double* __restrict__ S
 
 // ------------------------------------------------------------ node sweep
 // Nodes i in [-1, nx], j in [-1, ny] of grid `grid`; block (bx, by) of
-// 64 x 4 nodes.
+// blockDim.x x blockDim.y nodes.
 template <int STAGE, class FT>
 __device__ __forceinline__ void node_block(const double* __restrict__ S, double* __restrict__ Nb, const Geo& g,
                                            const Consts& k, int bx, int by, int grid) {
-  const int i = bx * 64 + threadIdx.x - 1;
-  const int j = by * 4 + threadIdx.y - 1;
+  const int i = bx * blockDim.x + threadIdx.x - 1;
+  const int j = by * blockDim.y + threadIdx.y - 1;
   if (i > g.nx || j > g.ny) return;
   const long pl = g.plane, o = at(g, j, i);
   const double* B = S + (long)grid * 12 * pl;
@@ -260,17 +265,17 @@ __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, d
 // holding its a-fluxes, and the offset r of its right (upper) interface:
 // primary x -> X, slot 0, r = 0; primary y -> Y, slot 0, r = 0;
 // dual x -> Y, slot 1, r = 1;    dual y -> X, slot 1, r = 1.
-// Block (bx, by) of 64 x 4 interior nodes.  A non-physical result (rho <= 0,
-// p <= 0, NaN) sets the stop flag and records where (`member` names the
-// batch member, 0 for a single problem).
+// Block (bx, by) of blockDim.x x blockDim.y interior nodes.  A non-physical
+// result (rho <= 0, p <= 0, NaN) sets the stop flag and records where
+// (`member` names the batch member, 0 for a single problem).
 template <int STAGE>
 __device__ __forceinline__ void update_block(const double* __restrict__ S, const double* __restrict__ E,
                                              const double* __restrict__ Nb, const double* __restrict__ Ain,
                                              double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
                                              const Consts& k, double dt, int bx, int by, int grid, Scal* sc,
                                              int member) {
-  const int i = bx * 64 + threadIdx.x;
-  const int j = by * 4 + threadIdx.y;
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
   const long pl = g.plane, o = at(g, j, i);
   const int r = grid;
@@ -852,6 +857,16 @@ struct fdcgks_problem {
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_kind;
   int ev_used = 0;
+  // launch shapes of the interface, node and update kernels (x, y threads)
+  dim3 tile[3] = {dim3(64, 4), dim3(64, 4), dim3(64, 4)};
+  // captured whole steps (one graph per ping-pong parity), replayed by fdcgks_step
+  int graph_steps = 16;  // steps per captured graph; 0: separate launches
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gx[2] = {nullptr, nullptr};
+  bool g_valid = false;
+  int g_use_cfl = -1;
+  int g_steps = 0;
+  double g_cfl = 0.0;
   // adjoint workspace (fdcgks_step_vjp), allocated on first use
   double* adj = nullptr;
   double *E1 = nullptr, *Nb1 = nullptr, *Lo = nullptr, *Op = nullptr, *LE = nullptr, *LN = nullptr;
@@ -924,27 +939,43 @@ fdcgks_status halo2d(fdcgks_problem* pb, double* S) {
   return launch_check(pb, "halo");
 }
 
+// Launches of the three stage kernels with a given block shape (x, y).
+template <int STAGE>
+void launch_edges(fdcgks_problem* pb, const double* Sin, dim3 blk) {
+  const Geo& g = pb->g;
+  dim3 ge(ceil_div(g.nx + 3, blk.x), ceil_div(g.ny + 3, blk.y / 2), 2);
+  if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
+    hipLaunchKernelGGL((k_edges2d<STAGE, float>), ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc);
+  else
+    hipLaunchKernelGGL((k_edges2d<STAGE, double>), ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc);
+}
+template <int STAGE>
+void launch_nodes(fdcgks_problem* pb, const double* Sin, dim3 blk) {
+  const Geo& g = pb->g;
+  dim3 gn(ceil_div(g.nx + 2, blk.x), ceil_div(g.ny + 2, blk.y), 2);
+  if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
+    hipLaunchKernelGGL((k_nodes2d<STAGE, float>), gn, blk, 0, pb->stream, Sin, pb->Nb, g, pb->k, pb->sc);
+  else
+    hipLaunchKernelGGL((k_nodes2d<STAGE, double>), gn, blk, 0, pb->stream, Sin, pb->Nb, g, pb->k, pb->sc);
+}
+template <int STAGE>
+void launch_update(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout, dim3 blk) {
+  const Geo& g = pb->g;
+  dim3 gu(ceil_div(g.nx, blk.x), ceil_div(g.ny, blk.y), 2);
+  hipLaunchKernelGGL((k_update2d<STAGE>), gu, blk, 0, pb->stream, Sin, pb->E, pb->Nb, Ain, Out, Aout, g, pb->k,
+                     pb->sc);
+}
+
 template <int STAGE>
 fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout) {
   const Geo& g = pb->g;
   fdcgks_status st = halo2d(pb, const_cast<double*>(Sin));
   if (st) return st;
-  dim3 blk(64, 4);
-  dim3 ge(ceil_div(g.nx + 3, 64), ceil_div(g.ny + 3, 2), 2);
-  if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
-    hipLaunchKernelGGL((k_edges2d<STAGE, float>), ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc);
-  else
-    hipLaunchKernelGGL((k_edges2d<STAGE, double>), ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc);
+  launch_edges<STAGE>(pb, Sin, pb->tile[0]);
   mark(pb, STAGE == 1 ? TK_EDGE1 : TK_EDGE2);
-  dim3 gn(ceil_div(g.nx + 2, 64), ceil_div(g.ny + 2, 4), 2);
-  if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
-    hipLaunchKernelGGL((k_nodes2d<STAGE, float>), gn, blk, 0, pb->stream, Sin, pb->Nb, g, pb->k, pb->sc);
-  else
-    hipLaunchKernelGGL((k_nodes2d<STAGE, double>), gn, blk, 0, pb->stream, Sin, pb->Nb, g, pb->k, pb->sc);
+  launch_nodes<STAGE>(pb, Sin, pb->tile[1]);
   mark(pb, STAGE == 1 ? TK_NODE1 : TK_NODE2);
-  dim3 gu(ceil_div(g.nx, 64), ceil_div(g.ny, 4), 2);
-  hipLaunchKernelGGL((k_update2d<STAGE>), gu, blk, 0, pb->stream, Sin, pb->E, pb->Nb, Ain, Out, Aout, g, pb->k,
-                     pb->sc);
+  launch_update<STAGE>(pb, Sin, Ain, Out, Aout, pb->tile[2]);
   mark(pb, STAGE == 1 ? TK_UPD1 : TK_UPD2);
   return launch_check(pb, "stage");
 }
@@ -977,6 +1008,90 @@ fdcgks_status launch_run1d(fdcgks_problem* pb, int mode, int nsteps, double dt, 
     hipLaunchKernelGGL(k_run1d<double>, dim3(1), dim3(256), 0, pb->stream, S0, S1, pb->Sstar, pb->Acc, pb->E, pb->Nb,
                        pb->g, pb->k, pb->sc, pb->ngrid, pb->prm.bc, nsteps, cfl, use_cfl, mode);
   return launch_check(pb, "run1d");
+}
+
+// ---- captured steps
+void graph_invalidate(fdcgks_problem* pb) {
+  for (hipGraphExec_t& x : pb->gx)
+    if (x) {
+      (void)hipGraphExecDestroy(x);
+      x = nullptr;
+    }
+  pb->g_valid = false;
+}
+
+// One whole 2D step (dt reduction, two stages, step end) captured per
+// ping-pong parity on a private stream and replayed on the problem's stream.
+// The graphs depend only on the buffers, the launch shapes and (cfl,
+// use_cfl): the fixed dt, t and t_end are read from device memory.
+fdcgks_status capture_steps(fdcgks_problem* pb, double dt, double cfl) {
+  const int use_cfl = dt > 0 ? 0 : 1;
+  if (pb->g_valid && pb->g_use_cfl == use_cfl && (!use_cfl || pb->g_cfl == cfl) && pb->g_steps == pb->graph_steps)
+    return FDCGKS_OK;
+  graph_invalidate(pb);
+  if (!pb->cap) HIPCHK(pb, hipStreamCreateWithFlags(&pb->cap, hipStreamNonBlocking));
+  hipStream_t user = pb->stream;
+  const int cur0 = pb->cur;
+  for (int c = 0; c < 2; ++c) {
+    HIPCHK(pb, hipStreamBeginCapture(pb->cap, hipStreamCaptureModeThreadLocal));
+    pb->stream = pb->cap;
+    fdcgks_status st = FDCGKS_OK;
+    for (int q = 0, cc = c; q < pb->graph_steps && !st; ++q, cc = 1 - cc) {
+      pb->cur = cc;
+      st = begin_step(pb, dt, cfl);
+      if (!st) st = stage2d<1>(pb, pb->S[cc], nullptr, pb->Sstar, pb->Acc);
+      if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cc], nullptr);
+      if (!st) {
+        hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, pb->stream, pb->sc);
+        st = launch_check(pb, "step_end");
+      }
+    }
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(pb->cap, &gr);
+    pb->stream = user;
+    pb->cur = cur0;
+    if (!st && e != hipSuccess) st = fail(pb, FDCGKS_EHIP, "step capture: %s", hipGetErrorString(e));
+    if (!st) {
+      e = hipGraphInstantiate(&pb->gx[c], gr, nullptr, nullptr, 0);
+      if (e != hipSuccess) st = fail(pb, FDCGKS_EHIP, "step graph instantiation: %s", hipGetErrorString(e));
+    }
+    if (gr) (void)hipGraphDestroy(gr);
+    if (st) {
+      graph_invalidate(pb);
+      return st;
+    }
+  }
+  pb->g_valid = true;
+  pb->g_steps = pb->graph_steps;
+  pb->g_use_cfl = use_cfl;
+  pb->g_cfl = cfl;
+  return FDCGKS_OK;
+}
+
+// ---- launch shapes
+// A shape is valid for kernel class c (0 interface, 1 node, 2 update) when it
+// has whole waves, at most 256 threads, x in {32, 64, 128, 256} and, for the
+// interface sweep, an even y (the two normals of a point are paired rows).
+bool tile_ok(int c, unsigned x, unsigned y) {
+  if (!(x == 32 || x == 64 || x == 128 || x == 256) || y < 1 || x * y > 256 || (x * y) % 64 != 0) return false;
+  return c != 0 || y % 2 == 0;
+}
+
+// Device milliseconds of `reps` launches of one stage-1 kernel with shape blk.
+float time_tile(fdcgks_problem* pb, int c, dim3 blk, int reps, hipEvent_t e0, hipEvent_t e1) {
+  auto one = [&]() {
+    if (c == 0) launch_edges<1>(pb, pb->S[pb->cur], blk);
+    else if (c == 1) launch_nodes<1>(pb, pb->S[pb->cur], blk);
+    else launch_update<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, blk);
+  };
+  one();  // warm-up
+  (void)hipEventRecord(e0, pb->stream);
+  for (int r = 0; r < reps; ++r) one();
+  (void)hipEventRecord(e1, pb->stream);
+  if (hipEventSynchronize(e1) != hipSuccess) return -1.f;
+  float ms = -1.f;
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return -1.f;
+  return ms;
 }
 
 fdcgks_status check_params(const fdcgks_params* p) {
@@ -1271,6 +1386,16 @@ fdcgks_status fdcgks_step(fdcgks_problem* pb, double dt, double cfl, int32_t nst
     mark(pb, TK_STEP);
     nsteps = 0;
   }
+  const int K = pb->graph_steps;
+  if (pb->prm.dim == 2 && K > 0 && nsteps >= K && !pb->timing) {
+    st = capture_steps(pb, dt, cfl);
+    for (; !st && nsteps >= K; nsteps -= K) {
+      hipError_t e = hipGraphLaunch(pb->gx[cur], pb->stream);
+      if (e != hipSuccess) st = fail(pb, FDCGKS_EHIP, "step graph launch: %s", hipGetErrorString(e));
+      cur ^= K & 1;
+    }
+    if (st) nsteps = 0;
+  }
   for (int s = 0; s < nsteps; ++s) {
     pb->cur = cur;
     st = begin_step(pb, dt, cfl);
@@ -1297,7 +1422,9 @@ fdcgks_status fdcgks_step(fdcgks_problem* pb, double dt, double cfl, int32_t nst
 
 fdcgks_status fdcgks_destroy(fdcgks_problem* pb) {
   if (!pb) return FDCGKS_OK;
-  if (pb->stream || true) (void)hipStreamSynchronize(pb->stream);
+  (void)hipStreamSynchronize(pb->stream);
+  graph_invalidate(pb);
+  if (pb->cap) (void)hipStreamDestroy(pb->cap);
   free_all(pb);
   for (hipEvent_t e : pb->ev) (void)hipEventDestroy(e);
   delete pb;
@@ -1432,6 +1559,94 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
     HIPCHK(pb, hipMemcpy2DAsync(lam_in + p * n, row, pb->LS0 + p * g.plane + interior, pitchb, row, g.ny, kout,
                                 pb->stream));
   if (!on_device) HIPCHK(pb, hipStreamSynchronize(pb->stream));
+  return FDCGKS_OK;
+}
+
+fdcgks_status fdcgks_set_option(fdcgks_problem* pb, int32_t option, int64_t value) {
+  if (!pb) return fail(nullptr, FDCGKS_EINVAL, "problem is NULL");
+  switch (option) {
+    case FDCGKS_OPT_GRAPH:
+      if (value < 0 || value > 64) return fail(pb, FDCGKS_EINVAL, "steps per graph must be in 0..64");
+      pb->graph_steps = (int)value;
+      graph_invalidate(pb);
+      return FDCGKS_OK;
+    case FDCGKS_OPT_TILE_EDGE:
+    case FDCGKS_OPT_TILE_NODE:
+    case FDCGKS_OPT_TILE_UPDATE: {
+      const int c = option - FDCGKS_OPT_TILE_EDGE;
+      const unsigned x = (unsigned)(value & 0xffff), y = (unsigned)((value >> 16) & 0xffff);
+      if (value < 0 || (value >> 32) != 0 || !tile_ok(c, x, y))
+        return fail(pb, FDCGKS_EINVAL, "invalid launch shape %u x %u for kernel class %d", x, y, c);
+      pb->tile[c] = dim3(x, y);
+      graph_invalidate(pb);
+      return FDCGKS_OK;
+    }
+    default:
+      return fail(pb, FDCGKS_EINVAL, "unknown option %d", option);
+  }
+}
+
+fdcgks_status fdcgks_get_option(const fdcgks_problem* cpb, int32_t option, int64_t* value) {
+  fdcgks_problem* pb = const_cast<fdcgks_problem*>(cpb);
+  if (!pb || !value) return fail(pb, FDCGKS_EINVAL, "NULL argument");
+  if (option == FDCGKS_OPT_GRAPH) {
+    *value = pb->graph_steps;
+    return FDCGKS_OK;
+  }
+  if (option >= FDCGKS_OPT_TILE_EDGE && option <= FDCGKS_OPT_TILE_UPDATE) {
+    const dim3 t = pb->tile[option - FDCGKS_OPT_TILE_EDGE];
+    *value = (int64_t)t.x | ((int64_t)t.y << 16);
+    return FDCGKS_OK;
+  }
+  return fail(pb, FDCGKS_EINVAL, "unknown option %d", option);
+}
+
+fdcgks_status fdcgks_autotune(fdcgks_problem* pb, int32_t reps) {
+  if (!pb) return fail(nullptr, FDCGKS_EINVAL, "problem is NULL");
+  if (reps < 1 || reps > 1000) return fail(pb, FDCGKS_EINVAL, "reps must be in 1..1000");
+  if (pb->prm.dim != 2) return FDCGKS_OK;  // the 1D path runs in one workgroup: nothing to tune
+  if (!state_ready(pb)) return fail(pb, FDCGKS_ESTATE, "set_state has not been called for every grid");
+  double dt = 0.0;
+  fdcgks_status st = fdcgks_compute_dt(pb, 0.4, &dt);
+  if (st) return st;
+  // one real stage 1 so that the update reads valid interface and node results
+  std::memset(pb->sc_host, 0, sizeof(Scal));
+  pb->sc_host->dt = dt;
+  st = write_scal(pb);
+  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc);
+  if (st) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(pb, hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(pb, FDCGKS_EHIP, "event creation failed");
+  }
+  static const unsigned cand[][2] = {{64, 4}, {64, 2}, {128, 2}, {32, 8}, {256, 1}, {128, 1}, {64, 1}, {32, 4}};
+  for (int c = 0; c < 3 && !st; ++c) {
+    float best = -1.f;
+    dim3 pick = pb->tile[c];
+    for (const auto& xy : cand) {
+      if (!tile_ok(c, xy[0], xy[1])) continue;
+      const float ms = time_tile(pb, c, dim3(xy[0], xy[1]), reps, e0, e1);
+      if (ms < 0.f) {
+        st = launch_check(pb, "autotune");
+        if (!st) st = fail(pb, FDCGKS_EHIP, "autotune timing failed");
+        break;
+      }
+      if (best < 0.f || ms < best) {
+        best = ms;
+        pick = dim3(xy[0], xy[1]);
+      }
+    }
+    pb->tile[c] = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  graph_invalidate(pb);
+  if (st) return st;
+  st = read_scal(pb);
+  if (st) return st;
+  if (pb->sc_host->stop & 1) return fail(pb, FDCGKS_ENONPHYS, "non-physical state during autotuning");
   return FDCGKS_OK;
 }
 

@@ -73,3 +73,7 @@ def test_null_arguments():
     assert L.fdcgks_set_state(None, 0, None, None, None, 0) == _lib.EINVAL
     assert L.fdcgks_step_vjp(None, 0.1, None, None, 0) == _lib.EINVAL
     assert L.fdcgks_batch_step(None, 0.5, 1, None, None, None) == _lib.EINVAL
+    v = C.c_int64()
+    assert L.fdcgks_set_option(None, 0, 1) == _lib.EINVAL
+    assert L.fdcgks_get_option(None, 0, C.byref(v)) == _lib.EINVAL
+    assert L.fdcgks_autotune(None, 3) == _lib.EINVAL
