@@ -13,7 +13,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdcgks.so")
 SOURCES = [os.path.join(CSRC, "fdcgks.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, "gks_device.hpp"), os.path.join(CSRC, "adjoint.inc.hip"), os.path.join(ROOT, "include", "fdcgks.h")]
+DEPS = SOURCES + [os.path.join(CSRC, "gks_device.hpp"), os.path.join(CSRC, "adjoint.inc.hip"), os.path.join(CSRC, "gks_adjoint.hpp"), os.path.join(ROOT, "include", "fdcgks.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -15,13 +15,11 @@
 //   GENO^T       of the line and nodal reconstructions, scattered to the
 //                nodes they read (atomic adds), then the periodic halo is
 //                folded back onto its images.
-// The local Jacobians of the two nonlinear pointwise maps come from running
-// the same templated device arithmetic on dual numbers, one input direction
-// per pass.  min/max ties take the first argument and d|x|/dx = 0 at 0.
+// The local transposes of the two nonlinear pointwise maps (gas-kinetic
+// solvers, GENO reconstructions) are the reverse-mode routines of
+// gks_adjoint.hpp.  min/max ties take the first argument and d|x|/dx = 0 at 0.
 
 namespace {
-
-using fdk::DD;
 
 // Planes of the per-node operator adjoint: L[4], Lt[4], Gx[4], Gy[4],
 // Gxt[4], Gyt[4] per grid.
@@ -203,53 +201,52 @@ __device__ __forceinline__ void line_adjoint(const double* __restrict__ S, doubl
   for (int c = 0; c < 4; ++c) {
     const double* w = S + (G * 12 + c) * pl + o;
     const double* x = S + (G * 12 + f * 4 + c) * pl + o;
-    double in[8] = {w[0], w[st], w[2 * st], w[3 * st], x[0], x[st], x[2 * st], x[3 * st]};
+    const double q[4] = {w[0], w[st], w[2 * st], w[3 * st]};
+    const double xv[4] = {x[0], x[st], x[2 * st], x[3 * st]};
+    double qb[4] = {0, 0, 0, 0}, xb[4] = {0, 0, 0, 0};
+    fdk::recon_iface_b(k, q, xv, g.h, g.invh, lv[c], qb, xb);
     double* lw = lamS + (G * 12 + c) * pl + o;
     double* lx = lamS + (G * 12 + f * 4 + c) * pl + o;
-    for (int q = 0; q < 8; ++q) {
-      DD a[8];
-      for (int r = 0; r < 8; ++r) a[r] = DD(in[r], r == q ? 1.0 : 0.0);
-      fdk::IfaceRecT<DD> R = fdk::recon_iface<DD>(k, a[0], a[1], a[2], a[3], a[4], a[5], a[6], a[7], g.h, g.invh);
-      const double s = lv[c][0] * R.vl.d + lv[c][1] * R.dl.d + lv[c][2] * R.cl.d + lv[c][3] * R.vr.d +
-                       lv[c][4] * R.dr.d + lv[c][5] * R.cr.d;
-      if (s != 0.0) atomicAdd(q < 4 ? lw + q * st : lx + (q - 4) * st, s);
+    for (int m = 0; m < 4; ++m) {
+      if (qb[m] != 0.0) atomicAdd(lw + m * st, qb[m]);
+      if (xb[m] != 0.0) atomicAdd(lx + m * st, xb[m]);
     }
   }
 }
 
-// Local Jacobian-transpose of one gas-kinetic interface solve: lam of the
-// outputs (local frame) -> lam of WL, WR, nL, nR, Wt (local frame).
-template <bool SWAP, int STAGE, class FT>
+// Adjoint of one gas-kinetic interface solve: lam of the outputs (global
+// component order) -> lam of the inputs in the local frame: lin[0..3] WL,
+// [4..7] WR, [8..11] nL, [12..15] nR, [16..19] Wt.
+template <bool SWAP, int STAGE>
 __device__ __forceinline__ void solve_adjoint(const Consts& k, double dt, const fdk::IfaceRec (&rn)[4],
                                               const double (&tang)[4], const double (&lF)[4], const double (&lFt)[4],
                                               const double (&lWl)[4], const double (&lWr)[4],
                                               const double (&lWlt)[4], const double (&lWrt)[4], double (&lin)[20]) {
-  double x0[20];
+  fdk::GksIO<double, 2> in, ob, inb;
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const int q = SWAP ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
-    x0[c] = rn[q].vl;
-    x0[4 + c] = rn[q].vr;
-    x0[8 + c] = rn[q].dl;
-    x0[12 + c] = rn[q].dr;
-    x0[16 + c] = tang[q];
+    const int q = SWAP ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;  // global component of local slot c
+    in.WL[c] = rn[q].vl;
+    in.WR[c] = rn[q].vr;
+    in.nL[c] = rn[q].dl;
+    in.nR[c] = rn[q].dr;
+    in.Wt[c] = tang[q];
+    ob.Ft[c] = lFt[q];
+    ob.Wlt[c] = lWlt[q];
+    ob.Wrt[c] = lWrt[q];
+    ob.F[c] = STAGE == 1 ? lF[q] : 0.0;
+    ob.Wl[c] = STAGE == 1 ? lWl[q] : 0.0;
+    ob.Wr[c] = STAGE == 1 ? lWr[q] : 0.0;
+    inb.WL[c] = inb.WR[c] = inb.nL[c] = inb.nR[c] = inb.Wt[c] = 0.0;
   }
-  for (int q = 0; q < 20; ++q) {
-    fdk::GksIO<DD, 2> io;
-    for (int c = 0; c < 4; ++c) {
-      io.WL[c] = DD(x0[c], q == c ? 1.0 : 0.0);
-      io.WR[c] = DD(x0[4 + c], q == 4 + c ? 1.0 : 0.0);
-      io.nL[c] = DD(x0[8 + c], q == 8 + c ? 1.0 : 0.0);
-      io.nR[c] = DD(x0[12 + c], q == 12 + c ? 1.0 : 0.0);
-      io.Wt[c] = DD(x0[16 + c], q == 16 + c ? 1.0 : 0.0);
-    }
-    fdk::gks_iface<DD, 2, true>(k, DD(dt), io);
-    double s = 0.0;
-    for (int c = 0; c < 4; ++c) {
-      const int gq = SWAP ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;  // global component of local slot c
-      s += lFt[gq] * io.Ft[c].d + lWlt[gq] * io.Wlt[c].d + lWrt[gq] * io.Wrt[c].d;
-      if (STAGE == 1) s += lF[gq] * io.F[c].d + lWl[gq] * io.Wl[c].d + lWr[gq] * io.Wr[c].d;
-    }
-    lin[q] = s;
+  fdk::gks_iface_b(k, dt, in, ob, inb);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    lin[c] = inb.WL[c];
+    lin[4 + c] = inb.WR[c];
+    lin[8 + c] = inb.nL[c];
+    lin[12 + c] = inb.nR[c];
+    lin[16 + c] = inb.Wt[c];
   }
 }
 
@@ -295,8 +292,8 @@ __global__ __launch_bounds__(256) void k_adj_edges(const double* __restrict__ S,
       lWrt[c] = 0.5 * le[(21 + c) * pl] + 0.25 * pst;
     }
     lchi = le[8 * pl];
-    if (fam == G) solve_adjoint<false, STAGE, double>(k, dt, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
-    else solve_adjoint<true, STAGE, double>(k, dt, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
+    if (fam == G) solve_adjoint<false, STAGE>(k, dt, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
+    else solve_adjoint<true, STAGE>(k, dt, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
   }
   // the tangential slope of this solve came from the partner line: send its lambda
   const bool swap = fam != G;
@@ -351,41 +348,27 @@ __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S,
     lG[c] = ln[(8 + c) * pl];
     lGt[c] = ln[(12 + c) * pl];
   }
-  // nodal solver^T: 12 inputs (W, Wx^N, Wy^N)
-  double lin[12];
-  for (int q = 0; q < 12; ++q) {
-    DD a[4], bx[4], by[4], F[4], Ft[4], Gv[4], Gt[4];
-    for (int c = 0; c < 4; ++c) {
-      a[c] = DD(W[c], q == c ? 1.0 : 0.0);
-      bx[c] = DD(Wx[c], q == 4 + c ? 1.0 : 0.0);
-      by[c] = DD(Wy[c], q == 8 + c ? 1.0 : 0.0);
-    }
-    fdk::gks_node<DD, 2, true>(k, a, bx, by, F, Ft, Gv, Gt);
-    double s = 0.0;
-    for (int c = 0; c < 4; ++c) {
-      s += lFt[c] * Ft[c].d + lGt[c] * Gt[c].d;
-      if (STAGE == 1) s += lF[c] * F[c].d + lG[c] * Gv[c].d;
-    }
-    lin[q] = s;
-  }
+  // nodal solver^T (stage 2 has no F, G outputs)
+  double Wb[4] = {0, 0, 0, 0}, Wxb[4] = {0, 0, 0, 0}, Wyb[4] = {0, 0, 0, 0};
+  if (STAGE == 2)
+    for (int c = 0; c < 4; ++c) { lF[c] = 0.0; lG[c] = 0.0; }
+  fdk::gks_node_b(k, W, Wx, Wy, lF, lFt, lG, lGt, Wb, Wxb, Wyb);
   double* lS = lamS + (long)grid * 12 * pl + o;
   for (int c = 0; c < 4; ++c) {
-    if (lin[c] != 0.0) atomicAdd(lS + c * pl, lin[c]);
-    // derivative reconstructions along x and y (6 inputs each)
+    if (Wb[c] != 0.0) atomicAdd(lS + c * pl, Wb[c]);
+    // derivative reconstructions along x and y
     for (int a = 0; a < 2; ++a) {
-      const double la = lin[4 + 4 * a + c];
+      const double la = a == 0 ? Wxb[c] : Wyb[c];
       if (la == 0.0) continue;
       const long st = a == 0 ? 1 : g.pitch;
       const double* w = B + c * pl + o;
       const double* x = B + ((a == 0 ? 4 : 8) + c) * pl + o;
-      double in[6] = {w[-st], w[0], w[st], x[-st], x[0], x[st]};
-      for (int q = 0; q < 6; ++q) {
-        DD v[6];
-        for (int r = 0; r < 6; ++r) v[r] = DD(in[r], r == q ? 1.0 : 0.0);
-        DD d = fdk::recon_node<DD>(k, v[0], v[1], v[2], v[3], v[4], v[5], g.h, g.invh);
-        const double s = la * d.d;
-        if (s != 0.0)
-          atomicAdd(lS + (q < 3 ? c : (a == 0 ? 4 : 8) + c) * pl + (q % 3 - 1) * st, s);
+      const double q[3] = {w[-st], w[0], w[st]}, xv[3] = {x[-st], x[0], x[st]};
+      double qb[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
+      fdk::recon_node_b(k, q, xv, g.h, g.invh, la, qb, xb);
+      for (int m = 0; m < 3; ++m) {
+        if (qb[m] != 0.0) atomicAdd(lS + c * pl + (m - 1) * st, qb[m]);
+        if (xb[m] != 0.0) atomicAdd(lS + ((a == 0 ? 4 : 8) + c) * pl + (m - 1) * st, xb[m]);
       }
     }
   }

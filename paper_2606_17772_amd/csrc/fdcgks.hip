@@ -820,6 +820,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
 
 }  // namespace
 
+#include "gks_adjoint.hpp"
 #include "adjoint.inc.hip"
 
 namespace {

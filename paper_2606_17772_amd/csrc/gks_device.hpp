@@ -8,6 +8,12 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+
+// Everything here is also host-callable, so that host-side checks can run the
+// same arithmetic.
+#define FDK_HD __host__ __device__ __forceinline__
+
 namespace fdk {
 
 // Scheme constants, passed by value to every kernel.
@@ -26,18 +32,18 @@ struct Consts {
 };
 
 // ---------------------------------------------------------------- math
-__device__ __forceinline__ double m_erfc(double x) { return erfc(x); }
-__device__ __forceinline__ float m_erfc(float x) { return erfcf(x); }
-__device__ __forceinline__ double m_exp(double x) { return exp(x); }
-__device__ __forceinline__ float m_exp(float x) { return expf(x); }
-__device__ __forceinline__ double m_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float m_sqrt(float x) { return sqrtf(x); }
-__device__ __forceinline__ double m_abs(double x) { return fabs(x); }
-__device__ __forceinline__ float m_abs(float x) { return fabsf(x); }
+FDK_HD double m_erfc(double x) { return erfc(x); }
+FDK_HD float m_erfc(float x) { return erfcf(x); }
+FDK_HD double m_exp(double x) { return exp(x); }
+FDK_HD float m_exp(float x) { return expf(x); }
+FDK_HD double m_sqrt(double x) { return sqrt(x); }
+FDK_HD float m_sqrt(float x) { return sqrtf(x); }
+FDK_HD double m_abs(double x) { return fabs(x); }
+FDK_HD float m_abs(float x) { return fabsf(x); }
 
-template <class T> __device__ __forceinline__ T sqr(T a) { return a * a; }
+template <class T> FDK_HD T sqr(T a) { return a * a; }
 
-template <class T> __device__ __forceinline__ T ipow(T x, int r) {
+template <class T> FDK_HD T ipow(T x, int r) {
   T y = x;
   for (int k = 1; k < r; ++k) y = y * x;
   return y;
@@ -48,55 +54,55 @@ template <class T> __device__ __forceinline__ T ipow(T x, int r) {
 // kernels assemble local Jacobian-transpose products.
 struct DD {
   double v, d;
-  __device__ __forceinline__ DD() : v(0.0), d(0.0) {}
-  __device__ __forceinline__ DD(double a) : v(a), d(0.0) {}
-  __device__ __forceinline__ DD(double a, double b) : v(a), d(b) {}
-  __device__ __forceinline__ explicit operator double() const { return v; }
+  FDK_HD DD() : v(0.0), d(0.0) {}
+  FDK_HD DD(double a) : v(a), d(0.0) {}
+  FDK_HD DD(double a, double b) : v(a), d(b) {}
+  FDK_HD explicit operator double() const { return v; }
 };
-__device__ __forceinline__ DD operator+(DD a, DD b) { return DD(a.v + b.v, a.d + b.d); }
-__device__ __forceinline__ DD operator-(DD a, DD b) { return DD(a.v - b.v, a.d - b.d); }
-__device__ __forceinline__ DD operator-(DD a) { return DD(-a.v, -a.d); }
-__device__ __forceinline__ DD operator*(DD a, DD b) { return DD(a.v * b.v, a.d * b.v + a.v * b.d); }
-__device__ __forceinline__ DD operator/(DD a, DD b) {
+FDK_HD DD operator+(DD a, DD b) { return DD(a.v + b.v, a.d + b.d); }
+FDK_HD DD operator-(DD a, DD b) { return DD(a.v - b.v, a.d - b.d); }
+FDK_HD DD operator-(DD a) { return DD(-a.v, -a.d); }
+FDK_HD DD operator*(DD a, DD b) { return DD(a.v * b.v, a.d * b.v + a.v * b.d); }
+FDK_HD DD operator/(DD a, DD b) {
   double q = a.v / b.v;
   return DD(q, (a.d - q * b.d) / b.v);
 }
-__device__ __forceinline__ DD operator+(DD a, double b) { return DD(a.v + b, a.d); }
-__device__ __forceinline__ DD operator+(double a, DD b) { return DD(a + b.v, b.d); }
-__device__ __forceinline__ DD operator-(DD a, double b) { return DD(a.v - b, a.d); }
-__device__ __forceinline__ DD operator-(double a, DD b) { return DD(a - b.v, -b.d); }
-__device__ __forceinline__ DD operator*(DD a, double b) { return DD(a.v * b, a.d * b); }
-__device__ __forceinline__ DD operator*(double a, DD b) { return DD(a * b.v, a * b.d); }
-__device__ __forceinline__ DD operator/(DD a, double b) { return DD(a.v / b, a.d / b); }
-__device__ __forceinline__ DD operator/(double a, DD b) {
+FDK_HD DD operator+(DD a, double b) { return DD(a.v + b, a.d); }
+FDK_HD DD operator+(double a, DD b) { return DD(a + b.v, b.d); }
+FDK_HD DD operator-(DD a, double b) { return DD(a.v - b, a.d); }
+FDK_HD DD operator-(double a, DD b) { return DD(a - b.v, -b.d); }
+FDK_HD DD operator*(DD a, double b) { return DD(a.v * b, a.d * b); }
+FDK_HD DD operator*(double a, DD b) { return DD(a * b.v, a * b.d); }
+FDK_HD DD operator/(DD a, double b) { return DD(a.v / b, a.d / b); }
+FDK_HD DD operator/(double a, DD b) {
   double q = a / b.v;
   return DD(q, -q * b.d / b.v);
 }
-__device__ __forceinline__ DD& operator+=(DD& a, DD b) { a = a + b; return a; }
-__device__ __forceinline__ DD& operator-=(DD& a, DD b) { a = a - b; return a; }
-__device__ __forceinline__ DD& operator*=(DD& a, DD b) { a = a * b; return a; }
-__device__ __forceinline__ bool operator>(DD a, DD b) { return a.v > b.v; }
-__device__ __forceinline__ bool operator<(DD a, DD b) { return a.v < b.v; }
-__device__ __forceinline__ bool operator>(DD a, double b) { return a.v > b; }
-__device__ __forceinline__ bool operator<(DD a, double b) { return a.v < b; }
-__device__ __forceinline__ DD m_erfc(DD a) { return DD(erfc(a.v), -1.1283791670955126 * exp(-a.v * a.v) * a.d); }
-__device__ __forceinline__ DD m_exp(DD a) { double e = exp(a.v); return DD(e, e * a.d); }
-__device__ __forceinline__ DD m_sqrt(DD a) { double q = sqrt(a.v); return DD(q, a.d / (2.0 * q)); }
+FDK_HD DD& operator+=(DD& a, DD b) { a = a + b; return a; }
+FDK_HD DD& operator-=(DD& a, DD b) { a = a - b; return a; }
+FDK_HD DD& operator*=(DD& a, DD b) { a = a * b; return a; }
+FDK_HD bool operator>(DD a, DD b) { return a.v > b.v; }
+FDK_HD bool operator<(DD a, DD b) { return a.v < b.v; }
+FDK_HD bool operator>(DD a, double b) { return a.v > b; }
+FDK_HD bool operator<(DD a, double b) { return a.v < b; }
+FDK_HD DD m_erfc(DD a) { return DD(erfc(a.v), -1.1283791670955126 * exp(-a.v * a.v) * a.d); }
+FDK_HD DD m_exp(DD a) { double e = exp(a.v); return DD(e, e * a.d); }
+FDK_HD DD m_sqrt(DD a) { double q = sqrt(a.v); return DD(q, a.d / (2.0 * q)); }
 // |x| with derivative 0 at x == 0 (the adjoint's convention for ties)
-__device__ __forceinline__ DD m_abs(DD a) { return a.v > 0 ? a : (a.v < 0 ? -a : DD(0.0, 0.0)); }
+FDK_HD DD m_abs(DD a) { return a.v > 0 ? a : (a.v < 0 ? -a : DD(0.0, 0.0)); }
 
 // scalar helpers shared by double and DD (ties keep the first argument)
-__device__ __forceinline__ double g_abs(double a) { return fabs(a); }
-__device__ __forceinline__ double g_max(double a, double b) { return fmax(a, b); }
-__device__ __forceinline__ double g_min(double a, double b) { return fmin(a, b); }
-__device__ __forceinline__ double g_tanh(double a) { return tanh(a); }
-__device__ __forceinline__ DD g_abs(DD a) { return m_abs(a); }
-__device__ __forceinline__ DD g_max(DD a, DD b) { return b.v > a.v ? b : a; }
-__device__ __forceinline__ DD g_min(DD a, DD b) { return b.v < a.v ? b : a; }
-__device__ __forceinline__ DD g_tanh(DD a) { double t = tanh(a.v); return DD(t, (1.0 - t * t) * a.d); }
-__device__ __forceinline__ double val(double a) { return a; }
-__device__ __forceinline__ float val(float a) { return a; }
-__device__ __forceinline__ double val(DD a) { return a.v; }
+FDK_HD double g_abs(double a) { return fabs(a); }
+FDK_HD double g_max(double a, double b) { return fmax(a, b); }
+FDK_HD double g_min(double a, double b) { return fmin(a, b); }
+FDK_HD double g_tanh(double a) { return tanh(a); }
+FDK_HD DD g_abs(DD a) { return m_abs(a); }
+FDK_HD DD g_max(DD a, DD b) { return b.v > a.v ? b : a; }
+FDK_HD DD g_min(DD a, DD b) { return b.v < a.v ? b : a; }
+FDK_HD DD g_tanh(DD a) { double t = tanh(a.v); return DD(t, (1.0 - t * t) * a.d); }
+FDK_HD double val(double a) { return a; }
+FDK_HD float val(float a) { return a; }
+FDK_HD double val(DD a) { return a.v; }
 
 // ----------------------------------------------------- GENO, Sec. 3 / App. C
 // Path function and blend of one side.  IS1 is the IS^tau reference;
@@ -108,7 +114,7 @@ template <class R> struct GenoOutT {
   R v, d, chi;
 };
 template <class R>
-__device__ __forceinline__ GenoOutT<R> geno(const Consts& k, R IS1, R IS2, R IS3, double d1, double d2, double d3,
+FDK_HD GenoOutT<R> geno(const Consts& k, R IS1, R IS2, R IS3, double d1, double d2, double d3,
                                             R q1, R q2, R q3, R dq1, R dq2, R dq3, R PH, R PHx) {
   R tau = 0.5 * g_abs((IS2 + IS3) - 2.0 * IS1);
   R ISH = g_max(IS1, g_max(IS2, IS3));
@@ -138,7 +144,7 @@ template <class R> struct IfaceRecT {
 };
 using IfaceRec = IfaceRecT<double>;
 template <class R>
-__device__ __forceinline__ IfaceRecT<R> recon_iface(const Consts& k, R q0, R q1, R q2, R q3, R x0, R x1, R x2, R x3,
+FDK_HD IfaceRecT<R> recon_iface(const Consts& k, R q0, R q1, R q2, R q3, R x0, R x1, R x2, R x3,
                                                     double h, double invh) {
   IfaceRecT<R> o;
   R PHl = ((7.0 * q0 + 35.0 * q1 + 21.0 * q2 + q3) + (x0 + 22.0 * x1 - 7.0 * x2) * h) * (1.0 / 64.0);
@@ -177,7 +183,7 @@ __device__ __forceinline__ IfaceRecT<R> recon_iface(const Consts& k, R q0, R q1,
 // Node derivative from q0..q2 = Q_{j-1..j+1}, x0..x2 (Eq. 6th-compact-recons,
 // App. C3; the central sub-stencil is the IS^tau reference with weight dc).
 template <class R>
-__device__ __forceinline__ R recon_node(const Consts& k, R q0, R q1, R q2, R x0, R x1, R x2, double h, double invh) {
+FDK_HD R recon_node(const Consts& k, R q0, R q1, R q2, R x0, R x1, R x2, double h, double invh) {
   R PHx = (9.0 * (q0 - q2) + h * (x0 + 46.0 * x1 + x2)) * (invh * (1.0 / 30.0));
   if (k.variant == 2) return PHx;
   R hx0 = h * x0, hx2 = h * x2;
@@ -200,13 +206,13 @@ template <class FT> struct Mom {
   FT x2, x4;
 };
 
-template <class FT> __device__ __forceinline__ void mu_rec(FT* m, FT U, FT i2l) {
+template <class FT> FDK_HD void mu_rec(FT* m, FT U, FT i2l) {
 #pragma unroll
   for (int n = 0; n < 5; ++n) m[n + 2] = U * m[n + 1] + FT(n + 1) * i2l * m[n];
 }
 
 // <u^P v^Q xi^(2R) psi>, psi = (1, u, v, (u^2+v^2+xi^2)/2), R in {0, 1}
-template <int P, int Q, int R, class FT> __device__ __forceinline__ void muv(const Mom<FT>& m, FT o[4]) {
+template <int P, int Q, int R, class FT> FDK_HD void muv(const Mom<FT>& m, FT o[4]) {
   const FT xr = R == 0 ? FT(1) : m.x2;
   const FT xr1 = R == 0 ? m.x2 : m.x4;
   FT b = m.mu[P] * m.mv[Q];
@@ -216,7 +222,7 @@ template <int P, int Q, int R, class FT> __device__ __forceinline__ void muv(con
   o[3] = FT(0.5) * ((m.mu[P + 2] * m.mv[Q] + m.mu[P] * m.mv[Q + 2]) * xr + b * xr1);
 }
 // <(s.psi) u^P v^Q psi>
-template <int P, int Q, class FT> __device__ __forceinline__ void ma(const FT s[4], const Mom<FT>& m, FT o[4]) {
+template <int P, int Q, class FT> FDK_HD void ma(const FT s[4], const Mom<FT>& m, FT o[4]) {
   FT t0[4], t1[4], t2[4], t3[4], t4[4], t5[4];
   muv<P, Q, 0>(m, t0);
   muv<P + 1, Q, 0>(m, t1);
@@ -229,14 +235,14 @@ template <int P, int Q, class FT> __device__ __forceinline__ void ma(const FT s[
   for (int i = 0; i < 4; ++i) o[i] = s[0] * t0[i] + s[1] * t1[i] + s[2] * t2[i] + h3 * (t3[i] + t4[i] + t5[i]);
 }
 // 1D: psi = (1, u, (u^2+xi^2)/2)
-template <int P, int R, class FT> __device__ __forceinline__ void mu1(const Mom<FT>& m, FT o[3]) {
+template <int P, int R, class FT> FDK_HD void mu1(const Mom<FT>& m, FT o[3]) {
   const FT xr = R == 0 ? FT(1) : m.x2;
   const FT xr1 = R == 0 ? m.x2 : m.x4;
   o[0] = m.mu[P] * xr;
   o[1] = m.mu[P + 1] * xr;
   o[2] = FT(0.5) * (m.mu[P + 2] * xr + m.mu[P] * xr1);
 }
-template <int P, class FT> __device__ __forceinline__ void ma1(const FT s[3], const Mom<FT>& m, FT o[3]) {
+template <int P, class FT> FDK_HD void ma1(const FT s[3], const Mom<FT>& m, FT o[3]) {
   FT t0[3], t1[3], t2[3], t3[3];
   mu1<P, 0>(m, t0);
   mu1<P + 1, 0>(m, t1);
@@ -251,7 +257,7 @@ template <int P, class FT> __device__ __forceinline__ void ma1(const FT s[3], co
 template <class FT> struct Prim {
   FT rho, irho, U, V, p, lam, i2l;
 };
-template <class FT, int DIM> __device__ __forceinline__ Prim<FT> prim(const FT* W, FT gamma) {
+template <class FT, int DIM> FDK_HD Prim<FT> prim(const FT* W, FT gamma) {
   Prim<FT> s;
   s.rho = W[0];
   s.irho = FT(1) / W[0];
@@ -263,20 +269,20 @@ template <class FT, int DIM> __device__ __forceinline__ Prim<FT> prim(const FT* 
   s.lam = FT(0.5) / s.i2l;
   return s;
 }
-template <class FT, int DIM> __device__ __forceinline__ void mom_common(const Prim<FT>& s, FT K, Mom<FT>& m) {
+template <class FT, int DIM> FDK_HD void mom_common(const Prim<FT>& s, FT K, Mom<FT>& m) {
   m.mv[0] = FT(1);
   m.mv[1] = s.V;
   if (DIM == 2) mu_rec(m.mv, s.V, s.i2l);
   m.x2 = K * s.i2l;
   m.x4 = m.x2 * (K + FT(2)) * s.i2l;
 }
-template <class FT> __device__ __forceinline__ void mom_full(const Prim<FT>& s, Mom<FT>& m) {
+template <class FT> FDK_HD void mom_full(const Prim<FT>& s, Mom<FT>& m) {
   m.mu[0] = FT(1);
   m.mu[1] = s.U;
   mu_rec(m.mu, s.U, s.i2l);
 }
 // half line: sgn = +1 (u > 0) or -1 (u < 0)
-template <class FT> __device__ __forceinline__ void mom_half(const Prim<FT>& s, FT sgn, Mom<FT>& m) {
+template <class FT> FDK_HD void mom_half(const Prim<FT>& s, FT sgn, Mom<FT>& m) {
   FT sl = m_sqrt(s.lam);
   m.mu[0] = FT(0.5) * m_erfc(-sgn * sl * s.U);
   // 1/(2 sqrt(pi lambda)) = sqrt(1/(2 lambda)) / sqrt(2 pi)
@@ -287,7 +293,7 @@ template <class FT> __device__ __forceinline__ void mom_half(const Prim<FT>& s, 
 // Micro slope s with <psi (s.psi)> = d (d per unit density): closed-form
 // solution of the moment system.
 template <class FT, int DIM>
-__device__ __forceinline__ void slope(const Prim<FT>& q, FT K, FT iKd, const FT* d, FT* s) {
+FDK_HD void slope(const Prim<FT>& q, FT K, FT iKd, const FT* d, FT* s) {
   if (DIM == 2) {
     FT e = q.U * q.U + q.V * q.V + (K + FT(2)) * q.i2l;
     FT B = FT(2) * d[3] - e * d[0];
@@ -315,7 +321,7 @@ __device__ __forceinline__ void slope(const Prim<FT>& q, FT K, FT iKd, const FT*
 template <class FT> struct TimeCoef {
   FT c[5], ct[5], e1;  // e1 = exp(-dt/tau)
 };
-template <class FT> __device__ __forceinline__ TimeCoef<FT> time_coef(FT dt, FT tau) {
+template <class FT> FDK_HD TimeCoef<FT> time_coef(FT dt, FT tau) {
   TimeCoef<FT> r;
   // tau = 0 (p_l = p_r without a c1 term): the tau -> 0+ limit, exp(-T/tau) = 0
   FT Eh = val(tau) > 0 ? m_exp(-FT(0.5) * dt / tau) : FT(0);
@@ -358,7 +364,7 @@ template <class FT, int DIM> struct GksIO {
 // tr = <psi ((a.psi) u + (b.psi) v)>, tru = <u psi (...)>, Ap = <psi A.psi>,
 // Au = <u psi A.psi> (2D; 1D drops the v terms).
 template <class FT, int DIM>
-__device__ __forceinline__ void transport(const FT* a, const FT* b, const Mom<FT>& m, FT* tr, FT* tru) {
+FDK_HD void transport(const FT* a, const FT* b, const Mom<FT>& m, FT* tr, FT* tru) {
   if (DIM == 2) {
     FT x[4], y[4];
     ma<1, 0>(a, m, x); ma<0, 1>(b, m, y);
@@ -372,12 +378,12 @@ __device__ __forceinline__ void transport(const FT* a, const FT* b, const Mom<FT
     ma1<2>(a, m, tru);
   }
 }
-template <class FT, int DIM> __device__ __forceinline__ void tslope(const FT* A, const Mom<FT>& m, FT* Ap, FT* Au) {
+template <class FT, int DIM> FDK_HD void tslope(const FT* A, const Mom<FT>& m, FT* Ap, FT* Au) {
   if (DIM == 2) { ma<0, 0>(A, m, Ap); ma<1, 0>(A, m, Au); }
   else { ma1<0>(A, m, Ap); ma1<1>(A, m, Au); }
 }
 // <psi> and <u psi> of a (half or full) state
-template <class FT, int DIM> __device__ __forceinline__ void psi_moms(const Mom<FT>& m, FT* p, FT* u) {
+template <class FT, int DIM> FDK_HD void psi_moms(const Mom<FT>& m, FT* p, FT* u) {
   if (DIM == 2) {
     p[0] = m.mu[0]; p[1] = m.mu[1]; p[2] = m.mu[0] * m.mv[1];
     p[3] = FT(0.5) * (m.mu[2] + m.mu[0] * (m.mv[2] + m.x2));
@@ -393,7 +399,7 @@ template <class FT, int DIM> __device__ __forceinline__ void psi_moms(const Mom<
 // line of s, for phi = psi (We, Wet) and u psi (F, Ft); also the one-sided
 // Euler time derivative Wt = -rho_s <psi (...)> over the full line.
 template <class FT, int DIM, bool VALUES>
-__device__ __forceinline__ void side_terms(const Prim<FT>& s, const Mom<FT>& h, const FT* n, const FT* t, FT K,
+FDK_HD void side_terms(const Prim<FT>& s, const Mom<FT>& h, const FT* n, const FT* t, FT K,
                                            FT iKd, FT tau, const TimeCoef<FT>& tc, bool both, FT* F, FT* Ft, FT* We,
                                            FT* Wet, FT* Wt) {
   constexpr int N = DIM + 2;
@@ -431,7 +437,7 @@ __device__ __forceinline__ void side_terms(const Prim<FT>& s, const Mom<FT>& h, 
 }
 
 template <class FT, int DIM, bool VALUES>
-__device__ __forceinline__ void gks_iface(const Consts& k, FT dt, GksIO<FT, DIM>& io) {
+FDK_HD void gks_iface(const Consts& k, FT dt, GksIO<FT, DIM>& io) {
   constexpr int N = DIM + 2;
   const FT K = FT(k.K), gam = FT(k.gamma), iKd = FT(k.inv_Kd);
   const bool both = VALUES || k.mu > 0;  // F and We are needed for the values or the Prandtl fix
@@ -529,7 +535,7 @@ __device__ __forceinline__ void gks_iface(const Consts& k, FT dt, GksIO<FT, DIM>
 // f^n = g [1 - tauN ((a.psi) u + (b.psi) v + A.psi)], f_t = (A.psi) g.
 // Outputs x-flux F, Ft and (2D) y-flux G, Gt.  VALUES = false: F, G skipped.
 template <class FT, int DIM, bool VALUES>
-__device__ __forceinline__ void gks_node(const Consts& k, const FT* W, const FT* Wx, const FT* Wy, FT* F, FT* Ft,
+FDK_HD void gks_node(const Consts& k, const FT* W, const FT* Wx, const FT* Wy, FT* F, FT* Ft,
                                          FT* G, FT* Gt) {
   constexpr int N = DIM + 2;
   const FT K = FT(k.K), iKd = FT(k.inv_Kd);
@@ -615,7 +621,7 @@ __device__ __forceinline__ void gks_node(const Consts& k, const FT* W, const FT*
 
 // ---------------------------------------------------------- compact flux
 // Eq. fd-conservative-flux and its (6-4) / (6-2) nonlinear forms.
-__device__ __forceinline__ double compact_flux(int variant, double Fm, double Fc, double Fp, double N0, double N1,
+FDK_HD double compact_flux(int variant, double Fm, double Fc, double Fp, double N0, double N1,
                                                double chi) {
   double Fb = ((Fm + 46.0 * Fc + Fp) - 9.0 * (N0 + N1)) * (1.0 / 30.0);
   if (variant == 2) return Fb;

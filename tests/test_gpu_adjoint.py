@@ -175,18 +175,34 @@ def test_vjp_central_differences_gpu(kw, eps, bar):
     assert abs(fd - an) <= bar * float(np.abs(lam * d).sum()), (fd, an)
 
 
-def _conservation_check(pb, S, dt):
+def _cut_scale(pb, S, dt, grid, c):
+    """Size of the adjoint contributions that cancel in a conserved sum: the
+    largest entry of J^T lam - lam for the indicator of half the domain (the
+    flux adjoints at the two cuts no longer cancel)."""
+    lam = np.zeros(S.shape)
+    lam[grid, c, :, : S.shape[-1] // 2] = 1.0
+    return float(np.abs(pb.step_vjp(dt, lam) - lam).max())
+
+
+def _conservation_check(pb, S, dt, cases=None):
     """Every grid's sums of rho, rho U, rho V, rho E are invariants of the
     step on a periodic grid (the compact fluxes telescope), at any state:
     the adjoint of the indicator of a W plane is that indicator.  The flux
-    terms cancel between each periodic interface and its halo image, so only
-    round-off of that cancellation remains (bar 1e-13 against entries of 1)."""
-    for grid in range(2):
-        for c in range(4):
-            lam = np.zeros(S.shape)
-            lam[grid, c] = 1.0
-            g = pb.step_vjp(dt, lam)
-            assert float(np.abs(g - lam).max()) <= 1e-13, (grid, c, float(np.abs(g - lam).max()))
+    adjoints cancel between each periodic interface and its halo image, and
+    the rest is round-off of summing about a hundred contributions per node
+    (atomic adds, any order) of size up to about ten times C, the net value
+    at a cut: bar 1024 eps max(1, C).  Smooth data give C ~ 0.1 and
+    deviations of a few eps; at the non-differentiable points of shear-layer
+    data C reaches a few hundred."""
+    worst = 0.0
+    for grid, c in cases or [(g, q) for g in range(2) for q in range(4)]:
+        lam = np.zeros(S.shape)
+        lam[grid, c] = 1.0
+        dev = float(np.abs(pb.step_vjp(dt, lam) - lam).max())
+        bar = 1024 * np.finfo(np.float64).eps * max(1.0, _cut_scale(pb, S, dt, grid, c))
+        worst = max(worst, dev / bar)
+        assert dev <= bar, (grid, c, dev, bar)
+    return worst
 
 
 def test_vjp_conservation_shear_layer():
@@ -198,6 +214,10 @@ def test_vjp_conservation_shear_layer():
     the conserved sums."""
     s, pr = _case("shear_ns_20")
     S = np.stack([pr.P, pr.D])
+    r = _conservation_check(_problem(s, S), S, 0.2 * pr.h / 3.0)
+    print(f"shear_ns_20: conserved-sum adjoints, worst deviation / bar = {r:.2e}")
+    s, pr = _case("smooth_ns_20")
+    S = np.stack([pr.P, pr.D])
     _conservation_check(_problem(s, S), S, 0.2 * pr.h / 3.0)
 
 
@@ -206,14 +226,10 @@ def test_vjp_conservation_full_size(n):
     """The same invariant on the 2048^2 Navier-Stokes shear layer."""
     pr = WL.shear_layer(n, seed=0)
     s = settings(dim=2, nx=n, ny=n, lx=pr.lx, mu=pr.params["mu"], prandtl=pr.params["prandtl"])
-    pb = _problem(s, np.stack([pr.P, pr.D]))
-    dt = 0.2 * pr.h / 3.0
-    lam = np.zeros((2, 12, n, n))
-    lam[1, 3] = 1.0
-    g = pb.step_vjp(dt, lam)
-    err = float(np.abs(g - lam).max())
-    print(f"2048^2 adjoint of the dual-grid energy sum: max deviation {err:.1e}")
-    assert err <= 1e-13
+    S = np.stack([pr.P, pr.D])
+    pb = _problem(s, S)
+    r = _conservation_check(pb, S, 0.2 * pr.h / 3.0, cases=[(1, 3)])
+    print(f"2048^2 adjoint of the dual-grid energy sum: deviation / bar = {r:.2e}")
 
 
 def test_vjp_rejects_unsupported():
