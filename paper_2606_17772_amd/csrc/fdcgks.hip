@@ -211,8 +211,12 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
 #undef XCH
 }
 
+// Waves per SIMD the interface sweep is compiled for (register budget).
+#ifndef FDCGKS_EDGE_WAVES
+#define FDCGKS_EDGE_WAVES 2
+#endif
 template <int STAGE, class FT>
-__global__ __launch_bounds__(256, 2) void k_edges2d(const double* __restrict__ S, double* __restrict__ E, Geo g,
+__global__ __launch_bounds__(256, FDCGKS_EDGE_WAVES) void k_edges2d(const double* __restrict__ S, double* __restrict__ E, Geo g,
                                                     Consts k, const Scal* __restrict__ sc) {
   if (sc->stop) return;  // grid-uniform
   edge_block<STAGE, FT>(S, E, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z);

@@ -689,8 +689,13 @@ FDK_HD void geno_b(const Consts& k, const GenoIn& g, double d1, double d2, doubl
   const double xH = tau * eL * inv, xL = tau * eH * inv;
   const double aH = 1.0 + ipow(xH, k.r), aL = 1.0 + ipow(xL, k.r);
   const double alpha = 2.0 * aH / (aH + aL);
-  const double th = tanh(k.C * alpha);
+  const double th = g_tanh(k.C * alpha);
   const double chi = th * k.inv_tanhC;
+  if (th == 1.0 && chi == 1.0) {  // as in the forward: v = PH, d = PHx, d chi / d alpha = 0
+    gb.PH += vb;
+    gb.PHx += db;
+    return;
+  }
   const double t1 = sqr(g.IS1 + k.eps_a), t2 = sqr(g.IS2 + k.eps_a), t3 = sqr(g.IS3 + k.eps_a);
   const double w1 = d1 * t2 * t3, w2 = d2 * t1 * t3, w3 = d3 * t1 * t2;
   const double is = 1.0 / (w1 + w2 + w3);

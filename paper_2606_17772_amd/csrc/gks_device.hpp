@@ -95,11 +95,13 @@ FDK_HD DD m_abs(DD a) { return a.v > 0 ? a : (a.v < 0 ? -a : DD(0.0, 0.0)); }
 FDK_HD double g_abs(double a) { return fabs(a); }
 FDK_HD double g_max(double a, double b) { return fmax(a, b); }
 FDK_HD double g_min(double a, double b) { return fmin(a, b); }
-FDK_HD double g_tanh(double a) { return tanh(a); }
+// tanh; beyond |a| = 19.5 it rounds to +-1 in FP64 (1 - tanh(a) < 2.3e-17,
+// under half an ulp of 1), so the library call is skipped there.
+FDK_HD double g_tanh(double a) { return a > 19.5 ? 1.0 : (a < -19.5 ? -1.0 : tanh(a)); }
 FDK_HD DD g_abs(DD a) { return m_abs(a); }
 FDK_HD DD g_max(DD a, DD b) { return b.v > a.v ? b : a; }
 FDK_HD DD g_min(DD a, DD b) { return b.v < a.v ? b : a; }
-FDK_HD DD g_tanh(DD a) { double t = tanh(a.v); return DD(t, (1.0 - t * t) * a.d); }
+FDK_HD DD g_tanh(DD a) { double t = g_tanh(a.v); return DD(t, (1.0 - t * t) * a.d); }
 FDK_HD double val(double a) { return a; }
 FDK_HD float val(float a) { return a; }
 FDK_HD double val(DD a) { return a.v; }
@@ -124,13 +126,22 @@ FDK_HD GenoOutT<R> geno(const Consts& k, R IS1, R IS2, R IS3, double d1, double 
   R xH = tau * eL * inv, xL = tau * eH * inv;
   R aH = 1.0 + ipow(xH, k.r), aL = 1.0 + ipow(xL, k.r);
   R alpha = 2.0 * aH / (aH + aL);
-  R chi = g_tanh(k.C * alpha) * k.inv_tanhC;
+  R th = g_tanh(k.C * alpha);
+  R chi = th * k.inv_tanhC;
+  GenoOutT<R> o;
+  // Smooth data: tanh saturates (its derivative is 0) and chi = 1 exactly, so
+  // the low-order blend has weight 0 in the value and in every derivative.
+  if (val(th) == 1.0 && val(chi) == 1.0) {
+    o.v = PH;
+    o.d = PHx;
+    o.chi = chi;
+    return o;
+  }
   R t1 = sqr(IS1 + k.eps_a), t2 = sqr(IS2 + k.eps_a), t3 = sqr(IS3 + k.eps_a);
   R w1 = d1 * t2 * t3, w2 = d2 * t1 * t3, w3 = d3 * t1 * t2;
   R is = 1.0 / (w1 + w2 + w3);
   R PL = (w1 * q1 + w2 * q2 + w3 * q3) * is;
   R PLx = (w1 * dq1 + w2 * dq2 + w3 * dq3) * is;
-  GenoOutT<R> o;
   o.v = chi * PH + (1.0 - chi) * PL;
   o.d = chi * PHx + (1.0 - chi) * PLx;
   o.chi = chi;
