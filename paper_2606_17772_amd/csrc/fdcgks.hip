@@ -152,10 +152,10 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
 template <int STAGE, class FT>
 __device__ __forceinline__ void edge_block(const double* __restrict__ S, double* __restrict__ E, const Geo& g,
                                            const Consts& k, double dt, int bx, int by, int fam) {
-  __shared__ double xch[8 * 256];
+  // LDS slots per thread: 0-3 tangential slope, 4-7 Wlt + Wrt, 8-11 Wl + Wr
+  __shared__ double xch[12 * 256];
   const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
   const int TX = blockDim.x, TY = blockDim.y;
-  // slot c of thread row r
 #define XCH(c, r) xch[((c) * TY + (r)) * TX + tx]
   const int i = bx * TX + tx + (fam == 0 ? -2 : -1);
   const int j = by * (TY >> 1) + (ty >> 1) + (fam == 0 ? -1 : -2);
@@ -168,6 +168,7 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
 #pragma unroll
     for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
   }
+  const double chi = fmin(rec[0].cl, rec[0].cr);  // path function of the density line
 #pragma unroll
   for (int c = 0; c < 4; ++c) XCH(c, ty) = 0.5 * (rec[c].dl + rec[c].dr);
   __syncthreads();
@@ -176,32 +177,35 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
   for (int c = 0; c < 4; ++c) tang[c] = XCH(c, ty ^ 1);
   double F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wl[4] = {0, 0, 0, 0}, Wr[4] = {0, 0, 0, 0};
   double Wlt[4] = {0, 0, 0, 0}, Wrt[4] = {0, 0, 0, 0};
+  double* e = E + ((long)fam * 50 + G * 25) * g.plane + at(g, j, i);
+  const long pl = g.plane;
   if (valid) {
     // the normal is y when FAM != G (rho U and rho V swap in the local frame)
     if (fam == G) solve_dir<false, STAGE, FT>(k, (FT)dt, rec, tang, F, Ft, Wl, Wr, Wlt, Wrt);
     else solve_dir<true, STAGE, FT>(k, (FT)dt, rec, tang, F, Ft, Wl, Wr, Wlt, Wrt);
+    // what needs no partner goes out at once
+    e[8 * pl] = chi;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      e[(4 + c) * pl] = Ft[c];
+      if (STAGE == 1) e[c * pl] = F[c];
+    }
   }
-  __syncthreads();
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    XCH(c, ty) = Wlt[c] + Wrt[c];
-    if (STAGE == 1) XCH(4 + c, ty) = Wl[c] + Wr[c];
+    XCH(4 + c, ty) = Wlt[c] + Wrt[c];
+    if (STAGE == 1) XCH(8 + c, ty) = Wl[c] + Wr[c];
   }
   __syncthreads();
   if (valid) {
-    // blend with the partner direction (Eq. W-model-2d) and store this normal's slot
-    double* e = E + ((long)fam * 50 + G * 25) * g.plane + at(g, j, i);
-    const long pl = g.plane;
-    e[8 * pl] = fmin(rec[0].cl, rec[0].cr);
+    // blend with the partner direction (Eq. W-model-2d)
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double st = XCH(c, ty ^ 1);
-      e[(4 + c) * pl] = Ft[c];
+      const double st = XCH(4 + c, ty ^ 1);
       e[(17 + c) * pl] = 0.5 * Wlt[c] + 0.25 * st;
       e[(21 + c) * pl] = 0.5 * Wrt[c] + 0.25 * st;
       if (STAGE == 1) {
-        const double sv = XCH(4 + c, ty ^ 1);
-        e[(0 + c) * pl] = F[c];
+        const double sv = XCH(8 + c, ty ^ 1);
         e[(9 + c) * pl] = 0.5 * Wl[c] + 0.25 * sv;
         e[(13 + c) * pl] = 0.5 * Wr[c] + 0.25 * sv;
       }
