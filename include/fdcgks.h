@@ -216,6 +216,15 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
  * member.  Same state layout and on_device rule as the single-problem calls. */
 typedef struct fdcgks_batch fdcgks_batch; /* opaque, owned by the library */
 
+/* How a batched stage is launched.  PERSISTENT: one cooperative launch per
+ * stage, sized to the co-resident grid, that walks the device work list in
+ * three phases separated by grid barriers (CFL partials and halo; interface
+ * and node sweeps; update).  PHASED (default): the same work list and device
+ * code as one launch per phase (halo, interfaces, nodes, update), so that
+ * every phase runs at its own occupancy.  Both give bitwise the same
+ * results. */
+enum { FDCGKS_BATCH_PERSISTENT = 0, FDCGKS_BATCH_PHASED = 1 };
+
 /* params[count]: every member 2D periodic; members may differ only in nx, ny,
  * x0, lx, y0, ly.  Allocates all device memory on the current device. */
 fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, void* hip_stream, fdcgks_batch** out);
@@ -231,6 +240,10 @@ fdcgks_status fdcgks_batch_step(fdcgks_batch* b, double cfl, int32_t nsteps, dou
                                 int32_t* steps_done);
 fdcgks_status fdcgks_batch_destroy(fdcgks_batch* b);
 const char* fdcgks_batch_last_error(const fdcgks_batch* b);
+
+/* Select FDCGKS_BATCH_PERSISTENT or FDCGKS_BATCH_PHASED for later
+ * fdcgks_batch_step calls (EINVAL otherwise). */
+fdcgks_status fdcgks_batch_set_mode(fdcgks_batch* b, int32_t mode);
 
 #ifdef __cplusplus
 }

@@ -321,6 +321,12 @@ class Batch:
         self._chk(self._L.fdcgks_batch_get_state(self._h, member, grid, *(C.c_void_p(a.ctypes.data) for a in out), 0))
         return np.concatenate(out, axis=0)
 
+    def set_mode(self, mode):
+        """'phased' (one launch per phase, default) or 'persistent' (one
+        cooperative launch per stage)."""
+        m = {"persistent": _lib.BATCH_PERSISTENT, "phased": _lib.BATCH_PHASED}[mode]
+        self._chk(self._L.fdcgks_batch_set_mode(self._h, m))
+
     def step(self, nsteps=1, cfl=0.5):
         """Returns (t[count], dt_last[count], steps_done)."""
         t = np.zeros(self.count)

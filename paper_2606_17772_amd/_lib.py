@@ -19,6 +19,7 @@ FLUX_6_4, FLUX_6_2, FLUX_LINEAR = 0, 1, 2
 FP64, FP32_FLUX = 0, 1
 GRAD_REEVAL, GRAD_CARRIED = 0, 1
 OPT_GRAPH, OPT_TILE_EDGE, OPT_TILE_NODE, OPT_TILE_UPDATE = 0, 1, 2, 3
+BATCH_PERSISTENT, BATCH_PHASED = 0, 1
 
 
 class Params(C.Structure):
@@ -67,6 +68,7 @@ SIGNATURES = {
     "fdcgks_batch_step": (C.c_int, [_vp, C.c_double, _i32, _dp, _dp, C.POINTER(_i32)]),
     "fdcgks_batch_destroy": (C.c_int, [_vp]),
     "fdcgks_batch_last_error": (C.c_char_p, [_vp]),
+    "fdcgks_batch_set_mode": (C.c_int, [_vp, _i32]),
 }
 
 _lib = None

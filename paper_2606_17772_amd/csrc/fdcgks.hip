@@ -759,6 +759,23 @@ __device__ __forceinline__ void halo_plane_block(double* __restrict__ P, const G
   __syncthreads();
 }
 
+// End of a batched step (one block): every member's time advances by its dt
+// and the step counts, unless a stage stopped it.
+// The stop flag as other workgroups of the same launch left it (coherent load).
+__device__ __forceinline__ int load_stop(const Scal* sc) {
+  return __hip_atomic_load(&sc->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void batch_step_end(const BArgs& a, const Consts& k) {
+  if (load_stop(a.sc)) return;
+  for (int q = threadIdx.y * blockDim.x + threadIdx.x; q < a.count; q += blockDim.x * blockDim.y) {
+    const double dt = member_dt(a, q, k);
+    a.t[q] += dt;
+    a.dt_last[q] = dt;
+  }
+  if (threadIdx.x == 0 && threadIdx.y == 0) a.sc->steps += 1;
+}
+
 template <int STAGE, class FT>
 __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
   namespace cg = cooperative_groups;
@@ -786,7 +803,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
   it += a.n_halo;
   grid.sync();
   // phase B: interfaces and nodes
-  const bool stopped = a.sc->stop != 0;
+  const bool stopped = load_stop(a.sc) != 0;
   if (!stopped) {
     for (int q = blockIdx.x; q < a.n_edge; q += nb) {
       const BItem& w = it[q];
@@ -816,15 +833,60 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
         update_block<2>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
     }
   }
-  if (STAGE == 2 && blockIdx.x == 0 && !stopped) {
-    for (int q = threadIdx.y * blockDim.x + threadIdx.x; q < a.count; q += blockDim.x * blockDim.y) {
-      const double dt = member_dt(a, q, k);
-      a.t[q] += dt;
-      a.dt_last[q] = dt;
-    }
-    if (threadIdx.x == 0 && threadIdx.y == 0) a.sc->steps += 1;
+  if (STAGE == 2) {
+    // the step counts only if no update of this stage stopped it
+    grid.sync();
+    if (blockIdx.x == 0) batch_step_end(a, k);
   }
 }
+
+// ---- the same stage as separate launches, one per phase (grid = work items)
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_bphase_halo(BArgs a, Consts k) {
+  if (a.sc->stop) return;
+  __shared__ double red[512];
+  const int q = blockIdx.x;
+  if (STAGE == 1 && q == 0)
+    for (int m = threadIdx.y * blockDim.x + threadIdx.x; m < a.count; m += blockDim.x * blockDim.y) {
+      unsigned long long* nx = a.slots + (long)(a.parity ^ 1) * 2 * a.count;
+      nx[m] = 0ull;
+      nx[a.count + m] = (unsigned long long)__double_as_longlong(1e300);
+    }
+  if (STAGE == 1 && q < a.n_cfl) {
+    cfl_block(a, k, a.items[q], red);
+    return;
+  }
+  const BItem& it = a.items[a.n_cfl + q - (STAGE == 1 ? a.n_cfl : 0)];
+  const BMember& M = a.mem[it.m];
+  double* S = STAGE == 1 ? M.S[a.cur] : M.Sstar;
+  halo_plane_block(S + (long)it.z * M.g.plane, M.g);
+}
+template <int STAGE, class FT>
+__global__ __launch_bounds__(256, FDCGKS_EDGE_WAVES) void k_bphase_edges(BArgs a, Consts k) {
+  if (a.sc->stop) return;
+  const BItem& w = a.items[a.n_cfl + a.n_halo + blockIdx.x];
+  const BMember& M = a.mem[w.m];
+  edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z);
+}
+template <int STAGE, class FT>
+__global__ __launch_bounds__(256) void k_bphase_nodes(BArgs a, Consts k) {
+  if (a.sc->stop) return;
+  const BItem& w = a.items[a.n_cfl + a.n_halo + a.n_edge + blockIdx.x];
+  const BMember& M = a.mem[w.m];
+  node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z);
+}
+template <int STAGE>
+__global__ __launch_bounds__(256) void k_bphase_update(BArgs a, Consts k) {
+  if (a.sc->stop) return;
+  const BItem& w = a.items[a.n_cfl + a.n_halo + a.n_edge + a.n_node + blockIdx.x];
+  const BMember& M = a.mem[w.m];
+  const double dt = member_dt(a, w.m, k);
+  if (STAGE == 1)
+    update_block<1>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
+  else
+    update_block<2>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
+}
+__global__ void k_bphase_end(BArgs a, Consts k) { batch_step_end(a, k); }
 
 }  // namespace
 
@@ -1679,6 +1741,7 @@ struct fdcgks_batch {
   Scal* sc_host = nullptr;
   int cur = 0, parity = 0;
   int blocks = 0;
+  int mode = FDCGKS_BATCH_PHASED;
   std::vector<char> have_state;
   std::string err;
 };
@@ -1920,14 +1983,39 @@ fdcgks_status fdcgks_batch_step(fdcgks_batch* b, double cfl, int32_t nsteps, dou
   a.dt_last = b->dt_last;
   a.sc = b->sc;
   const bool fp32 = b->prm0.flux_precision == FDCGKS_FP32_FLUX;
+  const dim3 blk(64, 4);
   for (int s = 0; s < nsteps; ++s) {
     a.cur = cur0 ^ (s & 1);
     a.parity = par0 ^ (s & 1);
-    void* args[2] = {&a, &b->k};
-    for (int stage = 1; stage <= 2; ++stage) {
-      void* fn = fp32 ? batch_kernel<float>(stage) : batch_kernel<double>(stage);
-      BHIPCHK(b, hipLaunchCooperativeKernel(fn, dim3(b->blocks), dim3(64, 4), args, 0, b->stream));
+    if (b->mode == FDCGKS_BATCH_PERSISTENT) {
+      void* args[2] = {&a, &b->k};
+      for (int stage = 1; stage <= 2; ++stage) {
+        void* fn = fp32 ? batch_kernel<float>(stage) : batch_kernel<double>(stage);
+        BHIPCHK(b, hipLaunchCooperativeKernel(fn, dim3(b->blocks), blk, args, 0, b->stream));
+      }
+      continue;
     }
+    hipLaunchKernelGGL(k_bphase_halo<1>, dim3(a.n_cfl + a.n_halo), blk, 0, b->stream, a, b->k);
+    if (fp32) {
+      hipLaunchKernelGGL((k_bphase_edges<1, float>), dim3(a.n_edge), blk, 0, b->stream, a, b->k);
+      hipLaunchKernelGGL((k_bphase_nodes<1, float>), dim3(a.n_node), blk, 0, b->stream, a, b->k);
+    } else {
+      hipLaunchKernelGGL((k_bphase_edges<1, double>), dim3(a.n_edge), blk, 0, b->stream, a, b->k);
+      hipLaunchKernelGGL((k_bphase_nodes<1, double>), dim3(a.n_node), blk, 0, b->stream, a, b->k);
+    }
+    hipLaunchKernelGGL(k_bphase_update<1>, dim3(a.n_upd), blk, 0, b->stream, a, b->k);
+    hipLaunchKernelGGL(k_bphase_halo<2>, dim3(a.n_halo), blk, 0, b->stream, a, b->k);
+    if (fp32) {
+      hipLaunchKernelGGL((k_bphase_edges<2, float>), dim3(a.n_edge), blk, 0, b->stream, a, b->k);
+      hipLaunchKernelGGL((k_bphase_nodes<2, float>), dim3(a.n_node), blk, 0, b->stream, a, b->k);
+    } else {
+      hipLaunchKernelGGL((k_bphase_edges<2, double>), dim3(a.n_edge), blk, 0, b->stream, a, b->k);
+      hipLaunchKernelGGL((k_bphase_nodes<2, double>), dim3(a.n_node), blk, 0, b->stream, a, b->k);
+    }
+    hipLaunchKernelGGL(k_bphase_update<2>, dim3(a.n_upd), blk, 0, b->stream, a, b->k);
+    hipLaunchKernelGGL(k_bphase_end, dim3(1), blk, 0, b->stream, a, b->k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, FDCGKS_EHIP, "batched launch failed: %s", hipGetErrorString(e));
   }
   BHIPCHK(b, hipMemcpyAsync(b->sc_host, b->sc, sizeof(Scal), hipMemcpyDeviceToHost, b->stream));
   if (t_out) BHIPCHK(b, hipMemcpyAsync(t_out, b->t, sizeof(double) * b->count, hipMemcpyDeviceToHost, b->stream));
@@ -1963,5 +2051,13 @@ fdcgks_status fdcgks_batch_destroy(fdcgks_batch* b) {
 }
 
 const char* fdcgks_batch_last_error(const fdcgks_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+
+fdcgks_status fdcgks_batch_set_mode(fdcgks_batch* b, int32_t mode) {
+  if (!b) return bfail(nullptr, FDCGKS_EINVAL, "batch is NULL");
+  if (mode != FDCGKS_BATCH_PERSISTENT && mode != FDCGKS_BATCH_PHASED)
+    return bfail(b, FDCGKS_EINVAL, "unknown batch mode %d", mode);
+  b->mode = mode;
+  return FDCGKS_OK;
+}
 
 }  // extern "C"

@@ -1,5 +1,6 @@
-"""Batched 2D solves (one cooperative persistent launch per stage over many
-uneven grids) against the single-problem HIP path and the oracle (GPU)."""
+"""Batched 2D solves over many uneven grids, in both launch modes (one launch
+per phase; one cooperative persistent launch per stage), against the
+single-problem HIP path and the oracle (GPU)."""
 import numpy as np
 import pytest
 
@@ -20,14 +21,25 @@ def _settings(pr):
     return settings(dim=2, nx=pr.nx, ny=pr.ny, lx=pr.lx)
 
 
-def test_batch_matches_single_problem_path_bitwise():
+MODES = ["phased", "persistent"]
+
+
+def _batch(probs, mode):
+    from paper_2606_17772_amd import Batch
+    B = Batch([gpu_params(_settings(p)) for p in probs])
+    B.set_mode(mode)
+    return B
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_matches_single_problem_path_bitwise(mode):
     """Every member of a batch of uneven grids (including ragged tile edges)
     is bitwise identical to the same problem run alone (same device
     arithmetic, per-member CFL time step)."""
-    from paper_2606_17772_amd import Batch, Problem
+    from paper_2606_17772_amd import Problem
     sizes = [16, 37, 64, 23, 90, 8]
     probs = _members(sizes)
-    B = Batch([gpu_params(_settings(p)) for p in probs])
+    B = _batch(probs, mode)
     for m, p in enumerate(probs):
         B.set_state_stacked(m, 0, p.P)
         B.set_state_stacked(m, 1, p.D)
@@ -43,12 +55,12 @@ def test_batch_matches_single_problem_path_bitwise():
             assert np.array_equal(B.get_state_stacked(m, g), pb.get_state_stacked(g)), (m, g)
 
 
-def test_batch_against_oracle():
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_against_oracle(mode):
     from oracle import oracle as O
-    from paper_2606_17772_amd import Batch
     sizes = [20, 33, 12]
     probs = _members(sizes, seed=7)
-    B = Batch([gpu_params(_settings(p)) for p in probs])
+    B = _batch(probs, mode)
     for m, p in enumerate(probs):
         B.set_state_stacked(m, 0, p.P)
         B.set_state_stacked(m, 1, p.D)
@@ -65,12 +77,13 @@ def test_batch_against_oracle():
             assert err <= max(TOL, 4 * sens), (m, where, err, sens)
 
 
-def test_batch_nonphysical_member_stops_and_rolls_back():
-    from paper_2606_17772_amd import Batch, FdcgksError
+@pytest.mark.parametrize("mode", MODES)
+def test_batch_nonphysical_member_stops_and_rolls_back(mode):
+    from paper_2606_17772_amd import FdcgksError
     probs = _members([16, 20])
     P = probs[1].P.copy()
     P[3, 5, 5] = -1.0  # negative energy -> p < 0
-    B = Batch([gpu_params(_settings(p)) for p in probs])
+    B = _batch(probs, mode)
     B.set_state_stacked(0, 0, probs[0].P)
     B.set_state_stacked(0, 1, probs[0].D)
     B.set_state_stacked(1, 0, P)
@@ -80,3 +93,32 @@ def test_batch_nonphysical_member_stops_and_rolls_back():
     assert ei.value.status == -4 and "member 1" in str(ei.value)
     assert np.array_equal(B.get_state_stacked(0, 0), probs[0].P)
     assert np.array_equal(B.get_state_stacked(1, 0), P)
+
+
+@pytest.mark.parametrize("mode", MODES + ["single"])
+def test_failure_in_stage_two_rolls_back(mode):
+    """Four-quadrant data (seed 1, 16^2) at CFL 1.2: stage 1 stays physical
+    (oracle: min p 0.35) and stage 2 does not (oracle: min p -0.27).  The
+    failing step is not counted, the state is the step's input, and a later
+    step at a stable CFL proceeds from it."""
+    from paper_2606_17772_amd import FdcgksError, Problem
+    pr = WL.riemann2d(16, seed=1)
+    if mode == "single":
+        pb = Problem(gpu_params(_settings(pr)))
+        pb.set_state_stacked(0, pr.P)
+        pb.set_state_stacked(1, pr.D)
+        with pytest.raises(FdcgksError) as ei:
+            pb.step(nsteps=3, cfl=1.2)
+        got = [pb.get_state_stacked(g) for g in (0, 1)]
+        t, n = pb.step(nsteps=1, cfl=0.4)
+    else:
+        B = _batch([pr], mode)
+        B.set_state_stacked(0, 0, pr.P)
+        B.set_state_stacked(0, 1, pr.D)
+        with pytest.raises(FdcgksError) as ei:
+            B.step(nsteps=3, cfl=1.2)
+        got = [B.get_state_stacked(0, g) for g in (0, 1)]
+        _, _, n = B.step(nsteps=1, cfl=0.4)
+    assert ei.value.status == -4 and "step 1 stage 2" in str(ei.value), str(ei.value)
+    assert np.array_equal(got[0], pr.P) and np.array_equal(got[1], pr.D)
+    assert n == 1
