@@ -154,6 +154,94 @@ def batch_comparison(steps):
     return out
 
 
+ADJ_STEPS, ADJ_EVERY, ADJ_CFL = 50, 7, 0.25
+
+
+def adjoint_batch_gradient(count=64):
+    """Gradient workload of the batched configuration: 64 members (sides
+    seeded in [64, 512]; vortex and four-quadrant Riemann data), each
+    advanced 50 steps at a time step frozen from its initial state (CFL 0.25;
+    a member whose frozen step goes non-physical is skipped and counted);
+    J = 1/2 sum over members and primary nodes of (rho(T) - rho_target)^2 h^2,
+    the target being the same run from the member's data drawn with another
+    seed; the control is an additive density perturbation on the primary
+    nodes (gradient = adjoint of the initial primary density).  Rollouts keep
+    every 7th state and recompute the rest.  Timed against the plain forward
+    steps of the same members, plus a central-difference check of the
+    gradient of one member along a random direction."""
+    import torch
+
+    import workloads as WL
+    from paper_2606_17772_amd import FdcgksError, Problem, make_params
+    from paper_2606_17772_amd.adjoint import rollout
+    dev = torch.device("cuda:0")
+    skipped = []
+    sizes = WL.batch_sizes(count, 64, 512, seed=0)
+    gen = lambda b, n, sd: WL.vortex(n, seed=sd) if b % 2 == 0 else WL.riemann2d(n, seed=sd)  # noqa: E731
+    t_fwd = t_grad = 0.0
+    J_total, gnorm2, members = 0.0, [0.0, 0.0], 0
+    check = None
+    for b, n in enumerate(sizes):
+        pr, tg = gen(b, n, b), gen(b, n, 5000 + b)
+        pb = Problem(make_params(dim=2, nx=n, ny=n, lx=pr.lx, ly=pr.ly))
+        S0 = torch.from_numpy(np.stack([pr.P, pr.D])).to(dev)
+        pb.set_state_all(S0)
+        dt = pb.compute_dt(ADJ_CFL)
+        try:
+            for S in (np.stack([tg.P, tg.D]), np.stack([pr.P, pr.D])):
+                pb.set_state_all(torch.from_numpy(S).to(dev))
+                pb.step(nsteps=ADJ_STEPS, dt=dt)
+        except FdcgksError:
+            skipped.append(b)
+            del pb
+            continue
+        pb.set_state_all(torch.from_numpy(np.stack([tg.P, tg.D])).to(dev))
+        pb.step(nsteps=ADJ_STEPS, dt=dt)
+        rho_t = pb.get_state_all(device=dev)[0, 0].clone()
+        h2 = pr.h * pr.h
+        # plain forward
+        pb.set_state_all(S0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.step(nsteps=ADJ_STEPS, dt=dt)
+        torch.cuda.synchronize()
+        t_fwd += time.perf_counter() - t0
+        # gradient: checkpointed rollout + reverse sweep
+        X = S0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = rollout(pb, X, dt, ADJ_STEPS, checkpoint_every=ADJ_EVERY)
+        J = 0.5 * ((out[0, 0] - rho_t) ** 2).sum() * h2
+        J.backward()
+        grad = X.grad[0, 0]
+        torch.cuda.synchronize()
+        t_grad += time.perf_counter() - t0
+        J_total += float(J.detach())
+        gnorm2[b % 2] += float((grad * grad).sum())
+        members += 1
+        if b == 0:  # central differences along a random density direction
+            v = torch.randn(grad.shape, dtype=torch.float64, device=dev,
+                            generator=torch.Generator(device=dev).manual_seed(1))
+            eps = 1e-6 * float(S0[0, 0].abs().max()) / float(v.abs().max())
+
+            def Jof(sign):
+                S = S0.clone()
+                S[0, 0] += sign * eps * v
+                pb.set_state_all(S)
+                pb.step(nsteps=ADJ_STEPS, dt=dt)
+                return 0.5 * float(((pb.get_state_all(device=dev)[0, 0] - rho_t) ** 2).sum()) * h2
+            fd = (Jof(1.0) - Jof(-1.0)) / (2 * eps)
+            an = float((grad * v).sum())
+            check = {"member": 0, "side": n, "directional_derivative_adjoint": an, "central_difference": fd,
+                     "rel_diff": abs(an - fd) / abs(fd)}
+        del pb, X, out, J
+    return {"workload": f"{members} members, sides in [64, 512], {ADJ_STEPS} steps at frozen CFL-{ADJ_CFL} dt, "
+                        f"checkpoint every {ADJ_EVERY} steps", "skipped_nonphysical_members": skipped,
+            "forward_s": round(t_fwd, 3), "gradient_s": round(t_grad, 3), "gradient_over_forward": round(t_grad / t_fwd, 2),
+            "J": J_total, "grad_norm_vortex_members": gnorm2[0] ** 0.5, "grad_norm_riemann_members": gnorm2[1] ** 0.5,
+            "fd_check": check}
+
+
 def graph_comparison(n=64, steps=400):
     """Launch overhead: a small problem (n^2 isentropic vortex) stepped with
     the captured-step graphs (16 steps per graph) and with separate kernel
@@ -316,6 +404,9 @@ def main():
         del pb
         torch.cuda.empty_cache()
         out["batched"] = batch_comparison(args.batch_steps)
+    if not args.no_adjoint and not args.no_batch:
+        torch.cuda.empty_cache()
+        out["batched_adjoint_gradient"] = adjoint_batch_gradient()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out), flush=True)
