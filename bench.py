@@ -68,6 +68,7 @@ def parse():
                     help="launch shapes kernel=XxY,... (default: the autotuner's pick at 2048^2)")
     ap.add_argument("--autotune", action="store_true", help="run fdcgks_autotune instead of --tiles")
     ap.add_argument("--no-graph", action="store_true", help="skip the small-problem graph-replay comparison")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux variant comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -152,6 +153,39 @@ def batch_comparison(steps):
                 "speedup_phased": rates["phased"] / loop, "speedup_persistent": rates["persistent"] / loop,
                 "bitwise_equal_sampled_members": bool(same)})
     return out
+
+
+def fp32_flux_comparison(pr, n, tiles, steps=10):
+    """The FP32-flux variant (gas-kinetic solvers in FP32, reconstruction,
+    assembly and update in FP64) on the same workload: time per step and the
+    largest relative difference of the values W from the FP64 path after
+    the same number of steps (per plane, relative to the plane's largest
+    value)."""
+    import torch
+
+    from paper_2606_17772_amd import Problem, make_params
+    dev = torch.device("cuda:0")
+    S0 = torch.from_numpy(np.stack([pr.P, pr.D])).to(dev)
+    res = {}
+    for fp32 in (False, True):
+        pb = Problem(make_params(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, mu=MU, prandtl=PR, fp32_flux=fp32))
+        for name, (x, y) in tiles.items():
+            pb.set_tile(name, x, y)
+        pb.set_state_all(S0)
+        dt = pb.compute_dt(CFL)
+        pb.step(nsteps=2, dt=dt)
+        pb.set_state_all(S0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        pb.step(nsteps=steps, dt=dt)
+        torch.cuda.synchronize()
+        res[fp32] = ((time.perf_counter() - t0) / steps * 1e3, pb.get_state_all(device=dev))
+        del pb
+    a, b = res[False][1][:, :4], res[True][1][:, :4]
+    err = float(((a - b).abs().amax(dim=(2, 3)) / a.abs().amax(dim=(2, 3))).max())
+    return {"workload": f"{n}x{n} shear layer, {steps} steps at the FP64 path's CFL dt",
+            "fp64_ms_per_step": round(res[False][0], 3), "fp32_flux_ms_per_step": round(res[True][0], 3),
+            "speedup": round(res[False][0] / res[True][0], 3), "max_rel_diff_values_vs_fp64": err}
 
 
 ADJ_STEPS, ADJ_EVERY, ADJ_CFL = 50, 7, 0.25
@@ -398,6 +432,11 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_comparison(pb, n)
+    if not args.no_fp32:
+        del pb
+        torch.cuda.empty_cache()
+        out["fp32_flux"] = fp32_flux_comparison(pr, n, tiles)
+        pb = None
     if not args.no_graph:
         out["graph_replay"] = graph_comparison()
     if not args.no_batch:

@@ -114,6 +114,36 @@ def test_t_end_clip(oracle):
     assert relerr(pb.get_state_stacked(1), oD, fl)[0] <= TOL
 
 
+def _bench_tiles(pb):
+    """The launch shapes the benchmark times."""
+    import bench
+    for item in bench.DEFAULT_TILES.split(","):
+        name, xy = item.split("=")
+        pb.set_tile(name, *(int(v) for v in xy.split("x")))
+
+
+def test_vortex_512_steps(oracle):
+    """2D Euler isentropic vortex at its benchmark size, 512^2 + dual: three
+    CFL-0.5 steps compared on every node (values and averaged gradients)
+    against the oracle, bar max(1e-12, 4 x the oracle's one-ulp
+    sensitivity over the same steps)."""
+    n = 512
+    pr = WL.vortex(n, seed=0)
+    s = settings(dim=2, nx=n, ny=n, lx=10.0)
+    par = oracle_par(oracle, s)
+    pb = _problem(s, pr.P, pr.D)
+    _bench_tiles(pb)
+    t, k = pb.step(nsteps=3, cfl=0.5)
+    run = lambda P, D: oracle.step2d(par, P, D, 3, cfl=0.5)[:2]  # noqa: E731
+    oP, oD, ot, ok = oracle.step2d(par, pr.P, pr.D, 3, cfl=0.5)
+    assert k == ok == 3 and abs(t - ot) <= 1e-14 * ot
+    fl = floors_state(ref_scales([pr.P, pr.D], s["gamma"], s["lx"]))
+    sens = ulp_sensitivity(run, pr.P, pr.D, fl, trials=1)
+    err = max(relerr(pb.get_state_stacked(0), oP, fl)[0], relerr(pb.get_state_stacked(1), oD, fl)[0])
+    print(f"vortex 512^2, 3 steps: gpu-oracle {err:.2e}, oracle 1-ulp sensitivity {sens:.2e}")
+    assert err <= max(TOL, 4 * sens), (err, sens)
+
+
 def test_full_size_sampled(oracle):
     """One full step on the 2048^2 shear-layer workload in the launch
     configuration the benchmark times, checked on sampled nodes.
@@ -130,6 +160,7 @@ def test_full_size_sampled(oracle):
     s = settings(dim=2, nx=n, ny=n, lx=1.0, mu=1e-4, prandtl=0.72)
     par = oracle_par(oracle, s)
     pb = _problem(s, pr.P, pr.D)
+    _bench_tiles(pb)
     dt = pb.compute_dt(0.5)
     rng = np.random.default_rng(0)
     ns = 48
