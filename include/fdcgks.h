@@ -176,9 +176,20 @@ fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* 
  * 256}, x*y a multiple of 64 and at most 256, y even for the interface
  * sweep (its two normals per point are paired thread rows).  Default 64 x 4.
  * The shape changes only the launch, never the arithmetic: results are
- * bitwise identical for every valid shape.  EINVAL for an unknown option or
- * an invalid value. */
-enum { FDCGKS_OPT_GRAPH = 0, FDCGKS_OPT_TILE_EDGE = 1, FDCGKS_OPT_TILE_NODE = 2, FDCGKS_OPT_TILE_UPDATE = 3 };
+ * bitwise identical for every valid shape.
+ * FDCGKS_OPT_FUSE_NODES (default 0): 1 makes 2D steps evaluate the nodal fluxes
+ * inside the update kernel (per 64 x 4 tile plus a one-node halo, in LDS)
+ * instead of a separate node sweep through a node buffer; the node and
+ * update shapes then do not apply (bitwise the same results).  The
+ * diagnostics and the step adjoint always use the separate sweep.
+ * EINVAL for an unknown option or an invalid value. */
+enum {
+  FDCGKS_OPT_GRAPH = 0,
+  FDCGKS_OPT_TILE_EDGE = 1,
+  FDCGKS_OPT_TILE_NODE = 2,
+  FDCGKS_OPT_TILE_UPDATE = 3,
+  FDCGKS_OPT_FUSE_NODES = 4
+};
 fdcgks_status fdcgks_set_option(fdcgks_problem* pb, int32_t option, int64_t value);
 fdcgks_status fdcgks_get_option(const fdcgks_problem* pb, int32_t option, int64_t* value);
 

@@ -229,6 +229,17 @@ class Problem:
     def use_graph(self, on):
         self.graph_steps = max(1, self.graph_steps) if on else 0
 
+    @property
+    def fuse_nodes(self):
+        """Node sweep evaluated inside the update kernel (2D steps)."""
+        v = C.c_int64()
+        self._chk(self._L.fdcgks_get_option(self._h, _lib.OPT_FUSE_NODES, C.byref(v)))
+        return bool(v.value)
+
+    @fuse_nodes.setter
+    def fuse_nodes(self, on):
+        self._chk(self._L.fdcgks_set_option(self._h, _lib.OPT_FUSE_NODES, 1 if on else 0))
+
     def tiles(self):
         """Block shapes {"edge": (x, y), "node": ..., "update": ...}."""
         out = {}

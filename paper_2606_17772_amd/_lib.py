@@ -18,7 +18,7 @@ BC_PERIODIC, BC_ZERO_GRADIENT = 0, 1
 FLUX_6_4, FLUX_6_2, FLUX_LINEAR = 0, 1, 2
 FP64, FP32_FLUX = 0, 1
 GRAD_REEVAL, GRAD_CARRIED = 0, 1
-OPT_GRAPH, OPT_TILE_EDGE, OPT_TILE_NODE, OPT_TILE_UPDATE = 0, 1, 2, 3
+OPT_GRAPH, OPT_TILE_EDGE, OPT_TILE_NODE, OPT_TILE_UPDATE, OPT_FUSE_NODES = 0, 1, 2, 3, 4
 BATCH_PERSISTENT, BATCH_PHASED = 0, 1
 
 

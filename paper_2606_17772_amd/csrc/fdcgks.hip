@@ -273,18 +273,16 @@ __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, d
 // holding its a-fluxes, and the offset r of its right (upper) interface:
 // primary x -> X, slot 0, r = 0; primary y -> Y, slot 0, r = 0;
 // dual x -> Y, slot 1, r = 1;    dual y -> X, slot 1, r = 1.
-// Block (bx, by) of blockDim.x x blockDim.y interior nodes.  A non-physical
-// result (rho <= 0, p <= 0, NaN) sets the stop flag and records where
-// (`member` names the batch member, 0 for a single problem).
-template <int STAGE>
-__device__ __forceinline__ void update_block(const double* __restrict__ S, const double* __restrict__ E,
-                                             const double* __restrict__ Nb, const double* __restrict__ Ain,
-                                             double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
-                                             const Consts& k, double dt, int bx, int by, int grid, Scal* sc,
-                                             int member) {
-  const int i = bx * blockDim.x + threadIdx.x;
-  const int j = by * blockDim.y + threadIdx.y;
-  if (i >= g.nx || j >= g.ny) return;
+// The nodal fluxes come through an accessor nf(a, q, off): component q of
+// (F, F_t) along x (a = 0) or (G, G_t) along y (a = 1), q = 0..3 values and
+// 4..7 time derivatives, at the node `off` = -1, 0, +1 along the axis.  A
+// non-physical result (rho <= 0, p <= 0, NaN) sets the stop flag and records
+// where (`member` names the batch member, 0 for a single problem).
+template <int STAGE, class NF>
+__device__ __forceinline__ void update_node(const double* __restrict__ S, const double* __restrict__ E,
+                                            const NF& nf, const double* __restrict__ Ain, double* __restrict__ Out,
+                                            double* __restrict__ Aout, const Geo& g, const Consts& k, double dt,
+                                            int i, int j, int grid, Scal* sc, int member) {
   const long pl = g.plane, o = at(g, j, i);
   const int r = grid;
   double L[4] = {0, 0, 0, 0}, Lt[4] = {0, 0, 0, 0}, Gr[2][4], Grt[2][4];
@@ -293,22 +291,23 @@ __device__ __forceinline__ void update_block(const double* __restrict__ S, const
     const int fam = (grid == 0) ? a : 1 - a;
     const long st = a == 0 ? 1 : g.pitch;
     const double* e = E + (long)fam * 50 * pl + (long)grid * 25 * pl + o;
-    const double* n = Nb + (long)grid * 16 * pl + (a == 0 ? 0 : 8) * pl + o;
     const double chiR = e[8 * pl + r * st], chiL = e[8 * pl + (r - 1) * st];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double* f = e + (0 + c) * pl;
       const double* ft = e + (4 + c) * pl;
-      const double* nf = n + c * pl;
-      const double* nft = n + (4 + c) * pl;
       if (STAGE == 1) {
-        double FR = fdk::compact_flux(k.variant, f[(r - 1) * st], f[r * st], f[(r + 1) * st], nf[0], nf[st], chiR);
-        double FL = fdk::compact_flux(k.variant, f[(r - 2) * st], f[(r - 1) * st], f[r * st], nf[-st], nf[0], chiL);
+        const double n0 = nf(a, c, 0);
+        double FR = fdk::compact_flux(k.variant, f[(r - 1) * st], f[r * st], f[(r + 1) * st], n0, nf(a, c, 1), chiR);
+        double FL = fdk::compact_flux(k.variant, f[(r - 2) * st], f[(r - 1) * st], f[r * st], nf(a, c, -1), n0, chiL);
         L[c] = L[c] - (FR - FL) * g.invh;
         Gr[a][c] = (e[(9 + c) * pl + r * st] - e[(13 + c) * pl + (r - 1) * st]) * g.invh;
       }
-      double FRt = fdk::compact_flux(k.variant, ft[(r - 1) * st], ft[r * st], ft[(r + 1) * st], nft[0], nft[st], chiR);
-      double FLt = fdk::compact_flux(k.variant, ft[(r - 2) * st], ft[(r - 1) * st], ft[r * st], nft[-st], nft[0], chiL);
+      const double nt0 = nf(a, 4 + c, 0);
+      double FRt = fdk::compact_flux(k.variant, ft[(r - 1) * st], ft[r * st], ft[(r + 1) * st], nt0, nf(a, 4 + c, 1),
+                                     chiR);
+      double FLt = fdk::compact_flux(k.variant, ft[(r - 2) * st], ft[(r - 1) * st], ft[r * st], nf(a, 4 + c, -1), nt0,
+                                     chiL);
       Lt[c] = Lt[c] - (FRt - FLt) * g.invh;
       Grt[a][c] = (e[(17 + c) * pl + r * st] - e[(21 + c) * pl + (r - 1) * st]) * g.invh;
     }
@@ -351,6 +350,101 @@ __device__ __forceinline__ void update_block(const double* __restrict__ S, const
       sc->fail_stage = STAGE;
     }
   }
+}
+
+// Nodal fluxes from the node buffer (planes grid*16 + a*8 + q).
+struct NodeFluxGlobal {
+  const double* n;  // Nb + grid*16*plane + o
+  long pl, pitch;
+  __device__ __forceinline__ double operator()(int a, int q, int off) const {
+    return n[(long)(a * 8 + q) * pl + off * (a == 0 ? 1 : pitch)];
+  }
+};
+
+// Block (bx, by) of blockDim.x x blockDim.y interior nodes.
+template <int STAGE>
+__device__ __forceinline__ void update_block(const double* __restrict__ S, const double* __restrict__ E,
+                                             const double* __restrict__ Nb, const double* __restrict__ Ain,
+                                             double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
+                                             const Consts& k, double dt, int bx, int by, int grid, Scal* sc,
+                                             int member) {
+  const int i = bx * blockDim.x + threadIdx.x;
+  const int j = by * blockDim.y + threadIdx.y;
+  if (i >= g.nx || j >= g.ny) return;
+  const NodeFluxGlobal nf{Nb + (long)grid * 16 * g.plane + at(g, j, i), g.plane, g.pitch};
+  update_node<STAGE>(S, E, nf, Ain, Out, Aout, g, k, dt, i, j, grid, sc, member);
+}
+
+// ------------------------------------------- node sweep fused into update
+// One block (64 x 4 threads) owns a 64 x 4 tile of grid blockIdx.z: it
+// evaluates the nodal fluxes of the tile and of a one-node halo along each
+// axis (F, F_t on rows j0..j0+3, columns i0-1..i0+64; G, G_t on columns
+// i0..i0+63, rows j0-1..j0+4) into LDS, then assembles and updates its nodes
+// from there.  The node buffer is neither written nor read.
+constexpr int FT_X = 66, FT_Y = 6;
+struct NodeFluxShared {
+  const double* xs;  // [8][4][66]
+  const double* ys;  // [8][6][64]
+  int tx, ty;
+  __device__ __forceinline__ double operator()(int a, int q, int off) const {
+    return a == 0 ? xs[(q * 4 + ty) * FT_X + tx + 1 + off] : ys[(q * FT_Y + ty + 1 + off) * 64 + tx];
+  }
+};
+
+template <int STAGE, class FT>
+__global__ __launch_bounds__(256) void k_nodeupd2d(const double* __restrict__ S, const double* __restrict__ E,
+                                                   const double* __restrict__ Ain, double* __restrict__ Out,
+                                                   double* __restrict__ Aout, Geo g, Consts k, Scal* __restrict__ sc) {
+  if (sc->stop) return;  // grid-uniform
+  __shared__ double xs[8 * 4 * FT_X];
+  __shared__ double ys[8 * FT_Y * 64];
+  const int grid = blockIdx.z, i0 = blockIdx.x * 64, j0 = blockIdx.y * 4;
+  const int tid = threadIdx.y * 64 + threadIdx.x;
+  const long pl = g.plane;
+  const double* B = S + (long)grid * 12 * pl;
+  // 4 x 66 positions on the tile rows (F and, inside, G), then 2 x 64 on the rows above and below (G)
+  for (int q = tid; q < 4 * FT_X + 2 * 64; q += 256) {
+    int r, c;
+    if (q < 4 * FT_X) {
+      r = q / FT_X;
+      c = q % FT_X - 1;
+    } else {
+      r = (q - 4 * FT_X) < 64 ? -1 : 4;
+      c = (q - 4 * FT_X) % 64;
+    }
+    const int i = i0 + c, j = j0 + r;
+    if (i > g.nx || j > g.ny) continue;  // beyond the fluxes any interior node of the tile reads
+    const long o = at(g, j, i);
+    FT W[4], Wx[4], Wy[4];
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      const double* w = B + cc * pl + o;
+      const double* x = B + (4 + cc) * pl + o;
+      const double* y = B + (8 + cc) * pl + o;
+      W[cc] = (FT)w[0];
+      Wx[cc] = (FT)fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
+      Wy[cc] = (FT)fdk::recon_node(k, w[-g.pitch], w[0], w[g.pitch], y[-g.pitch], y[0], y[g.pitch], g.h, g.invh);
+    }
+    FT F[4], Ft[4], Gv[4], Gt[4];
+    fdk::gks_node<FT, 2, STAGE == 1>(k, W, Wx, Wy, F, Ft, Gv, Gt);
+    const bool xrow = r >= 0 && r < 4, ycol = c >= 0 && c < 64;
+#pragma unroll
+    for (int cc = 0; cc < 4; ++cc) {
+      if (xrow) {
+        xs[((4 + cc) * 4 + r) * FT_X + c + 1] = (double)Ft[cc];
+        if (STAGE == 1) xs[(cc * 4 + r) * FT_X + c + 1] = (double)F[cc];
+      }
+      if (ycol) {
+        ys[((4 + cc) * FT_Y + r + 1) * 64 + c] = (double)Gt[cc];
+        if (STAGE == 1) ys[(cc * FT_Y + r + 1) * 64 + c] = (double)Gv[cc];
+      }
+    }
+  }
+  __syncthreads();
+  const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
+  if (i >= g.nx || j >= g.ny) return;
+  const NodeFluxShared nf{xs, ys, (int)threadIdx.x, (int)threadIdx.y};
+  update_node<STAGE>(S, E, nf, Ain, Out, Aout, g, k, sc->dt, i, j, grid, sc, 0);
 }
 
 template <int STAGE>
@@ -932,6 +1026,7 @@ struct fdcgks_problem {
   dim3 tile[3] = {dim3(64, 4), dim3(64, 4), dim3(64, 4)};
   // captured whole steps (one graph per ping-pong parity), replayed by fdcgks_step
   int graph_steps = 16;  // steps per captured graph; 0: separate launches
+  bool fuse_nodes = false;  // node sweep inside the update kernel
   hipStream_t cap = nullptr;
   hipGraphExec_t gx[2] = {nullptr, nullptr};
   bool g_valid = false;
@@ -1037,13 +1132,27 @@ void launch_update(fdcgks_problem* pb, const double* Sin, const double* Ain, dou
                      pb->sc);
 }
 
+// One stage.  fused: the node sweep runs inside the update kernel and the
+// node buffer is not written (callers that read it pass false).
 template <int STAGE>
-fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout) {
+fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout,
+                      bool fused) {
   const Geo& g = pb->g;
   fdcgks_status st = halo2d(pb, const_cast<double*>(Sin));
   if (st) return st;
   launch_edges<STAGE>(pb, Sin, pb->tile[0]);
   mark(pb, STAGE == 1 ? TK_EDGE1 : TK_EDGE2);
+  if (fused) {
+    dim3 gu(ceil_div(g.nx, 64), ceil_div(g.ny, 4), 2);
+    if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
+      hipLaunchKernelGGL((k_nodeupd2d<STAGE, float>), gu, dim3(64, 4), 0, pb->stream, Sin, pb->E, Ain, Out, Aout, g,
+                         pb->k, pb->sc);
+    else
+      hipLaunchKernelGGL((k_nodeupd2d<STAGE, double>), gu, dim3(64, 4), 0, pb->stream, Sin, pb->E, Ain, Out, Aout, g,
+                         pb->k, pb->sc);
+    mark(pb, STAGE == 1 ? TK_UPD1 : TK_UPD2);
+    return launch_check(pb, "stage");
+  }
   launch_nodes<STAGE>(pb, Sin, pb->tile[1]);
   mark(pb, STAGE == 1 ? TK_NODE1 : TK_NODE2);
   launch_update<STAGE>(pb, Sin, Ain, Out, Aout, pb->tile[2]);
@@ -1110,8 +1219,8 @@ fdcgks_status capture_steps(fdcgks_problem* pb, double dt, double cfl) {
     for (int q = 0, cc = c; q < pb->graph_steps && !st; ++q, cc = 1 - cc) {
       pb->cur = cc;
       st = begin_step(pb, dt, cfl);
-      if (!st) st = stage2d<1>(pb, pb->S[cc], nullptr, pb->Sstar, pb->Acc);
-      if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cc], nullptr);
+      if (!st) st = stage2d<1>(pb, pb->S[cc], nullptr, pb->Sstar, pb->Acc, pb->fuse_nodes);
+      if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cc], nullptr, pb->fuse_nodes);
       if (!st) {
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, pb->stream, pb->sc);
         st = launch_check(pb, "step_end");
@@ -1471,8 +1580,8 @@ fdcgks_status fdcgks_step(fdcgks_problem* pb, double dt, double cfl, int32_t nst
     pb->cur = cur;
     st = begin_step(pb, dt, cfl);
     mark(pb, TK_STEP);
-    if (!st) st = stage2d<1>(pb, pb->S[cur], nullptr, pb->Sstar, pb->Acc);
-    if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cur], nullptr);
+    if (!st) st = stage2d<1>(pb, pb->S[cur], nullptr, pb->Sstar, pb->Acc, pb->fuse_nodes);
+    if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cur], nullptr, pb->fuse_nodes);
     if (st) break;
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, pb->stream, pb->sc);
     mark(pb, TK_STEP);
@@ -1533,8 +1642,8 @@ fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, d
   double* scratch = pb->S[1 - pb->cur];  // the next-state buffer is free between steps
   if (!st) {
     if (pb->prm.dim == 1) st = launch_run1d(pb, stage, 0, dt, 0.0);
-    else if (stage == 1) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc);
-    else st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr);
+    else if (stage == 1) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, pb->fuse_nodes);
+    else st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr, pb->fuse_nodes);
   }
   if (st) return st;
   const Geo& g = pb->g;
@@ -1561,7 +1670,7 @@ fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* 
   std::memset(pb->sc_host, 0, sizeof(Scal));
   pb->sc_host->dt = dt;
   fdcgks_status st = write_scal(pb);
-  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc);
+  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, false);
   if (st) return st;
   const Geo& g = pb->g;
   size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
@@ -1612,10 +1721,10 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   double* scratch = pb->S[1 - pb->cur];
   pb->E = pb->E1;
   pb->Nb = pb->Nb1;
-  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc);
+  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, false);
   pb->E = E0;
   pb->Nb = N0;
-  if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr);
+  if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr, false);
   if (!st) st = read_scal(pb);
   if (st) return st;
   if (pb->sc_host->stop & 1)
@@ -1641,6 +1750,11 @@ fdcgks_status fdcgks_set_option(fdcgks_problem* pb, int32_t option, int64_t valu
       pb->graph_steps = (int)value;
       graph_invalidate(pb);
       return FDCGKS_OK;
+    case FDCGKS_OPT_FUSE_NODES:
+      if (value != 0 && value != 1) return fail(pb, FDCGKS_EINVAL, "node-fusion option must be 0 or 1");
+      pb->fuse_nodes = value != 0;
+      graph_invalidate(pb);
+      return FDCGKS_OK;
     case FDCGKS_OPT_TILE_EDGE:
     case FDCGKS_OPT_TILE_NODE:
     case FDCGKS_OPT_TILE_UPDATE: {
@@ -1664,6 +1778,10 @@ fdcgks_status fdcgks_get_option(const fdcgks_problem* cpb, int32_t option, int64
     *value = pb->graph_steps;
     return FDCGKS_OK;
   }
+  if (option == FDCGKS_OPT_FUSE_NODES) {
+    *value = pb->fuse_nodes ? 1 : 0;
+    return FDCGKS_OK;
+  }
   if (option >= FDCGKS_OPT_TILE_EDGE && option <= FDCGKS_OPT_TILE_UPDATE) {
     const dim3 t = pb->tile[option - FDCGKS_OPT_TILE_EDGE];
     *value = (int64_t)t.x | ((int64_t)t.y << 16);
@@ -1684,7 +1802,7 @@ fdcgks_status fdcgks_autotune(fdcgks_problem* pb, int32_t reps) {
   std::memset(pb->sc_host, 0, sizeof(Scal));
   pb->sc_host->dt = dt;
   st = write_scal(pb);
-  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc);
+  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, false);
   if (st) return st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(pb, hipEventCreate(&e0));

@@ -66,6 +66,23 @@ def test_every_launch_shape_gives_identical_results():
             assert np.array_equal(pb.get_state_all(), want), (kernel, x, y)
 
 
+@pytest.mark.parametrize("case", [0, 1])
+def test_fused_node_sweep_is_bitwise_equal(case):
+    """Nodal fluxes evaluated inside the update kernel (tile plus halo in
+    LDS) against the separate node sweep through the node buffer, several
+    steps, with the graphs on."""
+    s, pr = _cases()[case]
+    a = _problem(s, pr)
+    b = _problem(s, pr)
+    b.fuse_nodes = True
+    assert b.fuse_nodes and not a.fuse_nodes
+    for rep in range(3):
+        ta, na = a.step(nsteps=2, cfl=0.5)
+        tb, nb = b.step(nsteps=2, cfl=0.5)
+        assert na == nb == 2 and ta == tb
+        assert np.array_equal(a.get_state_all(), b.get_state_all()), rep
+
+
 def test_invalid_launch_shapes_rejected():
     from paper_2606_17772_amd import FdcgksError
     s, pr = _cases()[0]
