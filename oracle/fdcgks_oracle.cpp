@@ -81,6 +81,7 @@ template <class T> inline T sq(T a) { return a * a; }
 // file's own and is mirrored only by oracle/oracle.py.
 struct Par {
   int32_t dim, nx, ny, bc, dual_1d, variant, r, grad_carried;
+  int32_t recon_char, pad_;  // 1: reconstruct characteristic variables (Sec. 3)
   double x0, lx, y0, ly;
   double gamma, mu, prandtl;
   double C, eps, eps_a, d_central, d_side;
@@ -181,6 +182,123 @@ T recon_node(const Par& p, const T Q[3], const T X[3], double h) {
   T v, der, chi;
   geno_blend(p, IS, 2, d, q0, dq, Q[1], PHx, v, der, chi);
   return der;
+}
+
+// --------------------------------------- characteristic variables, Sec. 3
+// Q = L W with L the left eigenvectors of the Euler flux Jacobian along the
+// line, in the line's local frame (normal momentum = component 1), at a
+// reference state.  R (columns: fields u-c, u [, shear], u+c) is the textbook
+// right-eigenvector matrix; L is obtained by inverting R (Gauss-Jordan with
+// partial pivoting), not from a closed form.
+template <class T> void char_basis(int dim, double gamma, const T* W, T R[4][4], T L[4][4]) {
+  const int n = dim + 2;
+  T rho = W[0], u = W[1] / rho, v = dim == 2 ? W[2] / rho : T(0.0), E = W[n - 1];
+  T q2 = u * u + v * v;
+  T pr = (gamma - 1.0) * (E - 0.5 * rho * q2);
+  T c = sqrt(gamma * pr / rho), H = (E + pr) / rho;
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) R[a][b] = L[a][b] = T(0.0);
+  if (dim == 2) {
+    T cols[4][4] = {{T(1.0), u - c, v, H - u * c},
+                    {T(1.0), u, v, 0.5 * q2},
+                    {T(0.0), T(0.0), T(1.0), v},
+                    {T(1.0), u + c, v, H + u * c}};
+    for (int k = 0; k < 4; ++k)
+      for (int a = 0; a < 4; ++a) R[a][k] = cols[k][a];
+  } else {
+    T cols[3][3] = {{T(1.0), u - c, H - u * c}, {T(1.0), u, 0.5 * u * u}, {T(1.0), u + c, H + u * c}};
+    for (int k = 0; k < 3; ++k)
+      for (int a = 0; a < 3; ++a) R[a][k] = cols[k][a];
+  }
+  // L = R^-1
+  T A[4][8];
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < 2 * n; ++b) A[a][b] = b < n ? R[a][b] : T(b - n == a ? 1.0 : 0.0);
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r2 = col + 1; r2 < n; ++r2)
+      if (std::fabs(val(A[r2][col])) > std::fabs(val(A[piv][col]))) piv = r2;
+    for (int b = 0; b < 2 * n; ++b) std::swap(A[col][b], A[piv][b]);
+    T inv = 1.0 / A[col][col];
+    for (int b = 0; b < 2 * n; ++b) A[col][b] = A[col][b] * inv;
+    for (int r2 = 0; r2 < n; ++r2) {
+      if (r2 == col) continue;
+      T f = A[r2][col];
+      for (int b = 0; b < 2 * n; ++b) A[r2][b] = A[r2][b] - f * A[col][b];
+    }
+  }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b) L[a][b] = A[a][n + b];
+}
+
+// Interface reconstruction of all n components of one line (local frame):
+// component-wise (conservative) or on characteristic variables with the
+// eigenvectors at the mean of the two interface nodes; chi from rho, or the
+// smallest of the two acoustic fields' l and r path functions (ties: the
+// first of chi^l(u-c), chi^r(u-c), chi^l(u+c), chi^r(u+c)).
+template <class T>
+void recon_line(const Par& p, int dim, const T Q[4][4], const T X[4][4], double h, T vl[4], T dl[4], T vr[4],
+                T dr[4], T& chi) {
+  const int n = dim + 2;
+  if (!p.recon_char) {
+    T cl[4], cr[4];
+    for (int c = 0; c < n; ++c) recon_interface(p, Q[c], X[c], h, vl[c], dl[c], cl[c], vr[c], dr[c], cr[c]);
+    chi = std::min(val(cl[0]), val(cr[0])) == val(cl[0]) ? cl[0] : cr[0];
+    return;
+  }
+  T Wref[4], R[4][4], L[4][4];
+  for (int c = 0; c < n; ++c) Wref[c] = 0.5 * (Q[c][1] + Q[c][2]);
+  char_basis(dim, p.gamma, Wref, R, L);
+  T cvl[4], cdl[4], ccl[4], cvr[4], cdr[4], ccr[4];
+  for (int k = 0; k < n; ++k) {
+    T q[4], x[4];
+    for (int m = 0; m < 4; ++m) {
+      q[m] = T(0.0);
+      x[m] = T(0.0);
+      for (int c = 0; c < n; ++c) { q[m] = q[m] + L[k][c] * Q[c][m]; x[m] = x[m] + L[k][c] * X[c][m]; }
+    }
+    recon_interface(p, q, x, h, cvl[k], cdl[k], ccl[k], cvr[k], cdr[k], ccr[k]);
+  }
+  for (int c = 0; c < n; ++c) {
+    vl[c] = dl[c] = vr[c] = dr[c] = T(0.0);
+    for (int k = 0; k < n; ++k) {
+      vl[c] = vl[c] + R[c][k] * cvl[k];
+      dl[c] = dl[c] + R[c][k] * cdl[k];
+      vr[c] = vr[c] + R[c][k] * cvr[k];
+      dr[c] = dr[c] + R[c][k] * cdr[k];
+    }
+  }
+  const T cand[4] = {ccl[0], ccr[0], ccl[n - 1], ccr[n - 1]};
+  chi = cand[0];
+  for (int a = 1; a < 4; ++a)
+    if (val(cand[a]) < val(chi)) chi = cand[a];
+}
+
+// Node derivative of all n components along one line (local frame): on
+// characteristic variables the eigenvectors are taken at the node's state.
+template <class T> void recon_node_line(const Par& p, int dim, const T Q[4][3], const T X[4][3], double h, T d[4]) {
+  const int n = dim + 2;
+  if (!p.recon_char) {
+    for (int c = 0; c < n; ++c) d[c] = recon_node(p, Q[c], X[c], h);
+    return;
+  }
+  T Wref[4], R[4][4], L[4][4];
+  for (int c = 0; c < n; ++c) Wref[c] = Q[c][1];
+  char_basis(dim, p.gamma, Wref, R, L);
+  T cd[4];
+  for (int k = 0; k < n; ++k) {
+    T q[3], x[3];
+    for (int m = 0; m < 3; ++m) {
+      q[m] = T(0.0);
+      x[m] = T(0.0);
+      for (int c = 0; c < n; ++c) { q[m] = q[m] + L[k][c] * Q[c][m]; x[m] = x[m] + L[k][c] * X[c][m]; }
+    }
+    cd[k] = recon_node(p, q, x, h);
+  }
+  for (int c = 0; c < n; ++c) {
+    d[c] = T(0.0);
+    for (int k = 0; k < n; ++k) d[c] = d[c] + R[c][k] * cd[k];
+  }
 }
 
 // ----------------------------------------------- Maxwellian moments, App. A
@@ -527,18 +645,25 @@ template <class T> struct EdgeRes {
 template <class T> EdgeRes<T> edge2d(const Par& p, const Grid2<T>& G, int I, int J, double h, double dt) {
   EdgeRes<T> E;
   // line reconstructions: along x (nodes I-3, I-1, I+1, I+3) and along y
-  T Wl[2][4], Wr[2][4], Dl[2][4], Dr[2][4], cl[2][4], cr[2][4];
-  for (int ax = 0; ax < 2; ++ax)
-    for (int c = 0; c < 4; ++c) {
-      T Q[4], X[4];
+  // (in the line's local frame: the momentum along the line is component 1)
+  T Wl[2][4], Wr[2][4], Dl[2][4], Dr[2][4], chi_line[2];
+  for (int ax = 0; ax < 2; ++ax) {
+    int perm[4] = {0, 1, 2, 3};
+    if (ax == 1) { perm[1] = 2; perm[2] = 1; }
+    T Q[4][4], X[4][4], vl[4], dl[4], vr[4], dr[4];
+    for (int c = 0; c < 4; ++c)
       for (int m = 0; m < 4; ++m) {
         int o = 2 * m - 3;
         int Ii = ax == 0 ? I + o : I, Jj = ax == 0 ? J : J + o;
-        Q[m] = G.W(Ii, Jj, c);
-        X[m] = ax == 0 ? G.Wx(Ii, Jj, c) : G.Wy(Ii, Jj, c);
+        Q[c][m] = G.W(Ii, Jj, perm[c]);
+        X[c][m] = ax == 0 ? G.Wx(Ii, Jj, perm[c]) : G.Wy(Ii, Jj, perm[c]);
       }
-      recon_interface(p, Q, X, h, Wl[ax][c], Dl[ax][c], cl[ax][c], Wr[ax][c], Dr[ax][c], cr[ax][c]);
+    recon_line(p, 2, Q, X, h, vl, dl, vr, dr, chi_line[ax]);
+    for (int c = 0; c < 4; ++c) {
+      Wl[ax][perm[c]] = vl[c]; Dl[ax][perm[c]] = dl[c];
+      Wr[ax][perm[c]] = vr[c]; Dr[ax][perm[c]] = dr[c];
     }
+  }
   GksOut<T> o[2];
   for (int ax = 0; ax < 2; ++ax) {
     int bx = 1 - ax;
@@ -562,7 +687,7 @@ template <class T> EdgeRes<T> edge2d(const Par& p, const Grid2<T>& G, int I, int
       o[ax].Wl[q] = loc.Wl[c]; o[ax].Wr[q] = loc.Wr[c];
       o[ax].Wlt[q] = loc.Wlt[c]; o[ax].Wrt[q] = loc.Wrt[c];
     }
-    E.chi[ax] = std::min(val(cl[ax][0]), val(cr[ax][0])) == val(cl[ax][0]) ? cl[ax][0] : cr[ax][0];
+    E.chi[ax] = chi_line[ax];
   }
   for (int ax = 0; ax < 2; ++ax) {
     int bx = 1 - ax;
@@ -584,14 +709,20 @@ template <class T> EdgeRes<T> edge2d(const Par& p, const Grid2<T>& G, int I, int
 template <class T> struct NodeRes { T F[4], Ft[4], G[4], Gt[4]; };
 template <class T> NodeRes<T> node2d(const Par& p, const Grid2<T>& G, int I, int J, double h) {
   T W[4], Wx[4], Wy[4];
-  for (int c = 0; c < 4; ++c) {
-    T Q[3], X[3];
-    for (int m = 0; m < 3; ++m) { Q[m] = G.W(I + 2 * m - 2, J, c); X[m] = G.Wx(I + 2 * m - 2, J, c); }
-    Wx[c] = recon_node(p, Q, X, h);
-    for (int m = 0; m < 3; ++m) { Q[m] = G.W(I, J + 2 * m - 2, c); X[m] = G.Wy(I, J + 2 * m - 2, c); }
-    Wy[c] = recon_node(p, Q, X, h);
-    W[c] = G.W(I, J, c);
+  for (int ax = 0; ax < 2; ++ax) {
+    int perm[4] = {0, 1, 2, 3};
+    if (ax == 1) { perm[1] = 2; perm[2] = 1; }
+    T Q[4][3], X[4][3], d[4];
+    for (int c = 0; c < 4; ++c)
+      for (int m = 0; m < 3; ++m) {
+        int Ii = ax == 0 ? I + 2 * m - 2 : I, Jj = ax == 0 ? J : J + 2 * m - 2;
+        Q[c][m] = G.W(Ii, Jj, perm[c]);
+        X[c][m] = ax == 0 ? G.Wx(Ii, Jj, perm[c]) : G.Wy(Ii, Jj, perm[c]);
+      }
+    recon_node_line(p, 2, Q, X, h, d);
+    for (int c = 0; c < 4; ++c) (ax == 0 ? Wx : Wy)[perm[c]] = d[c];
   }
+  for (int c = 0; c < 4; ++c) W[c] = G.W(I, J, c);
   NodeRes<T> R;
   gks_node(p, 2, W, Wx, Wy, R.F, R.Ft, R.G, R.Gt);
   return R;
@@ -771,11 +902,12 @@ template <class T> struct Node1 { T F[3], Ft[3]; };
 
 // Interface between nodes j and j+1 (j from -2 to N).
 template <class T> Edge1<T> edge1d(const Par& p, const Line1<T>& L, int j, double h, double dt) {
-  T Wl[3], Wr[3], Dl[3], Dr[3], cl[3], cr[3];
-  for (int c = 0; c < 3; ++c) {
-    T Q[4], X[4];
-    for (int m = 0; m < 4; ++m) { Q[m] = L.W[c][j - 1 + m + 3]; X[m] = L.X[c][j - 1 + m + 3]; }
-    recon_interface(p, Q, X, h, Wl[c], Dl[c], cl[c], Wr[c], Dr[c], cr[c]);
+  T Wl[4], Wr[4], Dl[4], Dr[4], chi;
+  {
+    T Q[4][4], X[4][4];
+    for (int c = 0; c < 3; ++c)
+      for (int m = 0; m < 4; ++m) { Q[c][m] = L.W[c][j - 1 + m + 3]; X[c][m] = L.X[c][j - 1 + m + 3]; }
+    recon_line(p, 1, Q, X, h, Wl, Dl, Wr, Dr, chi);
   }
   GksOut<T> o;
   gks_interface(p, 1, Wl, Wr, Dl, Dr, (const T*)nullptr, dt, o);
@@ -784,17 +916,18 @@ template <class T> Edge1<T> edge1d(const Par& p, const Line1<T>& L, int j, doubl
     E.F[c] = o.F[c]; E.Ft[c] = o.Ft[c];
     E.Wl[c] = o.Wl[c]; E.Wr[c] = o.Wr[c]; E.Wlt[c] = o.Wlt[c]; E.Wrt[c] = o.Wrt[c];
   }
-  E.chi = std::min(val(cl[0]), val(cr[0])) == val(cl[0]) ? cl[0] : cr[0];
+  E.chi = chi;
   return E;
 }
 template <class T> Node1<T> node1d(const Par& p, const Line1<T>& L, int j, double h) {
-  T W[3], Wx[3];
-  for (int c = 0; c < 3; ++c) {
-    T Q[3], X[3];
-    for (int m = 0; m < 3; ++m) { Q[m] = L.W[c][j - 1 + m + 3]; X[m] = L.X[c][j - 1 + m + 3]; }
-    Wx[c] = recon_node(p, Q, X, h);
-    W[c] = L.W[c][j + 3];
+  T W[3], Wx[4];
+  {
+    T Q[4][3], X[4][3];
+    for (int c = 0; c < 3; ++c)
+      for (int m = 0; m < 3; ++m) { Q[c][m] = L.W[c][j - 1 + m + 3]; X[c][m] = L.X[c][j - 1 + m + 3]; }
+    recon_node_line(p, 1, Q, X, h, Wx);
   }
+  for (int c = 0; c < 3; ++c) W[c] = L.W[c][j + 3];
   Node1<T> R;
   gks_node(p, 1, W, Wx, (const T*)nullptr, R.F, R.Ft, (T*)nullptr, (T*)nullptr);
   return R;
@@ -853,6 +986,13 @@ int orc_abi_version() { return 1; }
 // out: vl, dl, cl, vr, dr, cr
 void orc_recon_interface(const Par* p, const double* Q, const double* X, double h, double* out) {
   recon_interface(*p, Q, X, h, out[0], out[1], out[2], out[3], out[4], out[5]);
+}
+// R and L (row-major 4x4, dim+2 used) at the local-frame state W.
+void orc_char_basis(int dim, double gamma, const double* W, double* R, double* L) {
+  double r[4][4], l[4][4];
+  char_basis(dim, gamma, W, r, l);
+  for (int a = 0; a < 4; ++a)
+    for (int b = 0; b < 4; ++b) { R[4 * a + b] = r[a][b]; L[4 * a + b] = l[a][b]; }
 }
 double orc_recon_node(const Par* p, const double* Q, const double* X, double h) {
   return recon_node(*p, Q, X, h);

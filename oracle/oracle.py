@@ -37,6 +37,7 @@ class Par(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32),
         ("dual_1d", C.c_int32), ("variant", C.c_int32), ("r", C.c_int32), ("grad_carried", C.c_int32),
+        ("recon_char", C.c_int32), ("pad_", C.c_int32),
         ("x0", C.c_double), ("lx", C.c_double), ("y0", C.c_double), ("ly", C.c_double),
         ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
         ("C", C.c_double), ("eps", C.c_double), ("eps_a", C.c_double),
@@ -52,7 +53,7 @@ BCS = {"periodic": 0, "zero_gradient": 1}
 def make_par(*, dim=2, nx=16, ny=16, x0=0.0, lx=1.0, y0=0.0, ly=None, bc="periodic", dual_1d=0,
              gamma=1.4, mu=0.0, prandtl=1.0, variant="6-4", geno_C=20.0, geno_r=3,
              geno_eps=1e-15, geno_eps_a=1e-6, d_central=8.0, d_side=1.0, tau_c1=0.0,
-             tau_c2=1.0, grad_carried=0, **_ignored) -> Par:
+             tau_c2=1.0, grad_carried=0, recon_vars="conservative", **_ignored) -> Par:
     """Problem description with the oracle's own field layout.  Defaults are the
     readings of the paper (C = 20, r = 3, eps = 1e-15, eps_a = 1e-6, d = 8/1,
     tau = 0 * dt + dt |dp|/(p_l+p_r) for Euler: D11 as amended)."""
@@ -68,6 +69,8 @@ def make_par(*, dim=2, nx=16, ny=16, x0=0.0, lx=1.0, y0=0.0, ly=None, bc="period
     p.C, p.eps, p.eps_a, p.d_central, p.d_side = geno_C, geno_eps, geno_eps_a, d_central, d_side
     p.tau_c1, p.tau_c2 = tau_c1, tau_c2
     p.grad_carried = int(grad_carried)
+    p.recon_char = {"conservative": 0, "characteristic": 1}[recon_vars] if isinstance(recon_vars, str) \
+        else int(recon_vars)
     return p
 
 
@@ -87,6 +90,7 @@ def lib():
             "orc_abi_version": (i, []),
             "orc_recon_interface": (None, [P, _dp, _dp, d, _dp]),
             "orc_recon_node": (d, [P, _dp, _dp, d]),
+            "orc_char_basis": (None, [C.c_int, d, _dp, _dp, _dp]),
             "orc_geno_blend": (None, [P, _dp, i, _dp, _dp, _dp, d, d, _dp]),
             "orc_maxwell": (None, [d, d, d, d, i, i, _dp]),
             "orc_slope": (None, [_dp, _dp, i, d, _dp]),
@@ -138,6 +142,15 @@ def recon_interface(par, Q, X, h):
 
 def recon_node(par, Q, X, h):
     return lib().orc_recon_node(C.byref(par), _p(_arr(Q, 3)), _p(_arr(X, 3)), h)
+
+
+def char_basis(dim, gamma, W):
+    """(R, L) (n x n, n = dim + 2) at the local-frame conservative state W."""
+    R = np.zeros(16)
+    L = np.zeros(16)
+    lib().orc_char_basis(dim, gamma, _p(_arr(W, dim + 2)), _p(R), _p(L))
+    n = dim + 2
+    return R.reshape(4, 4)[:n, :n], L.reshape(4, 4)[:n, :n]
 
 
 def geno_blend(par, IS, ref, d, q, dq, PH, PHx):
