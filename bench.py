@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="run fdcgks_autotune instead of --tiles")
     ap.add_argument("--no-graph", action="store_true", help="skip the small-problem graph-replay comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux variant comparison")
+    ap.add_argument("--no-char", action="store_true",
+                    help="skip the characteristic-variable reconstruction comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -155,37 +157,68 @@ def batch_comparison(steps):
     return out
 
 
-def fp32_flux_comparison(pr, n, tiles, steps=10):
-    """The FP32-flux variant (gas-kinetic solvers in FP32, reconstruction,
-    assembly and update in FP64) on the same workload: time per step and the
-    largest relative difference of the values W from the FP64 path after
-    the same number of steps (per plane, relative to the plane's largest
-    value)."""
+def _variant_runs(pr, n, tiles, variants, steps):
+    """Time `steps` steps of the workload for each keyword set in `variants`
+    (all at the first variant's CFL dt, from the same resident state):
+    [(ms per step, final state, per-kernel ms per step)]."""
     import torch
 
     from paper_2606_17772_amd import Problem, make_params
     dev = torch.device("cuda:0")
     S0 = torch.from_numpy(np.stack([pr.P, pr.D])).to(dev)
-    res = {}
-    for fp32 in (False, True):
-        pb = Problem(make_params(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, mu=MU, prandtl=PR, fp32_flux=fp32))
+    out, dt = [], None
+    for kw in variants:
+        pb = Problem(make_params(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, mu=MU, prandtl=PR, **kw))
         for name, (x, y) in tiles.items():
             pb.set_tile(name, x, y)
         pb.set_state_all(S0)
-        dt = pb.compute_dt(CFL)
+        if dt is None:
+            dt = pb.compute_dt(CFL)
         pb.step(nsteps=2, dt=dt)
         pb.set_state_all(S0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pb.step(nsteps=steps, dt=dt)
         torch.cuda.synchronize()
-        res[fp32] = ((time.perf_counter() - t0) / steps * 1e3, pb.get_state_all(device=dev))
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        S = pb.get_state_all(device=dev)
+        pb.set_state_all(S0)
+        _, _, kms = pb.step_timed(nsteps=2, dt=dt)
+        out.append((ms, S, {k: round(v / 2, 4) for k, v in kms.items()}))
         del pb
-    a, b = res[False][1][:, :4], res[True][1][:, :4]
-    err = float(((a - b).abs().amax(dim=(2, 3)) / a.abs().amax(dim=(2, 3))).max())
+    return out
+
+
+def _max_rel_values(a, b):
+    a, b = a[:, :4], b[:, :4]
+    return float(((a - b).abs().amax(dim=(2, 3)) / a.abs().amax(dim=(2, 3))).max())
+
+
+def fp32_flux_comparison(pr, n, tiles, steps=10):
+    """The FP32-flux variant (gas-kinetic solvers in FP32, reconstruction,
+    assembly and update in FP64) on the same workload: time per step and the
+    largest relative difference of the values W from the FP64 path after
+    the same number of steps (per plane, relative to the plane's largest
+    value)."""
+    (m64, S64, _), (m32, S32, _) = _variant_runs(pr, n, tiles, [{}, {"fp32_flux": True}], steps)
     return {"workload": f"{n}x{n} shear layer, {steps} steps at the FP64 path's CFL dt",
-            "fp64_ms_per_step": round(res[False][0], 3), "fp32_flux_ms_per_step": round(res[True][0], 3),
-            "speedup": round(res[False][0] / res[True][0], 3), "max_rel_diff_values_vs_fp64": err}
+            "fp64_ms_per_step": round(m64, 3), "fp32_flux_ms_per_step": round(m32, 3),
+            "speedup": round(m64 / m32, 3), "max_rel_diff_values_vs_fp64": _max_rel_values(S64, S32)}
+
+
+def characteristic_comparison(pr, n, tiles, steps=10):
+    """Reconstruction in characteristic variables (Sec. 3) on the same
+    workload: node-update rate, time per step and per kernel, and the largest
+    relative difference of the values W from the conservative-variable path
+    after the same steps (a scheme difference, not round-off)."""
+    runs = _variant_runs(pr, n, tiles, [{}, {"recon_vars": "characteristic"}], steps)
+    (mc, Sc, kc), (mh, Sh, kh) = runs
+    nodes = 2 * n * n
+    return {"workload": f"{n}x{n} shear layer, {steps} steps at the conservative path's CFL dt",
+            "node_updates_per_s": nodes * 2 / (mh * 1e-3), "ms_per_step": round(mh, 3),
+            "conservative_ms_per_step": round(mc, 3), "slowdown_vs_conservative": round(mh / mc, 3),
+            "kernel_ms_per_step": kh, "conservative_kernel_ms_per_step": kc,
+            "max_rel_diff_values_vs_conservative": _max_rel_values(Sc, Sh)}
 
 
 ADJ_STEPS, ADJ_EVERY, ADJ_CFL = 50, 7, 0.25
@@ -432,11 +465,14 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_comparison(pb, n)
-    if not args.no_fp32:
+    if not args.no_fp32 or not args.no_char:
         del pb
         torch.cuda.empty_cache()
-        out["fp32_flux"] = fp32_flux_comparison(pr, n, tiles)
         pb = None
+    if not args.no_fp32:
+        out["fp32_flux"] = fp32_flux_comparison(pr, n, tiles)
+    if not args.no_char:
+        out["characteristic"] = characteristic_comparison(pr, n, tiles)
     if not args.no_graph:
         out["graph_replay"] = graph_comparison()
     if not args.no_batch:

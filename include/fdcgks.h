@@ -62,6 +62,15 @@ enum { FDCGKS_FP64 = 0, FDCGKS_FP32_FLUX = 1 };
 /* Base of the averaged-gradient update (Eq. eq-interface-update): the gradient
  * re-evaluated from the stage-1 interface values (default) or the stored one. */
 enum { FDCGKS_GRAD_REEVAL = 0, FDCGKS_GRAD_CARRIED = 1 };
+/* Variables the GENO reconstruction works on (Sec. 3): each conservative
+ * component on its own (the path function from the density line), or the
+ * characteristic variables of the Euler flux Jacobian along each line, with
+ * the eigenvectors at the mean of the two interface-adjacent states (at the
+ * node's own state for node derivatives) and the path function the smallest
+ * of the acoustic fields' left and right values.  Characteristic mode is
+ * available to fdcgks_problem steps (1D and 2D, either flux precision); the
+ * step adjoint and batches reject it with FDCGKS_EINVAL. */
+enum { FDCGKS_RECON_CONSERVATIVE = 0, FDCGKS_RECON_CHARACTERISTIC = 1 };
 
 typedef struct fdcgks_params {
   int32_t dim;            /* 1 or 2 */
@@ -72,7 +81,7 @@ typedef struct fdcgks_params {
   int32_t flux_precision; /* FDCGKS_FP64 | FDCGKS_FP32_FLUX */
   int32_t grad_update;    /* FDCGKS_GRAD_* */
   int32_t geno_r;         /* exponent r of the GENO smoothness ratio, 1..8 (default 3) */
-  int32_t reserved;       /* must be 0 */
+  int32_t recon_vars;     /* FDCGKS_RECON_* (default conservative) */
   double x0, lx, y0, ly;  /* domain origin and lengths; 2D needs lx/nx == ly/ny */
   double gamma;           /* ratio of specific heats, > 1 and < 5/3 (2D) or < 3 (1D) */
   double mu;              /* dynamic viscosity; 0 = Euler */

@@ -18,12 +18,13 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BC_PERIODIC, BC_ZERO_GRADIENT, FLUX_6_2, FLUX_6_4, FLUX_LINEAR, FP32_FLUX, FP64,  # noqa: F401
-                   GRAD_CARRIED, GRAD_REEVAL, FdcgksError, Params)
+                   GRAD_CARRIED, GRAD_REEVAL, RECON_CHARACTERISTIC, RECON_CONSERVATIVE, FdcgksError, Params)
 
 __all__ = ["Problem", "Batch", "Params", "FdcgksError", "default_params", "make_params"]
 
 _VARIANTS = {"6-4": FLUX_6_4, "6-2": FLUX_6_2, "linear": FLUX_LINEAR}
 _BCS = {"periodic": BC_PERIODIC, "zero_gradient": BC_ZERO_GRADIENT}
+_RECON = {"conservative": RECON_CONSERVATIVE, "characteristic": RECON_CHARACTERISTIC}
 
 
 def default_params() -> Params:
@@ -35,7 +36,7 @@ def default_params() -> Params:
 def make_params(**kw) -> Params:
     """fdcgks_params from keywords (names of the C struct; also
     variant='6-4'|'6-2'|'linear', bc='periodic'|'zero_gradient',
-    fp32_flux=bool)."""
+    recon_vars='conservative'|'characteristic', fp32_flux=bool)."""
     p = default_params()
     kw = dict(kw)
     if "variant" in kw:
@@ -43,6 +44,8 @@ def make_params(**kw) -> Params:
         p.flux_variant = _VARIANTS[v] if isinstance(v, str) else int(v)
     if "bc" in kw and isinstance(kw["bc"], str):
         kw["bc"] = _BCS[kw["bc"]]
+    if "recon_vars" in kw and isinstance(kw["recon_vars"], str):
+        kw["recon_vars"] = _RECON[kw["recon_vars"]]
     if kw.pop("fp32_flux", False):
         p.flux_precision = FP32_FLUX
     if kw.pop("grad_carried", False):

@@ -18,6 +18,7 @@ BC_PERIODIC, BC_ZERO_GRADIENT = 0, 1
 FLUX_6_4, FLUX_6_2, FLUX_LINEAR = 0, 1, 2
 FP64, FP32_FLUX = 0, 1
 GRAD_REEVAL, GRAD_CARRIED = 0, 1
+RECON_CONSERVATIVE, RECON_CHARACTERISTIC = 0, 1
 OPT_GRAPH, OPT_TILE_EDGE, OPT_TILE_NODE, OPT_TILE_UPDATE, OPT_FUSE_NODES = 0, 1, 2, 3, 4
 BATCH_PERSISTENT, BATCH_PHASED = 0, 1
 
@@ -27,7 +28,7 @@ class Params(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32),
         ("dual_1d", C.c_int32), ("flux_variant", C.c_int32), ("flux_precision", C.c_int32),
-        ("grad_update", C.c_int32), ("geno_r", C.c_int32), ("reserved", C.c_int32),
+        ("grad_update", C.c_int32), ("geno_r", C.c_int32), ("recon_vars", C.c_int32),
         ("x0", C.c_double), ("lx", C.c_double), ("y0", C.c_double), ("ly", C.c_double),
         ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
         ("geno_C", C.c_double), ("geno_eps", C.c_double), ("geno_eps_a", C.c_double),

@@ -124,7 +124,9 @@ __device__ __forceinline__ void solve_dir(const Consts& k, FT dt, const fdk::Ifa
 // (0: primary, 1: dual).  The line runs along y when FAM != G: X-primary
 // along x from P(i-1,j); X-dual along y from D(i,j-2); Y-primary along y
 // from P(i,j-1); Y-dual along x from D(i-2,j).
-template <int FAM, int G>
+// CHAR: reconstruct characteristic variables (every rec[c].cl/cr then holds
+// the path function of the line).
+template <int FAM, int G, bool CHAR = false>
 __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const Geo& g, const Consts& k, int i, int j,
                                            fdk::IfaceRec (&rec)[4]) {
   constexpr bool ALONG_Y = (FAM ^ G) != 0;
@@ -133,11 +135,33 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
   const long o = ALONG_Y ? at(g, j - back, i) : at(g, j, i - back);
   constexpr int f = ALONG_Y ? 2 : 1;  // derivative field along the line
   const long pl = g.plane;
+  if constexpr (CHAR) {
+    // local frame of the line: the momentum along it is component 1
+    double Q[4][4], X[4][4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const double* w = S + (G * 12 + c) * pl + o;
-    const double* x = S + (G * 12 + f * 4 + c) * pl + o;
-    rec[c] = fdk::recon_iface(k, w[0], w[st], w[2 * st], w[3 * st], x[0], x[st], x[2 * st], x[3 * st], g.h, g.invh);
+    for (int c = 0; c < 4; ++c) {
+      const int q = ALONG_Y ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+      const double* w = S + (G * 12 + q) * pl + o;
+      const double* x = S + (G * 12 + f * 4 + q) * pl + o;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        Q[c][m] = w[m * st];
+        X[c][m] = x[m * st];
+      }
+    }
+    fdk::IfaceRec loc[4];
+    double chi;
+    fdk::recon_iface_char<2>(k, Q, X, g.h, g.invh, loc, chi);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rec[ALONG_Y ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c] = loc[c];
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double* w = S + (G * 12 + c) * pl + o;
+      const double* x = S + (G * 12 + f * 4 + c) * pl + o;
+      rec[c] =
+          fdk::recon_iface(k, w[0], w[st], w[2 * st], w[3 * st], x[0], x[st], x[2 * st], x[3 * st], g.h, g.invh);
+    }
   }
 }
 
@@ -149,7 +173,7 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
 // interior reads); block (bx, by) covers TX points in i and TY/2 in j.  The
 // partners exchange tangential slopes and blend sums through LDS.  Every
 // thread of the block must call this.
-template <int STAGE, class FT>
+template <int STAGE, class FT, bool CHAR = false>
 __device__ __forceinline__ void edge_block(const double* __restrict__ S, double* __restrict__ E, const Geo& g,
                                            const Consts& k, double dt, int bx, int by, int fam) {
   // LDS slots per thread: 0-3 tangential slope, 4-7 Wlt + Wrt, 8-11 Wl + Wr
@@ -162,13 +186,18 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
   const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
   fdk::IfaceRec rec[4];
   if (valid) {
-    if (fam == 0) { if (G == 0) edge_recon<0, 0>(S, g, k, i, j, rec); else edge_recon<0, 1>(S, g, k, i, j, rec); }
-    else { if (G == 0) edge_recon<1, 0>(S, g, k, i, j, rec); else edge_recon<1, 1>(S, g, k, i, j, rec); }
+    if (fam == 0) {
+      if (G == 0) edge_recon<0, 0, CHAR>(S, g, k, i, j, rec);
+      else edge_recon<0, 1, CHAR>(S, g, k, i, j, rec);
+    } else {
+      if (G == 0) edge_recon<1, 0, CHAR>(S, g, k, i, j, rec);
+      else edge_recon<1, 1, CHAR>(S, g, k, i, j, rec);
+    }
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
   }
-  const double chi = fmin(rec[0].cl, rec[0].cr);  // path function of the density line
+  const double chi = fmin(rec[0].cl, rec[0].cr);  // path function of the density (or acoustic) line
 #pragma unroll
   for (int c = 0; c < 4; ++c) XCH(c, ty) = 0.5 * (rec[c].dl + rec[c].dr);
   __syncthreads();
@@ -219,17 +248,59 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
 #ifndef FDCGKS_EDGE_WAVES
 #define FDCGKS_EDGE_WAVES 2
 #endif
-template <int STAGE, class FT>
+template <int STAGE, class FT, bool CHAR>
 __global__ __launch_bounds__(256, FDCGKS_EDGE_WAVES) void k_edges2d(const double* __restrict__ S, double* __restrict__ E, Geo g,
                                                     Consts k, const Scal* __restrict__ sc) {
   if (sc->stop) return;  // grid-uniform
-  edge_block<STAGE, FT>(S, E, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z);
+  edge_block<STAGE, FT, CHAR>(S, E, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------------ node sweep
+// Derivatives along x and y at node offset o of grid base B (3-point
+// reconstructions), component-wise or on characteristic variables (then in
+// each line's local frame, eigenvectors at the node's state).
+template <bool CHAR, class FT>
+__device__ __forceinline__ void node_derivs(const double* __restrict__ B, const Geo& g, const Consts& k, long o,
+                                            FT (&Wx)[4], FT (&Wy)[4]) {
+  const long pl = g.plane;
+  if constexpr (CHAR) {
+#pragma unroll
+    for (int ax = 0; ax < 2; ++ax) {
+      const long st = ax == 0 ? 1 : g.pitch;
+      double Q[4][3], X[4][3], d[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int q = ax == 1 ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+        const double* w = B + q * pl + o;
+        const double* x = B + ((ax + 1) * 4 + q) * pl + o;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          Q[c][m] = w[(m - 1) * st];
+          X[c][m] = x[(m - 1) * st];
+        }
+      }
+      fdk::recon_node_char<2>(k, Q, X, g.h, g.invh, d);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int q = ax == 1 ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+        (ax == 0 ? Wx : Wy)[q] = (FT)d[c];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const double* w = B + c * pl + o;
+      const double* x = B + (4 + c) * pl + o;
+      const double* y = B + (8 + c) * pl + o;
+      Wx[c] = (FT)fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
+      Wy[c] = (FT)fdk::recon_node(k, w[-g.pitch], w[0], w[g.pitch], y[-g.pitch], y[0], y[g.pitch], g.h, g.invh);
+    }
+  }
+}
+
 // Nodes i in [-1, nx], j in [-1, ny] of grid `grid`; block (bx, by) of
 // blockDim.x x blockDim.y nodes.
-template <int STAGE, class FT>
+template <int STAGE, class FT, bool CHAR = false>
 __device__ __forceinline__ void node_block(const double* __restrict__ S, double* __restrict__ Nb, const Geo& g,
                                            const Consts& k, int bx, int by, int grid) {
   const int i = bx * blockDim.x + threadIdx.x - 1;
@@ -239,14 +310,8 @@ __device__ __forceinline__ void node_block(const double* __restrict__ S, double*
   const double* B = S + (long)grid * 12 * pl;
   FT W[4], Wx[4], Wy[4];
 #pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const double* w = B + c * pl + o;
-    const double* x = B + (4 + c) * pl + o;
-    const double* y = B + (8 + c) * pl + o;
-    W[c] = (FT)w[0];
-    Wx[c] = (FT)fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
-    Wy[c] = (FT)fdk::recon_node(k, w[-g.pitch], w[0], w[g.pitch], y[-g.pitch], y[0], y[g.pitch], g.h, g.invh);
-  }
+  for (int c = 0; c < 4; ++c) W[c] = (FT)B[c * pl + o];
+  node_derivs<CHAR, FT>(B, g, k, o, Wx, Wy);
   FT F[4], Ft[4], G[4], Gt[4];
   fdk::gks_node<FT, 2, STAGE == 1>(k, W, Wx, Wy, F, Ft, G, Gt);
   double* n = Nb + (long)grid * 16 * pl + o;
@@ -261,11 +326,11 @@ __device__ __forceinline__ void node_block(const double* __restrict__ S, double*
   }
 }
 
-template <int STAGE, class FT>
+template <int STAGE, class FT, bool CHAR>
 __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, double* __restrict__ Nb, Geo g,
                                                  Consts k, const Scal* __restrict__ sc) {
   if (sc->stop) return;
-  node_block<STAGE, FT>(S, Nb, g, k, blockIdx.x, blockIdx.y, blockIdx.z);
+  node_block<STAGE, FT, CHAR>(S, Nb, g, k, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // ------------------------------------------------------ assemble + update
@@ -391,7 +456,7 @@ struct NodeFluxShared {
   }
 };
 
-template <int STAGE, class FT>
+template <int STAGE, class FT, bool CHAR>
 __global__ __launch_bounds__(256) void k_nodeupd2d(const double* __restrict__ S, const double* __restrict__ E,
                                                    const double* __restrict__ Ain, double* __restrict__ Out,
                                                    double* __restrict__ Aout, Geo g, Consts k, Scal* __restrict__ sc) {
@@ -417,14 +482,8 @@ __global__ __launch_bounds__(256) void k_nodeupd2d(const double* __restrict__ S,
     const long o = at(g, j, i);
     FT W[4], Wx[4], Wy[4];
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      const double* w = B + cc * pl + o;
-      const double* x = B + (4 + cc) * pl + o;
-      const double* y = B + (8 + cc) * pl + o;
-      W[cc] = (FT)w[0];
-      Wx[cc] = (FT)fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
-      Wy[cc] = (FT)fdk::recon_node(k, w[-g.pitch], w[0], w[g.pitch], y[-g.pitch], y[0], y[g.pitch], g.h, g.invh);
-    }
+    for (int cc = 0; cc < 4; ++cc) W[cc] = (FT)B[cc * pl + o];
+    node_derivs<CHAR, FT>(B, g, k, o, Wx, Wy);
     FT F[4], Ft[4], Gv[4], Gt[4];
     fdk::gks_node<FT, 2, STAGE == 1>(k, W, Wx, Wy, F, Ft, Gv, Gt);
     const bool xrow = r >= 0 && r < 4, ycol = c >= 0 && c < 64;
@@ -481,7 +540,7 @@ __device__ __forceinline__ void halo1d(double* __restrict__ S, const Geo& g, int
   }
 }
 
-template <int STAGE, class FT>
+template <int STAGE, class FT, bool CHAR>
 __device__ void stage1d_block(double* __restrict__ S, const double* __restrict__ Ain, double* __restrict__ Out,
                               double* __restrict__ Aout, double* __restrict__ E, double* __restrict__ Nb,
                               const Geo& g, const Consts& k, int lines, int bc, double dt, int* sfail,
@@ -496,13 +555,31 @@ __device__ void stage1d_block(double* __restrict__ S, const double* __restrict__
     const double* B = S + (long)l * 6 * pl;
     fdk::GksIO<FT, 1> io;
     double chi = 1.0;
+    if constexpr (CHAR) {
+      double Q[3][4], X[3][4];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double* w = B + c * pl + at(g, 0, j - 1);
-      const double* x = B + (3 + c) * pl + at(g, 0, j - 1);
-      fdk::IfaceRec r = fdk::recon_iface(k, w[0], w[1], w[2], w[3], x[0], x[1], x[2], x[3], g.h, g.invh);
-      io.WL[c] = (FT)r.vl; io.WR[c] = (FT)r.vr; io.nL[c] = (FT)r.dl; io.nR[c] = (FT)r.dr; io.Wt[c] = FT(0);
-      if (c == 0) chi = fmin(r.cl, r.cr);
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          Q[c][m] = B[c * pl + at(g, 0, j - 1 + m)];
+          X[c][m] = B[(3 + c) * pl + at(g, 0, j - 1 + m)];
+        }
+      fdk::IfaceRec r[3];
+      fdk::recon_iface_char<1>(k, Q, X, g.h, g.invh, r, chi);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        io.WL[c] = (FT)r[c].vl; io.WR[c] = (FT)r[c].vr; io.nL[c] = (FT)r[c].dl; io.nR[c] = (FT)r[c].dr;
+        io.Wt[c] = FT(0);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double* w = B + c * pl + at(g, 0, j - 1);
+        const double* x = B + (3 + c) * pl + at(g, 0, j - 1);
+        fdk::IfaceRec r = fdk::recon_iface(k, w[0], w[1], w[2], w[3], x[0], x[1], x[2], x[3], g.h, g.invh);
+        io.WL[c] = (FT)r.vl; io.WR[c] = (FT)r.vr; io.nL[c] = (FT)r.dl; io.nR[c] = (FT)r.dr; io.Wt[c] = FT(0);
+        if (c == 0) chi = fmin(r.cl, r.cr);
+      }
     }
     fdk::gks_iface<FT, 1, STAGE == 1>(k, (FT)dt, io);
     double* e = E + (long)l * 19 * pl + at(g, 0, j);
@@ -524,12 +601,29 @@ __device__ void stage1d_block(double* __restrict__ S, const double* __restrict__
     const int l = q / (N + 2), j = q % (N + 2) - 1;
     const double* B = S + (long)l * 6 * pl;
     FT W[3], Wx[3], F[3], Ft[3];
+    if constexpr (CHAR) {
+      double Q[3][3], X[3][3], d[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double* w = B + c * pl + at(g, 0, j);
-      const double* x = B + (3 + c) * pl + at(g, 0, j);
-      W[c] = (FT)w[0];
-      Wx[c] = (FT)fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          Q[c][m] = B[c * pl + at(g, 0, j - 1 + m)];
+          X[c][m] = B[(3 + c) * pl + at(g, 0, j - 1 + m)];
+        }
+      fdk::recon_node_char<1>(k, Q, X, g.h, g.invh, d);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        W[c] = (FT)Q[c][1];
+        Wx[c] = (FT)d[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double* w = B + c * pl + at(g, 0, j);
+        const double* x = B + (3 + c) * pl + at(g, 0, j);
+        W[c] = (FT)w[0];
+        Wx[c] = (FT)fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
+      }
     }
     fdk::gks_node<FT, 1, STAGE == 1>(k, W, Wx, (const FT*)nullptr, F, Ft, (FT*)nullptr, (FT*)nullptr);
     double* n = Nb + (long)l * 6 * pl + at(g, 0, j);
@@ -595,7 +689,7 @@ __device__ void stage1d_block(double* __restrict__ S, const double* __restrict__
 // Whole 1D run in one workgroup.  mode 0: up to nsteps steps, ping-pong
 // between S0 and S1 starting from S0; mode 1 / 2: one stage at sc->dt into
 // Sstar/Acc (1) or S1 (2), not committed.
-template <class FT>
+template <class FT, bool CHAR>
 __global__ __launch_bounds__(256) void k_run1d(double* S0, double* S1, double* Sstar, double* Acc, double* E,
                                                double* Nb, Geo g, Consts k, Scal* sc, int lines, int bc,
                                                int nsteps, double cfl, int use_cfl, int mode) {
@@ -607,8 +701,8 @@ __global__ __launch_bounds__(256) void k_run1d(double* S0, double* S1, double* S
   if (sstop) return;
   if (mode == 1 || mode == 2) {
     const double dt = sc->dt;
-    if (mode == 1) stage1d_block<1, FT>(S0, nullptr, Sstar, Acc, E, Nb, g, k, lines, bc, dt, &sfail, sc);
-    else stage1d_block<2, FT>(Sstar, Acc, S1, nullptr, E, Nb, g, k, lines, bc, dt, &sfail, sc);
+    if (mode == 1) stage1d_block<1, FT, CHAR>(S0, nullptr, Sstar, Acc, E, Nb, g, k, lines, bc, dt, &sfail, sc);
+    else stage1d_block<2, FT, CHAR>(Sstar, Acc, S1, nullptr, E, Nb, g, k, lines, bc, dt, &sfail, sc);
     if (threadIdx.x == 0 && sfail) sc->stop |= 1;
     return;
   }
@@ -657,9 +751,9 @@ __global__ __launch_bounds__(256) void k_run1d(double* S0, double* S1, double* S
     __syncthreads();
     if (sstop) break;
     const double dt = sdt;
-    stage1d_block<1, FT>(cur, nullptr, Sstar, Acc, E, Nb, g, k, lines, bc, dt, &sfail, sc);
+    stage1d_block<1, FT, CHAR>(cur, nullptr, Sstar, Acc, E, Nb, g, k, lines, bc, dt, &sfail, sc);
     if (sfail) break;
-    stage1d_block<2, FT>(Sstar, Acc, nxt, nullptr, E, Nb, g, k, lines, bc, dt, &sfail, sc);
+    stage1d_block<2, FT, CHAR>(Sstar, Acc, nxt, nullptr, E, Nb, g, k, lines, bc, dt, &sfail, sc);
     if (sfail) break;
     if (threadIdx.x == 0) {
       sc->t += dt;
@@ -1110,19 +1204,21 @@ template <int STAGE>
 void launch_edges(fdcgks_problem* pb, const double* Sin, dim3 blk) {
   const Geo& g = pb->g;
   dim3 ge(ceil_div(g.nx + 3, blk.x), ceil_div(g.ny + 3, blk.y / 2), 2);
-  if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
-    hipLaunchKernelGGL((k_edges2d<STAGE, float>), ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc);
-  else
-    hipLaunchKernelGGL((k_edges2d<STAGE, double>), ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc);
+  const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
+  const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
+  auto fn = f32 ? (ch ? k_edges2d<STAGE, float, true> : k_edges2d<STAGE, float, false>)
+                : (ch ? k_edges2d<STAGE, double, true> : k_edges2d<STAGE, double, false>);
+  hipLaunchKernelGGL(fn, ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc);
 }
 template <int STAGE>
 void launch_nodes(fdcgks_problem* pb, const double* Sin, dim3 blk) {
   const Geo& g = pb->g;
   dim3 gn(ceil_div(g.nx + 2, blk.x), ceil_div(g.ny + 2, blk.y), 2);
-  if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
-    hipLaunchKernelGGL((k_nodes2d<STAGE, float>), gn, blk, 0, pb->stream, Sin, pb->Nb, g, pb->k, pb->sc);
-  else
-    hipLaunchKernelGGL((k_nodes2d<STAGE, double>), gn, blk, 0, pb->stream, Sin, pb->Nb, g, pb->k, pb->sc);
+  const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
+  const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
+  auto fn = f32 ? (ch ? k_nodes2d<STAGE, float, true> : k_nodes2d<STAGE, float, false>)
+                : (ch ? k_nodes2d<STAGE, double, true> : k_nodes2d<STAGE, double, false>);
+  hipLaunchKernelGGL(fn, gn, blk, 0, pb->stream, Sin, pb->Nb, g, pb->k, pb->sc);
 }
 template <int STAGE>
 void launch_update(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout, dim3 blk) {
@@ -1144,12 +1240,11 @@ fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, 
   mark(pb, STAGE == 1 ? TK_EDGE1 : TK_EDGE2);
   if (fused) {
     dim3 gu(ceil_div(g.nx, 64), ceil_div(g.ny, 4), 2);
-    if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
-      hipLaunchKernelGGL((k_nodeupd2d<STAGE, float>), gu, dim3(64, 4), 0, pb->stream, Sin, pb->E, Ain, Out, Aout, g,
-                         pb->k, pb->sc);
-    else
-      hipLaunchKernelGGL((k_nodeupd2d<STAGE, double>), gu, dim3(64, 4), 0, pb->stream, Sin, pb->E, Ain, Out, Aout, g,
-                         pb->k, pb->sc);
+    const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
+    const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
+    auto fn = f32 ? (ch ? k_nodeupd2d<STAGE, float, true> : k_nodeupd2d<STAGE, float, false>)
+                  : (ch ? k_nodeupd2d<STAGE, double, true> : k_nodeupd2d<STAGE, double, false>);
+    hipLaunchKernelGGL(fn, gu, dim3(64, 4), 0, pb->stream, Sin, pb->E, Ain, Out, Aout, g, pb->k, pb->sc);
     mark(pb, STAGE == 1 ? TK_UPD1 : TK_UPD2);
     return launch_check(pb, "stage");
   }
@@ -1181,12 +1276,12 @@ fdcgks_status launch_run1d(fdcgks_problem* pb, int mode, int nsteps, double dt, 
   const int use_cfl = dt > 0 ? 0 : 1;
   double* S0 = pb->S[pb->cur];
   double* S1 = pb->S[1 - pb->cur];
-  if (pb->prm.flux_precision == FDCGKS_FP32_FLUX)
-    hipLaunchKernelGGL(k_run1d<float>, dim3(1), dim3(256), 0, pb->stream, S0, S1, pb->Sstar, pb->Acc, pb->E, pb->Nb,
-                       pb->g, pb->k, pb->sc, pb->ngrid, pb->prm.bc, nsteps, cfl, use_cfl, mode);
-  else
-    hipLaunchKernelGGL(k_run1d<double>, dim3(1), dim3(256), 0, pb->stream, S0, S1, pb->Sstar, pb->Acc, pb->E, pb->Nb,
-                       pb->g, pb->k, pb->sc, pb->ngrid, pb->prm.bc, nsteps, cfl, use_cfl, mode);
+  const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
+  const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
+  auto fn = f32 ? (ch ? k_run1d<float, true> : k_run1d<float, false>)
+                : (ch ? k_run1d<double, true> : k_run1d<double, false>);
+  hipLaunchKernelGGL(fn, dim3(1), dim3(256), 0, pb->stream, S0, S1, pb->Sstar, pb->Acc, pb->E, pb->Nb, pb->g, pb->k,
+                     pb->sc, pb->ngrid, pb->prm.bc, nsteps, cfl, use_cfl, mode);
   return launch_check(pb, "run1d");
 }
 
@@ -1305,7 +1400,8 @@ fdcgks_status check_params(const fdcgks_params* p) {
       !(p->geno_d_side > 0))
     return fail(nullptr, FDCGKS_EINVAL, "GENO constants must be > 0");
   if (!(p->tau_c1 >= 0) || !(p->tau_c2 >= 0)) return fail(nullptr, FDCGKS_EINVAL, "tau constants must be >= 0");
-  if (p->reserved != 0) return fail(nullptr, FDCGKS_EINVAL, "reserved must be 0");
+  if (p->recon_vars != FDCGKS_RECON_CONSERVATIVE && p->recon_vars != FDCGKS_RECON_CHARACTERISTIC)
+    return fail(nullptr, FDCGKS_EINVAL, "bad recon_vars");
   return FDCGKS_OK;
 }
 
@@ -1699,6 +1795,8 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   if (!pb || !lam_out || !lam_in) return fail(pb, FDCGKS_EINVAL, "NULL argument");
   if (pb->prm.dim != 2) return fail(pb, FDCGKS_EINVAL, "the step adjoint is implemented for 2D problems");
   if (pb->prm.flux_precision != FDCGKS_FP64) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs FP64 fluxes");
+  if (pb->prm.recon_vars != FDCGKS_RECON_CONSERVATIVE)
+    return fail(pb, FDCGKS_EINVAL, "the step adjoint needs conservative reconstruction");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, FDCGKS_EINVAL, "dt must be finite and > 0");
   if (!state_ready(pb)) return fail(pb, FDCGKS_ESTATE, "set_state has not been called for every grid");
   fdcgks_status st = adj_alloc(pb);
@@ -1910,6 +2008,8 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
     fdcgks_status st = check_params(&params[m]);
     if (st) return bfail(nullptr, st, "member %d: %s", m, g_create_error.c_str());
     if (params[m].dim != 2) return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches are 2D only", m);
+    if (params[m].recon_vars != FDCGKS_RECON_CONSERVATIVE)
+      return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches reconstruct conservative variables only", m);
     if (!same_scheme(params[0], params[m]))
       return bfail(nullptr, FDCGKS_EINVAL, "member %d: scheme constants differ from member 0", m);
   }

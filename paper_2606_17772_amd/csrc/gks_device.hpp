@@ -208,6 +208,148 @@ FDK_HD R recon_node(const Consts& k, R q0, R q1, R q2, R x0, R x1, R x2, double 
   return o.d;
 }
 
+// ------------------------------------- characteristic variables (Sec. 3)
+// Eigenvectors of the Euler flux Jacobian along a line, in the line's local
+// frame (component 1 is the momentum along the line), at a state W.  The
+// columns of R are the fields u - c, u, [shear,] u + c, normalised as
+// (1, u - c, [v,] H - u c), (1, u, [v,] |u|^2/2), [(0, 0, 1, v),]
+// (1, u + c, [v,] H + u c); L = R^-1 in closed form with b1 = (gamma-1)/c^2
+// and b2 = b1 |u|^2 / 2.  The map is linear, so values and derivatives
+// transform with the same matrices.  Nothing here is contracted into fused
+// multiply-adds, in particular not with the callers' arithmetic: otherwise
+// which products fuse would depend on the kernel the code is inlined into,
+// and the path function (very sensitive to the last bit of the
+// characteristic values on smooth data) would differ between kernels.
+struct CharFrame {
+  double u, v, c, ic, H, b1, b2, k2;  // k2 = |u|^2 / 2
+};
+template <int DIM> FDK_HD CharFrame char_frame(double gamma, const double* W) {
+#pragma clang fp contract(off)
+  CharFrame f;
+  const double ir = 1.0 / W[0];
+  f.u = W[1] * ir;
+  f.v = DIM == 2 ? W[2] * ir : 0.0;
+  f.k2 = 0.5 * (f.u * f.u + f.v * f.v);
+  const double p = (gamma - 1.0) * (W[DIM + 1] - W[0] * f.k2);
+  const double c2 = gamma * p * ir;
+  f.c = sqrt(c2);
+  f.ic = 1.0 / f.c;
+  f.H = (W[DIM + 1] + p) * ir;
+  f.b1 = (gamma - 1.0) / c2;
+  f.b2 = f.b1 * f.k2;
+  return f;
+}
+// q = L w
+template <int DIM> FDK_HD void to_char(const CharFrame& f, const double* w, double* q) {
+#pragma clang fp contract(off)
+  const double uc = f.u * f.ic;
+  const double s = f.b1 * (w[DIM + 1] - f.u * w[1] - (DIM == 2 ? f.v * w[2] : 0.0));  // b1 (E - u m - v n)
+  const double a = f.b2 * w[0] + s;  // b2 rho + b1 (E - u m - v n)
+  const double m = f.ic * w[1] - uc * w[0];  // (m - u rho) / c
+  q[0] = 0.5 * (a - m);
+  q[1] = w[0] - a;
+  if (DIM == 2) q[2] = w[2] - f.v * w[0];
+  q[DIM + 1] = 0.5 * (a + m);
+}
+// w = R q
+template <int DIM> FDK_HD void from_char(const CharFrame& f, const double* q, double* w) {
+#pragma clang fp contract(off)
+  const double lo = q[0], en = q[1], hi = q[DIM + 1];
+  const double sh = DIM == 2 ? q[2] : 0.0;
+  const double s = lo + en + hi;
+  w[0] = s;
+  w[1] = f.u * s + f.c * (hi - lo);
+  if (DIM == 2) w[2] = f.v * s + sh;
+  w[DIM + 1] = f.H * (lo + hi) + f.u * f.c * (hi - lo) + f.k2 * en + f.v * sh;
+}
+
+// Interface reconstruction of a whole line of N = DIM + 2 components on
+// characteristic variables.  Q[c][m], X[c][m]: values and averaged
+// derivatives in the local frame at the nodes m = 0..3 around the interface;
+// the eigenvectors are taken at the mean of the two interface-adjacent
+// states.  rec[c] receives the local-frame results; chi is the smallest of
+// the left and right path functions of the u - c and u + c fields.
+template <int DIM>
+FDK_HD void recon_iface_char(const Consts& k, const double (&Q)[DIM + 2][4], const double (&X)[DIM + 2][4], double h,
+                             double invh, IfaceRec (&rec)[DIM + 2], double& chi) {
+  constexpr int N = DIM + 2;
+  double Wm[N];
+  {
+#pragma clang fp contract(off)
+#pragma unroll
+    for (int c = 0; c < N; ++c) Wm[c] = 0.5 * (Q[c][1] + Q[c][2]);
+  }
+  const CharFrame f = char_frame<DIM>(k.gamma, Wm);
+  double qc[N][4], xc[N][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double a[N], b[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) a[c] = Q[c][m];
+    to_char<DIM>(f, a, b);
+#pragma unroll
+    for (int c = 0; c < N; ++c) { qc[c][m] = b[c]; a[c] = X[c][m]; }
+    to_char<DIM>(f, a, b);
+#pragma unroll
+    for (int c = 0; c < N; ++c) xc[c][m] = b[c];
+  }
+  IfaceRec cr[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c)
+    cr[c] = recon_iface<double>(k, qc[c][0], qc[c][1], qc[c][2], qc[c][3], xc[c][0], xc[c][1], xc[c][2], xc[c][3],
+                                h, invh);
+  chi = fmin(fmin(cr[0].cl, cr[0].cr), fmin(cr[N - 1].cl, cr[N - 1].cr));
+  double a[N], b[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) a[c] = cr[c].vl;
+  from_char<DIM>(f, a, b);
+#pragma unroll
+  for (int c = 0; c < N; ++c) { rec[c].vl = b[c]; a[c] = cr[c].dl; }
+  from_char<DIM>(f, a, b);
+#pragma unroll
+  for (int c = 0; c < N; ++c) { rec[c].dl = b[c]; a[c] = cr[c].vr; }
+  from_char<DIM>(f, a, b);
+#pragma unroll
+  for (int c = 0; c < N; ++c) { rec[c].vr = b[c]; a[c] = cr[c].dr; }
+  from_char<DIM>(f, a, b);
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    rec[c].dr = b[c];
+    rec[c].cl = rec[c].cr = chi;
+  }
+}
+
+// Node derivatives of a whole line on characteristic variables: Q[c][m],
+// X[c][m] at the nodes j-1, j, j+1 (local frame); eigenvectors at the
+// node's own state.
+template <int DIM>
+FDK_HD void recon_node_char(const Consts& k, const double (&Q)[DIM + 2][3], const double (&X)[DIM + 2][3], double h,
+                            double invh, double (&d)[DIM + 2]) {
+  constexpr int N = DIM + 2;
+  double Wc[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c) Wc[c] = Q[c][1];
+  const CharFrame f = char_frame<DIM>(k.gamma, Wc);
+  double qc[N][3], xc[N][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double a[N], b[N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) a[c] = Q[c][m];
+    to_char<DIM>(f, a, b);
+#pragma unroll
+    for (int c = 0; c < N; ++c) { qc[c][m] = b[c]; a[c] = X[c][m]; }
+    to_char<DIM>(f, a, b);
+#pragma unroll
+    for (int c = 0; c < N; ++c) xc[c][m] = b[c];
+  }
+  double dc[N];
+#pragma unroll
+  for (int c = 0; c < N; ++c)
+    dc[c] = recon_node<double>(k, qc[c][0], qc[c][1], qc[c][2], xc[c][0], xc[c][1], xc[c][2], h, invh);
+  from_char<DIM>(f, dc, d);
+}
+
 // ------------------------------------------- Maxwellian moments (App. A)
 // Per unit density: mu[n] = <u^n> (full or half line), mv[n] = <v^n>,
 // x2 = <xi^2>, x4 = <xi^4>.

@@ -25,7 +25,8 @@ def gpu_params(s):
               prandtl=s["prandtl"], variant=s["variant"], geno_C=s["geno_C"], geno_r=s["geno_r"],
               geno_eps=s["geno_eps"], geno_eps_a=s["geno_eps_a"], geno_d_central=s["d_central"],
               geno_d_side=s["d_side"], tau_c1=s["tau_c1"], tau_c2=s["tau_c2"], bc=s["bc"],
-              fp32_flux=s.get("fp32_flux", False), grad_carried=s.get("grad_carried", 0))
+              fp32_flux=s.get("fp32_flux", False), grad_carried=s.get("grad_carried", 0),
+              recon_vars=s.get("recon_vars", "conservative"))
     if s["dim"] == 2:
         kw["ly"] = s.get("ly", s["lx"] * s["ny"] / s["nx"])
     else:

@@ -47,7 +47,7 @@ def test_defaults():
 @pytest.mark.parametrize("bad", [
     dict(dim=3), dict(nx=3), dict(ny=2), dict(gamma=1.0), dict(gamma=1.7), dict(mu=-1.0),
     dict(mu=1e-3, prandtl=0.0), dict(flux_variant=7), dict(flux_precision=5), dict(geno_r=0),
-    dict(geno_eps=0.0), dict(tau_c1=-1.0), dict(bc=1), dict(lx=0.0), dict(ly=2.0), dict(reserved=1),
+    dict(geno_eps=0.0), dict(tau_c1=-1.0), dict(bc=1), dict(lx=0.0), dict(ly=2.0), dict(recon_vars=2),
     dict(dim=1, nx=100, ny=2), dict(grad_update=3),
 ])
 def test_create_rejects_bad_params(bad):
