@@ -82,12 +82,13 @@ template <class T> inline T sq(T a) { return a * a; }
 struct Par {
   int32_t dim, nx, ny, bc, dual_1d, variant, r, grad_carried;
   int32_t recon_char, pad_;  // 1: reconstruct characteristic variables (Sec. 3)
+  int32_t side[4];           // 2D boundary of the x-low, x-high, y-low, y-high sides
   double x0, lx, y0, ly;
   double gamma, mu, prandtl;
   double C, eps, eps_a, d_central, d_side;
   double tau_c1, tau_c2;
 };
-enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1 };
+enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1, BC_REFLECTING = 2, BC_NO_SLIP = 3 };
 enum { VAR_6_4 = 0, VAR_6_2 = 1, VAR_LINEAR = 2 };
 
 // ------------------------------------------------ GENO reconstruction, Sec. 3
@@ -615,23 +616,65 @@ template <class T> T compact_flux(const Par& p, T Fm, T Fc, T Fp, T N0, T N1, T 
 // State arrays: 12 planes of ny*nx doubles per grid, fields W[0..3],
 // Wx[0..3], Wy[0..3], x fastest.  P[j][i] at (x0+(i+1/2)h, y0+(j+1/2)h);
 // D[j][i] at (x0+(i+1)h, y0+(j+1)h); both periodic.
+// Bounded 2D axes.  Primary nodes sit at x0 + (i + 1/2) h, so a boundary
+// lies half a mesh beyond the end primary nodes; dual nodes sit at
+// x0 + (i + 1) h, so along a bounded axis the two boundary lines carry dual
+// nodes: the dual grid has n + 1 nodes there (lattice I = 2i, i = 0..n),
+// against n (lattice I = 2i + 2, periodic) otherwise.
+inline int bounded(const Par& p, int ax) { return p.side[2 * ax] != BC_PERIODIC ? 1 : 0; }
+
+// Ghost rule along one axis of lattice length L = 2n: moves the lattice
+// coordinate X onto a real node and returns the factor for component c of
+// field f (0: W, 1: Wx, 2: Wy).  Periodic: the periodic image.  Zero-gradient
+// (D29): the nearest boundary node of the same grid, derivative normal to the
+// boundary zero.  Reflecting and no-slip: the mirror image about the boundary
+// line; the normal momentum is odd (no-slip: both momenta), the rest even, and
+// a derivative normal to the boundary has the opposite parity of its field.
+inline double axis_image(int& X, int L, int lo, int hi, int ax, int f, int c) {
+  if (lo == BC_PERIODIC) {
+    X = ((X % L) + L) % L;
+    return 1.0;
+  }
+  if (X >= 0 && X <= L) return 1.0;
+  const int type = X < 0 ? lo : hi;
+  if (type == BC_ZERO_GRADIENT) {
+    const bool odd = (X & 1) != 0;
+    X = X < 0 ? (odd ? 1 : 0) : (odd ? L - 1 : L);
+    return f == 1 + ax ? 0.0 : 1.0;
+  }
+  X = X < 0 ? -X : 2 * L - X;
+  const bool odd_field = c == 1 + ax || (type == BC_NO_SLIP && (c == 1 || c == 2));
+  const double s = odd_field ? -1.0 : 1.0;
+  return f == 1 + ax ? -s : s;
+}
+
+// Node values on the half-spacing lattice: node (I, J), I + J even, is
+// primary for I odd and dual for I even; points beyond a bounded side are
+// ghosts given by axis_image.
 template <class T> struct Grid2 {
   int nx, ny;
   const T* P;
   const T* D;
-  long plane() const { return (long)nx * ny; }
-  static int md(int a, int m) { return ((a % m) + m) % m; }
-  // node at lattice point (I, J) with I+J even: grid and flat index
-  const T* node(int I, int J, long& k) const {
-    I = md(I, 2 * nx); J = md(J, 2 * ny);
-    if (I & 1) { k = (long)((J - 1) / 2) * nx + (I - 1) / 2; return P; }
-    int i = md(I / 2 - 1, nx), j = md(J / 2 - 1, ny);
-    k = (long)j * nx + i;
-    return D;
+  int side[4], wx, wy;
+  Grid2(const Par& p, const T* P_, const T* D_) : nx(p.nx), ny(p.ny), P(P_), D(D_) {
+    for (int k = 0; k < 4; ++k) side[k] = p.side[k];
+    wx = bounded(p, 0);
+    wy = bounded(p, 1);
   }
-  T W(int I, int J, int c) const { long k; const T* b = node(I, J, k); return b[c * plane() + k]; }
-  T Wx(int I, int J, int c) const { long k; const T* b = node(I, J, k); return b[(4 + c) * plane() + k]; }
-  T Wy(int I, int J, int c) const { long k; const T* b = node(I, J, k); return b[(8 + c) * plane() + k]; }
+  long plP() const { return (long)nx * ny; }
+  long plD() const { return (long)(nx + wx) * (ny + wy); }
+  static int md(int a, int m) { return ((a % m) + m) % m; }
+  T get(int I, int J, int f, int c) const {
+    const double s = axis_image(I, 2 * nx, side[0], side[1], 0, f, c) *
+                     axis_image(J, 2 * ny, side[2], side[3], 1, f, c);
+    if (s == 0.0) return T(0.0);
+    if (I & 1) return s * P[(4 * f + c) * plP() + (long)((J - 1) / 2) * nx + (I - 1) / 2];
+    const int i = wx ? I / 2 : md(I / 2 - 1, nx), j = wy ? J / 2 : md(J / 2 - 1, ny);
+    return s * D[(4 * f + c) * plD() + (long)j * (nx + wx) + i];
+  }
+  T W(int I, int J, int c) const { return get(I, J, 0, c); }
+  T Wx(int I, int J, int c) const { return get(I, J, 1, c); }
+  T Wy(int I, int J, int c) const { return get(I, J, 2, c); }
 };
 
 // What one virtual interface gives, per normal axis (0: x, 1: y).
@@ -728,22 +771,30 @@ template <class T> NodeRes<T> node2d(const Par& p, const Grid2<T>& G, int I, int
   return R;
 }
 
-// Edge / node result storage indexed by lattice point.
+// Edge / node results over a box of the lattice: a periodic axis covers one
+// period [0, 2n) and wraps; a bounded axis covers [-3, 2n + 3], everything
+// the operators of its real nodes read.  Interface points (I + J odd) and
+// nodes (I + J even) are kept apart, each at (J - J0) * RW + (I - I0) / 2.
 template <class T> struct Store2 {
-  int nx, ny;
-  std::vector<EdgeRes<T>> X, Y;  // X[j][i] at (2i+2, 2j+1); Y[j][i] at (2i+1, 2j+2)
-  std::vector<NodeRes<T>> P, D;
-  static int md(int a, int m) { return ((a % m) + m) % m; }
-  const EdgeRes<T>& edge(int I, int J) const {
-    I = md(I, 2 * nx); J = md(J, 2 * ny);
-    if ((I & 1) == 0) return X[(long)((J - 1) / 2) * nx + md(I / 2 - 1, nx)];
-    return Y[(long)md(J / 2 - 1, ny) * nx + (I - 1) / 2];
+  int nx, ny, wx, wy, I0, J0, LI, LJ, RW;
+  std::vector<EdgeRes<T>> E;
+  std::vector<NodeRes<T>> N;
+  void init(const Par& p) {
+    nx = p.nx; ny = p.ny;
+    wx = bounded(p, 0); wy = bounded(p, 1);
+    I0 = wx ? -3 : 0; LI = wx ? 2 * nx + 7 : 2 * nx;
+    J0 = wy ? -3 : 0; LJ = wy ? 2 * ny + 7 : 2 * ny;
+    RW = (LI + 1) / 2;
+    E.assign((size_t)RW * LJ, EdgeRes<T>());
+    N.assign((size_t)RW * LJ, NodeRes<T>());
   }
-  const NodeRes<T>& nodeR(int I, int J) const {
-    I = md(I, 2 * nx); J = md(J, 2 * ny);
-    if (I & 1) return P[(long)((J - 1) / 2) * nx + (I - 1) / 2];
-    return D[(long)md(J / 2 - 1, ny) * nx + md(I / 2 - 1, nx)];
+  long idx(int I, int J) const {
+    if (!wx) I = ((I % (2 * nx)) + 2 * nx) % (2 * nx);
+    if (!wy) J = ((J % (2 * ny)) + 2 * ny) % (2 * ny);
+    return (long)(J - J0) * RW + (I - I0) / 2;
   }
+  const EdgeRes<T>& edge(int I, int J) const { return E[idx(I, J)]; }
+  const NodeRes<T>& nodeR(int I, int J) const { return N[idx(I, J)]; }
 };
 
 // Stage operator at node (I, J): L, L_t (Eq. eq-conservation-law-2d with the
@@ -808,48 +859,67 @@ void s2o4(int stage, double dt, const NodeOp<T>& op, const T* st, const T* acc, 
   }
 }
 
+// Lattice coordinate of stored dual node i along an axis (bounded or not).
+inline int dual_lattice(int i, int bounded_axis) { return bounded_axis ? 2 * i : 2 * i + 2; }
+
+// Dual nodes on a reflecting or no-slip boundary carry the wall condition:
+// after each stage their wall-normal momentum (no-slip: both momenta) and that
+// momentum's derivative along the wall are set to zero.
+template <class T> void wall_constraint(const Par& p, int I, int J, T* out12) {
+  const int L[2] = {2 * p.nx, 2 * p.ny}, X[2] = {I, J};
+  for (int ax = 0; ax < 2; ++ax) {
+    if (!bounded(p, ax)) continue;
+    int type = X[ax] == 0 ? p.side[2 * ax] : (X[ax] == L[ax] ? p.side[2 * ax + 1] : BC_PERIODIC);
+    if (type != BC_REFLECTING && type != BC_NO_SLIP) continue;
+    const int along = 1 + (1 - ax);  // field of the derivative along the wall
+    for (int c = 1; c <= 2; ++c) {
+      if (type == BC_REFLECTING && c != 1 + ax) continue;
+      out12[c] = T(0.0);
+      out12[4 * along + c] = T(0.0);
+    }
+  }
+}
+
 template <class T>
 void stage2d(const Par& p, int stage, double dt, const T* P, const T* D, const T* accP, const T* accD,
              T* outP, T* outD, T* outAccP, T* outAccD, Store2<T>* keep = nullptr) {
   const int nx = p.nx, ny = p.ny;
   const double h = p.lx / nx;
-  Grid2<T> G{nx, ny, P, D};
+  const Grid2<T> G(p, P, D);
   Store2<T> S;
-  S.nx = nx; S.ny = ny;
-  S.X.resize((size_t)nx * ny); S.Y.resize((size_t)nx * ny);
-  S.P.resize((size_t)nx * ny); S.D.resize((size_t)nx * ny);
+  S.init(p);
 #pragma omp parallel for schedule(dynamic, 1)
-  for (int j = 0; j < ny; ++j)
-    for (int i = 0; i < nx; ++i) {
-      long k = (long)j * nx + i;
-      S.X[k] = edge2d(p, G, 2 * i + 2, 2 * j + 1, h, dt);
-      S.Y[k] = edge2d(p, G, 2 * i + 1, 2 * j + 2, h, dt);
-      S.P[k] = node2d(p, G, 2 * i + 1, 2 * j + 1, h);
-      S.D[k] = node2d(p, G, 2 * i + 2, 2 * j + 2, h);
+  for (int J = S.J0; J < S.J0 + S.LJ; ++J)
+    for (int I = S.I0; I < S.I0 + S.LI; ++I) {
+      if ((I + J) & 1) S.E[S.idx(I, J)] = edge2d(p, G, I, J, h, dt);
+      else S.N[S.idx(I, J)] = node2d(p, G, I, J, h);
     }
-  const long pl = (long)nx * ny;
   auto edgef = [&](int I, int J) -> const EdgeRes<T>& { return S.edge(I, J); };
   auto nodef = [&](int I, int J) -> const NodeRes<T>& { return S.nodeR(I, J); };
+  for (int g = 0; g < 2; ++g) {
+    const int mx = g == 0 ? nx : nx + G.wx, my = g == 0 ? ny : ny + G.wy;
+    const long pl = (long)mx * my;
+    const T* src = g == 0 ? P : D;
+    const T* acc = g == 0 ? accP : accD;
+    T* o = g == 0 ? outP : outD;
+    T* ao = g == 0 ? outAccP : outAccD;
 #pragma omp parallel for schedule(static)
-  for (int j = 0; j < ny; ++j)
-    for (int i = 0; i < nx; ++i) {
-      long k = (long)j * nx + i;
-      for (int g = 0; g < 2; ++g) {
-        int I = g == 0 ? 2 * i + 1 : 2 * i + 2, J = g == 0 ? 2 * j + 1 : 2 * j + 2;
+    for (int j = 0; j < my; ++j)
+      for (int i = 0; i < mx; ++i) {
+        const long k = (long)j * mx + i;
+        const int I = g == 0 ? 2 * i + 1 : dual_lattice(i, G.wx);
+        const int J = g == 0 ? 2 * j + 1 : dual_lattice(j, G.wy);
         NodeOp<T> op = node_operator<T>(p, I, J, h, edgef, nodef);
-        const T* src = g == 0 ? P : D;
-        const T* acc = g == 0 ? accP : accD;
         T st[12], ac[12], out[12], aout[12];
         for (int f = 0; f < 12; ++f) { st[f] = src[f * pl + k]; ac[f] = acc ? acc[f * pl + k] : T(0.0); }
         s2o4(stage, dt, op, st, ac, out, aout, p.grad_carried);
-        T* o = g == 0 ? outP : outD;
-        T* ao = g == 0 ? outAccP : outAccD;
+        if (g == 1) wall_constraint(p, I, J, out);
         for (int f = 0; f < 12; ++f) {
           o[f * pl + k] = out[f];
           if (stage == 1 && ao) ao[f * pl + k] = aout[f];
         }
       }
-    }
+  }
   if (keep) *keep = std::move(S);
 }
 
@@ -875,7 +945,10 @@ inline void speed_scan(const Par& p, int dim, const double* W, long plane, long 
 // ================================================================ 1D lines
 // A line holds 2*N planes... fields W[0..2], Wx[0..2] of N nodes at
 // x0 + (j + 1/2) h (primary) or x0 + (j + 1) h (the shifted copy, D24).
-// Ghosts: 3 per side, periodic or zero-gradient (D29).
+// Ghosts: 3 per side, periodic, zero-gradient (D29) or reflecting: the line
+// is continued by its mirror image about the face half a mesh beyond the end
+// node, the momentum odd and the other components even (so their
+// x-derivatives are odd and the momentum's even).
 template <class T> struct Line1 {
   int N, bc;
   std::vector<T> W[3], X[3];  // with 3 ghosts on each side: index j + 3
@@ -888,6 +961,10 @@ template <class T> struct Line1 {
         if (bc == BC_PERIODIC) {
           W[c][3 - g] = W[c][3 + N - g]; X[c][3 - g] = X[c][3 + N - g];
           W[c][N + 2 + g] = W[c][2 + g]; X[c][N + 2 + g] = X[c][2 + g];
+        } else if (bc == BC_REFLECTING) {
+          const double s = c == 1 ? -1.0 : 1.0;  // ghost j = -g mirrors node g - 1, ghost N - 1 + g node N - g
+          W[c][3 - g] = s * W[c][2 + g]; X[c][3 - g] = -s * X[c][2 + g];
+          W[c][N + 2 + g] = s * W[c][N + 3 - g]; X[c][N + 2 + g] = -s * X[c][N + 3 - g];
         } else {
           W[c][3 - g] = W[c][3]; X[c][3 - g] = 0.0;
           W[c][N + 2 + g] = W[c][N + 2]; X[c][N + 2 + g] = 0.0;
@@ -1045,17 +1122,18 @@ void orc_s2o4_scalar(int stage, double dt, double W, double L, double Lt, double
 }
 
 // --- 2D ------------------------------------------------------------------
-// P, D: 12 planes (W, Wx, Wy) of ny*nx each.  Stage 2 needs accP/accD.
+// P: 12 planes (W, Wx, Wy) of ny*nx; D likewise of (ny + by)*(nx + bx), with
+// bx, by = 1 along bounded axes.  Stage 2 needs accP/accD.
 void orc_stage2d(const Par* p, int stage, double dt, const double* P, const double* D, const double* accP,
                  const double* accD, double* outP, double* outD, double* outAccP, double* outAccD) {
   stage2d<double>(*p, stage, dt, P, D, accP, accD, outP, outD, outAccP, outAccD);
 }
 
 double orc_dt2d(const Par* p, const double* P, const double* D, double cfl) {
-  long pl = (long)p->nx * p->ny;
+  long pl = (long)p->nx * p->ny, pd = (long)(p->nx + bounded(*p, 0)) * (p->ny + bounded(*p, 1));
   double smax = 0, rmin = 1e300;
   speed_scan(*p, 2, P, pl, pl, smax, rmin);
-  speed_scan(*p, 2, D, pl, pl, smax, rmin);
+  speed_scan(*p, 2, D, pd, pd, smax, rmin);
   return dt_from(*p, smax, rmin, p->lx / p->nx, cfl);
 }
 
@@ -1063,8 +1141,8 @@ double orc_dt2d(const Par* p, const double* P, const double* D, double cfl) {
 // t_end > 0.  P, D updated in place; t in/out; returns steps taken.
 int orc_step2d(const Par* p, double* P, double* D, int nsteps, double dt_fixed, double cfl, double t_end,
                double* t) {
-  long n12 = 12L * p->nx * p->ny;
-  std::vector<double> sP(n12), sD(n12), aP(n12), aD(n12);
+  long n12 = 12L * p->nx * p->ny, d12 = 12L * (p->nx + bounded(*p, 0)) * (p->ny + bounded(*p, 1));
+  std::vector<double> sP(n12), sD(d12), aP(n12), aD(d12);
   int k = 0;
   for (; k < nsteps; ++k) {
     if (t_end > 0 && *t >= t_end) break;
@@ -1078,18 +1156,23 @@ int orc_step2d(const Par* p, double* P, double* D, int nsteps, double dt_fixed, 
 }
 
 // Per-interface and per-node intermediates of one stage, for kernel-level
-// comparison.  Xo, Yo: 50 planes each (per normal axis a = x, y: F[4], Ft[4],
-// chi, Wtl[4], Wtr[4], Wtlt[4], Wtrt[4]); Po, Do: 16 planes (F, Ft, G, Gt).
+// comparison, at (i, j) in [0, nx) x [0, ny): interface points X at lattice
+// (2i+2, 2j+1) and Y at (2i+1, 2j+2), nodes P at (2i+1, 2j+1) and D at
+// (2i+2, 2j+2).  Xo, Yo: 50 planes each (per normal axis a = x, y: F[4],
+// Ft[4], chi, Wtl[4], Wtr[4], Wtlt[4], Wtrt[4]); Po, Do: 16 planes (F, Ft, G,
+// Gt).
 void orc_intermediates2d(const Par* p, double dt, const double* P, const double* D, double* Xo, double* Yo,
                          double* Po, double* Do) {
   const int nx = p->nx, ny = p->ny;
   long n12 = 12L * nx * ny, pl = (long)nx * ny;
-  std::vector<double> a(n12), b(n12), c(n12), d(n12);
+  long d12 = 12L * (nx + bounded(*p, 0)) * (ny + bounded(*p, 1));
+  std::vector<double> a(n12), b(d12), c(n12), d(d12);
   Store2<double> S;
   stage2d<double>(*p, 1, dt, P, D, nullptr, nullptr, a.data(), b.data(), c.data(), d.data(), &S);
   for (long k = 0; k < pl; ++k) {
+    const int i = (int)(k % nx), j = (int)(k / nx);
     for (int fam = 0; fam < 2; ++fam) {
-      const EdgeRes<double>& E = fam == 0 ? S.X[k] : S.Y[k];
+      const EdgeRes<double>& E = fam == 0 ? S.edge(2 * i + 2, 2 * j + 1) : S.edge(2 * i + 1, 2 * j + 2);
       double* o = fam == 0 ? Xo : Yo;
       for (int ax = 0; ax < 2; ++ax) {
         double* q = o + (long)ax * 25 * pl;
@@ -1105,7 +1188,7 @@ void orc_intermediates2d(const Par* p, double dt, const double* P, const double*
       }
     }
     for (int g = 0; g < 2; ++g) {
-      const NodeRes<double>& R = g == 0 ? S.P[k] : S.D[k];
+      const NodeRes<double>& R = g == 0 ? S.nodeR(2 * i + 1, 2 * j + 1) : S.nodeR(2 * i + 2, 2 * j + 2);
       double* o = g == 0 ? Po : Do;
       for (int cc = 0; cc < 4; ++cc) {
         o[cc * pl + k] = R.F[cc]; o[(4 + cc) * pl + k] = R.Ft[cc];
@@ -1116,19 +1199,19 @@ void orc_intermediates2d(const Par* p, double dt, const double* P, const double*
 }
 
 // One stage evaluated at a sample of nodes only (for grids too large for a
-// full oracle sweep).  grid[s] (0: P, 1: D), jj[s], ii[s] name the nodes;
+// full oracle sweep).  grid[s] (0: P, 1: D), jj[s], ii[s] name the stored
+// nodes;
 // out[s*24 .. +12]: the stage output state, out[s*24+12 .. +12]: the stage-1
 // accumulators (zero for stage 2).
 void orc_stage2d_sample(const Par* p, int stage, double dt, const double* P, const double* D, const double* accP,
                         const double* accD, int ns, const int* grid, const int* jj, const int* ii, double* out) {
-  const int nx = p->nx, ny = p->ny;
+  const int nx = p->nx;
   const double h = p->lx / nx;
-  const long pl = (long)nx * ny;
-  Grid2<double> G{nx, ny, P, D};
+  const Grid2<double> G(*p, P, D);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int s = 0; s < ns; ++s) {
-    int I = grid[s] == 0 ? 2 * ii[s] + 1 : 2 * ii[s] + 2;
-    int J = grid[s] == 0 ? 2 * jj[s] + 1 : 2 * jj[s] + 2;
+    int I = grid[s] == 0 ? 2 * ii[s] + 1 : dual_lattice(ii[s], G.wx);
+    int J = grid[s] == 0 ? 2 * jj[s] + 1 : dual_lattice(jj[s], G.wy);
     // the 8 interfaces and 5 nodes the operator reads
     EdgeRes<double> E[2][4];
     NodeRes<double> Nn[2][3];
@@ -1149,12 +1232,15 @@ void orc_stage2d_sample(const Par* p, int stage, double dt, const double* P, con
       return Nn[ax][(o + 2) / 2];
     };
     NodeOp<double> op = node_operator<double>(*p, I, J, h, edgef, nodef);
-    long k = (long)jj[s] * nx + ii[s];
+    const int mx = grid[s] == 0 ? nx : nx + G.wx;
+    const long pl = grid[s] == 0 ? G.plP() : G.plD();
+    long k = (long)jj[s] * mx + ii[s];
     const double* src = grid[s] == 0 ? P : D;
     const double* acc = grid[s] == 0 ? accP : accD;
     double st[12], ac[12], o12[12], a12[12];
     for (int f = 0; f < 12; ++f) { st[f] = src[f * pl + k]; ac[f] = acc ? acc[f * pl + k] : 0.0; }
     s2o4(stage, dt, op, st, ac, o12, a12, p->grad_carried);
+    if (grid[s] == 1) wall_constraint(*p, I, J, o12);
     for (int f = 0; f < 12; ++f) { out[s * 24 + f] = o12[f]; out[s * 24 + 12 + f] = stage == 1 ? a12[f] : 0.0; }
   }
 }
@@ -1162,6 +1248,7 @@ void orc_stage2d_sample(const Par* p, int stage, double dt, const double* P, con
 // Tangent (forward-mode) of one full step at fixed dt: given state and a
 // direction (dP, dD), returns the stepped state and its directional
 // derivative.  Ties in min/max and |0| follow the adjoint's convention.
+// Periodic problems only.
 void orc_step2d_tangent(const Par* p, double dt, const double* P, const double* D, const double* dP,
                         const double* dD, double* outP, double* outD, double* outdP, double* outdD) {
   long n12 = 12L * p->nx * p->ny;

@@ -5,7 +5,9 @@ the ``cpu_baseline`` leg of ``bench.py``.  It never imports the product package
 and the product package never imports it.
 
 Arrays cross the boundary as contiguous float64 numpy arrays.  2D state: one
-array per grid of shape (12, ny, nx) holding W[0..3], Wx[0..3], Wy[0..3].  1D
+array per grid holding W[0..3], Wx[0..3], Wy[0..3]: (12, ny, nx) for the
+primary grid, (12, ny + by, nx + bx) for the dual grid, with bx (by) = 1 when
+the x (y) sides are not periodic (the boundary lines carry dual nodes).  1D
 state: (lines, 6, N) holding W[0..2], Wx[0..2] per line.
 """
 from __future__ import annotations
@@ -37,7 +39,7 @@ class Par(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32),
         ("dual_1d", C.c_int32), ("variant", C.c_int32), ("r", C.c_int32), ("grad_carried", C.c_int32),
-        ("recon_char", C.c_int32), ("pad_", C.c_int32),
+        ("recon_char", C.c_int32), ("pad_", C.c_int32), ("side", C.c_int32 * 4),
         ("x0", C.c_double), ("lx", C.c_double), ("y0", C.c_double), ("ly", C.c_double),
         ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
         ("C", C.c_double), ("eps", C.c_double), ("eps_a", C.c_double),
@@ -47,19 +49,26 @@ class Par(C.Structure):
 
 
 VARIANTS = {"6-4": 0, "6-2": 1, "linear": 2}
-BCS = {"periodic": 0, "zero_gradient": 1}
+BCS = {"periodic": 0, "zero_gradient": 1, "reflecting": 2, "no_slip": 3}
 
 
 def make_par(*, dim=2, nx=16, ny=16, x0=0.0, lx=1.0, y0=0.0, ly=None, bc="periodic", dual_1d=0,
              gamma=1.4, mu=0.0, prandtl=1.0, variant="6-4", geno_C=20.0, geno_r=3,
              geno_eps=1e-15, geno_eps_a=1e-6, d_central=8.0, d_side=1.0, tau_c1=0.0,
-             tau_c2=1.0, grad_carried=0, recon_vars="conservative", **_ignored) -> Par:
+             tau_c2=1.0, grad_carried=0, recon_vars="conservative", sides=None, **_ignored) -> Par:
     """Problem description with the oracle's own field layout.  Defaults are the
     readings of the paper (C = 20, r = 3, eps = 1e-15, eps_a = 1e-6, d = 8/1,
-    tau = 0 * dt + dt |dp|/(p_l+p_r) for Euler: D11 as amended)."""
+    tau = 0 * dt + dt |dp|/(p_l+p_r) for Euler: D11 as amended).  2D sides
+    (x-low, x-high, y-low, y-high) default to `bc` on every side."""
     p = Par()
     p.dim, p.nx, p.ny = dim, nx, (ny if dim == 2 else 1)
     p.bc = BCS[bc] if isinstance(bc, str) else int(bc)
+    sd = [p.bc] * 4 if sides is None else [BCS[b] if isinstance(b, str) else int(b) for b in sides]
+    if dim == 2:
+        for ax in range(2):
+            if (sd[2 * ax] == 0) != (sd[2 * ax + 1] == 0):
+                raise ValueError("a periodic side needs a periodic opposite side")
+    p.side[:] = sd
     p.dual_1d = int(dual_1d)
     p.variant = VARIANTS[variant] if isinstance(variant, str) else int(variant)
     p.r = int(geno_r)
@@ -219,6 +228,11 @@ def stage2d(par, stage, dt, P, D, accP=None, accD=None):
     return (oP, oD, aP, aD) if stage == 1 else (oP, oD)
 
 
+def dual_shape(par):
+    """(ny, nx) of the dual grid."""
+    return par.ny + (par.side[2] != 0), par.nx + (par.side[0] != 0)
+
+
 def dt2d(par, P, D, cfl):
     return lib().orc_dt2d(C.byref(par), _p(_arr(P)), _p(_arr(D)), cfl)
 
@@ -256,6 +270,8 @@ def stage2d_sample(par, stage, dt, P, D, grid, jj, ii, accP=None, accD=None):
 
 
 def step2d_tangent(par, dt, P, D, dP, dD):
+    if any(par.side[k] != 0 for k in range(4)):
+        raise ValueError("the tangent step is implemented for periodic problems")
     P, D, dP, dD = _arr(P), _arr(D), _arr(dP), _arr(dD)
     oP, oD, odP, odD = (np.zeros_like(P) for _ in range(4))
     lib().orc_step2d_tangent(C.byref(par), dt, _p(P), _p(D), _p(dP), _p(dD), _p(oP), _p(oD), _p(odP), _p(odD))

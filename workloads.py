@@ -208,6 +208,65 @@ def random_rough2d(nx, ny, seed=0, lx=1.0):
     return Problem2D("random_rough2d", nx, ny, 0.0, lx, 0.0, lx * ny / nx, P, D, {"gamma": GAMMA, "mu": 0.0})
 
 
+# ------------------------------------------------------ bounded 2D axes
+def sample_bounded(fn, nx, ny, h, bx, by, x0=0.0, y0=0.0, jumps=False):
+    """(P, D) from an analytic conservative field fn(X, Y) -> (4, ...) when
+    axes may be bounded (bx, by = 1).  Along a bounded axis the dual grid has
+    a node on each boundary line, so the dual state is (12, ny + by, nx + bx)
+    with dual node i at lattice 2i (else 2i + 2).  Derivatives are Gauss
+    differences of fn across each node's bounding interfaces (zero with
+    jumps=True)."""
+    def grid(I, J):
+        X = x0 + I * h / 2
+        Y = y0 + J * h / 2
+        X, Y = np.broadcast_arrays(X, Y)
+        G = np.zeros((12,) + X.shape)
+        G[0:4] = fn(X, Y)
+        if not jumps:
+            G[4:8] = (fn(X + h / 2, Y) - fn(X - h / 2, Y)) / h
+            G[8:12] = (fn(X, Y + h / 2) - fn(X, Y - h / 2)) / h
+        return np.ascontiguousarray(G)
+
+    P = grid(2 * np.arange(nx)[None, :] + 1, 2 * np.arange(ny)[:, None] + 1)
+    D = grid(2 * np.arange(nx + bx)[None, :] + (0 if bx else 2), 2 * np.arange(ny + by)[:, None] + (0 if by else 2))
+    return P, D
+
+
+def mirror_flow(lx, ly, bx, by, gamma=GAMMA):
+    """Smooth field for walls: along a bounded axis rho, p and the tangential
+    momentum are even and the normal momentum odd about both boundary lines
+    (half-period cosines and sines); along a periodic axis it is periodic."""
+    kx = math.pi / lx if bx else 2 * math.pi / lx
+    ky = math.pi / ly if by else 2 * math.pi / ly
+
+    def fn(X, Y):
+        cx, cy, sx, sy = np.cos(kx * X), np.cos(ky * Y), np.sin(kx * X), np.sin(ky * Y)
+        rho = 1.0 + 0.2 * cx * cy + 0.1 * np.cos(2 * kx * X)
+        U = 0.3 * sx * (1.0 + 0.2 * cy)
+        V = 0.3 * sy * (1.0 + 0.2 * cx)
+        p = 1.0 + 0.15 * cx * cy
+        return conservative(rho, U, V, p, gamma)
+    return fn
+
+
+def quadrants(states, xs=0.5, ys=0.5, gamma=GAMMA):
+    """Piecewise-constant four-quadrant field (states: (rho, U, V, p) of the
+    quadrants x < xs / x >= xs, then y < ys / y >= ys); use with jumps=True."""
+    def fn(X, Y):
+        quad = (X >= xs).astype(int) + 2 * (Y >= ys).astype(int)
+        return conservative(*(np.choose(quad, [s[k] for s in states]) for k in range(4)), gamma=gamma)
+    return fn
+
+
+def riemann2d_bounded(n, seed=0, gamma=GAMMA):
+    """Four-quadrant Riemann data on [0,1]^2 with every side bounded (states
+    as in riemann2d); dual nodes on the boundary lines."""
+    rng = np.random.default_rng(seed)
+    q = [(rng.uniform(0.1, 1), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.1, 1)) for _ in range(4)]
+    P, D = sample_bounded(quadrants(q, gamma=gamma), n, n, 1.0 / n, 1, 1, jumps=True)
+    return Problem2D("riemann2d_bounded", n, n, 0.0, 1.0, 0.0, 1.0, P, D, {"gamma": gamma, "mu": 0.0, "states": q})
+
+
 def batch_sizes(count=64, lo=64, hi=512, seed=0):
     rng = np.random.default_rng(seed)
     return [int(v) for v in rng.integers(lo, hi + 1, size=count)]
@@ -296,6 +355,18 @@ def seeded_shock_tube(N=400, seed=0):
     left = (rng.uniform(0.1, 1), rng.uniform(-1, 1), rng.uniform(0.1, 1))
     right = (rng.uniform(0.1, 1), rng.uniform(-1, 1), rng.uniform(0.1, 1))
     return shock_tube(N, left, right)
+
+
+def blast_wave(N=400, gamma=GAMMA):
+    """Woodward-Colella blast waves on [0, 1] (Sec. 5 blast test): p = 1000,
+    0.01, 100 on [0, 0.1), [0.1, 0.9), [0.9, 1], rho = 1, u = 0, reflecting
+    ends, t = 0.038.  Jumps fall on interfaces for N a multiple of 10."""
+    h = 1.0 / N
+    x = (np.arange(N) + 0.5) * h
+    p = np.where(x < 0.1, 1000.0, np.where(x < 0.9, 0.01, 100.0))
+    S = np.zeros((1, 6, N))
+    S[0, 0:3] = conservative1d(1.0, 0.0, p, gamma)
+    return Problem1D("blast_wave", N, 0.0, 1.0, S, "reflecting", {"gamma": gamma, "mu": 0.0, "t_end": 0.038})
 
 
 def sod(N=100):
