@@ -33,6 +33,12 @@
  * Grid 1 is the dual grid:    node (i, j) at (x0+(i+1)h,   y0+(j+1)h).
  * In 1D grid 1 is an independent copy on the shifted nodes, advanced only when
  * dual_1d is set.
+ *
+ * Bounded 2D axes.  A side that is not periodic lies half a mesh beyond the
+ * end primary nodes, so the dual grid has nodes on it: along a bounded x axis
+ * the dual grid has nx + 1 nodes, node i at x0 + i h (i = 0..nx), and its
+ * planes are (ny or ny + 1) x (nx + 1); likewise along y.  Every dual-grid
+ * array at the boundary (set_state, get_state, debug_stage) has that shape.
  */
 #ifndef FDCGKS_H
 #define FDCGKS_H
@@ -52,7 +58,20 @@ typedef enum {
   FDCGKS_ESTATE = -5    /* call out of order (e.g. step before set_state) */
 } fdcgks_status;
 
-enum { FDCGKS_BC_PERIODIC = 0, FDCGKS_BC_ZERO_GRADIENT = 1 };
+/* Boundary conditions (the paper uses walls and outflow sides in Sec. 5
+ * without defining their ghost nodes; this is the library's reading):
+ *   PERIODIC: periodic images (both sides of an axis);
+ *   ZERO_GRADIENT: ghosts copy the end node of their grid, with the
+ *     derivative normal to the side set to zero;
+ *   REFLECTING: slip wall / symmetry plane: ghosts are the mirror image about
+ *     the side, the normal momentum odd, the other components even, and a
+ *     derivative normal to the side of the opposite parity to its component;
+ *     dual nodes on the side keep zero normal momentum and zero derivative of
+ *     it along the side;
+ *   NO_SLIP: adiabatic no-slip wall (2D): as REFLECTING with both momenta
+ *     odd, and both momenta (and their derivatives along the side) zero at
+ *     the dual nodes on the side. */
+enum { FDCGKS_BC_PERIODIC = 0, FDCGKS_BC_ZERO_GRADIENT = 1, FDCGKS_BC_REFLECTING = 2, FDCGKS_BC_NO_SLIP = 3 };
 /* Numerical flux: (6-4) = Eq. fd-conservative-flux-2 with its low-order term
  * divided by 6; (6-2) = Eq. fd-conservative-flux-1; LINEAR = linear compact
  * flux and linear reconstruction (no GENO). */
@@ -75,13 +94,15 @@ enum { FDCGKS_RECON_CONSERVATIVE = 0, FDCGKS_RECON_CHARACTERISTIC = 1 };
 typedef struct fdcgks_params {
   int32_t dim;            /* 1 or 2 */
   int32_t nx, ny;         /* primary nodes per axis (ny = 1 in 1D); 2D needs nx, ny >= 4 */
-  int32_t bc;             /* FDCGKS_BC_*: 1D periodic or zero-gradient; 2D periodic only */
+  int32_t bc;             /* FDCGKS_BC_*: 1D both ends (not NO_SLIP); 2D every side not set in `side` */
   int32_t dual_1d;        /* 1D: also advance the shifted copy (grid 1) */
   int32_t flux_variant;   /* FDCGKS_FLUX_* */
   int32_t flux_precision; /* FDCGKS_FP64 | FDCGKS_FP32_FLUX */
   int32_t grad_update;    /* FDCGKS_GRAD_* */
   int32_t geno_r;         /* exponent r of the GENO smoothness ratio, 1..8 (default 3) */
   int32_t recon_vars;     /* FDCGKS_RECON_* (default conservative) */
+  int32_t side[4];        /* 2D: FDCGKS_BC_* of the x-low, x-high, y-low, y-high sides, -1 = bc (default);
+                             a periodic side needs a periodic opposite side */
   double x0, lx, y0, ly;  /* domain origin and lengths; 2D needs lx/nx == ly/ny */
   double gamma;           /* ratio of specific heats, > 1 and < 5/3 (2D) or < 3 (1D) */
   double mu;              /* dynamic viscosity; 0 = Euler */
@@ -154,8 +175,9 @@ const char* fdcgks_last_error(const fdcgks_problem* pb);
  * One stage without committing it, for stage-level comparison.  Stage 1
  * starts from the current state, stage 2 from the internal stage-1 buffers
  * left by the previous fdcgks_debug_stage(.., 1, ..) call, with the same dt.
- * Host outputs: out_state[grid][12][ny][nx] (2D; 1D: [grid][6][nx]) holds the
- * stage result (W*, grad W* after stage 1; W^{n+1}, grad W^{n+1} after stage
+ * Host outputs: out_state[grid][12][ny][nx] (2D; 1D: [grid][6][nx]; with
+ * bounded axes the dual grid's planes have their own size, see above) holds
+ * the stage result (W*, grad W* after stage 1; W^{n+1}, grad W^{n+1} after stage
  * 2); out_acc (stage 1 only, may be NULL) the accumulators
  * W + dt L + dt^2/6 L_t and the base gradient.  Grids not present are not
  * written. */
@@ -220,8 +242,9 @@ fdcgks_status fdcgks_autotune(fdcgks_problem* pb, int32_t reps);
  * step map at the current state.  The state is not advanced (the step is
  * recomputed internally; the next-state buffer is used as scratch).
  * Non-smooth points take fixed one-sided derivatives: |x| has derivative 0
- * at 0 and min/max ties select the first argument.  2D with FP64 fluxes only
- * (EINVAL otherwise); ENONPHYS if the recomputed step is non-physical.
+ * at 0 and min/max ties select the first argument.  2D periodic problems with
+ * FP64 fluxes and conservative reconstruction only (EINVAL otherwise);
+ * ENONPHYS if the recomputed step is non-physical.
  * on_device: both arrays are device pointers (1) or host pointers (0).
  * The first call allocates an adjoint workspace of about 410 planes of
  * (nx + 16) x (ny + 6) doubles, kept until fdcgks_destroy.  Calls on one
@@ -245,8 +268,9 @@ typedef struct fdcgks_batch fdcgks_batch; /* opaque, owned by the library */
  * results. */
 enum { FDCGKS_BATCH_PERSISTENT = 0, FDCGKS_BATCH_PHASED = 1 };
 
-/* params[count]: every member 2D periodic; members may differ only in nx, ny,
- * x0, lx, y0, ly.  Allocates all device memory on the current device. */
+/* params[count]: every member 2D periodic with conservative reconstruction
+ * (EINVAL otherwise); members may differ only in nx, ny, x0, lx, y0, ly.
+ * Allocates all device memory on the current device. */
 fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, void* hip_stream, fdcgks_batch** out);
 fdcgks_status fdcgks_batch_set_state(fdcgks_batch* b, int32_t member, int32_t grid, const double* W,
                                      const double* Wx, const double* Wy, int32_t on_device);

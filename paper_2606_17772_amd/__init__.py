@@ -17,13 +17,14 @@ import ctypes as C
 import numpy as np
 
 from . import _lib
-from ._lib import (BC_PERIODIC, BC_ZERO_GRADIENT, FLUX_6_2, FLUX_6_4, FLUX_LINEAR, FP32_FLUX, FP64,  # noqa: F401
+from ._lib import (BC_NO_SLIP, BC_PERIODIC, BC_REFLECTING, BC_ZERO_GRADIENT, FLUX_6_2, FLUX_6_4, FLUX_LINEAR, FP32_FLUX, FP64,  # noqa: F401
                    GRAD_CARRIED, GRAD_REEVAL, RECON_CHARACTERISTIC, RECON_CONSERVATIVE, FdcgksError, Params)
 
 __all__ = ["Problem", "Batch", "Params", "FdcgksError", "default_params", "make_params"]
 
 _VARIANTS = {"6-4": FLUX_6_4, "6-2": FLUX_6_2, "linear": FLUX_LINEAR}
-_BCS = {"periodic": BC_PERIODIC, "zero_gradient": BC_ZERO_GRADIENT}
+_BCS = {"periodic": BC_PERIODIC, "zero_gradient": BC_ZERO_GRADIENT, "reflecting": BC_REFLECTING,
+        "no_slip": BC_NO_SLIP}
 _RECON = {"conservative": RECON_CONSERVATIVE, "characteristic": RECON_CHARACTERISTIC}
 
 
@@ -35,7 +36,8 @@ def default_params() -> Params:
 
 def make_params(**kw) -> Params:
     """fdcgks_params from keywords (names of the C struct; also
-    variant='6-4'|'6-2'|'linear', bc='periodic'|'zero_gradient',
+    variant='6-4'|'6-2'|'linear', bc='periodic'|'zero_gradient'|'reflecting'|
+    'no_slip', sides=(x-low, x-high, y-low, y-high) boundary names or codes,
     recon_vars='conservative'|'characteristic', fp32_flux=bool)."""
     p = default_params()
     kw = dict(kw)
@@ -44,6 +46,9 @@ def make_params(**kw) -> Params:
         p.flux_variant = _VARIANTS[v] if isinstance(v, str) else int(v)
     if "bc" in kw and isinstance(kw["bc"], str):
         kw["bc"] = _BCS[kw["bc"]]
+    sides = kw.pop("sides", None)
+    if sides is not None:
+        p.side[:] = [_BCS[b] if isinstance(b, str) else int(b) for b in sides]
     if "recon_vars" in kw and isinstance(kw["recon_vars"], str):
         kw["recon_vars"] = _RECON[kw["recon_vars"]]
     if kw.pop("fp32_flux", False):
@@ -103,6 +108,17 @@ class Problem:
         self.ncomp = 4 if p.dim == 2 else 3
         self.ngrid = 2 if (p.dim == 2 or p.dual_1d) else 1
         self.shape = (self.ncomp, p.ny, p.nx)
+        # along a bounded 2D axis the dual grid has a node on each side
+        side = [p.side[k] if p.side[k] >= 0 else p.bc for k in range(4)]
+        self.bounded = (p.dim == 2 and side[0] != BC_PERIODIC, p.dim == 2 and side[2] != BC_PERIODIC)
+
+    def grid_dims(self, grid):
+        """(ny, nx) of the nodes of `grid`."""
+        p = self.params
+        return (p.ny + (grid == 1 and self.bounded[1]), p.nx + (grid == 1 and self.bounded[0]))
+
+    def grid_shape(self, grid):
+        return (self.ncomp,) + self.grid_dims(grid)
 
     # -- lifetime
     def close(self):
@@ -132,25 +148,28 @@ class Problem:
         py, dev3, k3 = _ptr(Wy) if Wy is not None else (C.c_void_p(None), dev, None)
         if len({dev, dev2, dev3}) != 1:
             raise TypeError("W, Wx, Wy must all live on the host or all on the device")
+        shape = self.grid_shape(grid)
         for a in (W, Wx) + ((Wy,) if Wy is not None else ()):
-            if tuple(a.shape) not in (self.shape, (self.ncomp * self.params.ny * self.params.nx,)):
-                raise ValueError(f"state arrays must have shape {self.shape}")
+            if tuple(a.shape) not in (shape, (int(np.prod(shape)),)):
+                raise ValueError(f"state arrays of grid {grid} must have shape {shape}")
         self._chk(self._L.fdcgks_set_state(self._h, grid, pw, px, py, dev))
 
     def set_state_stacked(self, grid, S):
-        """S: (12, ny, nx) (2D) or (6, N) (1D) stacked W, Wx[, Wy]."""
+        """S: (12, ny, nx) (2D; the dual grid's own size along bounded axes) or
+        (6, N) (1D) stacked W, Wx[, Wy]."""
         n = self.ncomp
-        S = np.ascontiguousarray(S, dtype=np.float64).reshape(-1, self.params.ny, self.params.nx)
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape((-1,) + self.grid_dims(grid))
         self.set_state(grid, np.ascontiguousarray(S[:n]), np.ascontiguousarray(S[n:2 * n]),
                        np.ascontiguousarray(S[2 * n:3 * n]) if self.params.dim == 2 else None)
 
     def get_state(self, grid, device=None):
         """Returns (W, Wx, Wy) as numpy (device=None) or torch tensors on `device`."""
+        shape = self.grid_shape(grid)
         if device is None:
-            out = [np.empty(self.shape) for _ in range(3 if self.params.dim == 2 else 2)]
+            out = [np.empty(shape) for _ in range(3 if self.params.dim == 2 else 2)]
         else:
             torch = _torch()
-            out = [torch.empty(self.shape, dtype=torch.float64, device=device)
+            out = [torch.empty(shape, dtype=torch.float64, device=device)
                    for _ in range(3 if self.params.dim == 2 else 2)]
         ptrs = [_ptr(a, True) for a in out]
         py = ptrs[2][0] if len(ptrs) == 3 else C.c_void_p(None)
@@ -162,7 +181,10 @@ class Problem:
 
     def set_state_all(self, S):
         """S: (ngrid, 12, ny, nx) (2D) stacked W, Wx, Wy of every grid, as a
-        contiguous float64 numpy array or torch tensor (host or device)."""
+        contiguous float64 numpy array or torch tensor (host or device);
+        both grids must have the same size (no bounded axis)."""
+        if any(self.bounded):
+            raise ValueError("grids differ in size along bounded axes: use set_state per grid")
         n = self.ncomp
         for g in range(self.ngrid):
             if self.params.dim == 2:
@@ -172,6 +194,8 @@ class Problem:
 
     def get_state_all(self, device=None):
         """(ngrid, 3*ncomp, ny, nx) as numpy (device=None) or a torch tensor on `device`."""
+        if any(self.bounded):
+            raise ValueError("grids differ in size along bounded axes: use get_state per grid")
         parts = [self.get_state(g, device) for g in range(self.ngrid)]
         if device is None:
             return np.stack([np.concatenate(p, axis=0) for p in parts])
@@ -272,13 +296,23 @@ class Problem:
 
     # -- diagnostics
     def debug_stage(self, stage, dt):
+        """One stage without committing it: (state, accumulators) for stage 1,
+        state for stage 2.  Each is an (ngrid, nf, ny, nx) array, or with
+        bounded axes a tuple of one (nf, ny_g, nx_g) array per grid."""
         p = self.params
         nf = 12 if p.dim == 2 else 6
-        out = np.zeros((self.ngrid, nf, p.ny, p.nx))
+        sizes = [nf * int(np.prod(self.grid_dims(g))) for g in range(self.ngrid)]
+        out = np.zeros(sum(sizes))
         acc = np.zeros_like(out)
         self._chk(self._L.fdcgks_debug_stage(self._h, stage, dt, C.c_void_p(out.ctypes.data),
                                              C.c_void_p(acc.ctypes.data)))
-        return (out, acc) if stage == 1 else out
+
+        def split(a):
+            if not any(self.bounded):
+                return a.reshape(self.ngrid, nf, p.ny, p.nx)
+            parts = np.split(a, np.cumsum(sizes)[:-1])
+            return tuple(q.reshape((nf,) + self.grid_dims(g)) for g, q in enumerate(parts))
+        return (split(out), split(acc)) if stage == 1 else split(out)
 
     def debug_intermediates(self, dt):
         p = self.params

@@ -14,7 +14,7 @@ LIB_PATH = os.environ.get("FDCGKS_LIB") or os.path.join(HERE, "libfdcgks.so")
 
 OK, EINVAL, ENOMEM, EHIP, ENONPHYS, ESTATE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENONPHYS", -5: "ESTATE"}
-BC_PERIODIC, BC_ZERO_GRADIENT = 0, 1
+BC_PERIODIC, BC_ZERO_GRADIENT, BC_REFLECTING, BC_NO_SLIP = 0, 1, 2, 3
 FLUX_6_4, FLUX_6_2, FLUX_LINEAR = 0, 1, 2
 FP64, FP32_FLUX = 0, 1
 GRAD_REEVAL, GRAD_CARRIED = 0, 1
@@ -29,6 +29,7 @@ class Params(C.Structure):
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32),
         ("dual_1d", C.c_int32), ("flux_variant", C.c_int32), ("flux_precision", C.c_int32),
         ("grad_update", C.c_int32), ("geno_r", C.c_int32), ("recon_vars", C.c_int32),
+        ("side", C.c_int32 * 4),
         ("x0", C.c_double), ("lx", C.c_double), ("y0", C.c_double), ("ly", C.c_double),
         ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
         ("geno_C", C.c_double), ("geno_eps", C.c_double), ("geno_eps_a", C.c_double),

@@ -20,6 +20,10 @@ FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fused only within one source expression: the rounding of
+    # the inlined stage code then does not depend on the kernel it sits in
+    # (single problems, batches, fused and separate sweeps agree bit for bit)
+    "-ffp-contract=on",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -39,10 +39,18 @@ namespace {
 
 constexpr int OX = 8, OY = 3, HALO = 3;
 
+// Bounded axes: along an axis whose sides are not periodic the dual grid has
+// nx + 1 (ny + 1) nodes, the first and last on the boundary lines.  Kernels
+// index dual nodes as on a periodic grid, i in [-1, nx - 1] there, and reach
+// the dual planes through `dshift` = sx + sy * pitch (stored dual node 0 is
+// kernel node -1).  side: x-low, x-high, y-low, y-high (FDCGKS_BC_*).
 struct Geo {
   int nx, ny, pitch, rows;
   long plane;
   double h, invh;
+  int sx = 0, sy = 0;
+  long dshift = 0;
+  int side[4] = {0, 0, 0, 0};
 };
 __device__ __forceinline__ long at(const Geo& g, int j, int i) { return (long)(j + OY) * g.pitch + (i + OX); }
 
@@ -58,32 +66,79 @@ struct Scal {
 __device__ __forceinline__ int imod(int a, int m) { return ((a % m) + m) % m; }
 
 // ------------------------------------------------------------ halo fill
-// Periodic images: rows first (interior columns), then whole columns.
+// Ghost index a along an axis of n real nodes of one grid: the node it copies
+// and the factor.  Periodic: the periodic image.  Zero-gradient: the end node,
+// the derivative normal to the side zeroed.  Reflecting / no-slip: the mirror
+// image about the boundary line, which lies half a mesh beyond the end node
+// (primary) or through it (dual, on_line); the normal momentum is odd
+// (no-slip: both momenta) and a derivative normal to the side has the
+// opposite parity of its component.
+__device__ __forceinline__ int ghost_src(int a, int n, int lo, int hi, bool on_line, bool normal_deriv, bool odd_refl,
+                                         bool odd_noslip, double& fac) {
+  fac = 1.0;
+  if (lo == FDCGKS_BC_PERIODIC) return imod(a, n);
+  const int type = a < 0 ? lo : hi;
+  if (type == FDCGKS_BC_ZERO_GRADIENT) {
+    if (normal_deriv) fac = 0.0;
+    return a < 0 ? 0 : n - 1;
+  }
+  const bool odd = type == FDCGKS_BC_NO_SLIP ? odd_noslip : odd_refl;
+  fac = odd != normal_deriv ? -1.0 : 1.0;
+  if (on_line) return a < 0 ? -a : 2 * (n - 1) - a;
+  return a < 0 ? -1 - a : 2 * n - 1 - a;
+}
+
+// Plane p of the 2D state (grid * 12 + field * 4 + comp), in stored node
+// coordinates: rows first (real columns), then whole columns.
+struct PlaneInfo {
+  int mx, my, field, comp;
+  bool dual;
+};
+__device__ __forceinline__ PlaneInfo plane_info(const Geo& g, int p) {
+  PlaneInfo q;
+  q.dual = p >= 12;
+  q.field = (p % 12) / 4;
+  q.comp = p % 4;
+  q.mx = g.nx + (q.dual ? g.sx : 0);
+  q.my = g.ny + (q.dual ? g.sy : 0);
+  return q;
+}
 __global__ void k_halo_rows(double* __restrict__ S, int nplanes, Geo g, const Scal* __restrict__ sc) {
   if (sc->stop) return;
-  long n = (long)nplanes * 2 * HALO * g.nx;
+  const int W = g.nx + g.sx;
+  long n = (long)nplanes * 2 * HALO * W;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    int i = (int)(t % g.nx);
-    long r = t / g.nx;
+    int i = (int)(t % W);
+    long r = t / W;
     int hr = (int)(r % (2 * HALO));
     int p = (int)(r / (2 * HALO));
-    int j = hr < HALO ? hr - HALO : g.ny + (hr - HALO);
+    const PlaneInfo q = plane_info(g, p);
+    if (i >= q.mx) continue;
+    int j = hr < HALO ? hr - HALO : q.my + (hr - HALO);
+    double fac;
+    int js = ghost_src(j, q.my, g.side[2], g.side[3], q.dual && g.sy, q.field == 2, q.comp == 2,
+                       q.comp == 1 || q.comp == 2, fac);
     double* P = S + p * g.plane;
-    P[at(g, j, i)] = P[at(g, imod(j, g.ny), i)];
+    P[at(g, j, i)] = fac * P[at(g, js, i)];
   }
 }
 __global__ void k_halo_cols(double* __restrict__ S, int nplanes, Geo g, const Scal* __restrict__ sc) {
   if (sc->stop) return;
-  int rows = g.ny + 2 * HALO;
+  int rows = g.ny + g.sy + 2 * HALO;
   long n = (long)nplanes * rows * 2 * HALO;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
     int hc = (int)(t % (2 * HALO));
     long r = t / (2 * HALO);
     int j = (int)(r % rows) - HALO;
     int p = (int)(r / rows);
-    int i = hc < HALO ? hc - HALO : g.nx + (hc - HALO);
+    const PlaneInfo q = plane_info(g, p);
+    if (j >= q.my + HALO) continue;
+    int i = hc < HALO ? hc - HALO : q.mx + (hc - HALO);
+    double fac;
+    int is = ghost_src(i, q.mx, g.side[0], g.side[1], q.dual && g.sx, q.field == 1, q.comp == 1,
+                       q.comp == 1 || q.comp == 2, fac);
     double* P = S + p * g.plane;
-    P[at(g, j, i)] = P[at(g, j, imod(i, g.nx))];
+    P[at(g, j, i)] = fac * P[at(g, j, is)];
   }
 }
 
@@ -132,7 +187,7 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
   constexpr bool ALONG_Y = (FAM ^ G) != 0;
   constexpr int back = G == 0 ? 1 : 2;
   const long st = ALONG_Y ? g.pitch : 1;
-  const long o = ALONG_Y ? at(g, j - back, i) : at(g, j, i - back);
+  const long o = (ALONG_Y ? at(g, j - back, i) : at(g, j, i - back)) + (G ? g.dshift : 0);
   constexpr int f = ALONG_Y ? 2 : 1;  // derivative field along the line
   const long pl = g.plane;
   if constexpr (CHAR) {
@@ -168,11 +223,12 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
 // One thread per (interface point, normal): blockDim (TX, TY) with TX a
 // multiple of 64 or 32 and TY even, threadIdx.y = 2 * row + G, so the two
 // solves of one point sit in neighbouring rows of threads (with TX >= 64,
-// neighbouring waves).  fam: X covers i in [-2, nx], j in [-1, ny+1]; Y
-// covers i in [-1, nx+1], j in [-2, ny] (everything the update of the
-// interior reads); block (bx, by) covers TX points in i and TY/2 in j.  The
-// partners exchange tangential slopes and blend sums through LDS.  Every
-// thread of the block must call this.
+// neighbouring waves).  fam: X covers i in [-2, nx], j in [-1 - sy, ny+1]; Y
+// covers i in [-1 - sx, nx+1], j in [-2, ny] (everything the update of the
+// nodes reads, the dual boundary nodes of bounded axes included); block
+// (bx, by) covers TX points in i and TY/2 in j.  The partners exchange
+// tangential slopes and blend sums through LDS.  Every thread of the block
+// must call this.
 template <int STAGE, class FT, bool CHAR = false>
 __device__ __forceinline__ void edge_block(const double* __restrict__ S, double* __restrict__ E, const Geo& g,
                                            const Consts& k, double dt, int bx, int by, int fam) {
@@ -181,8 +237,8 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
   const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
   const int TX = blockDim.x, TY = blockDim.y;
 #define XCH(c, r) xch[((c) * TY + (r)) * TX + tx]
-  const int i = bx * TX + tx + (fam == 0 ? -2 : -1);
-  const int j = by * (TY >> 1) + (ty >> 1) + (fam == 0 ? -1 : -2);
+  const int i = bx * TX + tx + (fam == 0 ? -2 : -1 - g.sx);
+  const int j = by * (TY >> 1) + (ty >> 1) + (fam == 0 ? -1 - g.sy : -2);
   const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
   fdk::IfaceRec rec[4];
   if (valid) {
@@ -298,16 +354,16 @@ __device__ __forceinline__ void node_derivs(const double* __restrict__ B, const 
   }
 }
 
-// Nodes i in [-1, nx], j in [-1, ny] of grid `grid`; block (bx, by) of
-// blockDim.x x blockDim.y nodes.
+// Nodes i in [-1 - sx, nx], j in [-1 - sy, ny] of grid `grid`; block (bx, by)
+// of blockDim.x x blockDim.y nodes.
 template <int STAGE, class FT, bool CHAR = false>
 __device__ __forceinline__ void node_block(const double* __restrict__ S, double* __restrict__ Nb, const Geo& g,
                                            const Consts& k, int bx, int by, int grid) {
-  const int i = bx * blockDim.x + threadIdx.x - 1;
-  const int j = by * blockDim.y + threadIdx.y - 1;
+  const int i = bx * blockDim.x + threadIdx.x - 1 - g.sx;
+  const int j = by * blockDim.y + threadIdx.y - 1 - g.sy;
   if (i > g.nx || j > g.ny) return;
   const long pl = g.plane, o = at(g, j, i);
-  const double* B = S + (long)grid * 12 * pl;
+  const double* B = S + (long)grid * 12 * pl + (grid ? g.dshift : 0);
   FT W[4], Wx[4], Wy[4];
 #pragma unroll
   for (int c = 0; c < 4; ++c) W[c] = (FT)B[c * pl + o];
@@ -377,11 +433,12 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
       Grt[a][c] = (e[(17 + c) * pl + r * st] - e[(21 + c) * pl + (r - 1) * st]) * g.invh;
     }
   }
-  const double* s = S + (long)grid * 12 * pl + o;
-  double* out = Out + (long)grid * 12 * pl + o;
+  const long so = o + (grid ? g.dshift : 0);  // the dual planes are shifted along bounded axes
+  const double* s = S + (long)grid * 12 * pl + so;
+  double* out = Out + (long)grid * 12 * pl + so;
   double W[4];
   if (STAGE == 1) {
-    double* ao = Aout + (long)grid * 12 * pl + o;
+    double* ao = Aout + (long)grid * 12 * pl + so;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       double w = s[c * pl];
@@ -396,13 +453,34 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
       ao[(8 + c) * pl] = gy;
     }
   } else {
-    const double* ai = Ain + (long)grid * 12 * pl + o;
+    const double* ai = Ain + (long)grid * 12 * pl + so;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       W[c] = ai[c * pl] + dt * dt / 3.0 * Lt[c];
       out[c * pl] = W[c];
       out[(4 + c) * pl] = ai[(4 + c) * pl] + dt * Grt[0][c];
       out[(8 + c) * pl] = ai[(8 + c) * pl] + dt * Grt[1][c];
+    }
+  }
+  // dual nodes on a reflecting / no-slip side carry the wall condition: the
+  // normal momentum (no-slip: both momenta) and its derivative along the wall
+  // are zero
+  if (grid == 1 && (g.sx | g.sy)) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const bool bnd = a == 0 ? g.sx != 0 : g.sy != 0;
+      const int pos = a == 0 ? i : j, n = a == 0 ? g.nx : g.ny;
+      const int type = !bnd ? FDCGKS_BC_PERIODIC
+                            : (pos == -1 ? g.side[2 * a] : (pos == n - 1 ? g.side[2 * a + 1] : FDCGKS_BC_PERIODIC));
+      if (type != FDCGKS_BC_REFLECTING && type != FDCGKS_BC_NO_SLIP) continue;
+      const int along = 2 - a;  // field of the derivative along the wall
+#pragma unroll
+      for (int c = 1; c <= 2; ++c) {
+        if (type == FDCGKS_BC_REFLECTING && c != 1 + a) continue;
+        W[c] = 0.0;
+        out[c * pl] = 0.0;
+        out[(4 * along + c) * pl] = 0.0;
+      }
     }
   }
   // non-physical state: rho <= 0, p <= 0 or NaN stops the run
@@ -426,15 +504,16 @@ struct NodeFluxGlobal {
   }
 };
 
-// Block (bx, by) of blockDim.x x blockDim.y interior nodes.
+// Block (bx, by) of blockDim.x x blockDim.y nodes; the dual grid starts at
+// i = -sx, j = -sy (its boundary nodes on bounded axes).
 template <int STAGE>
 __device__ __forceinline__ void update_block(const double* __restrict__ S, const double* __restrict__ E,
                                              const double* __restrict__ Nb, const double* __restrict__ Ain,
                                              double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
                                              const Consts& k, double dt, int bx, int by, int grid, Scal* sc,
                                              int member) {
-  const int i = bx * blockDim.x + threadIdx.x;
-  const int j = by * blockDim.y + threadIdx.y;
+  const int i = bx * blockDim.x + threadIdx.x - (grid ? g.sx : 0);
+  const int j = by * blockDim.y + threadIdx.y - (grid ? g.sy : 0);
   if (i >= g.nx || j >= g.ny) return;
   const NodeFluxGlobal nf{Nb + (long)grid * 16 * g.plane + at(g, j, i), g.plane, g.pitch};
   update_node<STAGE>(S, E, nf, Ain, Out, Aout, g, k, dt, i, j, grid, sc, member);
@@ -527,16 +606,19 @@ __global__ __launch_bounds__(256) void k_update2d(const double* __restrict__ S, 
 // interface and node results stay in global memory (cache resident at these
 // sizes).
 
-// ghost cells: periodic, or zero-gradient (copy W, zero derivative)
+// ghost cells: periodic, zero-gradient (copy W, zero derivative) or
+// reflecting (mirror about the face half a mesh beyond the end node: the
+// momentum and the other components' derivatives odd)
 __device__ __forceinline__ void halo1d(double* __restrict__ S, const Geo& g, int lines, int bc) {
   const long pl = g.plane;
   for (int q = threadIdx.x; q < lines * 6 * 2 * HALO; q += blockDim.x) {
     int gh = q % (2 * HALO), p = q / (2 * HALO);
-    int f = (p % 6) / 3;
+    int f = (p % 6) / 3, c = (p % 6) % 3;
     int i = gh < HALO ? gh - HALO : g.nx + (gh - HALO);
     double* P = S + p * pl;
-    if (bc == FDCGKS_BC_PERIODIC) P[at(g, 0, i)] = P[at(g, 0, imod(i, g.nx))];
-    else P[at(g, 0, i)] = f == 0 ? P[at(g, 0, i < 0 ? 0 : g.nx - 1)] : 0.0;
+    double fac;
+    const int src = ghost_src(i, g.nx, bc, bc, false, f == 1, c == 1, c == 1, fac);
+    P[at(g, 0, i)] = fac * P[at(g, 0, src)];
   }
 }
 
@@ -775,13 +857,16 @@ __global__ __launch_bounds__(256) void k_cfl_partial(const double* __restrict__ 
                                                      const Scal* __restrict__ sc) {
   __shared__ double smax[256], smin[256];
   double vmax = 0.0, rmin = 1e300;
-  long n = (long)ngrid * g.nx * g.ny;
+  // stored nodes; the dual grid has one more column (row) along a bounded axis
+  const int W = g.nx + g.sx, H = g.ny + g.sy;
+  long n = (long)ngrid * W * H;
   constexpr int NC = DIM + 2;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    int i = (int)(t % g.nx);
-    long r = t / g.nx;
-    int j = (int)(r % g.ny);
-    int gr = (int)(r / g.ny);
+    int i = (int)(t % W);
+    long r = t / W;
+    int j = (int)(r % H);
+    int gr = (int)(r / H);
+    if (gr == 0 && (i >= g.nx || j >= g.ny)) continue;
     const double* B = S + gr * gridstride + at(g, j, i);
     double rho = B[0], U = B[g.plane] / rho;
     double V = DIM == 2 ? B[2 * g.plane] / rho : 0.0;
@@ -1190,7 +1275,8 @@ fdcgks_status launch_check(fdcgks_problem* pb, const char* what) {
 // ---- 2D stage sequence
 fdcgks_status halo2d(fdcgks_problem* pb, double* S) {
   const Geo& g = pb->g;
-  long nr = (long)pb->nplanes * 2 * HALO * g.nx, nc = (long)pb->nplanes * (g.ny + 2 * HALO) * 2 * HALO;
+  long nr = (long)pb->nplanes * 2 * HALO * (g.nx + g.sx);
+  long nc = (long)pb->nplanes * (g.ny + g.sy + 2 * HALO) * 2 * HALO;
   hipLaunchKernelGGL(k_halo_rows, dim3(std::min(ceil_div(nr, 256), 4096)), dim3(256), 0, pb->stream, S,
                      pb->nplanes, g, pb->sc);
   hipLaunchKernelGGL(k_halo_cols, dim3(std::min(ceil_div(nc, 256), 4096)), dim3(256), 0, pb->stream, S,
@@ -1203,7 +1289,7 @@ fdcgks_status halo2d(fdcgks_problem* pb, double* S) {
 template <int STAGE>
 void launch_edges(fdcgks_problem* pb, const double* Sin, dim3 blk) {
   const Geo& g = pb->g;
-  dim3 ge(ceil_div(g.nx + 3, blk.x), ceil_div(g.ny + 3, blk.y / 2), 2);
+  dim3 ge(ceil_div(g.nx + 3 + g.sx, blk.x), ceil_div(g.ny + 3 + g.sy, blk.y / 2), 2);
   const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
   const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
   auto fn = f32 ? (ch ? k_edges2d<STAGE, float, true> : k_edges2d<STAGE, float, false>)
@@ -1213,7 +1299,7 @@ void launch_edges(fdcgks_problem* pb, const double* Sin, dim3 blk) {
 template <int STAGE>
 void launch_nodes(fdcgks_problem* pb, const double* Sin, dim3 blk) {
   const Geo& g = pb->g;
-  dim3 gn(ceil_div(g.nx + 2, blk.x), ceil_div(g.ny + 2, blk.y), 2);
+  dim3 gn(ceil_div(g.nx + 2 + g.sx, blk.x), ceil_div(g.ny + 2 + g.sy, blk.y), 2);
   const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
   const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
   auto fn = f32 ? (ch ? k_nodes2d<STAGE, float, true> : k_nodes2d<STAGE, float, false>)
@@ -1223,13 +1309,14 @@ void launch_nodes(fdcgks_problem* pb, const double* Sin, dim3 blk) {
 template <int STAGE>
 void launch_update(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout, dim3 blk) {
   const Geo& g = pb->g;
-  dim3 gu(ceil_div(g.nx, blk.x), ceil_div(g.ny, blk.y), 2);
+  dim3 gu(ceil_div(g.nx + g.sx, blk.x), ceil_div(g.ny + g.sy, blk.y), 2);
   hipLaunchKernelGGL((k_update2d<STAGE>), gu, blk, 0, pb->stream, Sin, pb->E, pb->Nb, Ain, Out, Aout, g, pb->k,
                      pb->sc);
 }
 
 // One stage.  fused: the node sweep runs inside the update kernel and the
-// node buffer is not written (callers that read it pass false).
+// node buffer is not written (callers that read it pass false); periodic
+// problems only (bounded axes take the separate kernels).
 template <int STAGE>
 fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout,
                       bool fused) {
@@ -1238,7 +1325,7 @@ fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, 
   if (st) return st;
   launch_edges<STAGE>(pb, Sin, pb->tile[0]);
   mark(pb, STAGE == 1 ? TK_EDGE1 : TK_EDGE2);
-  if (fused) {
+  if (fused && !(g.sx | g.sy)) {
     dim3 gu(ceil_div(g.nx, 64), ceil_div(g.ny, 4), 2);
     const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
     const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
@@ -1369,6 +1456,9 @@ float time_tile(fdcgks_problem* pb, int c, dim3 blk, int reps, hipEvent_t e0, hi
   return ms;
 }
 
+// Boundary of 2D side k (x-low, x-high, y-low, y-high): its own entry, or bc.
+int side_bc(const fdcgks_params& p, int k) { return p.side[k] >= 0 ? p.side[k] : p.bc; }
+
 fdcgks_status check_params(const fdcgks_params* p) {
   if (!p) return fail(nullptr, FDCGKS_EINVAL, "params is NULL");
   if (p->dim != 1 && p->dim != 2) return fail(nullptr, FDCGKS_EINVAL, "dim must be 1 or 2 (got %d)", p->dim);
@@ -1377,10 +1467,18 @@ fdcgks_status check_params(const fdcgks_params* p) {
   if (p->dim == 1 && (p->nx < 4 || p->ny != 1))
     return fail(nullptr, FDCGKS_EINVAL, "1D needs nx >= 4 and ny == 1 (got %d, %d)", p->nx, p->ny);
   if ((long)p->nx * p->ny > (1L << 28)) return fail(nullptr, FDCGKS_EINVAL, "grid too large");
-  if (p->dim == 2 && p->bc != FDCGKS_BC_PERIODIC)
-    return fail(nullptr, FDCGKS_EINVAL, "2D supports periodic boundaries only");
-  if (p->bc != FDCGKS_BC_PERIODIC && p->bc != FDCGKS_BC_ZERO_GRADIENT)
+  if (p->bc < FDCGKS_BC_PERIODIC || p->bc > FDCGKS_BC_NO_SLIP)
     return fail(nullptr, FDCGKS_EINVAL, "unknown boundary condition %d", p->bc);
+  if (p->dim == 1 && p->bc == FDCGKS_BC_NO_SLIP)
+    return fail(nullptr, FDCGKS_EINVAL, "1D walls are reflecting (no tangential velocity)");
+  if (p->dim == 2) {
+    for (int k = 0; k < 4; ++k)
+      if (p->side[k] < -1 || p->side[k] > FDCGKS_BC_NO_SLIP)
+        return fail(nullptr, FDCGKS_EINVAL, "unknown boundary condition %d on side %d", p->side[k], k);
+    for (int a = 0; a < 2; ++a)
+      if ((side_bc(*p, 2 * a) == FDCGKS_BC_PERIODIC) != (side_bc(*p, 2 * a + 1) == FDCGKS_BC_PERIODIC))
+        return fail(nullptr, FDCGKS_EINVAL, "a periodic side needs a periodic opposite side (axis %d)", a);
+  }
   if (!(p->lx > 0) || (p->dim == 2 && !(p->ly > 0))) return fail(nullptr, FDCGKS_EINVAL, "domain lengths must be > 0");
   if (p->dim == 2) {
     double hx = p->lx / p->nx, hy = p->ly / p->ny;
@@ -1479,6 +1577,7 @@ void fdcgks_default_params(fdcgks_params* p) {
   p->dim = 2;
   p->nx = p->ny = 64;
   p->bc = FDCGKS_BC_PERIODIC;
+  for (int k = 0; k < 4; ++k) p->side[k] = -1;
   p->flux_variant = FDCGKS_FLUX_6_4;
   p->flux_precision = FDCGKS_FP64;
   p->grad_update = FDCGKS_GRAD_REEVAL;
@@ -1507,7 +1606,13 @@ fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_pro
   g.nx = p->nx;
   g.ny = p->ny;
   g.pitch = ((p->nx + 2 * OX) + 15) / 16 * 16;
-  g.rows = p->ny + 2 * OY;
+  if (p->dim == 2) {
+    for (int k = 0; k < 4; ++k) g.side[k] = side_bc(*p, k);
+    g.sx = g.side[0] != FDCGKS_BC_PERIODIC;
+    g.sy = g.side[2] != FDCGKS_BC_PERIODIC;
+  }
+  g.rows = p->ny + 2 * OY + g.sy;  // a bounded y axis adds the dual boundary row
+  g.dshift = g.sx + (long)g.sy * g.pitch;
   g.plane = (long)g.pitch * g.rows;
   g.h = p->lx / p->nx;
   g.invh = 1.0 / g.h;
@@ -1562,23 +1667,29 @@ fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_pro
   return FDCGKS_OK;
 }
 
+// Stored nodes of a grid: the dual grid has one more column (row) along a
+// bounded axis.
+static int grid_nx(const fdcgks_problem* pb, int grid) { return pb->g.nx + (grid == 1 ? pb->g.sx : 0); }
+static int grid_ny(const fdcgks_problem* pb, int grid) { return pb->g.ny + (grid == 1 ? pb->g.sy : 0); }
+
 static fdcgks_status copy_grid(fdcgks_problem* pb, int grid, double* const* ptrs, int to_device_state,
                                int on_device) {
   const Geo& g = pb->g;
   int ncomp = pb->prm.dim == 2 ? 4 : 3;
   int nfield = pb->prm.dim == 2 ? 3 : 2;
+  const int mx = grid_nx(pb, grid), my = grid_ny(pb, grid);
   double* base = pb->S[pb->cur] + (long)grid * (pb->prm.dim == 2 ? 12 : 6) * g.plane;
-  size_t row = (size_t)g.nx * sizeof(double);
+  size_t row = (size_t)mx * sizeof(double);
   hipMemcpyKind kind = to_device_state ? (on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
                                        : (on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
   for (int f = 0; f < nfield; ++f)
     for (int c = 0; c < ncomp; ++c) {
       double* dev = base + (long)(f * (pb->prm.dim == 2 ? 4 : 3) + c) * g.plane + (long)OY * g.pitch + OX;
-      double* usr = ptrs[f] + (long)c * g.nx * g.ny;
+      double* usr = ptrs[f] + (long)c * mx * my;
       if (to_device_state)
-        HIPCHK(pb, hipMemcpy2DAsync(dev, (size_t)g.pitch * sizeof(double), usr, row, row, g.ny, kind, pb->stream));
+        HIPCHK(pb, hipMemcpy2DAsync(dev, (size_t)g.pitch * sizeof(double), usr, row, row, my, kind, pb->stream));
       else
-        HIPCHK(pb, hipMemcpy2DAsync(usr, row, dev, (size_t)g.pitch * sizeof(double), row, g.ny, kind, pb->stream));
+        HIPCHK(pb, hipMemcpy2DAsync(usr, row, dev, (size_t)g.pitch * sizeof(double), row, my, kind, pb->stream));
     }
   if (!on_device) HIPCHK(pb, hipStreamSynchronize(pb->stream));
   return FDCGKS_OK;
@@ -1744,15 +1855,20 @@ fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, d
   if (st) return st;
   const Geo& g = pb->g;
   const double* src = stage == 1 ? pb->Sstar : scratch;
-  size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
-  long n = (long)g.nx * g.ny;
-  const int nout = pb->ngrid * (pb->prm.dim == 2 ? 12 : 6);  // planes of the grids present
-  for (int p = 0; p < nout; ++p) {
-    HIPCHK(pb, hipMemcpy2DAsync(out_state + p * n, row, src + p * g.plane + (long)OY * g.pitch + OX, pitchb, row,
-                                g.ny, hipMemcpyDeviceToHost, pb->stream));
-    if (stage == 1 && out_acc)
-      HIPCHK(pb, hipMemcpy2DAsync(out_acc + p * n, row, pb->Acc + p * g.plane + (long)OY * g.pitch + OX, pitchb, row,
-                                  g.ny, hipMemcpyDeviceToHost, pb->stream));
+  size_t pitchb = (size_t)g.pitch * sizeof(double);
+  const int npg = pb->prm.dim == 2 ? 12 : 6;  // planes per grid
+  long off = 0;
+  for (int gr = 0; gr < pb->ngrid; ++gr) {
+    const int mx = grid_nx(pb, gr), my = grid_ny(pb, gr);
+    const size_t row = (size_t)mx * sizeof(double);
+    for (int q = 0; q < npg; ++q, off += (long)mx * my) {
+      const long p = (long)gr * npg + q;
+      HIPCHK(pb, hipMemcpy2DAsync(out_state + off, row, src + p * g.plane + (long)OY * g.pitch + OX, pitchb, row, my,
+                                  hipMemcpyDeviceToHost, pb->stream));
+      if (stage == 1 && out_acc)
+        HIPCHK(pb, hipMemcpy2DAsync(out_acc + off, row, pb->Acc + p * g.plane + (long)OY * g.pitch + OX, pitchb, row,
+                                    my, hipMemcpyDeviceToHost, pb->stream));
+    }
   }
   return read_scal(pb);
 }
@@ -1797,6 +1913,7 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   if (pb->prm.flux_precision != FDCGKS_FP64) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs FP64 fluxes");
   if (pb->prm.recon_vars != FDCGKS_RECON_CONSERVATIVE)
     return fail(pb, FDCGKS_EINVAL, "the step adjoint needs conservative reconstruction");
+  if (pb->g.sx | pb->g.sy) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs periodic sides");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, FDCGKS_EINVAL, "dt must be finite and > 0");
   if (!state_ready(pb)) return fail(pb, FDCGKS_ESTATE, "set_state has not been called for every grid");
   fdcgks_status st = adj_alloc(pb);
@@ -2010,6 +2127,9 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
     if (params[m].dim != 2) return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches are 2D only", m);
     if (params[m].recon_vars != FDCGKS_RECON_CONSERVATIVE)
       return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches reconstruct conservative variables only", m);
+    for (int k = 0; k < 4; ++k)
+      if (side_bc(params[m], k) != FDCGKS_BC_PERIODIC)
+        return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches are periodic only", m);
     if (!same_scheme(params[0], params[m]))
       return bfail(nullptr, FDCGKS_EINVAL, "member %d: scheme constants differ from member 0", m);
   }

@@ -30,10 +30,23 @@ def test_library_exports_every_declared_symbol():
     assert set(header_symbols()) <= set(_lib.SIGNATURES), "binding must declare every ABI symbol"
 
 
-def test_params_struct_matches_header_size():
+def test_params_struct_matches_header(tmp_path):
+    """The binding's fdcgks_params mirror has the header's size and field
+    offsets (a C program compiled against include/fdcgks.h prints them)."""
+    import subprocess
+
     from paper_2606_17772_amd import Params
-    # 10 int32 + 14 doubles, naturally aligned
-    assert C.sizeof(Params) == 10 * 4 + 14 * 8
+    names = [f[0] for f in Params._fields_]
+    src = tmp_path / "layout.c"
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fdcgks.h\"\nint main(void) {\n"
+                   '  printf("%zu\\n", sizeof(fdcgks_params));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof(fdcgks_params, {n}));\n' for n in names)
+                   + "  return 0;\n}\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert vals[0] == C.sizeof(Params)
+    assert vals[1:] == [getattr(Params, n).offset for n in names]
 
 
 def test_defaults():
@@ -47,15 +60,19 @@ def test_defaults():
 @pytest.mark.parametrize("bad", [
     dict(dim=3), dict(nx=3), dict(ny=2), dict(gamma=1.0), dict(gamma=1.7), dict(mu=-1.0),
     dict(mu=1e-3, prandtl=0.0), dict(flux_variant=7), dict(flux_precision=5), dict(geno_r=0),
-    dict(geno_eps=0.0), dict(tau_c1=-1.0), dict(bc=1), dict(lx=0.0), dict(ly=2.0), dict(recon_vars=2),
-    dict(dim=1, nx=100, ny=2), dict(grad_update=3),
+    dict(geno_eps=0.0), dict(tau_c1=-1.0), dict(bc=4), dict(bc=-1), dict(lx=0.0), dict(ly=2.0),
+    dict(recon_vars=2), dict(dim=1, nx=100, ny=2), dict(grad_update=3), dict(dim=1, nx=100, ny=1, bc=3),
+    dict(side=(0, 2, -1, -1)), dict(side=(-1, -1, 1, 0)), dict(side=(5, 5, -1, -1)), dict(bc=2, side=(0, -1, -1, -1)),
 ])
 def test_create_rejects_bad_params(bad):
     from paper_2606_17772_amd import _lib, default_params
     L = _lib.load()
     p = default_params()
     for k, v in bad.items():
-        setattr(p, k, v)
+        if k == "side":
+            p.side[:] = v
+        else:
+            setattr(p, k, v)
     h = C.c_void_p()
     st = L.fdcgks_create(C.byref(p), None, C.byref(h))
     assert st == _lib.EINVAL

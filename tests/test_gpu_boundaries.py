@@ -1,0 +1,273 @@
+"""Parity of the HIP path's non-periodic boundaries against the oracle (GPU).
+
+2D problems with bounded axes (the dual grid then carries nodes on the
+boundary lines: (ny + by, nx + bx) dual nodes) and 1D reflecting ends, on
+the same seeded inputs as the oracle.  Bars as for periodic problems:
+interface and node intermediates and both stages at the floored 1e-12 bar,
+several CFL steps at max(1e-12, 4 x the oracle's one-ulp sensitivity)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as WL
+from tests.helpers import (TOL, check_edge_intermediates, floors_edge, floors_node, floors_state, gpu_params,
+                           oracle_par, ref_scales, relerr, settings, ulp_sensitivity)
+
+pytestmark = pytest.mark.gpu
+
+
+def _case_refl_x():
+    nx, ny = 70, 37
+    h = 1.0 / nx
+    P, D = WL.sample_bounded(WL.mirror_flow(1.0, ny * h, 1, 0), nx, ny, h, 1, 0)
+    return settings(dim=2, nx=nx, ny=ny, lx=1.0, sides=["reflecting", "reflecting", "periodic", "periodic"]), P, D
+
+
+def _case_refl_all(**kw):
+    nx, ny = 67, 9
+    h = 1.0 / nx
+    P, D = WL.sample_bounded(WL.mirror_flow(1.0, ny * h, 1, 1), nx, ny, h, 1, 1)
+    return settings(dim=2, nx=nx, ny=ny, lx=1.0, bc="reflecting", **kw), P, D
+
+
+def _case_noslip_ns():
+    nx, ny = 40, 8
+    h = 1.0 / nx
+    base = WL.mirror_flow(1.0, ny * h, 1, 0)
+
+    def fn(X, Y):
+        W = base(X, Y)
+        rho = W[0]
+        U = W[1] / rho
+        V = 0.2 * np.sin(math.pi * X) * np.cos(2 * math.pi * Y / (ny * h))
+        p = 0.4 * (W[3] - 0.5 * rho * (U * U + (W[2] / rho) ** 2))
+        return WL.conservative(rho, U, V, p)
+    P, D = WL.sample_bounded(fn, nx, ny, h, 1, 0)
+    return settings(dim=2, nx=nx, ny=ny, lx=1.0, mu=1e-3, prandtl=0.72,
+                    sides=["no_slip", "no_slip", "periodic", "periodic"]), P, D
+
+
+def _case_zerograd_riemann():
+    pr = WL.riemann2d_bounded(33, seed=5)
+    return settings(dim=2, nx=33, ny=33, lx=1.0, bc="zero_gradient"), pr.P, pr.D
+
+
+def _case_mixed():
+    nx, ny = 48, 20
+    h = 1.0 / nx
+    P, D = WL.sample_bounded(WL.mirror_flow(1.0, ny * h, 1, 1), nx, ny, h, 1, 1)
+    return settings(dim=2, nx=nx, ny=ny, lx=1.0, mu=1e-3, prandtl=0.72,
+                    sides=["reflecting", "zero_gradient", "no_slip", "reflecting"]), P, D
+
+
+CASES = {
+    "reflecting_x_70x37": _case_refl_x,
+    "reflecting_all_67x9": _case_refl_all,
+    "no_slip_ns_40x8": _case_noslip_ns,
+    "zero_gradient_riemann_33": _case_zerograd_riemann,
+    "mixed_48x20": _case_mixed,
+    "reflecting_all_char_67x9": lambda: _case_refl_all(recon_vars="characteristic"),
+}
+
+
+def _problem(s, P, D):
+    from paper_2606_17772_amd import Problem
+    pb = Problem(gpu_params(s))
+    pb.set_state_stacked(0, P)
+    pb.set_state_stacked(1, D)
+    return pb
+
+
+def _floors(s, P, D):
+    return floors_state(ref_scales([P, D], s["gamma"], s["lx"]))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_intermediates_bounded(oracle, name):
+    s, P, D = CASES[name]()
+    dt = 0.2 * (s["lx"] / s["nx"]) / 3.0
+    par = oracle_par(oracle, s)
+    X, Y, NP, ND = oracle.intermediates2d(par, dt, P, D)
+    gx, gy, gp, gd = _problem(s, P, D).debug_intermediates(dt)
+    sc = ref_scales([P, D], s["gamma"], s["lx"])
+    check_edge_intermediates(oracle, par, dt, P, D, (gx, gy), (X, Y), floors_edge(sc), name)
+    for lab, g, o, fl in (("nodeP", gp, NP, floors_node(sc)), ("nodeD", gd, ND, floors_node(sc))):
+        err, where = relerr(g, o, fl)
+        assert err <= TOL, (lab, where, err)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_stages_bounded(oracle, name):
+    s, P, D = CASES[name]()
+    dt = 0.2 * (s["lx"] / s["nx"]) / 3.0
+    par = oracle_par(oracle, s)
+    oP, oD, aP, aD = oracle.stage2d(par, 1, dt, P, D)
+    o2P, o2D = oracle.stage2d(par, 2, dt, oP, oD, aP, aD)
+    pb = _problem(s, P, D)
+    assert pb.grid_shape(1)[1:] == D.shape[1:]
+    fl = _floors(s, P, D)
+    g1, ga = pb.debug_stage(1, dt)
+    for g, o in ((g1[0], oP), (g1[1], oD), (ga[0], aP), (ga[1], aD)):
+        err, where = relerr(g, o, fl)
+        assert err <= TOL, (where, err)
+    g2 = pb.debug_stage(2, dt)
+    for g, o in ((g2[0], o2P), (g2[1], o2D)):
+        err, where = relerr(g, o, fl)
+        assert err <= TOL, (where, err)
+
+
+@pytest.mark.parametrize("name,nsteps", [("reflecting_x_70x37", 3), ("no_slip_ns_40x8", 3),
+                                         ("zero_gradient_riemann_33", 2), ("mixed_48x20", 3)])
+def test_steps_bounded(oracle, name, nsteps):
+    s, P, D = CASES[name]()
+    par = oracle_par(oracle, s)
+    pb = _problem(s, P, D)
+    dt0 = oracle.dt2d(par, P, D, 0.5)
+    assert abs(pb.compute_dt(0.5) - dt0) <= 1e-14 * dt0
+    oP, oD, ot, ok = oracle.step2d(par, P, D, nsteps, cfl=0.5)
+    t, n = pb.step(nsteps=nsteps, cfl=0.5)
+    assert n == nsteps == ok and abs(t - ot) <= 1e-13 * ot
+    fl = _floors(s, P, D)
+    sens = ulp_sensitivity(lambda A, B: oracle.step2d(par, A, B, nsteps, cfl=0.5)[:2], P, D, fl)
+    for g, o in ((pb.get_state_stacked(0), oP), (pb.get_state_stacked(1), oD)):
+        err, where = relerr(g, o, fl)
+        print(f"{name} {nsteps} steps: gpu-oracle {err:.2e}, oracle 1-ulp sensitivity {sens:.2e}")
+        assert err <= max(TOL, 4 * sens), (where, err, sens)
+
+
+def test_captured_steps_bounded(oracle):
+    """Graph replays of bounded problems equal eager steps bit for bit, and
+    the fused node option falls back to the separate kernels."""
+    s, P, D = CASES["mixed_48x20"]()
+    a = _problem(s, P, D)
+    a.use_graph = False
+    a.step(nsteps=5, cfl=0.5)
+    b = _problem(s, P, D)
+    b.graph_steps = 4
+    b.fuse_nodes = True
+    b.step(nsteps=5, cfl=0.5)
+    for g in (0, 1):
+        assert np.array_equal(a.get_state_stacked(g), b.get_state_stacked(g))
+
+
+def test_wall_nodes_hold_the_wall_condition(oracle):
+    s, P, D = CASES["no_slip_ns_40x8"]()
+    pb = _problem(s, P, D)
+    pb.step(nsteps=3, cfl=0.5)
+    Dg = pb.get_state_stacked(1)
+    for col in (0, s["nx"]):
+        assert np.all(Dg[1:3, :, col] == 0.0) and np.all(Dg[9:11, :, col] == 0.0)
+
+
+def test_bounded_rejected_by_adjoint_and_batch():
+    from paper_2606_17772_amd import Batch, FdcgksError
+    s, P, D = CASES["reflecting_x_70x37"]()
+    pb = _problem(s, P, D)
+    with pytest.raises(FdcgksError, match="periodic sides"):
+        pb.step_vjp(0.001, np.zeros((2, 12) + P.shape[1:]))
+    with pytest.raises(FdcgksError, match="periodic only"):
+        Batch([gpu_params(s)])
+
+
+# ----------------------------------------------------------------------- 1D
+def _mirror_line(N):
+    h = 1.0 / N
+    x = (np.arange(N) + 0.5) * h
+
+    def state(xx):
+        return WL.conservative1d(1.0 + 0.2 * np.cos(math.pi * xx), 0.4 * np.sin(math.pi * xx),
+                                 1.0 + 0.1 * np.cos(2 * math.pi * xx))
+    S = np.zeros((1, 6, N))
+    S[0, :3] = state(x)
+    S[0, 3:] = (state(x + h / 2) - state(x - h / 2)) / h
+    return S
+
+
+def _problem1d(s, S):
+    from paper_2606_17772_amd import Problem
+    pb = Problem(gpu_params(s))
+    pb.set_state_stacked(0, S[0])
+    return pb
+
+
+def _floors1d(S, L=1.0, gamma=1.4):
+    W = S[:, :3]
+    U = W[:, 1] / W[:, 0]
+    p = (gamma - 1) * (W[:, 2] - 0.5 * W[:, 0] * U * U)
+    a = float((np.abs(U) + np.sqrt(gamma * p / W[:, 0])).max())
+    r = float(W[:, 0].max())
+    Wr = np.array([r, r * a, r * a * a])
+    return np.concatenate([Wr, Wr / L])
+
+
+@pytest.mark.parametrize("name", ["mirror_60", "blast_400"])
+def test_stages_1d_reflecting(oracle, name):
+    S = _mirror_line(60) if name == "mirror_60" else WL.blast_wave(400).S
+    N = S.shape[-1]
+    s = settings(dim=1, nx=N, lx=1.0, bc="reflecting")
+    par = oracle_par(oracle, s)
+    dt = 0.2 / N / 3.0 * (1.0 if name == "mirror_60" else 0.02)
+    o1, a1 = oracle.stage1d(par, 1, dt, S)
+    o2 = oracle.stage1d(par, 2, dt, o1, a1)
+    pb = _problem1d(s, S)
+    fl = _floors1d(S)
+    g1, ga = pb.debug_stage(1, dt)
+    for g, o in ((g1.reshape(S.shape), o1), (ga.reshape(S.shape), a1)):
+        err, where = relerr(g, o, fl, ndim_plane=1)
+        assert err <= TOL, (where, err)
+    err, where = relerr(pb.debug_stage(2, dt).reshape(S.shape), o2, fl, ndim_plane=1)
+    assert err <= TOL, (where, err)
+
+
+def test_smooth_run_1d_reflecting(oracle):
+    S = _mirror_line(60)
+    s = settings(dim=1, nx=60, lx=1.0, bc="reflecting")
+    par = oracle_par(oracle, s)
+    oS, ot, ok = oracle.step1d(par, S, 100000, cfl=0.5, t_end=0.5)
+    pb = _problem1d(s, S)
+    t, n = pb.step(nsteps=100000, cfl=0.5, t_end=0.5)
+    assert n == ok and abs(t - 0.5) < 1e-14
+    g = pb.get_state_stacked(0).reshape(S.shape)
+    rng = np.random.default_rng(0)
+    run = lambda X: oracle.step1d(par, X, 100000, cfl=0.5, t_end=0.5)[0]  # noqa: E731
+    fl = _floors1d(S)
+    sens = max(relerr(run(S * (1 + np.finfo(float).eps * rng.choice([-1.0, 1.0], size=S.shape))), oS, fl,
+                      ndim_plane=1)[0] for _ in range(2))
+    err = relerr(g, oS, fl, ndim_plane=1)[0]
+    print(f"1D reflecting smooth run: {n} steps, gpu-oracle {err:.2e}, oracle 1-ulp sensitivity {sens:.2e}")
+    assert err <= max(TOL, 4 * sens)
+    # walls let nothing through
+    for c in (0, 2):
+        assert abs(g[0, c].sum() - S[0, c].sum()) <= 1e-13 * np.abs(S[0, c]).sum()
+
+
+def test_blast_wave_stops_non_physical(oracle):
+    """The Woodward-Colella blast waves need the nonlinear S2O4 variant, which
+    is not built: with the linear update the state goes non-physical within a
+    few steps (the oracle: negative pressure after step 5).  The GPU run
+    stops there with ENONPHYS and keeps the last good state, which matches
+    the oracle's state after the same number of steps."""
+    from paper_2606_17772_amd import FdcgksError
+    pr = WL.blast_wave(400)
+    s = settings(dim=1, nx=400, lx=1.0, bc="reflecting")
+    par = oracle_par(oracle, s)
+    good, t = 0, 0.0
+    S = pr.S.copy()
+    while good < 50:
+        S2, t2, _ = oracle.step1d(par, S, 1, cfl=0.5, t=t)
+        W = S2[0, :3]
+        p = 0.4 * (W[2] - 0.5 * W[1] ** 2 / W[0])
+        if not (np.all(W[0] > 0) and np.all(p > 0)):
+            break
+        S, t, good = S2, t2, good + 1
+    assert 0 < good < 50
+    pb = _problem1d(s, pr.S)
+    with pytest.raises(FdcgksError) as ei:
+        pb.step(nsteps=100000, cfl=0.5, t_end=0.038)
+    assert ei.value.status == -4
+    g = pb.get_state_stacked(0).reshape(S.shape)
+    fl = _floors1d(pr.S)
+    err = relerr(g, S, fl, ndim_plane=1)[0]
+    print(f"blast wave: stopped after {good} good steps (oracle), state gpu-oracle {err:.2e}")
+    assert err <= 1e-9

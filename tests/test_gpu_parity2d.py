@@ -10,8 +10,9 @@ import numpy as np
 import pytest
 
 import workloads as WL
-from tests.helpers import (TOL, floors_edge, floors_node, floors_state, floors_state_interval, gpu_params,
-                           oracle_par, ref_scales, relerr, settings, ulp_sensitivity)
+from tests.helpers import (TOL, check_edge_intermediates, floors_edge, floors_node, floors_state,
+                           floors_state_interval, gpu_params, oracle_par, ref_scales, relerr, settings,
+                           ulp_sensitivity)
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +32,9 @@ CASES = {
     "shear_ns_36": lambda: (settings(dim=2, nx=36, ny=36, lx=1.0, mu=1e-3, prandtl=0.72),
                             WL.shear_layer(36, seed=2, k=20.0)),
     "riemann_33x20": lambda: (settings(dim=2, nx=33, ny=20, lx=1.0), WL.riemann2d(33, seed=5)),
+    "riemann_33x20_62": lambda: (settings(dim=2, nx=33, ny=20, lx=1.0, variant="6-2"), WL.riemann2d(33, seed=6)),
+    "rough_67x9_linear": lambda: (settings(dim=2, nx=67, ny=9, lx=1.0, variant="linear"),
+                                  WL.random_rough2d(67, 9, seed=7)),
 }
 
 
@@ -42,7 +46,10 @@ def _case(name):
     return s, pr
 
 
-@pytest.mark.parametrize("name", ["smooth_70x37", "rough_67x9", "vortex_40", "shear_ns_36", "riemann_33x20"])
+ALL = list(CASES)
+
+
+@pytest.mark.parametrize("name", ALL)
 def test_intermediates(oracle, name):
     s, pr = _case(name)
     dt = 0.2 * pr.h / 3.0
@@ -51,13 +58,13 @@ def test_intermediates(oracle, name):
     pb = _problem(s, pr.P, pr.D)
     gx, gy, gp, gd = pb.debug_intermediates(dt)
     sc = ref_scales([pr.P, pr.D], s["gamma"], s["lx"])
-    for lab, g, o, fl in (("X", gx, X, floors_edge(sc)), ("Y", gy, Y, floors_edge(sc)),
-                          ("nodeP", gp, NP, floors_node(sc)), ("nodeD", gd, ND, floors_node(sc))):
+    check_edge_intermediates(oracle, par, dt, pr.P, pr.D, (gx, gy), (X, Y), floors_edge(sc), name)
+    for lab, g, o, fl in (("nodeP", gp, NP, floors_node(sc)), ("nodeD", gd, ND, floors_node(sc))):
         err, where = relerr(g, o, fl)
         assert err <= TOL, (lab, where, err)
 
 
-@pytest.mark.parametrize("name", ["smooth_70x37", "rough_67x9", "vortex_40", "shear_ns_36", "riemann_33x20"])
+@pytest.mark.parametrize("name", ALL)
 def test_stages(oracle, name):
     s, pr = _case(name)
     dt = 0.2 * pr.h / 3.0
@@ -77,7 +84,7 @@ def test_stages(oracle, name):
 
 
 @pytest.mark.parametrize("name,nsteps", [("vortex_40", 3), ("shear_ns_36", 3), ("riemann_33x20", 2),
-                                         ("smooth_70x37", 3)])
+                                         ("smooth_70x37", 3), ("riemann_33x20_62", 2)])
 def test_steps_cfl(oracle, name, nsteps):
     """Several CFL steps.  Over several steps the nonlinear weights amplify
     round-off (near discontinuities by ~20x per step), so the bar is
