@@ -263,8 +263,7 @@ __global__ __launch_bounds__(256) void k_adj_edges(const double* __restrict__ S,
   const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
   fdk::IfaceRec rec[4];
   if (valid) {
-    if (fam == 0) { if (G == 0) edge_recon<0, 0>(S, g, k, i, j, rec); else edge_recon<0, 1>(S, g, k, i, j, rec); }
-    else { if (G == 0) edge_recon<1, 0>(S, g, k, i, j, rec); else edge_recon<1, 1>(S, g, k, i, j, rec); }
+    edge_recon<false>(S, g, k, i, j, fam, G, rec);
   } else {
     for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
   }

@@ -145,50 +145,55 @@ __global__ void k_halo_cols(double* __restrict__ S, int nplanes, Geo g, const Sc
 // ------------------------------------------------------- interface sweep
 // One gas-kinetic solve at an interface point: rn is the line normal to the
 // interface, rt the other line (its derivative gives the tangential slope).
-// SWAP: the normal is y, so rho U and rho V trade places in the local frame.
-template <bool SWAP, int STAGE, class FT>
-__device__ __forceinline__ void solve_dir(const Consts& k, FT dt, const fdk::IfaceRec (&rn)[4], const double (&tang)[4],
-                                          double (&F)[4], double (&Ft)[4], double (&Wl)[4], double (&Wr)[4],
-                                          double (&Wlt)[4], double (&Wrt)[4]) {
+// swap: the normal is y, so rho U and rho V trade places in the local frame.
+// The swap is applied to the data (selects), not by a second copy of the
+// solver: the interface sweep's code then fits the instruction cache.
+template <int STAGE, class FT>
+__device__ __forceinline__ void solve_dir(const Consts& k, FT dt, bool swap, const fdk::IfaceRec (&rn)[4],
+                                          const double (&tang)[4], double (&F)[4], double (&Ft)[4], double (&Wl)[4],
+                                          double (&Wr)[4], double (&Wlt)[4], double (&Wrt)[4]) {
   fdk::GksIO<FT, 2> io;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const int q = SWAP ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
-    io.WL[c] = (FT)rn[q].vl;
-    io.WR[c] = (FT)rn[q].vr;
-    io.nL[c] = (FT)rn[q].dl;
-    io.nR[c] = (FT)rn[q].dr;
-    io.Wt[c] = (FT)tang[q];
+    const int q = c == 1 ? 2 : (c == 2 ? 1 : c);
+    const bool sw = swap && q != c;
+    io.WL[c] = (FT)(sw ? rn[q].vl : rn[c].vl);
+    io.WR[c] = (FT)(sw ? rn[q].vr : rn[c].vr);
+    io.nL[c] = (FT)(sw ? rn[q].dl : rn[c].dl);
+    io.nR[c] = (FT)(sw ? rn[q].dr : rn[c].dr);
+    io.Wt[c] = (FT)(sw ? tang[q] : tang[c]);
   }
   fdk::gks_iface<FT, 2, STAGE == 1>(k, dt, io);
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const int q = SWAP ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
-    Ft[q] = (double)io.Ft[c];
-    Wlt[q] = (double)io.Wlt[c];
-    Wrt[q] = (double)io.Wrt[c];
+    const int q = c == 1 ? 2 : (c == 2 ? 1 : c);
+    const bool sw = swap && q != c;
+    Ft[c] = (double)(sw ? io.Ft[q] : io.Ft[c]);
+    Wlt[c] = (double)(sw ? io.Wlt[q] : io.Wlt[c]);
+    Wrt[c] = (double)(sw ? io.Wrt[q] : io.Wrt[c]);
     if (STAGE == 1) {
-      F[q] = (double)io.F[c];
-      Wl[q] = (double)io.Wl[c];
-      Wr[q] = (double)io.Wr[c];
+      F[c] = (double)(sw ? io.F[q] : io.F[c]);
+      Wl[c] = (double)(sw ? io.Wl[q] : io.Wl[c]);
+      Wr[c] = (double)(sw ? io.Wr[q] : io.Wr[c]);
     }
   }
 }
 
-// Reconstruction of one interface line.  Family FAM (0: X, 1: Y), grid G
-// (0: primary, 1: dual).  The line runs along y when FAM != G: X-primary
+// Reconstruction of one interface line.  Family fam (0: X, 1: Y), grid G
+// (0: primary, 1: dual).  The line runs along y when fam != G: X-primary
 // along x from P(i-1,j); X-dual along y from D(i,j-2); Y-primary along y
-// from P(i,j-1); Y-dual along x from D(i-2,j).
+// from P(i,j-1); Y-dual along x from D(i-2,j).  fam and G are runtime values
+// (uniform over a wave) so that one copy of the code serves all four lines.
 // CHAR: reconstruct characteristic variables (every rec[c].cl/cr then holds
 // the path function of the line).
-template <int FAM, int G, bool CHAR = false>
+template <bool CHAR = false>
 __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const Geo& g, const Consts& k, int i, int j,
-                                           fdk::IfaceRec (&rec)[4]) {
-  constexpr bool ALONG_Y = (FAM ^ G) != 0;
-  constexpr int back = G == 0 ? 1 : 2;
+                                           int fam, int G, fdk::IfaceRec (&rec)[4]) {
+  const bool ALONG_Y = (fam ^ G) != 0;
+  const int back = G == 0 ? 1 : 2;
   const long st = ALONG_Y ? g.pitch : 1;
   const long o = (ALONG_Y ? at(g, j - back, i) : at(g, j, i - back)) + (G ? g.dshift : 0);
-  constexpr int f = ALONG_Y ? 2 : 1;  // derivative field along the line
+  const int f = ALONG_Y ? 2 : 1;  // derivative field along the line
   const long pl = g.plane;
   if constexpr (CHAR) {
     // local frame of the line: the momentum along it is component 1
@@ -208,7 +213,10 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
     double chi;
     fdk::recon_iface_char<2>(k, Q, X, g.h, g.invh, loc, chi);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) rec[ALONG_Y ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c] = loc[c];
+    for (int c = 0; c < 4; ++c) {
+      const int q = c == 1 ? 2 : (c == 2 ? 1 : c);
+      rec[c] = ALONG_Y && q != c ? loc[q] : loc[c];
+    }
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -242,13 +250,7 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
   const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
   fdk::IfaceRec rec[4];
   if (valid) {
-    if (fam == 0) {
-      if (G == 0) edge_recon<0, 0, CHAR>(S, g, k, i, j, rec);
-      else edge_recon<0, 1, CHAR>(S, g, k, i, j, rec);
-    } else {
-      if (G == 0) edge_recon<1, 0, CHAR>(S, g, k, i, j, rec);
-      else edge_recon<1, 1, CHAR>(S, g, k, i, j, rec);
-    }
+    edge_recon<CHAR>(S, g, k, i, j, fam, G, rec);
   } else {
 #pragma unroll
     for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
@@ -266,8 +268,7 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
   const long pl = g.plane;
   if (valid) {
     // the normal is y when FAM != G (rho U and rho V swap in the local frame)
-    if (fam == G) solve_dir<false, STAGE, FT>(k, (FT)dt, rec, tang, F, Ft, Wl, Wr, Wlt, Wrt);
-    else solve_dir<true, STAGE, FT>(k, (FT)dt, rec, tang, F, Ft, Wl, Wr, Wlt, Wrt);
+    solve_dir<STAGE, FT>(k, (FT)dt, fam != G, rec, tang, F, Ft, Wl, Wr, Wlt, Wrt);
     // what needs no partner goes out at once
     e[8 * pl] = chi;
 #pragma unroll
@@ -399,6 +400,12 @@ __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, d
 // 4..7 time derivatives, at the node `off` = -1, 0, +1 along the axis.  A
 // non-physical result (rho <= 0, p <= 0, NaN) sets the stop flag and records
 // where (`member` names the batch member, 0 for a single problem).
+// Components are processed one at a time (the loop is not unrolled): each
+// reads its own ~20 planes and writes its outputs before the next starts, so
+// few values are live and the HBM-bound kernel runs at high occupancy.
+#ifndef FDCGKS_UPDATE_UNROLL
+#define FDCGKS_UPDATE_UNROLL 1
+#endif
 template <int STAGE, class NF>
 __device__ __forceinline__ void update_node(const double* __restrict__ S, const double* __restrict__ E,
                                             const NF& nf, const double* __restrict__ Ain, double* __restrict__ Out,
@@ -406,65 +413,14 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
                                             int i, int j, int grid, Scal* sc, int member) {
   const long pl = g.plane, o = at(g, j, i);
   const int r = grid;
-  double L[4] = {0, 0, 0, 0}, Lt[4] = {0, 0, 0, 0}, Gr[2][4], Grt[2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int fam = (grid == 0) ? a : 1 - a;
-    const long st = a == 0 ? 1 : g.pitch;
-    const double* e = E + (long)fam * 50 * pl + (long)grid * 25 * pl + o;
-    const double chiR = e[8 * pl + r * st], chiL = e[8 * pl + (r - 1) * st];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const double* f = e + (0 + c) * pl;
-      const double* ft = e + (4 + c) * pl;
-      if (STAGE == 1) {
-        const double n0 = nf(a, c, 0);
-        double FR = fdk::compact_flux(k.variant, f[(r - 1) * st], f[r * st], f[(r + 1) * st], n0, nf(a, c, 1), chiR);
-        double FL = fdk::compact_flux(k.variant, f[(r - 2) * st], f[(r - 1) * st], f[r * st], nf(a, c, -1), n0, chiL);
-        L[c] = L[c] - (FR - FL) * g.invh;
-        Gr[a][c] = (e[(9 + c) * pl + r * st] - e[(13 + c) * pl + (r - 1) * st]) * g.invh;
-      }
-      const double nt0 = nf(a, 4 + c, 0);
-      double FRt = fdk::compact_flux(k.variant, ft[(r - 1) * st], ft[r * st], ft[(r + 1) * st], nt0, nf(a, 4 + c, 1),
-                                     chiR);
-      double FLt = fdk::compact_flux(k.variant, ft[(r - 2) * st], ft[(r - 1) * st], ft[r * st], nf(a, 4 + c, -1), nt0,
-                                     chiL);
-      Lt[c] = Lt[c] - (FRt - FLt) * g.invh;
-      Grt[a][c] = (e[(17 + c) * pl + r * st] - e[(21 + c) * pl + (r - 1) * st]) * g.invh;
-    }
-  }
   const long so = o + (grid ? g.dshift : 0);  // the dual planes are shifted along bounded axes
   const double* s = S + (long)grid * 12 * pl + so;
   double* out = Out + (long)grid * 12 * pl + so;
-  double W[4];
-  if (STAGE == 1) {
-    double* ao = Aout + (long)grid * 12 * pl + so;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      double w = s[c * pl];
-      W[c] = w + 0.5 * dt * L[c] + 0.125 * dt * dt * Lt[c];
-      double gx = k.grad_carried ? s[(4 + c) * pl] : Gr[0][c];
-      double gy = k.grad_carried ? s[(8 + c) * pl] : Gr[1][c];
-      out[c * pl] = W[c];
-      out[(4 + c) * pl] = gx + 0.5 * dt * Grt[0][c];
-      out[(8 + c) * pl] = gy + 0.5 * dt * Grt[1][c];
-      ao[c * pl] = w + dt * L[c] + dt * dt / 6.0 * Lt[c];
-      ao[(4 + c) * pl] = gx;
-      ao[(8 + c) * pl] = gy;
-    }
-  } else {
-    const double* ai = Ain + (long)grid * 12 * pl + so;
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      W[c] = ai[c * pl] + dt * dt / 3.0 * Lt[c];
-      out[c * pl] = W[c];
-      out[(4 + c) * pl] = ai[(4 + c) * pl] + dt * Grt[0][c];
-      out[(8 + c) * pl] = ai[(8 + c) * pl] + dt * Grt[1][c];
-    }
-  }
-  // dual nodes on a reflecting / no-slip side carry the wall condition: the
+  // the wall condition of dual nodes on a reflecting / no-slip side: the
   // normal momentum (no-slip: both momenta) and its derivative along the wall
-  // are zero
+  // are zero; bit c of `zero` clears component c, bit 4 + c its x-derivative,
+  // bit 8 + c its y-derivative
+  int zero = 0;
   if (grid == 1 && (g.sx | g.sy)) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
@@ -475,17 +431,68 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
       if (type != FDCGKS_BC_REFLECTING && type != FDCGKS_BC_NO_SLIP) continue;
       const int along = 2 - a;  // field of the derivative along the wall
 #pragma unroll
-      for (int c = 1; c <= 2; ++c) {
-        if (type == FDCGKS_BC_REFLECTING && c != 1 + a) continue;
-        W[c] = 0.0;
-        out[c * pl] = 0.0;
-        out[(4 * along + c) * pl] = 0.0;
-      }
+      for (int c = 1; c <= 2; ++c)
+        if (type == FDCGKS_BC_NO_SLIP || c == 1 + a) zero |= (1 << c) | (1 << (4 * along + c));
     }
   }
+  double rho = 0.0, mom2 = 0.0, ener = 0.0;  // the new values, for the physicality check
+#pragma unroll FDCGKS_UPDATE_UNROLL
+  for (int c = 0; c < 4; ++c) {
+    double L = 0.0, Lt = 0.0, Gr[2], Grt[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int fam = (grid == 0) ? a : 1 - a;
+      const long st = a == 0 ? 1 : g.pitch;
+      const double* e = E + (long)fam * 50 * pl + (long)grid * 25 * pl + o;
+      const double chiR = e[8 * pl + r * st], chiL = e[8 * pl + (r - 1) * st];
+      const double* f = e + (0 + c) * pl;
+      const double* ft = e + (4 + c) * pl;
+      if (STAGE == 1) {
+        const double n0 = nf(a, c, 0);
+        double FR = fdk::compact_flux(k.variant, f[(r - 1) * st], f[r * st], f[(r + 1) * st], n0, nf(a, c, 1), chiR);
+        double FL = fdk::compact_flux(k.variant, f[(r - 2) * st], f[(r - 1) * st], f[r * st], nf(a, c, -1), n0, chiL);
+        L = L - (FR - FL) * g.invh;
+        Gr[a] = (e[(9 + c) * pl + r * st] - e[(13 + c) * pl + (r - 1) * st]) * g.invh;
+      }
+      const double nt0 = nf(a, 4 + c, 0);
+      double FRt = fdk::compact_flux(k.variant, ft[(r - 1) * st], ft[r * st], ft[(r + 1) * st], nt0, nf(a, 4 + c, 1),
+                                     chiR);
+      double FLt = fdk::compact_flux(k.variant, ft[(r - 2) * st], ft[(r - 1) * st], ft[r * st], nf(a, 4 + c, -1), nt0,
+                                     chiL);
+      Lt = Lt - (FRt - FLt) * g.invh;
+      Grt[a] = (e[(17 + c) * pl + r * st] - e[(21 + c) * pl + (r - 1) * st]) * g.invh;
+    }
+    double W, GX, GY;
+    if (STAGE == 1) {
+      double* ao = Aout + (long)grid * 12 * pl + so;
+      const double w = s[c * pl];
+      W = w + 0.5 * dt * L + 0.125 * dt * dt * Lt;
+      const double gx = k.grad_carried ? s[(4 + c) * pl] : Gr[0];
+      const double gy = k.grad_carried ? s[(8 + c) * pl] : Gr[1];
+      GX = gx + 0.5 * dt * Grt[0];
+      GY = gy + 0.5 * dt * Grt[1];
+      ao[c * pl] = w + dt * L + dt * dt / 6.0 * Lt;
+      ao[(4 + c) * pl] = gx;
+      ao[(8 + c) * pl] = gy;
+    } else {
+      const double* ai = Ain + (long)grid * 12 * pl + so;
+      W = ai[c * pl] + dt * dt / 3.0 * Lt;
+      GX = ai[(4 + c) * pl] + dt * Grt[0];
+      GY = ai[(8 + c) * pl] + dt * Grt[1];
+    }
+    if (zero & (1 << c)) W = 0.0;
+    if (zero & (1 << (4 + c))) GX = 0.0;
+    if (zero & (1 << (8 + c))) GY = 0.0;
+    out[c * pl] = W;
+    out[(4 + c) * pl] = GX;
+    out[(8 + c) * pl] = GY;
+    if (c == 0) rho = W;
+    else if (c == 3) ener = W;
+    else mom2 = mom2 + W * W;
+  }
   // non-physical state: rho <= 0, p <= 0 or NaN stops the run
-  double p = (k.gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
-  if (!(W[0] > 0.0) || !(p > 0.0)) {
+  double p = (k.gamma - 1.0) * (ener - 0.5 * mom2 / rho);
+  if (!(rho > 0.0) || !(p > 0.0)) {
     if (atomicCAS(&sc->stop, 0, 1) == 0) {
       sc->fail_grid = grid + 2 * member;
       sc->fail_i = i;
