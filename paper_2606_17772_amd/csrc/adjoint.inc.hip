@@ -188,15 +188,16 @@ __global__ __launch_bounds__(256) void k_adj_nodeflux(const double* __restrict__
 
 // ------------------------------------------------------- solver^T, GENO^T
 // GENO^T of one line: lam of (vl, dl, cl, vr, dr, cr) per component ->
-// scatter onto the line's nodes (W plane and derivative plane).
-template <int FAM, int G>
+// scatter onto the line's nodes (W plane and derivative plane).  fam and G
+// are runtime values (wave-uniform): one copy of the code serves all lines.
 __device__ __forceinline__ void line_adjoint(const double* __restrict__ S, double* __restrict__ lamS, const Geo& g,
-                                             const Consts& k, int i, int j, const double (&lv)[4][6]) {
-  constexpr bool ALONG_Y = (FAM ^ G) != 0;
-  constexpr int back = G == 0 ? 1 : 2;
+                                             const Consts& k, int i, int j, int fam, int G,
+                                             const double (&lv)[4][6]) {
+  const bool ALONG_Y = (fam ^ G) != 0;
+  const int back = G == 0 ? 1 : 2;
   const long st = ALONG_Y ? g.pitch : 1;
   const long o = ALONG_Y ? at(g, j - back, i) : at(g, j, i - back);
-  constexpr int f = ALONG_Y ? 2 : 1;
+  const int f = ALONG_Y ? 2 : 1;
   const long pl = g.plane;
   for (int c = 0; c < 4; ++c) {
     const double* w = S + (G * 12 + c) * pl + o;
@@ -216,27 +217,29 @@ __device__ __forceinline__ void line_adjoint(const double* __restrict__ S, doubl
 
 // Adjoint of one gas-kinetic interface solve: lam of the outputs (global
 // component order) -> lam of the inputs in the local frame: lin[0..3] WL,
-// [4..7] WR, [8..11] nL, [12..15] nR, [16..19] Wt.
-template <bool SWAP, int STAGE>
-__device__ __forceinline__ void solve_adjoint(const Consts& k, double dt, const fdk::IfaceRec (&rn)[4],
+// [4..7] WR, [8..11] nL, [12..15] nR, [16..19] Wt.  swap (normal along y) is
+// applied to the data, so one copy of the solver adjoint serves both normals.
+template <int STAGE>
+__device__ __forceinline__ void solve_adjoint(const Consts& k, double dt, bool swap, const fdk::IfaceRec (&rn)[4],
                                               const double (&tang)[4], const double (&lF)[4], const double (&lFt)[4],
                                               const double (&lWl)[4], const double (&lWr)[4],
                                               const double (&lWlt)[4], const double (&lWrt)[4], double (&lin)[20]) {
   fdk::GksIO<double, 2> in, ob, inb;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    const int q = SWAP ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;  // global component of local slot c
-    in.WL[c] = rn[q].vl;
-    in.WR[c] = rn[q].vr;
-    in.nL[c] = rn[q].dl;
-    in.nR[c] = rn[q].dr;
-    in.Wt[c] = tang[q];
-    ob.Ft[c] = lFt[q];
-    ob.Wlt[c] = lWlt[q];
-    ob.Wrt[c] = lWrt[q];
-    ob.F[c] = STAGE == 1 ? lF[q] : 0.0;
-    ob.Wl[c] = STAGE == 1 ? lWl[q] : 0.0;
-    ob.Wr[c] = STAGE == 1 ? lWr[q] : 0.0;
+    const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
+    const bool sw = swap && q0 != c;  // global component of local slot c is q0 when swapped
+    in.WL[c] = sw ? rn[q0].vl : rn[c].vl;
+    in.WR[c] = sw ? rn[q0].vr : rn[c].vr;
+    in.nL[c] = sw ? rn[q0].dl : rn[c].dl;
+    in.nR[c] = sw ? rn[q0].dr : rn[c].dr;
+    in.Wt[c] = sw ? tang[q0] : tang[c];
+    ob.Ft[c] = sw ? lFt[q0] : lFt[c];
+    ob.Wlt[c] = sw ? lWlt[q0] : lWlt[c];
+    ob.Wrt[c] = sw ? lWrt[q0] : lWrt[c];
+    ob.F[c] = STAGE == 1 ? (sw ? lF[q0] : lF[c]) : 0.0;
+    ob.Wl[c] = STAGE == 1 ? (sw ? lWl[q0] : lWl[c]) : 0.0;
+    ob.Wr[c] = STAGE == 1 ? (sw ? lWr[q0] : lWr[c]) : 0.0;
     inb.WL[c] = inb.WR[c] = inb.nL[c] = inb.nR[c] = inb.Wt[c] = 0.0;
   }
   fdk::gks_iface_b(k, dt, in, ob, inb);
@@ -291,32 +294,31 @@ __global__ __launch_bounds__(256) void k_adj_edges(const double* __restrict__ S,
       lWrt[c] = 0.5 * le[(21 + c) * pl] + 0.25 * pst;
     }
     lchi = le[8 * pl];
-    if (fam == G) solve_adjoint<false, STAGE>(k, dt, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
-    else solve_adjoint<true, STAGE>(k, dt, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
+    solve_adjoint<STAGE>(k, dt, fam != G, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
   }
   // the tangential slope of this solve came from the partner line: send its lambda
   const bool swap = fam != G;
   for (int c = 0; c < 4; ++c) {
-    const int lc = swap ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;  // local slot of global component c
-    xch[ty][c][tx] = lin[16 + lc];
+    const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
+    xch[ty][c][tx] = swap && q0 != c ? lin[16 + q0] : lin[16 + c];  // local slot of global component c
   }
   __syncthreads();
   if (valid) {
     double lv[4][6];
     for (int c = 0; c < 4; ++c) {
-      const int lc = swap ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+      const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
+      const bool sw = swap && q0 != c;  // local slot of global component c is q0 when swapped
       const double lt = 0.5 * xch[ty ^ 1][c][tx];  // partner's tangential slope = mean of my dl, dr
-      lv[c][0] = lin[lc];
-      lv[c][1] = lin[8 + lc] + lt;
+      lv[c][0] = sw ? lin[q0] : lin[c];
+      lv[c][1] = (sw ? lin[8 + q0] : lin[8 + c]) + lt;
       lv[c][2] = 0.0;
-      lv[c][3] = lin[4 + lc];
-      lv[c][4] = lin[12 + lc] + lt;
+      lv[c][3] = sw ? lin[4 + q0] : lin[4 + c];
+      lv[c][4] = (sw ? lin[12 + q0] : lin[12 + c]) + lt;
       lv[c][5] = 0.0;
     }
     // chi = min(chi_l, chi_r) of the density line (ties: left)
     if (rec[0].cr < rec[0].cl) lv[0][5] = lchi; else lv[0][2] = lchi;
-    if (fam == 0) { if (G == 0) line_adjoint<0, 0>(S, lamS, g, k, i, j, lv); else line_adjoint<0, 1>(S, lamS, g, k, i, j, lv); }
-    else { if (G == 0) line_adjoint<1, 0>(S, lamS, g, k, i, j, lv); else line_adjoint<1, 1>(S, lamS, g, k, i, j, lv); }
+    line_adjoint(S, lamS, g, k, i, j, fam, G, lv);
   }
 }
 
