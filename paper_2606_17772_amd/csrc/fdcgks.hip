@@ -65,6 +65,17 @@ struct Scal {
 
 __device__ __forceinline__ int imod(int a, int m) { return ((a % m) + m) % m; }
 
+// XCD-aware tile order.  The GPU deals consecutive workgroup ids round robin
+// to its 8 XCDs, each with its own L2, so row-major tiles put vertically
+// neighbouring tiles (which read the same stencil rows) on different L2s.
+// Instead every XCD takes a contiguous band of tiles: launch id (over ntiles
+// rounded up to a multiple of 8) -> tile; false for the padding ids.
+constexpr int NXCD = 8;
+__device__ __forceinline__ bool xcd_tile(int id, int padded, int ntiles, int& tile) {
+  tile = (id % NXCD) * (padded / NXCD) + id / NXCD;
+  return tile < ntiles;
+}
+
 // ------------------------------------------------------------ halo fill
 // Ghost index a along an axis of n real nodes of one grid: the node it copies
 // and the factor.  Periodic: the periodic image.  Zero-gradient: the end node,
@@ -307,9 +318,12 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
 #endif
 template <int STAGE, class FT, bool CHAR>
 __global__ __launch_bounds__(256, FDCGKS_EDGE_WAVES) void k_edges2d(const double* __restrict__ S, double* __restrict__ E, Geo g,
-                                                    Consts k, const Scal* __restrict__ sc) {
+                                                    Consts k, const Scal* __restrict__ sc, int tiles_x,
+                                                    int ntiles) {
   if (sc->stop) return;  // grid-uniform
-  edge_block<STAGE, FT, CHAR>(S, E, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z);
+  int t;
+  if (!xcd_tile(blockIdx.x, gridDim.x, ntiles, t)) return;  // block-uniform
+  edge_block<STAGE, FT, CHAR>(S, E, g, k, sc->dt, t % tiles_x, t / tiles_x, blockIdx.z);
 }
 
 // ------------------------------------------------------------ node sweep
@@ -385,9 +399,11 @@ __device__ __forceinline__ void node_block(const double* __restrict__ S, double*
 
 template <int STAGE, class FT, bool CHAR>
 __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, double* __restrict__ Nb, Geo g,
-                                                 Consts k, const Scal* __restrict__ sc) {
+                                                 Consts k, const Scal* __restrict__ sc, int tiles_x, int ntiles) {
   if (sc->stop) return;
-  node_block<STAGE, FT, CHAR>(S, Nb, g, k, blockIdx.x, blockIdx.y, blockIdx.z);
+  int t;
+  if (!xcd_tile(blockIdx.x, gridDim.x, ntiles, t)) return;
+  node_block<STAGE, FT, CHAR>(S, Nb, g, k, t % tiles_x, t / tiles_x, blockIdx.z);
 }
 
 // ------------------------------------------------------ assemble + update
@@ -593,7 +609,8 @@ __global__ __launch_bounds__(256) void k_nodeupd2d(const double* __restrict__ S,
 }
 
 template <int STAGE>
-__global__ __launch_bounds__(256) void k_update2d(const double* __restrict__ S, const double* __restrict__ E,
+// stage 2 reads and writes half the planes of stage 1: 80 VGPRs, 6 waves/SIMD
+__global__ __launch_bounds__(256, STAGE == 2 ? 6 : 4) void k_update2d(const double* __restrict__ S, const double* __restrict__ E,
                                                   const double* __restrict__ Nb, const double* __restrict__ Ain,
                                                   double* __restrict__ Out, double* __restrict__ Aout, Geo g,
                                                   Consts k, Scal* __restrict__ sc) {
@@ -1296,22 +1313,24 @@ fdcgks_status halo2d(fdcgks_problem* pb, double* S) {
 template <int STAGE>
 void launch_edges(fdcgks_problem* pb, const double* Sin, dim3 blk) {
   const Geo& g = pb->g;
-  dim3 ge(ceil_div(g.nx + 3 + g.sx, blk.x), ceil_div(g.ny + 3 + g.sy, blk.y / 2), 2);
+  const int tx = ceil_div(g.nx + 3 + g.sx, blk.x), nt = tx * ceil_div(g.ny + 3 + g.sy, blk.y / 2);
+  dim3 ge(ceil_div(nt, NXCD) * NXCD, 1, 2);  // tiles in XCD bands (xcd_tile)
   const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
   const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
   auto fn = f32 ? (ch ? k_edges2d<STAGE, float, true> : k_edges2d<STAGE, float, false>)
                 : (ch ? k_edges2d<STAGE, double, true> : k_edges2d<STAGE, double, false>);
-  hipLaunchKernelGGL(fn, ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc);
+  hipLaunchKernelGGL(fn, ge, blk, 0, pb->stream, Sin, pb->E, g, pb->k, pb->sc, tx, nt);
 }
 template <int STAGE>
 void launch_nodes(fdcgks_problem* pb, const double* Sin, dim3 blk) {
   const Geo& g = pb->g;
-  dim3 gn(ceil_div(g.nx + 2 + g.sx, blk.x), ceil_div(g.ny + 2 + g.sy, blk.y), 2);
+  const int tx = ceil_div(g.nx + 2 + g.sx, blk.x), nt = tx * ceil_div(g.ny + 2 + g.sy, blk.y);
+  dim3 gn(ceil_div(nt, NXCD) * NXCD, 1, 2);  // tiles in XCD bands (xcd_tile)
   const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
   const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
   auto fn = f32 ? (ch ? k_nodes2d<STAGE, float, true> : k_nodes2d<STAGE, float, false>)
                 : (ch ? k_nodes2d<STAGE, double, true> : k_nodes2d<STAGE, double, false>);
-  hipLaunchKernelGGL(fn, gn, blk, 0, pb->stream, Sin, pb->Nb, g, pb->k, pb->sc);
+  hipLaunchKernelGGL(fn, gn, blk, 0, pb->stream, Sin, pb->Nb, g, pb->k, pb->sc, tx, nt);
 }
 template <int STAGE>
 void launch_update(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout, dim3 blk) {
