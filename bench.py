@@ -30,7 +30,7 @@ MU, PR = 1e-4, 0.72
 PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector peak
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doubles, stage 2 reads 24 / writes 12
-# Dominant kernel: the stage-1 interface sweep k_edges2d<1,double>.  Unit of
+# Dominant kernel: the stage-1 interface sweep k_edges2d<1,double,false>.  Unit of
 # work: one interface point (two GENO line reconstructions, two gas-kinetic
 # solves, the blend); one launch processes 2 (n+3)^2 of them.  FP64 flops per
 # point and HBM bytes per launch are from the rocprofv3 counters of this
@@ -38,13 +38,8 @@ HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doub
 # wave instructions; FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 after the
 # copy-kernel calibration).  Both are None whenever the kernel has changed
 # since the counters were taken.
-FLOPS_PER_IFACE_POINT_STAGE1 = 6742
-TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 9.012e9
-# The same count with every GENO tanh and low-order blend evaluated (before
-# the exact shortcuts for saturated tanh and chi = 1 that skip a third of it
-# on this workload): the rate in these units is reported beside, not as, the
-# roofline figure.
-FULL_METHOD_FLOPS_PER_IFACE_POINT_STAGE1 = 10416
+FLOPS_PER_IFACE_POINT_STAGE1 = 6813
+TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 4.836e9
 
 
 # Launch shapes fdcgks_autotune picks on this workload (interface sweep,
@@ -436,9 +431,7 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": None,
                 "traffic": None}
-    roof["kernel"] = "k_edges2d<1,double> (stage-1 interface sweep)"
-    roof["full_method_equivalent_TFLOPs"] = round(
-        FULL_METHOD_FLOPS_PER_IFACE_POINT_STAGE1 * iface_points / (edge1_ms * 1e-3) / 1e12, 3)
+    roof["kernel"] = "k_edges2d<1,double,false> (stage-1 interface sweep)"
     roof["avg_launch_ms"] = round(edge1_ms, 4)
     hbm_gbs = value * HBM_BYTES_PER_NODE_STAGE / 1e9
     out = {
