@@ -129,17 +129,33 @@ void fdcgks_default_params(fdcgks_params* p);
 fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_problem** out);
 
 /* Copy one grid's state in.  W, Wx must be non-NULL; Wy must be non-NULL in 2D
- * and is ignored in 1D.  on_device = 1: device pointers (read on the problem's
- * stream, no host synchronisation); 0: host pointers (synchronous).  Values
- * with rho <= 0, p <= 0 or NaN are accepted here and reported by the first
- * step as FDCGKS_ENONPHYS. */
+ * and is ignored in 1D.  Each holds ncomp planes of the grid's ny_g rows of
+ * nx_g doubles (the layout above); a row starts every row_stride doubles
+ * (0 = nx_g, dense; otherwise >= nx_g) and a plane every ny_g * row_stride.
+ * on_device = 1: device pointers (read on the problem's stream, no host
+ * synchronisation); 0: host pointers (synchronous).  Values with rho <= 0,
+ * p <= 0 or NaN are accepted here and reported by the first step as
+ * FDCGKS_ENONPHYS. */
 fdcgks_status fdcgks_set_state(fdcgks_problem* pb, int32_t grid, const double* W, const double* Wx,
-                               const double* Wy, int32_t on_device);
+                               const double* Wy, int64_t row_stride, int32_t on_device);
 
-/* Copy one grid's state out (same layout and on_device rule as set_state;
- * with on_device = 0 the call waits for the stream). */
+/* Copy one grid's state out (same layout, row_stride and on_device rule as
+ * set_state; with on_device = 0 the call waits for the stream). */
 fdcgks_status fdcgks_get_state(const fdcgks_problem* pb, int32_t grid, double* W, double* Wx, double* Wy,
-                               int32_t on_device);
+                               int64_t row_stride, int32_t on_device);
+
+/* Every grid's state from point samples of the initial conservative field
+ * on the half-spacing lattice (periodic problems; EINVAL with a bounded
+ * side).  2D: S[ncomp][2 ny][2 nx], sample (c, ky, kx) at
+ * (x0 + (kx+1) h/2, y0 + (ky+1) h/2): (even, even) are the primary nodes,
+ * (odd, odd) the dual nodes, (odd, even) and (even, odd) the interface points
+ * X and Y.  1D: S[ncomp][2 nx], even samples the primary line, odd samples the
+ * shifted copy.  Nodal values are the samples; the averaged derivatives are
+ * the Gauss differences of the samples at the node's two bounding interfaces
+ * divided by h (Eq. define-averaged-gradient), with periodic wrap.
+ * on_device as for set_state (a host array is staged through the library's
+ * stage buffer). */
+fdcgks_status fdcgks_set_state_from_samples(fdcgks_problem* pb, const double* S, int32_t on_device);
 
 /* CFL time step of the current state (Sec. 5): dt = cfl h / max over all
  * nodes of (max(|U|,|V|) + c); with mu > 0 also dt <= cfl h^2 / (8 mu/rho_min).

@@ -278,6 +278,42 @@ def step2d_tangent(par, dt, P, D, dP, dD):
     return oP, oD, odP, odD
 
 
+def state_from_samples(par, S):
+    """Input state from point samples of the initial field on the
+    half-spacing lattice, periodic (Eq. define-averaged-gradient, D31): the
+    nodal value is the sample at the node, the averaged derivative the
+    difference of the samples at the node's two bounding interfaces over h.
+    2D: S (ncomp, 2ny, 2nx), sample (ky, kx) at (x0 + (kx+1)h/2,
+    y0 + (ky+1)h/2); returns (P, D).  1D: S (ncomp, 2nx); returns the
+    (lines, 6, nx) line state (line 1, the shifted copy, from odd samples)."""
+    S = np.asarray(S, dtype=np.float64)
+    h = par.lx / par.nx
+    if par.dim == 2:
+        nc, NY, NX = S.shape
+        out = []
+        for g in range(2):
+            A = np.zeros((12, par.ny, par.nx))
+            for j in range(par.ny):
+                for i in range(par.nx):
+                    kx, ky = 2 * i + g, 2 * j + g
+                    for c in range(nc):
+                        A[c, j, i] = S[c, ky, kx]
+                        A[4 + c, j, i] = (S[c, ky, (kx + 1) % NX] - S[c, ky, (kx - 1) % NX]) / h
+                        A[8 + c, j, i] = (S[c, (ky + 1) % NY, kx] - S[c, (ky - 1) % NY, kx]) / h
+            out.append(A)
+        return out[0], out[1]
+    nc, NX = S.shape
+    lines = 2 if par.dual_1d else 1
+    A = np.zeros((lines, 6, par.nx))
+    for ln in range(lines):
+        for j in range(par.nx):
+            k = 2 * j + ln
+            for c in range(nc):
+                A[ln, c, j] = S[c, k]
+                A[ln, 3 + c, j] = (S[c, (k + 1) % NX] - S[c, (k - 1) % NX]) / h
+    return A
+
+
 # ---------------------------------------------------------------------- 1D
 def stage1d(par, stage, dt, S, acc=None):
     S = _arr(S)

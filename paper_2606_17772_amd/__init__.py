@@ -142,17 +142,23 @@ class Problem:
         return _lib.check(st, self._h)
 
     # -- state
-    def set_state(self, grid, W, Wx, Wy=None):
+    def set_state(self, grid, W, Wx, Wy=None, row_stride=0):
+        """W, Wx[, Wy]: (ncomp, ny_g, nx_g) arrays of the grid (numpy, or torch
+        on the device).  row_stride > 0: the arrays are flat with rows of
+        row_stride elements (padded rows)."""
         pw, dev, k1 = _ptr(W)
         px, dev2, k2 = _ptr(Wx)
         py, dev3, k3 = _ptr(Wy) if Wy is not None else (C.c_void_p(None), dev, None)
         if len({dev, dev2, dev3}) != 1:
             raise TypeError("W, Wx, Wy must all live on the host or all on the device")
         shape = self.grid_shape(grid)
+        need = int(np.prod(shape)) if not row_stride else shape[0] * shape[1] * int(row_stride)
         for a in (W, Wx) + ((Wy,) if Wy is not None else ()):
-            if tuple(a.shape) not in (shape, (int(np.prod(shape)),)):
+            if not row_stride and tuple(a.shape) not in (shape, (need,)):
                 raise ValueError(f"state arrays of grid {grid} must have shape {shape}")
-        self._chk(self._L.fdcgks_set_state(self._h, grid, pw, px, py, dev))
+            if row_stride and int(np.prod(tuple(a.shape))) < need:
+                raise ValueError(f"strided state arrays of grid {grid} need {need} elements")
+        self._chk(self._L.fdcgks_set_state(self._h, grid, pw, px, py, int(row_stride), dev))
 
     def set_state_stacked(self, grid, S):
         """S: (12, ny, nx) (2D; the dual grid's own size along bounded axes) or
@@ -173,8 +179,31 @@ class Problem:
                    for _ in range(3 if self.params.dim == 2 else 2)]
         ptrs = [_ptr(a, True) for a in out]
         py = ptrs[2][0] if len(ptrs) == 3 else C.c_void_p(None)
-        self._chk(self._L.fdcgks_get_state(self._h, grid, ptrs[0][0], ptrs[1][0], py, ptrs[0][1]))
+        self._chk(self._L.fdcgks_get_state(self._h, grid, ptrs[0][0], ptrs[1][0], py, 0, ptrs[0][1]))
         return tuple(out)
+
+    def get_state_strided(self, grid, row_stride):
+        """(W, Wx[, Wy]) as flat numpy arrays with rows of row_stride elements
+        (the padding is left as zeros)."""
+        ny, nx = self.grid_dims(grid)
+        out = [np.zeros(self.ncomp * ny * row_stride) for _ in range(3 if self.params.dim == 2 else 2)]
+        py = C.c_void_p(out[2].ctypes.data) if len(out) == 3 else C.c_void_p(None)
+        self._chk(self._L.fdcgks_get_state(self._h, grid, C.c_void_p(out[0].ctypes.data),
+                                           C.c_void_p(out[1].ctypes.data), py, int(row_stride), 0))
+        return tuple(out)
+
+    def set_state_from_samples(self, S):
+        """Every grid's state from samples of the initial field on the
+        half-spacing lattice: (ncomp, 2 ny, 2 nx) in 2D, (ncomp, 2 nx) in 1D
+        (fdcgks_set_state_from_samples; periodic problems)."""
+        p = self.params
+        shape = (self.ncomp, 2 * p.ny, 2 * p.nx) if p.dim == 2 else (self.ncomp, 2 * p.nx)
+        if tuple(S.shape) != shape:
+            raise ValueError(f"samples must have shape {shape}")
+        if isinstance(S, np.ndarray):
+            S = np.ascontiguousarray(S, dtype=np.float64)
+        ps, dev, _ = _ptr(S)
+        self._chk(self._L.fdcgks_set_state_from_samples(self._h, ps, dev))
 
     def get_state_stacked(self, grid):
         return np.concatenate(self.get_state(grid), axis=0)

@@ -51,8 +51,9 @@ _i32 = C.c_int32
 SIGNATURES = {
     "fdcgks_default_params": (None, [C.POINTER(Params)]),
     "fdcgks_create": (C.c_int, [C.POINTER(Params), _vp, C.POINTER(_vp)]),
-    "fdcgks_set_state": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _i32]),
-    "fdcgks_get_state": (C.c_int, [_vp, _i32, _vp, _vp, _vp, _i32]),
+    "fdcgks_set_state": (C.c_int, [_vp, _i32, _vp, _vp, _vp, C.c_int64, _i32]),
+    "fdcgks_get_state": (C.c_int, [_vp, _i32, _vp, _vp, _vp, C.c_int64, _i32]),
+    "fdcgks_set_state_from_samples": (C.c_int, [_vp, _vp, _i32]),
     "fdcgks_compute_dt": (C.c_int, [_vp, C.c_double, _dp]),
     "fdcgks_step": (C.c_int, [_vp, C.c_double, C.c_double, _i32, C.c_double, _dp, C.POINTER(_i32)]),
     "fdcgks_step_timed": (C.c_int, [_vp, C.c_double, C.c_double, _i32, C.c_double, _dp, C.POINTER(_i32), _dp]),

@@ -872,6 +872,48 @@ __global__ __launch_bounds__(256) void k_run1d(double* S0, double* S1, double* S
   if (threadIdx.x == 0 && sfail) sc->stop |= 1;
 }
 
+// ------------------------------------------------ state from point samples
+// Nodal values are the samples; averaged derivatives are the Gauss
+// differences of the samples at the two bounding interfaces divided by h
+// (Eq. define-averaged-gradient), with periodic wrap.  2D samples
+// S[c][2ny][2nx]: sample (kx, ky) at (x0 + (kx+1) h/2, y0 + (ky+1) h/2);
+// primary node (i, j) is sample (2i, 2j), dual node (i, j) sample (2i+1, 2j+1).
+__global__ void k_from_samples2d(const double* __restrict__ S, double* __restrict__ St, Geo g) {
+  const int NX = 2 * g.nx, NY = 2 * g.ny;
+  const long n = 2L * 4 * g.nx * g.ny;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(t % g.nx);
+    long r = t / g.nx;
+    const int j = (int)(r % g.ny);
+    r /= g.ny;
+    const int c = (int)(r % 4), gr = (int)(r / 4);
+    const int kx = 2 * i + gr, ky = 2 * j + gr;
+    const double* P = S + (long)c * NY * NX;
+    const double w = P[(long)ky * NX + kx];
+    const double wx = (P[(long)ky * NX + imod(kx + 1, NX)] - P[(long)ky * NX + imod(kx - 1, NX)]) / g.h;
+    const double wy = (P[(long)imod(ky + 1, NY) * NX + kx] - P[(long)imod(ky - 1, NY) * NX + kx]) / g.h;
+    const long o = at(g, j, i);
+    St[(long)(gr * 12 + c) * g.plane + o] = w;
+    St[(long)(gr * 12 + 4 + c) * g.plane + o] = wx;
+    St[(long)(gr * 12 + 8 + c) * g.plane + o] = wy;
+  }
+}
+// 1D samples S[c][2nx]: node j of line l (0 primary, 1 the shifted copy) is
+// sample 2j + l.
+__global__ void k_from_samples1d(const double* __restrict__ S, double* __restrict__ St, Geo g, int lines) {
+  const int NX = 2 * g.nx;
+  const long n = (long)lines * 3 * g.nx;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const int j = (int)(t % g.nx);
+    const int c = (int)((t / g.nx) % 3), l = (int)(t / (3L * g.nx));
+    const int k = 2 * j + l;
+    const double* P = S + (long)c * NX;
+    const long o = at(g, 0, j);
+    St[(long)(l * 6 + c) * g.plane + o] = P[k];
+    St[(long)(l * 6 + 3 + c) * g.plane + o] = (P[imod(k + 1, NX)] - P[imod(k - 1, NX)]) / g.h;
+  }
+}
+
 // ------------------------------------------------------------ CFL / step
 // Per-block partial max(max(|U|,|V|) + c) and min rho over both grids
 // (2D: dim 2, 4 components; 1D lines: dim 1, 3 components).
@@ -1699,48 +1741,81 @@ static int grid_nx(const fdcgks_problem* pb, int grid) { return pb->g.nx + (grid
 static int grid_ny(const fdcgks_problem* pb, int grid) { return pb->g.ny + (grid == 1 ? pb->g.sy : 0); }
 
 static fdcgks_status copy_grid(fdcgks_problem* pb, int grid, double* const* ptrs, int to_device_state,
-                               int on_device) {
+                               int64_t row_stride, int on_device) {
   const Geo& g = pb->g;
   int ncomp = pb->prm.dim == 2 ? 4 : 3;
   int nfield = pb->prm.dim == 2 ? 3 : 2;
   const int mx = grid_nx(pb, grid), my = grid_ny(pb, grid);
+  if (row_stride == 0) row_stride = mx;
+  if (row_stride < mx) return fail(pb, FDCGKS_EINVAL, "row_stride %ld below the row length %d", (long)row_stride, mx);
   double* base = pb->S[pb->cur] + (long)grid * (pb->prm.dim == 2 ? 12 : 6) * g.plane;
-  size_t row = (size_t)mx * sizeof(double);
+  size_t row = (size_t)mx * sizeof(double), upitch = (size_t)row_stride * sizeof(double);
   hipMemcpyKind kind = to_device_state ? (on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
                                        : (on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
   for (int f = 0; f < nfield; ++f)
     for (int c = 0; c < ncomp; ++c) {
       double* dev = base + (long)(f * (pb->prm.dim == 2 ? 4 : 3) + c) * g.plane + (long)OY * g.pitch + OX;
-      double* usr = ptrs[f] + (long)c * mx * my;
+      double* usr = ptrs[f] + (long)c * row_stride * my;
       if (to_device_state)
-        HIPCHK(pb, hipMemcpy2DAsync(dev, (size_t)g.pitch * sizeof(double), usr, row, row, my, kind, pb->stream));
+        HIPCHK(pb, hipMemcpy2DAsync(dev, (size_t)g.pitch * sizeof(double), usr, upitch, row, my, kind, pb->stream));
       else
-        HIPCHK(pb, hipMemcpy2DAsync(usr, row, dev, (size_t)g.pitch * sizeof(double), row, my, kind, pb->stream));
+        HIPCHK(pb, hipMemcpy2DAsync(usr, upitch, dev, (size_t)g.pitch * sizeof(double), row, my, kind, pb->stream));
     }
   if (!on_device) HIPCHK(pb, hipStreamSynchronize(pb->stream));
   return FDCGKS_OK;
 }
 
 fdcgks_status fdcgks_set_state(fdcgks_problem* pb, int32_t grid, const double* W, const double* Wx, const double* Wy,
-                               int32_t on_device) {
+                               int64_t row_stride, int32_t on_device) {
   if (!pb) return fail(nullptr, FDCGKS_EINVAL, "problem is NULL");
   if (grid < 0 || grid >= pb->ngrid) return fail(pb, FDCGKS_EINVAL, "grid %d not present", grid);
   if (!W || !Wx || (pb->prm.dim == 2 && !Wy)) return fail(pb, FDCGKS_EINVAL, "state pointer is NULL");
   double* ptrs[3] = {const_cast<double*>(W), const_cast<double*>(Wx), const_cast<double*>(Wy)};
-  fdcgks_status st = copy_grid(pb, grid, ptrs, 1, on_device);
+  fdcgks_status st = copy_grid(pb, grid, ptrs, 1, row_stride, on_device);
   if (st) return st;
   pb->have_state[grid] = true;
   return FDCGKS_OK;
 }
 
 fdcgks_status fdcgks_get_state(const fdcgks_problem* cpb, int32_t grid, double* W, double* Wx, double* Wy,
-                               int32_t on_device) {
+                               int64_t row_stride, int32_t on_device) {
   fdcgks_problem* pb = const_cast<fdcgks_problem*>(cpb);
   if (!pb) return fail(nullptr, FDCGKS_EINVAL, "problem is NULL");
   if (grid < 0 || grid >= pb->ngrid) return fail(pb, FDCGKS_EINVAL, "grid %d not present", grid);
   if (!W || !Wx || (pb->prm.dim == 2 && !Wy)) return fail(pb, FDCGKS_EINVAL, "state pointer is NULL");
   double* ptrs[3] = {W, Wx, Wy};
-  return copy_grid(pb, grid, ptrs, 0, on_device);
+  return copy_grid(pb, grid, ptrs, 0, row_stride, on_device);
+}
+
+fdcgks_status fdcgks_set_state_from_samples(fdcgks_problem* pb, const double* S, int32_t on_device) {
+  if (!pb) return fail(nullptr, FDCGKS_EINVAL, "problem is NULL");
+  if (!S) return fail(pb, FDCGKS_EINVAL, "samples pointer is NULL");
+  const Geo& g = pb->g;
+  if (g.sx | g.sy || (pb->prm.dim == 1 && pb->prm.bc != FDCGKS_BC_PERIODIC))
+    return fail(pb, FDCGKS_EINVAL, "state from samples needs periodic sides");
+  const int ncomp = pb->prm.dim == 2 ? 4 : 3;
+  const long nS = (long)ncomp * 2 * g.nx * (pb->prm.dim == 2 ? 2 * g.ny : 1);
+  const double* src = S;
+  if (!on_device) {
+    // stage the host samples in the stage buffer (free between steps; it
+    // holds nplanes padded planes, more than the nS samples)
+    HIPCHK(pb, hipMemcpyAsync(pb->Sstar, S, (size_t)nS * sizeof(double), hipMemcpyHostToDevice, pb->stream));
+    src = pb->Sstar;
+  }
+  if (pb->prm.dim == 2) {
+    const long n = 2L * 4 * g.nx * g.ny;
+    hipLaunchKernelGGL(k_from_samples2d, dim3(std::min(ceil_div(n, 256), 65535)), dim3(256), 0, pb->stream, src,
+                       pb->S[pb->cur], g);
+  } else {
+    const long n = (long)pb->ngrid * 3 * g.nx;
+    hipLaunchKernelGGL(k_from_samples1d, dim3(std::min(ceil_div(n, 256), 65535)), dim3(256), 0, pb->stream, src,
+                       pb->S[pb->cur], g, pb->ngrid);
+  }
+  fdcgks_status st = launch_check(pb, "from_samples");
+  if (st) return st;
+  if (!on_device) HIPCHK(pb, hipStreamSynchronize(pb->stream));
+  for (int gr = 0; gr < pb->ngrid; ++gr) pb->have_state[gr] = true;
+  return FDCGKS_OK;
 }
 
 static bool state_ready(const fdcgks_problem* pb) {
