@@ -66,6 +66,7 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux variant comparison")
     ap.add_argument("--no-char", action="store_true",
                     help="skip the characteristic-variable reconstruction comparison")
+    ap.add_argument("--no-bounded", action="store_true", help="skip the walled-domain leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -214,6 +215,35 @@ def characteristic_comparison(pr, n, tiles, steps=10):
             "conservative_ms_per_step": round(mc, 3), "slowdown_vs_conservative": round(mh / mc, 3),
             "kernel_ms_per_step": kh, "conservative_kernel_ms_per_step": kc,
             "max_rel_diff_values_vs_conservative": _max_rel_values(Sc, Sh)}
+
+
+def bounded_comparison(n, tiles, steps=10):
+    """Bounded sides (walls) on a workload of the same size: a smooth flow
+    in [0,1]^2 with adiabatic no-slip walls at x = 0, 1 and reflecting
+    (symmetry) walls at y = 0, 1, Navier-Stokes at the shear layer's mu and
+    Pr; the dual grid then has (n+1)^2 nodes.  Node-update rate and time
+    per step against the periodic shear layer."""
+    import torch
+
+    import workloads as WL
+    from paper_2606_17772_amd import Problem, make_params
+    P, D = WL.sample_bounded(WL.mirror_flow(1.0, 1.0, 1, 1), n, n, 1.0 / n, 1, 1)
+    pb = Problem(make_params(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, mu=MU, prandtl=PR,
+                             sides=("no_slip", "no_slip", "reflecting", "reflecting")))
+    for name, (x, y) in tiles.items():
+        pb.set_tile(name, x, y)
+    pb.set_state_stacked(0, P)
+    pb.set_state_stacked(1, D)
+    pb.step(nsteps=2, cfl=CFL)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pb.step(nsteps=steps, cfl=CFL)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    nodes = n * n + (n + 1) * (n + 1)
+    return {"workload": f"{n}x{n} (+ {n + 1}x{n + 1} dual) smooth flow, no-slip x walls, reflecting y walls, "
+                        f"{steps} CFL steps", "ms_per_step": round(ms, 3),
+            "node_updates_per_s": nodes * 2 / (ms * 1e-3)}
 
 
 ADJ_STEPS, ADJ_EVERY, ADJ_CFL = 50, 7, 0.25
@@ -458,7 +488,7 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_comparison(pb, n)
-    if not args.no_fp32 or not args.no_char:
+    if not args.no_fp32 or not args.no_char or not args.no_bounded:
         del pb
         torch.cuda.empty_cache()
         pb = None
@@ -466,6 +496,9 @@ def main():
         out["fp32_flux"] = fp32_flux_comparison(pr, n, tiles)
     if not args.no_char:
         out["characteristic"] = characteristic_comparison(pr, n, tiles)
+    if not args.no_bounded:
+        torch.cuda.empty_cache()
+        out["bounded"] = bounded_comparison(n, tiles)
     if not args.no_graph:
         out["graph_replay"] = graph_comparison()
     if not args.no_batch:

@@ -61,6 +61,13 @@ def _case_mixed():
                     sides=["reflecting", "zero_gradient", "no_slip", "reflecting"]), P, D
 
 
+def _case_shock_tube():
+    """The viscous shock tube's first stages (its 100:1 jump goes non-physical
+    within a few steps under the linear S2O4 update, in the oracle too)."""
+    pr = WL.viscous_shock_tube(40)
+    return settings(dim=2, nx=40, ny=20, lx=1.0, mu=0.005, prandtl=0.72, sides=list(pr.params["sides"])), pr.P, pr.D
+
+
 CASES = {
     "reflecting_x_70x37": _case_refl_x,
     "reflecting_all_67x9": _case_refl_all,
@@ -68,6 +75,7 @@ CASES = {
     "zero_gradient_riemann_33": _case_zerograd_riemann,
     "mixed_48x20": _case_mixed,
     "reflecting_all_char_67x9": lambda: _case_refl_all(recon_vars="characteristic"),
+    "viscous_shock_tube_40x20": _case_shock_tube,
 }
 
 

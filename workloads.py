@@ -267,6 +267,21 @@ def riemann2d_bounded(n, seed=0, gamma=GAMMA):
     return Problem2D("riemann2d_bounded", n, n, 0.0, 1.0, 0.0, 1.0, P, D, {"gamma": gamma, "mu": 0.0, "states": q})
 
 
+def viscous_shock_tube(nx, gamma=GAMMA, mu=0.005, prandtl=0.72):
+    """Viscous shock tube (Sec. 5, Daru-Tenaud): the lower half [0,1] x [0,0.5]
+    of a unit cavity, (rho, U, V, p) = (120, 0, 0, 120/gamma) for x < 0.5 and
+    (1.2, 0, 0, 1.2/gamma) beyond, jump on an interface (nx even); adiabatic
+    no-slip walls left, right and bottom, a symmetry plane on top; Re = 200
+    (mu = 0.005), Pr = 0.72.  ny = nx / 2."""
+    ny = nx // 2
+    h = 1.0 / nx
+    fn = quadrants([(120.0, 0.0, 0.0, 120.0 / gamma), (1.2, 0.0, 0.0, 1.2 / gamma)] * 2, xs=0.5, ys=10.0, gamma=gamma)
+    P, D = sample_bounded(fn, nx, ny, h, 1, 1, jumps=True)
+    return Problem2D("viscous_shock_tube", nx, ny, 0.0, 1.0, 0.0, 0.5, P, D,
+                     {"gamma": gamma, "mu": mu, "prandtl": prandtl,
+                      "sides": ("no_slip", "no_slip", "no_slip", "reflecting")})
+
+
 def batch_sizes(count=64, lo=64, hi=512, seed=0):
     rng = np.random.default_rng(seed)
     return [int(v) for v in rng.integers(lo, hi + 1, size=count)]
