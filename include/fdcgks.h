@@ -157,6 +157,14 @@ fdcgks_status fdcgks_get_state(const fdcgks_problem* pb, int32_t grid, double* W
  * stage buffer). */
 fdcgks_status fdcgks_set_state_from_samples(fdcgks_problem* pb, const double* S, int32_t on_device);
 
+/* Diagnostics of the current state (synchronous): out[q] for q < ngrid*ncomp
+ * is the sum of conserved component q % ncomp over the stored nodes of grid
+ * q / ncomp (primary first); then the smallest rho and the smallest pressure
+ * over all nodes.  out must hold ngrid*ncomp + 2 doubles (2D: 10; 1D: 5 or
+ * 8).  Sums are formed in a fixed order, so repeated calls on one state agree
+ * bit for bit. */
+fdcgks_status fdcgks_diagnostics(fdcgks_problem* pb, double* out);
+
 /* CFL time step of the current state (Sec. 5): dt = cfl h / max over all
  * nodes of (max(|U|,|V|) + c); with mu > 0 also dt <= cfl h^2 / (8 mu/rho_min).
  * Synchronous. */

@@ -250,6 +250,15 @@ class Problem:
         self._chk(self._L.fdcgks_step_vjp(self._h, dt, po, pi, dev))
         return lam_in
 
+    def diagnostics(self):
+        """Conservation sums per grid ((ngrid, ncomp) array), smallest rho and
+        smallest pressure of the current state (fdcgks_diagnostics)."""
+        nq = self.ngrid * self.ncomp + 2
+        out = (C.c_double * nq)()
+        self._chk(self._L.fdcgks_diagnostics(self._h, out))
+        v = np.array(list(out))
+        return {"sums": v[:-2].reshape(self.ngrid, self.ncomp), "rho_min": float(v[-2]), "p_min": float(v[-1])}
+
     # -- time stepping
     def compute_dt(self, cfl):
         dt = C.c_double()

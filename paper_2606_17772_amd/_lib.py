@@ -55,6 +55,7 @@ SIGNATURES = {
     "fdcgks_get_state": (C.c_int, [_vp, _i32, _vp, _vp, _vp, C.c_int64, _i32]),
     "fdcgks_set_state_from_samples": (C.c_int, [_vp, _vp, _i32]),
     "fdcgks_compute_dt": (C.c_int, [_vp, C.c_double, _dp]),
+    "fdcgks_diagnostics": (C.c_int, [_vp, _dp]),
     "fdcgks_step": (C.c_int, [_vp, C.c_double, C.c_double, _i32, C.c_double, _dp, C.POINTER(_i32)]),
     "fdcgks_step_timed": (C.c_int, [_vp, C.c_double, C.c_double, _i32, C.c_double, _dp, C.POINTER(_i32), _dp]),
     "fdcgks_destroy": (C.c_int, [_vp]),

@@ -960,6 +960,55 @@ __global__ __launch_bounds__(256) void k_cfl_partial(const double* __restrict__ 
   (void)sc;
 }
 
+// Per-block partial diagnostics over the stored nodes of every grid: sums of
+// each conserved component per grid, min rho and min p.  part[block * NQ + q]
+// with q = grid * (DIM + 2) + comp, then NQ - 2 (min rho) and NQ - 1 (min p).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_diag_partial(const double* __restrict__ S, Geo g, int ngrid, long gridstride,
+                                                      double gamma, double* __restrict__ part) {
+  __shared__ double red[256];
+  constexpr int NC = DIM + 2;
+  const int W = g.nx + g.sx, H = g.ny + g.sy;
+  const long n = (long)ngrid * W * H;
+  double s0[NC], s1[NC], rmin = 1e300, pmin = 1e300;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) s0[c] = s1[c] = 0.0;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const int i = (int)(t % W);
+    long r = t / W;
+    const int j = (int)(r % H);
+    const int gr = (int)(r / H);
+    if (gr == 0 && (i >= g.nx || j >= g.ny)) continue;
+    const double* B = S + gr * gridstride + at(g, j, i);
+    double w[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) w[c] = B[c * g.plane];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      if (gr == 0) s0[c] += w[c];
+      else s1[c] += w[c];
+    }
+    const double rho = w[0], U = w[1] / rho, V = DIM == 2 ? w[2] / rho : 0.0;
+    const double p = (gamma - 1.0) * (w[NC - 1] - 0.5 * rho * (U * U + V * V));
+    rmin = fmin(rmin, rho);
+    pmin = fmin(pmin, p);
+  }
+  const int NQ = ngrid * NC + 2;
+  for (int q = 0; q < NQ; ++q) {
+    double v = q < NC ? s0[q] : (q < 2 * NC && ngrid == 2 ? s1[q - NC] : (q == NQ - 2 ? rmin : pmin));
+    const bool is_min = q >= NQ - 2;
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w)
+        red[threadIdx.x] = is_min ? fmin(red[threadIdx.x], red[threadIdx.x + w]) : red[threadIdx.x] + red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[(long)blockIdx.x * NQ + q] = red[0];
+    __syncthreads();
+  }
+}
+
 // Start of a step: dt from the partials (or the fixed dt), clipped to t_end;
 // sets the "done" bit when t has reached t_end.
 __global__ void k_step_begin(const double* __restrict__ part, int nparts, Scal* __restrict__ sc, double cfl,
@@ -1713,7 +1762,8 @@ fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_pro
     if (e == hipSuccess) e = hipMalloc((void**)t, sbytes);
   if (e == hipSuccess) e = hipMalloc((void**)&pb->E, ebytes);
   if (e == hipSuccess) e = hipMalloc((void**)&pb->Nb, nbytes);
-  if (e == hipSuccess) e = hipMalloc((void**)&pb->part, (size_t)2 * pb->nparts * sizeof(double));
+  // CFL partials (2 per block) and diagnostics partials (up to 10 per block)
+  if (e == hipSuccess) e = hipMalloc((void**)&pb->part, (size_t)10 * pb->nparts * sizeof(double));
   if (e == hipSuccess) e = hipMalloc((void**)&pb->sc, sizeof(Scal));
   if (e == hipSuccess) e = hipHostMalloc((void**)&pb->sc_host, sizeof(Scal), hipHostMallocDefault);
   if (e == hipSuccess) {
@@ -1845,6 +1895,32 @@ fdcgks_status fdcgks_compute_dt(fdcgks_problem* pb, double cfl, double* dt_out) 
   if (st) return st;
   if (pb->sc_host->stop) return fail(pb, FDCGKS_ENONPHYS, "state gives no positive time step");
   *dt_out = pb->sc_host->dt;
+  return FDCGKS_OK;
+}
+
+fdcgks_status fdcgks_diagnostics(fdcgks_problem* pb, double* out) {
+  if (!pb || !out) return fail(pb, FDCGKS_EINVAL, "NULL argument");
+  if (!state_ready(pb)) return fail(pb, FDCGKS_ESTATE, "set_state has not been called for every grid");
+  const Geo& g = pb->g;
+  const int nc = pb->prm.dim == 2 ? 4 : 3, NQ = pb->ngrid * nc + 2;
+  const long gstride = (pb->prm.dim == 2 ? 12 : 6) * g.plane;
+  if (pb->prm.dim == 2)
+    hipLaunchKernelGGL(k_diag_partial<2>, dim3(pb->nparts), dim3(256), 0, pb->stream, pb->S[pb->cur], g, pb->ngrid,
+                       gstride, pb->k.gamma, pb->part);
+  else
+    hipLaunchKernelGGL(k_diag_partial<1>, dim3(pb->nparts), dim3(256), 0, pb->stream, pb->S[pb->cur], g, pb->ngrid,
+                       gstride, pb->k.gamma, pb->part);
+  fdcgks_status st = launch_check(pb, "diagnostics");
+  if (st) return st;
+  std::vector<double> h((size_t)pb->nparts * NQ);
+  HIPCHK(pb, hipMemcpyAsync(h.data(), pb->part, h.size() * sizeof(double), hipMemcpyDeviceToHost, pb->stream));
+  HIPCHK(pb, hipStreamSynchronize(pb->stream));
+  for (int q = 0; q < NQ; ++q) out[q] = q >= NQ - 2 ? 1e300 : 0.0;
+  for (int b = 0; b < pb->nparts; ++b)  // fixed order: the result does not depend on timing
+    for (int q = 0; q < NQ; ++q) {
+      const double v = h[(size_t)b * NQ + q];
+      out[q] = q >= NQ - 2 ? std::fmin(out[q], v) : out[q] + v;
+    }
   return FDCGKS_OK;
 }
 

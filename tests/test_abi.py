@@ -90,6 +90,7 @@ def test_null_arguments():
     assert L.fdcgks_set_state(None, 0, None, None, None, 0, 0) == _lib.EINVAL
     assert L.fdcgks_get_state(None, 0, None, None, None, 0, 0) == _lib.EINVAL
     assert L.fdcgks_set_state_from_samples(None, None, 0) == _lib.EINVAL
+    assert L.fdcgks_diagnostics(None, None) == _lib.EINVAL
     assert L.fdcgks_step_vjp(None, 0.1, None, None, 0) == _lib.EINVAL
     assert L.fdcgks_batch_step(None, 0.5, 1, None, None, None) == _lib.EINVAL
     v = C.c_int64()
