@@ -547,7 +547,8 @@ __device__ __forceinline__ void update_block(const double* __restrict__ S, const
 // evaluates the nodal fluxes of the tile and of a one-node halo along each
 // axis (F, F_t on rows j0..j0+3, columns i0-1..i0+64; G, G_t on columns
 // i0..i0+63, rows j0-1..j0+4) into LDS, then assembles and updates its nodes
-// from there.  The node buffer is neither written nor read.
+// from there.  The node buffer is neither written nor read.  Periodic
+// problems only (the host takes the separate kernels for bounded axes).
 constexpr int FT_X = 66, FT_Y = 6;
 struct NodeFluxShared {
   const double* xs;  // [8][4][66]
