@@ -280,12 +280,14 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
   if (valid) {
     // the normal is y when FAM != G (rho U and rho V swap in the local frame)
     solve_dir<STAGE, FT>(k, (FT)dt, fam != G, rec, tang, F, Ft, Wl, Wr, Wlt, Wrt);
-    // what needs no partner goes out at once
-    e[8 * pl] = chi;
+    // what needs no partner goes out at once (non-temporal stores: the
+    // interface, node and state buffers are read back only by the next
+    // kernel, from HBM, so they are kept out of the caches)
+    __builtin_nontemporal_store((double)(chi), &e[8 * pl]);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      e[(4 + c) * pl] = Ft[c];
-      if (STAGE == 1) e[c * pl] = F[c];
+      __builtin_nontemporal_store((double)(Ft[c]), &e[(4 + c) * pl]);
+      if (STAGE == 1) __builtin_nontemporal_store((double)(F[c]), &e[c * pl]);
     }
   }
 #pragma unroll
@@ -299,12 +301,12 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double st = XCH(4 + c, ty ^ 1);
-      e[(17 + c) * pl] = 0.5 * Wlt[c] + 0.25 * st;
-      e[(21 + c) * pl] = 0.5 * Wrt[c] + 0.25 * st;
+      __builtin_nontemporal_store((double)(0.5 * Wlt[c] + 0.25 * st), &e[(17 + c) * pl]);
+      __builtin_nontemporal_store((double)(0.5 * Wrt[c] + 0.25 * st), &e[(21 + c) * pl]);
       if (STAGE == 1) {
         const double sv = XCH(8 + c, ty ^ 1);
-        e[(9 + c) * pl] = 0.5 * Wl[c] + 0.25 * sv;
-        e[(13 + c) * pl] = 0.5 * Wr[c] + 0.25 * sv;
+        __builtin_nontemporal_store((double)(0.5 * Wl[c] + 0.25 * sv), &e[(9 + c) * pl]);
+        __builtin_nontemporal_store((double)(0.5 * Wr[c] + 0.25 * sv), &e[(13 + c) * pl]);
       }
     }
   }
@@ -388,11 +390,11 @@ __device__ __forceinline__ void node_block(const double* __restrict__ S, double*
   double* n = Nb + (long)grid * 16 * pl + o;
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
-    n[(4 + c) * pl] = (double)Ft[c];
-    n[(12 + c) * pl] = (double)Gt[c];
+    __builtin_nontemporal_store((double)((double)Ft[c]), &n[(4 + c) * pl]);
+    __builtin_nontemporal_store((double)((double)Gt[c]), &n[(12 + c) * pl]);
     if (STAGE == 1) {
-      n[c * pl] = (double)F[c];
-      n[(8 + c) * pl] = (double)G[c];
+      __builtin_nontemporal_store((double)((double)F[c]), &n[c * pl]);
+      __builtin_nontemporal_store((double)((double)G[c]), &n[(8 + c) * pl]);
     }
   }
 }
@@ -487,9 +489,9 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
       const double gy = k.grad_carried ? s[(8 + c) * pl] : Gr[1];
       GX = gx + 0.5 * dt * Grt[0];
       GY = gy + 0.5 * dt * Grt[1];
-      ao[c * pl] = w + dt * L + dt * dt / 6.0 * Lt;
-      ao[(4 + c) * pl] = gx;
-      ao[(8 + c) * pl] = gy;
+      __builtin_nontemporal_store((double)(w + dt * L + dt * dt / 6.0 * Lt), &ao[c * pl]);
+      __builtin_nontemporal_store((double)(gx), &ao[(4 + c) * pl]);
+      __builtin_nontemporal_store((double)(gy), &ao[(8 + c) * pl]);
     } else {
       const double* ai = Ain + (long)grid * 12 * pl + so;
       W = ai[c * pl] + dt * dt / 3.0 * Lt;
@@ -499,9 +501,9 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
     if (zero & (1 << c)) W = 0.0;
     if (zero & (1 << (4 + c))) GX = 0.0;
     if (zero & (1 << (8 + c))) GY = 0.0;
-    out[c * pl] = W;
-    out[(4 + c) * pl] = GX;
-    out[(8 + c) * pl] = GY;
+    __builtin_nontemporal_store((double)(W), &out[c * pl]);
+    __builtin_nontemporal_store((double)(GX), &out[(4 + c) * pl]);
+    __builtin_nontemporal_store((double)(GY), &out[(8 + c) * pl]);
     if (c == 0) rho = W;
     else if (c == 3) ener = W;
     else mom2 = mom2 + W * W;
@@ -771,7 +773,7 @@ __device__ void stage1d_block(double* __restrict__ S, const double* __restrict__
         W[c] = w + 0.5 * dt * L + 0.125 * dt * dt * Lt;
         out[c * pl] = W[c];
         out[(3 + c) * pl] = G + 0.5 * dt * Gt;
-        ao[c * pl] = w + dt * L + dt * dt / 6.0 * Lt;
+        __builtin_nontemporal_store((double)(w + dt * L + dt * dt / 6.0 * Lt), &ao[c * pl]);
         ao[(3 + c) * pl] = G;
       } else {
         const double* ai = Ain + (long)l * 6 * pl + at(g, 0, j);
