@@ -89,7 +89,8 @@ template <class T> inline T sq(T a) { return a * a; }
 // file's own and is mirrored only by oracle/oracle.py.
 struct Par {
   int32_t dim, nx, ny, bc, dual_1d, variant, r, grad_carried;
-  int32_t recon_char, pad_;  // 1: reconstruct characteristic variables (Sec. 3)
+  int32_t recon_char;        // 1: reconstruct characteristic variables (Sec. 3)
+  int32_t flux_order;        // 6 or 8: width of the linear compact flux (Sec. 2.1)
   int32_t side[4];           // 2D boundary of the x-low, x-high, y-low, y-high sides
   double x0, lx, y0, ly;
   double gamma, mu, prandtl;
@@ -613,8 +614,16 @@ void gks_node(const Par& p, int dim, const T* W, const T* Wx, const T* Wy, T* F,
 // Fm, Fc, Fp: interface fluxes at j-1/2, j+1/2, j+3/2; N0, N1: nodal fluxes at
 // j, j+1; chi: the interface path function.  Eq. fd-conservative-flux, and
 // (6-4) with the low-order term divided by 6 (D1) or (6-2).
-template <class T> T compact_flux(const Par& p, T Fm, T Fc, T Fp, T N0, T N1, T chi) {
-  T Fbar = ((Fm + 46.0 * Fc + Fp) - 9.0 * (N0 + N1)) / 30.0;
+// flux_order 8 is the wider stencil that Sec. 2.1 mentions and leaves open,
+// read as: the same averaging conditions (Eq. fd-conservative-flux-recons)
+// imposed also on the nodal cells j-1 and j+2 (nodal fluxes Nm, Np2), so that
+// the flux derivative at node j reaches nodes j-2..j+2.  Seven conditions fix
+// a degree-6 polynomial; its value at the interface is exact to degree 7 by
+// symmetry, with error -h^8 F^(8) / 161280.
+template <class T> T compact_flux(const Par& p, T Fm, T Fc, T Fp, T Nm, T N0, T N1, T Np2, T chi) {
+  T Fbar = p.flux_order == 8
+               ? ((32.0 * (Fm + Fp) + 704.0 * Fc) - 171.0 * (N0 + N1) - 3.0 * (Nm + Np2)) / 420.0
+               : ((Fm + 46.0 * Fc + Fp) - 9.0 * (N0 + N1)) / 30.0;
   if (p.variant == VAR_LINEAR) return Fbar;
   if (p.variant == VAR_6_2) return (1.0 - chi) * Fc + chi * Fbar;
   return (1.0 - chi) * ((8.0 * Fc - N0 - N1) / 6.0) + chi * Fbar;
@@ -780,8 +789,9 @@ template <class T> NodeRes<T> node2d(const Par& p, const Grid2<T>& G, int I, int
 }
 
 // Edge / node results over a box of the lattice: a periodic axis covers one
-// period [0, 2n) and wraps; a bounded axis covers [-3, 2n + 3], everything
-// the operators of its real nodes read.  Interface points (I + J odd) and
+// period [0, 2n) and wraps; a bounded axis covers [-m, 2n + m], everything
+// the operators of its real nodes read (m = 3, or 5 when the flux of order 8
+// reads the nodes two steps beyond a boundary node).  Interface points (I + J odd) and
 // nodes (I + J even) are kept apart, each at (J - J0) * RW + (I - I0) / 2.
 template <class T> struct Store2 {
   int nx, ny, wx, wy, I0, J0, LI, LJ, RW;
@@ -790,8 +800,9 @@ template <class T> struct Store2 {
   void init(const Par& p) {
     nx = p.nx; ny = p.ny;
     wx = bounded(p, 0); wy = bounded(p, 1);
-    I0 = wx ? -3 : 0; LI = wx ? 2 * nx + 7 : 2 * nx;
-    J0 = wy ? -3 : 0; LJ = wy ? 2 * ny + 7 : 2 * ny;
+    const int m = p.flux_order == 8 ? 5 : 3;
+    I0 = wx ? -m : 0; LI = wx ? 2 * nx + 2 * m + 1 : 2 * nx;
+    J0 = wy ? -m : 0; LJ = wy ? 2 * ny + 2 * m + 1 : 2 * ny;
     RW = (LI + 1) / 2;
     E.assign((size_t)RW * LJ, EdgeRes<T>());
     N.assign((size_t)RW * LJ, NodeRes<T>());
@@ -821,16 +832,22 @@ NodeOp<T> node_operator(const Par& p, int I, int J, double h, EdgeF edge, NodeF 
     const EdgeRes<T>& em1 = edge(I - dI, J - dJ);
     const EdgeRes<T>& ep1 = edge(I + dI, J + dJ);
     const EdgeRes<T>& ep3 = edge(I + 3 * dI, J + 3 * dJ);
+    // nodes two steps apart on the lattice; the outer two only for flux_order 8
+    const bool wide = p.flux_order == 8;
     const NodeRes<T>& nm = nodef(I - 2 * dI, J - 2 * dJ);
     const NodeRes<T>& n0 = nodef(I, J);
     const NodeRes<T>& np = nodef(I + 2 * dI, J + 2 * dJ);
+    const NodeRes<T>& nm2 = wide ? nodef(I - 4 * dI, J - 4 * dJ) : n0;
+    const NodeRes<T>& np2 = wide ? nodef(I + 4 * dI, J + 4 * dJ) : n0;
     for (int c = 0; c < 4; ++c) {
       T Nm = ax == 0 ? nm.F[c] : nm.G[c], N0 = ax == 0 ? n0.F[c] : n0.G[c], Np = ax == 0 ? np.F[c] : np.G[c];
       T Nmt = ax == 0 ? nm.Ft[c] : nm.Gt[c], N0t = ax == 0 ? n0.Ft[c] : n0.Gt[c], Npt = ax == 0 ? np.Ft[c] : np.Gt[c];
-      T FR = compact_flux(p, em1.F[ax][c], ep1.F[ax][c], ep3.F[ax][c], N0, Np, ep1.chi[ax]);
-      T FL = compact_flux(p, em3.F[ax][c], em1.F[ax][c], ep1.F[ax][c], Nm, N0, em1.chi[ax]);
-      T FRt = compact_flux(p, em1.Ft[ax][c], ep1.Ft[ax][c], ep3.Ft[ax][c], N0t, Npt, ep1.chi[ax]);
-      T FLt = compact_flux(p, em3.Ft[ax][c], em1.Ft[ax][c], ep1.Ft[ax][c], Nmt, N0t, em1.chi[ax]);
+      T Nm2 = ax == 0 ? nm2.F[c] : nm2.G[c], Np2 = ax == 0 ? np2.F[c] : np2.G[c];
+      T Nm2t = ax == 0 ? nm2.Ft[c] : nm2.Gt[c], Np2t = ax == 0 ? np2.Ft[c] : np2.Gt[c];
+      T FR = compact_flux(p, em1.F[ax][c], ep1.F[ax][c], ep3.F[ax][c], Nm, N0, Np, Np2, ep1.chi[ax]);
+      T FL = compact_flux(p, em3.F[ax][c], em1.F[ax][c], ep1.F[ax][c], Nm2, Nm, N0, Np, em1.chi[ax]);
+      T FRt = compact_flux(p, em1.Ft[ax][c], ep1.Ft[ax][c], ep3.Ft[ax][c], Nmt, N0t, Npt, Np2t, ep1.chi[ax]);
+      T FLt = compact_flux(p, em3.Ft[ax][c], em1.Ft[ax][c], ep1.Ft[ax][c], Nm2t, Nmt, N0t, Npt, em1.chi[ax]);
       r.L[c] = r.L[c] - (FR - FL) / h;
       r.Lt[c] = r.Lt[c] - (FRt - FLt) / h;
       T g = (ep1.Wtl[ax][c] - em1.Wtr[ax][c]) / h;
@@ -1026,17 +1043,18 @@ void stage1d_line(const Par& p, int N, int stage, double dt, const T* S, const T
   Line1<T> L;
   L.load(S, N, p.bc);
   std::vector<Edge1<T>> E(N + 3);  // interface j+1/2 for j = -2..N  ->  E[j + 2]
-  std::vector<Node1<T>> Nd(N + 2);  // node j = -1..N  ->  Nd[j + 1]
+  std::vector<Node1<T>> Nd(N + 4);  // node j = -2..N+1  ->  Nd[j + 2]
   for (int j = -2; j <= N; ++j) E[j + 2] = edge1d(p, L, j, h, dt);
-  for (int j = -1; j <= N; ++j) Nd[j + 1] = node1d(p, L, j, h);
+  for (int j = -2; j <= N + 1; ++j) Nd[j + 2] = node1d(p, L, j, h);
   for (int j = 0; j < N; ++j) {
     const Edge1<T>&em3 = E[j - 2 + 2], &em1 = E[j - 1 + 2], &ep1 = E[j + 2], &ep3 = E[j + 1 + 2];
-    const Node1<T>&nm = Nd[j - 1 + 1], &n0 = Nd[j + 1], &np = Nd[j + 1 + 1];
+    const Node1<T>&nm2 = Nd[j - 2 + 2], &nm = Nd[j - 1 + 2], &n0 = Nd[j + 2], &np = Nd[j + 1 + 2],
+                  &np2 = Nd[j + 2 + 2];
     for (int c = 0; c < 3; ++c) {
-      T FR = compact_flux(p, em1.F[c], ep1.F[c], ep3.F[c], n0.F[c], np.F[c], ep1.chi);
-      T FL = compact_flux(p, em3.F[c], em1.F[c], ep1.F[c], nm.F[c], n0.F[c], em1.chi);
-      T FRt = compact_flux(p, em1.Ft[c], ep1.Ft[c], ep3.Ft[c], n0.Ft[c], np.Ft[c], ep1.chi);
-      T FLt = compact_flux(p, em3.Ft[c], em1.Ft[c], ep1.Ft[c], nm.Ft[c], n0.Ft[c], em1.chi);
+      T FR = compact_flux(p, em1.F[c], ep1.F[c], ep3.F[c], nm.F[c], n0.F[c], np.F[c], np2.F[c], ep1.chi);
+      T FL = compact_flux(p, em3.F[c], em1.F[c], ep1.F[c], nm2.F[c], nm.F[c], n0.F[c], np.F[c], em1.chi);
+      T FRt = compact_flux(p, em1.Ft[c], ep1.Ft[c], ep3.Ft[c], nm.Ft[c], n0.Ft[c], np.Ft[c], np2.Ft[c], ep1.chi);
+      T FLt = compact_flux(p, em3.Ft[c], em1.Ft[c], ep1.Ft[c], nm2.Ft[c], nm.Ft[c], n0.Ft[c], np.Ft[c], em1.chi);
       T Lc = -(FR - FL) / h, Ltc = -(FRt - FLt) / h;
       T g = (ep1.Wl[c] - em1.Wr[c]) / h, gt = (ep1.Wlt[c] - em1.Wrt[c]) / h;
       if (p.grad_carried) g = S[(3 + c) * N + j];
@@ -1113,8 +1131,9 @@ void orc_gks_node(const Par* p, int dim, const double* W, const double* Wx, cons
   int n = dim + 2;
   gks_node(*p, dim, W, Wx, Wy, out, out + n, out + 2 * n, out + 3 * n);
 }
-double orc_compact_flux(const Par* p, double Fm, double Fc, double Fp, double N0, double N1, double chi) {
-  return compact_flux(*p, Fm, Fc, Fp, N0, N1, chi);
+double orc_compact_flux(const Par* p, double Fm, double Fc, double Fp, double Nm, double N0, double N1, double Np2,
+                        double chi) {
+  return compact_flux(*p, Fm, Fc, Fp, Nm, N0, N1, Np2, chi);
 }
 // The S2O4 combination applied to one scalar with caller-given L and L_t
 // (stage 2 also takes the stage-1 accumulator).  out2: stage value, accumulator.
@@ -1316,8 +1335,8 @@ void orc_intermediates1d(const Par* p, double dt, const double* S, double* E, do
     }
     E[6 * ne + k] = Ev[k].chi;
   }
-  for (long k = 0; k < nn; ++k)
-    for (int c = 0; c < 3; ++c) { Nn[c * nn + k] = Nv[k].F[c]; Nn[(3 + c) * nn + k] = Nv[k].Ft[c]; }
+  for (long k = 0; k < nn; ++k)  // the kept nodes start at j = -2
+    for (int c = 0; c < 3; ++c) { Nn[c * nn + k] = Nv[k + 1].F[c]; Nn[(3 + c) * nn + k] = Nv[k + 1].Ft[c]; }
 }
 
 }  // extern "C"

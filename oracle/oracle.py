@@ -39,7 +39,7 @@ class Par(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32),
         ("dual_1d", C.c_int32), ("variant", C.c_int32), ("r", C.c_int32), ("grad_carried", C.c_int32),
-        ("recon_char", C.c_int32), ("pad_", C.c_int32), ("side", C.c_int32 * 4),
+        ("recon_char", C.c_int32), ("flux_order", C.c_int32), ("side", C.c_int32 * 4),
         ("x0", C.c_double), ("lx", C.c_double), ("y0", C.c_double), ("ly", C.c_double),
         ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
         ("C", C.c_double), ("eps", C.c_double), ("eps_a", C.c_double),
@@ -55,11 +55,13 @@ BCS = {"periodic": 0, "zero_gradient": 1, "reflecting": 2, "no_slip": 3}
 def make_par(*, dim=2, nx=16, ny=16, x0=0.0, lx=1.0, y0=0.0, ly=None, bc="periodic", dual_1d=0,
              gamma=1.4, mu=0.0, prandtl=1.0, variant="6-4", geno_C=20.0, geno_r=3,
              geno_eps=1e-15, geno_eps_a=1e-6, d_central=8.0, d_side=1.0, tau_c1=0.0,
-             tau_c2=1.0, grad_carried=0, recon_vars="conservative", sides=None, **_ignored) -> Par:
+             tau_c2=1.0, grad_carried=0, recon_vars="conservative", sides=None, flux_order=6, **_ignored) -> Par:
     """Problem description with the oracle's own field layout.  Defaults are the
     readings of the paper (C = 20, r = 3, eps = 1e-15, eps_a = 1e-6, d = 8/1,
     tau = 0 * dt + dt |dp|/(p_l+p_r) for Euler: D11 as amended).  2D sides
-    (x-low, x-high, y-low, y-high) default to `bc` on every side."""
+    (x-low, x-high, y-low, y-high) default to `bc` on every side.  flux_order
+    6 is the compact flux of Sec. 2.1; 8 the wider stencil over nodes
+    j-1..j+2 (a reading: the paper mentions it without formulas)."""
     p = Par()
     p.dim, p.nx, p.ny = dim, nx, (ny if dim == 2 else 1)
     p.bc = BCS[bc] if isinstance(bc, str) else int(bc)
@@ -78,6 +80,9 @@ def make_par(*, dim=2, nx=16, ny=16, x0=0.0, lx=1.0, y0=0.0, ly=None, bc="period
     p.C, p.eps, p.eps_a, p.d_central, p.d_side = geno_C, geno_eps, geno_eps_a, d_central, d_side
     p.tau_c1, p.tau_c2 = tau_c1, tau_c2
     p.grad_carried = int(grad_carried)
+    if int(flux_order) not in (6, 8):
+        raise ValueError("flux_order is 6 or 8")
+    p.flux_order = int(flux_order)
     p.recon_char = {"conservative": 0, "characteristic": 1}[recon_vars] if isinstance(recon_vars, str) \
         else int(recon_vars)
     return p
@@ -106,7 +111,7 @@ def lib():
             "orc_qcoef": (None, [d, d, _dp]),
             "orc_gks_interface": (None, [P, i, _dp, _dp, _dp, _dp, _dp, d, _dp]),
             "orc_gks_node": (None, [P, i, _dp, _dp, _dp, _dp]),
-            "orc_compact_flux": (d, [P, d, d, d, d, d, d]),
+            "orc_compact_flux": (d, [P, d, d, d, d, d, d, d, d]),
             "orc_s2o4_scalar": (None, [i, d, d, d, d, d, _dp]),
             "orc_stage2d": (None, [P, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
             "orc_dt2d": (d, [P, _dp, _dp, d]),
@@ -207,8 +212,10 @@ def gks_node(par, dim, W, Wx, Wy=None):
     return {"F": out[:n], "Ft": out[n:2 * n], "G": out[2 * n:3 * n], "Gt": out[3 * n:]}
 
 
-def compact_flux(par, Fm, Fc, Fp, N0, N1, chi):
-    return lib().orc_compact_flux(C.byref(par), Fm, Fc, Fp, N0, N1, chi)
+def compact_flux(par, Fm, Fc, Fp, N0, N1, chi, Nm=0.0, Np2=0.0):
+    """Interface fluxes Fm, Fc, Fp at j-1/2, j+1/2, j+3/2; nodal fluxes N0, N1
+    at j, j+1 (and Nm, Np2 at j-1, j+2, read by flux_order 8)."""
+    return lib().orc_compact_flux(C.byref(par), Fm, Fc, Fp, Nm, N0, N1, Np2, chi)
 
 
 def s2o4_scalar(stage, dt, W, L, Lt, acc=0.0):

@@ -51,14 +51,14 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1.0))
 
 
-@pytest.mark.parametrize("bx,by", [(1, 0), (0, 1), (1, 1)])
-def test_reflecting_equals_mirrored_periodic(oracle, bx, by):
+@pytest.mark.parametrize("bx,by,order", [(1, 0, 6), (0, 1, 6), (1, 1, 6), (1, 1, 8)])
+def test_reflecting_equals_mirrored_periodic(oracle, bx, by, order):
     nx, ny = 16, 12
     sides = ["reflecting" if bx else "periodic"] * 2 + ["reflecting" if by else "periodic"] * 2
     fn = WL.mirror_flow(LX, LY, bx, by)
-    par, P, D = _walled(oracle, nx, ny, bx, by, sides, fn)
+    par, P, D = _walled(oracle, nx, ny, bx, by, sides, fn, flux_order=order)
     assert D.shape == (12, ny + by, nx + bx)
-    qar, Q, E = _doubled(oracle, nx, ny, bx, by, fn)
+    qar, Q, E = _doubled(oracle, nx, ny, bx, by, fn, flux_order=order)
     dt = 0.2 * (LX / nx) / 3
     a = oracle.stage2d(par, 1, dt, P, D)
     b = oracle.stage2d(qar, 1, dt, Q, E)
@@ -71,7 +71,8 @@ def test_reflecting_equals_mirrored_periodic(oracle, bx, by):
     assert _rel(oD, _restrict(qD, nx, ny, bx, by, 1)) <= 1e-12
 
 
-def test_reflecting_1d_equals_mirrored_periodic(oracle):
+@pytest.mark.parametrize("order", [6, 8])
+def test_reflecting_1d_equals_mirrored_periodic(oracle, order):
     N = 40
     h = 1.0 / N
     x = (np.arange(2 * N) + 0.5) * h - 1.0
@@ -86,8 +87,8 @@ def test_reflecting_1d_equals_mirrored_periodic(oracle):
     S2[0, :3] = state(x)
     S2[0, 3:] = (state(x + h / 2) - state(x - h / 2)) / h
     S1 = np.ascontiguousarray(S2[:, :, N:])
-    p1 = oracle_par(oracle, settings(dim=1, nx=N, lx=1.0, bc="reflecting"))
-    p2 = oracle_par(oracle, settings(dim=1, nx=2 * N, lx=2.0))
+    p1 = oracle_par(oracle, settings(dim=1, nx=N, lx=1.0, bc="reflecting", flux_order=order))
+    p2 = oracle_par(oracle, settings(dim=1, nx=2 * N, lx=2.0, flux_order=order))
     a, _, k1 = oracle.step1d(p1, S1, 5, cfl=0.5)
     b, _, k2 = oracle.step1d(p2, S2, 5, cfl=0.5)
     assert k1 == k2 == 5
@@ -123,7 +124,8 @@ def test_no_slip_equals_reflecting_without_tangential_flow(oracle):
         assert _rel(a, b) <= 1e-15
 
 
-def test_zero_gradient_matches_wider_periodic_while_quiet(oracle):
+@pytest.mark.parametrize("order", [6, 8])
+def test_zero_gradient_matches_wider_periodic_while_quiet(oracle, order):
     """With the data uniform within 8 nodes of every side, one step on a
     zero-gradient domain equals the same step on a periodic domain 8 nodes
     wider on each side, restricted (nothing has reached the boundary)."""
@@ -139,14 +141,14 @@ def test_zero_gradient_matches_wider_periodic_while_quiet(oracle):
         return np.where(far[None], bump(0.0 * X, 0.0 * Y), W)
 
     P, D = WL.sample_bounded(quiet, n, n, h, 1, 1)
-    par = oracle_par(oracle, settings(dim=2, nx=n, ny=n, lx=1.0, bc="zero_gradient"))
+    par = oracle_par(oracle, settings(dim=2, nx=n, ny=n, lx=1.0, bc="zero_gradient", flux_order=order))
     # the same data embedded in a uniform frame of m nodes
     Q = np.zeros((12, n + 2 * m, n + 2 * m))
     Q[0:4] = P[0:4, 0, 0][:, None, None]
     E = Q.copy()
     Q[:, m:m + n, m:m + n] = P
     E[:, m - 1:m + n, m - 1:m + n] = D
-    qar = oracle_par(oracle, settings(dim=2, nx=n + 2 * m, ny=n + 2 * m, lx=1.0 + 2 * m * h))
+    qar = oracle_par(oracle, settings(dim=2, nx=n + 2 * m, ny=n + 2 * m, lx=1.0 + 2 * m * h, flux_order=order))
     dt = 0.2 * h / 3
     a = oracle.step2d(par, P, D, 1, dt=dt)
     b = oracle.step2d(qar, Q, E, 1, dt=dt)

@@ -86,6 +86,65 @@ def test_62_and_blend(oracle):
     assert oracle.compact_flux(p62, *a, 0.25) == pytest.approx(0.75 * 1.1 + 0.25 * Fb, abs=1e-15)
 
 
+def _brute_wide_flux_coeffs(h=1.0):
+    """The seven-condition solve for flux_order 8: the conditions of
+    _brute_flux_coeffs plus the averages over the node cells of j-1 and j+2
+    (a degree-6 polynomial).  Weights on (F_{j-1/2}, F_{j+1/2}, F_{j+3/2},
+    F_{j-1}, F_j, F_{j+1}, F_{j+2})."""
+    cells = [(-h, 0.0), (0.0, h), (h, 2 * h)]
+    nodes = [(-1.5 * h, -0.5 * h), (-0.5 * h, 0.5 * h), (0.5 * h, 1.5 * h), (1.5 * h, 2.5 * h)]
+    A = np.zeros((7, 7))
+    for r, (a, b) in enumerate(cells + nodes):
+        for k in range(7):
+            A[r, k] = (b ** (k + 1) - a ** (k + 1)) / ((k + 1) * (b - a))
+    ev = np.array([(0.5 * h) ** k for k in range(7)])
+    return np.linalg.solve(A.T, ev)
+
+
+def test_wide_linear_flux_is_the_seven_condition_solution(oracle):
+    p = _par(oracle, variant="linear", flux_order=8)
+    w = _brute_wide_flux_coeffs()
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        Fm, Fc, Fp, Nm, N0, N1, Np2 = rng.normal(size=7)
+        want = w @ np.array([Fm, Fc, Fp, Nm, N0, N1, Np2])
+        got = oracle.compact_flux(p, Fm, Fc, Fp, N0, N1, 0.3, Nm=Nm, Np2=Np2)
+        assert abs(got - want) < 1e-13
+
+
+def test_wide_flux_truncation_constant(oracle):
+    """Order 8: exact for polynomials of degree 7 (symmetry about the
+    interface), leading error -h^8 F^(8) / 161280 (from the moments of the
+    seven-condition solve)."""
+    p = _par(oracle, variant="linear", flux_order=8)
+    w = _brute_wide_flux_coeffs()
+    cells = [(-1.0, 0.0), (0.0, 1.0), (1.0, 2.0), (-1.5, -0.5), (-0.5, 0.5), (0.5, 1.5), (1.5, 2.5)]
+    mom = lambda k: np.array([(b ** (k + 1) - a ** (k + 1)) / ((k + 1) * (b - a)) for a, b in cells])  # noqa: E731
+    assert abs(w @ mom(7) - 0.5 ** 7) < 1e-12
+    assert abs((w @ mom(8) - 0.5 ** 8) / math.factorial(8) + 1.0 / 161280.0) < 1e-15
+    for h in (0.4, 0.2, 0.1):
+        F = lambda x: math.sin(x + 0.3)  # noqa: E731
+        avg = lambda a, b: (math.cos(a + 0.3) - math.cos(b + 0.3)) / (b - a)  # noqa: E731
+        Fm, Fc, Fp = avg(-h, 0), avg(0, h), avg(h, 2 * h)
+        Nm, N0, N1, Np2 = avg(-1.5 * h, -0.5 * h), avg(-0.5 * h, 0.5 * h), avg(0.5 * h, 1.5 * h), avg(1.5 * h, 2.5 * h)
+        err = oracle.compact_flux(p, Fm, Fc, Fp, N0, N1, 1.0, Nm=Nm, Np2=Np2) - F(0.5 * h)
+        lead = -h ** 8 * math.sin(0.5 * h + 0.3) / 161280.0
+        assert abs(err - lead) < 0.05 * abs(lead), (h, err, lead)
+
+
+def test_wide_flux_keeps_the_low_order_blend(oracle):
+    """flux_order changes only the linear flux F-bar: (6-4) and (6-2) blend it
+    with the same low-order fluxes and chi."""
+    a = (0.3, 1.1, -0.4, 0.8, 0.9)
+    Fb = oracle.compact_flux(_par(oracle, variant="linear", flux_order=8), *a, 0.0, Nm=0.2, Np2=-0.7)
+    lo = {"6-4": (8 * 1.1 - 0.8 - 0.9) / 6, "6-2": 1.1}
+    for v, L in lo.items():
+        q = _par(oracle, variant=v, flux_order=8)
+        assert oracle.compact_flux(q, *a, 0.25, Nm=0.2, Np2=-0.7) == pytest.approx(0.75 * L + 0.25 * Fb, abs=1e-15)
+    with pytest.raises(ValueError):
+        _par(oracle, flux_order=7)
+
+
 # --------------------------------------------------- reconstruction, Sec. 3
 def _poly_data(P, h, centers):
     """Nodal values and interval-averaged derivatives of polynomial P."""

@@ -146,6 +146,64 @@ def test_2d_accuracy_against_table_2(oracle):
     assert np.log2(a / c) > 5.5 and np.log2(b / d) > 5.5
 
 
+def test_wide_flux_raises_the_order_1d(oracle):
+    """flux_order 8 (the wider stencil of Sec. 2.1) on the same 1D test: the
+    flux error drops to O(h^8), so the order rises above 7 (the seventh-order
+    reconstruction of Sec. 3.1 now limits it) and the errors fall below those
+    of the sixth-order flux."""
+    errs = {}
+    for order in (6, 8):
+        errs[order] = []
+        for N in (8, 16, 32):
+            h = 2.0 / N
+            pr = WL.advection1d(N, noise=0, dual=False)
+            par = oracle.make_par(**settings(dim=1, nx=N, lx=2.0, variant="6-2", flux_order=order))
+            dt = 0.1 * h * (h / 0.25) / (1 + np.sqrt(1.4 / 0.8))
+            nst = int(np.ceil(2.0 / dt))
+            S, t, k = oracle.step1d(par, pr.S, nst, dt=2.0 / nst)
+            errs[order].append(np.abs(S[0, 0] - WL.advection1d_exact(N, 2.0)[0]).mean())
+    e6, e8 = errs[6], errs[8]
+    print("L1, flux order 6:", e6, " order 8:", e8)
+    assert all(np.log2(a / b) > 7.0 for a, b in zip(e8, e8[1:]))
+    assert e8[1] < 0.5 * e6[1] and e8[2] < 0.2 * e6[2]
+
+
+def test_wide_flux_raises_the_order_2d(oracle):
+    errs = {}
+    for order in (6, 8):
+        errs[order] = []
+        for N in (5, 10):
+            h = 2.0 / N
+            pr = WL.advection2d(N)
+            par = _p2(oracle, N, lx=2.0, variant="6-2", flux_order=order)
+            dt = 0.1 * h * (h / 0.4) / (1 + np.sqrt(1.4 / 0.8))
+            nst = int(np.ceil(2.0 / dt))
+            P, D, t, k = oracle.step2d(par, pr.P, pr.D, nst, dt=2.0 / nst)
+            eP, eD = WL.advection2d_exact(N, 2.0)
+            errs[order].append((np.abs(P[0] - eP[0]).sum() * h * h, np.abs(D[0] - eD[0]).max()))
+    (a, da), (b, db) = errs[8]
+    assert np.log2(a / b) > 7.0 and np.log2(da / db) > 7.0
+    assert b < 0.7 * errs[6][1][0]
+
+
+@pytest.mark.parametrize("case", ["free_stream", "conservation"])
+def test_wide_flux_invariants(oracle, case):
+    if case == "free_stream":
+        n = 9
+        W = WL.conservative(1.3, 0.4, -0.7, 2.0)
+        P = np.zeros((12, n, n))
+        P[0:4] = W[:, None, None]
+        oP, oD, t, k = oracle.step2d(_p2(oracle, n, flux_order=8), P, P.copy(), 2, dt=0.01)
+        assert np.abs(oP - P).max() < 1e-14 and np.abs(oD - P).max() < 1e-14
+        return
+    pr = WL.riemann2d(12, seed=2)
+    oP, oD, t, k = oracle.step2d(_p2(oracle, pr.nx, pr.ny, lx=pr.lx, flux_order=8), pr.P, pr.D, 2,
+                                 dt=0.2 * pr.h / 3)
+    for A, B in ((pr.P, oP), (pr.D, oD)):
+        for c in range(4):
+            assert abs(B[c].sum() - A[c].sum()) <= 1e-13 * np.abs(A[c]).sum(), c
+
+
 def test_1d_primary_and_shifted_copy_agree(oracle):
     """The shifted copy (reading D24) solves the same problem on nodes offset
     by h/2: both converge to the exact solution, so they agree to
