@@ -76,6 +76,15 @@ enum { FDCGKS_BC_PERIODIC = 0, FDCGKS_BC_ZERO_GRADIENT = 1, FDCGKS_BC_REFLECTING
  * divided by 6; (6-2) = Eq. fd-conservative-flux-1; LINEAR = linear compact
  * flux and linear reconstruction (no GENO). */
 enum { FDCGKS_FLUX_6_4 = 0, FDCGKS_FLUX_6_2 = 1, FDCGKS_FLUX_LINEAR = 2 };
+/* Width of the linear compact flux (flux_order): 6 = Eq. fd-conservative-flux
+ * (nodal fluxes at j, j+1); 8 = the wider stencil Sec. 2.1 mentions, read as
+ * the averaging conditions of Eq. fd-conservative-flux-recons imposed also on
+ * the nodal cells j-1 and j+2:
+ *   F = (32 (F_{j-1/2} + F_{j+3/2}) + 704 F_{j+1/2} - 171 (F_j + F_{j+1})
+ *        - 3 (F_{j-1} + F_{j+2})) / 420,
+ * exact to degree 7.  The flux variant's low-order term and blend are the same
+ * for both.  Order 8 is available to fdcgks_problem steps (1D and 2D, every
+ * boundary); the step adjoint and batches reject it with FDCGKS_EINVAL. */
 /* Precision of the gas-kinetic solver; reconstruction and update stay FP64. */
 enum { FDCGKS_FP64 = 0, FDCGKS_FP32_FLUX = 1 };
 /* Base of the averaged-gradient update (Eq. eq-interface-update): the gradient
@@ -101,6 +110,7 @@ typedef struct fdcgks_params {
   int32_t grad_update;    /* FDCGKS_GRAD_* */
   int32_t geno_r;         /* exponent r of the GENO smoothness ratio, 1..8 (default 3) */
   int32_t recon_vars;     /* FDCGKS_RECON_* (default conservative) */
+  int32_t flux_order;     /* 6 (default) or 8, see above */
   int32_t side[4];        /* 2D: FDCGKS_BC_* of the x-low, x-high, y-low, y-high sides, -1 = bc (default);
                              a periodic side needs a periodic opposite side */
   double x0, lx, y0, ly;  /* domain origin and lengths; 2D needs lx/nx == ly/ny */

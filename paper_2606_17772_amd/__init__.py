@@ -38,7 +38,8 @@ def make_params(**kw) -> Params:
     """fdcgks_params from keywords (names of the C struct; also
     variant='6-4'|'6-2'|'linear', bc='periodic'|'zero_gradient'|'reflecting'|
     'no_slip', sides=(x-low, x-high, y-low, y-high) boundary names or codes,
-    recon_vars='conservative'|'characteristic', fp32_flux=bool)."""
+    recon_vars='conservative'|'characteristic', fp32_flux=bool,
+    flux_order=6|8)."""
     p = default_params()
     kw = dict(kw)
     if "variant" in kw:

@@ -28,7 +28,7 @@ class Params(C.Structure):
     _fields_ = [
         ("dim", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("bc", C.c_int32),
         ("dual_1d", C.c_int32), ("flux_variant", C.c_int32), ("flux_precision", C.c_int32),
-        ("grad_update", C.c_int32), ("geno_r", C.c_int32), ("recon_vars", C.c_int32),
+        ("grad_update", C.c_int32), ("geno_r", C.c_int32), ("recon_vars", C.c_int32), ("flux_order", C.c_int32),
         ("side", C.c_int32 * 4),
         ("x0", C.c_double), ("lx", C.c_double), ("y0", C.c_double), ("ly", C.c_double),
         ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),

@@ -371,14 +371,22 @@ __device__ __forceinline__ void node_derivs(const double* __restrict__ B, const 
   }
 }
 
-// Nodes i in [-1 - sx, nx], j in [-1 - sy, ny] of grid `grid`; block (bx, by)
-// of blockDim.x x blockDim.y nodes.
+// Nodes whose fluxes the update reads beyond a grid's own nodes: one along
+// each axis, two for the order-8 flux.
+__host__ __device__ __forceinline__ int node_reach(const Consts& k) { return k.flux_order == 8 ? 2 : 1; }
+
+// Nodes i in [-w - sx, nx - 1 + w], j in [-w - sy, ny - 1 + w] of the dual
+// grid and i, j in [-w, n - 1 + w] of the primary grid (w = node_reach;
+// batches pass 1): w beyond the grid's own nodes, whose dual nodes start at
+// -1 on a bounded axis.  (A primary row at -w - 1 would read state row -w - 2,
+// beyond the 3-row halo when w = 2.)  Block (bx, by) of blockDim.x x
+// blockDim.y nodes.
 template <int STAGE, class FT, bool CHAR = false>
 __device__ __forceinline__ void node_block(const double* __restrict__ S, double* __restrict__ Nb, const Geo& g,
-                                           const Consts& k, int bx, int by, int grid) {
-  const int i = bx * blockDim.x + threadIdx.x - 1 - g.sx;
-  const int j = by * blockDim.y + threadIdx.y - 1 - g.sy;
-  if (i > g.nx || j > g.ny) return;
+                                           const Consts& k, int bx, int by, int grid, int w) {
+  const int i = bx * blockDim.x + threadIdx.x - w - (grid ? g.sx : 0);
+  const int j = by * blockDim.y + threadIdx.y - w - (grid ? g.sy : 0);
+  if (i > g.nx - 1 + w || j > g.ny - 1 + w) return;
   const long pl = g.plane, o = at(g, j, i);
   const double* B = S + (long)grid * 12 * pl + (grid ? g.dshift : 0);
   FT W[4], Wx[4], Wy[4];
@@ -405,7 +413,7 @@ __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, d
   if (sc->stop) return;
   int t;
   if (!xcd_tile(blockIdx.x, gridDim.x, ntiles, t)) return;
-  node_block<STAGE, FT, CHAR>(S, Nb, g, k, t % tiles_x, t / tiles_x, blockIdx.z);
+  node_block<STAGE, FT, CHAR>(S, Nb, g, k, t % tiles_x, t / tiles_x, blockIdx.z, node_reach(k));
 }
 
 // ------------------------------------------------------ assemble + update
@@ -415,7 +423,9 @@ __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, d
 // dual x -> Y, slot 1, r = 1;    dual y -> X, slot 1, r = 1.
 // The nodal fluxes come through an accessor nf(a, q, off): component q of
 // (F, F_t) along x (a = 0) or (G, G_t) along y (a = 1), q = 0..3 values and
-// 4..7 time derivatives, at the node `off` = -1, 0, +1 along the axis.  A
+// 4..7 time derivatives, at the node `off` = -1, 0, +1 along the axis (-2 and
+// +2 as well for the order-8 flux, WIDE: a template argument, so that the
+// order-6 kernels keep their register budget).  A
 // non-physical result (rho <= 0, p <= 0, NaN) sets the stop flag and records
 // where (`member` names the batch member, 0 for a single problem).
 // Components are processed one at a time (the loop is not unrolled): each
@@ -424,7 +434,7 @@ __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, d
 #ifndef FDCGKS_UPDATE_UNROLL
 #define FDCGKS_UPDATE_UNROLL 1
 #endif
-template <int STAGE, class NF>
+template <int STAGE, class NF, bool WIDE = false>
 __device__ __forceinline__ void update_node(const double* __restrict__ S, const double* __restrict__ E,
                                             const NF& nf, const double* __restrict__ Ain, double* __restrict__ Out,
                                             double* __restrict__ Aout, const Geo& g, const Consts& k, double dt,
@@ -465,19 +475,37 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
       const double chiR = e[8 * pl + r * st], chiL = e[8 * pl + (r - 1) * st];
       const double* f = e + (0 + c) * pl;
       const double* ft = e + (4 + c) * pl;
-      if (STAGE == 1) {
-        const double n0 = nf(a, c, 0);
-        double FR = fdk::compact_flux(k.variant, f[(r - 1) * st], f[r * st], f[(r + 1) * st], n0, nf(a, c, 1), chiR);
-        double FL = fdk::compact_flux(k.variant, f[(r - 2) * st], f[(r - 1) * st], f[r * st], nf(a, c, -1), n0, chiL);
-        L = L - (FR - FL) * g.invh;
-        Gr[a] = (e[(9 + c) * pl + r * st] - e[(13 + c) * pl + (r - 1) * st]) * g.invh;
+      if constexpr (WIDE) {
+        if (STAGE == 1) {
+          const double n0 = nf(a, c, 0), nm = nf(a, c, -1), np = nf(a, c, 1);
+          double FR = fdk::compact_flux8(k.variant, f[(r - 1) * st], f[r * st], f[(r + 1) * st], nm, n0, np,
+                                         nf(a, c, 2), chiR);
+          double FL = fdk::compact_flux8(k.variant, f[(r - 2) * st], f[(r - 1) * st], f[r * st], nf(a, c, -2), nm,
+                                         n0, np, chiL);
+          L = L - (FR - FL) * g.invh;
+          Gr[a] = (e[(9 + c) * pl + r * st] - e[(13 + c) * pl + (r - 1) * st]) * g.invh;
+        }
+        const double nt0 = nf(a, 4 + c, 0), ntm = nf(a, 4 + c, -1), ntp = nf(a, 4 + c, 1);
+        double FRt = fdk::compact_flux8(k.variant, ft[(r - 1) * st], ft[r * st], ft[(r + 1) * st], ntm, nt0, ntp,
+                                        nf(a, 4 + c, 2), chiR);
+        double FLt = fdk::compact_flux8(k.variant, ft[(r - 2) * st], ft[(r - 1) * st], ft[r * st], nf(a, 4 + c, -2),
+                                        ntm, nt0, ntp, chiL);
+        Lt = Lt - (FRt - FLt) * g.invh;
+      } else {
+        if (STAGE == 1) {
+          const double n0 = nf(a, c, 0);
+          double FR = fdk::compact_flux(k.variant, f[(r - 1) * st], f[r * st], f[(r + 1) * st], n0, nf(a, c, 1), chiR);
+          double FL = fdk::compact_flux(k.variant, f[(r - 2) * st], f[(r - 1) * st], f[r * st], nf(a, c, -1), n0, chiL);
+          L = L - (FR - FL) * g.invh;
+          Gr[a] = (e[(9 + c) * pl + r * st] - e[(13 + c) * pl + (r - 1) * st]) * g.invh;
+        }
+        const double nt0 = nf(a, 4 + c, 0);
+        double FRt = fdk::compact_flux(k.variant, ft[(r - 1) * st], ft[r * st], ft[(r + 1) * st], nt0,
+                                       nf(a, 4 + c, 1), chiR);
+        double FLt = fdk::compact_flux(k.variant, ft[(r - 2) * st], ft[(r - 1) * st], ft[r * st], nf(a, 4 + c, -1),
+                                       nt0, chiL);
+        Lt = Lt - (FRt - FLt) * g.invh;
       }
-      const double nt0 = nf(a, 4 + c, 0);
-      double FRt = fdk::compact_flux(k.variant, ft[(r - 1) * st], ft[r * st], ft[(r + 1) * st], nt0, nf(a, 4 + c, 1),
-                                     chiR);
-      double FLt = fdk::compact_flux(k.variant, ft[(r - 2) * st], ft[(r - 1) * st], ft[r * st], nf(a, 4 + c, -1), nt0,
-                                     chiL);
-      Lt = Lt - (FRt - FLt) * g.invh;
       Grt[a] = (e[(17 + c) * pl + r * st] - e[(21 + c) * pl + (r - 1) * st]) * g.invh;
     }
     double W, GX, GY;
@@ -531,7 +559,7 @@ struct NodeFluxGlobal {
 
 // Block (bx, by) of blockDim.x x blockDim.y nodes; the dual grid starts at
 // i = -sx, j = -sy (its boundary nodes on bounded axes).
-template <int STAGE>
+template <int STAGE, bool WIDE>
 __device__ __forceinline__ void update_block(const double* __restrict__ S, const double* __restrict__ E,
                                              const double* __restrict__ Nb, const double* __restrict__ Ain,
                                              double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
@@ -541,7 +569,7 @@ __device__ __forceinline__ void update_block(const double* __restrict__ S, const
   const int j = by * blockDim.y + threadIdx.y - (grid ? g.sy : 0);
   if (i >= g.nx || j >= g.ny) return;
   const NodeFluxGlobal nf{Nb + (long)grid * 16 * g.plane + at(g, j, i), g.plane, g.pitch};
-  update_node<STAGE>(S, E, nf, Ain, Out, Aout, g, k, dt, i, j, grid, sc, member);
+  update_node<STAGE, NodeFluxGlobal, WIDE>(S, E, nf, Ain, Out, Aout, g, k, dt, i, j, grid, sc, member);
 }
 
 // ------------------------------------------- node sweep fused into update
@@ -550,7 +578,8 @@ __device__ __forceinline__ void update_block(const double* __restrict__ S, const
 // axis (F, F_t on rows j0..j0+3, columns i0-1..i0+64; G, G_t on columns
 // i0..i0+63, rows j0-1..j0+4) into LDS, then assembles and updates its nodes
 // from there.  The node buffer is neither written nor read.  Periodic
-// problems only (the host takes the separate kernels for bounded axes).
+// problems with the order-6 flux only (the host takes the separate kernels
+// for bounded axes and for the order-8 flux, which reads two nodes away).
 constexpr int FT_X = 66, FT_Y = 6;
 struct NodeFluxShared {
   const double* xs;  // [8][4][66]
@@ -611,14 +640,14 @@ __global__ __launch_bounds__(256) void k_nodeupd2d(const double* __restrict__ S,
   update_node<STAGE>(S, E, nf, Ain, Out, Aout, g, k, sc->dt, i, j, grid, sc, 0);
 }
 
-template <int STAGE>
+template <int STAGE, bool WIDE>
 // stage 2 reads and writes half the planes of stage 1: 80 VGPRs, 6 waves/SIMD
 __global__ __launch_bounds__(256, STAGE == 2 ? 6 : 4) void k_update2d(const double* __restrict__ S, const double* __restrict__ E,
                                                   const double* __restrict__ Nb, const double* __restrict__ Ain,
                                                   double* __restrict__ Out, double* __restrict__ Aout, Geo g,
                                                   Consts k, Scal* __restrict__ sc) {
   if (sc->stop) return;
-  update_block<STAGE>(S, E, Nb, Ain, Out, Aout, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z, sc, 0);
+  update_block<STAGE, WIDE>(S, E, Nb, Ain, Out, Aout, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z, sc, 0);
 }
 
 // ================================================================== 1D
@@ -627,7 +656,7 @@ __global__ __launch_bounds__(256, STAGE == 2 ? 6 : 4) void k_update2d(const doub
 // state plane = line*6 + field*3 + comp (field 0 W, 1 Wx); interface buffer
 // plane = line*19 + q for the interface j+1/2 stored at column j, j in
 // [-2, N]: F[3], Ft[3], chi, Wl[3], Wr[3], Wlt[3], Wrt[3]; node buffer plane
-// = line*6 + q at column j in [-1, N]: F[3], Ft[3].
+// = line*6 + q at column j in [-w, N - 1 + w] (w = node_reach): F[3], Ft[3].
 // One workgroup advances every line of the problem through whole steps:
 // block barriers separate halo fill, interface and node sweeps, and update;
 // interface and node results stay in global memory (cache resident at these
@@ -705,9 +734,10 @@ __device__ void stage1d_block(double* __restrict__ S, const double* __restrict__
       }
     }
   }
-  // nodes j in [-1, N]
-  for (int q = threadIdx.x; q < lines * (N + 2); q += blockDim.x) {
-    const int l = q / (N + 2), j = q % (N + 2) - 1;
+  // nodes j in [-w, N - 1 + w]
+  const int w = node_reach(k);
+  for (int q = threadIdx.x; q < lines * (N + 2 * w); q += blockDim.x) {
+    const int l = q / (N + 2 * w), j = q % (N + 2 * w) - w;
     const double* B = S + (long)l * 6 * pl;
     FT W[3], Wx[3], F[3], Ft[3];
     if constexpr (CHAR) {
@@ -758,13 +788,18 @@ __device__ void stage1d_block(double* __restrict__ S, const double* __restrict__
       const double* ft = e + (3 + c) * pl;
       const double* nf = n + c * pl;
       const double* nft = n + (3 + c) * pl;
-      double FRt = fdk::compact_flux(k.variant, ft[-1], ft[0], ft[1], nft[0], nft[1], chiR);
-      double FLt = fdk::compact_flux(k.variant, ft[-2], ft[-1], ft[0], nft[-1], nft[0], chiL);
+      const bool wide = k.flux_order == 8;
+      double FRt = wide ? fdk::compact_flux8(k.variant, ft[-1], ft[0], ft[1], nft[-1], nft[0], nft[1], nft[2], chiR)
+                        : fdk::compact_flux(k.variant, ft[-1], ft[0], ft[1], nft[0], nft[1], chiR);
+      double FLt = wide ? fdk::compact_flux8(k.variant, ft[-2], ft[-1], ft[0], nft[-2], nft[-1], nft[0], nft[1], chiL)
+                        : fdk::compact_flux(k.variant, ft[-2], ft[-1], ft[0], nft[-1], nft[0], chiL);
       double Lt = -(FRt - FLt) * g.invh;
       double Gt = (e[(13 + c) * pl] - e[(16 + c) * pl - 1]) * g.invh;
       if (STAGE == 1) {
-        double FR = fdk::compact_flux(k.variant, f[-1], f[0], f[1], nf[0], nf[1], chiR);
-        double FL = fdk::compact_flux(k.variant, f[-2], f[-1], f[0], nf[-1], nf[0], chiL);
+        double FR = wide ? fdk::compact_flux8(k.variant, f[-1], f[0], f[1], nf[-1], nf[0], nf[1], nf[2], chiR)
+                         : fdk::compact_flux(k.variant, f[-1], f[0], f[1], nf[0], nf[1], chiR);
+        double FL = wide ? fdk::compact_flux8(k.variant, f[-2], f[-1], f[0], nf[-2], nf[-1], nf[0], nf[1], chiL)
+                         : fdk::compact_flux(k.variant, f[-2], f[-1], f[0], nf[-1], nf[0], chiL);
         double L = -(FR - FL) * g.invh;
         double G = (e[(7 + c) * pl] - e[(10 + c) * pl - 1]) * g.invh;
         if (k.grad_carried) G = s[(3 + c) * pl];
@@ -1207,7 +1242,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
     for (int q = blockIdx.x; q < a.n_node; q += nb) {
       const BItem& w = it[q];
       const BMember& M = a.mem[w.m];
-      node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z);
+      node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1);
     }
   }
   it += a.n_node;
@@ -1219,9 +1254,11 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
       const BMember& M = a.mem[w.m];
       const double dt = member_dt(a, w.m, k);
       if (STAGE == 1)
-        update_block<1>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
+        update_block<1, false>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc,
+                               w.m);
       else
-        update_block<2>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
+        update_block<2, false>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z,
+                               a.sc, w.m);
     }
   }
   if (STAGE == 2) {
@@ -1264,7 +1301,7 @@ __global__ __launch_bounds__(256) void k_bphase_nodes(BArgs a, Consts k) {
   if (a.sc->stop) return;
   const BItem& w = a.items[a.n_cfl + a.n_halo + a.n_edge + blockIdx.x];
   const BMember& M = a.mem[w.m];
-  node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z);
+  node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1);
 }
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_bphase_update(BArgs a, Consts k) {
@@ -1273,9 +1310,10 @@ __global__ __launch_bounds__(256) void k_bphase_update(BArgs a, Consts k) {
   const BMember& M = a.mem[w.m];
   const double dt = member_dt(a, w.m, k);
   if (STAGE == 1)
-    update_block<1>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
+    update_block<1, false>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
   else
-    update_block<2>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
+    update_block<2, false>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z, a.sc,
+                           w.m);
 }
 __global__ void k_bphase_end(BArgs a, Consts k) { batch_step_end(a, k); }
 
@@ -1418,7 +1456,8 @@ void launch_edges(fdcgks_problem* pb, const double* Sin, dim3 blk) {
 template <int STAGE>
 void launch_nodes(fdcgks_problem* pb, const double* Sin, dim3 blk) {
   const Geo& g = pb->g;
-  const int tx = ceil_div(g.nx + 2 + g.sx, blk.x), nt = tx * ceil_div(g.ny + 2 + g.sy, blk.y);
+  const int w = node_reach(pb->k);
+  const int tx = ceil_div(g.nx + 2 * w + g.sx, blk.x), nt = tx * ceil_div(g.ny + 2 * w + g.sy, blk.y);
   dim3 gn(ceil_div(nt, NXCD) * NXCD, 1, 2);  // tiles in XCD bands (xcd_tile)
   const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
   const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
@@ -1430,8 +1469,8 @@ template <int STAGE>
 void launch_update(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout, dim3 blk) {
   const Geo& g = pb->g;
   dim3 gu(ceil_div(g.nx + g.sx, blk.x), ceil_div(g.ny + g.sy, blk.y), 2);
-  hipLaunchKernelGGL((k_update2d<STAGE>), gu, blk, 0, pb->stream, Sin, pb->E, pb->Nb, Ain, Out, Aout, g, pb->k,
-                     pb->sc);
+  auto fn = pb->k.flux_order == 8 ? k_update2d<STAGE, true> : k_update2d<STAGE, false>;
+  hipLaunchKernelGGL(fn, gu, blk, 0, pb->stream, Sin, pb->E, pb->Nb, Ain, Out, Aout, g, pb->k, pb->sc);
 }
 
 // One stage.  fused: the node sweep runs inside the update kernel and the
@@ -1445,7 +1484,7 @@ fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, 
   if (st) return st;
   launch_edges<STAGE>(pb, Sin, pb->tile[0]);
   mark(pb, STAGE == 1 ? TK_EDGE1 : TK_EDGE2);
-  if (fused && !(g.sx | g.sy)) {
+  if (fused && !(g.sx | g.sy) && pb->k.flux_order != 8) {
     dim3 gu(ceil_div(g.nx, 64), ceil_div(g.ny, 4), 2);
     const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
     const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
@@ -1620,6 +1659,7 @@ fdcgks_status check_params(const fdcgks_params* p) {
   if (!(p->tau_c1 >= 0) || !(p->tau_c2 >= 0)) return fail(nullptr, FDCGKS_EINVAL, "tau constants must be >= 0");
   if (p->recon_vars != FDCGKS_RECON_CONSERVATIVE && p->recon_vars != FDCGKS_RECON_CHARACTERISTIC)
     return fail(nullptr, FDCGKS_EINVAL, "bad recon_vars");
+  if (p->flux_order != 6 && p->flux_order != 8) return fail(nullptr, FDCGKS_EINVAL, "flux_order must be 6 or 8");
   return FDCGKS_OK;
 }
 
@@ -1699,6 +1739,7 @@ void fdcgks_default_params(fdcgks_params* p) {
   p->bc = FDCGKS_BC_PERIODIC;
   for (int k = 0; k < 4; ++k) p->side[k] = -1;
   p->flux_variant = FDCGKS_FLUX_6_4;
+  p->flux_order = 6;
   p->flux_precision = FDCGKS_FP64;
   p->grad_update = FDCGKS_GRAD_REEVAL;
   p->geno_r = 3;
@@ -1753,6 +1794,7 @@ fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_pro
   k.r = p->geno_r;
   k.variant = p->flux_variant;
   k.grad_carried = p->grad_update == FDCGKS_GRAD_CARRIED;
+  k.flux_order = p->flux_order;
   pb->ngrid = p->dim == 2 ? 2 : (p->dual_1d ? 2 : 1);
   pb->nplanes = (int)state_planes(*p);
   size_t sbytes = (size_t)pb->nplanes * g.plane * sizeof(double);
@@ -2094,6 +2136,7 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   if (pb->prm.recon_vars != FDCGKS_RECON_CONSERVATIVE)
     return fail(pb, FDCGKS_EINVAL, "the step adjoint needs conservative reconstruction");
   if (pb->g.sx | pb->g.sy) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs periodic sides");
+  if (pb->prm.flux_order != 6) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs the order-6 flux");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, FDCGKS_EINVAL, "dt must be finite and > 0");
   if (!state_ready(pb)) return fail(pb, FDCGKS_ESTATE, "set_state has not been called for every grid");
   fdcgks_status st = adj_alloc(pb);
@@ -2307,6 +2350,7 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
     if (params[m].dim != 2) return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches are 2D only", m);
     if (params[m].recon_vars != FDCGKS_RECON_CONSERVATIVE)
       return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches reconstruct conservative variables only", m);
+    if (params[m].flux_order != 6) return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches use the order-6 flux", m);
     for (int k = 0; k < 4; ++k)
       if (side_bc(params[m], k) != FDCGKS_BC_PERIODIC)
         return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches are periodic only", m);
@@ -2343,6 +2387,7 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
   k.r = p.geno_r;
   k.variant = p.flux_variant;
   k.grad_carried = p.grad_update == FDCGKS_GRAD_CARRIED;
+  k.flux_order = 6;
   // per-member buffers and work lists
   std::vector<BItem> cfl, halo, edge, node, upd;
   b->mem.resize(count);

@@ -28,7 +28,7 @@ struct Consts {
   int r;              // GENO exponent
   int variant;        // 0: (6-4), 1: (6-2), 2: linear
   int grad_carried;
-  int pad;
+  int flux_order;     // 6, or 8: the linear compact flux over the wider stencil
 };
 
 // ---------------------------------------------------------------- math
@@ -777,6 +777,18 @@ FDK_HD void gks_node(const Consts& k, const FT* W, const FT* Wx, const FT* Wy, F
 FDK_HD double compact_flux(int variant, double Fm, double Fc, double Fp, double N0, double N1,
                                                double chi) {
   double Fb = ((Fm + 46.0 * Fc + Fp) - 9.0 * (N0 + N1)) * (1.0 / 30.0);
+  if (variant == 2) return Fb;
+  double lo = variant == 1 ? Fc : (8.0 * Fc - N0 - N1) * (1.0 / 6.0);
+  return lo + chi * (Fb - lo);
+}
+// The same with the linear flux of order 8: the averaging conditions of Eq.
+// fd-conservative-flux-recons imposed also on the nodal cells j-1 and j+2
+// (the wider stencil of Sec. 2.1; Nm, Np2 are the nodal fluxes there).  The
+// degree-6 solution at the interface is exact to degree 7 (symmetry), error
+// -h^8 F^(8) / 161280; the low-order fluxes and the blend are unchanged.
+FDK_HD double compact_flux8(int variant, double Fm, double Fc, double Fp, double Nm, double N0, double N1, double Np2,
+                            double chi) {
+  double Fb = ((32.0 * (Fm + Fp) + 704.0 * Fc) - 171.0 * (N0 + N1) - 3.0 * (Nm + Np2)) * (1.0 / 420.0);
   if (variant == 2) return Fb;
   double lo = variant == 1 ? Fc : (8.0 * Fc - N0 - N1) * (1.0 / 6.0);
   return lo + chi * (Fb - lo);

@@ -26,7 +26,7 @@ def gpu_params(s):
               geno_eps=s["geno_eps"], geno_eps_a=s["geno_eps_a"], geno_d_central=s["d_central"],
               geno_d_side=s["d_side"], tau_c1=s["tau_c1"], tau_c2=s["tau_c2"], bc=s["bc"],
               fp32_flux=s.get("fp32_flux", False), grad_carried=s.get("grad_carried", 0),
-              recon_vars=s.get("recon_vars", "conservative"))
+              recon_vars=s.get("recon_vars", "conservative"), flux_order=s.get("flux_order", 6))
     if s.get("sides") is not None:
         kw["sides"] = s["sides"]
     if s["dim"] == 2:

@@ -55,6 +55,7 @@ def test_defaults():
     assert (p.dim, p.nx, p.ny, p.geno_r) == (2, 64, 64, 3)
     assert p.geno_C == 20.0 and p.geno_eps == 1e-15 and p.geno_eps_a == 1e-6
     assert p.geno_d_central == 8.0 and p.geno_d_side == 1.0 and p.gamma == 1.4
+    assert p.flux_order == 6
 
 
 @pytest.mark.parametrize("bad", [
@@ -63,6 +64,7 @@ def test_defaults():
     dict(geno_eps=0.0), dict(tau_c1=-1.0), dict(bc=4), dict(bc=-1), dict(lx=0.0), dict(ly=2.0),
     dict(recon_vars=2), dict(dim=1, nx=100, ny=2), dict(grad_update=3), dict(dim=1, nx=100, ny=1, bc=3),
     dict(side=(0, 2, -1, -1)), dict(side=(-1, -1, 1, 0)), dict(side=(5, 5, -1, -1)), dict(bc=2, side=(0, -1, -1, -1)),
+    dict(flux_order=7), dict(flux_order=0),
 ])
 def test_create_rejects_bad_params(bad):
     from paper_2606_17772_amd import _lib, default_params
