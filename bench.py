@@ -67,6 +67,7 @@ def parse():
     ap.add_argument("--no-char", action="store_true",
                     help="skip the characteristic-variable reconstruction comparison")
     ap.add_argument("--no-bounded", action="store_true", help="skip the walled-domain leg")
+    ap.add_argument("--no-order8", action="store_true", help="skip the order-8 compact flux comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -215,6 +216,21 @@ def characteristic_comparison(pr, n, tiles, steps=10):
             "conservative_ms_per_step": round(mc, 3), "slowdown_vs_conservative": round(mh / mc, 3),
             "kernel_ms_per_step": kh, "conservative_kernel_ms_per_step": kc,
             "max_rel_diff_values_vs_conservative": _max_rel_values(Sc, Sh)}
+
+
+def order8_comparison(pr, n, tiles, steps=10):
+    """The compact flux of order 8 (the wider stencil, nodal fluxes at
+    j-1..j+2) on the same workload: node-update rate, time per step and per
+    kernel against the order-6 flux, and the largest relative difference of
+    the values W after the same steps (a discretisation difference)."""
+    runs = _variant_runs(pr, n, tiles, [{}, {"flux_order": 8}], steps)
+    (m6, S6, k6), (m8, S8, k8) = runs
+    nodes = 2 * n * n
+    return {"workload": f"{n}x{n} shear layer, {steps} steps at the order-6 path's CFL dt",
+            "node_updates_per_s": nodes * 2 / (m8 * 1e-3), "ms_per_step": round(m8, 3),
+            "order6_ms_per_step": round(m6, 3), "slowdown_vs_order6": round(m8 / m6, 3),
+            "kernel_ms_per_step": k8, "order6_kernel_ms_per_step": k6,
+            "max_rel_diff_values_vs_order6": _max_rel_values(S6, S8)}
 
 
 def bounded_comparison(n, tiles, steps=10):
@@ -488,7 +504,7 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_comparison(pb, n)
-    if not args.no_fp32 or not args.no_char or not args.no_bounded:
+    if not args.no_fp32 or not args.no_char or not args.no_bounded or not args.no_order8:
         del pb
         torch.cuda.empty_cache()
         pb = None
@@ -496,6 +512,8 @@ def main():
         out["fp32_flux"] = fp32_flux_comparison(pr, n, tiles)
     if not args.no_char:
         out["characteristic"] = characteristic_comparison(pr, n, tiles)
+    if not args.no_order8:
+        out["order8"] = order8_comparison(pr, n, tiles)
     if not args.no_bounded:
         torch.cuda.empty_cache()
         out["bounded"] = bounded_comparison(n, tiles)

@@ -641,8 +641,9 @@ __global__ __launch_bounds__(256) void k_nodeupd2d(const double* __restrict__ S,
 }
 
 template <int STAGE, bool WIDE>
-// stage 2 reads and writes half the planes of stage 1: 80 VGPRs, 6 waves/SIMD
-__global__ __launch_bounds__(256, STAGE == 2 ? 6 : 4) void k_update2d(const double* __restrict__ S, const double* __restrict__ E,
+// stage 2 reads and writes half the planes of stage 1: 80 VGPRs, 6 waves/SIMD;
+// the order-8 assembly holds two more nodal fluxes per axis: one wave fewer
+__global__ __launch_bounds__(256, (STAGE == 2 ? 6 : 4) - (WIDE ? 1 : 0)) void k_update2d(const double* __restrict__ S, const double* __restrict__ E,
                                                   const double* __restrict__ Nb, const double* __restrict__ Ain,
                                                   double* __restrict__ Out, double* __restrict__ Aout, Geo g,
                                                   Consts k, Scal* __restrict__ sc) {
