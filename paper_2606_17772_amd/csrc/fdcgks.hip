@@ -229,13 +229,23 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
       rec[c] = ALONG_Y && q != c ? loc[q] : loc[c];
     }
   } else {
+    // all 32 stencil values are loaded before the first reconstruction, so a
+    // wave waits for memory once rather than once per component
+    double Q[4][4], X[4][4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const double* w = S + (G * 12 + c) * pl + o;
       const double* x = S + (G * 12 + f * 4 + c) * pl + o;
-      rec[c] =
-          fdk::recon_iface(k, w[0], w[st], w[2 * st], w[3 * st], x[0], x[st], x[2 * st], x[3 * st], g.h, g.invh);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        Q[c][m] = w[m * st];
+        X[c][m] = x[m * st];
+      }
     }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+      rec[c] = fdk::recon_iface(k, Q[c][0], Q[c][1], Q[c][2], Q[c][3], X[c][0], X[c][1], X[c][2], X[c][3], g.h,
+                                g.invh);
   }
 }
 
@@ -360,13 +370,22 @@ __device__ __forceinline__ void node_derivs(const double* __restrict__ B, const 
       }
     }
   } else {
+    // the stencil is loaded before the first reconstruction (one wait for
+    // memory rather than one per component and axis)
+    double w[4][5], x[4][3], y[4][3];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-      const double* w = B + c * pl + o;
-      const double* x = B + (4 + c) * pl + o;
-      const double* y = B + (8 + c) * pl + o;
-      Wx[c] = (FT)fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
-      Wy[c] = (FT)fdk::recon_node(k, w[-g.pitch], w[0], w[g.pitch], y[-g.pitch], y[0], y[g.pitch], g.h, g.invh);
+      const double* pw = B + c * pl + o;
+      const double* px = B + (4 + c) * pl + o;
+      const double* py = B + (8 + c) * pl + o;
+      w[c][0] = pw[-1], w[c][1] = pw[0], w[c][2] = pw[1], w[c][3] = pw[-g.pitch], w[c][4] = pw[g.pitch];
+      x[c][0] = px[-1], x[c][1] = px[0], x[c][2] = px[1];
+      y[c][0] = py[-g.pitch], y[c][1] = py[0], y[c][2] = py[g.pitch];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      Wx[c] = (FT)fdk::recon_node(k, w[c][0], w[c][1], w[c][2], x[c][0], x[c][1], x[c][2], g.h, g.invh);
+      Wy[c] = (FT)fdk::recon_node(k, w[c][3], w[c][1], w[c][4], y[c][0], y[c][1], y[c][2], g.h, g.invh);
     }
   }
 }
