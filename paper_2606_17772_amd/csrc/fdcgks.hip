@@ -276,7 +276,14 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
 #pragma unroll
     for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
   }
-  const double chi = fmin(rec[0].cl, rec[0].cr);  // path function of the density (or acoustic) line
+  double* e = E + ((long)fam * 50 + G * 25) * g.plane + at(g, j, i);
+  const long pl = g.plane;
+  // what needs no partner goes out at once (non-temporal stores: the
+  // interface, node and state buffers are read back only by the next kernel,
+  // from HBM, so they are kept out of the caches); the path function of the
+  // density (or acoustic) line before the solve, so that it is not held
+  // through it
+  if (valid) __builtin_nontemporal_store(fmin(rec[0].cl, rec[0].cr), &e[8 * pl]);
 #pragma unroll
   for (int c = 0; c < 4; ++c) XCH(c, ty) = 0.5 * (rec[c].dl + rec[c].dr);
   __syncthreads();
@@ -285,15 +292,9 @@ __device__ __forceinline__ void edge_block(const double* __restrict__ S, double*
   for (int c = 0; c < 4; ++c) tang[c] = XCH(c, ty ^ 1);
   double F[4] = {0, 0, 0, 0}, Ft[4] = {0, 0, 0, 0}, Wl[4] = {0, 0, 0, 0}, Wr[4] = {0, 0, 0, 0};
   double Wlt[4] = {0, 0, 0, 0}, Wrt[4] = {0, 0, 0, 0};
-  double* e = E + ((long)fam * 50 + G * 25) * g.plane + at(g, j, i);
-  const long pl = g.plane;
   if (valid) {
     // the normal is y when FAM != G (rho U and rho V swap in the local frame)
     solve_dir<STAGE, FT>(k, (FT)dt, fam != G, rec, tang, F, Ft, Wl, Wr, Wlt, Wrt);
-    // what needs no partner goes out at once (non-temporal stores: the
-    // interface, node and state buffers are read back only by the next
-    // kernel, from HBM, so they are kept out of the caches)
-    __builtin_nontemporal_store((double)(chi), &e[8 * pl]);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       __builtin_nontemporal_store((double)(Ft[c]), &e[(4 + c) * pl]);
