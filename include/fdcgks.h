@@ -239,13 +239,17 @@ fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* 
  * FDCGKS_OPT_TILE_EDGE / _NODE / _UPDATE: block shape of the interface
  * sweep, node sweep and update kernels as x | (y << 16); x in {32, 64, 128,
  * 256}, x*y a multiple of 64 and at most 256, y even for the interface
- * sweep (its two normals per point are paired thread rows).  Default 64 x 4.
+ * sweep (its two normals per point are paired thread rows).  Defaults:
+ * 64 x 2 (interface), 64 x 1 (node), 128 x 1 (update), the autotuner's pick
+ * on a 2048^2 Navier-Stokes problem.
  * The shape changes only the launch, never the arithmetic: results are
  * bitwise identical for every valid shape.
  * FDCGKS_OPT_FUSE_NODES (default 0): 1 makes 2D steps evaluate the nodal fluxes
  * inside the update kernel (per 64 x 4 tile plus a one-node halo, in LDS)
  * instead of a separate node sweep through a node buffer; the node and
- * update shapes then do not apply (bitwise the same results).  The
+ * update shapes then do not apply (bitwise the same results).  Periodic
+ * problems with flux_order 6 only: bounded problems and the order-8 flux
+ * (which reads nodal fluxes two nodes away) keep the separate sweep.  The
  * diagnostics and the step adjoint always use the separate sweep.
  * EINVAL for an unknown option or an invalid value. */
 enum {

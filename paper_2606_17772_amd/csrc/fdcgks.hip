@@ -1378,8 +1378,9 @@ struct fdcgks_problem {
   std::vector<hipEvent_t> ev;
   std::vector<int> ev_kind;
   int ev_used = 0;
-  // launch shapes of the interface, node and update kernels (x, y threads)
-  dim3 tile[3] = {dim3(64, 4), dim3(64, 4), dim3(64, 4)};
+  // launch shapes of the interface, node and update kernels (x, y threads):
+  // fdcgks_autotune's pick on the 2048^2 shear layer
+  dim3 tile[3] = {dim3(64, 2), dim3(64, 1), dim3(128, 1)};
   // captured whole steps (one graph per ping-pong parity), replayed by fdcgks_step
   int graph_steps = 16;  // steps per captured graph; 0: separate launches
   bool fuse_nodes = false;  // node sweep inside the update kernel

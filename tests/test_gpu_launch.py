@@ -51,7 +51,7 @@ def test_graph_replays_match_separate_launches(case, k):
 def test_every_launch_shape_gives_identical_results():
     s, pr = _cases()[0]
     ref = _problem(s, pr)
-    assert ref.tiles() == {"edge": (64, 4), "node": (64, 4), "update": (64, 4)}
+    assert ref.tiles() == {"edge": (64, 2), "node": (64, 1), "update": (128, 1)}
     ref.step(nsteps=2, cfl=0.5)
     want = ref.get_state_all()
     shapes = [(64, 4), (64, 2), (128, 2), (32, 8), (256, 1), (128, 1), (64, 1), (32, 4)]
@@ -91,7 +91,7 @@ def test_invalid_launch_shapes_rejected():
         with pytest.raises(FdcgksError) as ei:
             pb.set_tile(kernel, x, y)
         assert ei.value.status == -1
-    assert pb.tiles()["edge"] == (64, 4)
+    assert pb.tiles()["edge"] == (64, 2)
 
 
 def test_autotune_keeps_results():
