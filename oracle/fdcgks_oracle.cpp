@@ -1239,13 +1239,15 @@ void orc_stage2d_sample(const Par* p, int stage, double dt, const double* P, con
   for (int s = 0; s < ns; ++s) {
     int I = grid[s] == 0 ? 2 * ii[s] + 1 : dual_lattice(ii[s], G.wx);
     int J = grid[s] == 0 ? 2 * jj[s] + 1 : dual_lattice(jj[s], G.wy);
-    // the 8 interfaces and 5 nodes the operator reads
+    // the 8 interfaces and 5 nodes the operator reads (9 nodes for the
+    // order-8 flux, which also reads the nodes two steps away on each axis)
+    const int reach = p->flux_order == 8 ? 2 : 1;
     EdgeRes<double> E[2][4];
-    NodeRes<double> Nn[2][3];
+    NodeRes<double> Nn[2][5];
     for (int ax = 0; ax < 2; ++ax) {
       int dI = ax == 0 ? 1 : 0, dJ = ax == 0 ? 0 : 1;
       for (int m = 0; m < 4; ++m) E[ax][m] = edge2d(*p, G, I + (2 * m - 3) * dI, J + (2 * m - 3) * dJ, h, dt);
-      for (int m = 0; m < 3; ++m) Nn[ax][m] = node2d(*p, G, I + (2 * m - 2) * dI, J + (2 * m - 2) * dJ, h);
+      for (int m = -reach; m <= reach; ++m) Nn[ax][m + 2] = node2d(*p, G, I + 2 * m * dI, J + 2 * m * dJ, h);
     }
     auto edgef = [&](int I2, int J2) -> const EdgeRes<double>& {
       int ax = (J2 == J) ? 0 : 1;
@@ -1253,10 +1255,10 @@ void orc_stage2d_sample(const Par* p, int stage, double dt, const double* P, con
       return E[ax][(o + 3) / 2];
     };
     auto nodef = [&](int I2, int J2) -> const NodeRes<double>& {
-      if (I2 == I && J2 == J) return Nn[0][1];
+      if (I2 == I && J2 == J) return Nn[0][2];
       int ax = (J2 == J) ? 0 : 1;
       int o = ax == 0 ? I2 - I : J2 - J;
-      return Nn[ax][(o + 2) / 2];
+      return Nn[ax][o / 2 + 2];
     };
     NodeOp<double> op = node_operator<double>(*p, I, J, h, edgef, nodef);
     const int mx = grid[s] == 0 ? nx : nx + G.wx;

@@ -164,3 +164,44 @@ def _plane_rel(g, o, fl):
     o = np.asarray(o, dtype=np.float64)
     num = np.abs(g - o).max(axis=(-2, -1))
     return num / np.maximum(np.abs(o).max(axis=(-2, -1)), fl)
+
+
+def check_full_size_sampled(oracle, s, P, D, pb, ns=48, seed=0, label=""):
+    """Both stages of one step at full size on sampled nodes of both grids
+    (corner and edge nodes included), against the oracle's sampled stage.
+
+    Values are held to the floored 1e-12 bar.  The averaged gradients are the
+    Gauss difference of two O(|W|) interface values divided by h, so a few ulp
+    of interface-value round-off (different erfc/exp implementations on the
+    two sides) become n * eps relative to |W|/L.  They are therefore compared
+    as interval differences h * grad W against |W| (floor |W|/h); the strict
+    |W|/L-floored figure is printed.  Stage 2 starts from the GPU's own
+    stage-1 buffers."""
+    dt = pb.compute_dt(0.5)
+    par = oracle.make_par(**s)
+    rng = np.random.default_rng(seed)
+    grid = rng.integers(0, 2, ns)
+    shapes = [P.shape[1:], D.shape[1:]]
+    corners = [(0, 0), (0, 1), (1, 0), (1, 1)]
+    jj = np.array([(shapes[g][0] - 1) * corners[k][0] if k < 4 else rng.integers(0, shapes[g][0])
+                   for k, g in enumerate(grid)])
+    ii = np.array([(shapes[g][1] - 1) * corners[k][1] if k < 4 else rng.integers(0, shapes[g][1])
+                   for k, g in enumerate(grid)])
+    o1, a1 = oracle.stage2d_sample(par, 1, dt, P, D, grid, jj, ii)
+    g1, ga = pb.debug_stage(1, dt)
+    gs = np.stack([g1[grid[k]][:, jj[k], ii[k]] for k in range(ns)])
+    gas = np.stack([ga[grid[k]][:, jj[k], ii[k]] for k in range(ns)])
+    sc = ref_scales([P, D], s["gamma"], s["lx"])
+    strict = floors_state(sc)
+    fl = floors_state_interval(sc, s["lx"] / s["nx"])
+    e_strict = max(np.abs(gs[:, f] - o1[:, f]).max() / max(np.abs(o1[:, f]).max(), strict[f]) for f in range(12))
+    print(f"{label} stage 1: max-relative error with |W|/L floors {e_strict:.2e}")
+    for f in range(12):
+        assert np.abs(gs[:, f] - o1[:, f]).max() / max(np.abs(o1[:, f]).max(), fl[f]) <= TOL, f
+        assert np.abs(gas[:, f] - a1[:, f]).max() / max(np.abs(a1[:, f]).max(), fl[f]) <= TOL, f
+    o2, _ = oracle.stage2d_sample(par, 2, dt, np.ascontiguousarray(g1[0]), np.ascontiguousarray(g1[1]), grid, jj, ii,
+                                  accP=np.ascontiguousarray(ga[0]), accD=np.ascontiguousarray(ga[1]))
+    g2 = pb.debug_stage(2, dt)
+    gs2 = np.stack([g2[grid[k]][:, jj[k], ii[k]] for k in range(ns)])
+    for f in range(12):
+        assert np.abs(gs2[:, f] - o2[:, f]).max() / max(np.abs(o2[:, f]).max(), fl[f]) <= TOL, f

@@ -11,8 +11,8 @@ import numpy as np
 import pytest
 
 import workloads as WL
-from tests.helpers import (TOL, check_edge_intermediates, floors_edge, floors_node, floors_state, gpu_params,
-                           oracle_par, ref_scales, relerr, settings, ulp_sensitivity)
+from tests.helpers import (TOL, check_edge_intermediates, check_full_size_sampled, floors_edge, floors_node,
+                           floors_state, gpu_params, oracle_par, ref_scales, relerr, settings, ulp_sensitivity)
 
 pytestmark = pytest.mark.gpu
 
@@ -176,6 +176,22 @@ def test_bounded_rejected_by_adjoint_and_batch():
         pb.step_vjp(0.001, np.zeros((2, 12) + P.shape[1:]))
     with pytest.raises(FdcgksError, match="periodic only"):
         Batch([gpu_params(s)])
+
+
+def test_full_size_sampled_walled(oracle):
+    """The walled workload the benchmark times at full size: 2048^2 primary
+    and 2049^2 dual nodes, a smooth Navier-Stokes flow between adiabatic
+    no-slip walls at x = 0, 1 and reflecting walls at y = 0, 1.  Both stages
+    on sampled nodes of both grids, the corner and wall nodes included
+    (bars: check_full_size_sampled)."""
+    n = 2048
+    h = 1.0 / n
+    P, D = WL.sample_bounded(WL.mirror_flow(1.0, 1.0, 1, 1), n, n, h, 1, 1)
+    s = settings(dim=2, nx=n, ny=n, lx=1.0, mu=1e-4, prandtl=0.72,
+                 sides=["no_slip", "no_slip", "reflecting", "reflecting"])
+    pb = _problem(s, P, D)
+    assert pb.grid_shape(1)[1:] == (n + 1, n + 1)
+    check_full_size_sampled(oracle, s, P, D, pb, label="2048^2 walled")
 
 
 # ----------------------------------------------------------------------- 1D

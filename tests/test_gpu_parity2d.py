@@ -6,13 +6,11 @@ ragged tail in x and y), and on sampled nodes at the full 2048^2 size.
 Bar: per-plane max |gpu - oracle| / max(max |oracle|, floor) <= 1e-12 (FP64), the floor being
 the dimensional reference scale of the field (tests/helpers.py).
 """
-import numpy as np
 import pytest
 
 import workloads as WL
-from tests.helpers import (TOL, check_edge_intermediates, floors_edge, floors_node, floors_state,
-                           floors_state_interval, gpu_params, oracle_par, ref_scales, relerr, settings,
-                           ulp_sensitivity)
+from tests.helpers import (TOL, check_edge_intermediates, check_full_size_sampled, floors_edge, floors_node,
+                           floors_state, gpu_params, oracle_par, ref_scales, relerr, settings, ulp_sensitivity)
 
 pytestmark = pytest.mark.gpu
 
@@ -153,65 +151,11 @@ def test_vortex_512_steps(oracle):
 
 def test_full_size_sampled(oracle):
     """One full step on the 2048^2 shear-layer workload in the launch
-    configuration the benchmark times, checked on sampled nodes.
-
-    Values are held to the same floored 1e-12 bar as the small grids.  The
-    averaged gradients are the Gauss difference of two O(|W|) interface
-    values divided by h (Eq. define-averaged-gradient), so a few ulp of
-    interface-value round-off (different erfc/exp implementations on the two
-    sides) become n * eps relative to |W|/L: about 2e-13 per ulp at n = 2048.
-    They are therefore compared as interval differences h * grad W against
-    |W| (floor |W|/h); the strict |W|/L-floored figure is printed."""
+    configuration the benchmark times, checked on sampled nodes (bars:
+    check_full_size_sampled)."""
     n = 2048
     pr = WL.shear_layer(n, seed=0)
     s = settings(dim=2, nx=n, ny=n, lx=1.0, mu=1e-4, prandtl=0.72)
-    par = oracle_par(oracle, s)
     pb = _problem(s, pr.P, pr.D)
     _bench_tiles(pb)
-    dt = pb.compute_dt(0.5)
-    rng = np.random.default_rng(0)
-    ns = 48
-    grid = rng.integers(0, 2, ns)
-    jj = np.concatenate([[0, n - 1, 0, n - 1], rng.integers(0, n, ns - 4)])
-    ii = np.concatenate([[0, 0, n - 1, n - 1], rng.integers(0, n, ns - 4)])
-    o1, a1 = oracle.stage2d_sample(par, 1, dt, pr.P, pr.D, grid, jj, ii)
-    g1, ga = pb.debug_stage(1, dt)
-    gs = np.stack([g1[grid[k], :, jj[k], ii[k]] for k in range(ns)])
-    gas = np.stack([ga[grid[k], :, jj[k], ii[k]] for k in range(ns)])
-    # per field, relative to the field's scale over the samples (floored)
-    sc = ref_scales([pr.P, pr.D], s["gamma"], s["lx"])
-    strict = floors_state(sc)
-    fl = floors_state_interval(sc, 1.0 / n)
-    e_strict = max(np.abs(gs[:, f] - o1[:, f]).max() / max(np.abs(o1[:, f]).max(), strict[f]) for f in range(12))
-    print(f"2048^2 stage 1: max-relative error with |W|/L floors {e_strict:.2e}")
-    for f in range(12):
-        den = max(np.abs(o1[:, f]).max(), fl[f])
-        assert np.abs(gs[:, f] - o1[:, f]).max() / den <= TOL, f
-        den = max(np.abs(a1[:, f]).max(), fl[f])
-        assert np.abs(gas[:, f] - a1[:, f]).max() / den <= TOL, f
-    # stage 2 from the GPU's own stage-1 buffers, re-evaluated by the oracle
-    o2, _ = oracle.stage2d_sample(par, 2, dt, np.ascontiguousarray(g1[0]), np.ascontiguousarray(g1[1]), grid, jj, ii,
-                                  accP=np.ascontiguousarray(ga[0]), accD=np.ascontiguousarray(ga[1]))
-    g2 = pb.debug_stage(2, dt)
-    gs2 = np.stack([g2[grid[k], :, jj[k], ii[k]] for k in range(ns)])
-    for f in range(12):
-        den = max(np.abs(o2[:, f]).max(), fl[f])
-        assert np.abs(gs2[:, f] - o2[:, f]).max() / den <= TOL, f
-
-
-def test_fp32_flux_error_report(oracle):
-    """FP32 gas-kinetic variant: its error against the FP64 oracle is
-    reported, and bounded well above FP64 round-off but far below the
-    solution scale."""
-    s, pr = _case("vortex_40")
-    s32 = dict(s, fp32_flux=True)
-    par = oracle_par(oracle, s)
-    dt = 0.2 * pr.h / 3.0
-    oP, oD, _, _ = oracle.stage2d(par, 1, dt, pr.P, pr.D)
-    pb = _problem(s32, pr.P, pr.D)
-    g1, _ = pb.debug_stage(1, dt)
-    fl = floors_state(ref_scales([pr.P, pr.D], s["gamma"], s["lx"]))
-    errW = relerr(g1[0][:4], oP[:4], fl[:4])[0]
-    errG = relerr(g1[0][4:], oP[4:], fl[4:])[0]
-    print(f"FP32-flux stage-1 max-relative error: values {errW:.3e}, gradients {errG:.3e}")
-    assert errW < 1e-5 and errG < 1e-3
+    check_full_size_sampled(oracle, s, pr.P, pr.D, pb, label="2048^2 shear layer")

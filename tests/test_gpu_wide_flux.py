@@ -13,7 +13,8 @@ import pytest
 import workloads as WL
 from tests import test_gpu_boundaries as TB
 from tests import test_gpu_parity1d as T1
-from tests.helpers import TOL, floors_state, gpu_params, oracle_par, ref_scales, relerr, settings, ulp_sensitivity
+from tests.helpers import (TOL, check_full_size_sampled, floors_state, gpu_params, oracle_par, ref_scales, relerr,
+                           settings, ulp_sensitivity)
 
 pytestmark = pytest.mark.gpu
 
@@ -108,6 +109,16 @@ def test_graph_and_fused_option_order8(name):
     b.step(nsteps=5, cfl=0.5)
     for g in (0, 1):
         assert np.array_equal(a.get_state_stacked(g), b.get_state_stacked(g))
+
+
+def test_full_size_sampled_order8(oracle):
+    """The order-8 flux on the 2048^2 shear layer (the benchmark's order-8
+    leg): both stages on sampled nodes (bars: check_full_size_sampled)."""
+    n = 2048
+    pr = WL.shear_layer(n, seed=0)
+    s = settings(dim=2, nx=n, ny=n, lx=1.0, mu=1e-4, prandtl=0.72, flux_order=8)
+    pb = _problem(s, pr.P, pr.D)
+    check_full_size_sampled(oracle, s, pr.P, pr.D, pb, label="2048^2 order 8")
 
 
 # ----------------------------------------------------------------------- 1D

@@ -204,6 +204,33 @@ def test_wide_flux_invariants(oracle, case):
             assert abs(B[c].sum() - A[c].sum()) <= 1e-13 * np.abs(A[c]).sum(), c
 
 
+@pytest.mark.parametrize("order", [6, 8])
+@pytest.mark.parametrize("walled", [False, True])
+def test_sampled_stage_equals_whole_grid(oracle, order, walled):
+    """The oracle's sampled stage (the full-size GPU tests compare against it)
+    gives bit for bit the whole-grid stage at the same nodes."""
+    if walled:
+        nx, ny = 24, 10
+        h = 1.0 / nx
+        P, D = WL.sample_bounded(WL.mirror_flow(1.0, ny * h, 1, 1), nx, ny, h, 1, 1)
+        s = settings(dim=2, nx=nx, ny=ny, lx=1.0, mu=1e-3, prandtl=0.72, flux_order=order,
+                     sides=["no_slip", "zero_gradient", "reflecting", "no_slip"])
+    else:
+        pr = WL.random_rough2d(23, 17, seed=3)
+        P, D = pr.P, pr.D
+        s = settings(dim=2, nx=23, ny=17, lx=1.0, flux_order=order)
+    par = oracle.make_par(**s)
+    dt = 0.2 * (s["lx"] / s["nx"]) / 3
+    oP, oD, aP, aD = oracle.stage2d(par, 1, dt, P, D)
+    rng = np.random.default_rng(0)
+    grid = rng.integers(0, 2, 40)
+    jj = np.array([rng.integers(0, (oP if g == 0 else oD).shape[1]) for g in grid])
+    ii = np.array([rng.integers(0, (oP if g == 0 else oD).shape[2]) for g in grid])
+    o, a = oracle.stage2d_sample(par, 1, dt, P, D, grid, jj, ii)
+    assert np.array_equal(o, np.stack([(oP if g == 0 else oD)[:, j, i] for g, j, i in zip(grid, jj, ii)]))
+    assert np.array_equal(a, np.stack([(aP if g == 0 else aD)[:, j, i] for g, j, i in zip(grid, jj, ii)]))
+
+
 def test_1d_primary_and_shifted_copy_agree(oracle):
     """The shifted copy (reading D24) solves the same problem on nodes offset
     by h/2: both converge to the exact solution, so they agree to
