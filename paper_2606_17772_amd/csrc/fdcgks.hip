@@ -982,25 +982,26 @@ __global__ __launch_bounds__(256) void k_cfl_partial(const double* __restrict__ 
                                                      const Scal* __restrict__ sc) {
   __shared__ double smax[256], smin[256];
   double vmax = 0.0, rmin = 1e300;
-  // stored nodes; the dual grid has one more column (row) along a bounded axis
+  // stored nodes; the dual grid has one more column (row) along a bounded
+  // axis.  A block takes whole rows (no per-node index division), its
+  // threads the columns.
   const int W = g.nx + g.sx, H = g.ny + g.sy;
-  long n = (long)ngrid * W * H;
   constexpr int NC = DIM + 2;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    int i = (int)(t % W);
-    long r = t / W;
-    int j = (int)(r % H);
-    int gr = (int)(r / H);
-    if (gr == 0 && (i >= g.nx || j >= g.ny)) continue;
-    const double* B = S + gr * gridstride + at(g, j, i);
-    double rho = B[0], U = B[g.plane] / rho;
-    double V = DIM == 2 ? B[2 * g.plane] / rho : 0.0;
-    double rE = B[(NC - 1) * g.plane];
-    double p = (gamma - 1.0) * (rE - 0.5 * rho * (U * U + V * V));
-    double c = sqrt(gamma * p / rho);
-    double s = fmax(fabs(U), fabs(V)) + c;
-    vmax = fmax(vmax, s);  // NaN speeds are dropped here and caught by the update's check
-    rmin = fmin(rmin, rho);
+  for (int row = blockIdx.x; row < ngrid * H; row += gridDim.x) {
+    const int gr = row / H, j = row - gr * H;
+    if (gr == 0 && j >= g.ny) continue;  // block-uniform
+    const int w = gr == 0 ? g.nx : W;
+    const double* B = S + gr * gridstride + at(g, j, 0);
+    for (int i = threadIdx.x; i < w; i += blockDim.x) {
+      double rho = B[i], U = B[g.plane + i] / rho;
+      double V = DIM == 2 ? B[2 * g.plane + i] / rho : 0.0;
+      double rE = B[(NC - 1) * g.plane + i];
+      double p = (gamma - 1.0) * (rE - 0.5 * rho * (U * U + V * V));
+      double c = sqrt(gamma * p / rho);
+      double s = fmax(fabs(U), fabs(V)) + c;
+      vmax = fmax(vmax, s);  // NaN speeds are dropped here and caught by the update's check
+      rmin = fmin(rmin, rho);
+    }
   }
   smax[threadIdx.x] = vmax;
   smin[threadIdx.x] = rmin;
