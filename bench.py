@@ -417,7 +417,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU decomposition is described in DESIGN.md but not built", file=sys.stderr)
+              "the multi-GPU decomposition is a design, not built", file=sys.stderr)
         sys.exit(2)
     import torch
 
