@@ -24,6 +24,10 @@ FLAGS = [
     # the inlined stage code then does not depend on the kernel it sits in
     # (single problems, batches, fused and separate sweeps agree bit for bit)
     "-ffp-contract=on",
+    # instruction scheduling that groups memory clauses: the interface sweep
+    # then fits its registers without spilling (246 VGPRs), and a step is
+    # about 1% faster on the 2048^2 workload; the arithmetic is unchanged
+    "-mllvm", "-amdgpu-sched-strategy=max-memory-clause",
     "-I", os.path.join(ROOT, "include"),
 ]
 
