@@ -68,6 +68,7 @@ def parse():
                     help="skip the characteristic-variable reconstruction comparison")
     ap.add_argument("--no-bounded", action="store_true", help="skip the walled-domain leg")
     ap.add_argument("--no-order8", action="store_true", help="skip the order-8 compact flux comparison")
+    ap.add_argument("--no-pcie", action="store_true", help="skip the host-buffer (PCIe-inclusive) leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -216,6 +217,31 @@ def characteristic_comparison(pr, n, tiles, steps=10):
             "conservative_ms_per_step": round(mc, 3), "slowdown_vs_conservative": round(mh / mc, 3),
             "kernel_ms_per_step": kh, "conservative_kernel_ms_per_step": kc,
             "max_rel_diff_values_vs_conservative": _max_rel_values(Sc, Sh)}
+
+
+def pcie_inclusive(pb, pr, n, steps):
+    """The boundary's host path: both grids' state handed over from host
+    (pageable numpy) arrays, `steps` CFL steps, and the state read back into
+    host arrays.  Node-update rate including both transfers, and the transfer
+    times; `value` excludes them (inputs already resident in HBM)."""
+    import torch
+    t0 = time.perf_counter()
+    for g, S in ((0, pr.P), (1, pr.D)):
+        pb.set_state(g, S[0:4], S[4:8], S[8:12])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, k = pb.step(nsteps=steps, cfl=CFL)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    out = [pb.get_state(g) for g in (0, 1)]
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    assert k == steps and out[1][0].shape == (4, n, n)
+    nbytes = 2 * pr.P.nbytes
+    return {"workload": f"{n}x{n} shear layer: state in from host arrays, {steps} CFL steps, state out to host arrays",
+            "node_updates_per_s": 2 * n * n * 2 * steps / (t3 - t0), "host_to_device_ms": round((t1 - t0) * 1e3, 2),
+            "steps_ms": round((t2 - t1) * 1e3, 2), "device_to_host_ms": round((t3 - t2) * 1e3, 2),
+            "bytes_each_way": nbytes}
 
 
 def order8_comparison(pr, n, tiles, steps=10):
@@ -502,6 +528,8 @@ def main():
                          "frac": round(hbm_gbs / PEAK_HBM_GBS, 4)},
         "kernel_ms_per_step": {k2: round(v / kn, 4) for k2, v in kms.items()},
     }
+    if not args.no_pcie:
+        out["pcie_inclusive"] = pcie_inclusive(pb, pr, n, args.steps)
     if not args.no_adjoint:
         out["adjoint"] = adjoint_comparison(pb, n)
     if not args.no_fp32 or not args.no_char or not args.no_bounded or not args.no_order8:
