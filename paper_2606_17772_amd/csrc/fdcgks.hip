@@ -2196,10 +2196,17 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   const long n = (long)g.nx * g.ny;
   const long interior = (long)OY * g.pitch + OX;
   // adjoint of the step output into the padded layout (halo stays zero)
-  const hipMemcpyKind kin = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  // host input: one contiguous transfer into the interface buffer (written
+  // by the forward recompute only after these copies, in stream order), then
+  // device-to-device 2D copies into the padded layout
+  const double* lsrc = lam_out;
+  if (!on_device) {
+    HIPCHK(pb, hipMemcpyAsync(pb->E, lam_out, (size_t)24 * n * sizeof(double), hipMemcpyHostToDevice, pb->stream));
+    lsrc = pb->E;
+  }
   for (int p = 0; p < 24; ++p)
-    HIPCHK(pb, hipMemcpy2DAsync(pb->Lo + p * g.plane + interior, pitchb, lam_out + p * n, row, row, g.ny, kin,
-                                pb->stream));
+    HIPCHK(pb, hipMemcpy2DAsync(pb->Lo + p * g.plane + interior, pitchb, lsrc + p * n, row, row, g.ny,
+                                hipMemcpyDeviceToDevice, pb->stream));
   // forward recompute at the frozen dt: stage-1 results into E1/Nb1, stage-2 into E/Nb
   std::memset(pb->sc_host, 0, sizeof(Scal));
   pb->sc_host->dt = dt;
@@ -2222,11 +2229,16 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   st = adj_stage<2>(pb, dt, pb->Sstar, pb->E, pb->Nb, pb->Lo, nullptr, pb->LAcc, pb->LSs);
   if (!st) st = adj_stage<1>(pb, dt, pb->S[pb->cur], pb->E1, pb->Nb1, pb->LSs, pb->LAcc, pb->LS0, pb->LS0);
   if (st) return st;
-  const hipMemcpyKind kout = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  // host output: dense through the interface buffer (free once the reverse
+  // sweeps are done), then one contiguous transfer
+  double* ldst = on_device ? lam_in : pb->E;
   for (int p = 0; p < 24; ++p)
-    HIPCHK(pb, hipMemcpy2DAsync(lam_in + p * n, row, pb->LS0 + p * g.plane + interior, pitchb, row, g.ny, kout,
-                                pb->stream));
-  if (!on_device) HIPCHK(pb, hipStreamSynchronize(pb->stream));
+    HIPCHK(pb, hipMemcpy2DAsync(ldst + p * n, row, pb->LS0 + p * g.plane + interior, pitchb, row, g.ny,
+                                hipMemcpyDeviceToDevice, pb->stream));
+  if (!on_device) {
+    HIPCHK(pb, hipMemcpyAsync(lam_in, pb->E, (size_t)24 * n * sizeof(double), hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(pb, hipStreamSynchronize(pb->stream));
+  }
   return FDCGKS_OK;
 }
 
