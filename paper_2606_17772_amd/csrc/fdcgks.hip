@@ -2546,17 +2546,26 @@ static fdcgks_status batch_copy(fdcgks_batch* b, int m, int grid, double* const*
   const Geo& g = b->mem[m].g;
   double* base = b->mem[m].S[b->cur] + (long)grid * 12 * g.plane;
   size_t row = (size_t)g.nx * sizeof(double);
-  hipMemcpyKind kind = to_dev ? (on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice)
-                              : (on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost);
-  for (int f = 0; f < 3; ++f)
+  const size_t dense = (size_t)g.nx * g.ny;
+  // host arrays go through the member's interface buffer (idle between
+  // steps) as one contiguous transfer per field, like single problems
+  for (int f = 0; f < 3; ++f) {
+    double* stage = on_device ? ptrs[f] : b->mem[m].E;
+    if (to_dev && !on_device)
+      BHIPCHK(b, hipMemcpyAsync(stage, ptrs[f], 4 * dense * sizeof(double), hipMemcpyHostToDevice, b->stream));
     for (int c = 0; c < 4; ++c) {
       double* dev = base + (long)(f * 4 + c) * g.plane + (long)OY * g.pitch + OX;
-      double* usr = ptrs[f] + (long)c * g.nx * g.ny;
+      double* usr = stage + (long)c * dense;
       if (to_dev)
-        BHIPCHK(b, hipMemcpy2DAsync(dev, (size_t)g.pitch * sizeof(double), usr, row, row, g.ny, kind, b->stream));
+        BHIPCHK(b, hipMemcpy2DAsync(dev, (size_t)g.pitch * sizeof(double), usr, row, row, g.ny,
+                                    hipMemcpyDeviceToDevice, b->stream));
       else
-        BHIPCHK(b, hipMemcpy2DAsync(usr, row, dev, (size_t)g.pitch * sizeof(double), row, g.ny, kind, b->stream));
+        BHIPCHK(b, hipMemcpy2DAsync(usr, row, dev, (size_t)g.pitch * sizeof(double), row, g.ny,
+                                    hipMemcpyDeviceToDevice, b->stream));
     }
+    if (!to_dev && !on_device)
+      BHIPCHK(b, hipMemcpyAsync(ptrs[f], stage, 4 * dense * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  }
   if (!on_device) BHIPCHK(b, hipStreamSynchronize(b->stream));
   return FDCGKS_OK;
 }
