@@ -293,8 +293,10 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
 /* ---------------------------------------------------------------- batches
  * Many independent periodic 2D problems of different sizes advanced together
  * (same scheme constants, each member its own grid, mesh size and CFL time
- * step): one cooperative persistent launch per S2O4 stage covers every
- * member.  Same state layout and on_device rule as the single-problem calls. */
+ * step): every launch covers every member, one launch per phase of a stage
+ * (default) or one cooperative persistent launch per stage (see
+ * fdcgks_batch_set_mode).  Same state layout and on_device rule as the
+ * single-problem calls. */
 typedef struct fdcgks_batch fdcgks_batch; /* opaque, owned by the library */
 
 /* How a batched stage is launched.  PERSISTENT: one cooperative launch per
@@ -307,7 +309,8 @@ typedef struct fdcgks_batch fdcgks_batch; /* opaque, owned by the library */
 enum { FDCGKS_BATCH_PERSISTENT = 0, FDCGKS_BATCH_PHASED = 1 };
 
 /* params[count]: every member 2D periodic with conservative reconstruction
- * (EINVAL otherwise); members may differ only in nx, ny, x0, lx, y0, ly.
+ * and flux_order 6 (EINVAL otherwise); members may differ only in nx, ny, x0,
+ * lx, y0, ly.
  * Allocates all device memory on the current device. */
 fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, void* hip_stream, fdcgks_batch** out);
 fdcgks_status fdcgks_batch_set_state(fdcgks_batch* b, int32_t member, int32_t grid, const double* W,
