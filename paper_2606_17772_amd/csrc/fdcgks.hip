@@ -2,8 +2,10 @@
 //
 // Device layout (2D).  Every field is a padded plane of FP64, x fastest:
 // row pitch `pitch` doubles, interior node (i, j) at (j + OY) * pitch +
-// (i + OX) with OX = 8 (64-byte aligned interior rows) and OY = 3; three
-// halo rows/columns on each side hold the periodic images.
+// (i + OX) with OX = 16 (interior rows start on a 128-byte cache line, so
+// the 128-wide update tiles touch whole lines) and OY = 3; three halo
+// rows/columns on each side hold the periodic images or the ghosts of
+// bounded sides.
 //   state buffer : 24 planes, plane = grid*12 + field*4 + comp
 //                  (grid 0 primary, 1 dual; field 0 W, 1 Wx, 2 Wy)
 //   edge buffer  : 2 families (X, Y) x 2 normals (primary-line, dual-line)
@@ -37,7 +39,7 @@ using fdk::Consts;
 
 namespace {
 
-constexpr int OX = 8, OY = 3, HALO = 3;
+constexpr int OX = 16, OY = 3, HALO = 3;
 
 // Bounded axes: along an axis whose sides are not periodic the dual grid has
 // nx + 1 (ny + 1) nodes, the first and last on the boundary lines.  Kernels
@@ -255,20 +257,22 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
 // neighbouring waves).  fam: X covers i in [-2, nx], j in [-1 - sy, ny+1]; Y
 // covers i in [-1 - sx, nx+1], j in [-2, ny] (everything the update of the
 // nodes reads, the dual boundary nodes of bounded axes included); block
-// (bx, by) covers TX points in i and TY/2 in j.  The partners exchange
-// tangential slopes and blend sums through LDS.  Every thread of the block
-// must call this.
+// (bx, by) covers TX points in i from ix0 + bx TX (threads outside the
+// family's range stay idle but join the barriers) and TY/2 in j.  The
+// partners exchange tangential slopes and blend sums through LDS.  Every
+// thread of the block must call this.
 template <int STAGE, class FT, bool CHAR = false>
 __device__ __forceinline__ void edge_block(const double* __restrict__ S, double* __restrict__ E, const Geo& g,
-                                           const Consts& k, double dt, int bx, int by, int fam) {
+                                           const Consts& k, double dt, int bx, int by, int fam, int ix0) {
   // LDS slots per thread: 0-3 tangential slope, 4-7 Wlt + Wrt, 8-11 Wl + Wr
   __shared__ double xch[12 * 256];
   const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
   const int TX = blockDim.x, TY = blockDim.y;
 #define XCH(c, r) xch[((c) * TY + (r)) * TX + tx]
-  const int i = bx * TX + tx + (fam == 0 ? -2 : -1 - g.sx);
+  const int i = bx * TX + tx + ix0;
   const int j = by * (TY >> 1) + (ty >> 1) + (fam == 0 ? -1 - g.sy : -2);
-  const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
+  const bool valid = i >= (fam == 0 ? -2 : -1 - g.sx) && i <= (fam == 0 ? g.nx : g.nx + 1) &&
+                     j <= (fam == 0 ? g.ny + 1 : g.ny);
   fdk::IfaceRec rec[4];
   if (valid) {
     edge_recon<CHAR>(S, g, k, i, j, fam, G, rec);
@@ -336,7 +340,7 @@ __global__ __launch_bounds__(256, FDCGKS_EDGE_WAVES) void k_edges2d(const double
   if (sc->stop) return;  // grid-uniform
   int t;
   if (!xcd_tile(blockIdx.x, gridDim.x, ntiles, t)) return;  // block-uniform
-  edge_block<STAGE, FT, CHAR>(S, E, g, k, sc->dt, t % tiles_x, t / tiles_x, blockIdx.z);
+  edge_block<STAGE, FT, CHAR>(S, E, g, k, sc->dt, t % tiles_x, t / tiles_x, blockIdx.z, -OX);
 }
 
 // ------------------------------------------------------------ node sweep
@@ -400,13 +404,14 @@ __host__ __device__ __forceinline__ int node_reach(const Consts& k) { return k.f
 // batches pass 1): w beyond the grid's own nodes, whose dual nodes start at
 // -1 on a bounded axis.  (A primary row at -w - 1 would read state row -w - 2,
 // beyond the 3-row halo when w = 2.)  Block (bx, by) of blockDim.x x
-// blockDim.y nodes.
+// blockDim.y nodes, x from ix0 + bx blockDim.x (threads outside the range
+// return).
 template <int STAGE, class FT, bool CHAR = false>
 __device__ __forceinline__ void node_block(const double* __restrict__ S, double* __restrict__ Nb, const Geo& g,
-                                           const Consts& k, int bx, int by, int grid, int w) {
-  const int i = bx * blockDim.x + threadIdx.x - w - (grid ? g.sx : 0);
+                                           const Consts& k, int bx, int by, int grid, int w, int ix0) {
+  const int i = bx * blockDim.x + threadIdx.x + ix0;
   const int j = by * blockDim.y + threadIdx.y - w - (grid ? g.sy : 0);
-  if (i > g.nx - 1 + w || j > g.ny - 1 + w) return;
+  if (i < -w - (grid ? g.sx : 0) || i > g.nx - 1 + w || j > g.ny - 1 + w) return;
   const long pl = g.plane, o = at(g, j, i);
   const double* B = S + (long)grid * 12 * pl + (grid ? g.dshift : 0);
   FT W[4], Wx[4], Wy[4];
@@ -433,7 +438,7 @@ __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, d
   if (sc->stop) return;
   int t;
   if (!xcd_tile(blockIdx.x, gridDim.x, ntiles, t)) return;
-  node_block<STAGE, FT, CHAR>(S, Nb, g, k, t % tiles_x, t / tiles_x, blockIdx.z, node_reach(k));
+  node_block<STAGE, FT, CHAR>(S, Nb, g, k, t % tiles_x, t / tiles_x, blockIdx.z, node_reach(k), -OX);
 }
 
 // ------------------------------------------------------ assemble + update
@@ -1256,7 +1261,8 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
     for (int q = blockIdx.x; q < a.n_edge; q += nb) {
       const BItem& w = it[q];
       const BMember& M = a.mem[w.m];
-      edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z);
+      edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z,
+                            w.z == 0 ? -2 : -1);
     }
   }
   it += a.n_edge;
@@ -1264,7 +1270,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
     for (int q = blockIdx.x; q < a.n_node; q += nb) {
       const BItem& w = it[q];
       const BMember& M = a.mem[w.m];
-      node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1);
+      node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1, -1);
     }
   }
   it += a.n_node;
@@ -1316,14 +1322,15 @@ __global__ __launch_bounds__(256, FDCGKS_EDGE_WAVES) void k_bphase_edges(BArgs a
   if (a.sc->stop) return;
   const BItem& w = a.items[a.n_cfl + a.n_halo + blockIdx.x];
   const BMember& M = a.mem[w.m];
-  edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z);
+  edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z,
+                        w.z == 0 ? -2 : -1);
 }
 template <int STAGE, class FT>
 __global__ __launch_bounds__(256) void k_bphase_nodes(BArgs a, Consts k) {
   if (a.sc->stop) return;
   const BItem& w = a.items[a.n_cfl + a.n_halo + a.n_edge + blockIdx.x];
   const BMember& M = a.mem[w.m];
-  node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1);
+  node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1, -1);
 }
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_bphase_update(BArgs a, Consts k) {
@@ -1468,7 +1475,9 @@ fdcgks_status halo2d(fdcgks_problem* pb, double* S) {
 template <int STAGE>
 void launch_edges(fdcgks_problem* pb, const double* Sin, dim3 blk) {
   const Geo& g = pb->g;
-  const int tx = ceil_div(g.nx + 3 + g.sx, blk.x), nt = tx * ceil_div(g.ny + 3 + g.sy, blk.y / 2);
+  // x tiles start at i = -OX (column 0 of the padded row), so every wave's
+  // row segment starts on a cache line; the last point is i = nx + 1
+  const int tx = ceil_div(g.nx + 2 + OX, blk.x), nt = tx * ceil_div(g.ny + 3 + g.sy, blk.y / 2);
   dim3 ge(ceil_div(nt, NXCD) * NXCD, 1, 2);  // tiles in XCD bands (xcd_tile)
   const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
   const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
@@ -1480,7 +1489,8 @@ template <int STAGE>
 void launch_nodes(fdcgks_problem* pb, const double* Sin, dim3 blk) {
   const Geo& g = pb->g;
   const int w = node_reach(pb->k);
-  const int tx = ceil_div(g.nx + 2 * w + g.sx, blk.x), nt = tx * ceil_div(g.ny + 2 * w + g.sy, blk.y);
+  // x tiles start at i = -OX (a cache-line boundary); the last node is nx - 1 + w
+  const int tx = ceil_div(g.nx + w + OX, blk.x), nt = tx * ceil_div(g.ny + 2 * w + g.sy, blk.y);
   dim3 gn(ceil_div(nt, NXCD) * NXCD, 1, 2);  // tiles in XCD bands (xcd_tile)
   const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
   const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
