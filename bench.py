@@ -39,7 +39,7 @@ HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doub
 # copy-kernel calibration).  Both are None whenever the kernel has changed
 # since the counters were taken.
 FLOPS_PER_IFACE_POINT_STAGE1 = 6813
-TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 4.867e9
+TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 4.473e9
 
 
 # Launch shapes fdcgks_autotune picks on this workload (interface sweep,
