@@ -442,7 +442,7 @@ def adjoint_comparison(pb, n, reps=2):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU decomposition is a design, not built", file=sys.stderr)
         sys.exit(2)
     import torch
