@@ -121,6 +121,25 @@ def test_full_size_sampled_order8(oracle):
     check_full_size_sampled(oracle, s, pr.P, pr.D, pb, label="2048^2 order 8")
 
 
+def test_fp32_flux_order8_error_report(oracle):
+    """The FP32 gas-kinetic variant with the order-8 flux (FP64 assembly and
+    update): one stage against the FP64 oracle, reported, and held to the
+    error level of the FP32 variant with the order-6 flux."""
+    s, P, D = CASES["shear_ns_36"]()
+    par = oracle_par(oracle, s)
+    dt = 0.2 * (s["lx"] / s["nx"]) / 3.0
+    oP, oD, _, _ = oracle.stage2d(par, 1, dt, P, D)
+    fl = _floors(s, P, D)
+    err = {}
+    for order in (6, 8):
+        so = dict(s, flux_order=order, fp32_flux=True)
+        g1, _ = _problem(so, P, D).debug_stage(1, dt)
+        ref = (oP, oD) if order == 8 else oracle.stage2d(oracle_par(oracle, dict(s, flux_order=6)), 1, dt, P, D)[:2]
+        err[order] = max(relerr(g1[g][:4], ref[g][:4], fl[:4])[0] for g in (0, 1))
+    print(f"FP32-flux stage-1 max-relative error on values: order 6 {err[6]:.3e}, order 8 {err[8]:.3e}")
+    assert err[8] < 1e-5 and err[8] < 10 * err[6]
+
+
 # ----------------------------------------------------------------------- 1D
 CASES1D = {
     "rough_77": lambda: (settings(dim=1, nx=77, lx=1.0, flux_order=8), T1._rough1d(77, 5)),
