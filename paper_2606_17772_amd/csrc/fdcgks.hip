@@ -1270,7 +1270,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
     for (int q = blockIdx.x; q < a.n_node; q += nb) {
       const BItem& w = it[q];
       const BMember& M = a.mem[w.m];
-      node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1, -1);
+      node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1, -OX);
     }
   }
   it += a.n_node;
@@ -1330,7 +1330,7 @@ __global__ __launch_bounds__(256) void k_bphase_nodes(BArgs a, Consts k) {
   if (a.sc->stop) return;
   const BItem& w = a.items[a.n_cfl + a.n_halo + a.n_edge + blockIdx.x];
   const BMember& M = a.mem[w.m];
-  node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1, -1);
+  node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1, -OX);
 }
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_bphase_update(BArgs a, Consts k) {
@@ -2496,7 +2496,7 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
         for (int bx = 0; bx < ceil_div(g.nx + 3, 64); ++bx) edge.push_back({m, z, bx, by});
     for (int z = 0; z < 2; ++z)
       for (int by = 0; by < ceil_div(g.ny + 2, 4); ++by)
-        for (int bx = 0; bx < ceil_div(g.nx + 2, 64); ++bx) node.push_back({m, z, bx, by});
+        for (int bx = 0; bx < ceil_div(g.nx + 1 + OX, 64); ++bx) node.push_back({m, z, bx, by});  // from i = -OX
     for (int z = 0; z < 2; ++z)
       for (int by = 0; by < ceil_div(g.ny, 4); ++by)
         for (int bx = 0; bx < ceil_div(g.nx, 64); ++bx) upd.push_back({m, z, bx, by});
