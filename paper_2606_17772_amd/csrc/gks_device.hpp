@@ -49,62 +49,15 @@ template <class T> FDK_HD T ipow(T x, int r) {
   return y;
 }
 
-// Forward-mode dual number (value, one tangent): running the same templated
-// arithmetic on it gives directional derivatives, from which the adjoint
-// kernels assemble local Jacobian-transpose products.
-struct DD {
-  double v, d;
-  FDK_HD DD() : v(0.0), d(0.0) {}
-  FDK_HD DD(double a) : v(a), d(0.0) {}
-  FDK_HD DD(double a, double b) : v(a), d(b) {}
-  FDK_HD explicit operator double() const { return v; }
-};
-FDK_HD DD operator+(DD a, DD b) { return DD(a.v + b.v, a.d + b.d); }
-FDK_HD DD operator-(DD a, DD b) { return DD(a.v - b.v, a.d - b.d); }
-FDK_HD DD operator-(DD a) { return DD(-a.v, -a.d); }
-FDK_HD DD operator*(DD a, DD b) { return DD(a.v * b.v, a.d * b.v + a.v * b.d); }
-FDK_HD DD operator/(DD a, DD b) {
-  double q = a.v / b.v;
-  return DD(q, (a.d - q * b.d) / b.v);
-}
-FDK_HD DD operator+(DD a, double b) { return DD(a.v + b, a.d); }
-FDK_HD DD operator+(double a, DD b) { return DD(a + b.v, b.d); }
-FDK_HD DD operator-(DD a, double b) { return DD(a.v - b, a.d); }
-FDK_HD DD operator-(double a, DD b) { return DD(a - b.v, -b.d); }
-FDK_HD DD operator*(DD a, double b) { return DD(a.v * b, a.d * b); }
-FDK_HD DD operator*(double a, DD b) { return DD(a * b.v, a * b.d); }
-FDK_HD DD operator/(DD a, double b) { return DD(a.v / b, a.d / b); }
-FDK_HD DD operator/(double a, DD b) {
-  double q = a / b.v;
-  return DD(q, -q * b.d / b.v);
-}
-FDK_HD DD& operator+=(DD& a, DD b) { a = a + b; return a; }
-FDK_HD DD& operator-=(DD& a, DD b) { a = a - b; return a; }
-FDK_HD DD& operator*=(DD& a, DD b) { a = a * b; return a; }
-FDK_HD bool operator>(DD a, DD b) { return a.v > b.v; }
-FDK_HD bool operator<(DD a, DD b) { return a.v < b.v; }
-FDK_HD bool operator>(DD a, double b) { return a.v > b; }
-FDK_HD bool operator<(DD a, double b) { return a.v < b; }
-FDK_HD DD m_erfc(DD a) { return DD(erfc(a.v), -1.1283791670955126 * exp(-a.v * a.v) * a.d); }
-FDK_HD DD m_exp(DD a) { double e = exp(a.v); return DD(e, e * a.d); }
-FDK_HD DD m_sqrt(DD a) { double q = sqrt(a.v); return DD(q, a.d / (2.0 * q)); }
-// |x| with derivative 0 at x == 0 (the adjoint's convention for ties)
-FDK_HD DD m_abs(DD a) { return a.v > 0 ? a : (a.v < 0 ? -a : DD(0.0, 0.0)); }
-
-// scalar helpers shared by double and DD (ties keep the first argument)
+// scalar helpers (ties keep the first argument)
 FDK_HD double g_abs(double a) { return fabs(a); }
 FDK_HD double g_max(double a, double b) { return fmax(a, b); }
 FDK_HD double g_min(double a, double b) { return fmin(a, b); }
 // tanh; beyond |a| = 19.5 it rounds to +-1 in FP64 (1 - tanh(a) < 2.3e-17,
 // under half an ulp of 1), so the library call is skipped there.
 FDK_HD double g_tanh(double a) { return a > 19.5 ? 1.0 : (a < -19.5 ? -1.0 : tanh(a)); }
-FDK_HD DD g_abs(DD a) { return m_abs(a); }
-FDK_HD DD g_max(DD a, DD b) { return b.v > a.v ? b : a; }
-FDK_HD DD g_min(DD a, DD b) { return b.v < a.v ? b : a; }
-FDK_HD DD g_tanh(DD a) { double t = g_tanh(a.v); return DD(t, (1.0 - t * t) * a.d); }
 FDK_HD double val(double a) { return a; }
 FDK_HD float val(float a) { return a; }
-FDK_HD double val(DD a) { return a.v; }
 
 // ----------------------------------------------------- GENO, Sec. 3 / App. C
 // Path function and blend of one side.  IS1 is the IS^tau reference;
