@@ -1,0 +1,50 @@
+"""Source-level operation count of the stage-1 interface sweep (CPU).
+
+tests/opcount_iface.cpp runs the library's own reconstruction and
+gas-kinetic solver templates on the host with a counting scalar, for one
+interface point (two solves).  The counts put the roofline's flop figure in
+context: the benchmark divides the FP64 operations the GPU executes (6,813
+per point, hardware counters, FMA = 2) by the launch time; the source-level
+count of the same arithmetic is higher, because the compiler folds constants
+and shares subexpressions that the source repeats."""
+import json
+import os
+import shutil
+import subprocess
+
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+
+
+@pytest.fixture(scope="module")
+def counts(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    exe = str(tmp_path_factory.mktemp("opcount") / "opcount")
+    subprocess.run([HIPCC, "-std=c++17", "-O1", "--cuda-host-only", "-x", "hip",
+                    os.path.join(HERE, "opcount_iface.cpp"), "-o", exe], check=True, capture_output=True)
+    out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout
+    rows = [json.loads(l) for l in out.splitlines() if l.strip()]
+    return {r["case"]: r for r in rows}
+
+
+def test_transcendental_calls_per_interface_point(counts):
+    """Per solve: two erfc and two exp for the half-space moments of the two
+    sides, one exp for the time coefficients, four square roots; tanh only
+    where a GENO path function does not saturate."""
+    for case in ("smooth", "jump"):
+        c = counts[case]
+        assert (c["erfc"], c["exp"], c["sqrt"]) == (4, 6, 8), c
+    assert counts["smooth"]["tanh"] == 0
+    assert counts["jump"]["tanh"] == 16  # 2 solves x 4 components x 2 sides
+
+
+def test_arithmetic_count(counts):
+    s, j = counts["smooth"], counts["jump"]
+    print("source-level operations per interface point:", s, j)
+    # the low-order blends run only at the jump
+    assert j["arith"] > s["arith"] and j["div"] > s["div"]
+    # above the executed FP64 count of the GPU build (6,813 flop per point)
+    assert 6813 < s["arith"] < 15000
