@@ -463,7 +463,8 @@ template <int STAGE, class NF, bool WIDE = false>
 __device__ __forceinline__ void update_node(const double* __restrict__ S, const double* __restrict__ E,
                                             const NF& nf, const double* __restrict__ Ain, double* __restrict__ Out,
                                             double* __restrict__ Aout, const Geo& g, const Consts& k, double dt,
-                                            int i, int j, int grid, Scal* sc, int member) {
+                                            int i, int j, int grid, Scal* sc, int member, bool want_cfl,
+                                            double& cfl_s, double& cfl_r) {
   const long pl = g.plane, o = at(g, j, i);
   const int r = grid;
   const long so = o + (grid ? g.dshift : 0);  // the dual planes are shifted along bounded axes
@@ -488,7 +489,7 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
         if (type == FDCGKS_BC_NO_SLIP || c == 1 + a) zero |= (1 << c) | (1 << (4 * along + c));
     }
   }
-  double rho = 0.0, mom2 = 0.0, ener = 0.0;  // the new values, for the physicality check
+  double rho = 0.0, mom2 = 0.0, ener = 0.0, mU = 0.0, mV = 0.0;  // the new values
 #pragma unroll FDCGKS_UPDATE_UNROLL
   for (int c = 0; c < 4; ++c) {
     double L = 0.0, Lt = 0.0, Gr[2], Grt[2];
@@ -559,7 +560,20 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
     __builtin_nontemporal_store((double)(GY), &out[(8 + c) * pl]);
     if (c == 0) rho = W;
     else if (c == 3) ener = W;
-    else mom2 = mom2 + W * W;
+    else {
+      mom2 = mom2 + W * W;
+      if (c == 1) mU = W;
+      else mV = W;
+    }
+  }
+  if (want_cfl) {
+    // wave speed and density of the new state, written as the CFL reduction
+    // (k_cfl_partial) writes them, so the next step's dt is bit for bit the same
+    const double U = mU / rho, V = mV / rho;
+    const double pc = (k.gamma - 1.0) * (ener - 0.5 * rho * (U * U + V * V));
+    const double c = sqrt(k.gamma * pc / rho);
+    cfl_s = fmax(fabs(U), fabs(V)) + c;
+    cfl_r = rho;
   }
   // non-physical state: rho <= 0, p <= 0 or NaN stops the run
   double p = (k.gamma - 1.0) * (ener - 0.5 * mom2 / rho);
@@ -589,12 +603,34 @@ __device__ __forceinline__ void update_block(const double* __restrict__ S, const
                                              const double* __restrict__ Nb, const double* __restrict__ Ain,
                                              double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
                                              const Consts& k, double dt, int bx, int by, int grid, Scal* sc,
-                                             int member) {
+                                             int member, bool want_cfl, double& cfl_s, double& cfl_r) {
   const int i = bx * blockDim.x + threadIdx.x - (grid ? g.sx : 0);
   const int j = by * blockDim.y + threadIdx.y - (grid ? g.sy : 0);
   if (i >= g.nx || j >= g.ny) return;
   const NodeFluxGlobal nf{Nb + (long)grid * 16 * g.plane + at(g, j, i), g.plane, g.pitch};
-  update_node<STAGE, NodeFluxGlobal, WIDE>(S, E, nf, Ain, Out, Aout, g, k, dt, i, j, grid, sc, member);
+  update_node<STAGE, NodeFluxGlobal, WIDE>(S, E, nf, Ain, Out, Aout, g, k, dt, i, j, grid, sc, member, want_cfl,
+                                           cfl_s, cfl_r);
+}
+
+// Folds a wave's CFL contributions (largest wave speed, smallest density)
+// into the partials slot of its block, so that the next step's time step
+// needs no separate pass over the state.  Both are reduced as k_cfl_partial
+// reduces them (speeds from 0, NaN speeds dropped).  Speeds are >= 0 and the
+// densities kept are > 0, so their bit patterns order like their values.
+__device__ __forceinline__ void cfl_fold(double* __restrict__ part, int nparts, double s, double r) {
+  s = fmax(0.0, s);
+  if (!(r > 0.0)) r = 1e300;  // a non-physical density has already stopped the run
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s = fmax(s, __shfl_xor(s, off));
+    r = fmin(r, __shfl_xor(r, off));
+  }
+  if (((threadIdx.y * blockDim.x + threadIdx.x) & 63) == 0) {
+    const int slot = (int)((blockIdx.x + (long)gridDim.x * (blockIdx.y + (long)gridDim.y * blockIdx.z)) % nparts);
+    atomicMax(reinterpret_cast<unsigned long long*>(part + 2 * slot), (unsigned long long)__double_as_longlong(s));
+    atomicMin(reinterpret_cast<unsigned long long*>(part + 2 * slot + 1),
+              (unsigned long long)__double_as_longlong(r));
+  }
 }
 
 // ------------------------------------------- node sweep fused into update
@@ -662,18 +698,27 @@ __global__ __launch_bounds__(256) void k_nodeupd2d(const double* __restrict__ S,
   const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
   if (i >= g.nx || j >= g.ny) return;
   const NodeFluxShared nf{xs, ys, (int)threadIdx.x, (int)threadIdx.y};
-  update_node<STAGE>(S, E, nf, Ain, Out, Aout, g, k, sc->dt, i, j, grid, sc, 0);
+  double cs = 0.0, cr = 0.0;  // no CFL fold in the fused kernel
+  update_node<STAGE>(S, E, nf, Ain, Out, Aout, g, k, sc->dt, i, j, grid, sc, 0, false, cs, cr);
 }
 
 template <int STAGE, bool WIDE>
-// stage 2 reads and writes half the planes of stage 1: 80 VGPRs, 6 waves/SIMD;
-// the order-8 assembly holds two more nodal fluxes per axis: one wave fewer
-__global__ __launch_bounds__(256, (STAGE == 2 ? 6 : 4) - (WIDE ? 1 : 0)) void k_update2d(const double* __restrict__ S, const double* __restrict__ E,
+// stage 2 reads and writes half the planes of stage 1 and folds the CFL
+// partials: up to 96 VGPRs, 5 waves/SIMD; the order-8 assembly holds two more
+// nodal fluxes per axis: one wave fewer
+__global__ __launch_bounds__(256, (STAGE == 2 ? 5 : 4) - (WIDE ? 1 : 0)) void k_update2d(const double* __restrict__ S, const double* __restrict__ E,
                                                   const double* __restrict__ Nb, const double* __restrict__ Ain,
                                                   double* __restrict__ Out, double* __restrict__ Aout, Geo g,
-                                                  Consts k, Scal* __restrict__ sc) {
-  if (sc->stop) return;
-  update_block<STAGE, WIDE>(S, E, Nb, Ain, Out, Aout, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z, sc, 0);
+                                                  Consts k, Scal* __restrict__ sc, double* __restrict__ part,
+                                                  int nparts) {
+  if (sc->stop) return;  // grid-uniform
+  // part (stage 2 of a CFL step after the first): fold the new state's wave
+  // speeds into the time-step partials; every lane reaches the fold
+  double s = 0.0, r = 1e300;
+  const bool fold = STAGE == 2 && part != nullptr;
+  update_block<STAGE, WIDE>(S, E, Nb, Ain, Out, Aout, g, k, sc->dt, blockIdx.x, blockIdx.y, blockIdx.z, sc, 0, fold,
+                            s, r);
+  if (fold) cfl_fold(part, nparts, s, r);
 }
 
 // ================================================================== 1D
@@ -1076,7 +1121,7 @@ __global__ __launch_bounds__(256) void k_diag_partial(const double* __restrict__
 
 // Start of a step: dt from the partials (or the fixed dt), clipped to t_end;
 // sets the "done" bit when t has reached t_end.
-__global__ void k_step_begin(const double* __restrict__ part, int nparts, Scal* __restrict__ sc, double cfl,
+__global__ void k_step_begin(double* __restrict__ part, int nparts, Scal* __restrict__ sc, double cfl,
                              double h, double mu, int use_cfl) {
   __shared__ double smax[256], smin[256];
   double vmax = 0.0, rmin = 1e300;
@@ -1084,6 +1129,9 @@ __global__ void k_step_begin(const double* __restrict__ part, int nparts, Scal* 
     for (int t = threadIdx.x; t < nparts; t += blockDim.x) {
       vmax = fmax(vmax, part[2 * t]);
       rmin = fmin(rmin, part[2 * t + 1]);
+      // emptied for the fold of the next state by this step's stage-2 update
+      part[2 * t] = 0.0;
+      part[2 * t + 1] = 1e300;
     }
   smax[threadIdx.x] = vmax;
   smin[threadIdx.x] = rmin;
@@ -1281,12 +1329,13 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
       const BItem& w = it[q];
       const BMember& M = a.mem[w.m];
       const double dt = member_dt(a, w.m, k);
+      double cs = 0.0, cr = 0.0;  // batches reduce their time steps themselves
       if (STAGE == 1)
         update_block<1, false>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc,
-                               w.m);
+                               w.m, false, cs, cr);
       else
         update_block<2, false>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z,
-                               a.sc, w.m);
+                               a.sc, w.m, false, cs, cr);
     }
   }
   if (STAGE == 2) {
@@ -1338,11 +1387,13 @@ __global__ __launch_bounds__(256) void k_bphase_update(BArgs a, Consts k) {
   const BItem& w = a.items[a.n_cfl + a.n_halo + a.n_edge + a.n_node + blockIdx.x];
   const BMember& M = a.mem[w.m];
   const double dt = member_dt(a, w.m, k);
+  double cs = 0.0, cr = 0.0;  // batches reduce their time steps themselves
   if (STAGE == 1)
-    update_block<1, false>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m);
+    update_block<1, false>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m,
+                           false, cs, cr);
   else
     update_block<2, false>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z, a.sc,
-                           w.m);
+                           w.m, false, cs, cr);
 }
 __global__ void k_bphase_end(BArgs a, Consts k) { batch_step_end(a, k); }
 
@@ -1392,6 +1443,7 @@ struct fdcgks_problem {
   // captured whole steps (one graph per ping-pong parity), replayed by fdcgks_step
   int graph_steps = 16;  // steps per captured graph; 0: separate launches
   bool fuse_nodes = false;  // node sweep inside the update kernel
+  bool cfl_fold = false;    // the stage-2 update being launched folds the CFL partials
   hipStream_t cap = nullptr;
   hipGraphExec_t gx[2] = {nullptr, nullptr};
   bool g_valid = false;
@@ -1503,7 +1555,9 @@ void launch_update(fdcgks_problem* pb, const double* Sin, const double* Ain, dou
   const Geo& g = pb->g;
   dim3 gu(ceil_div(g.nx + g.sx, blk.x), ceil_div(g.ny + g.sy, blk.y), 2);
   auto fn = pb->k.flux_order == 8 ? k_update2d<STAGE, true> : k_update2d<STAGE, false>;
-  hipLaunchKernelGGL(fn, gu, blk, 0, pb->stream, Sin, pb->E, pb->Nb, Ain, Out, Aout, g, pb->k, pb->sc);
+  double* fold = STAGE == 2 && pb->cfl_fold ? pb->part : nullptr;
+  hipLaunchKernelGGL(fn, gu, blk, 0, pb->stream, Sin, pb->E, pb->Nb, Ain, Out, Aout, g, pb->k, pb->sc, fold,
+                     pb->nparts);
 }
 
 // One stage.  fused: the node sweep runs inside the update kernel and the
@@ -1534,10 +1588,16 @@ fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, 
   return launch_check(pb, "stage");
 }
 
-fdcgks_status begin_step(fdcgks_problem* pb, double dt, double cfl) {
+// Whether a CFL step's stage-2 update folds the partials for the next step:
+// 2D steps with the separate node sweep (the fused node kernel does not fold).
+bool fold_ok(const fdcgks_problem* pb, double dt) { return !(dt > 0) && !pb->fuse_nodes && pb->prm.dim == 2; }
+
+// fresh: reduce the CFL partials from the state (the first step of a call or
+// graph); otherwise the previous step's stage-2 update folded them.
+fdcgks_status begin_step(fdcgks_problem* pb, double dt, double cfl, bool fresh = true) {
   const Geo& g = pb->g;
   int use_cfl = dt > 0 ? 0 : 1;
-  if (use_cfl) {
+  if (use_cfl && fresh) {
     long gstride = (pb->prm.dim == 2 ? 12 : 6) * g.plane;
     if (pb->prm.dim == 2)
       hipLaunchKernelGGL(k_cfl_partial<2>, dim3(pb->nparts), dim3(256), 0, pb->stream, pb->S[pb->cur], g, pb->ngrid,
@@ -1592,9 +1652,11 @@ fdcgks_status capture_steps(fdcgks_problem* pb, double dt, double cfl) {
     fdcgks_status st = FDCGKS_OK;
     for (int q = 0, cc = c; q < pb->graph_steps && !st; ++q, cc = 1 - cc) {
       pb->cur = cc;
-      st = begin_step(pb, dt, cfl);
+      st = begin_step(pb, dt, cfl, q == 0 || !fold_ok(pb, dt));
       if (!st) st = stage2d<1>(pb, pb->S[cc], nullptr, pb->Sstar, pb->Acc, pb->fuse_nodes);
+      pb->cfl_fold = fold_ok(pb, dt);
       if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cc], nullptr, pb->fuse_nodes);
+      pb->cfl_fold = false;
       if (!st) {
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, pb->stream, pb->sc);
         st = launch_check(pb, "step_end");
@@ -2067,10 +2129,12 @@ fdcgks_status fdcgks_step(fdcgks_problem* pb, double dt, double cfl, int32_t nst
   }
   for (int s = 0; s < nsteps; ++s) {
     pb->cur = cur;
-    st = begin_step(pb, dt, cfl);
+    st = begin_step(pb, dt, cfl, s == 0 || !fold_ok(pb, dt));
     mark(pb, TK_STEP);
     if (!st) st = stage2d<1>(pb, pb->S[cur], nullptr, pb->Sstar, pb->Acc, pb->fuse_nodes);
+    pb->cfl_fold = fold_ok(pb, dt);
     if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cur], nullptr, pb->fuse_nodes);
+    pb->cfl_fold = false;
     if (st) break;
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, pb->stream, pb->sc);
     mark(pb, TK_STEP);

@@ -83,6 +83,40 @@ def test_fused_node_sweep_is_bitwise_equal(case):
         assert np.array_equal(a.get_state_all(), b.get_state_all()), rep
 
 
+@pytest.mark.parametrize("case", [0, 1, "walled"])
+def test_cfl_fold_matches_fresh_reduction(case):
+    """Within one call, the time step of every CFL step after the first comes
+    from the wave speeds the previous step's stage-2 update folded; one step
+    per call reduces them from the stored state.  Both give the same time
+    steps and states bit for bit, with and without captured steps."""
+    from paper_2606_17772_amd import Problem
+    from tests import test_gpu_boundaries as TB
+    if case == "walled":  # the dual grid holds one more node per bounded axis
+        s, P, D = TB._case_mixed()
+    else:
+        s, pr = _cases()[case]
+        P, D = pr.P, pr.D
+
+    def make(**opt):
+        pb = Problem(gpu_params(s))
+        pb.set_state_stacked(0, P)
+        pb.set_state_stacked(1, D)
+        for k, v in opt.items():
+            setattr(pb, k, v)
+        return pb
+
+    one, run, cap = make(use_graph=False), make(use_graph=False), make(graph_steps=3)
+    t1 = 0.0
+    for _ in range(7):
+        t1, n = one.step(nsteps=1, cfl=0.5, t=t1)
+        assert n == 1
+    for pb in (run, cap):
+        t, n = pb.step(nsteps=7, cfl=0.5)
+        assert n == 7 and t == t1
+        for g in (0, 1):
+            assert np.array_equal(pb.get_state_stacked(g), one.get_state_stacked(g))
+
+
 def test_invalid_launch_shapes_rejected():
     from paper_2606_17772_amd import FdcgksError
     s, pr = _cases()[0]
