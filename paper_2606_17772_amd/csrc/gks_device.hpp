@@ -75,13 +75,36 @@ FDK_HD GenoOutT<R> geno(const Consts& k, R IS1, R IS2, R IS3, double d1, double 
   R ISH = g_max(IS1, g_max(IS2, IS3));
   R ISL = g_min(IS1, g_min(IS2, IS3));
   R eH = ISH + k.eps, eL = ISL + k.eps;
+  GenoOutT<R> o;
+  // Smooth data decided before any division.  With A = eH^r + tau^r and
+  // B = eL^r + tau^r, alpha below equals 2 A eL^r / (A eL^r + B eH^r).  Where
+  // C alpha >= 19.5 (1 + 1e-12) in that division-free form (rounding moves it
+  // by a few 1e-16), the alpha computed below gives C alpha > 19.5, tanh is 1,
+  // and with 1/tanh(C) = 1 the value returned is the one of the shortcut
+  // further down.  Other points (and inf / NaN / underflowed products) take
+  // the full path.
+  if (k.inv_tanhC == 1.0) {
+    R pH = eH, pL = eL, pt = tau;
+    for (int q = 1; q < k.r; ++q) {
+      pH = pH * eH;
+      pL = pL * eL;
+      pt = pt * tau;
+    }
+    R a = (pH + pt) * pL, b = (pL + pt) * pH;
+    R lhs = (2.0 * k.C) * a, rhs = (19.5 * (1.0 + 1e-12)) * (a + b);
+    if (val(rhs) >= 1e-290 && val(lhs) <= 1e300 && val(lhs) >= val(rhs)) {
+      o.v = PH;
+      o.d = PHx;
+      o.chi = R(1.0);
+      return o;
+    }
+  }
   R inv = 1.0 / (eH * eL);
   R xH = tau * eL * inv, xL = tau * eH * inv;
   R aH = 1.0 + ipow(xH, k.r), aL = 1.0 + ipow(xL, k.r);
   R alpha = 2.0 * aH / (aH + aL);
   R th = g_tanh(k.C * alpha);
   R chi = th * k.inv_tanhC;
-  GenoOutT<R> o;
   // Smooth data: tanh saturates (its derivative is 0) and chi = 1 exactly, so
   // the low-order blend has weight 0 in the value and in every derivative.
   if (val(th) == 1.0 && val(chi) == 1.0) {
