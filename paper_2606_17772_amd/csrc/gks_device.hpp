@@ -414,8 +414,8 @@ template <class FT> FDK_HD void mom_full(const Prim<FT>& s, Mom<FT>& m) {
 template <class FT> FDK_HD void mom_half(const Prim<FT>& s, FT sgn, Mom<FT>& m) {
   FT sl = m_sqrt(s.lam);
   m.mu[0] = FT(0.5) * m_erfc(-sgn * sl * s.U);
-  // 1/(2 sqrt(pi lambda)) = sqrt(1/(2 lambda)) / sqrt(2 pi)
-  m.mu[1] = s.U * m.mu[0] + sgn * m_exp(-s.lam * s.U * s.U) * m_sqrt(s.i2l) * FT(0.39894228040143267794);
+  // 1/(2 sqrt(pi lambda)) = (1/(2 lambda)) sqrt(lambda) / sqrt(pi): no second square root
+  m.mu[1] = s.U * m.mu[0] + sgn * m_exp(-s.lam * s.U * s.U) * (s.i2l * sl) * FT(0.56418958354775628695);
   mu_rec(m.mu, s.U, s.i2l);
 }
 
