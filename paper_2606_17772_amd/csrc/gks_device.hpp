@@ -384,7 +384,7 @@ template <int P, class FT> FDK_HD void ma1(const FT s[3], const Mom<FT>& m, FT o
 
 // Primitive variables and the shared v / xi moments of a state.
 template <class FT> struct Prim {
-  FT rho, irho, U, V, p, lam, i2l;
+  FT rho, irho, U, V, p, lam, i2l, ip;  // ip = 1/p
 };
 template <class FT, int DIM> FDK_HD Prim<FT> prim(const FT* W, FT gamma) {
   Prim<FT> s;
@@ -395,7 +395,8 @@ template <class FT, int DIM> FDK_HD Prim<FT> prim(const FT* W, FT gamma) {
   FT rE = W[DIM + 1];
   s.p = (gamma - FT(1)) * (rE - FT(0.5) * s.rho * (s.U * s.U + s.V * s.V));
   s.i2l = s.p * s.irho;          // 1/(2 lambda) = p/rho
-  s.lam = FT(0.5) / s.i2l;
+  s.ip = FT(1) / s.p;            // lambda = rho/(2p); 1/p also serves the collision time
+  s.lam = FT(0.5) * s.rho * s.ip;
   return s;
 }
 template <class FT, int DIM> FDK_HD void mom_common(const Prim<FT>& s, FT K, Mom<FT>& m) {
@@ -587,7 +588,7 @@ FDK_HD void gks_iface(const Consts& k, FT dt, GksIO<FT, DIM>& io) {
   }
   Prim<FT> s0 = prim<FT, DIM>(W0, gam);
   // collision time and time coefficients
-  FT tau = (k.mu > 0 ? FT(k.mu) / s0.p : FT(k.tau_c1) * dt) +
+  FT tau = (k.mu > 0 ? FT(k.mu) * s0.ip : FT(k.tau_c1) * dt) +
            FT(k.tau_c2) * dt * m_abs(sL.p - sR.p) / (sL.p + sR.p);
   TimeCoef<FT> tc = time_coef(dt, tau);
   FT F[N], We[N], Wet[N], WtL[N], WtR[N];
@@ -689,7 +690,7 @@ FDK_HD void gks_node(const Consts& k, const FT* W, const FT* Wx, const FT* Wy, F
 #pragma unroll
   for (int i = 0; i < N; ++i) d[i] = -tr[i];
   slope<FT, DIM>(s, K, iKd, d, A);
-  FT tauN = k.mu > 0 ? FT(k.mu) / s.p : FT(0);
+  FT tauN = k.mu > 0 ? FT(k.mu) * s.ip : FT(0);
   const bool visc = k.mu > 0;
   FT Fu[N], Gv[N];
   if (DIM == 2) {
