@@ -441,6 +441,7 @@ template <class T> void slope(const Maxw<T>& full, T rho, const T* D, int dim, T
 // BGK-NS solution it cites, with decisions D10-D14, D21.
 template <class T> struct GksOut {
   T F[4], Ft[4], We[4], Wet[4], Wl[4], Wr[4], Wlt[4], Wrt[4];
+  T W0[4];  // compatibility state
   T tau;
 };
 
@@ -473,6 +474,7 @@ void gks_interface(const Par& p, int dim, const T* WL, const T* WR, const T* WnL
   T W0[4];
   for (int i = 0; i < n; ++i)
     W0[i] = sl.rho * avg(mlh, ppsi<T>(i, dim)) + sr.rho * avg(mrh, ppsi<T>(i, dim));
+  for (int i = 0; i < n; ++i) o.W0[i] = W0[i];
   Prim<T> s0 = prim(W0, dim, g);
   Maxw<T> m0 = maxwell(s0.U, s0.V, s0.lam, K, 0, dim);
   // spatial micro slopes (normal a, tangential b); D12 for the equilibrium
@@ -1116,7 +1118,7 @@ void orc_slope(const double* W, const double* D, int dim, double gamma, double* 
   slope(m, q.rho, D, dim, s);
 }
 void orc_qcoef(double T_, double tau, double* q) { qcoef(T_, tau, q); }
-// out: F, Ft, We, Wet, Wl, Wr, Wlt, Wrt (each dim+2), then tau
+// out: F, Ft, We, Wet, Wl, Wr, Wlt, Wrt (each dim+2), then tau, then W0 (dim+2)
 void orc_gks_interface(const Par* p, int dim, const double* WL, const double* WR, const double* WnL,
                        const double* WnR, const double* Wt, double dt, double* out) {
   GksOut<double> o;
@@ -1125,6 +1127,7 @@ void orc_gks_interface(const Par* p, int dim, const double* WL, const double* WR
   const double* src[8] = {o.F, o.Ft, o.We, o.Wet, o.Wl, o.Wr, o.Wlt, o.Wrt};
   for (int s = 0; s < 8; ++s) for (int i = 0; i < n; ++i) out[s * n + i] = src[s][i];
   out[8 * n] = o.tau;
+  for (int i = 0; i < n; ++i) out[8 * n + 1 + i] = o.W0[i];
 }
 // out: F, Ft, G, Gt (each dim+2)
 void orc_gks_node(const Par* p, int dim, const double* W, const double* Wx, const double* Wy, double* out) {

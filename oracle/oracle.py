@@ -194,13 +194,14 @@ def qcoef(T, tau):
 
 def gks_interface(par, dim, WL, WR, WnL, WnR, Wt, dt):
     n = dim + 2
-    out = np.zeros(8 * n + 1)
+    out = np.zeros(9 * n + 1)
     wt = _arr(Wt if Wt is not None else np.zeros(n), n)
     lib().orc_gks_interface(C.byref(par), dim, _p(_arr(WL, n)), _p(_arr(WR, n)), _p(_arr(WnL, n)),
                             _p(_arr(WnR, n)), _p(wt), dt, _p(out))
     keys = ["F", "Ft", "We", "Wet", "Wl", "Wr", "Wlt", "Wrt"]
     r = {k: out[i * n:(i + 1) * n].copy() for i, k in enumerate(keys)}
     r["tau"] = out[8 * n]
+    r["W0"] = out[8 * n + 1:9 * n + 1].copy()
     return r
 
 

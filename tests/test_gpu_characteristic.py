@@ -12,7 +12,7 @@ import pytest
 
 import workloads as WL
 from tests.helpers import (TOL, check_edge_intermediates, floors_edge, floors_node, floors_state,
-                           floors_state_interval, gpu_params, oracle_par, ref_scales, relerr, settings,
+                           check_full_size_sampled, gpu_params, oracle_par, ref_scales, relerr, settings,
                            ulp_sensitivity)
 from tests.test_gpu_parity1d import CASES as CASES1D
 from tests.test_gpu_parity1d import _floors as _floors1d
@@ -135,27 +135,13 @@ def test_fp32_flux_char_error_report(oracle):
 
 def test_full_size_sampled_char(oracle):
     """One step of the 2048^2 shear layer in characteristic mode, in the
-    benchmark's launch shapes, on sampled nodes (gradients compared as
-    interval differences, as in the conservative full-size test)."""
+    benchmark's launch shapes, on sampled nodes (bars: check_full_size_sampled)."""
     n = 2048
     pr = WL.shear_layer(n, seed=0)
     s = settings(dim=2, nx=n, ny=n, lx=1.0, mu=1e-4, prandtl=0.72, **CHAR)
-    par = oracle_par(oracle, s)
     pb = _problem(s, pr.P, pr.D)
     _bench_tiles(pb)
-    dt = pb.compute_dt(0.5)
-    rng = np.random.default_rng(1)
-    ns = 32
-    grid = rng.integers(0, 2, ns)
-    jj = np.concatenate([[0, n - 1], rng.integers(0, n, ns - 2)])
-    ii = np.concatenate([[n - 1, 0], rng.integers(0, n, ns - 2)])
-    o1, a1 = oracle.stage2d_sample(par, 1, dt, pr.P, pr.D, grid, jj, ii)
-    g1, ga = pb.debug_stage(1, dt)
-    fl = floors_state_interval(ref_scales([pr.P, pr.D], s["gamma"], s["lx"]), 1.0 / n)
-    for g, o in ((g1, o1), (ga, a1)):
-        gs = np.stack([g[grid[k], :, jj[k], ii[k]] for k in range(ns)])
-        for f in range(12):
-            assert np.abs(gs[:, f] - o[:, f]).max() / max(np.abs(o[:, f]).max(), fl[f]) <= TOL, f
+    check_full_size_sampled(oracle, s, pr.P, pr.D, pb, ns=32, seed=1, label="2048^2 characteristic")
 
 
 @pytest.mark.parametrize("name", list(CASES1D))
