@@ -198,6 +198,33 @@ fdcgks_status fdcgks_step(fdcgks_problem* pb, double dt, double cfl, int32_t nst
 fdcgks_status fdcgks_step_timed(fdcgks_problem* pb, double dt, double cfl, int32_t nsteps, double t_end,
                                 double* t_inout, int32_t* steps_done, double* kernel_ms);
 
+/* ---------------------------------------------------- allocation-free run
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the 1D run
+ * of fdcgks_create + fdcgks_set_state + fdcgks_step + fdcgks_get_state in one
+ * call that allocates nothing.  Every working buffer (state ping-pong, stage
+ * buffers, interface and node results, step scalars) lives in a static device
+ * array of the library, about 11.4 MB per device, held until the process
+ * ends; the call itself does no hipMalloc, hipFree or other allocation.
+ *   p       : a 1D problem (dim 1, ny 1), nx <= 2048; periodic, zero-gradient
+ *             or reflecting ends, dual_1d for the shifted copy; the other
+ *             fields as for fdcgks_create;
+ *   state   : device memory of the current device, [lines][6][nx] doubles
+ *             (lines = 2 with dual_1d, else 1; per line W[3] then Wx[3], each
+ *             nx contiguous), read at the start and overwritten with the
+ *             state after the last completed step;
+ *   dt, cfl, nsteps, t_end, t_inout, steps_done: as for fdcgks_step.
+ * Runs on hip_stream (0 = the null stream) and synchronizes it once, to
+ * return t and the step count.  Results are bitwise those of the handle
+ * path.  EINVAL for larger problems, 2D, NULL pointers or a state pointer
+ * that is not device memory of the current device; ENONPHYS as fdcgks_step
+ * (state = the last good step).  Messages: fdcgks_last_error(NULL).
+ * Calls on one device share the array: calls that overlap in time on one
+ * device (other threads, other streams) race and must be serialised by the
+ * caller. */
+fdcgks_status fdcgks_step1d_static(const fdcgks_params* p, double* state, double dt, double cfl, int32_t nsteps,
+                                   double t_end, double* t_inout, int32_t* steps_done, void* hip_stream);
+
 /* Free all device memory of the problem.  NULL is accepted. */
 fdcgks_status fdcgks_destroy(fdcgks_problem* pb);
 

@@ -20,7 +20,7 @@ from . import _lib
 from ._lib import (BC_NO_SLIP, BC_PERIODIC, BC_REFLECTING, BC_ZERO_GRADIENT, FLUX_6_2, FLUX_6_4, FLUX_LINEAR, FP32_FLUX, FP64,  # noqa: F401
                    GRAD_CARRIED, GRAD_REEVAL, RECON_CHARACTERISTIC, RECON_CONSERVATIVE, FdcgksError, Params)
 
-__all__ = ["Problem", "Batch", "Params", "FdcgksError", "default_params", "make_params"]
+__all__ = ["Problem", "Batch", "Params", "FdcgksError", "default_params", "make_params", "step1d_static"]
 
 _VARIANTS = {"6-4": FLUX_6_4, "6-2": FLUX_6_2, "linear": FLUX_LINEAR}
 _BCS = {"periodic": BC_PERIODIC, "zero_gradient": BC_ZERO_GRADIENT, "reflecting": BC_REFLECTING,
@@ -94,6 +94,23 @@ def _ptr(a, writable=False):
             raise TypeError("tensors must be contiguous float64")
         return C.c_void_p(a.data_ptr()), (1 if a.is_cuda else 0), a
     raise TypeError(f"unsupported array type {type(a)}")
+
+
+def step1d_static(params: Params, state, nsteps=1, dt=0.0, cfl=0.5, t_end=0.0, t=0.0, stream=None):
+    """fdcgks_step1d_static: a whole 1D run that allocates nothing on the
+    device.  state: a contiguous float64 CUDA tensor of shape (lines, 6, nx)
+    (lines = 2 with dual_1d), advanced in place.  Returns (t, steps_done)."""
+    L = _lib.load()
+    torch = _torch()
+    if not (isinstance(state, torch.Tensor) and state.is_cuda and state.dtype == torch.float64
+            and state.is_contiguous()):
+        raise TypeError("state must be a contiguous float64 CUDA tensor")
+    tt = C.c_double(t)
+    n = C.c_int32()
+    s = _current_stream() if stream is None else C.c_void_p(stream)
+    _lib.check(L.fdcgks_step1d_static(C.byref(params), C.c_void_p(state.data_ptr()), dt, cfl, nsteps, t_end,
+                                      C.byref(tt), C.byref(n), s))
+    return tt.value, n.value
 
 
 class Problem:

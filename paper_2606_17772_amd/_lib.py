@@ -58,6 +58,8 @@ SIGNATURES = {
     "fdcgks_diagnostics": (C.c_int, [_vp, _dp]),
     "fdcgks_step": (C.c_int, [_vp, C.c_double, C.c_double, _i32, C.c_double, _dp, C.POINTER(_i32)]),
     "fdcgks_step_timed": (C.c_int, [_vp, C.c_double, C.c_double, _i32, C.c_double, _dp, C.POINTER(_i32), _dp]),
+    "fdcgks_step1d_static": (C.c_int, [C.POINTER(Params), _vp, C.c_double, C.c_double, _i32, C.c_double, _dp,
+                                       C.POINTER(_i32), _vp]),
     "fdcgks_destroy": (C.c_int, [_vp]),
     "fdcgks_last_error": (C.c_char_p, [_vp]),
     "fdcgks_debug_stage": (C.c_int, [_vp, _i32, C.c_double, _vp, _vp]),

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1397,6 +1398,45 @@ __global__ __launch_bounds__(256) void k_bphase_update(BArgs a, Consts k) {
 }
 __global__ void k_bphase_end(BArgs a, Consts k) { batch_step_end(a, k); }
 
+
+// ------------------------------------------- allocation-free 1D run
+// fdcgks_step1d_static keeps every buffer of a 1D run in one file-scope
+// device array: the four state buffers (12 planes each), the interface
+// buffer (19 planes per line) and the node buffer (6 planes per line) of a
+// problem of at most STATIC1D_MAX_NX nodes per line, then the step scalars.
+// The array is per device and lives until the process ends.
+constexpr int STATIC1D_MAX_NX = 2048;
+constexpr long STATIC1D_PLANE = (long)(((STATIC1D_MAX_NX + 2 * OX) + 15) / 16 * 16) * (1 + 2 * OY);
+constexpr long STATIC1D_PLANES = 4 * 12 + 2 * 19 + 2 * 6;
+constexpr long STATIC1D_DOUBLES = STATIC1D_PLANES * STATIC1D_PLANE + 64;
+static_assert(sizeof(Scal) <= 64 * sizeof(double), "step scalars exceed their slot");
+static __device__ __align__(256) double scratch[STATIC1D_DOUBLES];
+
+// Step scalars of a run: t, t_end and the fixed dt set, everything else zero.
+__global__ void k_static1d_begin(Scal* __restrict__ sc, double t, double t_end, double dt_fixed) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  Scal z = {};
+  z.t = t;
+  z.t_end = t_end;
+  z.dt_fixed = dt_fixed;
+  *sc = z;
+}
+
+// Dense caller state [lines][6][nx] (W[3], Wx[3]) to the padded planes of S0
+// (dir 0), or back from the buffer holding the last completed step (dir 1:
+// S0 after an even number of steps, S1 after an odd one).
+__global__ void k_static1d_io(double* __restrict__ dense, double* __restrict__ S0, const double* __restrict__ S1,
+                              Geo g, int lines, const Scal* __restrict__ sc, int dir) {
+  const long n = (long)lines * 6 * g.nx;
+  const double* src = dir == 1 && (sc->steps & 1) ? S1 : S0;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const long p = t / g.nx;
+    const int i = (int)(t % g.nx);
+    const long o = p * g.plane + at(g, 0, i);
+    if (dir == 0) S0[o] = dense[t];
+    else dense[t] = src[o];
+  }
+}
 }  // namespace
 
 #include "gks_adjoint.hpp"
@@ -1405,7 +1445,9 @@ __global__ void k_bphase_end(BArgs a, Consts k) { batch_step_end(a, k); }
 namespace {
 
 // ================================================================== host
-thread_local std::string g_create_error;
+// errors of calls without a problem handle (create, the allocation-free run):
+// a fixed buffer, so that reporting one allocates nothing
+thread_local char g_create_error[512];
 
 struct Launch {
   dim3 grid, block;
@@ -1464,7 +1506,7 @@ fdcgks_status fail(fdcgks_problem* pb, fdcgks_status st, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  if (pb) pb->err = buf; else g_create_error = buf;
+  if (pb) pb->err = buf; else std::snprintf(g_create_error, sizeof g_create_error, "%s", buf);
   return st;
 }
 #define HIPCHK(pb, call)                                                                     \
@@ -1713,6 +1755,42 @@ float time_tile(fdcgks_problem* pb, int c, dim3 blk, int reps, hipEvent_t e0, hi
 // Boundary of 2D side k (x-low, x-high, y-low, y-high): its own entry, or bc.
 int side_bc(const fdcgks_params& p, int k) { return p.side[k] >= 0 ? p.side[k] : p.bc; }
 
+// Padded-plane geometry and scheme constants of a problem (validated params).
+void setup_geometry(const fdcgks_params& prm, Geo& g, Consts& k) {
+  const fdcgks_params* p = &prm;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.pitch = ((p->nx + 2 * OX) + 15) / 16 * 16;
+  if (p->dim == 2) {
+    for (int q = 0; q < 4; ++q) g.side[q] = side_bc(*p, q);
+    g.sx = g.side[0] != FDCGKS_BC_PERIODIC;
+    g.sy = g.side[2] != FDCGKS_BC_PERIODIC;
+  }
+  g.rows = p->ny + 2 * OY + g.sy;  // a bounded y axis adds the dual boundary row
+  g.dshift = g.sx + (long)g.sy * g.pitch;
+  g.plane = (long)g.pitch * g.rows;
+  g.h = p->lx / p->nx;
+  g.invh = 1.0 / g.h;
+  k.gamma = p->gamma;
+  k.K = p->dim == 2 ? (4.0 - 2.0 * p->gamma) / (p->gamma - 1.0) : (3.0 - p->gamma) / (p->gamma - 1.0);
+  k.inv_Kd = 1.0 / (k.K + (p->dim == 2 ? 2.0 : 1.0));
+  k.mu = p->mu;
+  k.prfix = p->mu > 0 ? 1.0 / p->prandtl - 1.0 : 0.0;
+  k.C = p->geno_C;
+  k.inv_tanhC = 1.0 / std::tanh(p->geno_C);
+  k.eps = p->geno_eps;
+  k.eps_a = p->geno_eps_a;
+  k.dc = p->geno_d_central;
+  k.ds = p->geno_d_side;
+  k.tau_c1 = p->tau_c1;
+  k.tau_c2 = p->tau_c2;
+  k.r = p->geno_r;
+  k.variant = p->flux_variant;
+  k.grad_carried = p->grad_update == FDCGKS_GRAD_CARRIED;
+  k.flux_order = p->flux_order;
+}
+
+
 fdcgks_status check_params(const fdcgks_params* p) {
   if (!p) return fail(nullptr, FDCGKS_EINVAL, "params is NULL");
   if (p->dim != 1 && p->dim != 2) return fail(nullptr, FDCGKS_EINVAL, "dim must be 1 or 2 (got %d)", p->dim);
@@ -1858,38 +1936,8 @@ fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_pro
   fdcgks_problem* pb = new fdcgks_problem();
   pb->prm = *p;
   pb->stream = (hipStream_t)hip_stream;
-  Geo& g = pb->g;
-  g.nx = p->nx;
-  g.ny = p->ny;
-  g.pitch = ((p->nx + 2 * OX) + 15) / 16 * 16;
-  if (p->dim == 2) {
-    for (int k = 0; k < 4; ++k) g.side[k] = side_bc(*p, k);
-    g.sx = g.side[0] != FDCGKS_BC_PERIODIC;
-    g.sy = g.side[2] != FDCGKS_BC_PERIODIC;
-  }
-  g.rows = p->ny + 2 * OY + g.sy;  // a bounded y axis adds the dual boundary row
-  g.dshift = g.sx + (long)g.sy * g.pitch;
-  g.plane = (long)g.pitch * g.rows;
-  g.h = p->lx / p->nx;
-  g.invh = 1.0 / g.h;
-  Consts& k = pb->k;
-  k.gamma = p->gamma;
-  k.K = p->dim == 2 ? (4.0 - 2.0 * p->gamma) / (p->gamma - 1.0) : (3.0 - p->gamma) / (p->gamma - 1.0);
-  k.inv_Kd = 1.0 / (k.K + (p->dim == 2 ? 2.0 : 1.0));
-  k.mu = p->mu;
-  k.prfix = p->mu > 0 ? 1.0 / p->prandtl - 1.0 : 0.0;
-  k.C = p->geno_C;
-  k.inv_tanhC = 1.0 / std::tanh(p->geno_C);
-  k.eps = p->geno_eps;
-  k.eps_a = p->geno_eps_a;
-  k.dc = p->geno_d_central;
-  k.ds = p->geno_d_side;
-  k.tau_c1 = p->tau_c1;
-  k.tau_c2 = p->tau_c2;
-  k.r = p->geno_r;
-  k.variant = p->flux_variant;
-  k.grad_carried = p->grad_update == FDCGKS_GRAD_CARRIED;
-  k.flux_order = p->flux_order;
+  setup_geometry(*p, pb->g, pb->k);
+  const Geo& g = pb->g;
   pb->ngrid = p->dim == 2 ? 2 : (p->dual_1d ? 2 : 1);
   pb->nplanes = (int)state_planes(*p);
   size_t sbytes = (size_t)pb->nplanes * g.plane * sizeof(double);
@@ -2153,6 +2201,93 @@ fdcgks_status fdcgks_step(fdcgks_problem* pb, double dt, double cfl, int32_t nst
   return FDCGKS_OK;
 }
 
+// Device address of `scratch` on each device, looked up once per device with
+// that device current.
+static std::atomic<double*> g_static_ptr[64];
+
+fdcgks_status fdcgks_step1d_static(const fdcgks_params* p, double* state, double dt, double cfl, int32_t nsteps,
+                                   double t_end, double* t_inout, int32_t* steps_done, void* hip_stream) {
+  fdcgks_status st = check_params(p);
+  if (st) return st;
+  if (p->dim != 1) return fail(nullptr, FDCGKS_EINVAL, "the allocation-free run is 1D only");
+  if (p->nx > STATIC1D_MAX_NX)
+    return fail(nullptr, FDCGKS_EINVAL, "the allocation-free run takes at most %d nodes per line (got %d)",
+                STATIC1D_MAX_NX, p->nx);
+  if (!state || !t_inout) return fail(nullptr, FDCGKS_EINVAL, "state and t_inout must not be NULL");
+  if (nsteps < 0) return fail(nullptr, FDCGKS_EINVAL, "nsteps < 0");
+  if (!(dt > 0) && !(cfl > 0)) return fail(nullptr, FDCGKS_EINVAL, "need dt > 0 or cfl > 0");
+  if (!std::isfinite(dt) || !std::isfinite(*t_inout) || !std::isfinite(t_end))
+    return fail(nullptr, FDCGKS_EINVAL, "dt, t and t_end must be finite");
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, state) != hipSuccess || attr.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    return fail(nullptr, FDCGKS_EINVAL, "state must be device memory");
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+    return fail(nullptr, FDCGKS_EHIP, "no usable current device");
+  if (attr.device != dev) return fail(nullptr, FDCGKS_EINVAL, "state lives on device %d, not the current %d",
+                                      attr.device, dev);
+  const int lines = p->dual_1d ? 2 : 1;
+  {
+    // the caller's array must hold lines * 6 * nx doubles inside its allocation
+    hipDeviceptr_t lo = nullptr;
+    size_t len = 0;
+    if (hipMemGetAddressRange(&lo, &len, state) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(nullptr, FDCGKS_EINVAL, "state is not a device allocation");
+    }
+    const char* end = reinterpret_cast<const char*>(state) + (size_t)lines * 6 * p->nx * sizeof(double);
+    if (end > static_cast<const char*>(lo) + len)
+      return fail(nullptr, FDCGKS_EINVAL, "state allocation is smaller than %d x 6 x %d doubles", lines, p->nx);
+  }
+  double* base = g_static_ptr[dev].load();
+  if (!base) {
+    void* a = nullptr;
+    hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !a)
+      return fail(nullptr, FDCGKS_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+    base = static_cast<double*>(a);
+    g_static_ptr[dev].store(base);
+  }
+  Geo g;
+  Consts k;
+  setup_geometry(*p, g, k);
+  const long pl = g.plane;  // <= STATIC1D_PLANE since nx <= STATIC1D_MAX_NX
+  double* S0 = base;
+  double* S1 = base + 12 * pl;
+  double* Sstar = base + 24 * pl;
+  double* Acc = base + 36 * pl;
+  double* E = base + 48 * pl;
+  double* Nb = base + 86 * pl;
+  Scal* sc = reinterpret_cast<Scal*>(base + STATIC1D_PLANES * pl);
+  hipStream_t stream = (hipStream_t)hip_stream;
+  const int use_cfl = dt > 0 ? 0 : 1;
+  const bool f32 = p->flux_precision == FDCGKS_FP32_FLUX;
+  const bool ch = p->recon_vars == FDCGKS_RECON_CHARACTERISTIC;
+  auto fn = f32 ? (ch ? k_run1d<float, true> : k_run1d<float, false>)
+                : (ch ? k_run1d<double, true> : k_run1d<double, false>);
+  const int ioblocks = ceil_div((long)lines * 6 * g.nx, 256);
+  hipLaunchKernelGGL(k_static1d_begin, dim3(1), dim3(64), 0, stream, sc, *t_inout, t_end, dt);
+  hipLaunchKernelGGL(k_static1d_io, dim3(ioblocks), dim3(256), 0, stream, state, S0, S1, g, lines, sc, 0);
+  if (nsteps > 0)
+    hipLaunchKernelGGL(fn, dim3(1), dim3(256), 0, stream, S0, S1, Sstar, Acc, E, Nb, g, k, sc, lines, p->bc, nsteps,
+                       cfl, use_cfl, 0);
+  hipLaunchKernelGGL(k_static1d_io, dim3(ioblocks), dim3(256), 0, stream, state, S0, S1, g, lines, sc, 1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(nullptr, FDCGKS_EHIP, "launch failed: %s", hipGetErrorString(e));
+  Scal h;
+  e = hipMemcpyAsync(&h, sc, sizeof(Scal), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return fail(nullptr, FDCGKS_EHIP, "reading the step scalars: %s", hipGetErrorString(e));
+  *t_inout = h.t;
+  if (steps_done) *steps_done = h.steps;
+  if (h.stop & 1)
+    return fail(nullptr, FDCGKS_ENONPHYS, "non-physical state in step %d stage %d at line %d node %d", h.steps + 1,
+                h.fail_stage, h.fail_grid, h.fail_i);
+  return FDCGKS_OK;
+}
+
 fdcgks_status fdcgks_destroy(fdcgks_problem* pb) {
   if (!pb) return FDCGKS_OK;
   (void)hipStreamSynchronize(pb->stream);
@@ -2181,7 +2316,7 @@ fdcgks_status fdcgks_step_timed(fdcgks_problem* pb, double dt, double cfl, int32
 }
 
 const char* fdcgks_last_error(const fdcgks_problem* pb) {
-  return pb ? pb->err.c_str() : g_create_error.c_str();
+  return pb ? pb->err.c_str() : g_create_error;
 }
 
 fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, double* out_state, double* out_acc) {
@@ -2445,7 +2580,7 @@ fdcgks_status bfail(fdcgks_batch* b, fdcgks_status st, const char* fmt, ...) {
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  if (b) b->err = buf; else g_create_error = buf;
+  if (b) b->err = buf; else std::snprintf(g_create_error, sizeof g_create_error, "%s", buf);
   return st;
 }
 #define BHIPCHK(b, call)                                                                      \
@@ -2482,7 +2617,7 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
   if (count < 1 || !params) return bfail(nullptr, FDCGKS_EINVAL, "need count >= 1 and a params array");
   for (int m = 0; m < count; ++m) {
     fdcgks_status st = check_params(&params[m]);
-    if (st) return bfail(nullptr, st, "member %d: %s", m, g_create_error.c_str());
+    if (st) return bfail(nullptr, st, "member %d: %s", m, std::string(g_create_error).c_str());
     if (params[m].dim != 2) return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches are 2D only", m);
     if (params[m].recon_vars != FDCGKS_RECON_CONSERVATIVE)
       return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches reconstruct conservative variables only", m);
@@ -2758,7 +2893,7 @@ fdcgks_status fdcgks_batch_destroy(fdcgks_batch* b) {
   return FDCGKS_OK;
 }
 
-const char* fdcgks_batch_last_error(const fdcgks_batch* b) { return b ? b->err.c_str() : g_create_error.c_str(); }
+const char* fdcgks_batch_last_error(const fdcgks_batch* b) { return b ? b->err.c_str() : g_create_error; }
 
 fdcgks_status fdcgks_batch_set_mode(fdcgks_batch* b, int32_t mode) {
   if (!b) return bfail(nullptr, FDCGKS_EINVAL, "batch is NULL");
