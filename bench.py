@@ -55,7 +55,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=N)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=1024, help="side of the oracle's timed sample")
+    ap.add_argument("--cpu-n", type=int, default=N, help="side of the oracle's timed workload")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the 1D periodic, 1D shock-tube and 512^2 vortex legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-problem comparison")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward comparison")
@@ -74,32 +76,143 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(n):
-    """The oracle, unmodified, timed on this host: one full S2O4 step of the
-    same workload at n x n (same scheme and per-node work)."""
+def _host_info():
+    """Threads the oracle may use, logical CPUs, and the CPU model of this host."""
     import ctypes
-
-    import numpy as np
-
-    import workloads as WL
-    from oracle import oracle as O
-    pr = WL.shear_layer(n, seed=0, mu=MU, prandtl=PR)
-    par = O.make_par(dim=2, nx=n, ny=n, lx=1.0, mu=MU, prandtl=PR)
-    dt = O.dt2d(par, pr.P, pr.D, CFL)
-    t0 = time.perf_counter()
-    O.step2d(par, pr.P, pr.D, 1, dt=dt)
-    sec = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
     try:
-        lib = ctypes.CDLL(None)
-        f = getattr(lib, "omp_get_max_threads", None)
+        f = getattr(ctypes.CDLL(None), "omp_get_max_threads", None)
         if f:
             threads = int(f())
     except OSError:
         pass
-    return {"value": 2 * n * n * 2 / sec, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"one S2O4 step (2 stages) of the {n}x{n} double shear layer (same parameters and per-node "
-                      f"work as the {N}x{N} workload), {sec:.1f} s"}
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return threads, {"nproc": os.cpu_count(), "affinity_cpus": aff, "cpu_model": model}
+
+
+def cpu_baseline(n):
+    """The oracle, unmodified, timed on this host: stage 1 of one S2O4 step of
+    the n x n workload itself (the full-size state; stage 2 does less work, so
+    the per-stage rate is a bound from below), plus whole runs of the small
+    configurations (1D periodic, 1D shock tubes) and one step of the 512^2
+    vortex."""
+    import workloads as WL
+    from oracle import oracle as O
+    threads, host = _host_info()
+    pr = WL.shear_layer(n, seed=0, mu=MU, prandtl=PR)
+    par = O.make_par(dim=2, nx=n, ny=n, lx=1.0, mu=MU, prandtl=PR)
+    dt = O.dt2d(par, pr.P, pr.D, CFL)
+    t0 = time.perf_counter()
+    O.stage2d(par, 1, dt, pr.P, pr.D)
+    sec = time.perf_counter() - t0
+    del pr
+    out = {"value": 2 * n * n / sec, "unit": "node-updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"stage 1 of one S2O4 step of the {n}x{n} double shear layer (the full-size state, "
+                     f"{2 * n * n} nodes), {sec:.1f} s on {threads} threads", **host}
+    cfg = {}
+    # 1D periodic, N = 100 + shifted copy, to t = 2
+    a = WL.advection1d(100, seed=0)
+    p1 = O.make_par(dim=1, nx=100, lx=2.0, dual_1d=1)
+    t0 = time.perf_counter()
+    _, tt, k = O.step1d(p1, a.S, 100000, cfl=CFL, t_end=2.0)
+    sec = time.perf_counter() - t0
+    cfg["1d_periodic"] = {"steps": k, "t": tt, "seconds": round(sec, 3),
+                          "node_updates_per_s": 2 * 100 * 2 * k / sec}
+    # 1D shock tubes, N = 400, seeds 0..2, to t = 0.2
+    tubes = []
+    for seed in range(3):
+        tb = WL.seeded_shock_tube(400, seed)
+        p2 = O.make_par(dim=1, nx=400, lx=1.0, bc="zero_gradient")
+        t0 = time.perf_counter()
+        _, tt, k = O.step1d(p2, tb.S, 100000, cfl=CFL, t_end=0.2)
+        sec = time.perf_counter() - t0
+        tubes.append({"seed": seed, "steps": k, "seconds": round(sec, 3), "node_updates_per_s": 400 * 2 * k / sec})
+    cfg["1d_shock_tubes"] = tubes
+    # 2D vortex 512^2: one CFL step (a whole 10-step run is ten of these)
+    v = WL.vortex(512, seed=0)
+    p3 = O.make_par(dim=2, nx=512, ny=512, lx=v.lx)
+    t0 = time.perf_counter()
+    O.step2d(p3, v.P, v.D, 1, cfl=CFL)
+    sec = time.perf_counter() - t0
+    cfg["vortex_512"] = {"sample": "one CFL step", "seconds_per_step": round(sec, 3),
+                         "node_updates_per_s": 2 * 512 * 512 * 2 / sec}
+    out["configs"] = cfg
+    return out
+
+
+def config_legs(tiles):
+    """The smaller configurations on the GPU: the 1D periodic run (N = 100 +
+    shifted copy, noise seed 0, CFL 0.5 to t = 2), the seeded 1D shock tubes
+    (N = 400, seeds 0..2, CFL 0.5 to t = 0.2; one launch per run), and the
+    512^2 isentropic vortex (10 CFL steps, FP64 and the FP32-flux variant).
+    Rates are node-updates per second per stage over the whole run, inputs
+    resident on the device, first run untimed."""
+    import torch
+
+    import workloads as WL
+    from paper_2606_17772_amd import Problem, make_params
+    dev = torch.device("cuda:0")
+
+    def run1d(prm, S, t_end):
+        pb = Problem(prm)
+        for g in range(S.shape[0]):
+            pb.set_state_stacked(g, S[g])
+        pb.step(nsteps=100000, cfl=CFL, t_end=t_end)  # warm-up run
+        for g in range(S.shape[0]):
+            pb.set_state_stacked(g, S[g])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tt, k = pb.step(nsteps=100000, cfl=CFL, t_end=t_end)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, tt, k
+
+    out = {}
+    a = WL.advection1d(100, seed=0)
+    sec, tt, k = run1d(make_params(dim=1, nx=100, lx=2.0, dual_1d=1), a.S, 2.0)
+    out["1d_periodic"] = {"workload": "1D Euler, periodic [0,2], N=100 + 100 shifted, noise seed 0, CFL 0.5 to t=2",
+                          "steps": k, "t": tt, "ms": round(sec * 1e3, 3), "node_updates_per_s": 2 * 100 * 2 * k / sec}
+    tubes = []
+    for seed in range(3):
+        tb = WL.seeded_shock_tube(400, seed)
+        sec, tt, k = run1d(make_params(dim=1, nx=400, lx=1.0, bc="zero_gradient"), tb.S, 0.2)
+        tubes.append({"seed": seed, "left": tb.params["left"], "right": tb.params["right"], "steps": k,
+                      "ms": round(sec * 1e3, 3), "node_updates_per_s": 400 * 2 * k / sec})
+    out["1d_shock_tubes"] = {"workload": "1D Euler shock tubes, N=400 on [0,1], seeded states, zero-gradient ends, "
+                                         "CFL 0.5 to t=0.2", "runs": tubes}
+    v = WL.vortex(512, seed=0)
+    S0 = torch.from_numpy(np.stack([v.P, v.D])).to(dev)
+    res = {}
+    for name, kw in (("fp64", {}), ("fp32_flux", {"fp32_flux": True})):
+        pb = Problem(make_params(dim=2, nx=512, ny=512, lx=v.lx, ly=v.ly, **kw))
+        for tname, (x, y) in tiles.items():
+            pb.set_tile(tname, x, y)
+        pb.set_state_all(S0)
+        pb.step(nsteps=10, cfl=CFL)
+        pb.set_state_all(S0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, k = pb.step(nsteps=10, cfl=CFL)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        res[name] = (sec, k, pb.get_state_all(device=dev))
+        del pb
+    (s64, k64, S64), (s32, k32, S32) = res["fp64"], res["fp32_flux"]
+    out["vortex_512"] = {"workload": "2D Euler isentropic vortex, periodic [0,10]^2, 512^2 + dual, beta 5, seed 0, "
+                                     "10 CFL-0.5 steps", "steps": k64, "fp64_ms_per_step": round(s64 / k64 * 1e3, 4),
+                         "fp64_node_updates_per_s": 2 * 512 * 512 * 2 * k64 / s64,
+                         "fp32_flux_ms_per_step": round(s32 / k32 * 1e3, 4),
+                         "fp32_flux_node_updates_per_s": 2 * 512 * 512 * 2 * k32 / s32,
+                         "fp32_flux_max_rel_diff_values_vs_fp64": _max_rel_values(S64, S32)}
+    return out
 
 
 BATCH_CFL = 0.4  # the four-quadrant Riemann members need CFL <= 0.4 (the paper's tests use CFL >= 0.4)
@@ -301,8 +414,8 @@ def adjoint_batch_gradient(count=64):
     seed; the control is an additive density perturbation on the primary
     nodes (gradient = adjoint of the initial primary density).  Rollouts keep
     every 7th state and recompute the rest.  Timed against the plain forward
-    steps of the same members, plus a central-difference check of the
-    gradient of one member along a random direction."""
+    steps of the same members, plus central-difference checks of the
+    gradient of a vortex and a Riemann member along 8 random directions."""
     import torch
 
     import workloads as WL
@@ -314,7 +427,7 @@ def adjoint_batch_gradient(count=64):
     gen = lambda b, n, sd: WL.vortex(n, seed=sd) if b % 2 == 0 else WL.riemann2d(n, seed=sd)  # noqa: E731
     t_fwd = t_grad = 0.0
     J_total, gnorm2, members = 0.0, [0.0, 0.0], 0
-    check = None
+    checks = []
     for b, n in enumerate(sizes):
         pr, tg = gen(b, n, b), gen(b, n, 5000 + b)
         pb = Problem(make_params(dim=2, nx=n, ny=n, lx=pr.lx, ly=pr.ly))
@@ -353,27 +466,57 @@ def adjoint_batch_gradient(count=64):
         J_total += float(J.detach())
         gnorm2[b % 2] += float((grad * grad).sum())
         members += 1
-        if b == 0:  # central differences along a random density direction
-            v = torch.randn(grad.shape, dtype=torch.float64, device=dev,
-                            generator=torch.Generator(device=dev).manual_seed(1))
-            eps = 1e-6 * float(S0[0, 0].abs().max()) / float(v.abs().max())
-
-            def Jof(sign):
-                S = S0.clone()
-                S[0, 0] += sign * eps * v
-                pb.set_state_all(S)
-                pb.step(nsteps=ADJ_STEPS, dt=dt)
-                return 0.5 * float(((pb.get_state_all(device=dev)[0, 0] - rho_t) ** 2).sum()) * h2
-            fd = (Jof(1.0) - Jof(-1.0)) / (2 * eps)
-            an = float((grad * v).sum())
-            check = {"member": 0, "side": n, "directional_derivative_adjoint": an, "central_difference": fd,
-                     "rel_diff": abs(an - fd) / abs(fd)}
+        if b in (0, 1):  # central differences along 8 random density directions (vortex b = 0, Riemann b = 1)
+            checks.append(_fd_directions(pb, S0, dt, rho_t, h2, grad, n, b))
         del pb, X, out, J
     return {"workload": f"{members} members, sides in [64, 512], {ADJ_STEPS} steps at frozen CFL-{ADJ_CFL} dt, "
                         f"checkpoint every {ADJ_EVERY} steps", "skipped_nonphysical_members": skipped,
             "forward_s": round(t_fwd, 3), "gradient_s": round(t_grad, 3), "gradient_over_forward": round(t_grad / t_fwd, 2),
-            "J": J_total, "grad_norm_vortex_members": gnorm2[0] ** 0.5, "grad_norm_riemann_members": gnorm2[1] ** 0.5,
-            "fd_check": check}
+            "J": J_total, "grad_norm_vortex_members": gnorm2[0] ** 0.5, "fd_checks": checks}
+
+
+def _fd_directions(pb, S0, dt, rho_t, h2, grad, n, b, ndir=8):
+    """Adjoint directional derivatives <grad J, v> against central
+    differences of J along `ndir` seeded random density directions v, at
+    eps = 1e-6 and 1e-4 of the density scale.  On Riemann data the central
+    difference itself depends on eps: J of the discrete scheme is not smooth
+    at round-off level there (GENO's path function switches where smoothness
+    indicators are ~0), so the adjoint is the derivative of a branch that a
+    finite step leaves; such members are reported, not asserted."""
+    import torch
+    dev = S0.device
+    gen = torch.Generator(device=dev).manual_seed(100 + b)
+
+    def Jof(v, e):
+        S = S0.clone()
+        S[0, 0] += e * v
+        pb.set_state_all(S)
+        pb.step(nsteps=ADJ_STEPS, dt=dt)
+        return 0.5 * float(((pb.get_state_all(device=dev)[0, 0] - rho_t) ** 2).sum()) * h2
+
+    rel = {"1e-6": [], "1e-4": []}
+    an_all, fd_all = [], []
+    scale = float(S0[0, 0].abs().max())
+    for _ in range(ndir):
+        v = torch.randn(grad.shape, dtype=torch.float64, device=dev, generator=gen)
+        v /= float(v.abs().max())
+        an = float((grad * v).sum())
+        an_all.append(an)
+        for tag, f in (("1e-6", 1e-6), ("1e-4", 1e-4)):
+            e = f * scale
+            fd = (Jof(v, e) - Jof(v, -e)) / (2 * e)
+            if tag == "1e-6":
+                fd_all.append(fd)
+            rel[tag].append(abs(an - fd) / max(abs(fd), 1e-300))
+    kind = "vortex" if b % 2 == 0 else "riemann"
+    worst = max(abs(a - f) for a, f in zip(an_all, fd_all)) / max(abs(f) for f in fd_all)
+    out = {"member": b, "kind": kind, "side": n, "directions": ndir, "adjoint": an_all, "central_difference_1e-6": fd_all,
+           "max_abs_diff_over_max_abs_fd_1e-6": worst,
+           "max_rel_diff_eps_1e-6": max(rel["1e-6"]), "max_rel_diff_eps_1e-4": max(rel["1e-4"])}
+    if kind == "riemann":
+        out["note"] = ("J is not smooth at round-off level on piecewise-constant data (GENO path functions switch where "
+                       "smoothness indicators vanish): compare the spread between the two eps")
+    return out
 
 
 def graph_comparison(n=64, steps=400):
@@ -547,6 +690,8 @@ def main():
         out["bounded"] = bounded_comparison(n, tiles)
     if not args.no_graph:
         out["graph_replay"] = graph_comparison()
+    if not args.no_configs:
+        out["configs"] = config_legs(tiles)
     if not args.no_batch:
         del pb
         torch.cuda.empty_cache()
