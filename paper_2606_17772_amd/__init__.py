@@ -323,6 +323,28 @@ class Problem:
     def fuse_nodes(self, on):
         self._chk(self._L.fdcgks_set_option(self._h, _lib.OPT_FUSE_NODES, 1 if on else 0))
 
+    @property
+    def fuse_stage(self):
+        """Interface sweep and update in one marching kernel (2D steps)."""
+        v = C.c_int64()
+        self._chk(self._L.fdcgks_get_option(self._h, _lib.OPT_FUSE_STAGE, C.byref(v)))
+        return bool(v.value)
+
+    @fuse_stage.setter
+    def fuse_stage(self, on):
+        self._chk(self._L.fdcgks_set_option(self._h, _lib.OPT_FUSE_STAGE, 1 if on else 0))
+
+    @property
+    def fused_rows(self):
+        """Node rows per block of the fused stage kernel (0: automatic)."""
+        v = C.c_int64()
+        self._chk(self._L.fdcgks_get_option(self._h, _lib.OPT_FUSED_ROWS, C.byref(v)))
+        return v.value
+
+    @fused_rows.setter
+    def fused_rows(self, rows):
+        self._chk(self._L.fdcgks_set_option(self._h, _lib.OPT_FUSED_ROWS, int(rows)))
+
     def tiles(self):
         """Block shapes {"edge": (x, y), "node": ..., "update": ...}."""
         out = {}

@@ -722,6 +722,338 @@ __global__ __launch_bounds__(256, (STAGE == 2 ? 5 : 4) - (WIDE ? 1 : 0)) void k_
   if (fold) cfl_fold(part, nparts, s, r);
 }
 
+
+// ------------------------------------ interface sweep fused with the update
+// Periodic problems with the order-6 flux.  A block of 64 x 4 threads owns a
+// strip of FS_W node columns [i0, i0 + FS_W) of both grids and a chunk of
+// node rows [jlo, jhi), and marches up the rows.  Row step J evaluates the
+// interface points of row J with the interface sweep's own code
+// (reconstruction, solver, blend; thread row ty = 2 * family + normal):
+//   ty 0: X(i0 - 2 + lane, J), primary-line normal: x-fluxes of primary nodes
+//   ty 1: X(i0 - 2 + lane, J), dual-line normal:    y-fluxes of dual nodes
+//   ty 2: Y(i0 - 1 + lane, J), primary-line normal: y-fluxes of primary nodes
+//   ty 3: Y(i0 - 1 + lane, J), dual-line normal:    x-fluxes of dual nodes
+// and then, without an interface buffer:
+//   ty 0: x-flux difference and x-gradients of primary row J (neighbouring
+//         interfaces by lane shuffles); the flux difference waits a step in LDS;
+//   ty 3: the same for dual row J (it waits two steps);
+//   ty 2: y-flux of primary row J-1 from the column's last three Y rows (an
+//         LDS ring private to the lane), y-gradients of primary row J, and the
+//         S2O4 update of primary row J-1;
+//   ty 1: y-flux of dual row J-2 from the last three X rows, y-gradients of
+//         dual row J-1, and the S2O4 update of dual row J-2.
+// Nodal fluxes come from the node buffer (the node sweep runs first).  Every
+// value is formed by the same expressions as in the separate interface sweep
+// and update, so the results are bitwise those of the separate kernels.
+constexpr int FS_W = 61;
+
+template <int STAGE>
+struct FusedLds {
+  static constexpr int NV = STAGE == 1 ? 8 : 4;  // F[4], Ft[4] (stage 2: Ft[4]); also L[4], Lt[4] (Lt[4])
+  static constexpr int NX = STAGE == 1 ? 12 : 8;  // exchange slots per thread
+  // per lane: two rows of fluxes, the last path function, the last W-tilde-r
+  // (and _t), the last compact flux (and _t)
+  static constexpr int RS = 2 * NV + 1 + NV + NV;
+  static constexpr int CHI = 2 * NV, WR = 2 * NV + 1, FB = 3 * NV + 1;
+  double xch[NX * 256];
+  double ring[2][RS * 64];     // [0]: ty 2 (Y rows), [1]: ty 1 (X rows); field-major, lane fastest
+  double partP[2][NV * 64];    // x-flux differences of primary rows J, J-1
+  double partD[3][NV * 64];    // of dual rows J, J-1, J-2
+};
+
+// One interface point (both normals of the point are the partner rows ty,
+// ty ^ 1 of the block), values kept in registers: fluxes, the path function
+// of the density (or acoustic) line and the blended interface values.
+struct IfaceVals {
+  double F[4], Ft[4], chi, Wl[4], Wr[4], Wlt[4], Wrt[4];
+};
+template <int STAGE, class FT, bool CHAR>
+__device__ __forceinline__ void fused_iface(const double* __restrict__ S, const Geo& g, const Consts& k, double dt,
+                                            int i, int j, int fam, bool valid, double* xch, IfaceVals& o) {
+  const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
+  constexpr int TX = 64, TY = 4;
+#define XCH(c, r) xch[((c) * TY + (r)) * TX + tx]
+  fdk::IfaceRec rec[4];
+  if (valid) {
+    edge_recon<CHAR>(S, g, k, i, j, fam, G, rec);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
+  }
+  o.chi = fmin(rec[0].cl, rec[0].cr);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) XCH(c, ty) = 0.5 * (rec[c].dl + rec[c].dr);
+  __syncthreads();
+  double tang[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) tang[c] = XCH(c, ty ^ 1);
+  double Wl[4] = {0, 0, 0, 0}, Wr[4] = {0, 0, 0, 0}, Wlt[4] = {0, 0, 0, 0}, Wrt[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) { o.F[c] = 0.0; o.Ft[c] = 0.0; }
+  if (valid) solve_dir<STAGE, FT>(k, (FT)dt, fam != G, rec, tang, o.F, o.Ft, Wl, Wr, Wlt, Wrt);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    XCH(4 + c, ty) = Wlt[c] + Wrt[c];
+    if (STAGE == 1) XCH(8 + c, ty) = Wl[c] + Wr[c];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const double st = XCH(4 + c, ty ^ 1);
+    o.Wlt[c] = 0.5 * Wlt[c] + 0.25 * st;
+    o.Wrt[c] = 0.5 * Wrt[c] + 0.25 * st;
+    if (STAGE == 1) {
+      const double sv = XCH(8 + c, ty ^ 1);
+      o.Wl[c] = 0.5 * Wl[c] + 0.25 * sv;
+      o.Wr[c] = 0.5 * Wr[c] + 0.25 * sv;
+    } else {
+      o.Wl[c] = o.Wr[c] = 0.0;
+    }
+  }
+#undef XCH
+}
+
+// S2O4 update of node (i, j) of `grid` from its complete L (and Lt) per
+// component (the gradients are written by the caller), with the
+// non-physical check and the CFL contribution of update_node.
+template <int STAGE>
+__device__ __forceinline__ void fused_node_update(const double* __restrict__ S, const double* __restrict__ Ain,
+                                                  double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
+                                                  const Consts& k, double dt, int i, int j, int grid,
+                                                  const double (&L)[4], const double (&Lt)[4], Scal* sc,
+                                                  bool want_cfl, double& cfl_s, double& cfl_r) {
+  const long pl = g.plane, o = at(g, j, i);
+  const double* s = S + (long)grid * 12 * pl + o;
+  double* out = Out + (long)grid * 12 * pl + o;
+  double rho = 0.0, mom2 = 0.0, ener = 0.0, mU = 0.0, mV = 0.0;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double W;
+    if (STAGE == 1) {
+      double* ao = Aout + (long)grid * 12 * pl + o;
+      const double w = s[c * pl];
+      W = w + 0.5 * dt * L[c] + 0.125 * dt * dt * Lt[c];
+      __builtin_nontemporal_store((double)(w + dt * L[c] + dt * dt / 6.0 * Lt[c]), &ao[c * pl]);
+    } else {
+      const double* ai = Ain + (long)grid * 12 * pl + o;
+      W = ai[c * pl] + dt * dt / 3.0 * Lt[c];
+    }
+    __builtin_nontemporal_store((double)(W), &out[c * pl]);
+    if (c == 0) rho = W;
+    else if (c == 3) ener = W;
+    else {
+      mom2 = mom2 + W * W;
+      if (c == 1) mU = W;
+      else mV = W;
+    }
+  }
+  if (want_cfl) {
+    const double U = mU / rho, V = mV / rho;
+    const double pc = (k.gamma - 1.0) * (ener - 0.5 * rho * (U * U + V * V));
+    const double c = sqrt(k.gamma * pc / rho);
+    cfl_s = fmax(cfl_s, fmax(0.0, fmax(fabs(U), fabs(V)) + c));
+    cfl_r = fmin(cfl_r, rho > 0.0 ? rho : 1e300);
+  }
+  double p = (k.gamma - 1.0) * (ener - 0.5 * mom2 / rho);
+  if (!(rho > 0.0) || !(p > 0.0)) {
+    if (atomicCAS(&sc->stop, 0, 1) == 0) {
+      sc->fail_grid = grid;
+      sc->fail_i = i;
+      sc->fail_j = j;
+      sc->fail_stage = STAGE;
+    }
+  }
+}
+
+// Gradients of node (i, j) of `grid` along axis a from the Gauss differences
+// Gr (stage 1) and Grt, written to Out (and the stage-1 accumulators).
+template <int STAGE>
+__device__ __forceinline__ void fused_grad(const double* __restrict__ S, const double* __restrict__ Ain,
+                                           double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
+                                           const Consts& k, double dt, int i, int j, int grid, int a,
+                                           const double (&Gr)[4], const double (&Grt)[4]) {
+  const long pl = g.plane, o = at(g, j, i);
+  const int f = 4 + 4 * a;  // field of the derivative along axis a
+  double* out = Out + (long)grid * 12 * pl + o;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    double GA;
+    if (STAGE == 1) {
+      const double* s = S + (long)grid * 12 * pl + o;
+      double* ao = Aout + (long)grid * 12 * pl + o;
+      const double gx = k.grad_carried ? s[(f + c) * pl] : Gr[c];
+      GA = gx + 0.5 * dt * Grt[c];
+      __builtin_nontemporal_store((double)(gx), &ao[(f + c) * pl]);
+    } else {
+      const double* ai = Ain + (long)grid * 12 * pl + o;
+      GA = ai[(f + c) * pl] + dt * Grt[c];
+    }
+    __builtin_nontemporal_store((double)(GA), &out[(f + c) * pl]);
+  }
+}
+
+template <int STAGE, class FT, bool CHAR>
+__global__ __launch_bounds__(256, 2) void k_fused2d(const double* __restrict__ S, const double* __restrict__ Nb,
+                                                    const double* __restrict__ Ain, double* __restrict__ Out,
+                                                    double* __restrict__ Aout, Geo g, Consts k,
+                                                    Scal* __restrict__ sc, double* __restrict__ part, int nparts,
+                                                    int nstrips, int nchunks, int rows) {
+  if (sc->stop) return;  // grid-uniform
+  int t;
+  if (!xcd_tile(blockIdx.x, gridDim.x, nstrips * nchunks, t)) return;  // block-uniform
+  using LD = FusedLds<STAGE>;
+  constexpr int NV = LD::NV;
+  __shared__ LD lds;
+  const int strip = t / nchunks, chunk = t % nchunks;
+  const int i0 = strip * FS_W;
+  const int jlo = chunk * rows, jhi = min(g.ny, jlo + rows);
+  const int lane = threadIdx.x, ty = threadIdx.y, fam = ty >> 1;
+  const int i = fam == 0 ? i0 - 2 + lane : i0 - 1 + lane;  // the lane's interface column
+  const double dt = sc->dt;
+  const long pl = g.plane;
+  const bool fold = STAGE == 2 && part != nullptr;
+  double cfl_s = 0.0, cfl_r = 1e300;
+  for (int J = jlo - 2; J <= jhi + 1; ++J) {
+    // X rows jlo-1 .. jhi+1, Y rows jlo-2 .. jhi (block-uniform per wave pair)
+    const bool row_ok = fam == 0 ? J >= jlo - 1 : J <= jhi;
+    const bool valid = row_ok && i <= (fam == 0 ? g.nx : g.nx + 1);
+    IfaceVals v;
+    fused_iface<STAGE, FT, CHAR>(S, g, k, dt, i, J, fam, valid, lds.xch, v);
+    if (ty == 0 || ty == 3) {
+      // x-flux differences and x-gradients of row J: primary (ty 0, nodes
+      // i = i0 - 2 + lane, lanes 2..62) or dual (ty 3, nodes i = i0 - 1 + lane,
+      // lanes 1..61)
+      const bool dual = ty == 3;
+      const int off = dual ? 1 : 2;
+      const int node = i0 + lane - off;  // the node this lane updates
+      const bool doit = J >= jlo && J < jhi;  // wave-uniform
+      if (doit) {
+        // compact flux at this lane's interface m: primary F~(X m) uses nodal
+        // fluxes at P(m), P(m + 1); dual F~(Y m) at D(m - 1), D(m)
+        const int m = i;
+        const bool need = lane >= 1 && lane <= 62 && (dual ? m <= g.nx : m <= g.nx - 1);
+        const double* nb = Nb + (dual ? 16 * pl : 0) + at(g, J, dual ? m - 1 : m);
+        double Fb[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const int qq = STAGE == 1 ? q : 4 + q;  // plane of F (q < 4) or Ft
+          const int c = qq & 3;
+          const double f0 = qq < 4 ? v.F[c] : v.Ft[c];
+          const double fm = __shfl_up(f0, 1), fp = __shfl_down(f0, 1);
+          Fb[q] = need ? fdk::compact_flux(k.variant, fm, f0, fp, nb[qq * pl], nb[qq * pl + 1], v.chi) : 0.0;
+        }
+        double Lx[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          // primary node: FR = F~(lane), FL = F~(lane - 1); dual: FR = F~(lane + 1), FL = F~(lane)
+          const double FR = dual ? __shfl_down(Fb[q], 1) : Fb[q];
+          const double FL = dual ? Fb[q] : __shfl_up(Fb[q], 1);
+          double Lq = 0.0;
+          Lq = Lq - (FR - FL) * g.invh;
+          Lx[q] = Lq;
+        }
+        double Gr[4], Grt[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          // primary: W~l(X node) - W~r(X node - 1); dual: W~l(Y node + 1) - W~r(Y node)
+          const double wlt = dual ? __shfl_down(v.Wlt[c], 1) : v.Wlt[c];
+          const double wrt = dual ? v.Wrt[c] : __shfl_up(v.Wrt[c], 1);
+          Grt[c] = (wlt - wrt) * g.invh;
+          if (STAGE == 1) {
+            const double wl = dual ? __shfl_down(v.Wl[c], 1) : v.Wl[c];
+            const double wr = dual ? v.Wr[c] : __shfl_up(v.Wr[c], 1);
+            Gr[c] = (wl - wr) * g.invh;
+          } else {
+            Gr[c] = 0.0;
+          }
+        }
+        if (lane >= off && lane < off + FS_W && node < g.nx) {
+          double* pp = dual ? lds.partD[J % 3] : lds.partP[J & 1];
+#pragma unroll
+          for (int q = 0; q < NV; ++q) pp[q * 64 + (node - i0)] = Lx[q];
+          fused_grad<STAGE>(S, Ain, Out, Aout, g, k, dt, node, J, dual ? 1 : 0, 0, Gr, Grt);
+        }
+      }
+    } else {
+      // y-direction: primary column (ty 2, i = i0 - 1 + lane, lanes 1..61) or
+      // dual column (ty 1, i = i0 - 2 + lane, lanes 2..62); the ring holds the
+      // last two rows of this column's interfaces
+      const bool dual = ty == 1;
+      const int off = dual ? 2 : 1;
+      const bool col = lane >= off && lane < off + FS_W && i < g.nx;
+      double* rg = lds.ring[dual ? 1 : 0];
+#define RING(f) rg[(f) * 64 + lane]
+      // compact flux at row J - 1 of this column: primary F~(Y J-1) between
+      // P(J-1), P(J); dual F~(X J-1) between D(J-2), D(J-1)
+      const bool flux = dual ? (J >= jlo + 1 && J <= jhi + 1) : (J >= jlo && J <= jhi);
+      if (flux && col) {
+        const int r0 = dual ? J - 2 : J - 1;  // lower node row of the flux
+        const double* nb = Nb + (dual ? 16 * pl : 0) + at(g, r0, i);
+        double Fb[NV];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const int qq = STAGE == 1 ? q : 4 + q;
+          const int c = qq & 3;
+          const double f2 = qq < 4 ? v.F[c] : v.Ft[c];
+          const double f0 = RING((J & 1) * NV + q), f1 = RING(((J - 1) & 1) * NV + q);
+          Fb[q] = fdk::compact_flux(k.variant, f0, f1, f2, nb[(8 + qq) * pl], nb[(8 + qq) * pl + g.pitch],
+                                    RING(LD::CHI));
+        }
+        const int ru = dual ? J - 2 : J - 1;  // the row updated now
+        if (ru >= jlo) {
+          const double* pp = dual ? lds.partD[ru % 3] : lds.partP[ru & 1];
+          double L[4] = {0, 0, 0, 0}, Lt[4];
+#pragma unroll
+          for (int q = 0; q < NV; ++q) {
+            double Lq = pp[q * 64 + (i - i0)];
+            Lq = Lq - (Fb[q] - RING(LD::FB + q)) * g.invh;
+            if (STAGE == 1) {
+              if (q < 4) L[q] = Lq;
+              else Lt[q - 4] = Lq;
+            } else {
+              Lt[q] = Lq;
+            }
+          }
+          fused_node_update<STAGE>(S, Ain, Out, Aout, g, k, dt, i, ru, dual ? 1 : 0, L, Lt, sc, fold, cfl_s, cfl_r);
+        }
+#pragma unroll
+        for (int q = 0; q < NV; ++q) RING(LD::FB + q) = Fb[q];
+      }
+      // y-gradients of primary row J (W~l(Y J) - W~r(Y J-1)) or dual row J-1
+      // (W~l(X J) - W~r(X J-1))
+      const int rg_row = dual ? J - 1 : J;
+      if (rg_row >= jlo && rg_row < jhi && col) {
+        double Gr[4], Grt[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          Grt[c] = (v.Wlt[c] - RING(LD::WR + (STAGE == 1 ? 4 : 0) + c)) * g.invh;
+          Gr[c] = STAGE == 1 ? (v.Wl[c] - RING(LD::WR + c)) * g.invh : 0.0;
+        }
+        fused_grad<STAGE>(S, Ain, Out, Aout, g, k, dt, i, rg_row, dual ? 1 : 0, 1, Gr, Grt);
+      }
+      if (valid && col) {
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const int qq = STAGE == 1 ? q : 4 + q;
+          RING((J & 1) * NV + q) = qq < 4 ? v.F[qq & 3] : v.Ft[qq & 3];
+        }
+        RING(LD::CHI) = v.chi;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          if (STAGE == 1) {
+            RING(LD::WR + c) = v.Wr[c];
+            RING(LD::WR + 4 + c) = v.Wrt[c];
+          } else {
+            RING(LD::WR + c) = v.Wrt[c];
+          }
+        }
+      }
+#undef RING
+    }
+  }
+  if (fold) cfl_fold(part, nparts, cfl_s, cfl_r);
+}
+
 // ================================================================== 1D
 // A 1D problem is one line (grid 0) or two independent lines (grid 1 = the
 // copy on nodes shifted by h/2).  Planes have one interior row (j = 0):
@@ -1485,6 +1817,9 @@ struct fdcgks_problem {
   // captured whole steps (one graph per ping-pong parity), replayed by fdcgks_step
   int graph_steps = 16;  // steps per captured graph; 0: separate launches
   bool fuse_nodes = false;  // node sweep inside the update kernel
+  bool fuse_stage = false;  // interface sweep and update in one marching kernel (k_fused2d)
+  int fused_rows = 0;       // node rows per block of k_fused2d (0: from the CU count)
+  int ncu = 256;            // compute units of the device
   bool cfl_fold = false;    // the stage-2 update being launched folds the CFL partials
   hipStream_t cap = nullptr;
   hipGraphExec_t gx[2] = {nullptr, nullptr};
@@ -1602,18 +1937,59 @@ void launch_update(fdcgks_problem* pb, const double* Sin, const double* Ain, dou
                      pb->nparts);
 }
 
-// One stage.  fused: the node sweep runs inside the update kernel and the
-// node buffer is not written (callers that read it pass false); periodic
-// problems only (bounded axes take the separate kernels).
+// Launch of the fused interface sweep + update (k_fused2d): strips of FS_W
+// node columns, each cut into chunks of rows so that about two blocks per CU
+// run at once.
+template <int STAGE>
+void launch_fused(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout) {
+  const Geo& g = pb->g;
+  const int nstrips = ceil_div(g.nx, FS_W);
+  int rows = pb->fused_rows;
+  if (rows <= 0) {
+    const int nch = std::max(1, 2 * pb->ncu / nstrips);
+    rows = std::max(16, ceil_div(g.ny, nch));
+  }
+  rows = std::min(rows, g.ny);
+  const int nchunks = ceil_div(g.ny, rows);
+  const int nblk = nstrips * nchunks;
+  const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
+  const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
+  auto fn = f32 ? (ch ? k_fused2d<STAGE, float, true> : k_fused2d<STAGE, float, false>)
+                : (ch ? k_fused2d<STAGE, double, true> : k_fused2d<STAGE, double, false>);
+  double* fold = STAGE == 2 && pb->cfl_fold ? pb->part : nullptr;
+  hipLaunchKernelGGL(fn, dim3(ceil_div(nblk, NXCD) * NXCD), dim3(64, 4), 0, pb->stream, Sin, pb->Nb, Ain, Out, Aout,
+                     g, pb->k, pb->sc, fold, pb->nparts, nstrips, nchunks, rows);
+}
+
+// How a stage is launched: 0 separate interface sweep, node sweep and
+// update; 1 the node sweep inside the update kernel; 2 the interface sweep
+// fused with the update after the node sweep.  Both fusions need periodic
+// axes and the order-6 flux; otherwise the separate kernels run.
+enum { STAGE_SEPARATE = 0, STAGE_FUSE_NODES = 1, STAGE_FUSE_IFACE = 2 };
+int stage_mode(const fdcgks_problem* pb) {
+  if ((pb->g.sx | pb->g.sy) || pb->k.flux_order == 8 || pb->prm.dim != 2) return STAGE_SEPARATE;
+  if (pb->fuse_stage) return STAGE_FUSE_IFACE;
+  return pb->fuse_nodes ? STAGE_FUSE_NODES : STAGE_SEPARATE;
+}
+
+// One stage in launch mode `mode` (stage_mode; callers that read the
+// interface or node buffers afterwards pass STAGE_SEPARATE).
 template <int STAGE>
 fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, double* Out, double* Aout,
-                      bool fused) {
+                      int mode) {
   const Geo& g = pb->g;
   fdcgks_status st = halo2d(pb, const_cast<double*>(Sin));
   if (st) return st;
+  if (mode == STAGE_FUSE_IFACE) {
+    launch_nodes<STAGE>(pb, Sin, pb->tile[1]);
+    mark(pb, STAGE == 1 ? TK_NODE1 : TK_NODE2);
+    launch_fused<STAGE>(pb, Sin, Ain, Out, Aout);
+    mark(pb, STAGE == 1 ? TK_UPD1 : TK_UPD2);
+    return launch_check(pb, "stage");
+  }
   launch_edges<STAGE>(pb, Sin, pb->tile[0]);
   mark(pb, STAGE == 1 ? TK_EDGE1 : TK_EDGE2);
-  if (fused && !(g.sx | g.sy) && pb->k.flux_order != 8) {
+  if (mode == STAGE_FUSE_NODES) {
     dim3 gu(ceil_div(g.nx, 64), ceil_div(g.ny, 4), 2);
     const bool f32 = pb->prm.flux_precision == FDCGKS_FP32_FLUX;
     const bool ch = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
@@ -1632,7 +2008,9 @@ fdcgks_status stage2d(fdcgks_problem* pb, const double* Sin, const double* Ain, 
 
 // Whether a CFL step's stage-2 update folds the partials for the next step:
 // 2D steps with the separate node sweep (the fused node kernel does not fold).
-bool fold_ok(const fdcgks_problem* pb, double dt) { return !(dt > 0) && !pb->fuse_nodes && pb->prm.dim == 2; }
+bool fold_ok(const fdcgks_problem* pb, double dt) {
+  return !(dt > 0) && pb->prm.dim == 2 && stage_mode(pb) != STAGE_FUSE_NODES;
+}
 
 // fresh: reduce the CFL partials from the state (the first step of a call or
 // graph); otherwise the previous step's stage-2 update folded them.
@@ -1695,9 +2073,9 @@ fdcgks_status capture_steps(fdcgks_problem* pb, double dt, double cfl) {
     for (int q = 0, cc = c; q < pb->graph_steps && !st; ++q, cc = 1 - cc) {
       pb->cur = cc;
       st = begin_step(pb, dt, cfl, q == 0 || !fold_ok(pb, dt));
-      if (!st) st = stage2d<1>(pb, pb->S[cc], nullptr, pb->Sstar, pb->Acc, pb->fuse_nodes);
+      if (!st) st = stage2d<1>(pb, pb->S[cc], nullptr, pb->Sstar, pb->Acc, stage_mode(pb));
       pb->cfl_fold = fold_ok(pb, dt);
-      if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cc], nullptr, pb->fuse_nodes);
+      if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cc], nullptr, stage_mode(pb));
       pb->cfl_fold = false;
       if (!st) {
         hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, pb->stream, pb->sc);
@@ -1940,6 +2318,12 @@ fdcgks_status fdcgks_create(const fdcgks_params* p, void* hip_stream, fdcgks_pro
   const Geo& g = pb->g;
   pb->ngrid = p->dim == 2 ? 2 : (p->dual_1d ? 2 : 1);
   pb->nplanes = (int)state_planes(*p);
+  {
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+      pb->ncu = cu;
+  }
   size_t sbytes = (size_t)pb->nplanes * g.plane * sizeof(double);
   size_t ebytes = (size_t)100 * g.plane * sizeof(double);
   size_t nbytes = (size_t)32 * g.plane * sizeof(double);
@@ -2179,9 +2563,9 @@ fdcgks_status fdcgks_step(fdcgks_problem* pb, double dt, double cfl, int32_t nst
     pb->cur = cur;
     st = begin_step(pb, dt, cfl, s == 0 || !fold_ok(pb, dt));
     mark(pb, TK_STEP);
-    if (!st) st = stage2d<1>(pb, pb->S[cur], nullptr, pb->Sstar, pb->Acc, pb->fuse_nodes);
+    if (!st) st = stage2d<1>(pb, pb->S[cur], nullptr, pb->Sstar, pb->Acc, stage_mode(pb));
     pb->cfl_fold = fold_ok(pb, dt);
-    if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cur], nullptr, pb->fuse_nodes);
+    if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, pb->S[1 - cur], nullptr, stage_mode(pb));
     pb->cfl_fold = false;
     if (st) break;
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(1), 0, pb->stream, pb->sc);
@@ -2330,8 +2714,8 @@ fdcgks_status fdcgks_debug_stage(fdcgks_problem* pb, int32_t stage, double dt, d
   double* scratch = pb->S[1 - pb->cur];  // the next-state buffer is free between steps
   if (!st) {
     if (pb->prm.dim == 1) st = launch_run1d(pb, stage, 0, dt, 0.0);
-    else if (stage == 1) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, pb->fuse_nodes);
-    else st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr, pb->fuse_nodes);
+    else if (stage == 1) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, stage_mode(pb));
+    else st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr, stage_mode(pb));
   }
   if (st) return st;
   const Geo& g = pb->g;
@@ -2363,7 +2747,7 @@ fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* 
   std::memset(pb->sc_host, 0, sizeof(Scal));
   pb->sc_host->dt = dt;
   fdcgks_status st = write_scal(pb);
-  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, false);
+  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, STAGE_SEPARATE);
   if (st) return st;
   const Geo& g = pb->g;
   size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
@@ -2425,10 +2809,10 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   double* scratch = pb->S[1 - pb->cur];
   pb->E = pb->E1;
   pb->Nb = pb->Nb1;
-  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, false);
+  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, STAGE_SEPARATE);
   pb->E = E0;
   pb->Nb = N0;
-  if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr, false);
+  if (!st) st = stage2d<2>(pb, pb->Sstar, pb->Acc, scratch, nullptr, STAGE_SEPARATE);
   if (!st) st = read_scal(pb);
   if (st) return st;
   if (pb->sc_host->stop & 1)
@@ -2464,6 +2848,16 @@ fdcgks_status fdcgks_set_option(fdcgks_problem* pb, int32_t option, int64_t valu
       pb->fuse_nodes = value != 0;
       graph_invalidate(pb);
       return FDCGKS_OK;
+    case FDCGKS_OPT_FUSE_STAGE:
+      if (value != 0 && value != 1) return fail(pb, FDCGKS_EINVAL, "stage-fusion option must be 0 or 1");
+      pb->fuse_stage = value != 0;
+      graph_invalidate(pb);
+      return FDCGKS_OK;
+    case FDCGKS_OPT_FUSED_ROWS:
+      if (value < 0 || value > (1 << 20)) return fail(pb, FDCGKS_EINVAL, "rows per fused block must be >= 0");
+      pb->fused_rows = (int)value;
+      graph_invalidate(pb);
+      return FDCGKS_OK;
     case FDCGKS_OPT_TILE_EDGE:
     case FDCGKS_OPT_TILE_NODE:
     case FDCGKS_OPT_TILE_UPDATE: {
@@ -2491,6 +2885,14 @@ fdcgks_status fdcgks_get_option(const fdcgks_problem* cpb, int32_t option, int64
     *value = pb->fuse_nodes ? 1 : 0;
     return FDCGKS_OK;
   }
+  if (option == FDCGKS_OPT_FUSE_STAGE) {
+    *value = pb->fuse_stage ? 1 : 0;
+    return FDCGKS_OK;
+  }
+  if (option == FDCGKS_OPT_FUSED_ROWS) {
+    *value = pb->fused_rows;
+    return FDCGKS_OK;
+  }
   if (option >= FDCGKS_OPT_TILE_EDGE && option <= FDCGKS_OPT_TILE_UPDATE) {
     const dim3 t = pb->tile[option - FDCGKS_OPT_TILE_EDGE];
     *value = (int64_t)t.x | ((int64_t)t.y << 16);
@@ -2511,7 +2913,7 @@ fdcgks_status fdcgks_autotune(fdcgks_problem* pb, int32_t reps) {
   std::memset(pb->sc_host, 0, sizeof(Scal));
   pb->sc_host->dt = dt;
   st = write_scal(pb);
-  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, false);
+  if (!st) st = stage2d<1>(pb, pb->S[pb->cur], nullptr, pb->Sstar, pb->Acc, STAGE_SEPARATE);
   if (st) return st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(pb, hipEventCreate(&e0));
