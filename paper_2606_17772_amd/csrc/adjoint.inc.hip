@@ -215,109 +215,99 @@ __device__ __forceinline__ void line_adjoint(const double* __restrict__ S, doubl
   }
 }
 
-// Adjoint of one gas-kinetic interface solve: lam of the outputs (global
-// component order) -> lam of the inputs in the local frame: lin[0..3] WL,
-// [4..7] WR, [8..11] nL, [12..15] nR, [16..19] Wt.  swap (normal along y) is
-// applied to the data, so one copy of the solver adjoint serves both normals.
-template <int STAGE>
-__device__ __forceinline__ void solve_adjoint(const Consts& k, double dt, bool swap, const fdk::IfaceRec (&rn)[4],
-                                              const double (&tang)[4], const double (&lF)[4], const double (&lFt)[4],
-                                              const double (&lWl)[4], const double (&lWr)[4],
-                                              const double (&lWlt)[4], const double (&lWrt)[4], double (&lin)[20]) {
-  fdk::GksIO<double, 2> in, ob, inb;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
-    const bool sw = swap && q0 != c;  // global component of local slot c is q0 when swapped
-    in.WL[c] = sw ? rn[q0].vl : rn[c].vl;
-    in.WR[c] = sw ? rn[q0].vr : rn[c].vr;
-    in.nL[c] = sw ? rn[q0].dl : rn[c].dl;
-    in.nR[c] = sw ? rn[q0].dr : rn[c].dr;
-    in.Wt[c] = sw ? tang[q0] : tang[c];
-    ob.Ft[c] = sw ? lFt[q0] : lFt[c];
-    ob.Wlt[c] = sw ? lWlt[q0] : lWlt[c];
-    ob.Wrt[c] = sw ? lWrt[q0] : lWrt[c];
-    ob.F[c] = STAGE == 1 ? (sw ? lF[q0] : lF[c]) : 0.0;
-    ob.Wl[c] = STAGE == 1 ? (sw ? lWl[q0] : lWl[c]) : 0.0;
-    ob.Wr[c] = STAGE == 1 ? (sw ? lWr[q0] : lWr[c]) : 0.0;
-    inb.WL[c] = inb.WR[c] = inb.nL[c] = inb.nR[c] = inb.Wt[c] = 0.0;
-  }
-  fdk::gks_iface_b(k, dt, in, ob, inb);
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    lin[c] = inb.WL[c];
-    lin[4 + c] = inb.WR[c];
-    lin[8 + c] = inb.nL[c];
-    lin[12 + c] = inb.nR[c];
-    lin[16 + c] = inb.Wt[c];
-  }
-}
-
 // Reverse of the interface sweep: same thread layout as the forward sweep
-// (two threads per point, partners in neighbouring waves).
+// (two threads per point, partners in neighbouring waves).  The adjoint of a
+// solve needs about 400 registers per lane at its peak; the solve's inputs,
+// their adjoint accumulators and the moment adjoints live in LDS instead of
+// registers (one wave per SIMD, one block per CU), so that nothing spills.
+// The normal along y (fam != G) swaps rho U and rho V in the local frame:
+// the swap is applied to the data, so one copy of the solver adjoint serves
+// both normals.
 template <int STAGE>
-__global__ __launch_bounds__(256) void k_adj_edges(const double* __restrict__ S, const double* __restrict__ lamE,
-                                                   double* __restrict__ lamS, Geo g, Consts k, double dt) {
+__global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__ S, const double* __restrict__ lamE,
+                                                      double* __restrict__ lamS, Geo g, Consts k, double dt) {
   __shared__ double xch[4][4][64];
+  __shared__ fdk::SolveIO s_in[256], s_inb[256];
+  __shared__ fdk::AccB s_ab[256];
   const int fam = blockIdx.z;
-  const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
+  const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1, tid = ty * 64 + tx;
   const int i = blockIdx.x * 64 + tx + (fam == 0 ? -2 : -1);
   const int j = blockIdx.y * 2 + (ty >> 1) + (fam == 0 ? -1 : -2);
   const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
-  fdk::IfaceRec rec[4];
-  if (valid) {
-    edge_recon<false>(S, g, k, i, j, fam, G, rec);
-  } else {
-    for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
+  const bool swap = fam != G;
+  fdk::SolveIO& in = s_in[tid];
+  fdk::SolveIO& inb = s_inb[tid];
+  bool chi_right = false;  // chi = min(chi_l, chi_r) of the density line took chi_r (ties: left)
+  {
+    fdk::IfaceRec rec[4];
+    if (valid) {
+      edge_recon<false>(S, g, k, i, j, fam, G, rec);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xch[ty][c][tx] = 0.5 * (rec[c].dl + rec[c].dr);
+    __syncthreads();
+    // solve inputs in the local frame (global component of local slot c: q0 when swapped)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
+      const int q = swap ? q0 : c;
+      in.WL[c] = rec[q].vl;
+      in.WR[c] = rec[q].vr;
+      in.nL[c] = rec[q].dl;
+      in.nR[c] = rec[q].dr;
+      in.Wt[c] = xch[ty ^ 1][q][tx];
+      inb.WL[c] = inb.WR[c] = inb.nL[c] = inb.nR[c] = inb.Wt[c] = 0.0;
+    }
+    chi_right = rec[0].cr < rec[0].cl;
   }
-  for (int c = 0; c < 4; ++c) xch[ty][c][tx] = 0.5 * (rec[c].dl + rec[c].dr);
   __syncthreads();
-  double tang[4];
-  for (int c = 0; c < 4; ++c) tang[c] = xch[ty ^ 1][c][tx];
-  __syncthreads();
-  double lin[20];
-  for (int q = 0; q < 20; ++q) lin[q] = 0.0;
   double lchi = 0.0;
   if (valid) {
     const long pl = g.plane, o = at(g, j, i);
     const double* le = lamE + ((long)fam * 50 + G * 25) * pl + o;
     const double* lp = lamE + ((long)fam * 50 + (1 - G) * 25) * pl + o;  // partner slot
-    double lF[4], lFt[4], lWl[4], lWr[4], lWlt[4], lWrt[4];
+    fdk::GksIO<double, 2> ob;
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
       // blend^T: W~(own) = W^/2 + (partner W^l + W^r)/4 and W~(partner) = W^p/2 + (own W^l + W^r)/4
-      const double ps = lp[(9 + c) * pl] + lp[(13 + c) * pl], pst = lp[(17 + c) * pl] + lp[(21 + c) * pl];
-      lF[c] = le[c * pl];
-      lFt[c] = le[(4 + c) * pl];
-      lWl[c] = 0.5 * le[(9 + c) * pl] + 0.25 * ps;
-      lWr[c] = 0.5 * le[(13 + c) * pl] + 0.25 * ps;
-      lWlt[c] = 0.5 * le[(17 + c) * pl] + 0.25 * pst;
-      lWrt[c] = 0.5 * le[(21 + c) * pl] + 0.25 * pst;
+      const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
+      const int q = swap ? q0 : c;
+      const double ps = lp[(9 + q) * pl] + lp[(13 + q) * pl], pst = lp[(17 + q) * pl] + lp[(21 + q) * pl];
+      ob.Ft[c] = le[(4 + q) * pl];
+      ob.Wlt[c] = 0.5 * le[(17 + q) * pl] + 0.25 * pst;
+      ob.Wrt[c] = 0.5 * le[(21 + q) * pl] + 0.25 * pst;
+      ob.F[c] = STAGE == 1 ? le[q * pl] : 0.0;
+      ob.Wl[c] = STAGE == 1 ? 0.5 * le[(9 + q) * pl] + 0.25 * ps : 0.0;
+      ob.Wr[c] = STAGE == 1 ? 0.5 * le[(13 + q) * pl] + 0.25 * ps : 0.0;
     }
     lchi = le[8 * pl];
-    solve_adjoint<STAGE>(k, dt, fam != G, rec, tang, lF, lFt, lWl, lWr, lWlt, lWrt, lin);
+    fdk::gks_iface_b(k, dt, in, ob, inb, s_ab[tid]);
   }
   // the tangential slope of this solve came from the partner line: send its lambda
-  const bool swap = fam != G;
+#pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
-    xch[ty][c][tx] = swap && q0 != c ? lin[16 + q0] : lin[16 + c];  // local slot of global component c
+    xch[ty][c][tx] = swap && q0 != c ? inb.Wt[q0] : inb.Wt[c];  // global component c
   }
   __syncthreads();
   if (valid) {
     double lv[4][6];
+#pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
-      const bool sw = swap && q0 != c;  // local slot of global component c is q0 when swapped
+      const int q = swap ? q0 : c;  // local slot of global component c
       const double lt = 0.5 * xch[ty ^ 1][c][tx];  // partner's tangential slope = mean of my dl, dr
-      lv[c][0] = sw ? lin[q0] : lin[c];
-      lv[c][1] = (sw ? lin[8 + q0] : lin[8 + c]) + lt;
+      lv[c][0] = inb.WL[q];
+      lv[c][1] = inb.nL[q] + lt;
       lv[c][2] = 0.0;
-      lv[c][3] = sw ? lin[4 + q0] : lin[4 + c];
-      lv[c][4] = (sw ? lin[12 + q0] : lin[12 + c]) + lt;
+      lv[c][3] = inb.WR[q];
+      lv[c][4] = inb.nR[q] + lt;
       lv[c][5] = 0.0;
     }
-    // chi = min(chi_l, chi_r) of the density line (ties: left)
-    if (rec[0].cr < rec[0].cl) lv[0][5] = lchi; else lv[0][2] = lchi;
+    if (chi_right) lv[0][5] = lchi; else lv[0][2] = lchi;
     line_adjoint(S, lamS, g, k, i, j, fam, G, lv);
   }
 }

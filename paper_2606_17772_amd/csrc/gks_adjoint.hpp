@@ -251,6 +251,12 @@ FDK_HD double time_coef_b(double dt, double tau, const double cb[5], const doubl
 // Adjoints of the accumulated moments of f^n and f_t^n and the outputs.
 struct AccB {
   double F[4], Ft[4], We[4], Wet[4];
+  double pad;  // odd size in 8-byte words: per-thread copies in LDS spread over the banks
+};
+// Inputs of one interface solve (or their adjoints), padded like AccB.
+struct SolveIO {
+  double WL[4], WR[4], nL[4], nR[4], Wt[4];
+  double pad;
 };
 
 // One side's terms (see side_terms).  Wtb: adjoint of this side's Euler time
@@ -404,43 +410,68 @@ FDK_HD void equilibrium_b(const Prim<double>& s0, double K, double iKd, const do
   s0b.rho += rhob;
 }
 
+// A value the optimiser may not reuse from an earlier identical computation:
+// the adjoint below recomputes cheap forward quantities (primitive states,
+// half-line moments, time coefficients) where they are needed instead of
+// keeping them in registers through the whole reverse sweep.
+FDK_HD double fresh(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(x));
+#endif
+  return x;
+}
+// A compiler-only memory barrier between the phases of the solver adjoint:
+// values the caller keeps in memory (the LDS-resident inputs and
+// accumulators) are reloaded after it instead of being held in registers.
+FDK_HD void phase_barrier() {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" ::: "memory");
+#endif
+}
+// Primitive state and half-line moments of one side (sgn = +1: u > 0).
+FDK_HD void side_state(const double* W, double gamma, double K, double sgn, Prim<double>& s, Mom<double>& h) {
+  double Wf[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) Wf[i] = fresh(W[i]);
+  s = prim<double, 2>(Wf, gamma);
+  mom_common<double, 2>(s, K, h);
+  mom_half(s, sgn, h);
+}
+
 // Adjoint of the 2D interface solver with all outputs (gks_iface<double, 2,
-// true>).  out: adjoints of F, Ft, Wl, Wr, Wlt, Wrt (fields of o).  Adds the
-// adjoints of WL, WR, nL, nR, Wt into inb (same field names).
-FDK_HD void gks_iface_b(const Consts& k, double dt, const GksIO<double, 2>& in, const GksIO<double, 2>& ob,
-                        GksIO<double, 2>& inb) {
+// true>).  ob: adjoints of F, Ft, Wl, Wr, Wlt, Wrt.  Adds the adjoints of
+// WL, WR, nL, nR, Wt into inb (same field names).  in, inb and the moment
+// adjoint ab are references to storage the caller chooses (the reverse
+// interface sweep keeps them in LDS).  Ordered to keep few values live: the forward pass keeps only W0, tau and
+// the outputs the output adjoints need; each side's state and half-line
+// moments are recomputed for its reverse, and the adjoint of its half-line
+// moments is reduced to its primitive state at once (the moment maps are
+// linear in their adjoints, so the later W0 contribution is reduced
+// separately and added).
+template <class TIn, class TInb>
+FDK_HD void gks_iface_b(const Consts& k, double dt, const TIn& in, const GksIO<double, 2>& ob, TInb& inb, AccB& ab) {
   const double K = k.K, gam = k.gamma, iKd = k.inv_Kd;
   // ---- forward
-  Prim<double> sL = prim<double, 2>(in.WL, gam), sR = prim<double, 2>(in.WR, gam);
-  Mom<double> hL, hR;
-  mom_common<double, 2>(sL, K, hL);
-  mom_half(sL, 1.0, hL);
-  mom_common<double, 2>(sR, K, hR);
-  mom_half(sR, -1.0, hR);
-  double W0[4], pL[4], pR[4];
+  double W0[4], tau, F[4], Ft[4], We[4], Wet[4], WtL[4], WtR[4];
   {
-    double u[4];
-    psi_moms<double, 2>(hL, pL, u);
-    psi_moms<double, 2>(hR, pR, u);
+    Prim<double> sL, sR;
+    Mom<double> hL, hR;
+    side_state(in.WL, gam, K, 1.0, sL, hL);
+    side_state(in.WR, gam, K, -1.0, sR, hR);
+    {
+      double pL[4], pR[4], u[4];
+      psi_moms<double, 2>(hL, pL, u);
+      psi_moms<double, 2>(hR, pR, u);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) W0[i] = sL.rho * pL[i] + sR.rho * pR[i];
-  }
-  Prim<double> s0 = prim<double, 2>(W0, gam);
-  const double dP = sL.p - sR.p, sP = sL.p + sR.p;
-  const double tau = (k.mu > 0 ? k.mu / s0.p : k.tau_c1 * dt) + k.tau_c2 * dt * m_abs(dP) / sP;
-  TimeCoef<double> tc = time_coef(dt, tau);
-  // forward values needed by the output and Prandtl adjoints
-  GksIO<double, 2> fw;
+      for (int i = 0; i < 4; ++i) W0[i] = sL.rho * pL[i] + sR.rho * pR[i];
+    }
+    const Prim<double> s0 = prim<double, 2>(W0, gam);
+    tau = (k.mu > 0 ? k.mu / s0.p : k.tau_c1 * dt) + k.tau_c2 * dt * m_abs(sL.p - sR.p) / (sL.p + sR.p);
+    const TimeCoef<double> tc = time_coef(dt, tau);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    fw.WL[i] = in.WL[i]; fw.WR[i] = in.WR[i]; fw.nL[i] = in.nL[i]; fw.nR[i] = in.nR[i]; fw.Wt[i] = in.Wt[i];
-  }
-  double F[4], We[4], Wet[4], WtL[4], WtR[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) { F[i] = 0.0; fw.Ft[i] = 0.0; We[i] = 0.0; Wet[i] = 0.0; }
-  side_terms<double, 2, true>(sL, hL, in.nL, in.Wt, K, iKd, tau, tc, true, F, fw.Ft, We, Wet, WtL);
-  side_terms<double, 2, true>(sR, hR, in.nR, in.Wt, K, iKd, tau, tc, true, F, fw.Ft, We, Wet, WtR);
-  {
+    for (int i = 0; i < 4; ++i) { F[i] = 0.0; Ft[i] = 0.0; We[i] = 0.0; Wet[i] = 0.0; }
+    side_terms<double, 2, true>(sL, hL, in.nL, in.Wt, K, iKd, tau, tc, true, F, Ft, We, Wet, WtL);
+    side_terms<double, 2, true>(sR, hR, in.nR, in.Wt, K, iKd, tau, tc, true, F, Ft, We, Wet, WtR);
     Mom<double> m0;
     mom_common<double, 2>(s0, K, m0);
     mom_full(s0, m0);
@@ -459,15 +490,20 @@ FDK_HD void gks_iface_b(const Consts& k, double dt, const GksIO<double, 2>& in, 
     psi_moms<double, 2>(m0, p0, u0);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      fw.Ft[i] += s0.rho * (tc.ct[0] * u0[i] + tc.ct[1] * tu0[i] + tc.ct[2] * Au0[i]);
+      Ft[i] += s0.rho * (tc.ct[0] * u0[i] + tc.ct[1] * tu0[i] + tc.ct[2] * Au0[i]);
       Wet[i] += s0.rho * (tc.ct[0] * p0[i] + tc.ct[1] * t0[i] + tc.ct[2] * Ap0[i]);
       F[i] += s0.rho * (tc.c[0] * u0[i] + tc.c[1] * tu0[i] + tc.c[2] * Au0[i]);
       We[i] += s0.rho * (tc.c[0] * p0[i] + tc.c[1] * t0[i] + tc.c[2] * Ap0[i]);
     }
   }
+  phase_barrier();
+  double W0f[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) W0f[i] = fresh(W0[i]);
+  const Prim<double> s0 = prim<double, 2>(W0f, gam);
+  const TimeCoef<double> tc = time_coef(dt, fresh(tau));
   // ---- reverse: outputs
   const double e = tc.e1, oe = 1.0 - e;
-  AccB ab;
   double WtLb[4], WtRb[4], eb = 0.0;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -488,7 +524,6 @@ FDK_HD void gks_iface_b(const Consts& k, double dt, const GksIO<double, 2>& in, 
     const double U = s0.U, V = s0.V, f = k.prfix;
     const double a = 1.5 * U * U + 0.5 * V * V, bq = 0.5 * U * (U * U + V * V);
     const double qb = f * ab.F[3], qtb = f * ab.Ft[3];
-    const double* Ft = fw.Ft;
     s0b.U += qb * (-F[1] + 3.0 * U * F[0] - We[3] + V * We[2] - 0.5 * (3.0 * U * U + V * V) * We[0]) +
              qtb * (-Ft[1] + 3.0 * U * Ft[0] - Wet[3] + V * Wet[2] - 0.5 * (3.0 * U * U + V * V) * Wet[0]);
     s0b.V += qb * (-F[2] + V * F[0] + U * We[2] - U * V * We[0]) +
@@ -500,42 +535,70 @@ FDK_HD void gks_iface_b(const Consts& k, double dt, const GksIO<double, 2>& in, 
   }
   // ---- reverse: equilibrium and the two sides
   double cb[5] = {0, 0, 0, 0, 0}, ctb[5] = {0, 0, 0, 0, 0}, taub = 0.0;
+  phase_barrier();
   equilibrium_b(s0, K, iKd, in.nL, in.nR, in.Wt, tc, ab, inb.nL, inb.nR, inb.Wt, s0b, cb, ctb);
-  Mom<double> hLb, hRb;
-  mom_zero(hLb);
-  mom_zero(hRb);
-  side_terms_b(sL, hL, in.nL, in.Wt, K, iKd, tau, tc, ab, WtLb, inb.nL, inb.Wt, sLb, hLb, taub, cb, ctb);
-  side_terms_b(sR, hR, in.nR, in.Wt, K, iKd, tau, tc, ab, WtRb, inb.nR, inb.Wt, sRb, hRb, taub, cb, ctb);
+#pragma unroll 1
+  for (int side = 0; side < 2; ++side) {
+    phase_barrier();
+    const double sgn = side == 0 ? 1.0 : -1.0;
+    Prim<double> s;
+    Mom<double> h, hb;
+    side_state(side == 0 ? in.WL : in.WR, gam, K, sgn, s, h);
+    mom_zero(hb);
+    PrimB sb = primb_zero();
+    double wtb[4];  // selected by value: a pointer select would put both arrays in scratch memory
+#pragma unroll
+    for (int i = 0; i < 4; ++i) wtb[i] = side == 0 ? WtLb[i] : WtRb[i];
+    side_terms_b(s, h, side == 0 ? in.nL : in.nR, in.Wt, K, iKd, tau, tc, ab, wtb, side == 0 ? inb.nL : inb.nR,
+                 inb.Wt, sb, hb, taub, cb, ctb);
+    mom_half_b(s, sgn, h, hb, sb);
+    mom_common_b(s, K, h, hb, sb);
+    if (side == 0) sLb = sb;
+    else sRb = sb;
+  }
   // ---- reverse: collision time and time coefficients
+  phase_barrier();
   taub += time_coef_b(dt, tau, cb, ctb, eb);
   if (k.mu > 0) s0b.p += -k.mu / (s0.p * s0.p) * taub;
   {
+    const Prim<double> pl = prim<double, 2>(in.WL, gam), pr = prim<double, 2>(in.WR, gam);
+    const double dP = pl.p - pr.p, sP = pl.p + pr.p;
     const double g = k.tau_c2 * dt, sg = dP > 0 ? 1.0 : (dP < 0 ? -1.0 : 0.0), ad = m_abs(dP);
     sLb.p += g * (sg / sP - ad / (sP * sP)) * taub;
     sRb.p += g * (-sg / sP - ad / (sP * sP)) * taub;
   }
-  // ---- reverse: compatibility state W0 and the half moments
+  // ---- reverse: compatibility state W0, then each side's state
   double W0b[4] = {0, 0, 0, 0};
-  prim_b(W0, s0, gam, s0b, W0b);
-  {
+  prim_b(W0f, s0, gam, s0b, W0b);
+#pragma unroll 1
+  for (int side = 0; side < 2; ++side) {
+    phase_barrier();
+    const double sgn = side == 0 ? 1.0 : -1.0;
+    Prim<double> s;
+    Mom<double> h, hb;
+    side_state(side == 0 ? in.WL : in.WR, gam, K, sgn, s, h);
+    mom_zero(hb);
+    PrimB sb;
+    sb.rho = side == 0 ? sLb.rho : sRb.rho;
+    sb.irho = side == 0 ? sLb.irho : sRb.irho;
+    sb.U = side == 0 ? sLb.U : sRb.U;
+    sb.V = side == 0 ? sLb.V : sRb.V;
+    sb.p = side == 0 ? sLb.p : sRb.p;
+    sb.i2l = side == 0 ? sLb.i2l : sRb.i2l;
+    sb.lam = side == 0 ? sLb.lam : sRb.lam;
     const double zero[4] = {0, 0, 0, 0};
-    double pLb[4], pRb[4];
+    double p[4], u[4], pb[4];
+    psi_moms<double, 2>(h, p, u);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      pLb[i] = sL.rho * W0b[i];
-      pRb[i] = sR.rho * W0b[i];
-      sLb.rho += pL[i] * W0b[i];
-      sRb.rho += pR[i] * W0b[i];
+      pb[i] = s.rho * W0b[i];
+      sb.rho += p[i] * W0b[i];
     }
-    psi_moms_b(hL, pLb, zero, hLb);
-    psi_moms_b(hR, pRb, zero, hRb);
+    psi_moms_b(h, pb, zero, hb);
+    mom_half_b(s, sgn, h, hb, sb);
+    mom_common_b(s, K, h, hb, sb);
+    prim_b(side == 0 ? in.WL : in.WR, s, gam, sb, side == 0 ? inb.WL : inb.WR);
   }
-  mom_half_b(sL, 1.0, hL, hLb, sLb);
-  mom_common_b(sL, K, hL, hLb, sLb);
-  mom_half_b(sR, -1.0, hR, hRb, sRb);
-  mom_common_b(sR, K, hR, hRb, sRb);
-  prim_b(in.WL, sL, gam, sLb, inb.WL);
-  prim_b(in.WR, sR, gam, sRb, inb.WR);
 }
 
 // Adjoint of the 2D nodal solver with all outputs (gks_node<double, 2, true>).
