@@ -329,26 +329,29 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
                               int32_t on_device);
 
 /* ---------------------------------------------------------------- batches
- * Many independent periodic 2D problems of different sizes advanced together
- * (same scheme constants, each member its own grid, mesh size and CFL time
+ * Many independent 2D problems of different sizes advanced together (same
+ * scheme constants, each member its own grid, mesh size, sides and CFL time
  * step): every launch covers every member, one launch per phase of a stage
- * (default) or one cooperative persistent launch per stage (see
- * fdcgks_batch_set_mode).  Same state layout and on_device rule as the
- * single-problem calls. */
+ * (captured as HIP graphs by default) or one cooperative persistent launch
+ * per stage (see fdcgks_batch_set_mode).  Same state layout and on_device
+ * rule as the single-problem calls; the dual grid of a member with bounded
+ * axes has one more column / row along them. */
 typedef struct fdcgks_batch fdcgks_batch; /* opaque, owned by the library */
 
 /* How a batched stage is launched.  PERSISTENT: one cooperative launch per
  * stage, sized to the co-resident grid, that walks the device work list in
  * three phases separated by grid barriers (CFL partials and halo; interface
- * and node sweeps; update).  PHASED (default): the same work list and device
- * code as one launch per phase (halo, interfaces, nodes, update), so that
- * every phase runs at its own occupancy.  Both give bitwise the same
- * results. */
-enum { FDCGKS_BATCH_PERSISTENT = 0, FDCGKS_BATCH_PHASED = 1 };
+ * and node sweeps; update).  PHASED: the same work list and device code as
+ * one launch per phase (halo, interfaces, nodes, update), so that every
+ * phase runs at its own occupancy.  GRAPH (default): the PHASED launches of
+ * 16 steps captured as one HIP graph (per start parity and cfl, on first
+ * use) and replayed; the last nsteps mod 16 steps launch separately.  All
+ * give bitwise the same results. */
+enum { FDCGKS_BATCH_PERSISTENT = 0, FDCGKS_BATCH_PHASED = 1, FDCGKS_BATCH_GRAPH = 2 };
 
-/* params[count]: every member 2D periodic with conservative reconstruction
- * and flux_order 6 (EINVAL otherwise); members may differ only in nx, ny, x0,
- * lx, y0, ly.
+/* params[count]: every member 2D with conservative reconstruction and
+ * flux_order 6 (EINVAL otherwise); members may differ only in nx, ny, x0,
+ * lx, y0, ly and their sides (bc, side[4]).
  * Allocates all device memory on the current device. */
 fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, void* hip_stream, fdcgks_batch** out);
 fdcgks_status fdcgks_batch_set_state(fdcgks_batch* b, int32_t member, int32_t grid, const double* W,
@@ -364,8 +367,8 @@ fdcgks_status fdcgks_batch_step(fdcgks_batch* b, double cfl, int32_t nsteps, dou
 fdcgks_status fdcgks_batch_destroy(fdcgks_batch* b);
 const char* fdcgks_batch_last_error(const fdcgks_batch* b);
 
-/* Select FDCGKS_BATCH_PERSISTENT or FDCGKS_BATCH_PHASED for later
- * fdcgks_batch_step calls (EINVAL otherwise). */
+/* Select FDCGKS_BATCH_PERSISTENT, FDCGKS_BATCH_PHASED or FDCGKS_BATCH_GRAPH
+ * for later fdcgks_batch_step calls (EINVAL otherwise). */
 fdcgks_status fdcgks_batch_set_mode(fdcgks_batch* b, int32_t mode);
 
 #ifdef __cplusplus

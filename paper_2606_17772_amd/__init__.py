@@ -403,7 +403,8 @@ class Problem:
 
 class Batch:
     """Many independent 2D problems advanced together (fdcgks_batch_*):
-    one cooperative persistent launch per stage for all members."""
+    every launch covers every member (phased launches captured as graphs by
+    default; see set_mode)."""
 
     def __init__(self, params_list, stream=None):
         self._L = _lib.load()
@@ -435,22 +436,28 @@ class Batch:
         py, _, _ = _ptr(Wy)
         self._chk(self._L.fdcgks_batch_set_state(self._h, member, grid, pw, px, py, dev))
 
-    def set_state_stacked(self, member, grid, S):
+    def grid_dims(self, member, grid):
+        """(ny, nx) of the nodes of `grid` of a member (the dual grid has one
+        more row / column along a bounded axis)."""
         p = self.params[member]
-        S = np.ascontiguousarray(S, dtype=np.float64).reshape(12, p.ny, p.nx)
+        side = [p.side[k] if p.side[k] >= 0 else p.bc for k in range(4)]
+        return (p.ny + (grid == 1 and side[2] != BC_PERIODIC), p.nx + (grid == 1 and side[0] != BC_PERIODIC))
+
+    def set_state_stacked(self, member, grid, S):
+        S = np.ascontiguousarray(S, dtype=np.float64).reshape((12,) + self.grid_dims(member, grid))
         self.set_state(member, grid, np.ascontiguousarray(S[:4]), np.ascontiguousarray(S[4:8]),
                        np.ascontiguousarray(S[8:12]))
 
     def get_state_stacked(self, member, grid):
-        p = self.params[member]
-        out = [np.empty((4, p.ny, p.nx)) for _ in range(3)]
+        out = [np.empty((4,) + self.grid_dims(member, grid)) for _ in range(3)]
         self._chk(self._L.fdcgks_batch_get_state(self._h, member, grid, *(C.c_void_p(a.ctypes.data) for a in out), 0))
         return np.concatenate(out, axis=0)
 
     def set_mode(self, mode):
-        """'phased' (one launch per phase, default) or 'persistent' (one
-        cooperative launch per stage)."""
-        m = {"persistent": _lib.BATCH_PERSISTENT, "phased": _lib.BATCH_PHASED}[mode]
+        """'graph' (one launch per phase, 16 steps per captured HIP graph;
+        default), 'phased' (the same launches, not captured) or 'persistent'
+        (one cooperative launch per stage)."""
+        m = {"persistent": _lib.BATCH_PERSISTENT, "phased": _lib.BATCH_PHASED, "graph": _lib.BATCH_GRAPH}[mode]
         self._chk(self._L.fdcgks_batch_set_mode(self._h, m))
 
     def step(self, nsteps=1, cfl=0.5):

@@ -21,7 +21,7 @@ GRAD_REEVAL, GRAD_CARRIED = 0, 1
 RECON_CONSERVATIVE, RECON_CHARACTERISTIC = 0, 1
 OPT_GRAPH, OPT_TILE_EDGE, OPT_TILE_NODE, OPT_TILE_UPDATE, OPT_FUSE_NODES, OPT_FUSE_STAGE, OPT_FUSED_ROWS = \
     0, 1, 2, 3, 4, 5, 6
-BATCH_PERSISTENT, BATCH_PHASED = 0, 1
+BATCH_PERSISTENT, BATCH_PHASED, BATCH_GRAPH = 0, 1, 2
 
 
 class Params(C.Structure):

@@ -1541,16 +1541,19 @@ __device__ __forceinline__ double member_dt(const BArgs& a, int m, const Consts&
   return dt;
 }
 
-// CFL partial of one member over rows [16 by, 16 by + 16) of both grids.
+// CFL partial of one member over stored rows [16 by, 16 by + 16) of both
+// grids (the dual grid has one more row and column along a bounded axis).
 __device__ __forceinline__ void cfl_block(const BArgs& a, const Consts& k, const BItem& it, double* red) {
   const BMember& M = a.mem[it.m];
   const Geo& g = M.g;
   const double* S = M.S[a.cur];
   const int nthr = blockDim.x * blockDim.y, tid = threadIdx.y * blockDim.x + threadIdx.x;
   double vmax = 0.0, rmin = 1e300;
-  const int j0 = it.by * 16, j1 = min(g.ny, j0 + 16);
-  for (int q = tid; q < 2 * (j1 - j0) * g.nx; q += nthr) {
-    int i = q % g.nx, r = q / g.nx, j = j0 + r % (j1 - j0), gr = r / (j1 - j0);
+  const int H = g.ny + g.sy, W = g.nx + g.sx;
+  const int j0 = it.by * 16, j1 = min(H, j0 + 16);
+  for (int q = tid; q < 2 * (j1 - j0) * W; q += nthr) {
+    int i = q % W, r = q / W, j = j0 + r % (j1 - j0), gr = r / (j1 - j0);
+    if (gr == 0 && (i >= g.nx || j >= g.ny)) continue;
     const double* B = S + (long)gr * 12 * g.plane + at(g, j, i);
     double rho = B[0], U = B[g.plane] / rho, V = B[2 * g.plane] / rho;
     double p = (k.gamma - 1.0) * (B[3 * g.plane] - 0.5 * rho * (U * U + V * V));
@@ -1576,19 +1579,29 @@ __device__ __forceinline__ void cfl_block(const BArgs& a, const Consts& k, const
   __syncthreads();
 }
 
-// Periodic halo of one state plane (rows, then whole columns).
-__device__ __forceinline__ void halo_plane_block(double* __restrict__ P, const Geo& g) {
+// Halo of state plane p of a member (rows over the real columns, then whole
+// columns): periodic images or the ghosts of bounded sides, as k_halo_rows /
+// k_halo_cols fill them for a single problem.
+__device__ __forceinline__ void halo_plane_block(double* __restrict__ S, const Geo& g, int p) {
   const int nthr = blockDim.x * blockDim.y, tid = threadIdx.y * blockDim.x + threadIdx.x;
-  for (int q = tid; q < 2 * HALO * g.nx; q += nthr) {
-    int i = q % g.nx, hr = q / g.nx;
-    int j = hr < HALO ? hr - HALO : g.ny + (hr - HALO);
-    P[at(g, j, i)] = P[at(g, imod(j, g.ny), i)];
+  const PlaneInfo q = plane_info(g, p);
+  double* P = S + (long)p * g.plane;
+  for (int t = tid; t < 2 * HALO * q.mx; t += nthr) {
+    const int i = t % q.mx, hr = t / q.mx;
+    const int j = hr < HALO ? hr - HALO : q.my + (hr - HALO);
+    double fac;
+    const int js = ghost_src(j, q.my, g.side[2], g.side[3], q.dual && g.sy, q.field == 2, q.comp == 2,
+                             q.comp == 1 || q.comp == 2, fac);
+    P[at(g, j, i)] = fac * P[at(g, js, i)];
   }
   __syncthreads();
-  for (int q = tid; q < (g.ny + 2 * HALO) * 2 * HALO; q += nthr) {
-    int hc = q % (2 * HALO), j = q / (2 * HALO) - HALO;
-    int i = hc < HALO ? hc - HALO : g.nx + (hc - HALO);
-    P[at(g, j, i)] = P[at(g, j, imod(i, g.nx))];
+  for (int t = tid; t < (q.my + 2 * HALO) * 2 * HALO; t += nthr) {
+    const int hc = t % (2 * HALO), j = t / (2 * HALO) - HALO;
+    const int i = hc < HALO ? hc - HALO : q.mx + (hc - HALO);
+    double fac;
+    const int is = ghost_src(i, q.mx, g.side[0], g.side[1], q.dual && g.sx, q.field == 1, q.comp == 1,
+                             q.comp == 1 || q.comp == 2, fac);
+    P[at(g, j, i)] = fac * P[at(g, j, is)];
   }
   __syncthreads();
 }
@@ -1631,8 +1644,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
   it += a.n_cfl;
   for (int q = blockIdx.x; q < a.n_halo; q += nb) {
     const BMember& M = a.mem[it[q].m];
-    double* S = STAGE == 1 ? M.S[a.cur] : M.Sstar;
-    halo_plane_block(S + (long)it[q].z * M.g.plane, M.g);
+    halo_plane_block(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.g, it[q].z);
   }
   it += a.n_halo;
   grid.sync();
@@ -1643,7 +1655,7 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
       const BItem& w = it[q];
       const BMember& M = a.mem[w.m];
       edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z,
-                            w.z == 0 ? -2 : -1);
+                            w.z == 0 ? -2 : -1 - M.g.sx);
     }
   }
   it += a.n_edge;
@@ -1696,8 +1708,7 @@ __global__ __launch_bounds__(256) void k_bphase_halo(BArgs a, Consts k) {
   }
   const BItem& it = a.items[a.n_cfl + q - (STAGE == 1 ? a.n_cfl : 0)];
   const BMember& M = a.mem[it.m];
-  double* S = STAGE == 1 ? M.S[a.cur] : M.Sstar;
-  halo_plane_block(S + (long)it.z * M.g.plane, M.g);
+  halo_plane_block(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.g, it.z);
 }
 template <int STAGE, class FT>
 __global__ __launch_bounds__(256, FDCGKS_EDGE_WAVES) void k_bphase_edges(BArgs a, Consts k) {
@@ -1705,7 +1716,7 @@ __global__ __launch_bounds__(256, FDCGKS_EDGE_WAVES) void k_bphase_edges(BArgs a
   const BItem& w = a.items[a.n_cfl + a.n_halo + blockIdx.x];
   const BMember& M = a.mem[w.m];
   edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z,
-                        w.z == 0 ? -2 : -1);
+                        w.z == 0 ? -2 : -1 - M.g.sx);
 }
 template <int STAGE, class FT>
 __global__ __launch_bounds__(256) void k_bphase_nodes(BArgs a, Consts k) {
@@ -2970,7 +2981,12 @@ struct fdcgks_batch {
   Scal* sc_host = nullptr;
   int cur = 0, parity = 0;
   int blocks = 0;
-  int mode = FDCGKS_BATCH_PHASED;
+  int mode = FDCGKS_BATCH_GRAPH;
+  // FDCGKS_BATCH_GRAPH: BATCH_GRAPH_STEPS phased steps captured as one HIP
+  // graph per start parity (cur, parity), on a private stream, for one cfl
+  hipStream_t cap = nullptr;
+  hipGraphExec_t gx[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};
+  double g_cfl[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
   std::vector<char> have_state;
   std::string err;
 };
@@ -2991,7 +3007,19 @@ fdcgks_status bfail(fdcgks_batch* b, fdcgks_status st, const char* fmt, ...) {
     if (e_ != hipSuccess) return bfail(b, FDCGKS_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
   } while (0)
 
+void batch_graphs_free(fdcgks_batch* b) {
+  for (auto& row : b->gx)
+    for (hipGraphExec_t& x : row)
+      if (x) {
+        (void)hipGraphExecDestroy(x);
+        x = nullptr;
+      }
+}
+
 void batch_free(fdcgks_batch* b) {
+  batch_graphs_free(b);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  b->cap = nullptr;
   for (void* p : b->allocs) (void)hipFree(p);
   b->allocs.clear();
   if (b->sc_host) (void)hipHostFree(b->sc_host);
@@ -3004,6 +3032,33 @@ bool same_scheme(const fdcgks_params& a, const fdcgks_params& b) {
          a.geno_C == b.geno_C && a.geno_eps == b.geno_eps && a.geno_eps_a == b.geno_eps_a &&
          a.geno_d_central == b.geno_d_central && a.geno_d_side == b.geno_d_side && a.tau_c1 == b.tau_c1 &&
          a.tau_c2 == b.tau_c2;
+}
+
+// Steps per captured batch graph (even, so that a graph keeps the parity).
+constexpr int BATCH_GRAPH_STEPS = 16;
+
+// One batched step as one launch per phase on `stream`.
+void batch_phased_step(const BArgs& a, const Consts& k, bool fp32, hipStream_t stream) {
+  const dim3 blk(64, 4);
+  hipLaunchKernelGGL(k_bphase_halo<1>, dim3(a.n_cfl + a.n_halo), blk, 0, stream, a, k);
+  if (fp32) {
+    hipLaunchKernelGGL((k_bphase_edges<1, float>), dim3(a.n_edge), blk, 0, stream, a, k);
+    hipLaunchKernelGGL((k_bphase_nodes<1, float>), dim3(a.n_node), blk, 0, stream, a, k);
+  } else {
+    hipLaunchKernelGGL((k_bphase_edges<1, double>), dim3(a.n_edge), blk, 0, stream, a, k);
+    hipLaunchKernelGGL((k_bphase_nodes<1, double>), dim3(a.n_node), blk, 0, stream, a, k);
+  }
+  hipLaunchKernelGGL(k_bphase_update<1>, dim3(a.n_upd), blk, 0, stream, a, k);
+  hipLaunchKernelGGL(k_bphase_halo<2>, dim3(a.n_halo), blk, 0, stream, a, k);
+  if (fp32) {
+    hipLaunchKernelGGL((k_bphase_edges<2, float>), dim3(a.n_edge), blk, 0, stream, a, k);
+    hipLaunchKernelGGL((k_bphase_nodes<2, float>), dim3(a.n_node), blk, 0, stream, a, k);
+  } else {
+    hipLaunchKernelGGL((k_bphase_edges<2, double>), dim3(a.n_edge), blk, 0, stream, a, k);
+    hipLaunchKernelGGL((k_bphase_nodes<2, double>), dim3(a.n_node), blk, 0, stream, a, k);
+  }
+  hipLaunchKernelGGL(k_bphase_update<2>, dim3(a.n_upd), blk, 0, stream, a, k);
+  hipLaunchKernelGGL(k_bphase_end, dim3(1), blk, 0, stream, a, k);
 }
 
 template <class FT> void* batch_kernel(int stage) {
@@ -3024,9 +3079,6 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
     if (params[m].recon_vars != FDCGKS_RECON_CONSERVATIVE)
       return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches reconstruct conservative variables only", m);
     if (params[m].flux_order != 6) return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches use the order-6 flux", m);
-    for (int k = 0; k < 4; ++k)
-      if (side_bc(params[m], k) != FDCGKS_BC_PERIODIC)
-        return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches are periodic only", m);
     if (!same_scheme(params[0], params[m]))
       return bfail(nullptr, FDCGKS_EINVAL, "member %d: scheme constants differ from member 0", m);
   }
@@ -3076,13 +3128,8 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
   };
   for (int m = 0; m < count && e == hipSuccess; ++m) {
     Geo& g = b->mem[m].g;
-    g.nx = params[m].nx;
-    g.ny = params[m].ny;
-    g.pitch = ((params[m].nx + 2 * OX) + 15) / 16 * 16;
-    g.rows = params[m].ny + 2 * OY;
-    g.plane = (long)g.pitch * g.rows;
-    g.h = params[m].lx / params[m].nx;
-    g.invh = 1.0 / g.h;
+    Consts km;  // the shared constants are b->k
+    setup_geometry(params[m], g, km);
     size_t sb = (size_t)24 * g.plane * sizeof(double);
     b->mem[m].S[0] = alloc(sb);
     b->mem[m].S[1] = alloc(sb);
@@ -3090,17 +3137,19 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
     b->mem[m].Acc = alloc(sb);
     b->mem[m].E = alloc((size_t)100 * g.plane * sizeof(double));
     b->mem[m].Nb = alloc((size_t)32 * g.plane * sizeof(double));
-    for (int by = 0; by < ceil_div(g.ny, 16); ++by) cfl.push_back({m, 0, 0, by});
+    // ranges of the single-problem launches; a bounded axis adds the dual
+    // grid's boundary row / column
+    for (int by = 0; by < ceil_div(g.ny + g.sy, 16); ++by) cfl.push_back({m, 0, 0, by});
     for (int pl = 0; pl < 24; ++pl) halo.push_back({m, pl, 0, 0});
     for (int z = 0; z < 2; ++z)
-      for (int by = 0; by < ceil_div(g.ny + 3, 2); ++by)
-        for (int bx = 0; bx < ceil_div(g.nx + 3, 64); ++bx) edge.push_back({m, z, bx, by});
+      for (int by = 0; by < ceil_div(g.ny + 3 + g.sy, 2); ++by)
+        for (int bx = 0; bx < ceil_div(g.nx + 3 + g.sx, 64); ++bx) edge.push_back({m, z, bx, by});
     for (int z = 0; z < 2; ++z)
-      for (int by = 0; by < ceil_div(g.ny + 2, 4); ++by)
+      for (int by = 0; by < ceil_div(g.ny + 2 + g.sy, 4); ++by)
         for (int bx = 0; bx < ceil_div(g.nx + 1 + OX, 64); ++bx) node.push_back({m, z, bx, by});  // from i = -OX
     for (int z = 0; z < 2; ++z)
-      for (int by = 0; by < ceil_div(g.ny, 4); ++by)
-        for (int bx = 0; bx < ceil_div(g.nx, 64); ++bx) upd.push_back({m, z, bx, by});
+      for (int by = 0; by < ceil_div(g.ny + g.sy, 4); ++by)
+        for (int bx = 0; bx < ceil_div(g.nx + g.sx, 64); ++bx) upd.push_back({m, z, bx, by});
   }
   b->n_cfl = (int)cfl.size();
   b->n_halo = (int)halo.size();
@@ -3156,8 +3205,9 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
 static fdcgks_status batch_copy(fdcgks_batch* b, int m, int grid, double* const* ptrs, int to_dev, int on_device) {
   const Geo& g = b->mem[m].g;
   double* base = b->mem[m].S[b->cur] + (long)grid * 12 * g.plane;
-  size_t row = (size_t)g.nx * sizeof(double);
-  const size_t dense = (size_t)g.nx * g.ny;
+  const int mx = g.nx + (grid ? g.sx : 0), my = g.ny + (grid ? g.sy : 0);  // stored nodes of the grid
+  size_t row = (size_t)mx * sizeof(double);
+  const size_t dense = (size_t)mx * my;
   // host arrays go through the member's interface buffer (idle between
   // steps) as one contiguous transfer per field, like single problems
   for (int f = 0; f < 3; ++f) {
@@ -3168,10 +3218,10 @@ static fdcgks_status batch_copy(fdcgks_batch* b, int m, int grid, double* const*
       double* dev = base + (long)(f * 4 + c) * g.plane + (long)OY * g.pitch + OX;
       double* usr = stage + (long)c * dense;
       if (to_dev)
-        BHIPCHK(b, hipMemcpy2DAsync(dev, (size_t)g.pitch * sizeof(double), usr, row, row, g.ny,
+        BHIPCHK(b, hipMemcpy2DAsync(dev, (size_t)g.pitch * sizeof(double), usr, row, row, my,
                                     hipMemcpyDeviceToDevice, b->stream));
       else
-        BHIPCHK(b, hipMemcpy2DAsync(usr, row, dev, (size_t)g.pitch * sizeof(double), row, g.ny,
+        BHIPCHK(b, hipMemcpy2DAsync(usr, row, dev, (size_t)g.pitch * sizeof(double), row, my,
                                     hipMemcpyDeviceToDevice, b->stream));
     }
     if (!to_dev && !on_device)
@@ -3228,37 +3278,48 @@ fdcgks_status fdcgks_batch_step(fdcgks_batch* b, double cfl, int32_t nsteps, dou
   a.dt_last = b->dt_last;
   a.sc = b->sc;
   const bool fp32 = b->prm0.flux_precision == FDCGKS_FP32_FLUX;
-  const dim3 blk(64, 4);
-  for (int s = 0; s < nsteps; ++s) {
+  int s = 0;
+  if (b->mode == FDCGKS_BATCH_GRAPH && nsteps >= BATCH_GRAPH_STEPS) {
+    // whole graphs of BATCH_GRAPH_STEPS (even) steps leave cur and parity unchanged
+    hipGraphExec_t& gx = b->gx[cur0][par0];
+    if (gx && b->g_cfl[cur0][par0] != cfl) {
+      (void)hipGraphExecDestroy(gx);
+      gx = nullptr;
+    }
+    if (!gx) {
+      if (!b->cap) BHIPCHK(b, hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+      BHIPCHK(b, hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+      for (int q = 0; q < BATCH_GRAPH_STEPS; ++q) {
+        a.cur = cur0 ^ (q & 1);
+        a.parity = par0 ^ (q & 1);
+        batch_phased_step(a, b->k, fp32, b->cap);
+      }
+      hipGraph_t gr = nullptr;
+      hipError_t e = hipStreamEndCapture(b->cap, &gr);
+      if (e == hipSuccess) e = hipGetLastError();
+      if (e == hipSuccess) e = hipGraphInstantiate(&gx, gr, nullptr, nullptr, 0);
+      if (gr) (void)hipGraphDestroy(gr);
+      if (e != hipSuccess) {
+        gx = nullptr;
+        return bfail(b, FDCGKS_EHIP, "batched step capture: %s", hipGetErrorString(e));
+      }
+      b->g_cfl[cur0][par0] = cfl;
+    }
+    for (; s + BATCH_GRAPH_STEPS <= nsteps; s += BATCH_GRAPH_STEPS)
+      BHIPCHK(b, hipGraphLaunch(gx, b->stream));
+  }
+  for (; s < nsteps; ++s) {
     a.cur = cur0 ^ (s & 1);
     a.parity = par0 ^ (s & 1);
     if (b->mode == FDCGKS_BATCH_PERSISTENT) {
       void* args[2] = {&a, &b->k};
       for (int stage = 1; stage <= 2; ++stage) {
         void* fn = fp32 ? batch_kernel<float>(stage) : batch_kernel<double>(stage);
-        BHIPCHK(b, hipLaunchCooperativeKernel(fn, dim3(b->blocks), blk, args, 0, b->stream));
+        BHIPCHK(b, hipLaunchCooperativeKernel(fn, dim3(b->blocks), dim3(64, 4), args, 0, b->stream));
       }
       continue;
     }
-    hipLaunchKernelGGL(k_bphase_halo<1>, dim3(a.n_cfl + a.n_halo), blk, 0, b->stream, a, b->k);
-    if (fp32) {
-      hipLaunchKernelGGL((k_bphase_edges<1, float>), dim3(a.n_edge), blk, 0, b->stream, a, b->k);
-      hipLaunchKernelGGL((k_bphase_nodes<1, float>), dim3(a.n_node), blk, 0, b->stream, a, b->k);
-    } else {
-      hipLaunchKernelGGL((k_bphase_edges<1, double>), dim3(a.n_edge), blk, 0, b->stream, a, b->k);
-      hipLaunchKernelGGL((k_bphase_nodes<1, double>), dim3(a.n_node), blk, 0, b->stream, a, b->k);
-    }
-    hipLaunchKernelGGL(k_bphase_update<1>, dim3(a.n_upd), blk, 0, b->stream, a, b->k);
-    hipLaunchKernelGGL(k_bphase_halo<2>, dim3(a.n_halo), blk, 0, b->stream, a, b->k);
-    if (fp32) {
-      hipLaunchKernelGGL((k_bphase_edges<2, float>), dim3(a.n_edge), blk, 0, b->stream, a, b->k);
-      hipLaunchKernelGGL((k_bphase_nodes<2, float>), dim3(a.n_node), blk, 0, b->stream, a, b->k);
-    } else {
-      hipLaunchKernelGGL((k_bphase_edges<2, double>), dim3(a.n_edge), blk, 0, b->stream, a, b->k);
-      hipLaunchKernelGGL((k_bphase_nodes<2, double>), dim3(a.n_node), blk, 0, b->stream, a, b->k);
-    }
-    hipLaunchKernelGGL(k_bphase_update<2>, dim3(a.n_upd), blk, 0, b->stream, a, b->k);
-    hipLaunchKernelGGL(k_bphase_end, dim3(1), blk, 0, b->stream, a, b->k);
+    batch_phased_step(a, b->k, fp32, b->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, FDCGKS_EHIP, "batched launch failed: %s", hipGetErrorString(e));
   }
@@ -3299,7 +3360,7 @@ const char* fdcgks_batch_last_error(const fdcgks_batch* b) { return b ? b->err.c
 
 fdcgks_status fdcgks_batch_set_mode(fdcgks_batch* b, int32_t mode) {
   if (!b) return bfail(nullptr, FDCGKS_EINVAL, "batch is NULL");
-  if (mode != FDCGKS_BATCH_PERSISTENT && mode != FDCGKS_BATCH_PHASED)
+  if (mode != FDCGKS_BATCH_PERSISTENT && mode != FDCGKS_BATCH_PHASED && mode != FDCGKS_BATCH_GRAPH)
     return bfail(b, FDCGKS_EINVAL, "unknown batch mode %d", mode);
   b->mode = mode;
   return FDCGKS_OK;

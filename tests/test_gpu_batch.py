@@ -1,6 +1,7 @@
-"""Batched 2D solves over many uneven grids, in both launch modes (one launch
-per phase; one cooperative persistent launch per stage), against the
-single-problem HIP path and the oracle (GPU)."""
+"""Batched 2D solves over many uneven grids, in every launch mode (one launch
+per phase, also captured as HIP graphs; one cooperative persistent launch per
+stage), with periodic and bounded members, against the single-problem HIP
+path and the oracle (GPU)."""
 import numpy as np
 import pytest
 
@@ -21,14 +22,34 @@ def _settings(pr):
     return settings(dim=2, nx=pr.nx, ny=pr.ny, lx=pr.lx)
 
 
-MODES = ["phased", "persistent"]
+MODES = ["phased", "persistent", "graph"]
 
 
-def _batch(probs, mode):
+def _batch(probs, mode, setts=None):
     from paper_2606_17772_amd import Batch
-    B = Batch([gpu_params(_settings(p)) for p in probs])
+    B = Batch([gpu_params(s) for s in (setts or [_settings(p) for p in probs])])
     B.set_mode(mode)
     return B
+
+
+def _bounded_members():
+    """Members with bounded sides: zero-gradient four-quadrant Riemann data,
+    a no-slip / reflecting Navier-Stokes flow, mixed sides, and a periodic
+    vortex beside them."""
+    out = []
+    pr = WL.riemann2d_bounded(21, seed=3)
+    out.append((settings(dim=2, nx=21, ny=21, lx=1.0, bc="zero_gradient"), pr.P, pr.D))
+    P, D = WL.sample_bounded(WL.mirror_flow(1.0, 0.5, 1, 1), 30, 15, 1.0 / 30, 1, 1)
+    out.append((settings(dim=2, nx=30, ny=15, lx=1.0, mu=0.0, sides=["no_slip", "no_slip", "reflecting",
+                                                                     "reflecting"]), P, D))
+    P, D = WL.sample_bounded(WL.mirror_flow(1.0, 20 / 48, 1, 1), 48, 20, 1.0 / 48, 1, 1)
+    out.append((settings(dim=2, nx=48, ny=20, lx=1.0, sides=["reflecting", "zero_gradient", "zero_gradient",
+                                                             "reflecting"]), P, D))
+    v = WL.vortex(26, seed=5)
+    out.append((_settings(v), v.P, v.D))
+    pr = WL.riemann2d_bounded(67, seed=4)
+    out.append((settings(dim=2, nx=67, ny=67, lx=1.0, bc="zero_gradient"), pr.P, pr.D))
+    return out
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -122,3 +143,70 @@ def test_failure_in_stage_two_rolls_back(mode):
     assert ei.value.status == -4 and "step 1 stage 2" in str(ei.value), str(ei.value)
     assert np.array_equal(got[0], pr.P) and np.array_equal(got[1], pr.D)
     assert n == 1
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_bounded_members_match_single_problems_bitwise(mode):
+    """Members with zero-gradient, reflecting and no-slip sides (their dual
+    grids carry the boundary nodes) advance bit for bit like the same
+    problems alone; 18 steps, so that the graph mode replays a captured
+    graph and launches the remainder."""
+    from paper_2606_17772_amd import Problem
+    mem = _bounded_members()
+    B = _batch(None, mode, [m[0] for m in mem])
+    for k, (s, P, D) in enumerate(mem):
+        B.set_state_stacked(k, 0, P)
+        B.set_state_stacked(k, 1, D)
+    t, dt, n = B.step(nsteps=18, cfl=0.4)
+    assert n == 18
+    for k, (s, P, D) in enumerate(mem):
+        pb = Problem(gpu_params(s))
+        pb.set_state_stacked(0, P)
+        pb.set_state_stacked(1, D)
+        ts, ns = pb.step(nsteps=18, cfl=0.4)
+        assert ns == 18 and t[k] == ts, (k, t[k], ts)
+        for g in (0, 1):
+            assert np.array_equal(B.get_state_stacked(k, g), pb.get_state_stacked(g)), (k, g)
+
+
+def test_bounded_members_against_oracle():
+    """Zero-gradient Riemann and walled members against the oracle, two CFL
+    steps (bar: max(1e-12, 4 x the oracle's one-ulp sensitivity))."""
+    from oracle import oracle as O
+    mem = _bounded_members()
+    B = _batch(None, "graph", [m[0] for m in mem])
+    for k, (s, P, D) in enumerate(mem):
+        B.set_state_stacked(k, 0, P)
+        B.set_state_stacked(k, 1, D)
+    t, dt, n = B.step(nsteps=2, cfl=0.4)
+    for k, (s, P, D) in enumerate(mem):
+        par = oracle_par(O, s)
+        oP, oD, ot, ok = O.step2d(par, P, D, 2, cfl=0.4)
+        assert ok == 2 and abs(t[k] - ot) <= 1e-13 * ot
+        fl = floors_state(ref_scales([P, D], 1.4, s["lx"]))
+        sens = ulp_sensitivity(lambda A, C: O.step2d(par, A, C, 2, cfl=0.4)[:2], P, D, fl)
+        for g, o in ((B.get_state_stacked(k, 0), oP), (B.get_state_stacked(k, 1), oD)):
+            err, where = relerr(g, o, fl)
+            print(f"member {k} grid: gpu-oracle {err:.2e}, oracle 1-ulp sensitivity {sens:.2e}")
+            assert err <= max(TOL, 4 * sens), (k, where, err, sens)
+
+
+def test_graph_mode_replays_equal_separate_launches():
+    """40 steps (two captured 16-step graphs and 8 separate steps), then 16
+    more from the other parity, against the same steps launched separately;
+    every replay is checked after the program's own synchronising reads."""
+    sizes = [16, 37, 64, 23]
+    probs = _members(sizes, seed=11)
+    A = _batch(probs, "graph")
+    C = _batch(probs, "phased")
+    for m, p in enumerate(probs):
+        for B in (A, C):
+            B.set_state_stacked(m, 0, p.P)
+            B.set_state_stacked(m, 1, p.D)
+    for steps in (40, 16, 33):
+        ta, _, na = A.step(nsteps=steps, cfl=0.4)
+        tc, _, nc = C.step(nsteps=steps, cfl=0.4)
+        assert na == nc == steps and np.array_equal(ta, tc)
+        for m in range(len(probs)):
+            for g in (0, 1):
+                assert np.array_equal(A.get_state_stacked(m, g), C.get_state_stacked(m, g)), (steps, m, g)

@@ -168,14 +168,12 @@ def test_wall_nodes_hold_the_wall_condition(oracle):
         assert np.all(Dg[1:3, :, col] == 0.0) and np.all(Dg[9:11, :, col] == 0.0)
 
 
-def test_bounded_rejected_by_adjoint_and_batch():
-    from paper_2606_17772_amd import Batch, FdcgksError
+def test_bounded_rejected_by_adjoint():
+    from paper_2606_17772_amd import FdcgksError
     s, P, D = CASES["reflecting_x_70x37"]()
     pb = _problem(s, P, D)
     with pytest.raises(FdcgksError, match="periodic sides"):
         pb.step_vjp(0.001, np.zeros((2, 12) + P.shape[1:]))
-    with pytest.raises(FdcgksError, match="periodic only"):
-        Batch([gpu_params(s)])
 
 
 def test_full_size_sampled_walled(oracle):
