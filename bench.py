@@ -59,7 +59,7 @@ def parse():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the 1D periodic, 1D shock-tube and 512^2 vortex legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-per-problem comparison")
-    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-steps", type=int, default=32)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-vs-forward comparison")
     ap.add_argument("--tiles", default=DEFAULT_TILES,
                     help="launch shapes kernel=XxY,... (default: the autotuner's pick at 2048^2)")
@@ -219,26 +219,35 @@ BATCH_CFL = 0.4  # the four-quadrant Riemann members need CFL <= 0.4 (the paper'
 
 
 def batch_comparison(steps):
-    """64 independent 2D Euler problems (sides seeded in [64, 512]; vortex and
-    four-quadrant Riemann members, CFL 0.4) advanced by the batched launches
-    (one launch per phase, and one cooperative persistent launch per stage)
-    and by a loop over single problems on the same GPU."""
+    """64 independent 2D Euler problems (sides seeded in [64, 512]; vortex
+    members periodic, four-quadrant Riemann members with zero-gradient sides,
+    CFL 0.4) advanced by the batched launches (one launch per phase captured
+    as HIP graphs of 16 steps; the same launches uncaptured; one cooperative
+    persistent launch per stage) and by a loop over single problems (each
+    with its own captured step graphs) on the same GPU."""
     import torch
 
     import workloads as WL
     from paper_2606_17772_amd import Batch, Problem, make_params
-    probs = WL.batch_problems(64, 64, 512, seed=0)
-    prms = [make_params(dim=2, nx=p.nx, ny=p.ny, lx=p.lx, ly=p.ly) for p in probs]
-    nodes = sum(2 * p.nx * p.ny for p in probs)
-    out = {"members": len(probs), "nodes_per_stage": nodes, "steps": steps}
+    probs = WL.batch_problems(64, 64, 512, seed=0, bounded=True)
+    prms = [make_params(dim=2, nx=p.nx, ny=p.ny, lx=p.lx, ly=p.ly, bc=p.params.get("bc", "periodic"))
+            for p in probs]
+    bounded = [p.params.get("bc", "periodic") != "periodic" for p in probs]
+    nodes = sum(p.nx * p.ny + (p.nx + b) * (p.ny + b) for p, b in zip(probs, bounded))
+    out = {"members": len(probs), "zero_gradient_members": int(sum(bounded)), "nodes_per_stage": nodes,
+           "steps": steps}
     rates, states = {}, {}
-    for mode in ("phased", "persistent"):
+    for mode in ("graph", "phased", "persistent"):
         B = Batch(prms)
         B.set_mode(mode)
         for m, p in enumerate(probs):
             B.set_state_stacked(m, 0, p.P)
             B.set_state_stacked(m, 1, p.D)
         B.step(nsteps=1, cfl=BATCH_CFL)
+        B.step(nsteps=16, cfl=BATCH_CFL)  # captures the graphs (graph mode)
+        for m, p in enumerate(probs):
+            B.set_state_stacked(m, 0, p.P)
+            B.set_state_stacked(m, 1, p.D)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         B.step(nsteps=steps, cfl=BATCH_CFL)
@@ -251,7 +260,10 @@ def batch_comparison(steps):
         singles[m].set_state_stacked(0, p.P)
         singles[m].set_state_stacked(1, p.D)
     for pb in singles:
-        pb.step(nsteps=1, cfl=BATCH_CFL)
+        pb.step(nsteps=16, cfl=BATCH_CFL)  # captures each problem's step graphs
+    for m, p in enumerate(probs):
+        singles[m].set_state_stacked(0, p.P)
+        singles[m].set_state_stacked(1, p.D)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for pb in singles:
@@ -260,10 +272,11 @@ def batch_comparison(steps):
     loop = nodes * 2 * steps / (time.perf_counter() - t0)
     same = all(np.array_equal(states[md][q], singles[m].get_state_stacked(0))
                for md in states for q, m in enumerate((0, 1, 63)))
-    out.update({"phased_node_updates_per_s": rates["phased"],
+    out.update({"graph_node_updates_per_s": rates["graph"], "phased_node_updates_per_s": rates["phased"],
                 "persistent_node_updates_per_s": rates["persistent"],
                 "per_problem_loop_node_updates_per_s": loop,
-                "speedup_phased": rates["phased"] / loop, "speedup_persistent": rates["persistent"] / loop,
+                "speedup_graph": rates["graph"] / loop, "speedup_phased": rates["phased"] / loop,
+                "speedup_persistent": rates["persistent"] / loop,
                 "bitwise_equal_sampled_members": bool(same)})
     return out
 
@@ -406,7 +419,8 @@ ADJ_STEPS, ADJ_EVERY, ADJ_CFL = 50, 7, 0.25
 
 def adjoint_batch_gradient(count=64):
     """Gradient workload of the batched configuration: 64 members (sides
-    seeded in [64, 512]; vortex and four-quadrant Riemann data), each
+    seeded in [64, 512]; vortex and four-quadrant Riemann data, both
+    periodic here because the step adjoint covers periodic sides), each
     advanced 50 steps at a time step frozen from its initial state (CFL 0.25;
     a member whose frozen step goes non-physical is skipped and counted);
     J = 1/2 sum over members and primary nodes of (rho(T) - rho_target)^2 h^2,

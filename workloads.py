@@ -264,7 +264,8 @@ def riemann2d_bounded(n, seed=0, gamma=GAMMA):
     rng = np.random.default_rng(seed)
     q = [(rng.uniform(0.1, 1), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.1, 1)) for _ in range(4)]
     P, D = sample_bounded(quadrants(q, gamma=gamma), n, n, 1.0 / n, 1, 1, jumps=True)
-    return Problem2D("riemann2d_bounded", n, n, 0.0, 1.0, 0.0, 1.0, P, D, {"gamma": gamma, "mu": 0.0, "states": q})
+    return Problem2D("riemann2d_bounded", n, n, 0.0, 1.0, 0.0, 1.0, P, D,
+                     {"gamma": gamma, "mu": 0.0, "states": q, "bc": "zero_gradient"})
 
 
 def viscous_shock_tube(nx, gamma=GAMMA, mu=0.005, prandtl=0.72):
@@ -287,12 +288,16 @@ def batch_sizes(count=64, lo=64, hi=512, seed=0):
     return [int(v) for v in rng.integers(lo, hi + 1, size=count)]
 
 
-def batch_problems(count=64, lo=64, hi=512, seed=0):
+def batch_problems(count=64, lo=64, hi=512, seed=0, bounded=False):
     """Batched workload: even members isentropic vortices, odd members
-    four-quadrant Riemann problems, sides seeded in [lo, hi]."""
+    four-quadrant Riemann problems (periodic, or with zero-gradient sides and
+    the dual grid's boundary nodes when bounded), sides seeded in [lo, hi]."""
     out = []
     for b, n in enumerate(batch_sizes(count, lo, hi, seed)):
-        out.append(vortex(n, seed=seed * 1000 + b) if b % 2 == 0 else riemann2d(n, seed=seed * 1000 + b))
+        if b % 2 == 0:
+            out.append(vortex(n, seed=seed * 1000 + b))
+        else:
+            out.append((riemann2d_bounded if bounded else riemann2d)(n, seed=seed * 1000 + b))
     return out
 
 
