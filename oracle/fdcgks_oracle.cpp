@@ -34,8 +34,10 @@
 // the forward-mode (tangent) reference used to check the adjoint step.
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <vector>
 
@@ -96,6 +98,8 @@ struct Par {
   double gamma, mu, prandtl;
   double C, eps, eps_a, d_central, d_side;
   double tau_c1, tau_c2;
+  double z0, lz;             // 3D: z origin and length
+  int32_t nz, pad_;          // 3D: nodes per grid along z
 };
 enum { BC_PERIODIC = 0, BC_ZERO_GRADIENT = 1, BC_REFLECTING = 2, BC_NO_SLIP = 3 };
 enum { VAR_6_4 = 0, VAR_6_2 = 1, VAR_LINEAR = 2 };
@@ -197,18 +201,28 @@ T recon_node(const Par& p, const T Q[3], const T X[3], double h) {
 // --------------------------------------- characteristic variables, Sec. 3
 // Q = L W with L the left eigenvectors of the Euler flux Jacobian along the
 // line, in the line's local frame (normal momentum = component 1), at a
-// reference state.  R (columns: fields u-c, u [, shear], u+c) is the textbook
-// right-eigenvector matrix; L is obtained by inverting R (Gauss-Jordan with
-// partial pivoting), not from a closed form.
-template <class T> void char_basis(int dim, double gamma, const T* W, T R[4][4], T L[4][4]) {
+// reference state.  R (columns: fields u-c, u [, shears], u+c) is the
+// textbook right-eigenvector matrix; L is obtained by inverting R
+// (Gauss-Jordan with partial pivoting), not from a closed form.
+template <class T> void char_basis(int dim, double gamma, const T* W, T R[5][5], T L[5][5]) {
   const int n = dim + 2;
-  T rho = W[0], u = W[1] / rho, v = dim == 2 ? W[2] / rho : T(0.0), E = W[n - 1];
+  T rho = W[0], u = W[1] / rho, v = dim >= 2 ? W[2] / rho : T(0.0), w = dim == 3 ? W[3] / rho : T(0.0);
+  T E = W[n - 1];
   T q2 = u * u + v * v;
+  if (dim == 3) q2 = q2 + w * w;
   T pr = (gamma - 1.0) * (E - 0.5 * rho * q2);
   T c = sqrt(gamma * pr / rho), H = (E + pr) / rho;
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) R[a][b] = L[a][b] = T(0.0);
-  if (dim == 2) {
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b) R[a][b] = L[a][b] = T(0.0);
+  if (dim == 3) {
+    T cols[5][5] = {{T(1.0), u - c, v, w, H - u * c},
+                    {T(1.0), u, v, w, 0.5 * q2},
+                    {T(0.0), T(0.0), T(1.0), T(0.0), v},
+                    {T(0.0), T(0.0), T(0.0), T(1.0), w},
+                    {T(1.0), u + c, v, w, H + u * c}};
+    for (int k = 0; k < 5; ++k)
+      for (int a = 0; a < 5; ++a) R[a][k] = cols[k][a];
+  } else if (dim == 2) {
     T cols[4][4] = {{T(1.0), u - c, v, H - u * c},
                     {T(1.0), u, v, 0.5 * q2},
                     {T(0.0), T(0.0), T(1.0), v},
@@ -221,7 +235,7 @@ template <class T> void char_basis(int dim, double gamma, const T* W, T R[4][4],
       for (int a = 0; a < 3; ++a) R[a][k] = cols[k][a];
   }
   // L = R^-1
-  T A[4][8];
+  T A[5][10];
   for (int a = 0; a < n; ++a)
     for (int b = 0; b < 2 * n; ++b) A[a][b] = b < n ? R[a][b] : T(b - n == a ? 1.0 : 0.0);
   for (int col = 0; col < n; ++col) {
@@ -247,19 +261,19 @@ template <class T> void char_basis(int dim, double gamma, const T* W, T R[4][4],
 // smallest of the two acoustic fields' l and r path functions (ties: the
 // first of chi^l(u-c), chi^r(u-c), chi^l(u+c), chi^r(u+c)).
 template <class T>
-void recon_line(const Par& p, int dim, const T Q[4][4], const T X[4][4], double h, T vl[4], T dl[4], T vr[4],
-                T dr[4], T& chi) {
+void recon_line(const Par& p, int dim, const T Q[5][4], const T X[5][4], double h, T vl[5], T dl[5], T vr[5],
+                T dr[5], T& chi) {
   const int n = dim + 2;
   if (!p.recon_char) {
-    T cl[4], cr[4];
+    T cl[5], cr[5];
     for (int c = 0; c < n; ++c) recon_interface(p, Q[c], X[c], h, vl[c], dl[c], cl[c], vr[c], dr[c], cr[c]);
     chi = std::min(val(cl[0]), val(cr[0])) == val(cl[0]) ? cl[0] : cr[0];
     return;
   }
-  T Wref[4], R[4][4], L[4][4];
+  T Wref[5], R[5][5], L[5][5];
   for (int c = 0; c < n; ++c) Wref[c] = 0.5 * (Q[c][1] + Q[c][2]);
   char_basis(dim, p.gamma, Wref, R, L);
-  T cvl[4], cdl[4], ccl[4], cvr[4], cdr[4], ccr[4];
+  T cvl[5], cdl[5], ccl[5], cvr[5], cdr[5], ccr[5];
   for (int k = 0; k < n; ++k) {
     T q[4], x[4];
     for (int m = 0; m < 4; ++m) {
@@ -286,16 +300,16 @@ void recon_line(const Par& p, int dim, const T Q[4][4], const T X[4][4], double 
 
 // Node derivative of all n components along one line (local frame): on
 // characteristic variables the eigenvectors are taken at the node's state.
-template <class T> void recon_node_line(const Par& p, int dim, const T Q[4][3], const T X[4][3], double h, T d[4]) {
+template <class T> void recon_node_line(const Par& p, int dim, const T Q[5][3], const T X[5][3], double h, T d[5]) {
   const int n = dim + 2;
   if (!p.recon_char) {
     for (int c = 0; c < n; ++c) d[c] = recon_node(p, Q[c], X[c], h);
     return;
   }
-  T Wref[4], R[4][4], L[4][4];
+  T Wref[5], R[5][5], L[5][5];
   for (int c = 0; c < n; ++c) Wref[c] = Q[c][1];
   char_basis(dim, p.gamma, Wref, R, L);
-  T cd[4];
+  T cd[5];
   for (int k = 0; k < n; ++k) {
     T q[3], x[3];
     for (int m = 0; m < 3; ++m) {
@@ -312,42 +326,47 @@ template <class T> void recon_node_line(const Par& p, int dim, const T Q[4][3], 
 }
 
 // ----------------------------------------------- Maxwellian moments, App. A
-// Polynomials in (u, v, xi^2): sum of k * u^a v^b (xi^2)^c.
+// Polynomials in (u, v, w, xi^2): sum of k * u^a v^b w^e (xi^2)^c.
 template <class T> struct Poly {
+  static constexpr int CAP = 256;
   int n = 0;
-  int a[96], b[96], c[96];
-  T k[96];
-  void add(int aa, int bb, int cc, T kk) {
+  int a[CAP], b[CAP], c[CAP], e[CAP];
+  T k[CAP];
+  void add(int aa, int bb, int cc, T kk, int ee = 0) {
     for (int i = 0; i < n; ++i)
-      if (a[i] == aa && b[i] == bb && c[i] == cc) { k[i] = k[i] + kk; return; }
-    a[n] = aa; b[n] = bb; c[n] = cc; k[n] = kk; ++n;
+      if (a[i] == aa && b[i] == bb && c[i] == cc && e[i] == ee) { k[i] = k[i] + kk; return; }
+    if (n == CAP) std::abort();
+    a[n] = aa; b[n] = bb; c[n] = cc; e[n] = ee; k[n] = kk; ++n;
   }
 };
 template <class T> Poly<T> pmul(const Poly<T>& P, const Poly<T>& Q) {
   Poly<T> R;
   for (int i = 0; i < P.n; ++i)
-    for (int j = 0; j < Q.n; ++j) R.add(P.a[i] + Q.a[j], P.b[i] + Q.b[j], P.c[i] + Q.c[j], P.k[i] * Q.k[j]);
+    for (int j = 0; j < Q.n; ++j)
+      R.add(P.a[i] + Q.a[j], P.b[i] + Q.b[j], P.c[i] + Q.c[j], P.k[i] * Q.k[j], P.e[i] + Q.e[j]);
   return R;
 }
 template <class T> Poly<T> padd(const Poly<T>& P, const Poly<T>& Q, T sq_ = T(1.0)) {
   Poly<T> R = P;
-  for (int j = 0; j < Q.n; ++j) R.add(Q.a[j], Q.b[j], Q.c[j], sq_ * Q.k[j]);
+  for (int j = 0; j < Q.n; ++j) R.add(Q.a[j], Q.b[j], Q.c[j], sq_ * Q.k[j], Q.e[j]);
   return R;
 }
 template <class T> Poly<T> pconst(T k) { Poly<T> R; R.add(0, 0, 0, k); return R; }
-template <class T> Poly<T> pmono(int a, int b, int c, T k) { Poly<T> R; R.add(a, b, c, k); return R; }
+template <class T> Poly<T> pmono(int a, int b, int c, T k, int e = 0) { Poly<T> R; R.add(a, b, c, k, e); return R; }
 
 // Collision invariants psi (App. A1): 2D (1, u, v, (u^2+v^2+xi^2)/2);
-// 1D (1, u, (u^2+xi^2)/2).
+// 1D (1, u, (u^2+xi^2)/2); 3D (1, u, v, w, (u^2+v^2+w^2+xi^2)/2).
 template <class T> Poly<T> ppsi(int i, int dim) {
   Poly<T> R;
   int last = dim + 1;
   if (i == 0) R.add(0, 0, 0, T(1.0));
   else if (i == 1) R.add(1, 0, 0, T(1.0));
-  else if (i == 2 && dim == 2) R.add(0, 1, 0, T(1.0));
+  else if (i == 2 && dim >= 2) R.add(0, 1, 0, T(1.0));
+  else if (i == 3 && dim == 3) R.add(0, 0, 0, T(1.0), 1);
   else if (i == last) {
     R.add(2, 0, 0, T(0.5));
-    if (dim == 2) R.add(0, 2, 0, T(0.5));
+    if (dim >= 2) R.add(0, 2, 0, T(0.5));
+    if (dim == 3) R.add(0, 0, 0, T(0.5), 2);
     R.add(0, 0, 1, T(0.5));
   }
   return R;
@@ -360,11 +379,11 @@ template <class T> Poly<T> pslope(const T* s, int dim) {
 }
 
 // Normalised moments of a Maxwellian (per unit density): <u^n> over the full
-// line or a half line, <v^n> over the full line, <xi^(2k)>.
+// line or a half line, <v^n> and (3D) <w^n> over the full line, <xi^(2k)>.
 template <class T> struct Maxw {
-  T mu[10], mv[10], mx[3];
+  T mu[10], mv[10], mw[10], mx[3];
 };
-template <class T> Maxw<T> maxwell(T U, T V, T lam, double K, int half, int dim) {
+template <class T> Maxw<T> maxwell(T U, T V, T lam, double K, int half, int dim, T Wv = T(0.0)) {
   Maxw<T> m;
   T sl = sqrt(lam);
   if (half == 0) {
@@ -377,9 +396,13 @@ template <class T> Maxw<T> maxwell(T U, T V, T lam, double K, int half, int dim)
   }
   for (int k = 0; k + 2 < 10; ++k) m.mu[k + 2] = U * m.mu[k + 1] + (k + 1) / (2.0 * lam) * m.mu[k];
   m.mv[0] = 1.0;
-  m.mv[1] = (dim == 2) ? V : T(0.0);
+  m.mv[1] = (dim >= 2) ? V : T(0.0);
   for (int k = 0; k + 2 < 10; ++k) m.mv[k + 2] = m.mv[1] * m.mv[k + 1] + (k + 1) / (2.0 * lam) * m.mv[k];
   if (dim == 1) for (int k = 1; k < 10; ++k) m.mv[k] = 0.0;  // no v in 1D: only b = 0 occurs
+  m.mw[0] = 1.0;
+  m.mw[1] = (dim == 3) ? Wv : T(0.0);
+  for (int k = 0; k + 2 < 10; ++k) m.mw[k + 2] = m.mw[1] * m.mw[k + 1] + (k + 1) / (2.0 * lam) * m.mw[k];
+  if (dim < 3) for (int k = 1; k < 10; ++k) m.mw[k] = 0.0;  // no w below 3D: only e = 0 occurs
   m.mx[0] = 1.0;
   m.mx[1] = K / (2.0 * lam);
   m.mx[2] = K * (K + 2.0) / (4.0 * lam * lam);
@@ -387,23 +410,25 @@ template <class T> Maxw<T> maxwell(T U, T V, T lam, double K, int half, int dim)
 }
 template <class T> T avg(const Maxw<T>& m, const Poly<T>& P) {
   T s = 0.0;
-  for (int i = 0; i < P.n; ++i) s = s + P.k[i] * m.mu[P.a[i]] * m.mv[P.b[i]] * m.mx[P.c[i]];
+  for (int i = 0; i < P.n; ++i) s = s + P.k[i] * m.mu[P.a[i]] * m.mv[P.b[i]] * m.mw[P.e[i]] * m.mx[P.c[i]];
   return s;
 }
 
-// Internal degrees of freedom from gamma (D22).
+// Internal degrees of freedom from gamma (D22): K + dim = 2 / (gamma - 1).
 inline double kdof(double gamma, int dim) {
+  if (dim == 3) return (5.0 - 3.0 * gamma) / (gamma - 1.0);
   return dim == 2 ? (4.0 - 2.0 * gamma) / (gamma - 1.0) : (3.0 - gamma) / (gamma - 1.0);
 }
 
-template <class T> struct Prim { T rho, U, V, p, lam; };
+template <class T> struct Prim { T rho, U, V, Wv, p, lam; };
 template <class T> Prim<T> prim(const T* W, int dim, double gamma) {
   Prim<T> s;
   s.rho = W[0];
   s.U = W[1] / W[0];
-  s.V = dim == 2 ? W[2] / W[0] : T(0.0);
+  s.V = dim >= 2 ? W[2] / W[0] : T(0.0);
+  s.Wv = dim == 3 ? W[3] / W[0] : T(0.0);
   T rE = W[dim + 1];
-  s.p = (gamma - 1.0) * (rE - 0.5 * s.rho * (s.U * s.U + s.V * s.V));
+  s.p = (gamma - 1.0) * (rE - 0.5 * s.rho * (s.U * s.U + s.V * s.V + s.Wv * s.Wv));
   s.lam = s.rho / (2.0 * s.p);
   return s;
 }
@@ -412,7 +437,7 @@ template <class T> Prim<T> prim(const T* W, int dim, double gamma) {
 // (App. A; Xu's BGK-NS scheme), by Gaussian elimination with partial pivoting.
 template <class T> void slope(const Maxw<T>& full, T rho, const T* D, int dim, T* s) {
   int n = dim + 2;
-  T A[4][5];
+  T A[5][6];
   for (int i = 0; i < n; ++i) {
     for (int k = 0; k < n; ++k) A[i][k] = avg(full, pmul(ppsi<T>(i, dim), ppsi<T>(k, dim)));
     A[i][n] = D[i] / rho;
@@ -435,13 +460,14 @@ template <class T> void slope(const Maxw<T>& full, T rho, const T* D, int dim, T
 }
 
 // ------------------------------------------- gas-kinetic interface solver
-// One interface in its local frame: the normal velocity is u; in 2D the
-// tangential velocity is v.  Inputs: reconstructed left/right states, their
-// normal slopes, the tangential slope (2D), the step dt.  App. A1-A2 and the
+// One interface in its local frame: the normal velocity is u; the tangential
+// velocities are v (2D, 3D) and w (3D).  Inputs: reconstructed left/right
+// states, their normal slopes, the tangential slopes along the v axis (Wt,
+// 2D and 3D) and the w axis (Wt2, 3D), the step dt.  App. A1-A2 and the
 // BGK-NS solution it cites, with decisions D10-D14, D21.
 template <class T> struct GksOut {
-  T F[4], Ft[4], We[4], Wet[4], Wl[4], Wr[4], Wlt[4], Wrt[4];
-  T W0[4];  // compatibility state
+  T F[5], Ft[5], We[5], Wet[5], Wl[5], Wr[5], Wlt[5], Wrt[5];
+  T W0[5];  // compatibility state
   T tau;
 };
 
@@ -464,42 +490,49 @@ template <class T> struct Term { int state; int k; Poly<T> P; };
 
 template <class T>
 void gks_interface(const Par& p, int dim, const T* WL, const T* WR, const T* WnL, const T* WnR,
-                   const T* Wt, double dt, GksOut<T>& o) {
+                   const T* Wt, double dt, GksOut<T>& o, const T* Wt2 = nullptr) {
   const int n = dim + 2;
   const double g = p.gamma, K = kdof(g, dim);
   Prim<T> sl = prim(WL, dim, g), sr = prim(WR, dim, g);
-  Maxw<T> mlh = maxwell(sl.U, sl.V, sl.lam, K, +1, dim), mlf = maxwell(sl.U, sl.V, sl.lam, K, 0, dim);
-  Maxw<T> mrh = maxwell(sr.U, sr.V, sr.lam, K, -1, dim), mrf = maxwell(sr.U, sr.V, sr.lam, K, 0, dim);
+  Maxw<T> mlh = maxwell(sl.U, sl.V, sl.lam, K, +1, dim, sl.Wv), mlf = maxwell(sl.U, sl.V, sl.lam, K, 0, dim, sl.Wv);
+  Maxw<T> mrh = maxwell(sr.U, sr.V, sr.lam, K, -1, dim, sr.Wv), mrf = maxwell(sr.U, sr.V, sr.lam, K, 0, dim, sr.Wv);
   // compatibility (equilibrium) state at the interface
-  T W0[4];
+  T W0[5];
   for (int i = 0; i < n; ++i)
     W0[i] = sl.rho * avg(mlh, ppsi<T>(i, dim)) + sr.rho * avg(mrh, ppsi<T>(i, dim));
   for (int i = 0; i < n; ++i) o.W0[i] = W0[i];
   Prim<T> s0 = prim(W0, dim, g);
-  Maxw<T> m0 = maxwell(s0.U, s0.V, s0.lam, K, 0, dim);
-  // spatial micro slopes (normal a, tangential b); D12 for the equilibrium
-  T zero[4] = {0, 0, 0, 0};
-  T aL[4], aR[4], bL[4] = {0, 0, 0, 0}, bR[4] = {0, 0, 0, 0}, a0[4], b0[4] = {0, 0, 0, 0};
+  Maxw<T> m0 = maxwell(s0.U, s0.V, s0.lam, K, 0, dim, s0.Wv);
+  // spatial micro slopes (normal a, tangential b and c); D12 for the
+  // equilibrium
+  T aL[5], aR[5], a0[5];
+  T bL[5] = {0, 0, 0, 0, 0}, bR[5] = {0, 0, 0, 0, 0}, b0[5] = {0, 0, 0, 0, 0};
+  T cL[5] = {0, 0, 0, 0, 0}, cR[5] = {0, 0, 0, 0, 0}, c0[5] = {0, 0, 0, 0, 0};
   slope(mlf, sl.rho, WnL, dim, aL);
   slope(mrf, sr.rho, WnR, dim, aR);
-  T Wn0[4];
+  T Wn0[5];
   for (int i = 0; i < n; ++i) Wn0[i] = 0.5 * (WnL[i] + WnR[i]);
   slope(m0, s0.rho, Wn0, dim, a0);
-  if (dim == 2) {
+  if (dim >= 2) {
     slope(mlf, sl.rho, Wt, dim, bL);
     slope(mrf, sr.rho, Wt, dim, bR);
     slope(m0, s0.rho, Wt, dim, b0);
   }
-  (void)zero;
-  Poly<T> u1 = pmono<T>(1, 0, 0, 1.0), v1 = pmono<T>(0, 1, 0, 1.0);
-  auto transport = [&](const T* a, const T* b) {  // (a.psi) u + (b.psi) v
+  if (dim == 3) {
+    slope(mlf, sl.rho, Wt2, dim, cL);
+    slope(mrf, sr.rho, Wt2, dim, cR);
+    slope(m0, s0.rho, Wt2, dim, c0);
+  }
+  Poly<T> u1 = pmono<T>(1, 0, 0, 1.0), v1 = pmono<T>(0, 1, 0, 1.0), w1 = pmono<T>(0, 0, 0, 1.0, 1);
+  auto transport = [&](const T* a, const T* b, const T* c) {  // (a.psi) u + (b.psi) v + (c.psi) w
     Poly<T> P = pmul(pslope(a, dim), u1);
-    if (dim == 2) P = padd(P, pmul(pslope(b, dim), v1));
+    if (dim >= 2) P = padd(P, pmul(pslope(b, dim), v1));
+    if (dim == 3) P = padd(P, pmul(pslope(c, dim), w1));
     return P;
   };
-  Poly<T> trL = transport(aL, bL), trR = transport(aR, bR), tr0 = transport(a0, b0);
-  // time slopes from compatibility: <psi (A.psi)> = -<psi ((a.psi)u + (b.psi)v)>
-  T AL[4], AR[4], A0[4], rhsL[4], rhsR[4], rhs0[4];
+  Poly<T> trL = transport(aL, bL, cL), trR = transport(aR, bR, cR), tr0 = transport(a0, b0, c0);
+  // time slopes from compatibility: <psi (A.psi)> = -<psi (transport)>
+  T AL[5], AR[5], A0[5], rhsL[5], rhsR[5], rhs0[5];
   for (int i = 0; i < n; ++i) {
     rhsL[i] = -sl.rho * avg(mlf, pmul(ppsi<T>(i, dim), trL));
     rhsR[i] = -sr.rho * avg(mrf, pmul(ppsi<T>(i, dim), trR));
@@ -544,10 +577,12 @@ void gks_interface(const Par& p, int dim, const T* WL, const T* WR, const T* WnL
     o.Wet[i] = moment(psi, ct);
   }
   // Prandtl-number fix of the energy flux (D21): (1/Pr - 1) times the heat
-  // flux 1/2 <(u-U0)((u-U0)^2 + (v-V0)^2 + xi^2)> of the same distribution.
+  // flux 1/2 <(u-U0)((u-U0)^2 + (v-V0)^2 + (w-W0)^2 + xi^2)> of the same
+  // distribution.
   if (p.mu > 0) {
     Poly<T> du = padd(u1, pconst<T>(-s0.U)), c2 = pmul(du, du);
-    if (dim == 2) { Poly<T> dv = padd(v1, pconst<T>(-s0.V)); c2 = padd(c2, pmul(dv, dv)); }
+    if (dim >= 2) { Poly<T> dv = padd(v1, pconst<T>(-s0.V)); c2 = padd(c2, pmul(dv, dv)); }
+    if (dim == 3) { Poly<T> dw = padd(w1, pconst<T>(-s0.Wv)); c2 = padd(c2, pmul(dw, dw)); }
     c2 = padd(c2, pmono<T>(0, 0, 1, 1.0));
     Poly<T> hq = pmul(pmul(du, c2), pconst<T>(0.5));
     double f = 1.0 / p.prandtl - 1.0;
@@ -567,20 +602,24 @@ void gks_interface(const Par& p, int dim, const T* WL, const T* WR, const T* WnL
 }
 
 // Smooth nodal flux (Sec. 2.1: smooth nodal values; D11: tau_N = mu/p):
-// f^n = g [1 - tau_N ((a.psi)u + (b.psi)v + A.psi)], f_t^n = (A.psi) g.
-// Outputs the x- (and in 2D y-) flux and their time derivatives.
+// f^n = g [1 - tau_N ((a.psi)u + (b.psi)v + (c.psi)w + A.psi)],
+// f_t^n = (A.psi) g.  Outputs the x- (2D, 3D: y-; 3D: z-) flux and their time
+// derivatives.
 template <class T>
-void gks_node(const Par& p, int dim, const T* W, const T* Wx, const T* Wy, T* F, T* Ft, T* G, T* Gt) {
+void gks_node(const Par& p, int dim, const T* W, const T* Wx, const T* Wy, T* F, T* Ft, T* G, T* Gt,
+              const T* Wz = nullptr, T* H = nullptr, T* Ht = nullptr) {
   const int n = dim + 2;
   const double g = p.gamma, K = kdof(g, dim);
   Prim<T> s = prim(W, dim, g);
-  Maxw<T> m = maxwell(s.U, s.V, s.lam, K, 0, dim);
-  T a[4], b[4] = {0, 0, 0, 0}, A[4], rhs[4];
+  Maxw<T> m = maxwell(s.U, s.V, s.lam, K, 0, dim, s.Wv);
+  T a[5], b[5] = {0, 0, 0, 0, 0}, c[5] = {0, 0, 0, 0, 0}, A[5], rhs[5];
   slope(m, s.rho, Wx, dim, a);
-  if (dim == 2) slope(m, s.rho, Wy, dim, b);
-  Poly<T> u1 = pmono<T>(1, 0, 0, 1.0), v1 = pmono<T>(0, 1, 0, 1.0);
+  if (dim >= 2) slope(m, s.rho, Wy, dim, b);
+  if (dim == 3) slope(m, s.rho, Wz, dim, c);
+  Poly<T> u1 = pmono<T>(1, 0, 0, 1.0), v1 = pmono<T>(0, 1, 0, 1.0), w1 = pmono<T>(0, 0, 0, 1.0, 1);
   Poly<T> tr = pmul(pslope(a, dim), u1);
-  if (dim == 2) tr = padd(tr, pmul(pslope(b, dim), v1));
+  if (dim >= 2) tr = padd(tr, pmul(pslope(b, dim), v1));
+  if (dim == 3) tr = padd(tr, pmul(pslope(c, dim), w1));
   for (int i = 0; i < n; ++i) rhs[i] = -s.rho * avg(m, pmul(ppsi<T>(i, dim), tr));
   slope(m, s.rho, rhs, dim, A);
   T tauN = p.mu > 0 ? T(p.mu) / s.p : T(0.0);
@@ -590,24 +629,34 @@ void gks_node(const Par& p, int dim, const T* W, const T* Wx, const T* Wy, T* F,
     Poly<T> psi = ppsi<T>(i, dim);
     F[i] = s.rho * avg(m, pmul(pmul(u1, psi), fn));
     Ft[i] = s.rho * avg(m, pmul(pmul(u1, psi), ft));
-    if (dim == 2) {
+    if (dim >= 2) {
       G[i] = s.rho * avg(m, pmul(pmul(v1, psi), fn));
       Gt[i] = s.rho * avg(m, pmul(pmul(v1, psi), ft));
+    }
+    if (dim == 3) {
+      H[i] = s.rho * avg(m, pmul(pmul(w1, psi), fn));
+      Ht[i] = s.rho * avg(m, pmul(pmul(w1, psi), ft));
     }
   }
   if (p.mu > 0) {  // Prandtl fix (D21) with the node's own velocity
     double f = 1.0 / p.prandtl - 1.0;
-    Poly<T> du = padd(u1, pconst<T>(-s.U)), dv = padd(v1, pconst<T>(-s.V));
+    Poly<T> du = padd(u1, pconst<T>(-s.U)), dv = padd(v1, pconst<T>(-s.V)), dw = padd(w1, pconst<T>(-s.Wv));
     Poly<T> c2 = pmul(du, du);
-    if (dim == 2) c2 = padd(c2, pmul(dv, dv));
+    if (dim >= 2) c2 = padd(c2, pmul(dv, dv));
+    if (dim == 3) c2 = padd(c2, pmul(dw, dw));
     c2 = padd(c2, pmono<T>(0, 0, 1, 1.0));
     Poly<T> qx = pmul(pmul(du, c2), pconst<T>(0.5));
     F[n - 1] = F[n - 1] + f * s.rho * avg(m, pmul(qx, fn));
     Ft[n - 1] = Ft[n - 1] + f * s.rho * avg(m, pmul(qx, ft));
-    if (dim == 2) {
+    if (dim >= 2) {
       Poly<T> qy = pmul(pmul(dv, c2), pconst<T>(0.5));
       G[n - 1] = G[n - 1] + f * s.rho * avg(m, pmul(qy, fn));
       Gt[n - 1] = Gt[n - 1] + f * s.rho * avg(m, pmul(qy, ft));
+    }
+    if (dim == 3) {
+      Poly<T> qz = pmul(pmul(dw, c2), pconst<T>(0.5));
+      H[n - 1] = H[n - 1] + f * s.rho * avg(m, pmul(qz, fn));
+      Ht[n - 1] = Ht[n - 1] + f * s.rho * avg(m, pmul(qz, ft));
     }
   }
 }
@@ -712,7 +761,7 @@ template <class T> EdgeRes<T> edge2d(const Par& p, const Grid2<T>& G, int I, int
   for (int ax = 0; ax < 2; ++ax) {
     int perm[4] = {0, 1, 2, 3};
     if (ax == 1) { perm[1] = 2; perm[2] = 1; }
-    T Q[4][4], X[4][4], vl[4], dl[4], vr[4], dr[4];
+    T Q[5][4], X[5][4], vl[5], dl[5], vr[5], dr[5];
     for (int c = 0; c < 4; ++c)
       for (int m = 0; m < 4; ++m) {
         int o = 2 * m - 3;
@@ -774,7 +823,7 @@ template <class T> NodeRes<T> node2d(const Par& p, const Grid2<T>& G, int I, int
   for (int ax = 0; ax < 2; ++ax) {
     int perm[4] = {0, 1, 2, 3};
     if (ax == 1) { perm[1] = 2; perm[2] = 1; }
-    T Q[4][3], X[4][3], d[4];
+    T Q[5][3], X[5][3], d[5];
     for (int c = 0; c < 4; ++c)
       for (int m = 0; m < 3; ++m) {
         int Ii = ax == 0 ? I + 2 * m - 2 : I, Jj = ax == 0 ? J : J + 2 * m - 2;
@@ -950,7 +999,7 @@ void stage2d(const Par& p, int stage, double dt, const T* P, const T* D, const T
   if (keep) *keep = std::move(S);
 }
 
-// CFL time step (Sec. 5, D20): dt = CFL h / max(max(|U|,|V|) + c); with
+// CFL time step (Sec. 5, D20): dt = CFL h / max(max(|U|,|V|[,|W|]) + c); with
 // viscosity also dt <= CFL h^2 / (8 nu_max), nu_max = mu / rho_min.
 inline double dt_from(const Par& p, double smax, double rmin, double h, double cfl) {
   double dt = cfl * h / smax;
@@ -959,14 +1008,302 @@ inline double dt_from(const Par& p, double smax, double rmin, double h, double c
 }
 inline void speed_scan(const Par& p, int dim, const double* W, long plane, long n, double& smax, double& rmin) {
   for (long k = 0; k < n; ++k) {
-    double w[4];
+    double w[5];
     for (int c = 0; c < dim + 2; ++c) w[c] = W[c * plane + k];
     Prim<double> s = prim(w, dim, p.gamma);
     double cs = std::sqrt(p.gamma * s.p / s.rho);
-    double vmax = dim == 2 ? std::max(std::fabs(s.U), std::fabs(s.V)) : std::fabs(s.U);
+    double vmax = dim >= 2 ? std::max(std::fabs(s.U), std::fabs(s.V)) : std::fabs(s.U);
+    if (dim == 3) vmax = std::max(vmax, std::fabs(s.Wv));
     smax = std::max(smax, vmax + cs);
     rmin = std::min(rmin, s.rho);
   }
+}
+
+// ================================================================ 3D grids
+// The dual-grid layout of Sec. 4 carried to three dimensions (the paper
+// calls the extension straightforward and gives no grid; reading D32).  On
+// the half-spacing lattice, point (I, J, L) sits at (x0 + I h/2, y0 + J h/2,
+// z0 + L h/2).  Points with zero or two even coordinates are nodes of four
+// grids: primary P (odd, odd, odd) and the three face-offset duals
+// Dxy (even, even, odd), Dxz (even, odd, even), Dyz (odd, even, even).
+// Points with one or three even coordinates are virtual interfaces.  One
+// lattice step along any axis from a node reaches an interface point and two
+// steps reach a node of the same grid, so the line stencils are the 2D ones
+// ("-3,-1,+1,+3" at an interface, "-2,0,+2" at a node).  Every interface
+// point lies on three lines, one per axis, each of a different grid, and
+// hosts one solve per axis; the tangential slopes of a solve come from the
+// other two lines through the same point (Sec. 4 item 1(b), D30).
+// Periodic along all three axes.  State: 20 planes of nz*ny*nx doubles per
+// grid, fields W[0..4], Wx, Wy, Wz (5 components each), x fastest; stored
+// node i along an axis sits at lattice coordinate 2i+1 where the grid's
+// coordinate is odd and 2i+2 where it is even.
+inline int grid3_of(int I, int J, int L) {  // 0 P, 1 Dxy, 2 Dxz, 3 Dyz, -1 interface point
+  const bool ex = !(I & 1), ey = !(J & 1), ez = !(L & 1);
+  if (!ex && !ey && !ez) return 0;
+  if (ex && ey && !ez) return 1;
+  if (ex && !ey && ez) return 2;
+  if (!ex && ey && ez) return 3;
+  return -1;
+}
+// Interface-point classes: 0 (even, odd, odd), 1 (odd, even, odd),
+// 2 (odd, odd, even), 3 (even, even, even).
+inline int iface3_of(int I, int J, int L) {
+  const bool ex = !(I & 1), ey = !(J & 1), ez = !(L & 1);
+  if (ex && ey && ez) return 3;
+  if (ex && !ey && !ez) return 0;
+  if (!ex && ey && !ez) return 1;
+  if (!ex && !ey && ez) return 2;
+  return -1;
+}
+
+template <class T> struct Grid3 {
+  int nx, ny, nz;
+  const T* S[4];
+  Grid3(const Par& p, const T* const* S_) : nx(p.nx), ny(p.ny), nz(p.nz) {
+    for (int g = 0; g < 4; ++g) S[g] = S_[g];
+  }
+  long pl() const { return (long)nx * ny * nz; }
+  static int md(int a, int m) { return ((a % m) + m) % m; }
+  static int store(int X, int n) { return (X & 1) ? md((X - 1) / 2, n) : md(X / 2 - 1, n); }
+  T get(int I, int J, int L, int f, int c) const {
+    const int g = grid3_of(I, J, L);
+    const long k = ((long)store(L, nz) * ny + store(J, ny)) * nx + store(I, nx);
+    return S[g][(5 * f + c) * pl() + k];
+  }
+};
+
+// Local frame of a line along axis ax: the momentum along the line becomes
+// component 1 (swap of components 1 and 1 + ax); the tangential velocities v
+// and w are then those of the axes perm[2] - 1 and perm[3] - 1.
+inline void perm3(int ax, int perm[5]) {
+  for (int c = 0; c < 5; ++c) perm[c] = c;
+  perm[1] = 1 + ax;
+  perm[1 + ax] = 1;
+}
+
+// What one interface point gives, per normal axis (0: x, 1: y, 2: z).
+template <class T> struct EdgeRes3 {
+  T F[3][5], Ft[3][5], chi[3];
+  T Wtl[3][5], Wtr[3][5], Wtlt[3][5], Wtrt[3][5];  // blended interface values (D33)
+};
+
+template <class T> EdgeRes3<T> edge3d(const Par& p, const Grid3<T>& G, int I, int J, int L, double h, double dt) {
+  EdgeRes3<T> E;
+  // the three line reconstructions through the point (local frames)
+  T Wl[3][5], Wr[3][5], Dl[3][5], Dr[3][5], chi_line[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    int perm[5];
+    perm3(ax, perm);
+    T Q[5][4], X[5][4], vl[5], dl[5], vr[5], dr[5];
+    for (int c = 0; c < 5; ++c)
+      for (int m = 0; m < 4; ++m) {
+        const int o = 2 * m - 3;
+        const int Ii = I + (ax == 0 ? o : 0), Jj = J + (ax == 1 ? o : 0), Ll = L + (ax == 2 ? o : 0);
+        Q[c][m] = G.get(Ii, Jj, Ll, 0, perm[c]);
+        X[c][m] = G.get(Ii, Jj, Ll, 1 + ax, perm[c]);
+      }
+    recon_line(p, 3, Q, X, h, vl, dl, vr, dr, chi_line[ax]);
+    for (int c = 0; c < 5; ++c) {
+      Wl[ax][perm[c]] = vl[c]; Dl[ax][perm[c]] = dl[c];
+      Wr[ax][perm[c]] = vr[c]; Dr[ax][perm[c]] = dr[c];
+    }
+  }
+  // tangential slopes along each axis: the mean of that line's l/r derivatives
+  T Wt[3][5];
+  for (int ax = 0; ax < 3; ++ax)
+    for (int c = 0; c < 5; ++c) Wt[ax][c] = 0.5 * (Dl[ax][c] + Dr[ax][c]);
+  GksOut<T> o[3];
+  for (int ax = 0; ax < 3; ++ax) {
+    int perm[5];
+    perm3(ax, perm);
+    const int av = perm[2] - 1, aw = perm[3] - 1;  // axes of the local v and w
+    T Lq[5], Rq[5], nL[5], nR[5], tv[5], tw[5];
+    for (int c = 0; c < 5; ++c) {
+      Lq[c] = Wl[ax][perm[c]]; Rq[c] = Wr[ax][perm[c]];
+      nL[c] = Dl[ax][perm[c]]; nR[c] = Dr[ax][perm[c]];
+      tv[c] = Wt[av][perm[c]]; tw[c] = Wt[aw][perm[c]];
+    }
+    GksOut<T> loc;
+    gks_interface(p, 3, Lq, Rq, nL, nR, tv, dt, loc, tw);
+    for (int c = 0; c < 5; ++c) {
+      const int q = perm[c];
+      o[ax].F[q] = loc.F[c]; o[ax].Ft[q] = loc.Ft[c];
+      o[ax].Wl[q] = loc.Wl[c]; o[ax].Wr[q] = loc.Wr[c];
+      o[ax].Wlt[q] = loc.Wlt[c]; o[ax].Wrt[q] = loc.Wrt[c];
+    }
+    E.chi[ax] = chi_line[ax];
+  }
+  // D33: each direction carries weight 1/3, the normal one with its own side,
+  // the two tangential ones with the mean of their l and r values.
+  for (int ax = 0; ax < 3; ++ax)
+    for (int c = 0; c < 5; ++c) {
+      T s = T(0.0), st = T(0.0);
+      for (int b = 0; b < 3; ++b)
+        if (b != ax) { s = s + (o[b].Wl[c] + o[b].Wr[c]); st = st + (o[b].Wlt[c] + o[b].Wrt[c]); }
+      E.F[ax][c] = o[ax].F[c];
+      E.Ft[ax][c] = o[ax].Ft[c];
+      E.Wtl[ax][c] = o[ax].Wl[c] / 3.0 + s / 6.0;
+      E.Wtr[ax][c] = o[ax].Wr[c] / 3.0 + s / 6.0;
+      E.Wtlt[ax][c] = o[ax].Wlt[c] / 3.0 + st / 6.0;
+      E.Wtrt[ax][c] = o[ax].Wrt[c] / 3.0 + st / 6.0;
+    }
+  return E;
+}
+
+// Nodal fluxes at a node: 3-point derivative reconstructions along x, y and
+// z (Sec. 4 item 2, App. C3), then the smooth nodal GKS.
+template <class T> struct NodeRes3 { T F[3][5], Ft[3][5]; };  // per axis: x-, y-, z-flux
+template <class T> NodeRes3<T> node3d(const Par& p, const Grid3<T>& G, int I, int J, int L, double h) {
+  T W[5], D[3][5];
+  for (int ax = 0; ax < 3; ++ax) {
+    int perm[5];
+    perm3(ax, perm);
+    T Q[5][3], X[5][3], d[5];
+    for (int c = 0; c < 5; ++c)
+      for (int m = 0; m < 3; ++m) {
+        const int o = 2 * m - 2;
+        const int Ii = I + (ax == 0 ? o : 0), Jj = J + (ax == 1 ? o : 0), Ll = L + (ax == 2 ? o : 0);
+        Q[c][m] = G.get(Ii, Jj, Ll, 0, perm[c]);
+        X[c][m] = G.get(Ii, Jj, Ll, 1 + ax, perm[c]);
+      }
+    recon_node_line(p, 3, Q, X, h, d);
+    for (int c = 0; c < 5; ++c) D[ax][perm[c]] = d[c];
+  }
+  for (int c = 0; c < 5; ++c) W[c] = G.get(I, J, L, 0, c);
+  NodeRes3<T> R;
+  gks_node(p, 3, W, D[0], D[1], R.F[0], R.Ft[0], R.F[1], R.Ft[1], D[2], R.F[2], R.Ft[2]);
+  return R;
+}
+
+// Edge / node results over one period of the lattice, (2nz, 2ny, 2nx)
+// points; interface points and nodes kept apart, each at
+// (L * 2ny + J) * nx + I / 2 (wrapped).
+template <class T> struct Store3 {
+  int nx, ny, nz;
+  std::vector<EdgeRes3<T>> E;
+  std::vector<NodeRes3<T>> N;
+  void init(const Par& p) {
+    nx = p.nx; ny = p.ny; nz = p.nz;
+    E.assign((size_t)4 * nx * ny * nz, EdgeRes3<T>());
+    N.assign((size_t)4 * nx * ny * nz, NodeRes3<T>());
+  }
+  long idx(int I, int J, int L) const {
+    I = ((I % (2 * nx)) + 2 * nx) % (2 * nx);
+    J = ((J % (2 * ny)) + 2 * ny) % (2 * ny);
+    L = ((L % (2 * nz)) + 2 * nz) % (2 * nz);
+    return ((long)L * 2 * ny + J) * nx + I / 2;
+  }
+};
+
+// Stage operator at a node: L, L_t (the 3D form of
+// Eq. eq-conservation-law-2d with the compact flux along each axis) and the
+// re-evaluated averaged gradients and their time derivatives (Eq.
+// define-averaged-gradient with the blended interface values, D15).
+template <class T> struct NodeOp3 { T L[5], Lt[5], G[3][5], Gt[3][5]; };
+
+template <class T, class EdgeF, class NodeF>
+NodeOp3<T> node_operator3(const Par& p, int I, int J, int L, double h, EdgeF edge, NodeF nodef) {
+  NodeOp3<T> r;
+  for (int c = 0; c < 5; ++c) { r.L[c] = 0.0; r.Lt[c] = 0.0; }
+  const bool wide = p.flux_order == 8;
+  for (int ax = 0; ax < 3; ++ax) {
+    const int dI = ax == 0, dJ = ax == 1, dL = ax == 2;
+    auto at = [&](int k) { return std::array<int, 3>{I + k * dI, J + k * dJ, L + k * dL}; };
+    auto E = [&](int k) -> const EdgeRes3<T>& { auto q = at(k); return edge(q[0], q[1], q[2]); };
+    auto Nd = [&](int k) -> const NodeRes3<T>& { auto q = at(k); return nodef(q[0], q[1], q[2]); };
+    const EdgeRes3<T>& em3 = E(-3);
+    const EdgeRes3<T>& em1 = E(-1);
+    const EdgeRes3<T>& ep1 = E(1);
+    const EdgeRes3<T>& ep3 = E(3);
+    const NodeRes3<T>& nm = Nd(-2);
+    const NodeRes3<T>& n0 = Nd(0);
+    const NodeRes3<T>& np = Nd(2);
+    const NodeRes3<T>& nm2 = wide ? Nd(-4) : n0;
+    const NodeRes3<T>& np2 = wide ? Nd(4) : n0;
+    for (int c = 0; c < 5; ++c) {
+      T FR = compact_flux(p, em1.F[ax][c], ep1.F[ax][c], ep3.F[ax][c], nm.F[ax][c], n0.F[ax][c], np.F[ax][c],
+                          np2.F[ax][c], ep1.chi[ax]);
+      T FL = compact_flux(p, em3.F[ax][c], em1.F[ax][c], ep1.F[ax][c], nm2.F[ax][c], nm.F[ax][c], n0.F[ax][c],
+                          np.F[ax][c], em1.chi[ax]);
+      T FRt = compact_flux(p, em1.Ft[ax][c], ep1.Ft[ax][c], ep3.Ft[ax][c], nm.Ft[ax][c], n0.Ft[ax][c],
+                           np.Ft[ax][c], np2.Ft[ax][c], ep1.chi[ax]);
+      T FLt = compact_flux(p, em3.Ft[ax][c], em1.Ft[ax][c], ep1.Ft[ax][c], nm2.Ft[ax][c], nm.Ft[ax][c],
+                           n0.Ft[ax][c], np.Ft[ax][c], em1.chi[ax]);
+      r.L[c] = r.L[c] - (FR - FL) / h;
+      r.Lt[c] = r.Lt[c] - (FRt - FLt) / h;
+      r.G[ax][c] = (ep1.Wtl[ax][c] - em1.Wtr[ax][c]) / h;
+      r.Gt[ax][c] = (ep1.Wtlt[ax][c] - em1.Wtrt[ax][c]) / h;
+    }
+  }
+  return r;
+}
+
+// S2O4 on a 3D node (the 2D combination with a third gradient).  st, acc,
+// out, acc_out: 20 values (W, Wx, Wy, Wz).
+template <class T>
+void s2o4_3d(int stage, double dt, const NodeOp3<T>& op, const T* st, const T* acc, T* out, T* acc_out,
+             int carried = 0) {
+  for (int c = 0; c < 5; ++c) {
+    if (stage == 1) {
+      out[c] = st[c] + 0.5 * dt * op.L[c] + 0.125 * dt * dt * op.Lt[c];
+      acc_out[c] = st[c] + dt * op.L[c] + dt * dt / 6.0 * op.Lt[c];
+      for (int ax = 0; ax < 3; ++ax) {
+        const T g = carried ? st[5 * (1 + ax) + c] : op.G[ax][c];
+        out[5 * (1 + ax) + c] = g + 0.5 * dt * op.Gt[ax][c];
+        acc_out[5 * (1 + ax) + c] = g;
+      }
+    } else {
+      out[c] = acc[c] + dt * dt / 3.0 * op.Lt[c];
+      for (int ax = 0; ax < 3; ++ax) out[5 * (1 + ax) + c] = acc[5 * (1 + ax) + c] + dt * op.Gt[ax][c];
+    }
+  }
+}
+
+// Lattice coordinate of stored node i of grid g along axis ax.
+inline int lattice3(int g, int ax, int i) {
+  static const int even[4][3] = {{0, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+  return even[g][ax] ? 2 * i + 2 : 2 * i + 1;
+}
+
+// S, acc, out, acc_out: 4 grids of 20 planes each, one after another.
+template <class T>
+void stage3d(const Par& p, int stage, double dt, const T* S, const T* acc, T* out, T* acc_out,
+             Store3<T>* keep = nullptr) {
+  const int nx = p.nx, ny = p.ny, nz = p.nz;
+  const double h = p.lx / nx;
+  const long pl = (long)nx * ny * nz, gsz = 20 * pl;
+  const T* Sg[4] = {S, S + gsz, S + 2 * gsz, S + 3 * gsz};
+  const Grid3<T> G(p, Sg);
+  Store3<T> St;
+  St.init(p);
+#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+  for (int L = 0; L < 2 * nz; ++L)
+    for (int J = 0; J < 2 * ny; ++J)
+      for (int I = 0; I < 2 * nx; ++I) {
+        if (iface3_of(I, J, L) >= 0) St.E[St.idx(I, J, L)] = edge3d(p, G, I, J, L, h, dt);
+        else St.N[St.idx(I, J, L)] = node3d(p, G, I, J, L, h);
+      }
+  auto edgef = [&](int I, int J, int L) -> const EdgeRes3<T>& { return St.E[St.idx(I, J, L)]; };
+  auto nodef = [&](int I, int J, int L) -> const NodeRes3<T>& { return St.N[St.idx(I, J, L)]; };
+  for (int g = 0; g < 4; ++g) {
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < pl; ++k) {
+      const int i = (int)(k % nx), j = (int)((k / nx) % ny), l = (int)(k / ((long)nx * ny));
+      const int I = lattice3(g, 0, i), J = lattice3(g, 1, j), L = lattice3(g, 2, l);
+      NodeOp3<T> op = node_operator3<T>(p, I, J, L, h, edgef, nodef);
+      T st[20], ac[20], o[20], a[20];
+      for (int f = 0; f < 20; ++f) {
+        st[f] = S[g * gsz + f * pl + k];
+        ac[f] = acc ? acc[g * gsz + f * pl + k] : T(0.0);
+      }
+      s2o4_3d(stage, dt, op, st, ac, o, a, p.grad_carried);
+      for (int f = 0; f < 20; ++f) {
+        out[g * gsz + f * pl + k] = o[f];
+        if (stage == 1 && acc_out) acc_out[g * gsz + f * pl + k] = a[f];
+      }
+    }
+  }
+  if (keep) *keep = std::move(St);
 }
 
 // ================================================================ 1D lines
@@ -1006,9 +1343,9 @@ template <class T> struct Node1 { T F[3], Ft[3]; };
 
 // Interface between nodes j and j+1 (j from -2 to N).
 template <class T> Edge1<T> edge1d(const Par& p, const Line1<T>& L, int j, double h, double dt) {
-  T Wl[4], Wr[4], Dl[4], Dr[4], chi;
+  T Wl[5], Wr[5], Dl[5], Dr[5], chi;
   {
-    T Q[4][4], X[4][4];
+    T Q[5][4], X[5][4];
     for (int c = 0; c < 3; ++c)
       for (int m = 0; m < 4; ++m) { Q[c][m] = L.W[c][j - 1 + m + 3]; X[c][m] = L.X[c][j - 1 + m + 3]; }
     recon_line(p, 1, Q, X, h, Wl, Dl, Wr, Dr, chi);
@@ -1024,9 +1361,9 @@ template <class T> Edge1<T> edge1d(const Par& p, const Line1<T>& L, int j, doubl
   return E;
 }
 template <class T> Node1<T> node1d(const Par& p, const Line1<T>& L, int j, double h) {
-  T W[3], Wx[4];
+  T W[3], Wx[5];
   {
-    T Q[4][3], X[4][3];
+    T Q[5][3], X[5][3];
     for (int c = 0; c < 3; ++c)
       for (int m = 0; m < 3; ++m) { Q[c][m] = L.W[c][j - 1 + m + 3]; X[c][m] = L.X[c][j - 1 + m + 3]; }
     recon_node_line(p, 1, Q, X, h, Wx);
@@ -1092,12 +1429,12 @@ int orc_abi_version() { return 1; }
 void orc_recon_interface(const Par* p, const double* Q, const double* X, double h, double* out) {
   recon_interface(*p, Q, X, h, out[0], out[1], out[2], out[3], out[4], out[5]);
 }
-// R and L (row-major 4x4, dim+2 used) at the local-frame state W.
+// R and L (row-major 5x5, dim+2 used) at the local-frame state W.
 void orc_char_basis(int dim, double gamma, const double* W, double* R, double* L) {
-  double r[4][4], l[4][4];
+  double r[5][5], l[5][5];
   char_basis(dim, gamma, W, r, l);
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) { R[4 * a + b] = r[a][b]; L[4 * a + b] = l[a][b]; }
+  for (int a = 0; a < 5; ++a)
+    for (int b = 0; b < 5; ++b) { R[5 * a + b] = r[a][b]; L[5 * a + b] = l[a][b]; }
 }
 double orc_recon_node(const Par* p, const double* Q, const double* X, double h) {
   return recon_node(*p, Q, X, h);
@@ -1119,20 +1456,22 @@ void orc_slope(const double* W, const double* D, int dim, double gamma, double* 
 }
 void orc_qcoef(double T_, double tau, double* q) { qcoef(T_, tau, q); }
 // out: F, Ft, We, Wet, Wl, Wr, Wlt, Wrt (each dim+2), then tau, then W0 (dim+2)
+// Wt: tangential slope along the v axis (2D, 3D); Wt2: along the w axis (3D).
 void orc_gks_interface(const Par* p, int dim, const double* WL, const double* WR, const double* WnL,
-                       const double* WnR, const double* Wt, double dt, double* out) {
+                       const double* WnR, const double* Wt, const double* Wt2, double dt, double* out) {
   GksOut<double> o;
-  gks_interface(*p, dim, WL, WR, WnL, WnR, Wt, dt, o);
+  gks_interface(*p, dim, WL, WR, WnL, WnR, Wt, dt, o, Wt2);
   int n = dim + 2;
   const double* src[8] = {o.F, o.Ft, o.We, o.Wet, o.Wl, o.Wr, o.Wlt, o.Wrt};
   for (int s = 0; s < 8; ++s) for (int i = 0; i < n; ++i) out[s * n + i] = src[s][i];
   out[8 * n] = o.tau;
   for (int i = 0; i < n; ++i) out[8 * n + 1 + i] = o.W0[i];
 }
-// out: F, Ft, G, Gt (each dim+2)
-void orc_gks_node(const Par* p, int dim, const double* W, const double* Wx, const double* Wy, double* out) {
+// out: F, Ft, G, Gt, H, Ht (each dim+2; G from 2D, H in 3D)
+void orc_gks_node(const Par* p, int dim, const double* W, const double* Wx, const double* Wy, const double* Wz,
+                  double* out) {
   int n = dim + 2;
-  gks_node(*p, dim, W, Wx, Wy, out, out + n, out + 2 * n, out + 3 * n);
+  gks_node(*p, dim, W, Wx, Wy, out, out + n, out + 2 * n, out + 3 * n, Wz, out + 4 * n, out + 5 * n);
 }
 double orc_compact_flux(const Par* p, double Fm, double Fc, double Fp, double Nm, double N0, double N1, double Np2,
                         double chi) {
@@ -1289,6 +1628,82 @@ void orc_step2d_tangent(const Par* p, double dt, const double* P, const double* 
   stage2d<Dual>(*p, 1, dt, xP.data(), xD.data(), nullptr, nullptr, sP.data(), sD.data(), aP.data(), aD.data());
   stage2d<Dual>(*p, 2, dt, sP.data(), sD.data(), aP.data(), aD.data(), yP.data(), yD.data(), nullptr, nullptr);
   for (long k = 0; k < n12; ++k) { outP[k] = yP[k].v; outD[k] = yD[k].v; outdP[k] = yP[k].d; outdD[k] = yD[k].d; }
+}
+
+// --- 3D --------------------------------------------------------------------
+// S: 4 grids (P, Dxy, Dxz, Dyz) of 20 planes (W, Wx, Wy, Wz) of nz*ny*nx,
+// one after another; periodic.  Stage 2 needs acc.
+void orc_stage3d(const Par* p, int stage, double dt, const double* S, const double* acc, double* out,
+                 double* acc_out) {
+  stage3d<double>(*p, stage, dt, S, acc, out, acc_out);
+}
+
+double orc_dt3d(const Par* p, const double* S, double cfl) {
+  const long pl = (long)p->nx * p->ny * p->nz;
+  double smax = 0, rmin = 1e300;
+  for (int g = 0; g < 4; ++g) speed_scan(*p, 3, S + 20 * pl * g, pl, pl, smax, rmin);
+  return dt_from(*p, smax, rmin, p->lx / p->nx, cfl);
+}
+
+// Advance nsteps (dt_fixed > 0: fixed step, else CFL); stops at t_end when
+// t_end > 0.  S updated in place; t in/out; returns steps taken.
+int orc_step3d(const Par* p, double* S, int nsteps, double dt_fixed, double cfl, double t_end, double* t) {
+  const long n = 80L * p->nx * p->ny * p->nz;
+  std::vector<double> s1(n), a1(n);
+  int k = 0;
+  for (; k < nsteps; ++k) {
+    if (t_end > 0 && *t >= t_end) break;
+    double dt = dt_fixed > 0 ? dt_fixed : orc_dt3d(p, S, cfl);
+    if (t_end > 0 && *t + dt > t_end) dt = t_end - *t;
+    stage3d<double>(*p, 1, dt, S, nullptr, s1.data(), a1.data());
+    stage3d<double>(*p, 2, dt, s1.data(), a1.data(), S, nullptr);
+    *t += dt;
+  }
+  return k;
+}
+
+// Per-interface and per-node intermediates of stage 1, at (i, j, k) in
+// [0, nx) x [0, ny) x [0, nz).  E: interface classes q = 0..3 ((even, odd,
+// odd), (odd, even, odd), (odd, odd, even), (even, even, even); lattice
+// coordinate 2i+2 where even, 2i+1 where odd), each 3 normal axes of 31
+// planes: F[5], Ft[5], chi, Wtl[5], Wtr[5], Wtlt[5], Wtrt[5].  N: grids
+// g = 0..3, 30 planes: F, Ft, G, Gt, H, Ht.
+void orc_intermediates3d(const Par* p, double dt, const double* S, double* E, double* N) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const long pl = (long)nx * ny * nz;
+  std::vector<double> a(80 * pl), b(80 * pl);
+  Store3<double> St;
+  stage3d<double>(*p, 1, dt, S, nullptr, a.data(), b.data(), &St);
+  static const int even[4][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}, {1, 1, 1}};
+  for (long k = 0; k < pl; ++k) {
+    const int i = (int)(k % nx), j = (int)((k / nx) % ny), l = (int)(k / ((long)nx * ny));
+    for (int q = 0; q < 4; ++q) {
+      const int I = even[q][0] ? 2 * i + 2 : 2 * i + 1, J = even[q][1] ? 2 * j + 2 : 2 * j + 1;
+      const int L = even[q][2] ? 2 * l + 2 : 2 * l + 1;
+      const EdgeRes3<double>& R = St.E[St.idx(I, J, L)];
+      for (int ax = 0; ax < 3; ++ax) {
+        double* o = E + ((long)q * 3 + ax) * 31 * pl;
+        for (int c = 0; c < 5; ++c) {
+          o[(0 + c) * pl + k] = R.F[ax][c];
+          o[(5 + c) * pl + k] = R.Ft[ax][c];
+          o[(11 + c) * pl + k] = R.Wtl[ax][c];
+          o[(16 + c) * pl + k] = R.Wtr[ax][c];
+          o[(21 + c) * pl + k] = R.Wtlt[ax][c];
+          o[(26 + c) * pl + k] = R.Wtrt[ax][c];
+        }
+        o[10 * pl + k] = R.chi[ax];
+      }
+    }
+    for (int g = 0; g < 4; ++g) {
+      const NodeRes3<double>& R = St.N[St.idx(lattice3(g, 0, i), lattice3(g, 1, j), lattice3(g, 2, l))];
+      double* o = N + (long)g * 30 * pl;
+      for (int ax = 0; ax < 3; ++ax)
+        for (int c = 0; c < 5; ++c) {
+          o[(10 * ax + c) * pl + k] = R.F[ax][c];
+          o[(10 * ax + 5 + c) * pl + k] = R.Ft[ax][c];
+        }
+    }
+  }
 }
 
 // --- 1D --------------------------------------------------------------------

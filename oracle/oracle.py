@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY: imported by ``tests/``, ``__graft_entry__.smoke()`` an
 the ``cpu_baseline`` leg of ``bench.py``.  It never imports the product package
 and the product package never imports it.
 
-Arrays cross the boundary as contiguous float64 numpy arrays.  2D state: one
+Arrays cross the boundary as contiguous float64 numpy arrays.  3D state:
+(4, 20, nz, ny, nx), the four grids of the 3D lattice.  2D state: one
 array per grid holding W[0..3], Wx[0..3], Wy[0..3]: (12, ny, nx) for the
 primary grid, (12, ny + by, nx + bx) for the dual grid, with bx (by) = 1 when
 the x (y) sides are not periodic (the boundary lines carry dual nodes).  1D
@@ -45,6 +46,7 @@ class Par(C.Structure):
         ("C", C.c_double), ("eps", C.c_double), ("eps_a", C.c_double),
         ("d_central", C.c_double), ("d_side", C.c_double),
         ("tau_c1", C.c_double), ("tau_c2", C.c_double),
+        ("z0", C.c_double), ("lz", C.c_double), ("nz", C.c_int32), ("pad_", C.c_int32),
     ]
 
 
@@ -52,7 +54,7 @@ VARIANTS = {"6-4": 0, "6-2": 1, "linear": 2}
 BCS = {"periodic": 0, "zero_gradient": 1, "reflecting": 2, "no_slip": 3}
 
 
-def make_par(*, dim=2, nx=16, ny=16, x0=0.0, lx=1.0, y0=0.0, ly=None, bc="periodic", dual_1d=0,
+def make_par(*, dim=2, nx=16, ny=16, nz=1, x0=0.0, lx=1.0, y0=0.0, ly=None, z0=0.0, lz=None, bc="periodic", dual_1d=0,
              gamma=1.4, mu=0.0, prandtl=1.0, variant="6-4", geno_C=20.0, geno_r=3,
              geno_eps=1e-15, geno_eps_a=1e-6, d_central=8.0, d_side=1.0, tau_c1=0.0,
              tau_c2=1.0, grad_carried=0, recon_vars="conservative", sides=None, flux_order=6, **_ignored) -> Par:
@@ -61,9 +63,13 @@ def make_par(*, dim=2, nx=16, ny=16, x0=0.0, lx=1.0, y0=0.0, ly=None, bc="period
     tau = 0 * dt + dt |dp|/(p_l+p_r) for Euler: D11 as amended).  2D sides
     (x-low, x-high, y-low, y-high) default to `bc` on every side.  flux_order
     6 is the compact flux of Sec. 2.1; 8 the wider stencil over nodes
-    j-1..j+2 (a reading: the paper mentions it without formulas)."""
+    j-1..j+2 (a reading: the paper mentions it without formulas).  3D
+    problems (dim 3) are periodic on all sides, with nz nodes along z."""
     p = Par()
-    p.dim, p.nx, p.ny = dim, nx, (ny if dim == 2 else 1)
+    p.dim, p.nx, p.ny = dim, nx, (ny if dim >= 2 else 1)
+    p.nz = nz if dim == 3 else 1
+    if dim == 3 and (bc != "periodic" or sides is not None):
+        raise ValueError("3D problems are periodic")
     p.bc = BCS[bc] if isinstance(bc, str) else int(bc)
     sd = [p.bc] * 4 if sides is None else [BCS[b] if isinstance(b, str) else int(b) for b in sides]
     if dim == 2:
@@ -76,6 +82,8 @@ def make_par(*, dim=2, nx=16, ny=16, x0=0.0, lx=1.0, y0=0.0, ly=None, bc="period
     p.r = int(geno_r)
     p.x0, p.lx, p.y0 = x0, lx, y0
     p.ly = lx * p.ny / nx if ly is None else ly
+    p.z0 = z0
+    p.lz = lx * p.nz / nx if lz is None else lz
     p.gamma, p.mu, p.prandtl = gamma, mu, prandtl
     p.C, p.eps, p.eps_a, p.d_central, p.d_side = geno_C, geno_eps, geno_eps_a, d_central, d_side
     p.tau_c1, p.tau_c2 = tau_c1, tau_c2
@@ -109,8 +117,8 @@ def lib():
             "orc_maxwell": (None, [d, d, d, d, i, i, _dp]),
             "orc_slope": (None, [_dp, _dp, i, d, _dp]),
             "orc_qcoef": (None, [d, d, _dp]),
-            "orc_gks_interface": (None, [P, i, _dp, _dp, _dp, _dp, _dp, d, _dp]),
-            "orc_gks_node": (None, [P, i, _dp, _dp, _dp, _dp]),
+            "orc_gks_interface": (None, [P, i, _dp, _dp, _dp, _dp, _dp, _dp, d, _dp]),
+            "orc_gks_node": (None, [P, i, _dp, _dp, _dp, _dp, _dp]),
             "orc_compact_flux": (d, [P, d, d, d, d, d, d, d, d]),
             "orc_s2o4_scalar": (None, [i, d, d, d, d, d, _dp]),
             "orc_stage2d": (None, [P, i, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
@@ -119,6 +127,10 @@ def lib():
             "orc_intermediates2d": (None, [P, d, _dp, _dp, _dp, _dp, _dp, _dp]),
             "orc_stage2d_sample": (None, [P, i, d, _dp, _dp, _dp, _dp, i, _ip, _ip, _ip, _dp]),
             "orc_step2d_tangent": (None, [P, d, _dp, _dp, _dp, _dp, _dp, _dp, _dp, _dp]),
+            "orc_stage3d": (None, [P, i, d, _dp, _dp, _dp, _dp]),
+            "orc_dt3d": (d, [P, _dp, d]),
+            "orc_step3d": (i, [P, _dp, i, d, d, d, _dp]),
+            "orc_intermediates3d": (None, [P, d, _dp, _dp, _dp]),
             "orc_stage1d": (None, [P, i, d, _dp, _dp, _dp, _dp]),
             "orc_dt1d": (d, [P, _dp, d]),
             "orc_step1d": (i, [P, _dp, i, d, d, d, _dp]),
@@ -160,11 +172,11 @@ def recon_node(par, Q, X, h):
 
 def char_basis(dim, gamma, W):
     """(R, L) (n x n, n = dim + 2) at the local-frame conservative state W."""
-    R = np.zeros(16)
-    L = np.zeros(16)
+    R = np.zeros(25)
+    L = np.zeros(25)
     lib().orc_char_basis(dim, gamma, _p(_arr(W, dim + 2)), _p(R), _p(L))
     n = dim + 2
-    return R.reshape(4, 4)[:n, :n], L.reshape(4, 4)[:n, :n]
+    return R.reshape(5, 5)[:n, :n], L.reshape(5, 5)[:n, :n]
 
 
 def geno_blend(par, IS, ref, d, q, dq, PH, PHx):
@@ -192,12 +204,15 @@ def qcoef(T, tau):
     return q
 
 
-def gks_interface(par, dim, WL, WR, WnL, WnR, Wt, dt):
+def gks_interface(par, dim, WL, WR, WnL, WnR, Wt, dt, Wt2=None):
+    """Interface solver in the local frame; Wt, Wt2: tangential slopes along
+    the v and (3D) w axes."""
     n = dim + 2
     out = np.zeros(9 * n + 1)
     wt = _arr(Wt if Wt is not None else np.zeros(n), n)
+    wt2 = _arr(Wt2 if Wt2 is not None else np.zeros(n), n)
     lib().orc_gks_interface(C.byref(par), dim, _p(_arr(WL, n)), _p(_arr(WR, n)), _p(_arr(WnL, n)),
-                            _p(_arr(WnR, n)), _p(wt), dt, _p(out))
+                            _p(_arr(WnR, n)), _p(wt), _p(wt2), dt, _p(out))
     keys = ["F", "Ft", "We", "Wet", "Wl", "Wr", "Wlt", "Wrt"]
     r = {k: out[i * n:(i + 1) * n].copy() for i, k in enumerate(keys)}
     r["tau"] = out[8 * n]
@@ -205,12 +220,14 @@ def gks_interface(par, dim, WL, WR, WnL, WnR, Wt, dt):
     return r
 
 
-def gks_node(par, dim, W, Wx, Wy=None):
+def gks_node(par, dim, W, Wx, Wy=None, Wz=None):
     n = dim + 2
-    out = np.zeros(4 * n)
+    out = np.zeros(6 * n)
     wy = _arr(Wy if Wy is not None else np.zeros(n), n)
-    lib().orc_gks_node(C.byref(par), dim, _p(_arr(W, n)), _p(_arr(Wx, n)), _p(wy), _p(out))
-    return {"F": out[:n], "Ft": out[n:2 * n], "G": out[2 * n:3 * n], "Gt": out[3 * n:]}
+    wz = _arr(Wz if Wz is not None else np.zeros(n), n)
+    lib().orc_gks_node(C.byref(par), dim, _p(_arr(W, n)), _p(_arr(Wx, n)), _p(wy), _p(wz), _p(out))
+    return {"F": out[:n], "Ft": out[n:2 * n], "G": out[2 * n:3 * n], "Gt": out[3 * n:4 * n],
+            "H": out[4 * n:5 * n], "Ht": out[5 * n:]}
 
 
 def compact_flux(par, Fm, Fc, Fp, N0, N1, chi, Nm=0.0, Np2=0.0):
@@ -320,6 +337,45 @@ def state_from_samples(par, S):
                 A[ln, c, j] = S[c, k]
                 A[ln, 3 + c, j] = (S[c, (k + 1) % NX] - S[c, (k - 1) % NX]) / h
     return A
+
+
+# ---------------------------------------------------------------------- 3D
+def _s3(par, S):
+    S = _arr(S)
+    assert S.shape == (4, 20, par.nz, par.ny, par.nx), S.shape
+    return S
+
+
+def stage3d(par, stage, dt, S, acc=None):
+    """One stage on the four 3D grids, S (4, 20, nz, ny, nx); stage 1 returns
+    (out, acc), stage 2 out."""
+    S = _s3(par, S)
+    out = np.zeros_like(S)
+    a = np.zeros_like(S) if stage == 1 else None
+    lib().orc_stage3d(C.byref(par), stage, dt, _p(S), _p(None if acc is None else _s3(par, acc)), _p(out), _p(a))
+    return (out, a) if stage == 1 else out
+
+
+def dt3d(par, S, cfl):
+    return lib().orc_dt3d(C.byref(par), _p(_s3(par, S)), cfl)
+
+
+def step3d(par, S, nsteps, dt=0.0, cfl=0.5, t_end=0.0, t=0.0):
+    """Advance; returns (S, t, steps)."""
+    S = _s3(par, S).copy()
+    tt = C.c_double(t)
+    k = lib().orc_step3d(C.byref(par), _p(S), nsteps, dt, cfl, t_end, C.byref(tt))
+    return S, tt.value, k
+
+
+def intermediates3d(par, dt, S):
+    """Stage-1 intermediates: interface classes (4, 3 normals, 31, nz, ny, nx)
+    and nodal fluxes (4 grids, 30, nz, ny, nx)."""
+    shp = (par.nz, par.ny, par.nx)
+    E = np.zeros((4, 3, 31) + shp)
+    N = np.zeros((4, 30) + shp)
+    lib().orc_intermediates3d(C.byref(par), dt, _p(_s3(par, S)), _p(E), _p(N))
+    return E, N
 
 
 # ---------------------------------------------------------------------- 1D

@@ -14,7 +14,10 @@ solution is evaluated point by point instead:
     interface that the trajectory starts from (left for u > 0, right for u < 0);
 * g_l, g_r, g0 are Maxwellians tabulated on Gauss-Legendre grids in (u, v)
   and in |xi| (K internal degrees of freedom, radial measure r^(K-1)),
-  normalised numerically;
+  normalised numerically; in 3D the tangential directions v and w take
+  Gauss-Hermite nodes about the Maxwellian's own V and W instead, which
+  integrate its polynomial-times-Gaussian integrands exactly (at most degree 9
+  per direction here, 12 nodes);
 * the compatibility state W0 is the psi-moment of the left half-space
   Maxwellian plus that of the right one; micro slopes solve the moment systems
   <psi (s.psi) g> = D with matrices integrated on the grid (numpy solve);
@@ -41,7 +44,8 @@ G = 1.4
 
 
 def _kdof(dim):
-    return (4 - 2 * G) / (G - 1) if dim == 2 else (3 - G) / (G - 1)
+    # K + dim = 2 / (gamma - 1)
+    return 2 / (G - 1) - dim
 
 
 def _gl(a, b, n):
@@ -52,17 +56,19 @@ def _gl(a, b, n):
 class _Maxwellian:
     """A Maxwellian rho (lam/pi)^((K+D)/2) exp(-lam (|u - U|^2 + xi^2))
     tabulated on a grid covering its mass; half = +1 keeps u > 0, -1 keeps
-    u < 0, 0 the whole line.  Arrays broadcast as (u, v, r) in 2D and (u, r)
-    in 1D; `w` holds quadrature weight times the Maxwellian."""
+    u < 0, 0 the whole line.  Arrays broadcast as (u, v, w, r) in 3D,
+    (u, v, r) in 2D and (u, r) in 1D; `w` holds quadrature weight times the
+    Maxwellian."""
 
     def __init__(self, W, dim, half=0, n=96):
         self.dim = dim
         rho = W[0]
         U = W[1] / rho
-        V = W[2] / rho if dim == 2 else 0.0
-        p = (G - 1) * (W[-1] - 0.5 * rho * (U * U + V * V))
+        V = W[2] / rho if dim >= 2 else 0.0
+        Wv = W[3] / rho if dim == 3 else 0.0
+        p = (G - 1) * (W[-1] - 0.5 * rho * (U * U + V * V + Wv * Wv))
         lam = rho / (2 * p)
-        self.rho, self.U, self.V, self.p, self.lam = rho, U, V, p, lam
+        self.rho, self.U, self.V, self.Wv, self.p, self.lam = rho, U, V, Wv, p, lam
         K = _kdof(dim)
         span = 13.0 / np.sqrt(lam)
         lo, hi = U - span, U + span
@@ -81,7 +87,18 @@ class _Maxwellian:
         gv = np.exp(-lam * (v - V) ** 2) * wv if dim == 2 else wv
         gr = np.exp(-lam * r * r) * wr
         norm = guf.sum() * gv.sum() * gr.sum()
-        if dim == 2:
+        if dim == 3:
+            # Gauss-Hermite in v and w: nodes V + x / sqrt(lam), W + x / sqrt(lam)
+            # carry the Gaussian itself (gv above is then the plain weight 1)
+            x, wx = np.polynomial.hermite.hermgauss(12)
+            v, gv = V + x / np.sqrt(lam), wx / wx.sum()
+            w = Wv + x / np.sqrt(lam)
+            gw = wx / wx.sum()
+            self.u, self.v = u[:, None, None, None], v[None, :, None, None]
+            self.wv, self.x2 = w[None, None, :, None], (r * r)[None, None, None, :]
+            self.w = (rho * gu[:, None, None, None] * gv[None, :, None, None] * gw[None, None, :, None]
+                      * gr[None, None, None, :] / norm)
+        elif dim == 2:
             self.u, self.v, self.x2 = u[:, None, None], v[None, :, None], (r * r)[None, None, :]
             self.w = rho * gu[:, None, None] * gv[None, :, None] * gr[None, None, :] / norm
         else:
@@ -91,6 +108,9 @@ class _Maxwellian:
         self.ups = [self.u * ps for ps in self.ps]
 
     def psi(self):
+        if self.dim == 3:
+            return [np.ones_like(self.u), self.u, self.v, self.wv,
+                    0.5 * (self.u ** 2 + self.v ** 2 + self.wv ** 2 + self.x2)]
         if self.dim == 2:
             return [np.ones_like(self.u), self.u, self.v, 0.5 * (self.u ** 2 + self.v ** 2 + self.x2)]
         return [np.ones_like(self.u), self.u, 0.5 * (self.u ** 2 + self.x2)]
@@ -111,32 +131,43 @@ class _Maxwellian:
         return np.linalg.solve(M, D)
 
 
-def _brute_interface(WL, WR, WnL, WnR, Wt, dt, dim, mu=0.0, prandtl=1.0, c1=0.0, c2=1.0, nt=16, mistake=None):
-    """`mistake` plants one plausible error (for the sharpness test only)."""
+def _brute_interface(WL, WR, WnL, WnR, Wt, dt, dim, mu=0.0, prandtl=1.0, c1=0.0, c2=1.0, nt=16, mistake=None,
+                     Wt2=None):
+    """`mistake` plants one plausible error (for the sharpness test only).
+    Wt, Wt2: tangential slopes along v and (3D) w."""
     n = dim + 2
     hl, hr = _Maxwellian(WL, dim, +1), _Maxwellian(WR, dim, -1 if mistake != "half_space" else +1)
     fl, fr = _Maxwellian(WL, dim, 0), _Maxwellian(WR, dim, 0)
     W0 = hl.moments(1.0) + hr.moments(1.0)
     g0 = _Maxwellian(W0, dim, 0)
     Wt = np.zeros(n) if Wt is None else np.asarray(Wt, float)
+    Wt2 = np.zeros(n) if Wt2 is None else np.asarray(Wt2, float)
+
+    def transport(m, a, b, c):
+        tr = m.lin(a) * m.u + m.lin(b) * m.v
+        return tr + m.lin(c) * m.wv if dim == 3 else tr
 
     def slopes(full, Dn):
         a = full.slope(Dn)
-        b = full.slope(Wt) if dim == 2 else np.zeros(n)
+        b = full.slope(Wt) if dim >= 2 else np.zeros(n)
+        c = full.slope(Wt2) if dim == 3 else np.zeros(n)
         # one-sided Euler time derivative and the time slope from compatibility
-        Wtime = -full.moments(full.lin(a) * full.u + full.lin(b) * full.v)
+        Wtime = -full.moments(transport(full, a, b, c))
         A = full.slope(Wtime)
-        return a, b, A, Wtime
+        return a, b, c, A, Wtime
 
-    aL, bL, AL, WtL = slopes(fl, np.asarray(WnL, float))
-    aR, bR, AR, WtR = slopes(fr, np.asarray(WnR, float))
-    a0, b0, A0, _ = slopes(g0, 0.5 * (np.asarray(WnL, float) + np.asarray(WnR, float)))
+    aL, bL, cL, AL, WtL = slopes(fl, np.asarray(WnL, float))
+    aR, bR, cR, AR, WtR = slopes(fr, np.asarray(WnR, float))
+    a0, b0, c0, A0, _ = slopes(g0, 0.5 * (np.asarray(WnL, float) + np.asarray(WnR, float)))
     tau = (mu / g0.p if mu > 0 else c1 * dt) + c2 * dt * abs(hl.p - hr.p) / (hl.p + hr.p)
     assert tau > 0
 
-    for m in (g0, hl, hr):  # 1/2 (u - U0)((u - U0)^2 + (v - V0)^2 + xi^2)
+    for m in (g0, hl, hr):  # 1/2 (u - U0)((u - U0)^2 + (v - V0)^2 + (w - W0)^2 + xi^2)
         du, dv = m.u - g0.U, m.v - g0.V
-        m.heat = 0.5 * du * (du * du + (dv * dv if dim == 2 else 0.0) + m.x2)
+        c2 = du * du + (dv * dv if dim >= 2 else 0.0) + m.x2
+        if dim == 3:
+            c2 = c2 + (m.wv - g0.Wv) ** 2
+        m.heat = 0.5 * du * c2
 
     # distribution at the interface at time t, per Maxwellian it multiplies
     def f_at(t):
@@ -144,10 +175,10 @@ def _brute_interface(WL, WR, WnL, WnR, Wt, dt, dim, mu=0.0, prandtl=1.0, c1=0.0,
         e = np.exp(-(t - tp) / tau) * wp / tau
         ca, cb, cc = e.sum(), (e * (t - tp)).sum(), (e * tp).sum()
         # (1/tau) int g(-u (t-t'), -v (t-t'), t') e^{-(t-t')/tau} dt'
-        feq = ca - cb * (g0.lin(a0) * g0.u + g0.lin(b0) * g0.v) + cc * g0.lin(A0) * (mistake != "no_A0")
+        feq = ca - cb * transport(g0, a0, b0, c0) + cc * g0.lin(A0) * (mistake != "no_A0")
         out = [(g0, feq)]
-        for h, a, b, A in ((hl, aL, bL, AL), (hr, aR, bR, AR)):
-            tr = h.lin(a) * h.u + h.lin(b) * h.v
+        for h, a, b, c, A in ((hl, aL, bL, cL, AL), (hr, aR, bR, cR, AR)):
+            tr = transport(h, a, b, c)
             # e^{-t/tau} f0(-u t, -v t) on the half space the trajectory starts from
             tA = 0.0 if mistake == "no_tauA" else tau * h.lin(A)
             out.append((h, np.exp(-t / tau) * (1.0 - t * tr - tau * tr - tA)))
@@ -188,6 +219,9 @@ def _state(rng, dim):
     if dim == 1:
         return np.array([rho, rho * U, p / (G - 1) + 0.5 * rho * U * U])
     V = rng.uniform(-0.8, 0.8)
+    if dim == 3:
+        Wv = rng.uniform(-0.8, 0.8)
+        return np.array([rho, rho * U, rho * V, rho * Wv, p / (G - 1) + 0.5 * rho * (U * U + V * V + Wv * Wv)])
     return np.array([rho, rho * U, rho * V, p / (G - 1) + 0.5 * rho * (U * U + V * V)])
 
 
@@ -206,6 +240,9 @@ CASES = [
     (2, 2e-3, 0.0, 0.02, 4),
     (1, 0.0, 0.0, 0.02, 5),
     (1, 2e-3, 0.0, 0.01, 6),
+    (3, 0.0, 0.0, 0.02, 7),
+    (3, 0.0, 0.05, 0.01, 8),
+    (3, 2e-3, 0.0, 0.02, 9),
 ]
 
 
@@ -219,11 +256,12 @@ def test_interface_solver_at_a_jump_by_quadrature(oracle, dim, mu, c1, dt, seed)
     n = dim + 2
     WL, WR = _state(rng, dim), _state(rng, dim)
     WnL, WnR = rng.normal(size=n), rng.normal(size=n)
-    Wt = rng.normal(size=n) if dim == 2 else None
+    Wt = rng.normal(size=n) if dim >= 2 else None
+    Wt2 = rng.normal(size=n) if dim == 3 else None
     pr = 0.72 if mu > 0 else 1.0
-    par = oracle.make_par(**settings(dim=dim, nx=8, ny=8, lx=1.0, mu=mu, prandtl=pr, tau_c1=c1))
-    r = oracle.gks_interface(par, dim, WL, WR, WnL, WnR, Wt, dt)
-    b = _brute_interface(WL, WR, WnL, WnR, Wt, dt, dim, mu=mu, prandtl=pr, c1=c1)
+    par = oracle.make_par(**settings(dim=dim, nx=8, ny=8, nz=8, lx=1.0, mu=mu, prandtl=pr, tau_c1=c1))
+    r = oracle.gks_interface(par, dim, WL, WR, WnL, WnR, Wt, dt, Wt2=Wt2)
+    b = _brute_interface(WL, WR, WnL, WnR, Wt, dt, dim, mu=mu, prandtl=pr, c1=c1, Wt2=Wt2)
     assert r["tau"] == pytest.approx(b["tau"], rel=1e-12)
     # measured: <= 1.3e-14 on values, <= 1e-13 on time derivatives (the
     # differences of the two time integrals divided by dt^2 amplify quadrature

@@ -16,6 +16,13 @@ data with jumps placed on interfaces the derivative is set to zero.
 
 2D state per grid: float64 array (12, ny, nx) = W[0..3], Wx[0..3], Wy[0..3],
 W = (rho, rho U, rho V, rho E).  1D state per line: (6, N) = W[0..2], Wx[0..2].
+
+3D: point (I, J, L) of the lattice at (x0 + I h/2, y0 + J h/2, z0 + L h/2).
+Four grids: primary P (odd, odd, odd) and the face-offset duals Dxy (even,
+even, odd), Dxz (even, odd, even), Dyz (odd, even, even); stored node i along
+an axis is lattice coordinate 2i+1 where the grid is odd and 2i+2 where it is
+even (periodic wrap).  State: (4, 20, nz, ny, nx) = per grid W[0..4],
+Wx[0..4], Wy[0..4], Wz[0..4], W = (rho, rho U, rho V, rho W, rho E).
 """
 from __future__ import annotations
 
@@ -395,3 +402,130 @@ def sod(N=100):
 
 def lax(N=100):
     return shock_tube(N, (0.445, 0.698, 3.528), (0.5, 0.0, 0.571))
+
+
+# --------------------------------------------------------------------- 3D
+# grid g is even along axis a where EVEN3[g][a]
+EVEN3 = ((0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1))
+
+
+def conservative3d(rho, U, V, Wv, p, gamma=GAMMA):
+    rho, U, V, Wv, p = np.broadcast_arrays(*(np.asarray(a, dtype=np.float64) for a in (rho, U, V, Wv, p)))
+    return np.stack([rho, rho * U, rho * V, rho * Wv, p / (gamma - 1.0) + 0.5 * rho * (U * U + V * V + Wv * Wv)])
+
+
+def lattice3(nx, ny, nz, h, x0=0.0, y0=0.0, z0=0.0):
+    """(X, Y, Z), each (2nz, 2ny, 2nx): coordinates of the half-spacing lattice."""
+    X = x0 + np.arange(2 * nx)[None, None, :] * h / 2
+    Y = y0 + np.arange(2 * ny)[None, :, None] * h / 2
+    Z = z0 + np.arange(2 * nz)[:, None, None] * h / 2
+    return np.broadcast_arrays(X, Y, Z)
+
+
+def state3d_from_samples(S, h):
+    """S: (5, 2nz, 2ny, 2nx) conservative samples on the half lattice ->
+    (4, 20, nz, ny, nx): nodal values and the averaged derivatives (difference
+    of the samples at the two bounding interfaces over h) of the four grids."""
+    _, LL, JJ, II = S.shape
+    n = (II // 2, JJ // 2, LL // 2)
+    out = np.empty((4, 20, n[2], n[1], n[0]))
+    for g in range(4):
+        c = [2 * np.arange(n[a]) + (2 if EVEN3[g][a] else 1) for a in range(3)]
+        I, J, L = c[0][None, None, :], c[1][None, :, None], c[2][:, None, None]
+
+        def at(di, dj, dl):
+            return S[:, (L + dl) % LL, (J + dj) % JJ, (I + di) % II]
+
+        out[g, 0:5] = at(0, 0, 0)
+        out[g, 5:10] = (at(1, 0, 0) - at(-1, 0, 0)) / h
+        out[g, 10:15] = (at(0, 1, 0) - at(0, -1, 0)) / h
+        out[g, 15:20] = (at(0, 0, 1) - at(0, 0, -1)) / h
+    return np.ascontiguousarray(out)
+
+
+@dataclass
+class Problem3D:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    lx: float
+    S: np.ndarray
+    params: dict = field(default_factory=dict)
+
+    @property
+    def h(self):
+        return self.lx / self.nx
+
+    @property
+    def ly(self):
+        return self.h * self.ny
+
+    @property
+    def lz(self):
+        return self.h * self.nz
+
+
+def advection3d(n, lx=2.0):
+    """rho = 1 + 0.2 sin(pi (x+y+z)), U = V = W = p = 1 on [0, 2]^3: the
+    accuracy test of Sec. 5.1 carried to 3D."""
+    h = lx / n
+    X, Y, Z = lattice3(n, n, n, h)
+    S = conservative3d(1.0 + 0.2 * np.sin(np.pi * (X + Y + Z)), 1.0, 1.0, 1.0, 1.0)
+    return Problem3D("advection3d", n, n, n, lx, state3d_from_samples(S, h), {"gamma": GAMMA, "mu": 0.0})
+
+
+def advection3d_exact(n, t, lx=2.0):
+    h = lx / n
+    X, Y, Z = lattice3(n, n, n, h)
+    S = conservative3d(1.0 + 0.2 * np.sin(np.pi * (X + Y + Z - 3 * t)), 1.0, 1.0, 1.0, 1.0)
+    return state3d_from_samples(S, h)
+
+
+def random_smooth3d(nx, ny, nz, seed=0, amp=0.1, modes=3, lx=1.0):
+    """A seeded smooth periodic 3D flow (sums of low Fourier modes)."""
+    rng = np.random.default_rng(seed)
+    h = lx / nx
+    X, Y, Z = lattice3(nx, ny, nz, h)
+    ly, lz = h * ny, h * nz
+
+    def fld(base):
+        f = np.full_like(X, base)
+        for _ in range(modes):
+            kx, ky, kz = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0, 2 * math.pi)
+            f = f + amp * rng.uniform(-1, 1) * np.sin(2 * math.pi * (kx * X / lx + ky * Y / ly + kz * Z / lz) + ph)
+        return f
+
+    S = conservative3d(fld(1.0), fld(0.3), fld(-0.2), fld(0.1), fld(1.0))
+    return Problem3D("random_smooth3d", nx, ny, nz, lx, state3d_from_samples(S, h), {"gamma": GAMMA, "mu": 0.0})
+
+
+def random_rough3d(nx, ny, nz, seed=0, lx=1.0):
+    """Seeded noisy 3D data (independent random nodal values and derivatives)
+    that drive every GENO branch; for parity tests only."""
+    rng = np.random.default_rng(seed)
+    S = np.empty((4, 20, nz, ny, nx))
+    for g in range(4):
+        shp = (nz, ny, nx)
+        S[g, 0:5] = conservative3d(rng.uniform(0.5, 1.5, shp), rng.uniform(-0.5, 0.5, shp),
+                                   rng.uniform(-0.5, 0.5, shp), rng.uniform(-0.5, 0.5, shp),
+                                   rng.uniform(0.5, 1.5, shp))
+        S[g, 5:20] = rng.normal(0.0, 0.5, size=(15,) + shp)
+    return Problem3D("random_rough3d", nx, ny, nz, lx, S, {"gamma": GAMMA, "mu": 0.0})
+
+
+def taylor_green3d(n, Ma=0.1, gamma=GAMMA, mu=None, Re=1600.0):
+    """Taylor-Green vortex on the periodic [0, 2 pi]^3: U = sin x cos y cos z,
+    V = -cos x sin y cos z, W = 0, rho = 1, p = 1/(gamma Ma^2) +
+    (cos 2x + cos 2y)(cos 2z + 2)/16 (unit velocity and length scales);
+    mu = 1/Re unless given."""
+    lx = 2 * math.pi
+    h = lx / n
+    X, Y, Z = lattice3(n, n, n, h)
+    U = np.sin(X) * np.cos(Y) * np.cos(Z)
+    V = -np.cos(X) * np.sin(Y) * np.cos(Z)
+    p = 1.0 / (gamma * Ma * Ma) + (np.cos(2 * X) + np.cos(2 * Y)) * (np.cos(2 * Z) + 2.0) / 16.0
+    S = conservative3d(1.0, U, V, 0.0, p, gamma)
+    return Problem3D("taylor_green3d", n, n, n, lx, state3d_from_samples(S, h),
+                     {"gamma": gamma, "mu": (1.0 / Re) if mu is None else mu, "Ma": Ma})
