@@ -18,9 +18,11 @@ import numpy as np
 
 from . import _lib
 from ._lib import (BC_NO_SLIP, BC_PERIODIC, BC_REFLECTING, BC_ZERO_GRADIENT, FLUX_6_2, FLUX_6_4, FLUX_LINEAR, FP32_FLUX, FP64,  # noqa: F401
-                   GRAD_CARRIED, GRAD_REEVAL, RECON_CHARACTERISTIC, RECON_CONSERVATIVE, FdcgksError, Params)
+                   GRAD_CARRIED, GRAD_REEVAL, RECON_CHARACTERISTIC, RECON_CONSERVATIVE, FdcgksError, Params,
+                   Params3D)
 
-__all__ = ["Problem", "Batch", "Params", "FdcgksError", "default_params", "make_params", "step1d_static"]
+__all__ = ["Problem", "Problem3D", "Batch", "Params", "Params3D", "FdcgksError", "default_params", "make_params",
+           "make_params3d", "step1d_static"]
 
 _VARIANTS = {"6-4": FLUX_6_4, "6-2": FLUX_6_2, "linear": FLUX_LINEAR}
 _BCS = {"periodic": BC_PERIODIC, "zero_gradient": BC_ZERO_GRADIENT, "reflecting": BC_REFLECTING,
@@ -468,3 +470,129 @@ class Batch:
         self._chk(self._L.fdcgks_batch_step(self._h, cfl, nsteps, t.ctypes.data_as(C.POINTER(C.c_double)),
                                             dt.ctypes.data_as(C.POINTER(C.c_double)), C.byref(n)))
         return t, dt, n.value
+
+
+# ---------------------------------------------------------------------- 3D
+def make_params3d(**kw) -> Params3D:
+    """fdcgks3d_params from keywords (names of the C struct; also
+    variant='6-4'|'6-2'|'linear', grad_carried=bool)."""
+    p = Params3D()
+    _lib.load().fdcgks3d_default_params(C.byref(p))
+    kw = dict(kw)
+    if "variant" in kw:
+        v = kw.pop("variant")
+        p.flux_variant = _VARIANTS[v] if isinstance(v, str) else int(v)
+    if kw.pop("grad_carried", False):
+        p.grad_update = GRAD_CARRIED
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise TypeError(f"unknown parameter {k!r}")
+        setattr(p, k, v)
+    return p
+
+
+class Problem3D:
+    """One 3D FD-CGKS problem (four grids, periodic) on the current HIP device
+    (see fdcgks3d_create).  A grid's state is a (20, nz, ny, nx) array: W[5],
+    Wx[5], Wy[5], Wz[5]."""
+
+    KERNEL_CLASSES = ("edge1", "node1", "update1", "edge2", "node2", "update2", "step")
+
+    def __init__(self, params: Params3D | None = None, stream=None, **kw):
+        self._L = _lib.load()
+        self.params = params if params is not None else make_params3d(**kw)
+        self._h = C.c_void_p()
+        s = _current_stream() if stream is None else C.c_void_p(stream)
+        _lib.check(self._L.fdcgks3d_create(C.byref(self.params), s, C.byref(self._h)), None, dim3=True)
+        p = self.params
+        self.shape = (20, p.nz, p.ny, p.nx)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._L.fdcgks3d_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, st):
+        return _lib.check(st, self._h, dim3=True)
+
+    def set_state(self, grid, S):
+        """S: (20, nz, ny, nx) numpy array or torch tensor on the device."""
+        if isinstance(S, np.ndarray):
+            S = np.ascontiguousarray(S, dtype=np.float64)
+        if tuple(S.shape) != self.shape:
+            raise ValueError(f"grid state must have shape {self.shape}")
+        ptr, dev, keep = _ptr(S)
+        self._chk(self._L.fdcgks3d_set_state(self._h, grid, ptr, dev))
+
+    def set_state_all(self, S):
+        """S: (4, 20, nz, ny, nx)."""
+        for g in range(4):
+            self.set_state(g, S[g])
+
+    def get_state(self, grid, device=None):
+        if device is None:
+            out = np.empty(self.shape)
+        else:
+            out = _torch().empty(self.shape, dtype=_torch().float64, device=device)
+        ptr, dev, keep = _ptr(out, True)
+        self._chk(self._L.fdcgks3d_get_state(self._h, grid, ptr, dev))
+        return out
+
+    def get_state_all(self):
+        return np.stack([self.get_state(g) for g in range(4)])
+
+    def compute_dt(self, cfl):
+        d = C.c_double()
+        self._chk(self._L.fdcgks3d_compute_dt(self._h, cfl, C.byref(d)))
+        return d.value
+
+    def diagnostics(self):
+        out = np.zeros(22)
+        self._chk(self._L.fdcgks3d_diagnostics(self._h, out.ctypes.data_as(C.POINTER(C.c_double))))
+        return out
+
+    def step(self, nsteps=1, dt=0.0, cfl=0.5, t_end=0.0, t=0.0):
+        """Returns (t, steps_done)."""
+        tt = C.c_double(t)
+        n = C.c_int32()
+        self._chk(self._L.fdcgks3d_step(self._h, dt, cfl, nsteps, t_end, C.byref(tt), C.byref(n)))
+        return tt.value, n.value
+
+    def step_timed(self, nsteps=1, dt=0.0, cfl=0.5, t_end=0.0, t=0.0):
+        """step() with per-kernel device milliseconds: (t, steps, {class: ms})."""
+        tt = C.c_double(t)
+        n = C.c_int32()
+        ms = (C.c_double * 7)()
+        self._chk(self._L.fdcgks3d_step_timed(self._h, dt, cfl, nsteps, t_end, C.byref(tt), C.byref(n), ms))
+        return tt.value, n.value, dict(zip(self.KERNEL_CLASSES, list(ms)))
+
+    def debug_stage(self, stage, dt):
+        """(state, accumulators) of stage 1 or the state of stage 2, each
+        (4, 20, nz, ny, nx), without committing the stage."""
+        out = np.zeros((4,) + self.shape)
+        acc = np.zeros_like(out)
+        self._chk(self._L.fdcgks3d_debug_stage(self._h, stage, dt, C.c_void_p(out.ctypes.data),
+                                               C.c_void_p(acc.ctypes.data)))
+        return (out, acc) if stage == 1 else out
+
+    def debug_intermediates(self, dt):
+        """Stage-1 interface records (4 classes, 3 normals, 31, nz, ny, nx) and
+        nodal fluxes (4 grids, 30, nz, ny, nx)."""
+        p = self.params
+        E = np.zeros((4, 3, 31, p.nz, p.ny, p.nx))
+        N = np.zeros((4, 30, p.nz, p.ny, p.nx))
+        self._chk(self._L.fdcgks3d_debug_intermediates(self._h, dt, C.c_void_p(E.ctypes.data),
+                                                       C.c_void_p(N.ctypes.data)))
+        return E, N

@@ -39,6 +39,19 @@ class Params(C.Structure):
     ]
 
 
+class Params3D(C.Structure):
+    """Mirror of fdcgks3d_params."""
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("flux_variant", C.c_int32),
+        ("flux_order", C.c_int32), ("grad_update", C.c_int32), ("geno_r", C.c_int32), ("reserved", C.c_int32),
+        ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double), ("lx", C.c_double),
+        ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
+        ("geno_C", C.c_double), ("geno_eps", C.c_double), ("geno_eps_a", C.c_double),
+        ("geno_d_central", C.c_double), ("geno_d_side", C.c_double),
+        ("tau_c1", C.c_double), ("tau_c2", C.c_double),
+    ]
+
+
 class FdcgksError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"fdcgks {STATUS_NAMES.get(status, status)}: {msg}")
@@ -76,6 +89,19 @@ SIGNATURES = {
     "fdcgks_batch_destroy": (C.c_int, [_vp]),
     "fdcgks_batch_last_error": (C.c_char_p, [_vp]),
     "fdcgks_batch_set_mode": (C.c_int, [_vp, _i32]),
+    # 3D (include/fdcgks3d.h)
+    "fdcgks3d_default_params": (None, [C.POINTER(Params3D)]),
+    "fdcgks3d_create": (C.c_int, [C.POINTER(Params3D), _vp, C.POINTER(_vp)]),
+    "fdcgks3d_set_state": (C.c_int, [_vp, _i32, _vp, _i32]),
+    "fdcgks3d_get_state": (C.c_int, [_vp, _i32, _vp, _i32]),
+    "fdcgks3d_compute_dt": (C.c_int, [_vp, C.c_double, _dp]),
+    "fdcgks3d_diagnostics": (C.c_int, [_vp, _dp]),
+    "fdcgks3d_step": (C.c_int, [_vp, C.c_double, C.c_double, _i32, C.c_double, _dp, C.POINTER(_i32)]),
+    "fdcgks3d_step_timed": (C.c_int, [_vp, C.c_double, C.c_double, _i32, C.c_double, _dp, C.POINTER(_i32), _dp]),
+    "fdcgks3d_debug_stage": (C.c_int, [_vp, _i32, C.c_double, _vp, _vp]),
+    "fdcgks3d_debug_intermediates": (C.c_int, [_vp, C.c_double, _vp, _vp]),
+    "fdcgks3d_destroy": (C.c_int, [_vp]),
+    "fdcgks3d_last_error": (C.c_char_p, [_vp]),
 }
 
 _lib = None
@@ -107,9 +133,10 @@ def load():
     return L
 
 
-def check(status, handle=None, batch=False):
+def check(status, handle=None, batch=False, dim3=False):
     if status != OK:
         L = load()
-        msg = (L.fdcgks_batch_last_error if batch else L.fdcgks_last_error)(handle)
+        msg = (L.fdcgks_batch_last_error if batch else
+               L.fdcgks3d_last_error if dim3 else L.fdcgks_last_error)(handle)
         raise FdcgksError(status, msg.decode() if msg else "")
     return status

@@ -12,8 +12,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdcgks.so")
-SOURCES = [os.path.join(CSRC, "fdcgks.hip")]
-DEPS = SOURCES + [os.path.join(CSRC, "gks_device.hpp"), os.path.join(CSRC, "adjoint.inc.hip"), os.path.join(CSRC, "gks_adjoint.hpp"), os.path.join(ROOT, "include", "fdcgks.h")]
+SOURCES = [os.path.join(CSRC, "fdcgks.hip"), os.path.join(CSRC, "fdcgks3d.hip")]
+DEPS = SOURCES + [os.path.join(CSRC, "gks_device.hpp"), os.path.join(CSRC, "gks3d_device.hpp"),
+                  os.path.join(CSRC, "adjoint.inc.hip"), os.path.join(CSRC, "gks_adjoint.hpp"),
+                  os.path.join(ROOT, "include", "fdcgks.h"), os.path.join(ROOT, "include", "fdcgks3d.h")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

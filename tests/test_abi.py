@@ -1,4 +1,4 @@
-"""The C-ABI library loads and exports every symbol include/fdcgks.h declares;
+"""The C-ABI library loads and exports every symbol include/*.h declares;
 argument validation happens before any device work (CPU only)."""
 import ctypes as C
 import os
@@ -10,9 +10,13 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_symbols():
-    src = open(os.path.join(ROOT, "include", "fdcgks.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(fdcgks_[a-z_0-9]+)\s*\(", src)))
+    out = set()
+    for name in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if name.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", name)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            out |= set(re.findall(r"\b(fdcgks(?:3d)?_[a-z_0-9]+)\s*\(", src))
+    return sorted(out)
 
 
 def test_header_declares_the_boundary():
@@ -30,17 +34,19 @@ def test_library_exports_every_declared_symbol():
     assert set(header_symbols()) <= set(_lib.SIGNATURES), "binding must declare every ABI symbol"
 
 
-def test_params_struct_matches_header(tmp_path):
-    """The binding's fdcgks_params mirror has the header's size and field
-    offsets (a C program compiled against include/fdcgks.h prints them)."""
+@pytest.mark.parametrize("cname,pyname", [("fdcgks_params", "Params"), ("fdcgks3d_params", "Params3D")])
+def test_params_struct_matches_header(tmp_path, cname, pyname):
+    """The binding's params mirrors have the headers' sizes and field offsets
+    (a C program compiled against include/ prints them)."""
     import subprocess
 
-    from paper_2606_17772_amd import Params
+    import paper_2606_17772_amd as P
+    Params = getattr(P, pyname)
     names = [f[0] for f in Params._fields_]
     src = tmp_path / "layout.c"
-    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fdcgks.h\"\nint main(void) {\n"
-                   '  printf("%zu\\n", sizeof(fdcgks_params));\n'
-                   + "".join(f'  printf("%zu\\n", offsetof(fdcgks_params, {n}));\n' for n in names)
+    src.write_text("#include <stdio.h>\n#include <stddef.h>\n#include \"fdcgks3d.h\"\nint main(void) {\n"
+                   f'  printf("%zu\\n", sizeof({cname}));\n'
+                   + "".join(f'  printf("%zu\\n", offsetof({cname}, {n}));\n' for n in names)
                    + "  return 0;\n}\n")
     exe = tmp_path / "layout"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
@@ -99,3 +105,25 @@ def test_null_arguments():
     assert L.fdcgks_set_option(None, 0, 1) == _lib.EINVAL
     assert L.fdcgks_get_option(None, 0, C.byref(v)) == _lib.EINVAL
     assert L.fdcgks_autotune(None, 3) == _lib.EINVAL
+
+
+def test_defaults_3d():
+    from paper_2606_17772_amd import make_params3d
+    p = make_params3d()
+    assert (p.nx, p.ny, p.nz, p.geno_r, p.flux_order) == (32, 32, 32, 3, 6)
+    assert p.geno_C == 20.0 and p.gamma == 1.4 and p.lx == 1.0 and p.reserved == 0
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=3), dict(nz=2), dict(gamma=1.0), dict(gamma=1.7), dict(mu=-1.0), dict(mu=1e-3, prandtl=0.0),
+    dict(flux_variant=3), dict(flux_order=7), dict(geno_r=9), dict(geno_eps=0.0), dict(tau_c2=-1.0),
+    dict(lx=0.0), dict(grad_update=2), dict(reserved=1), dict(nx=1024, ny=1024, nz=128),
+])
+def test_create3d_rejects_bad_params(bad):
+    from paper_2606_17772_amd import _lib, make_params3d
+    L = _lib.load()
+    p = make_params3d(**bad)
+    h = C.c_void_p()
+    st = L.fdcgks3d_create(C.byref(p), None, C.byref(h))
+    assert st == _lib.EINVAL and not h.value
+    assert L.fdcgks3d_last_error(None)

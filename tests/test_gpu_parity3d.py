@@ -1,0 +1,211 @@
+"""3D parity of the HIP path (include/fdcgks3d.h) against the oracle (GPU).
+
+Same seeded inputs on both sides, compared element by element on whole
+grids: interface records and nodal fluxes of stage 1, both stages, and a few
+whole steps.  Grids span two 64-wide interface blocks with a ragged tail
+along x, and non-cubic shapes.  Bar: per-plane max |gpu - oracle| /
+max(max |oracle|, floor) <= 1e-12 (FP64), the floor being the dimensional
+scale of the field (rho, rho a, rho a^2 over the domain length and time
+scale); the path function chi, a ratio of differences of nearly equal
+smoothness indicators, is held to max(1e-12, 4 x the oracle's own change
+under a one-ulp input perturbation).
+"""
+import numpy as np
+import pytest
+
+import workloads as WL
+from tests.helpers import settings
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _gpu_params(s):
+    from paper_2606_17772_amd import make_params3d
+    return make_params3d(nx=s["nx"], ny=s["ny"], nz=s["nz"], lx=s["lx"], gamma=s["gamma"], mu=s["mu"],
+                         prandtl=s["prandtl"], variant=s["variant"], geno_C=s["geno_C"], geno_r=s["geno_r"],
+                         geno_eps=s["geno_eps"], geno_eps_a=s["geno_eps_a"], geno_d_central=s["d_central"],
+                         geno_d_side=s["d_side"], tau_c1=s["tau_c1"], tau_c2=s["tau_c2"],
+                         flux_order=s.get("flux_order", 6), grad_carried=s.get("grad_carried", 0))
+
+
+def _problem(s, S):
+    from paper_2606_17772_amd import Problem3D
+    pb = Problem3D(_gpu_params(s))
+    pb.set_state_all(S)
+    return pb
+
+
+CASES = {
+    "rough_70x5x4": lambda: (settings(dim=3, nx=70, ny=5, nz=4, lx=1.0), WL.random_rough3d(70, 5, 4, seed=1)),
+    "smooth_9x8x7": lambda: (settings(dim=3, nx=9, ny=8, nz=7, lx=1.0), WL.random_smooth3d(9, 8, 7, seed=2)),
+    "smooth_ns_8": lambda: (settings(dim=3, nx=8, ny=8, nz=8, lx=1.0, mu=2e-3, prandtl=0.72),
+                            WL.random_smooth3d(8, 8, 8, seed=3)),
+    "rough_ns_6x7x5": lambda: (settings(dim=3, nx=6, ny=7, nz=5, lx=1.0, mu=2e-3, prandtl=0.72),
+                               WL.random_rough3d(6, 7, 5, seed=4)),
+    "rough_6x7x5_62": lambda: (settings(dim=3, nx=6, ny=7, nz=5, lx=1.0, variant="6-2"),
+                               WL.random_rough3d(6, 7, 5, seed=5)),
+    "rough_6x5x7_linear": lambda: (settings(dim=3, nx=6, ny=5, nz=7, lx=1.0, variant="linear"),
+                                   WL.random_rough3d(6, 5, 7, seed=6)),
+    "rough_7x6x5_order8": lambda: (settings(dim=3, nx=7, ny=6, nz=5, lx=1.0, flux_order=8),
+                                   WL.random_rough3d(7, 6, 5, seed=7)),
+    "rough_5x6x7_carried": lambda: (settings(dim=3, nx=5, ny=6, nz=7, lx=1.0, grad_carried=1),
+                                    WL.random_rough3d(5, 6, 7, seed=8)),
+}
+
+
+def _scales(S, gamma, L):
+    W = S[:, 0:5]
+    rho = W[:, 0]
+    u = W[:, 1:4] / rho[:, None]
+    p = (gamma - 1.0) * (W[:, 4] - 0.5 * rho * (u * u).sum(axis=1))
+    a = float((np.abs(u).max(axis=1) + np.sqrt(gamma * p / rho)).max())
+    r = float(rho.max())
+    Wr = np.array([r, r * a, r * a, r * a, r * a * a])
+    return {"W": Wr, "grad": Wr / L, "flux": Wr * a, "flux_t": Wr * a * a / L, "Wt": Wr * a / L}
+
+
+def _relerr(g, o, floors):
+    """Largest per-plane error; planes are everything but the last three axes,
+    floors broadcast over them."""
+    num = np.abs(g - o).max(axis=(-3, -2, -1))
+    den = np.maximum(np.abs(o).max(axis=(-3, -2, -1)), floors)
+    r = num / den
+    return float(r.max()), np.unravel_index(int(np.argmax(r)), r.shape)
+
+
+def _state_floors(sc):
+    return np.concatenate([sc["W"], sc["grad"], sc["grad"], sc["grad"]])
+
+
+def _edge_floors(sc):
+    one = np.concatenate([sc["flux"], sc["flux_t"], [1.0], sc["W"], sc["W"], sc["Wt"], sc["Wt"]])
+    return np.broadcast_to(one, (4, 3, 31))
+
+
+def _node_floors(sc):
+    one = np.concatenate([sc["flux"], sc["flux_t"]])
+    return np.broadcast_to(np.concatenate([one, one, one]), (4, 30))
+
+
+def _chi_sensitivity(oracle, par, dt, S, E0, trials=2):
+    rng = np.random.default_rng(0)
+    worst = 0.0
+    for _ in range(trials):
+        Sp = S * (1 + np.finfo(np.float64).eps * rng.choice([-1.0, 1.0], size=S.shape))
+        E1, _ = oracle.intermediates3d(par, dt, Sp)
+        worst = max(worst, float(np.abs(E1[:, :, 10] - E0[:, :, 10]).max()))
+    return worst
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_intermediates3d(oracle, name):
+    s, pr = CASES[name]()
+    dt = 0.2 * pr.h / 3.0
+    par = oracle.make_par(**s)
+    E, N = oracle.intermediates3d(par, dt, pr.S)
+    pb = _problem(s, pr.S)
+    gE, gN = pb.debug_intermediates(dt)
+    sc = _scales(pr.S, s["gamma"], s["lx"])
+    chi_tol = max(TOL, 4 * _chi_sensitivity(oracle, par, dt, pr.S, E))
+    fl = _edge_floors(sc)
+    mask = np.ones(31, bool)
+    mask[10] = False
+    err, at = _relerr(gE[:, :, mask], E[:, :, mask], fl[:, :, mask])
+    print(f"{name}: interface records {err:.2e} at {at}, chi {np.abs(gE[:, :, 10] - E[:, :, 10]).max():.2e} "
+          f"(bar {chi_tol:.1e})")
+    assert err <= TOL, (name, err, at)
+    assert np.abs(gE[:, :, 10] - E[:, :, 10]).max() <= chi_tol
+    err, at = _relerr(gN, N, _node_floors(sc))
+    print(f"{name}: nodal fluxes {err:.2e} at {at}")
+    assert err <= TOL, (name, err, at)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_stages3d(oracle, name):
+    s, pr = CASES[name]()
+    dt = 0.2 * pr.h / 3.0
+    par = oracle.make_par(**s)
+    pb = _problem(s, pr.S)
+    g1, ga = pb.debug_stage(1, dt)
+    o1, oa = oracle.stage3d(par, 1, dt, pr.S)
+    fl = _state_floors(_scales(pr.S, s["gamma"], s["lx"]))
+    for lab, g, o in (("stage1", g1, o1), ("acc", ga, oa)):
+        err, at = _relerr(g, o, fl)
+        print(f"{name}: {lab} {err:.2e} at {at}")
+        assert err <= TOL, (name, lab, err, at)
+    # stage 2 from the same (the GPU's) stage-1 buffers on both sides
+    g2 = pb.debug_stage(2, dt)
+    o2 = oracle.stage3d(par, 2, dt, g1, ga)
+    err, at = _relerr(g2, o2, fl)
+    print(f"{name}: stage2 {err:.2e} at {at}")
+    assert err <= TOL, (name, "stage2", err, at)
+
+
+@pytest.mark.parametrize("name", ["smooth_9x8x7", "smooth_ns_8", "rough_70x5x4"])
+def test_steps3d(oracle, name):
+    """Three CFL steps: the same time steps, and states within max(1e-12, 4 x
+    the oracle's one-ulp sensitivity over the same steps)."""
+    s, pr = CASES[name]()
+    par = oracle.make_par(**s)
+    pb = _problem(s, pr.S)
+    cfl = 0.4
+    dt_g = pb.compute_dt(cfl)
+    dt_o = oracle.dt3d(par, pr.S, cfl)
+    assert abs(dt_g - dt_o) <= 1e-14 * dt_o
+    t, k = pb.step(nsteps=3, dt=dt_o)
+    assert k == 3
+    G = pb.get_state_all()
+    O, _, _ = oracle.step3d(par, pr.S, 3, dt=dt_o)
+    fl = _state_floors(_scales(pr.S, s["gamma"], s["lx"]))
+    rng = np.random.default_rng(1)
+    Sp = pr.S * (1 + np.finfo(np.float64).eps * rng.choice([-1.0, 1.0], size=pr.S.shape))
+    Op, _, _ = oracle.step3d(par, Sp, 3, dt=dt_o)
+    sens = _relerr(Op, O, fl)[0]
+    err, at = _relerr(G, O, fl)
+    print(f"{name}: 3 steps {err:.2e} at {at} (oracle one-ulp sensitivity {sens:.1e})")
+    assert err <= max(TOL, 4 * sens), (name, err, at, sens)
+
+
+def test_free_stream_and_conservation3d():
+    from paper_2606_17772_amd import Problem3D
+    n = 6
+    S = np.zeros((4, 20, n, n, n))
+    S[:, 0:5] = WL.conservative3d(1.3, 0.4, -0.7, 0.25, 2.0)[None, :, None, None, None]
+    pb = Problem3D(nx=n, ny=n, nz=n, lx=1.0)
+    pb.set_state_all(S)
+    pb.step(nsteps=2, dt=0.01)
+    assert np.abs(pb.get_state_all() - S).max() < 1e-14
+    pr = WL.random_rough3d(9, 7, 6, seed=11)
+    pb = Problem3D(nx=9, ny=7, nz=6, lx=pr.lx)
+    pb.set_state_all(pr.S)
+    d0 = pb.diagnostics()
+    pb.step(nsteps=2, dt=0.2 * pr.h / 3)
+    d1 = pb.diagnostics()
+    for q in range(20):
+        g, c = divmod(q, 5)
+        assert abs(d1[q] - d0[q]) <= 1e-13 * np.abs(pr.S[g, c]).sum(), q
+
+
+def test_nonphysical_state_is_reported_and_rolled_back():
+    """A node with p < 0 has no CFL step; a NaN in the state makes the first
+    step fail with ENONPHYS and leaves the state as it was.  (A p < 0 node
+    alone need not survive a step: its nodal solver stays finite and the
+    update may bring p back above 0.)"""
+    from paper_2606_17772_amd import FdcgksError, Problem3D, _lib
+    pr = WL.random_smooth3d(6, 6, 6, seed=12)
+    S = pr.S.copy()
+    S[2, 4, 3, 2, 1] = 0.01 * S[2, 4, 3, 2, 1]  # energy below the kinetic energy: p < 0
+    pb = Problem3D(nx=6, ny=6, nz=6, lx=pr.lx)
+    pb.set_state_all(S)
+    with pytest.raises(FdcgksError) as ei:
+        pb.compute_dt(0.4)
+    assert ei.value.status == _lib.ENONPHYS
+    S = pr.S.copy()
+    S[1, 4, 2, 3, 4] = np.nan
+    pb.set_state_all(S)
+    with pytest.raises(FdcgksError) as ei:
+        pb.step(nsteps=2, dt=0.01)
+    assert ei.value.status == _lib.ENONPHYS
+    assert np.array_equal(pb.get_state_all(), S, equal_nan=True)
