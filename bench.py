@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-bounded", action="store_true", help="skip the walled-domain leg")
     ap.add_argument("--no-order8", action="store_true", help="skip the order-8 compact flux comparison")
     ap.add_argument("--no-pcie", action="store_true", help="skip the host-buffer (PCIe-inclusive) leg")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D (four-grid) leg")
+    ap.add_argument("--n3d", type=int, default=128, help="side of the 3D Taylor-Green leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 512 MiB device copy first (reference for HBM byte counters)")
     return ap.parse_args()
@@ -145,6 +147,15 @@ def cpu_baseline(n):
     sec = time.perf_counter() - t0
     cfg["vortex_512"] = {"sample": "one CFL step", "seconds_per_step": round(sec, 3),
                          "node_updates_per_s": 2 * 512 * 512 * 2 / sec}
+    # 3D Taylor-Green vortex: stage 1 at 32^3 (the GPU leg runs 128^3)
+    tg = WL.taylor_green3d(32)
+    p4 = O.make_par(dim=3, nx=32, ny=32, nz=32, lx=tg.lx, mu=tg.params["mu"], prandtl=PR)
+    dt4 = O.dt3d(p4, tg.S, 0.4)
+    t0 = time.perf_counter()
+    O.stage3d(p4, 1, dt4, tg.S)
+    sec = time.perf_counter() - t0
+    cfg["taylor_green_3d"] = {"sample": "stage 1 of one step at 32^3 x 4 grids", "seconds": round(sec, 3),
+                              "node_updates_per_s": 4 * 32 ** 3 / sec}
     out["configs"] = cfg
     return out
 
@@ -558,6 +569,46 @@ def graph_comparison(n=64, steps=400):
             "separate_launch_node_updates_per_s": res["separate"], "speedup": res["graph"] / res["separate"]}
 
 
+def three_d_leg(n=128, steps=5):
+    """The 3D extension (four grids: primary plus the three face-offset
+    duals): a Taylor-Green vortex, Re 1600, Ma 0.1, Pr 0.72, on n^3 cells per
+    grid, stepped at a fixed CFL-0.4 dt; node-updates count all four grids.
+    Not one of the paper's configurations (its tests are 1D and 2D)."""
+    import torch
+
+    import workloads as WL
+    from paper_2606_17772_amd import Problem3D
+    pr = WL.taylor_green3d(n)
+    pb = Problem3D(nx=n, ny=n, nz=n, lx=pr.lx, mu=pr.params["mu"], prandtl=PR)
+    dev = torch.device("cuda:0")
+    for g in range(4):
+        pb.set_state(g, torch.from_numpy(pr.S[g]).to(dev))
+    dt = pb.compute_dt(0.4)
+    pb.step(nsteps=1, dt=dt)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    _, k = pb.step(nsteps=steps, dt=dt)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    _, _, kms = pb.step_timed(nsteps=2, dt=dt)
+    d = pb.diagnostics()
+    nodes = 4 * n ** 3
+    solves = 12 * n ** 3
+    edge1 = kms["edge1"] / 2
+    del pb
+    torch.cuda.empty_cache()
+    return {"workload": f"3D Taylor-Green vortex {n}^3 x 4 grids, Re 1600, Ma 0.1, Pr 0.72, (6-4) GENO, FP64, "
+                        f"fixed dt (CFL 0.4), {steps} steps",
+            "node_updates_per_s": nodes * 2 / (ms * 1e-3), "ms_per_step": round(ms, 3),
+            "kernel_ms_per_step": {k2: round(v / 2, 4) for k2, v in kms.items()},
+            "interface_solves_per_s_stage1": solves / (edge1 * 1e-3),
+            "min_rho": d[20], "min_p": d[21]}
+
+
 def adjoint_comparison(pb, n, reps=2):
     """Vector-Jacobian product of one step (fdcgks_step_vjp: forward
     recompute at the frozen dt, then the reverse sweep) on the same workload
@@ -704,6 +755,9 @@ def main():
         out["bounded"] = bounded_comparison(n, tiles)
     if not args.no_graph:
         out["graph_replay"] = graph_comparison()
+    if not args.no_3d:
+        torch.cuda.empty_cache()
+        out["three_d"] = three_d_leg(args.n3d)
     if not args.no_configs:
         out["configs"] = config_legs(tiles)
     if not args.no_batch:
