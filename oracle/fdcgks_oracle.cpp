@@ -1706,6 +1706,65 @@ void orc_intermediates3d(const Par* p, double dt, const double* S, double* E, do
   }
 }
 
+// One stage evaluated at a sample of nodes only (for grids too large for a
+// whole oracle sweep): grid[s] (0..3) and kk[s], jj[s], ii[s] name the stored
+// nodes.  Each sample evaluates the interface points and nodes its operator
+// reads from the whole state.  out[s*40 .. +20]: the stage output state,
+// out[s*40+20 .. +20]: the stage-1 accumulators (zero for stage 2).
+void orc_stage3d_sample(const Par* p, int stage, double dt, const double* S, const double* acc, int ns,
+                        const int* grid, const int* kk, const int* jj, const int* ii, double* out) {
+  const int nx = p->nx, ny = p->ny, nz = p->nz;
+  const double h = p->lx / nx;
+  const long pl = (long)nx * ny * nz, gsz = 20 * pl;
+  const double* Sg[4] = {S, S + gsz, S + 2 * gsz, S + 3 * gsz};
+  const Grid3<double> G(*p, Sg);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int s = 0; s < ns; ++s) {
+    const int g = grid[s];
+    const int I = lattice3(g, 0, ii[s]), J = lattice3(g, 1, jj[s]), L = lattice3(g, 2, kk[s]);
+    const int reach = p->flux_order == 8 ? 2 : 1;
+    // the 12 interface points (offsets -3, -1, 1, 3 per axis) and the nodes
+    // (offsets -2 reach .. 2 reach per axis) the operator reads
+    EdgeRes3<double> E[3][4];
+    NodeRes3<double> Nn[3][5];
+    for (int ax = 0; ax < 3; ++ax) {
+      const int dI = ax == 0, dJ = ax == 1, dL = ax == 2;
+      for (int m = 0; m < 4; ++m) {
+        const int o = 2 * m - 3;
+        E[ax][m] = edge3d(*p, G, I + o * dI, J + o * dJ, L + o * dL, h, dt);
+      }
+      for (int m = -reach; m <= reach; ++m)
+        Nn[ax][m + 2] = node3d(*p, G, I + 2 * m * dI, J + 2 * m * dJ, L + 2 * m * dL, h);
+    }
+    auto axis_off = [&](int I2, int J2, int L2, int& ax) {
+      ax = (J2 != J) ? 1 : ((L2 != L) ? 2 : 0);
+      return ax == 0 ? I2 - I : (ax == 1 ? J2 - J : L2 - L);
+    };
+    auto edgef = [&](int I2, int J2, int L2) -> const EdgeRes3<double>& {
+      int ax;
+      const int o = axis_off(I2, J2, L2, ax);
+      return E[ax][(o + 3) / 2];
+    };
+    auto nodef = [&](int I2, int J2, int L2) -> const NodeRes3<double>& {
+      int ax;
+      const int o = axis_off(I2, J2, L2, ax);
+      return Nn[ax][o / 2 + 2];
+    };
+    NodeOp3<double> op = node_operator3<double>(*p, I, J, L, h, edgef, nodef);
+    const long k = ((long)kk[s] * ny + jj[s]) * nx + ii[s];
+    double st[20], ac[20], o20[20], a20[20];
+    for (int f = 0; f < 20; ++f) {
+      st[f] = S[g * gsz + f * pl + k];
+      ac[f] = acc ? acc[g * gsz + f * pl + k] : 0.0;
+    }
+    s2o4_3d(stage, dt, op, st, ac, o20, a20, p->grad_carried);
+    for (int f = 0; f < 20; ++f) {
+      out[s * 40 + f] = o20[f];
+      out[s * 40 + 20 + f] = stage == 1 ? a20[f] : 0.0;
+    }
+  }
+}
+
 // --- 1D --------------------------------------------------------------------
 // S: 6 planes of N (W[3], Wx[3]) per line; nl lines (1, or 2 with the shifted
 // copy) stored one after another.

@@ -131,6 +131,7 @@ def lib():
             "orc_dt3d": (d, [P, _dp, d]),
             "orc_step3d": (i, [P, _dp, i, d, d, d, _dp]),
             "orc_intermediates3d": (None, [P, d, _dp, _dp, _dp]),
+            "orc_stage3d_sample": (None, [P, i, d, _dp, _dp, i, _ip, _ip, _ip, _ip, _dp]),
             "orc_stage1d": (None, [P, i, d, _dp, _dp, _dp, _dp]),
             "orc_dt1d": (d, [P, _dp, d]),
             "orc_step1d": (i, [P, _dp, i, d, d, d, _dp]),
@@ -376,6 +377,18 @@ def intermediates3d(par, dt, S):
     N = np.zeros((4, 30) + shp)
     lib().orc_intermediates3d(C.byref(par), dt, _p(_s3(par, S)), _p(E), _p(N))
     return E, N
+
+
+def stage3d_sample(par, stage, dt, S, grid, kk, jj, ii, acc=None):
+    """Stage output at the listed nodes only: (ns, 20) state and (ns, 20)
+    accumulators."""
+    ar = [np.ascontiguousarray(a, dtype=np.int32) for a in (grid, kk, jj, ii)]
+    ns = ar[0].size
+    out = np.zeros((ns, 40))
+    ip = lambda a: a.ctypes.data_as(_ip)  # noqa: E731
+    lib().orc_stage3d_sample(C.byref(par), stage, dt, _p(_s3(par, S)), _p(None if acc is None else _s3(par, acc)),
+                             ns, *(ip(a) for a in ar), _p(out))
+    return out[:, :20], out[:, 20:]
 
 
 # ---------------------------------------------------------------------- 1D

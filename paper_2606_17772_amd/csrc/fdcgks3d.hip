@@ -40,7 +40,8 @@ namespace {
 constexpr int NSP = 20;   // state planes per grid
 constexpr int NEP = 31;   // edge planes per (class, axis)
 constexpr int NNP = 30;   // node-flux planes per grid
-constexpr int EDGE_LANES = 64;
+constexpr int EDGE_THREADS = 256;   // interface sweep block: four waves
+constexpr int EDGE_POINTS = 85;     // interface points per block (3 solves each)
 // Minimum waves per SIMD of the interface and node sweeps.  Measured on a
 // 128^3 Navier-Stokes step: the interface sweep is fastest at 1 (about 440
 // registers, no spills; 2 waves spill 192 registers and take 40% longer),
@@ -102,35 +103,40 @@ __device__ __forceinline__ long cell_along(long cell, const Axis& a, int m) {
 __device__ __forceinline__ int lperm(int ax, int cc) { return cc == 1 ? 1 + ax : (cc == 1 + ax ? 1 : cc); }
 
 // --------------------------------------------------------- interface sweep
-// One thread per (interface point, normal axis): block = 64 points of one
-// class along x (lanes) x 3 axes (waves, so every wave takes one axis).  The
-// axis is a run-time value, so every component permutation goes through LDS
-// (addresses are free to compute; registers cannot be indexed at run time):
+// One thread per (interface point, normal axis): thread t of a block takes
+// point t / 3 of EDGE_POINTS consecutive points of one class (cells in
+// x-fastest order) and normal axis t % 3, so the three solves of a point sit
+// in neighbouring lanes.  A block is four waves (255 busy threads): the solver
+// needs about 440 registers, one wave per SIMD, and a four-wave block keeps
+// all four SIMDs of a compute unit busy (a three-wave block left one idle).
+// The axis varies across a wave, so every component permutation goes through
+// LDS (addresses are free to compute; registers cannot be indexed at run
+// time):
 //   phase 1: line reconstruction -> LDS (global component order);
 //   phase 2: the solve's inputs read from LDS in the line's local frame, the
 //            tangential slopes from the other two lines' entries;
 //   phase 3: the solve; fluxes to HBM, interface values -> LDS;
 //   phase 4: blend of the interface values over the three directions.
 template <bool VALUES>
-__global__ __launch_bounds__(3 * EDGE_LANES, FDCGKS3D_EDGE_WAVES) void k_edges3d(Consts k, Geo3 g, double dt, const double* __restrict__ S,
-                                                            double* __restrict__ E) {
-  __shared__ double xs[3][20][EDGE_LANES];
-  const int lane = threadIdx.x % EDGE_LANES;
-  const int ax = threadIdx.x / EDGE_LANES;  // wave-uniform
+__global__ __launch_bounds__(EDGE_THREADS, FDCGKS3D_EDGE_WAVES) void k_edges3d(Consts k, Geo3 g, double dt,
+                                                                              const double* __restrict__ S,
+                                                                              double* __restrict__ E) {
+  __shared__ double xs[20][EDGE_THREADS];
+  const int t = threadIdx.x;
+  const int ax = t % 3;
+  const int base = t - ax;  // slot of this point's x solve
   const int q = blockIdx.y;
-  const int nbx = (g.nx + EDGE_LANES - 1) / EDGE_LANES;
-  const int row = blockIdx.x / nbx;  // k * ny + j
-  const int i = (blockIdx.x % nbx) * EDGE_LANES + lane;
-  const bool live = i < g.nx;
+  const long P = (long)blockIdx.x * EDGE_POINTS + t / 3;
+  const bool live = t < 3 * EDGE_POINTS && P < g.n;
+  const long cell = live ? P : 0;
   Cell c;
-  c.c[0] = live ? i : g.nx - 1;
-  c.c[1] = row % g.ny;
-  c.c[2] = row / g.ny;
+  c.c[0] = (int)(cell % g.nx);
+  c.c[1] = (int)((cell / g.nx) % g.ny);
+  c.c[2] = (int)(cell / ((long)g.nx * g.ny));
   const int qm = class_mask(q);
   const bool even = (qm >> ax) & 1;
   const int gl = grid_of(qm ^ (1 << ax));  // grid of this line's nodes
   const double* Sg = S + (long)gl * NSP * g.n;
-  const long cell = cell_index(g, c.c[0], c.c[1], c.c[2]);
   const Axis A = axis_of(g, c, ax);
   // phase 1: line reconstruction (chi from the density line)
   double chi;
@@ -144,10 +150,10 @@ __global__ __launch_bounds__(3 * EDGE_LANES, FDCGKS3D_EDGE_WAVES) void k_edges3d
       const double* X = Sg + (long)(5 * (1 + ax) + cc) * g.n;
       fdk::IfaceRec r = fdk::recon_iface<double>(k, W[at[0]], W[at[1]], W[at[2]], W[at[3]], X[at[0]], X[at[1]],
                                                  X[at[2]], X[at[3]], g.h, g.invh);
-      xs[ax][cc][lane] = r.vl;
-      xs[ax][5 + cc][lane] = r.vr;
-      xs[ax][10 + cc][lane] = r.dl;
-      xs[ax][15 + cc][lane] = r.dr;
+      xs[cc][t] = r.vl;
+      xs[5 + cc][t] = r.vr;
+      xs[10 + cc][t] = r.dl;
+      xs[15 + cc][t] = r.dr;
       if (cc == 0) chi = fdk::g_min(r.cl, r.cr);
     }
   }
@@ -155,17 +161,17 @@ __global__ __launch_bounds__(3 * EDGE_LANES, FDCGKS3D_EDGE_WAVES) void k_edges3d
   // phase 2: inputs in the local frame; the local v and w are the velocities
   // of axes av and aw, whose lines give the tangential slopes (mean of their
   // l and r derivatives)
-  const int av = ax == 1 ? 0 : 1, aw = ax == 2 ? 0 : 2;
+  const int tv = base + (ax == 1 ? 0 : 1), tw = base + (ax == 2 ? 0 : 2);
   fdk3::GksIO3 io;
 #pragma unroll
   for (int cc = 0; cc < 5; ++cc) {
     const int p = lperm(ax, cc);
-    io.WL[cc] = xs[ax][p][lane];
-    io.WR[cc] = xs[ax][5 + p][lane];
-    io.nL[cc] = xs[ax][10 + p][lane];
-    io.nR[cc] = xs[ax][15 + p][lane];
-    io.Wt[cc] = 0.5 * (xs[av][10 + p][lane] + xs[av][15 + p][lane]);
-    io.Wt2[cc] = 0.5 * (xs[aw][10 + p][lane] + xs[aw][15 + p][lane]);
+    io.WL[cc] = xs[p][t];
+    io.WR[cc] = xs[5 + p][t];
+    io.nL[cc] = xs[10 + p][t];
+    io.nR[cc] = xs[15 + p][t];
+    io.Wt[cc] = 0.5 * (xs[10 + p][tv] + xs[15 + p][tv]);
+    io.Wt2[cc] = 0.5 * (xs[10 + p][tw] + xs[15 + p][tw]);
   }
   __syncthreads();
   // phase 3: the solve; fluxes go out, interface values to LDS (global order)
@@ -174,11 +180,11 @@ __global__ __launch_bounds__(3 * EDGE_LANES, FDCGKS3D_EDGE_WAVES) void k_edges3d
 #pragma unroll
   for (int cc = 0; cc < 5; ++cc) {
     const int p = lperm(ax, cc);
-    xs[ax][10 + p][lane] = io.Wlt[cc];
-    xs[ax][15 + p][lane] = io.Wrt[cc];
+    xs[10 + p][t] = io.Wlt[cc];
+    xs[15 + p][t] = io.Wrt[cc];
     if (VALUES) {
-      xs[ax][p][lane] = io.Wl[cc];
-      xs[ax][5 + p][lane] = io.Wr[cc];
+      xs[p][t] = io.Wl[cc];
+      xs[5 + p][t] = io.Wr[cc];
     }
     if (live) {
       Eo[(long)(5 + p) * g.n] = io.Ft[cc];
@@ -188,17 +194,17 @@ __global__ __launch_bounds__(3 * EDGE_LANES, FDCGKS3D_EDGE_WAVES) void k_edges3d
   __syncthreads();
   // phase 4: blend, weight 1/3 per direction (the normal one with its own
   // side, the tangential ones with the mean of l and r)
-  const int b1 = ax == 0 ? 1 : 0, b2 = ax == 2 ? 1 : 2;  // the other axes, increasing
+  const int b1 = base + (ax == 0 ? 1 : 0), b2 = base + (ax == 2 ? 1 : 2);  // the other axes, increasing
   if (!live) return;
 #pragma unroll
   for (int cc = 0; cc < 5; ++cc) {
-    const double st = (xs[b1][10 + cc][lane] + xs[b1][15 + cc][lane]) + (xs[b2][10 + cc][lane] + xs[b2][15 + cc][lane]);
-    Eo[(21 + cc) * g.n] = xs[ax][10 + cc][lane] / 3.0 + st / 6.0;
-    Eo[(26 + cc) * g.n] = xs[ax][15 + cc][lane] / 3.0 + st / 6.0;
+    const double st = (xs[10 + cc][b1] + xs[15 + cc][b1]) + (xs[10 + cc][b2] + xs[15 + cc][b2]);
+    Eo[(21 + cc) * g.n] = xs[10 + cc][t] / 3.0 + st / 6.0;
+    Eo[(26 + cc) * g.n] = xs[15 + cc][t] / 3.0 + st / 6.0;
     if (VALUES) {
-      const double sv = (xs[b1][cc][lane] + xs[b1][5 + cc][lane]) + (xs[b2][cc][lane] + xs[b2][5 + cc][lane]);
-      Eo[(11 + cc) * g.n] = xs[ax][cc][lane] / 3.0 + sv / 6.0;
-      Eo[(16 + cc) * g.n] = xs[ax][5 + cc][lane] / 3.0 + sv / 6.0;
+      const double sv = (xs[cc][b1] + xs[5 + cc][b1]) + (xs[cc][b2] + xs[5 + cc][b2]);
+      Eo[(11 + cc) * g.n] = xs[cc][t] / 3.0 + sv / 6.0;
+      Eo[(16 + cc) * g.n] = xs[5 + cc][t] / 3.0 + sv / 6.0;
     }
   }
   Eo[10 * g.n] = chi;
@@ -522,7 +528,7 @@ struct Timer {
 fdcgks_status stage3d(fdcgks3d_problem* pb, int stage, double dt, const double* Sin, const double* Ain, double* Out,
                       double* Aout, Timer* tm) {
   const Geo3& g = pb->g;
-  const dim3 eg(blocks_x(g, EDGE_LANES), 4), eb(3 * EDGE_LANES);
+  const dim3 eg((unsigned)((g.n + EDGE_POINTS - 1) / EDGE_POINTS), 4), eb(EDGE_THREADS);
   const dim3 ng(blocks_x(g, NODE_BLOCK), 4), nb(NODE_BLOCK);
   const dim3 ug(blocks_x(g, UPD_BLOCK), 4), ub(UPD_BLOCK);
   if (stage == 1) {
@@ -791,7 +797,7 @@ fdcgks_status fdcgks3d_debug_intermediates(fdcgks3d_problem* pb, double dt, doub
   if (!edges || !nodes || !(dt > 0)) return fail(pb, FDCGKS_EINVAL, "need edges, nodes and dt > 0");
   if (!all_set(pb)) return fail(pb, FDCGKS_ESTATE, "set the state of all four grids first");
   const Geo3& g = pb->g;
-  const dim3 eg(blocks_x(g, EDGE_LANES), 4), eb(3 * EDGE_LANES);
+  const dim3 eg((unsigned)((g.n + EDGE_POINTS - 1) / EDGE_POINTS), 4), eb(EDGE_THREADS);
   const dim3 ng(blocks_x(g, NODE_BLOCK), 4), nb(NODE_BLOCK);
   hipLaunchKernelGGL(k_edges3d<true>, eg, eb, 0, pb->stream, pb->k, g, dt, pb->S[pb->cur], pb->E);
   hipLaunchKernelGGL(k_nodes3d<true>, ng, nb, 0, pb->stream, pb->k, g, pb->S[pb->cur], pb->Nb);

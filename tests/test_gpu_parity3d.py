@@ -209,3 +209,47 @@ def test_nonphysical_state_is_reported_and_rolled_back():
         pb.step(nsteps=2, dt=0.01)
     assert ei.value.status == _lib.ENONPHYS
     assert np.array_equal(pb.get_state_all(), S, equal_nan=True)
+
+
+def test_full_size_sampled_taylor_green_128(oracle):
+    """The bench's 3D configuration (Taylor-Green vortex, 128^3 on each grid,
+    Navier-Stokes) at its CFL dt: both stages at 48 sampled nodes of every
+    grid, against the oracle evaluating those nodes from the whole state.
+    Bar: max(1e-12, 4 x the oracle's one-ulp sensitivity of the same sampled
+    stage), with the dimensional floors."""
+    from paper_2606_17772_amd import Problem3D
+    n = 128
+    pr = WL.taylor_green3d(n)
+    s = settings(dim=3, nx=n, ny=n, nz=n, lx=pr.lx, mu=pr.params["mu"], prandtl=0.72)
+    par = oracle.make_par(**s)
+    pb = Problem3D(_gpu_params(s))
+    pb.set_state_all(pr.S)
+    dt = pb.compute_dt(0.4)
+    g1, ga = pb.debug_stage(1, dt)
+    g2 = pb.debug_stage(2, dt)
+    del pb
+    rng = np.random.default_rng(5)
+    ns = 48
+    grid = np.repeat(np.arange(4), ns // 4)
+    kk, jj, ii = (rng.integers(0, n, ns) for _ in range(3))
+    fl = _state_floors(_scales(pr.S, s["gamma"], s["lx"]))
+    Sp = pr.S * (1 + np.finfo(np.float64).eps * rng.choice([-1.0, 1.0], size=pr.S.shape))
+    for stage in (1, 2):
+        src, acc = (pr.S, None) if stage == 1 else (g1, ga)
+        srcp = Sp if stage == 1 else g1 * (1 + np.finfo(np.float64).eps * rng.choice([-1.0, 1.0], size=g1.shape))
+        o, oa = oracle.stage3d_sample(par, stage, dt, src, grid, kk, jj, ii, acc=acc)
+        op, _ = oracle.stage3d_sample(par, stage, dt, srcp, grid, kk, jj, ii, acc=acc)
+        G = g1 if stage == 1 else g2
+        got = np.stack([G[grid[q], :, kk[q], jj[q], ii[q]] for q in range(ns)])
+        den = np.maximum(np.abs(o).max(axis=0), fl)
+        err = float((np.abs(got - o).max(axis=0) / den).max())
+        sens = float((np.abs(op - o).max(axis=0) / den).max())
+        vals = float((np.abs(got - o)[:, :5].max(axis=0) / den[:5]).max())
+        bar = max(TOL, 4 * sens)
+        print(f"128^3 Taylor-Green stage {stage}: max-relative error {err:.2e} (values {vals:.2e}); "
+              f"oracle one-ulp sensitivity {sens:.2e}; bar {bar:.2e}")
+        assert err <= bar, (stage, err, bar)
+        if stage == 1:
+            gota = np.stack([ga[grid[q], :, kk[q], jj[q], ii[q]] for q in range(ns)])
+            erra = float((np.abs(gota - oa).max(axis=0) / den).max())
+            assert erra <= bar, ("acc", erra, bar)

@@ -202,3 +202,22 @@ def test_3d_accuracy_order(oracle):
         errs.append((e.mean(), e.max()))
     (a, b), (c, d) = errs
     assert np.log2(a / c) > 5.5 and np.log2(b / d) > 5.5, errs
+
+
+def test_sampled_stage_equals_whole_grid(oracle):
+    """The sampled 3D stage (used at sizes too large for a whole sweep) gives
+    the whole-grid stage's values at its nodes, bit for bit (order 6 and 8)."""
+    pr = WL.random_rough3d(6, 5, 7, seed=9)
+    rng = np.random.default_rng(3)
+    ns = 30
+    grid, kk, jj, ii = (rng.integers(0, 4, ns), rng.integers(0, 7, ns), rng.integers(0, 5, ns),
+                        rng.integers(0, 6, ns))
+    for order in (6, 8):
+        par = _p3(oracle, 6, 5, 7, lx=pr.lx, flux_order=order, mu=1e-3, prandtl=0.72)
+        o1, a1 = oracle.stage3d(par, 1, 0.01, pr.S)
+        s1, sa = oracle.stage3d_sample(par, 1, 0.01, pr.S, grid, kk, jj, ii)
+        o2 = oracle.stage3d(par, 2, 0.01, o1, a1)
+        s2, _ = oracle.stage3d_sample(par, 2, 0.01, o1, grid, kk, jj, ii, acc=a1)
+        for q in range(ns):
+            at = (grid[q], slice(None), kk[q], jj[q], ii[q])
+            assert np.array_equal(s1[q], o1[at]) and np.array_equal(sa[q], a1[at]) and np.array_equal(s2[q], o2[at])
