@@ -23,3 +23,21 @@ def test_roofline_constants():
     # 0.81 + 3.36 GB of the 2048^2 workload)
     assert 6000 < bench.FLOPS_PER_IFACE_POINT_STAGE1 < 8000
     assert 4.17e9 <= bench.TRAFFIC_BYTES_PER_LAUNCH_STAGE1 < 6e9
+
+
+def test_roofline_constants_come_from_the_committed_profile():
+    """bench.py's flop and traffic figures for the stage-1 interface sweep are
+    the ones the committed rocprofv3 summary records for that kernel (its
+    counter table row: flop / unit, read GB, written GB after calibration)."""
+    import re
+    sys.path.insert(0, ROOT)
+    import bench
+    rows = [ln for ln in open(os.path.join(ROOT, "profiles", "k_edges2d_shear2048.md"))
+            if ln.startswith("| `k_edges2d<1, double, false>`") and ln.count("|") >= 8]
+    assert rows, "counter row of the stage-1 interface sweep"
+    cells = [c.strip() for c in rows[0].strip().strip("|").split("|")]
+    flop_per_point = int(cells[4])
+    read_gb, written_gb = float(cells[5]), float(cells[6])
+    assert bench.FLOPS_PER_IFACE_POINT_STAGE1 == flop_per_point
+    assert abs(bench.TRAFFIC_BYTES_PER_LAUNCH_STAGE1 - (read_gb + written_gb) * 1e9) <= 2e6
+    assert re.search(r"2 \(n\+3\)\^2", open(os.path.join(ROOT, "profiles", "k_edges2d_shear2048.md")).read())
