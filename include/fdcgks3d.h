@@ -85,8 +85,11 @@ void fdcgks3d_default_params(fdcgks3d_params* p);
 fdcgks_status fdcgks3d_create(const fdcgks3d_params* p, void* hip_stream, fdcgks3d_problem** out);
 
 /* Copy one grid (0..3) in or out: 20 planes of nz*ny*nx doubles (layout
- * above).  on_device = 1: device pointers, enqueued on the problem's stream;
- * 0: host pointers, synchronous. */
+ * above).  on_device = 1: device pointers (EINVAL for anything else),
+ * enqueued on the problem's stream; 0: host pointers, synchronous.  Values
+ * with rho <= 0, p <= 0 or NaN are accepted and reported by the first step or
+ * compute_dt as FDCGKS_ENONPHYS.  get_state before any set_state of that grid:
+ * FDCGKS_ESTATE. */
 fdcgks_status fdcgks3d_set_state(fdcgks3d_problem* pb, int32_t grid, const double* S, int32_t on_device);
 fdcgks_status fdcgks3d_get_state(const fdcgks3d_problem* pb, int32_t grid, double* S, int32_t on_device);
 
@@ -102,6 +105,8 @@ fdcgks_status fdcgks3d_diagnostics(fdcgks3d_problem* pb, double* out);
 
 /* Advance up to nsteps S2O4 steps (dt > 0 fixed, dt <= 0 the CFL step of
  * each step's start state; t_end > 0 clips the last step and stops there).
+ * EINVAL for non-finite dt, t or t_end, nsteps < 0, or dt <= 0 without
+ * cfl > 0; ESTATE until all four grids have a state.
  * Each step synchronises the stream once to check it: on FDCGKS_ENONPHYS
  * (rho <= 0, p <= 0 or NaN at some node) the state is the one after the last
  * good step and *t_inout, *steps_done describe it. */

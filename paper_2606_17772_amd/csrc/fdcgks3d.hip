@@ -574,6 +574,17 @@ fdcgks_status cfl_dt(fdcgks3d_problem* pb, const double* S, double cfl, double* 
 
 bool all_set(const fdcgks3d_problem* pb) { return pb->have[0] && pb->have[1] && pb->have[2] && pb->have[3]; }
 
+// A pointer handed over with on_device = 1 must be device memory: a host
+// pointer in a device-to-device copy would be read by the GPU.
+bool device_memory(const void* p) {
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return attr.type == hipMemoryTypeDevice;
+}
+
 fdcgks_status run(fdcgks3d_problem* pb, double dt, double cfl, int32_t nsteps, double t_end, double* t_inout,
                   int32_t* steps_done, double* kernel_ms) {
   if (steps_done) *steps_done = 0;
@@ -581,6 +592,8 @@ fdcgks_status run(fdcgks3d_problem* pb, double dt, double cfl, int32_t nsteps, d
   if (nsteps < 0) return fail(pb, FDCGKS_EINVAL, "nsteps must be >= 0");
   if (!all_set(pb)) return fail(pb, FDCGKS_ESTATE, "set the state of all four grids first");
   if (dt <= 0 && !(cfl > 0)) return fail(pb, FDCGKS_EINVAL, "cfl must be > 0 when dt <= 0");
+  if (!std::isfinite(dt) || !std::isfinite(*t_inout) || !std::isfinite(t_end))
+    return fail(pb, FDCGKS_EINVAL, "dt, t and t_end must be finite");
   Timer tm{pb, kernel_ms != nullptr};
   std::vector<double> acc(T3_COUNT, 0.0);
   if (kernel_ms)
@@ -693,6 +706,7 @@ fdcgks_status fdcgks3d_set_state(fdcgks3d_problem* pb, int32_t grid, const doubl
   if (!pb) return fail(nullptr, FDCGKS_EINVAL, "problem is NULL");
   if (grid < 0 || grid > 3) return fail(pb, FDCGKS_EINVAL, "grid must be 0..3");
   if (!S) return fail(pb, FDCGKS_EINVAL, "state pointer is NULL");
+  if (on_device && !device_memory(S)) return fail(pb, FDCGKS_EINVAL, "on_device = 1 needs device memory");
   const size_t bytes = (size_t)NSP * pb->g.n * sizeof(double);
   double* dst = pb->S[pb->cur] + (long)grid * NSP * pb->g.n;
   if (on_device) HIPCHK3(pb, hipMemcpyAsync(dst, S, bytes, hipMemcpyDeviceToDevice, pb->stream));
@@ -710,6 +724,7 @@ fdcgks_status fdcgks3d_get_state(const fdcgks3d_problem* cpb, int32_t grid, doub
   if (grid < 0 || grid > 3) return fail(pb, FDCGKS_EINVAL, "grid must be 0..3");
   if (!S) return fail(pb, FDCGKS_EINVAL, "state pointer is NULL");
   if (!pb->have[grid]) return fail(pb, FDCGKS_ESTATE, "grid %d has no state", grid);
+  if (on_device && !device_memory(S)) return fail(pb, FDCGKS_EINVAL, "on_device = 1 needs device memory");
   const size_t bytes = (size_t)NSP * pb->g.n * sizeof(double);
   const double* src = pb->S[pb->cur] + (long)grid * NSP * pb->g.n;
   if (on_device) HIPCHK3(pb, hipMemcpyAsync(S, src, bytes, hipMemcpyDeviceToDevice, pb->stream));

@@ -253,3 +253,34 @@ def test_full_size_sampled_taylor_green_128(oracle):
             gota = np.stack([ga[grid[q], :, kk[q], jj[q], ii[q]] for q in range(ns)])
             erra = float((np.abs(gota - oa).max(axis=0) / den).max())
             assert erra <= bar, ("acc", erra, bar)
+
+
+def test_abi_errors_3d():
+    """Argument and order errors of the 3D ABI come back as statuses, before
+    any device work."""
+    import ctypes as C
+
+    from paper_2606_17772_amd import Problem3D, _lib
+    n = 4
+    pb = Problem3D(nx=n, ny=n, nz=n, lx=1.0)
+    L = _lib.load()
+    host = np.zeros((20, n, n, n))
+    h = pb._h
+    ptr = C.c_void_p(host.ctypes.data)
+    assert L.fdcgks3d_get_state(h, 0, ptr, 0) == _lib.ESTATE          # no state yet
+    assert L.fdcgks3d_set_state(h, 4, ptr, 0) == _lib.EINVAL          # grid out of range
+    assert L.fdcgks3d_set_state(h, 0, ptr, 1) == _lib.EINVAL          # host memory passed as device memory
+    tt, k = C.c_double(0.0), C.c_int32()
+    assert L.fdcgks3d_step(h, 0.01, 0.5, 1, 0.0, C.byref(tt), C.byref(k)) == _lib.ESTATE
+    pr = WL.random_smooth3d(n, n, n, seed=13)
+    pb.set_state_all(pr.S)
+    assert L.fdcgks3d_step(h, float("nan"), 0.5, 1, 0.0, C.byref(tt), C.byref(k)) == _lib.EINVAL
+    assert L.fdcgks3d_step(h, 0.0, 0.0, 1, 0.0, C.byref(tt), C.byref(k)) == _lib.EINVAL
+    assert L.fdcgks3d_step(h, 0.01, 0.5, -1, 0.0, C.byref(tt), C.byref(k)) == _lib.EINVAL
+    assert L.fdcgks3d_debug_stage(h, 3, 0.01, ptr, None) == _lib.EINVAL
+    with pytest.raises(ValueError):  # the binding checks shapes before the call
+        pb.set_state(0, np.zeros((20, n, n, n + 1)))
+    # t_end stops the run exactly there
+    t, k2 = pb.step(nsteps=100, cfl=0.4, t_end=0.01)
+    assert t == 0.01 and 0 < k2 < 100
+    assert np.array_equal(pb.get_state_all()[0, 0].shape, (n, n, n))
