@@ -29,8 +29,12 @@
  *     the S2O4 update of values and averaged gradients (Eqs. eq-nodal-update,
  *     eq-interface-update).
  *
- * All sides are periodic.  Reconstruction is on conservative variables and
- * the gas-kinetic solver runs in FP64.
+ * All sides are periodic and the gas-kinetic solver runs in FP64.  The GENO
+ * reconstruction works on conservative variables or, as in 2D, on the
+ * characteristic variables of the Euler flux Jacobian along each line (local
+ * frame, eigenvectors at the mean of the two interface-adjacent states or at
+ * the node, path function the smallest of the u -+ c fields' left and right
+ * values).
  *
  * State layout at the boundary: one grid is 20 contiguous planes of
  * nz*ny*nx doubles, x fastest,
@@ -61,7 +65,7 @@ typedef struct fdcgks3d_params {
   int32_t flux_order;     /* 6 (default) or 8, as for 2D problems */
   int32_t grad_update;    /* FDCGKS_GRAD_* */
   int32_t geno_r;         /* GENO exponent r, 1..8 (default 3) */
-  int32_t reserved;       /* must be 0 */
+  int32_t recon_vars;     /* FDCGKS_RECON_* (fdcgks.h): conservative (default) or characteristic, as in 2D */
   double x0, y0, z0;      /* domain origin */
   double lx;              /* x length; h = lx / nx, the y and z lengths are h ny, h nz */
   double gamma;           /* ratio of specific heats, 1 < gamma < 5/3 */

@@ -475,10 +475,13 @@ class Batch:
 # ---------------------------------------------------------------------- 3D
 def make_params3d(**kw) -> Params3D:
     """fdcgks3d_params from keywords (names of the C struct; also
-    variant='6-4'|'6-2'|'linear', grad_carried=bool)."""
+    variant='6-4'|'6-2'|'linear', grad_carried=bool,
+    recon_vars='conservative'|'characteristic')."""
     p = Params3D()
     _lib.load().fdcgks3d_default_params(C.byref(p))
     kw = dict(kw)
+    if "recon_vars" in kw and isinstance(kw["recon_vars"], str):
+        kw["recon_vars"] = _RECON[kw["recon_vars"]]
     if "variant" in kw:
         v = kw.pop("variant")
         p.flux_variant = _VARIANTS[v] if isinstance(v, str) else int(v)

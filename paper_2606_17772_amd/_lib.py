@@ -43,7 +43,7 @@ class Params3D(C.Structure):
     """Mirror of fdcgks3d_params."""
     _fields_ = [
         ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("flux_variant", C.c_int32),
-        ("flux_order", C.c_int32), ("grad_update", C.c_int32), ("geno_r", C.c_int32), ("reserved", C.c_int32),
+        ("flux_order", C.c_int32), ("grad_update", C.c_int32), ("geno_r", C.c_int32), ("recon_vars", C.c_int32),
         ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double), ("lx", C.c_double),
         ("gamma", C.c_double), ("mu", C.c_double), ("prandtl", C.c_double),
         ("geno_C", C.c_double), ("geno_eps", C.c_double), ("geno_eps_a", C.c_double),

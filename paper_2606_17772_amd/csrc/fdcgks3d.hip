@@ -117,7 +117,7 @@ __device__ __forceinline__ int lperm(int ax, int cc) { return cc == 1 ? 1 + ax :
 //            tangential slopes from the other two lines' entries;
 //   phase 3: the solve; fluxes to HBM, interface values -> LDS;
 //   phase 4: blend of the interface values over the three directions.
-template <bool VALUES>
+template <bool VALUES, bool CHAR>
 __global__ __launch_bounds__(EDGE_THREADS, FDCGKS3D_EDGE_WAVES) void k_edges3d(Consts k, Geo3 g, double dt,
                                                                               const double* __restrict__ S,
                                                                               double* __restrict__ E) {
@@ -138,9 +138,33 @@ __global__ __launch_bounds__(EDGE_THREADS, FDCGKS3D_EDGE_WAVES) void k_edges3d(C
   const int gl = grid_of(qm ^ (1 << ax));  // grid of this line's nodes
   const double* Sg = S + (long)gl * NSP * g.n;
   const Axis A = axis_of(g, c, ax);
-  // phase 1: line reconstruction (chi from the density line)
+  // phase 1: line reconstruction (conservative: chi from the density line;
+  // characteristic: in the line's local frame, chi from the u -+ c fields)
   double chi;
-  {
+  if (CHAR) {
+    long at[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) at[m] = cell_along(cell, A, odd_step(A.coord, 2 * m - 3, even));
+    double Q[5][4], X[5][4];
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc) {
+      const int p = lperm(ax, cc);
+      const double* W = Sg + (long)p * g.n;
+      const double* Xp = Sg + (long)(5 * (1 + ax) + p) * g.n;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) { Q[cc][m] = W[at[m]]; X[cc][m] = Xp[at[m]]; }
+    }
+    fdk::IfaceRec rec[5];
+    fdk::recon_iface_char<3>(k, Q, X, g.h, g.invh, rec, chi);
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc) {
+      const int p = lperm(ax, cc);
+      xs[p][t] = rec[cc].vl;
+      xs[5 + p][t] = rec[cc].vr;
+      xs[10 + p][t] = rec[cc].dl;
+      xs[15 + p][t] = rec[cc].dr;
+    }
+  } else {
     long at[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) at[m] = cell_along(cell, A, odd_step(A.coord, 2 * m - 3, even));
@@ -211,7 +235,7 @@ __global__ __launch_bounds__(EDGE_THREADS, FDCGKS3D_EDGE_WAVES) void k_edges3d(C
 }
 
 // -------------------------------------------------------------- node sweep
-template <bool VALUES>
+template <bool VALUES, bool CHAR>
 __global__ __launch_bounds__(NODE_BLOCK, FDCGKS3D_NODE_WAVES) void k_nodes3d(Consts k, Geo3 g, const double* __restrict__ S,
                                                         double* __restrict__ Nb) {
   const int nbx = (g.nx + NODE_BLOCK - 1) / NODE_BLOCK;
@@ -232,6 +256,21 @@ __global__ __launch_bounds__(NODE_BLOCK, FDCGKS3D_NODE_WAVES) void k_nodes3d(Con
   for (int ax = 0; ax < 3; ++ax) {
     const Axis A = axis_of(g, c, ax);
     const long am = cell_along(cell, A, A.coord - 1), ap = cell_along(cell, A, A.coord + 1);
+    if (CHAR) {  // in the line's local frame (ax is a compile-time index here)
+      double Q[5][3], X[5][3], d[5];
+#pragma unroll
+      for (int cc = 0; cc < 5; ++cc) {
+        const int p = lperm(ax, cc);
+        const double* Wp = Sg + (long)p * g.n;
+        const double* Xp = Sg + (long)(5 * (1 + ax) + p) * g.n;
+        Q[cc][0] = Wp[am]; Q[cc][1] = Wp[cell]; Q[cc][2] = Wp[ap];
+        X[cc][0] = Xp[am]; X[cc][1] = Xp[cell]; X[cc][2] = Xp[ap];
+      }
+      fdk::recon_node_char<3>(k, Q, X, g.h, g.invh, d);
+#pragma unroll
+      for (int cc = 0; cc < 5; ++cc) D[ax][lperm(ax, cc)] = d[cc];
+      continue;
+    }
 #pragma unroll
     for (int cc = 0; cc < 5; ++cc) {
       const double* Wp = Sg + (long)cc * g.n;
@@ -406,6 +445,7 @@ struct fdcgks3d_problem {
   int* bad = nullptr;                 // non-physical flag
   unsigned long long* host = nullptr; // pinned readback (2 reduction slots + flag)
   int cur = 0;
+  bool chr = false;  // characteristic reconstruction
   bool have[4] = {false, false, false, false};
   std::string err;
   std::vector<hipEvent_t> ev;
@@ -455,7 +495,8 @@ fdcgks_status check(const fdcgks3d_params* p) {
   if (p->nx < 4 || p->ny < 4 || p->nz < 4)
     return fail(nullptr, FDCGKS_EINVAL, "3D needs nx, ny, nz >= 4 (got %d x %d x %d)", p->nx, p->ny, p->nz);
   if ((long)p->nx * p->ny * p->nz > (1L << 26)) return fail(nullptr, FDCGKS_EINVAL, "grid too large");
-  if (p->reserved != 0) return fail(nullptr, FDCGKS_EINVAL, "reserved must be 0");
+  if (p->recon_vars != FDCGKS_RECON_CONSERVATIVE && p->recon_vars != FDCGKS_RECON_CHARACTERISTIC)
+    return fail(nullptr, FDCGKS_EINVAL, "bad recon_vars");
   if (!(p->lx > 0)) return fail(nullptr, FDCGKS_EINVAL, "lx must be > 0");
   if (!(p->gamma > 1.0) || !(p->gamma < 5.0 / 3.0)) return fail(nullptr, FDCGKS_EINVAL, "gamma out of range");
   if (!(p->mu >= 0)) return fail(nullptr, FDCGKS_EINVAL, "mu must be >= 0");
@@ -532,17 +573,21 @@ fdcgks_status stage3d(fdcgks3d_problem* pb, int stage, double dt, const double* 
   const dim3 ng(blocks_x(g, NODE_BLOCK), 4), nb(NODE_BLOCK);
   const dim3 ug(blocks_x(g, UPD_BLOCK), 4), ub(UPD_BLOCK);
   if (stage == 1) {
-    hipLaunchKernelGGL(k_edges3d<true>, eg, eb, 0, pb->stream, pb->k, g, dt, Sin, pb->E);
+    if (pb->chr) hipLaunchKernelGGL((k_edges3d<true, true>), eg, eb, 0, pb->stream, pb->k, g, dt, Sin, pb->E);
+    else hipLaunchKernelGGL((k_edges3d<true, false>), eg, eb, 0, pb->stream, pb->k, g, dt, Sin, pb->E);
     if (tm) tm->mark(T3_EDGE1);
-    hipLaunchKernelGGL(k_nodes3d<true>, ng, nb, 0, pb->stream, pb->k, g, Sin, pb->Nb);
+    if (pb->chr) hipLaunchKernelGGL((k_nodes3d<true, true>), ng, nb, 0, pb->stream, pb->k, g, Sin, pb->Nb);
+    else hipLaunchKernelGGL((k_nodes3d<true, false>), ng, nb, 0, pb->stream, pb->k, g, Sin, pb->Nb);
     if (tm) tm->mark(T3_NODE1);
     hipLaunchKernelGGL(k_update3d<1>, ug, ub, 0, pb->stream, pb->k, g, dt, Sin, (const double*)nullptr, pb->E,
                        pb->Nb, Out, Aout, pb->bad);
     if (tm) tm->mark(T3_UPD1);
   } else {
-    hipLaunchKernelGGL(k_edges3d<false>, eg, eb, 0, pb->stream, pb->k, g, dt, Sin, pb->E);
+    if (pb->chr) hipLaunchKernelGGL((k_edges3d<false, true>), eg, eb, 0, pb->stream, pb->k, g, dt, Sin, pb->E);
+    else hipLaunchKernelGGL((k_edges3d<false, false>), eg, eb, 0, pb->stream, pb->k, g, dt, Sin, pb->E);
     if (tm) tm->mark(T3_EDGE2);
-    hipLaunchKernelGGL(k_nodes3d<false>, ng, nb, 0, pb->stream, pb->k, g, Sin, pb->Nb);
+    if (pb->chr) hipLaunchKernelGGL((k_nodes3d<false, true>), ng, nb, 0, pb->stream, pb->k, g, Sin, pb->Nb);
+    else hipLaunchKernelGGL((k_nodes3d<false, false>), ng, nb, 0, pb->stream, pb->k, g, Sin, pb->Nb);
     if (tm) tm->mark(T3_NODE2);
     hipLaunchKernelGGL(k_update3d<2>, ug, ub, 0, pb->stream, pb->k, g, dt, Sin, Ain, pb->E, pb->Nb, Out,
                        (double*)nullptr, pb->bad);
@@ -676,6 +721,7 @@ fdcgks_status fdcgks3d_create(const fdcgks3d_params* p, void* hip_stream, fdcgks
   fdcgks3d_problem* pb = new fdcgks3d_problem();
   pb->prm = *p;
   setup(*p, pb->g, pb->k);
+  pb->chr = p->recon_vars == FDCGKS_RECON_CHARACTERISTIC;
   pb->stream = (hipStream_t)hip_stream;
   const long n = pb->g.n;
   const size_t state = (size_t)4 * NSP * n * sizeof(double);
@@ -814,8 +860,13 @@ fdcgks_status fdcgks3d_debug_intermediates(fdcgks3d_problem* pb, double dt, doub
   const Geo3& g = pb->g;
   const dim3 eg((unsigned)((g.n + EDGE_POINTS - 1) / EDGE_POINTS), 4), eb(EDGE_THREADS);
   const dim3 ng(blocks_x(g, NODE_BLOCK), 4), nb(NODE_BLOCK);
-  hipLaunchKernelGGL(k_edges3d<true>, eg, eb, 0, pb->stream, pb->k, g, dt, pb->S[pb->cur], pb->E);
-  hipLaunchKernelGGL(k_nodes3d<true>, ng, nb, 0, pb->stream, pb->k, g, pb->S[pb->cur], pb->Nb);
+  if (pb->chr) {
+    hipLaunchKernelGGL((k_edges3d<true, true>), eg, eb, 0, pb->stream, pb->k, g, dt, pb->S[pb->cur], pb->E);
+    hipLaunchKernelGGL((k_nodes3d<true, true>), ng, nb, 0, pb->stream, pb->k, g, pb->S[pb->cur], pb->Nb);
+  } else {
+    hipLaunchKernelGGL((k_edges3d<true, false>), eg, eb, 0, pb->stream, pb->k, g, dt, pb->S[pb->cur], pb->E);
+    hipLaunchKernelGGL((k_nodes3d<true, false>), ng, nb, 0, pb->stream, pb->k, g, pb->S[pb->cur], pb->Nb);
+  }
   fdcgks_status st = launched(pb, "3D interface / node sweeps");
   if (st != FDCGKS_OK) return st;
   HIPCHK3(pb, hipMemcpyAsync(edges, pb->E, (size_t)12 * NEP * g.n * sizeof(double), hipMemcpyDeviceToHost,

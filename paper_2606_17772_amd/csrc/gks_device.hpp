@@ -187,10 +187,10 @@ FDK_HD R recon_node(const Consts& k, R q0, R q1, R q2, R x0, R x1, R x2, double 
 // ------------------------------------- characteristic variables (Sec. 3)
 // Eigenvectors of the Euler flux Jacobian along a line, in the line's local
 // frame (component 1 is the momentum along the line), at a state W.  The
-// columns of R are the fields u - c, u, [shear,] u + c, normalised as
-// (1, u - c, [v,] H - u c), (1, u, [v,] |u|^2/2), [(0, 0, 1, v),]
-// (1, u + c, [v,] H + u c); L = R^-1 in closed form with b1 = (gamma-1)/c^2
-// and b2 = b1 |u|^2 / 2.  The map is linear, so values and derivatives
+// columns of R are the fields u - c, u, [shears,] u + c, normalised as
+// (1, u - c, [v, w,] H - u c), (1, u, [v, w,] |u|^2/2), [(0, 0, 1, 0, v),
+// (0, 0, 0, 1, w),] (1, u + c, [v, w,] H + u c) (2D: no w); L = R^-1 in
+// closed form with b1 = (gamma-1)/c^2 and b2 = b1 |u|^2 / 2.  The map is linear, so values and derivatives
 // transform with the same matrices.  Nothing here is contracted into fused
 // multiply-adds, in particular not with the callers' arithmetic: otherwise
 // which products fuse would depend on the kernel the code is inlined into,
@@ -198,14 +198,17 @@ FDK_HD R recon_node(const Consts& k, R q0, R q1, R q2, R x0, R x1, R x2, double 
 // characteristic values on smooth data) would differ between kernels.
 struct CharFrame {
   double u, v, c, ic, H, b1, b2, k2;  // k2 = |u|^2 / 2
+  double w;                            // 3D only
 };
 template <int DIM> FDK_HD CharFrame char_frame(double gamma, const double* W) {
 #pragma clang fp contract(off)
   CharFrame f;
   const double ir = 1.0 / W[0];
   f.u = W[1] * ir;
-  f.v = DIM == 2 ? W[2] * ir : 0.0;
-  f.k2 = 0.5 * (f.u * f.u + f.v * f.v);
+  f.v = DIM >= 2 ? W[2] * ir : 0.0;
+  f.w = DIM == 3 ? W[3] * ir : 0.0;
+  if (DIM == 3) f.k2 = 0.5 * (f.u * f.u + f.v * f.v + f.w * f.w);
+  else f.k2 = 0.5 * (f.u * f.u + f.v * f.v);
   const double p = (gamma - 1.0) * (W[DIM + 1] - W[0] * f.k2);
   const double c2 = gamma * p * ir;
   f.c = sqrt(c2);
@@ -219,24 +222,33 @@ template <int DIM> FDK_HD CharFrame char_frame(double gamma, const double* W) {
 template <int DIM> FDK_HD void to_char(const CharFrame& f, const double* w, double* q) {
 #pragma clang fp contract(off)
   const double uc = f.u * f.ic;
-  const double s = f.b1 * (w[DIM + 1] - f.u * w[1] - (DIM == 2 ? f.v * w[2] : 0.0));  // b1 (E - u m - v n)
-  const double a = f.b2 * w[0] + s;  // b2 rho + b1 (E - u m - v n)
+  double s;  // b1 (E - u m - v n [- w o])
+  if (DIM == 3) s = f.b1 * (w[4] - f.u * w[1] - f.v * w[2] - f.w * w[3]);
+  else s = f.b1 * (w[DIM + 1] - f.u * w[1] - (DIM == 2 ? f.v * w[2] : 0.0));
+  const double a = f.b2 * w[0] + s;  // b2 rho + s
   const double m = f.ic * w[1] - uc * w[0];  // (m - u rho) / c
   q[0] = 0.5 * (a - m);
   q[1] = w[0] - a;
-  if (DIM == 2) q[2] = w[2] - f.v * w[0];
+  if (DIM >= 2) q[2] = w[2] - f.v * w[0];
+  if (DIM == 3) q[3] = w[3] - f.w * w[0];
   q[DIM + 1] = 0.5 * (a + m);
 }
 // w = R q
 template <int DIM> FDK_HD void from_char(const CharFrame& f, const double* q, double* w) {
 #pragma clang fp contract(off)
   const double lo = q[0], en = q[1], hi = q[DIM + 1];
-  const double sh = DIM == 2 ? q[2] : 0.0;
+  const double sh = DIM >= 2 ? q[2] : 0.0;
+  const double sw = DIM == 3 ? q[3] : 0.0;
   const double s = lo + en + hi;
   w[0] = s;
   w[1] = f.u * s + f.c * (hi - lo);
-  if (DIM == 2) w[2] = f.v * s + sh;
-  w[DIM + 1] = f.H * (lo + hi) + f.u * f.c * (hi - lo) + f.k2 * en + f.v * sh;
+  if (DIM >= 2) w[2] = f.v * s + sh;
+  if (DIM == 3) {
+    w[3] = f.w * s + sw;
+    w[4] = f.H * (lo + hi) + f.u * f.c * (hi - lo) + f.k2 * en + f.v * sh + f.w * sw;
+  } else {
+    w[DIM + 1] = f.H * (lo + hi) + f.u * f.c * (hi - lo) + f.k2 * en + f.v * sh;
+  }
 }
 
 // Interface reconstruction of a whole line of N = DIM + 2 components on

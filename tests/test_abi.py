@@ -111,13 +111,13 @@ def test_defaults_3d():
     from paper_2606_17772_amd import make_params3d
     p = make_params3d()
     assert (p.nx, p.ny, p.nz, p.geno_r, p.flux_order) == (32, 32, 32, 3, 6)
-    assert p.geno_C == 20.0 and p.gamma == 1.4 and p.lx == 1.0 and p.reserved == 0
+    assert p.geno_C == 20.0 and p.gamma == 1.4 and p.lx == 1.0 and p.recon_vars == 0
 
 
 @pytest.mark.parametrize("bad", [
     dict(nx=3), dict(nz=2), dict(gamma=1.0), dict(gamma=1.7), dict(mu=-1.0), dict(mu=1e-3, prandtl=0.0),
     dict(flux_variant=3), dict(flux_order=7), dict(geno_r=9), dict(geno_eps=0.0), dict(tau_c2=-1.0),
-    dict(lx=0.0), dict(grad_update=2), dict(reserved=1), dict(nx=1024, ny=1024, nz=128),
+    dict(lx=0.0), dict(grad_update=2), dict(recon_vars=2), dict(nx=1024, ny=1024, nz=128),
 ])
 def test_create3d_rejects_bad_params(bad):
     from paper_2606_17772_amd import _lib, make_params3d

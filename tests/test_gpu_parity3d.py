@@ -27,7 +27,8 @@ def _gpu_params(s):
                          prandtl=s["prandtl"], variant=s["variant"], geno_C=s["geno_C"], geno_r=s["geno_r"],
                          geno_eps=s["geno_eps"], geno_eps_a=s["geno_eps_a"], geno_d_central=s["d_central"],
                          geno_d_side=s["d_side"], tau_c1=s["tau_c1"], tau_c2=s["tau_c2"],
-                         flux_order=s.get("flux_order", 6), grad_carried=s.get("grad_carried", 0))
+                         flux_order=s.get("flux_order", 6), grad_carried=s.get("grad_carried", 0),
+                         recon_vars=s.get("recon_vars", "conservative"))
 
 
 def _problem(s, S):
@@ -52,6 +53,12 @@ CASES = {
                                    WL.random_rough3d(7, 6, 5, seed=7)),
     "rough_5x6x7_carried": lambda: (settings(dim=3, nx=5, ny=6, nz=7, lx=1.0, grad_carried=1),
                                     WL.random_rough3d(5, 6, 7, seed=8)),
+    "rough_70x5x4_char": lambda: (settings(dim=3, nx=70, ny=5, nz=4, lx=1.0, recon_vars="characteristic"),
+                                  WL.random_rough3d(70, 5, 4, seed=21)),
+    "smooth_9x8x7_char": lambda: (settings(dim=3, nx=9, ny=8, nz=7, lx=1.0, recon_vars="characteristic"),
+                                  WL.random_smooth3d(9, 8, 7, seed=22)),
+    "smooth_ns_8_char": lambda: (settings(dim=3, nx=8, ny=8, nz=8, lx=1.0, mu=2e-3, prandtl=0.72,
+                                          recon_vars="characteristic"), WL.random_smooth3d(8, 8, 8, seed=23)),
 }
 
 
@@ -143,7 +150,8 @@ def test_stages3d(oracle, name):
     assert err <= TOL, (name, "stage2", err, at)
 
 
-@pytest.mark.parametrize("name", ["smooth_9x8x7", "smooth_ns_8", "rough_70x5x4"])
+@pytest.mark.parametrize("name", ["smooth_9x8x7", "smooth_ns_8", "rough_70x5x4", "smooth_9x8x7_char",
+                                  "rough_70x5x4_char"])
 def test_steps3d(oracle, name):
     """Three CFL steps: the same time steps, and states within max(1e-12, 4 x
     the oracle's one-ulp sensitivity over the same steps)."""
