@@ -41,7 +41,8 @@ constexpr int NSP = 20;   // state planes per grid
 constexpr int NEP = 31;   // edge planes per (class, axis)
 constexpr int NNP = 30;   // node-flux planes per grid
 constexpr int EDGE_THREADS = 256;   // interface sweep block: four waves
-constexpr int EDGE_POINTS = 85;     // interface points per block (3 solves each)
+constexpr int EDGE_WAVE_POINTS = 21;  // interface points per wave (63 busy lanes, 3 solves per point)
+constexpr int EDGE_POINTS = 4 * EDGE_WAVE_POINTS;  // interface points per block
 // Minimum waves per SIMD of the interface and node sweeps.  Measured on a
 // 128^3 Navier-Stokes step: the interface sweep is fastest at 1 (about 440
 // registers, no spills; 2 waves spill 192 registers and take 40% longer),
@@ -102,13 +103,24 @@ __device__ __forceinline__ long cell_along(long cell, const Axis& a, int m) {
 // component lperm(ax, cc) and vice versa (the swap is its own inverse).
 __device__ __forceinline__ int lperm(int ax, int cc) { return cc == 1 ? 1 + ax : (cc == 1 + ax ? 1 : cc); }
 
+// Orders the LDS accesses of one wave: writes before the call are seen by
+// every lane of the wave after it.  A wave's LDS operations execute in order;
+// the fences keep the compiler from moving accesses across the call.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // --------------------------------------------------------- interface sweep
-// One thread per (interface point, normal axis): thread t of a block takes
-// point t / 3 of EDGE_POINTS consecutive points of one class (cells in
-// x-fastest order) and normal axis t % 3, so the three solves of a point sit
-// in neighbouring lanes.  A block is four waves (255 busy threads): the solver
-// needs about 440 registers, one wave per SIMD, and a four-wave block keeps
-// all four SIMDs of a compute unit busy (a three-wave block left one idle).
+// One thread per (interface point, normal axis): lane l < 63 of wave w takes
+// point 21 w + l / 3 of EDGE_POINTS consecutive points of one class (cells in
+// x-fastest order) and normal axis l % 3; lane 63 idles.  The three solves of
+// a point thus sit in neighbouring lanes of one wave, which exchange data
+// through LDS with wave-level ordering only (no block barrier, so a wave never
+// waits for the other waves of its block).  A block is four waves: the solver
+// needs about 440 registers, one wave per SIMD, and a four-wave block keeps all
+// four SIMDs of a compute unit busy (a three-wave block left one idle).
 // The axis varies across a wave, so every component permutation goes through
 // LDS (addresses are free to compute; registers cannot be indexed at run
 // time):
@@ -123,11 +135,13 @@ __global__ __launch_bounds__(EDGE_THREADS, FDCGKS3D_EDGE_WAVES) void k_edges3d(C
                                                                               double* __restrict__ E) {
   __shared__ double xs[20][EDGE_THREADS];
   const int t = threadIdx.x;
-  const int ax = t % 3;
-  const int base = t - ax;  // slot of this point's x solve
+  const int lane = t % 64, wv = t / 64;
+  const bool busy = lane < 3 * EDGE_WAVE_POINTS;
+  const int ax = busy ? lane % 3 : 0;
+  const int base = t - ax;  // slot of this point's x solve (the idle lane reads its own slots)
   const int q = blockIdx.y;
-  const long P = (long)blockIdx.x * EDGE_POINTS + t / 3;
-  const bool live = t < 3 * EDGE_POINTS && P < g.n;
+  const long P = (long)blockIdx.x * EDGE_POINTS + wv * EDGE_WAVE_POINTS + lane / 3;
+  const bool live = busy && P < g.n;
   const long cell = live ? P : 0;
   Cell c;
   c.c[0] = (int)(cell % g.nx);
@@ -181,7 +195,7 @@ __global__ __launch_bounds__(EDGE_THREADS, FDCGKS3D_EDGE_WAVES) void k_edges3d(C
       if (cc == 0) chi = fdk::g_min(r.cl, r.cr);
     }
   }
-  __syncthreads();
+  wave_sync();
   // phase 2: inputs in the local frame; the local v and w are the velocities
   // of axes av and aw, whose lines give the tangential slopes (mean of their
   // l and r derivatives)
@@ -197,7 +211,7 @@ __global__ __launch_bounds__(EDGE_THREADS, FDCGKS3D_EDGE_WAVES) void k_edges3d(C
     io.Wt[cc] = 0.5 * (xs[10 + p][tv] + xs[15 + p][tv]);
     io.Wt2[cc] = 0.5 * (xs[10 + p][tw] + xs[15 + p][tw]);
   }
-  __syncthreads();
+  wave_sync();
   // phase 3: the solve; fluxes go out, interface values to LDS (global order)
   fdk3::gks_iface<VALUES>(k, dt, io);
   double* Eo = E + (long)(q * 3 + ax) * NEP * g.n + cell;
@@ -215,7 +229,7 @@ __global__ __launch_bounds__(EDGE_THREADS, FDCGKS3D_EDGE_WAVES) void k_edges3d(C
       if (VALUES) Eo[(long)p * g.n] = io.F[cc];
     }
   }
-  __syncthreads();
+  wave_sync();
   // phase 4: blend, weight 1/3 per direction (the normal one with its own
   // side, the tangential ones with the mean of l and r)
   const int b1 = base + (ax == 0 ? 1 : 0), b2 = base + (ax == 2 ? 1 : 2);  // the other axes, increasing
