@@ -40,6 +40,9 @@ HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doub
 # since the counters were taken.
 FLOPS_PER_IFACE_POINT_STAGE1 = 6251
 TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 4.473e9
+# 3D leg: the stage-1 interface sweep k_edges3d<true,false>, unit one solve
+# (12 per cell), from profiles/k_edges3d_taylor_green128.md (same counters).
+FLOPS_PER_SOLVE_3D_STAGE1 = 5787
 
 
 # Launch shapes fdcgks_autotune picks on this workload (interface sweep,
@@ -601,11 +604,16 @@ def three_d_leg(n=128, steps=5):
     edge1 = kms["edge1"] / 2
     del pb
     torch.cuda.empty_cache()
+    achieved = FLOPS_PER_SOLVE_3D_STAGE1 * solves / (edge1 * 1e-3) / 1e12
     return {"workload": f"3D Taylor-Green vortex {n}^3 x 4 grids, Re 1600, Ma 0.1, Pr 0.72, (6-4) GENO, FP64, "
                         f"fixed dt (CFL 0.4), {steps} steps",
             "node_updates_per_s": nodes * 2 / (ms * 1e-3), "ms_per_step": round(ms, 3),
             "kernel_ms_per_step": {k2: round(v / 2, 4) for k2, v in kms.items()},
             "interface_solves_per_s_stage1": solves / (edge1 * 1e-3),
+            "roofline": {"kernel": "k_edges3d<true,false> (stage-1 interface sweep)", "bound": "alu",
+                         "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "flop_per_solve": FLOPS_PER_SOLVE_3D_STAGE1,
+                         "avg_launch_ms": round(edge1, 4)},
             "min_rho": d[20], "min_p": d[21]}
 
 

@@ -41,3 +41,15 @@ def test_roofline_constants_come_from_the_committed_profile():
     assert bench.FLOPS_PER_IFACE_POINT_STAGE1 == flop_per_point
     assert abs(bench.TRAFFIC_BYTES_PER_LAUNCH_STAGE1 - (read_gb + written_gb) * 1e9) <= 2e6
     assert re.search(r"2 \(n\+3\)\^2", open(os.path.join(ROOT, "profiles", "k_edges2d_shear2048.md")).read())
+
+
+def test_3d_flop_constant_comes_from_the_committed_profile():
+    import re
+    sys.path.insert(0, ROOT)
+    import bench
+    txt = open(os.path.join(ROOT, "profiles", "k_edges3d_taylor_green128.md")).read()
+    rows = [ln for ln in txt.splitlines() if ln.startswith("| `k_edges3d<true, false>`") and ln.count("|") >= 8]
+    assert rows
+    cells = [c.strip() for c in rows[0].strip().strip("|").split("|")]
+    assert bench.FLOPS_PER_SOLVE_3D_STAGE1 == int(cells[4])
+    assert re.search(r"12 interface solves per cell", txt)
