@@ -217,9 +217,11 @@ __device__ __forceinline__ void line_adjoint(const double* __restrict__ S, doubl
 
 // Reverse of the interface sweep: same thread layout as the forward sweep
 // (two threads per point, partners in neighbouring waves).  The adjoint of a
-// solve needs about 400 registers per lane at its peak; the solve's inputs,
-// their adjoint accumulators and the moment adjoints live in LDS instead of
-// registers (one wave per SIMD, one block per CU), so that nothing spills.
+// solve runs in phases (see gks_iface_b) whose largest needs about 380
+// registers; the solve's inputs, their adjoint accumulators, the moment
+// adjoints and the time-coefficient adjoints live in LDS (155 KB per block:
+// one block of four waves per CU, one wave per SIMD), so that only a few
+// values spill.
 // The normal along y (fam != G) swaps rho U and rho V in the local frame:
 // the swap is applied to the data, so one copy of the solver adjoint serves
 // both normals.
@@ -267,24 +269,30 @@ __global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__
   double lchi = 0.0;
   if (valid) {
     const long pl = g.plane, o = at(g, j, i);
-    const double* le = lamE + ((long)fam * 50 + G * 25) * pl + o;
-    const double* lp = lamE + ((long)fam * 50 + (1 - G) * 25) * pl + o;  // partner slot
-    fdk::GksIO<double, 2> ob;
+    const double* le0 = lamE + ((long)fam * 50 + G * 25) * pl + o;
+    const double* lp0 = lamE + ((long)fam * 50 + (1 - G) * 25) * pl + o;  // partner slot
+    // output adjoints, read inside the solver adjoint's first phase (the
+    // addresses are formed there too: hoisted out of its phase loop they
+    // would hold 32 registers through every phase)
+    auto obload = [&](fdk::GksIO<double, 2>& ob) {
+      const double* le = fdk::opaque_ptr(le0);
+      const double* lp = fdk::opaque_ptr(lp0);
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      // blend^T: W~(own) = W^/2 + (partner W^l + W^r)/4 and W~(partner) = W^p/2 + (own W^l + W^r)/4
-      const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
-      const int q = swap ? q0 : c;
-      const double ps = lp[(9 + q) * pl] + lp[(13 + q) * pl], pst = lp[(17 + q) * pl] + lp[(21 + q) * pl];
-      ob.Ft[c] = le[(4 + q) * pl];
-      ob.Wlt[c] = 0.5 * le[(17 + q) * pl] + 0.25 * pst;
-      ob.Wrt[c] = 0.5 * le[(21 + q) * pl] + 0.25 * pst;
-      ob.F[c] = STAGE == 1 ? le[q * pl] : 0.0;
-      ob.Wl[c] = STAGE == 1 ? 0.5 * le[(9 + q) * pl] + 0.25 * ps : 0.0;
-      ob.Wr[c] = STAGE == 1 ? 0.5 * le[(13 + q) * pl] + 0.25 * ps : 0.0;
-    }
-    lchi = le[8 * pl];
-    fdk::gks_iface_b(k, dt, in, ob, inb, s_ab[tid]);
+      for (int c = 0; c < 4; ++c) {
+        // blend^T: W~(own) = W^/2 + (partner W^l + W^r)/4 and W~(partner) = W^p/2 + (own W^l + W^r)/4
+        const int q0 = c == 1 ? 2 : (c == 2 ? 1 : c);
+        const int q = swap ? q0 : c;
+        const double ps = lp[(9 + q) * pl] + lp[(13 + q) * pl], pst = lp[(17 + q) * pl] + lp[(21 + q) * pl];
+        ob.Ft[c] = le[(4 + q) * pl];
+        ob.Wlt[c] = 0.5 * le[(17 + q) * pl] + 0.25 * pst;
+        ob.Wrt[c] = 0.5 * le[(21 + q) * pl] + 0.25 * pst;
+        ob.F[c] = STAGE == 1 ? le[q * pl] : 0.0;
+        ob.Wl[c] = STAGE == 1 ? 0.5 * le[(9 + q) * pl] + 0.25 * ps : 0.0;
+        ob.Wr[c] = STAGE == 1 ? 0.5 * le[(13 + q) * pl] + 0.25 * ps : 0.0;
+      }
+    };
+    lchi = le0[8 * pl];
+    fdk::gks_iface_b(k, dt, in, obload, inb, s_ab[tid]);
   }
   // the tangential slope of this solve came from the partner line: send its lambda
 #pragma unroll

@@ -251,6 +251,7 @@ FDK_HD double time_coef_b(double dt, double tau, const double cb[5], const doubl
 // Adjoints of the accumulated moments of f^n and f_t^n and the outputs.
 struct AccB {
   double F[4], Ft[4], We[4], Wet[4];
+  double cb[5], ctb[5], taub, eb;  // adjoints of the time coefficients, of tau and of exp(-dt/tau)
   double pad;  // odd size in 8-byte words: per-thread copies in LDS spread over the banks
 };
 // Inputs of one interface solve (or their adjoints), padded like AccB.
@@ -438,166 +439,205 @@ FDK_HD void side_state(const double* W, double gamma, double K, double sgn, Prim
   mom_half(s, sgn, h);
 }
 
+// A phase number the compiler cannot see through: the solver adjoint below
+// runs its phases as iterations of one loop over it, so that no phase's code
+// is peeled, merged or scheduled into another.
+FDK_HD int opaque_int(int x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+s"(x));
+#endif
+  return x;
+}
+
+// A pointer the compiler cannot see through (address arithmetic on it stays
+// where it is written).
+template <class T> FDK_HD T* opaque_ptr(T* p) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm volatile("" : "+v"(p));
+#endif
+  return p;
+}
+
 // Adjoint of the 2D interface solver with all outputs (gks_iface<double, 2,
-// true>).  ob: adjoints of F, Ft, Wl, Wr, Wlt, Wrt.  Adds the adjoints of
-// WL, WR, nL, nR, Wt into inb (same field names).  in, inb and the moment
-// adjoint ab are references to storage the caller chooses (the reverse
-// interface sweep keeps them in LDS).  Ordered to keep few values live: the forward pass keeps only W0, tau and
-// the outputs the output adjoints need; each side's state and half-line
-// moments are recomputed for its reverse, and the adjoint of its half-line
-// moments is reduced to its primitive state at once (the moment maps are
-// linear in their adjoints, so the later W0 contribution is reduced
-// separately and added).
-template <class TIn, class TInb>
-FDK_HD void gks_iface_b(const Consts& k, double dt, const TIn& in, const GksIO<double, 2>& ob, TInb& inb, AccB& ab) {
+// true>).  obload(ob) fills ob with the adjoints of F, Ft, Wl, Wr, Wlt, Wrt;
+// it is called once, inside the first phase.  Adds the adjoints of WL, WR, nL,
+// nR, Wt into inb (same field names).  in, inb and the moment adjoint ab are
+// references to storage the caller chooses (the reverse interface sweep keeps
+// them in LDS).
+//
+// The work runs as seven phases, the iterations of one loop over an opaque
+// phase number; only W0, tau and a few adjoint accumulators (about 40
+// doubles) are carried from phase to phase, everything else is recomputed in
+// the phase that needs it:
+//   0  forward solve (kept: W0, tau), then the reverse of the output blend
+//      and of the Prandtl correction;
+//   1  reverse of the equilibrium part;
+//   2, 3  reverse of the left / right side terms, reduced to the adjoint of
+//      that side's W at once;
+//   4  reverse of the collision time and time coefficients, giving the
+//      adjoint of W0;
+//   5, 6  the compatibility state's share of the left / right W adjoint (W0
+//      is a sum of half-line moments of the two sides).
+// Written as straight-line code, the compiler interleaves the phases and keeps
+// recomputed values of one phase alive into the next: about 400 registers
+// spill.  As loop iterations each phase holds only its own values.
+template <class TIn, class TOb, class TInb>
+FDK_HD void gks_iface_b(const Consts& k, double dt, const TIn& in, const TOb& obload, TInb& inb, AccB& ab) {
   const double K = k.K, gam = k.gamma, iKd = k.inv_Kd;
-  // ---- forward
-  double W0[4], tau, F[4], Ft[4], We[4], Wet[4], WtL[4], WtR[4];
-  {
-    Prim<double> sL, sR;
-    Mom<double> hL, hR;
-    side_state(in.WL, gam, K, 1.0, sL, hL);
-    side_state(in.WR, gam, K, -1.0, sR, hR);
-    {
-      double pL[4], pR[4], u[4];
-      psi_moms<double, 2>(hL, pL, u);
-      psi_moms<double, 2>(hR, pR, u);
+  // carried between phases
+  double W0[4], tau = 0.0, WtLb[4], WtRb[4];
+  PrimB s0b = primb_zero();
+  double* cb = ab.cb;
+  double* ctb = ab.ctb;
+  double& taub = ab.taub;
+  double& eb = ab.eb;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) W0[i] = sL.rho * pL[i] + sR.rho * pR[i];
-    }
-    const Prim<double> s0 = prim<double, 2>(W0, gam);
-    tau = (k.mu > 0 ? k.mu / s0.p : k.tau_c1 * dt) + k.tau_c2 * dt * m_abs(sL.p - sR.p) / (sL.p + sR.p);
-    const TimeCoef<double> tc = time_coef(dt, tau);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) { F[i] = 0.0; Ft[i] = 0.0; We[i] = 0.0; Wet[i] = 0.0; }
-    side_terms<double, 2, true>(sL, hL, in.nL, in.Wt, K, iKd, tau, tc, true, F, Ft, We, Wet, WtL);
-    side_terms<double, 2, true>(sR, hR, in.nR, in.Wt, K, iKd, tau, tc, true, F, Ft, We, Wet, WtR);
-    Mom<double> m0;
-    mom_common<double, 2>(s0, K, m0);
-    mom_full(s0, m0);
-    double a0[4], b0[4], A0[4], d[4], t0[4], tu0[4], Ap0[4], Au0[4], p0[4], u0[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) d[i] = 0.5 * (in.nL[i] + in.nR[i]) * s0.irho;
-    slope<double, 2>(s0, K, iKd, d, a0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) d[i] = in.Wt[i] * s0.irho;
-    slope<double, 2>(s0, K, iKd, d, b0);
-    transport<double, 2>(a0, b0, m0, t0, tu0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) d[i] = -t0[i];
-    slope<double, 2>(s0, K, iKd, d, A0);
-    tslope<double, 2>(A0, m0, Ap0, Au0);
-    psi_moms<double, 2>(m0, p0, u0);
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      Ft[i] += s0.rho * (tc.ct[0] * u0[i] + tc.ct[1] * tu0[i] + tc.ct[2] * Au0[i]);
-      Wet[i] += s0.rho * (tc.ct[0] * p0[i] + tc.ct[1] * t0[i] + tc.ct[2] * Ap0[i]);
-      F[i] += s0.rho * (tc.c[0] * u0[i] + tc.c[1] * tu0[i] + tc.c[2] * Au0[i]);
-      We[i] += s0.rho * (tc.c[0] * p0[i] + tc.c[1] * t0[i] + tc.c[2] * Ap0[i]);
-    }
-  }
-  phase_barrier();
-  double W0f[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) W0f[i] = fresh(W0[i]);
-  const Prim<double> s0 = prim<double, 2>(W0f, gam);
-  const TimeCoef<double> tc = time_coef(dt, fresh(tau));
-  // ---- reverse: outputs
-  const double e = tc.e1, oe = 1.0 - e;
-  double WtLb[4], WtRb[4], eb = 0.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    ab.Wet[i] = oe * (ob.Wlt[i] + ob.Wrt[i]);
-    WtLb[i] = e * ob.Wlt[i];
-    WtRb[i] = e * ob.Wrt[i];
-    ab.We[i] = oe * (ob.Wl[i] + ob.Wr[i]);
-    inb.WL[i] += e * ob.Wl[i];
-    inb.WR[i] += e * ob.Wr[i];
-    eb += (WtL[i] - Wet[i]) * ob.Wlt[i] + (WtR[i] - Wet[i]) * ob.Wrt[i] + (in.WL[i] - We[i]) * ob.Wl[i] +
-          (in.WR[i] - We[i]) * ob.Wr[i];
-    ab.F[i] = ob.F[i];
-    ab.Ft[i] = ob.Ft[i];
-  }
-  PrimB s0b = primb_zero(), sLb = primb_zero(), sRb = primb_zero();
-  // ---- reverse: Prandtl correction (F, Ft hold the values before it)
-  if (k.mu > 0) {
-    const double U = s0.U, V = s0.V, f = k.prfix;
-    const double a = 1.5 * U * U + 0.5 * V * V, bq = 0.5 * U * (U * U + V * V);
-    const double qb = f * ab.F[3], qtb = f * ab.Ft[3];
-    s0b.U += qb * (-F[1] + 3.0 * U * F[0] - We[3] + V * We[2] - 0.5 * (3.0 * U * U + V * V) * We[0]) +
-             qtb * (-Ft[1] + 3.0 * U * Ft[0] - Wet[3] + V * Wet[2] - 0.5 * (3.0 * U * U + V * V) * Wet[0]);
-    s0b.V += qb * (-F[2] + V * F[0] + U * We[2] - U * V * We[0]) +
-             qtb * (-Ft[2] + V * Ft[0] + U * Wet[2] - U * V * Wet[0]);
-    ab.F[3] += qb; ab.F[1] += -U * qb; ab.F[2] += -V * qb; ab.F[0] += a * qb;
-    ab.We[3] += -U * qb; ab.We[2] += U * V * qb; ab.We[0] += -bq * qb;
-    ab.Ft[3] += qtb; ab.Ft[1] += -U * qtb; ab.Ft[2] += -V * qtb; ab.Ft[0] += a * qtb;
-    ab.Wet[3] += -U * qtb; ab.Wet[2] += U * V * qtb; ab.Wet[0] += -bq * qtb;
-  }
-  // ---- reverse: equilibrium and the two sides
-  double cb[5] = {0, 0, 0, 0, 0}, ctb[5] = {0, 0, 0, 0, 0}, taub = 0.0;
-  phase_barrier();
-  equilibrium_b(s0, K, iKd, in.nL, in.nR, in.Wt, tc, ab, inb.nL, inb.nR, inb.Wt, s0b, cb, ctb);
+  for (int i = 0; i < 5; ++i) { cb[i] = 0.0; ctb[i] = 0.0; }
+  taub = 0.0;
+  eb = 0.0;
 #pragma unroll 1
-  for (int side = 0; side < 2; ++side) {
+  for (int ph0 = 0; ph0 < 7; ++ph0) {
     phase_barrier();
-    const double sgn = side == 0 ? 1.0 : -1.0;
-    Prim<double> s;
-    Mom<double> h, hb;
-    side_state(side == 0 ? in.WL : in.WR, gam, K, sgn, s, h);
-    mom_zero(hb);
-    PrimB sb = primb_zero();
-    double wtb[4];  // selected by value: a pointer select would put both arrays in scratch memory
+    const int ph = opaque_int(ph0);
+    if (ph == 0) {
+      // ---- forward
+      double F[4], Ft[4], We[4], Wet[4], WtL[4], WtR[4];
+      {
+        Prim<double> sL, sR;
+        Mom<double> hL, hR;
+        side_state(in.WL, gam, K, 1.0, sL, hL);
+        side_state(in.WR, gam, K, -1.0, sR, hR);
+        {
+          double pL[4], pR[4], u[4];
+          psi_moms<double, 2>(hL, pL, u);
+          psi_moms<double, 2>(hR, pR, u);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) wtb[i] = side == 0 ? WtLb[i] : WtRb[i];
-    side_terms_b(s, h, side == 0 ? in.nL : in.nR, in.Wt, K, iKd, tau, tc, ab, wtb, side == 0 ? inb.nL : inb.nR,
-                 inb.Wt, sb, hb, taub, cb, ctb);
-    mom_half_b(s, sgn, h, hb, sb);
-    mom_common_b(s, K, h, hb, sb);
-    if (side == 0) sLb = sb;
-    else sRb = sb;
-  }
-  // ---- reverse: collision time and time coefficients
-  phase_barrier();
-  taub += time_coef_b(dt, tau, cb, ctb, eb);
-  if (k.mu > 0) s0b.p += -k.mu / (s0.p * s0.p) * taub;
-  {
-    const Prim<double> pl = prim<double, 2>(in.WL, gam), pr = prim<double, 2>(in.WR, gam);
-    const double dP = pl.p - pr.p, sP = pl.p + pr.p;
-    const double g = k.tau_c2 * dt, sg = dP > 0 ? 1.0 : (dP < 0 ? -1.0 : 0.0), ad = m_abs(dP);
-    sLb.p += g * (sg / sP - ad / (sP * sP)) * taub;
-    sRb.p += g * (-sg / sP - ad / (sP * sP)) * taub;
-  }
-  // ---- reverse: compatibility state W0, then each side's state
-  double W0b[4] = {0, 0, 0, 0};
-  prim_b(W0f, s0, gam, s0b, W0b);
-#pragma unroll 1
-  for (int side = 0; side < 2; ++side) {
-    phase_barrier();
-    const double sgn = side == 0 ? 1.0 : -1.0;
-    Prim<double> s;
-    Mom<double> h, hb;
-    side_state(side == 0 ? in.WL : in.WR, gam, K, sgn, s, h);
-    mom_zero(hb);
-    PrimB sb;
-    sb.rho = side == 0 ? sLb.rho : sRb.rho;
-    sb.irho = side == 0 ? sLb.irho : sRb.irho;
-    sb.U = side == 0 ? sLb.U : sRb.U;
-    sb.V = side == 0 ? sLb.V : sRb.V;
-    sb.p = side == 0 ? sLb.p : sRb.p;
-    sb.i2l = side == 0 ? sLb.i2l : sRb.i2l;
-    sb.lam = side == 0 ? sLb.lam : sRb.lam;
-    const double zero[4] = {0, 0, 0, 0};
-    double p[4], u[4], pb[4];
-    psi_moms<double, 2>(h, p, u);
+          for (int i = 0; i < 4; ++i) W0[i] = sL.rho * pL[i] + sR.rho * pR[i];
+        }
+        const Prim<double> s0 = prim<double, 2>(W0, gam);
+        tau = (k.mu > 0 ? k.mu / s0.p : k.tau_c1 * dt) + k.tau_c2 * dt * m_abs(sL.p - sR.p) / (sL.p + sR.p);
+        const TimeCoef<double> tc = time_coef(dt, tau);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      pb[i] = s.rho * W0b[i];
-      sb.rho += p[i] * W0b[i];
+        for (int i = 0; i < 4; ++i) { F[i] = 0.0; Ft[i] = 0.0; We[i] = 0.0; Wet[i] = 0.0; }
+        side_terms<double, 2, true>(sL, hL, in.nL, in.Wt, K, iKd, tau, tc, true, F, Ft, We, Wet, WtL);
+        side_terms<double, 2, true>(sR, hR, in.nR, in.Wt, K, iKd, tau, tc, true, F, Ft, We, Wet, WtR);
+        Mom<double> m0;
+        mom_common<double, 2>(s0, K, m0);
+        mom_full(s0, m0);
+        double a0[4], b0[4], A0[4], d[4], t0[4], tu0[4], Ap0[4], Au0[4], p0[4], u0[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[i] = 0.5 * (in.nL[i] + in.nR[i]) * s0.irho;
+        slope<double, 2>(s0, K, iKd, d, a0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[i] = in.Wt[i] * s0.irho;
+        slope<double, 2>(s0, K, iKd, d, b0);
+        transport<double, 2>(a0, b0, m0, t0, tu0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) d[i] = -t0[i];
+        slope<double, 2>(s0, K, iKd, d, A0);
+        tslope<double, 2>(A0, m0, Ap0, Au0);
+        psi_moms<double, 2>(m0, p0, u0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          Ft[i] += s0.rho * (tc.ct[0] * u0[i] + tc.ct[1] * tu0[i] + tc.ct[2] * Au0[i]);
+          Wet[i] += s0.rho * (tc.ct[0] * p0[i] + tc.ct[1] * t0[i] + tc.ct[2] * Ap0[i]);
+          F[i] += s0.rho * (tc.c[0] * u0[i] + tc.c[1] * tu0[i] + tc.c[2] * Au0[i]);
+          We[i] += s0.rho * (tc.c[0] * p0[i] + tc.c[1] * t0[i] + tc.c[2] * Ap0[i]);
+        }
+      }
+      // ---- reverse: outputs
+      GksIO<double, 2> ob;
+      obload(ob);
+      const double e = time_coef(dt, tau).e1, oe = 1.0 - e;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ab.Wet[i] = oe * (ob.Wlt[i] + ob.Wrt[i]);
+        WtLb[i] = e * ob.Wlt[i];
+        WtRb[i] = e * ob.Wrt[i];
+        ab.We[i] = oe * (ob.Wl[i] + ob.Wr[i]);
+        inb.WL[i] += e * ob.Wl[i];
+        inb.WR[i] += e * ob.Wr[i];
+        eb += (WtL[i] - Wet[i]) * ob.Wlt[i] + (WtR[i] - Wet[i]) * ob.Wrt[i] + (in.WL[i] - We[i]) * ob.Wl[i] +
+              (in.WR[i] - We[i]) * ob.Wr[i];
+        ab.F[i] = ob.F[i];
+        ab.Ft[i] = ob.Ft[i];
+      }
+      // ---- reverse: Prandtl correction (F, Ft hold the values before it)
+      if (k.mu > 0) {
+        const Prim<double> s0 = prim<double, 2>(W0, gam);
+        const double U = s0.U, V = s0.V, f = k.prfix;
+        const double a = 1.5 * U * U + 0.5 * V * V, bq = 0.5 * U * (U * U + V * V);
+        const double qb = f * ab.F[3], qtb = f * ab.Ft[3];
+        s0b.U += qb * (-F[1] + 3.0 * U * F[0] - We[3] + V * We[2] - 0.5 * (3.0 * U * U + V * V) * We[0]) +
+                 qtb * (-Ft[1] + 3.0 * U * Ft[0] - Wet[3] + V * Wet[2] - 0.5 * (3.0 * U * U + V * V) * Wet[0]);
+        s0b.V += qb * (-F[2] + V * F[0] + U * We[2] - U * V * We[0]) +
+                 qtb * (-Ft[2] + V * Ft[0] + U * Wet[2] - U * V * Wet[0]);
+        ab.F[3] += qb; ab.F[1] += -U * qb; ab.F[2] += -V * qb; ab.F[0] += a * qb;
+        ab.We[3] += -U * qb; ab.We[2] += U * V * qb; ab.We[0] += -bq * qb;
+        ab.Ft[3] += qtb; ab.Ft[1] += -U * qtb; ab.Ft[2] += -V * qtb; ab.Ft[0] += a * qtb;
+        ab.Wet[3] += -U * qtb; ab.Wet[2] += U * V * qtb; ab.Wet[0] += -bq * qtb;
+      }
+    } else if (ph == 1) {
+      // ---- reverse: equilibrium
+      const Prim<double> s0 = prim<double, 2>(W0, gam);
+      equilibrium_b(s0, K, iKd, in.nL, in.nR, in.Wt, time_coef(dt, tau), ab, inb.nL, inb.nR, inb.Wt, s0b, cb, ctb);
+    } else if (ph <= 3) {
+      // ---- reverse: one side's terms, reduced to the adjoint of its W
+      const int side = ph - 2;
+      const double sgn = side == 0 ? 1.0 : -1.0;
+      Prim<double> s;
+      Mom<double> h, hb;
+      side_state(side == 0 ? in.WL : in.WR, gam, K, sgn, s, h);
+      mom_zero(hb);
+      PrimB sb = primb_zero();
+      double wtb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) wtb[i] = side == 0 ? WtLb[i] : WtRb[i];
+      side_terms_b(s, h, side == 0 ? in.nL : in.nR, in.Wt, K, iKd, tau, time_coef(dt, tau), ab, wtb,
+                   side == 0 ? inb.nL : inb.nR, inb.Wt, sb, hb, taub, cb, ctb);
+      mom_half_b(s, sgn, h, hb, sb);
+      mom_common_b(s, K, h, hb, sb);
+      prim_b(side == 0 ? in.WL : in.WR, s, gam, sb, side == 0 ? inb.WL : inb.WR);
+    } else if (ph == 4) {
+      // ---- reverse: collision time and time coefficients; the adjoint of W0
+      const Prim<double> s0 = prim<double, 2>(W0, gam);
+      taub += time_coef_b(dt, tau, cb, ctb, eb);
+      if (k.mu > 0) s0b.p += -k.mu / (s0.p * s0.p) * taub;
+      const Prim<double> pl = prim<double, 2>(in.WL, gam), pr = prim<double, 2>(in.WR, gam);
+      const double dP = pl.p - pr.p, sP = pl.p + pr.p;
+      const double g = k.tau_c2 * dt, sg = dP > 0 ? 1.0 : (dP < 0 ? -1.0 : 0.0), ad = m_abs(dP);
+      // reuse: cb[0..3] = adjoint of W0, cb[4], ctb[0] = adjoints of the two sides' p
+      const double pLb = g * (sg / sP - ad / (sP * sP)) * taub;
+      const double pRb = g * (-sg / sP - ad / (sP * sP)) * taub;
+      double W0b[4] = {0, 0, 0, 0};
+      prim_b(W0, s0, gam, s0b, W0b);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cb[i] = W0b[i];
+      cb[4] = pLb;
+      ctb[0] = pRb;
+    } else {
+      // ---- reverse: the compatibility state's share of each side's state
+      const int side = ph - 5;
+      const double sgn = side == 0 ? 1.0 : -1.0;
+      Prim<double> s;
+      Mom<double> h, hb;
+      side_state(side == 0 ? in.WL : in.WR, gam, K, sgn, s, h);
+      mom_zero(hb);
+      PrimB sb = primb_zero();
+      sb.p = side == 0 ? cb[4] : ctb[0];
+      const double zero[4] = {0, 0, 0, 0};
+      double p[4], u[4], pb[4];
+      psi_moms<double, 2>(h, p, u);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        pb[i] = s.rho * cb[i];
+        sb.rho += p[i] * cb[i];
+      }
+      psi_moms_b(h, pb, zero, hb);
+      mom_half_b(s, sgn, h, hb, sb);
+      mom_common_b(s, K, h, hb, sb);
+      prim_b(side == 0 ? in.WL : in.WR, s, gam, sb, side == 0 ? inb.WL : inb.WR);
     }
-    psi_moms_b(h, pb, zero, hb);
-    mom_half_b(s, sgn, h, hb, sb);
-    mom_common_b(s, K, h, hb, sb);
-    prim_b(side == 0 ? in.WL : in.WR, s, gam, sb, side == 0 ? inb.WL : inb.WR);
   }
 }
 
