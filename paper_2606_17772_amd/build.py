@@ -34,8 +34,9 @@ FLAGS = [
     # loop of the solver adjoint (and of the persistent batch and 1D step
     # loops), the 64-bit constants of erfc/exp and similar invariants are held
     # in registers through every iteration and spill.  Measured on the 2048^2
-    # workload: step VJP -2.7%, persistent batch +27%, 1D runs +5-8%; the
-    # interface, node and update sweeps compile to the same code
+    # workload: step VJP -2.7%, persistent batch +27%, 1D runs +5-8%; the 2D
+    # interface, node and update sweeps compile to the same code, the other
+    # kernels within noise
     "-mllvm", "-disable-machine-licm",
     "-I", os.path.join(ROOT, "include"),
 ]

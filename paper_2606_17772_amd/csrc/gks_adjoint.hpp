@@ -466,9 +466,10 @@ template <class T> FDK_HD T* opaque_ptr(T* p) {
 // them in LDS).
 //
 // The work runs as seven phases, the iterations of one loop over an opaque
-// phase number; only W0, tau and a few adjoint accumulators (about 40
-// doubles) are carried from phase to phase, everything else is recomputed in
-// the phase that needs it:
+// phase number; only W0, tau, the compatibility state's adjoint and the
+// seeds of the two sides' time derivatives (20 doubles) are carried in
+// registers from phase to phase, the time-coefficient adjoints in ab, and
+// everything else is recomputed in the phase that needs it:
 //   0  forward solve (kept: W0, tau), then the reverse of the output blend
 //      and of the Prandtl correction;
 //   1  reverse of the equilibrium part;
