@@ -84,7 +84,7 @@ enum { FDCGKS_FLUX_6_4 = 0, FDCGKS_FLUX_6_2 = 1, FDCGKS_FLUX_LINEAR = 2 };
  *        - 3 (F_{j-1} + F_{j+2})) / 420,
  * exact to degree 7.  The flux variant's low-order term and blend are the same
  * for both.  Order 8 is available to fdcgks_problem steps (1D and 2D, every
- * boundary); the step adjoint and batches reject it with FDCGKS_EINVAL. */
+ * boundary) and to batches; the step adjoint rejects it with FDCGKS_EINVAL. */
 /* Precision of the gas-kinetic solver; reconstruction and update stay FP64. */
 enum { FDCGKS_FP64 = 0, FDCGKS_FP32_FLUX = 1 };
 /* Base of the averaged-gradient update (Eq. eq-interface-update): the gradient
@@ -96,8 +96,8 @@ enum { FDCGKS_GRAD_REEVAL = 0, FDCGKS_GRAD_CARRIED = 1 };
  * the eigenvectors at the mean of the two interface-adjacent states (at the
  * node's own state for node derivatives) and the path function the smallest
  * of the acoustic fields' left and right values.  Characteristic mode is
- * available to fdcgks_problem steps (1D and 2D, either flux precision); the
- * step adjoint and batches reject it with FDCGKS_EINVAL. */
+ * available to fdcgks_problem steps (1D and 2D, either flux precision) and to
+ * batches; the step adjoint rejects it with FDCGKS_EINVAL. */
 enum { FDCGKS_RECON_CONSERVATIVE = 0, FDCGKS_RECON_CHARACTERISTIC = 1 };
 
 typedef struct fdcgks_params {
@@ -349,9 +349,11 @@ typedef struct fdcgks_batch fdcgks_batch; /* opaque, owned by the library */
  * give bitwise the same results. */
 enum { FDCGKS_BATCH_PERSISTENT = 0, FDCGKS_BATCH_PHASED = 1, FDCGKS_BATCH_GRAPH = 2 };
 
-/* params[count]: every member 2D with conservative reconstruction and
- * flux_order 6 (EINVAL otherwise); members may differ only in nx, ny, x0,
- * lx, y0, ly and their sides (bc, side[4]).
+/* params[count]: every member 2D (EINVAL otherwise); members may differ only
+ * in nx, ny, x0, lx, y0, ly and their sides (bc, side[4]): the scheme
+ * constants, the reconstruction variables, the flux order and the flux
+ * precision are the batch's, and each member advances bit for bit like the
+ * same problem alone.
  * Allocates all device memory on the current device. */
 fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, void* hip_stream, fdcgks_batch** out);
 fdcgks_status fdcgks_batch_set_state(fdcgks_batch* b, int32_t member, int32_t grid, const double* W,

@@ -1623,7 +1623,7 @@ __device__ __forceinline__ void batch_step_end(const BArgs& a, const Consts& k) 
   if (threadIdx.x == 0 && threadIdx.y == 0) a.sc->steps += 1;
 }
 
-template <int STAGE, class FT>
+template <int STAGE, class FT, bool CHAR, bool WIDE>
 __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
   namespace cg = cooperative_groups;
   cg::grid_group grid = cg::this_grid();
@@ -1654,8 +1654,8 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
     for (int q = blockIdx.x; q < a.n_edge; q += nb) {
       const BItem& w = it[q];
       const BMember& M = a.mem[w.m];
-      edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z,
-                            w.z == 0 ? -2 : -1 - M.g.sx);
+      edge_block<STAGE, FT, CHAR>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by,
+                                  w.z, w.z == 0 ? -2 : -1 - M.g.sx);
     }
   }
   it += a.n_edge;
@@ -1663,7 +1663,8 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
     for (int q = blockIdx.x; q < a.n_node; q += nb) {
       const BItem& w = it[q];
       const BMember& M = a.mem[w.m];
-      node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1, -OX);
+      node_block<STAGE, FT, CHAR>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, node_reach(k),
+                                  -OX);
     }
   }
   it += a.n_node;
@@ -1676,11 +1677,11 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
       const double dt = member_dt(a, w.m, k);
       double cs = 0.0, cr = 0.0;  // batches reduce their time steps themselves
       if (STAGE == 1)
-        update_block<1, false>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc,
-                               w.m, false, cs, cr);
+        update_block<1, WIDE>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc,
+                              w.m, false, cs, cr);
       else
-        update_block<2, false>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z,
-                               a.sc, w.m, false, cs, cr);
+        update_block<2, WIDE>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z,
+                              a.sc, w.m, false, cs, cr);
     }
   }
   if (STAGE == 2) {
@@ -1710,22 +1711,23 @@ __global__ __launch_bounds__(256) void k_bphase_halo(BArgs a, Consts k) {
   const BMember& M = a.mem[it.m];
   halo_plane_block(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.g, it.z);
 }
-template <int STAGE, class FT>
+// CHAR: characteristic reconstruction; WIDE: the order-8 flux (node reach 2).
+template <int STAGE, class FT, bool CHAR>
 __global__ __launch_bounds__(256, FDCGKS_EDGE_WAVES) void k_bphase_edges(BArgs a, Consts k) {
   if (a.sc->stop) return;
   const BItem& w = a.items[a.n_cfl + a.n_halo + blockIdx.x];
   const BMember& M = a.mem[w.m];
-  edge_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by, w.z,
-                        w.z == 0 ? -2 : -1 - M.g.sx);
+  edge_block<STAGE, FT, CHAR>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by,
+                              w.z, w.z == 0 ? -2 : -1 - M.g.sx);
 }
-template <int STAGE, class FT>
+template <int STAGE, class FT, bool CHAR>
 __global__ __launch_bounds__(256) void k_bphase_nodes(BArgs a, Consts k) {
   if (a.sc->stop) return;
   const BItem& w = a.items[a.n_cfl + a.n_halo + a.n_edge + blockIdx.x];
   const BMember& M = a.mem[w.m];
-  node_block<STAGE, FT>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, 1, -OX);
+  node_block<STAGE, FT, CHAR>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.Nb, M.g, k, w.bx, w.by, w.z, node_reach(k), -OX);
 }
-template <int STAGE>
+template <int STAGE, bool WIDE>
 __global__ __launch_bounds__(256) void k_bphase_update(BArgs a, Consts k) {
   if (a.sc->stop) return;
   const BItem& w = a.items[a.n_cfl + a.n_halo + a.n_edge + a.n_node + blockIdx.x];
@@ -1733,11 +1735,11 @@ __global__ __launch_bounds__(256) void k_bphase_update(BArgs a, Consts k) {
   const double dt = member_dt(a, w.m, k);
   double cs = 0.0, cr = 0.0;  // batches reduce their time steps themselves
   if (STAGE == 1)
-    update_block<1, false>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m,
-                           false, cs, cr);
+    update_block<1, WIDE>(M.S[a.cur], M.E, M.Nb, nullptr, M.Sstar, M.Acc, M.g, k, dt, w.bx, w.by, w.z, a.sc, w.m,
+                          false, cs, cr);
   else
-    update_block<2, false>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z, a.sc,
-                           w.m, false, cs, cr);
+    update_block<2, WIDE>(M.Sstar, M.E, M.Nb, M.Acc, M.S[a.cur ^ 1], nullptr, M.g, k, dt, w.bx, w.by, w.z, a.sc,
+                          w.m, false, cs, cr);
 }
 __global__ void k_bphase_end(BArgs a, Consts k) { batch_step_end(a, k); }
 
@@ -3031,38 +3033,51 @@ bool same_scheme(const fdcgks_params& a, const fdcgks_params& b) {
          a.flux_precision == b.flux_precision && a.grad_update == b.grad_update && a.geno_r == b.geno_r &&
          a.geno_C == b.geno_C && a.geno_eps == b.geno_eps && a.geno_eps_a == b.geno_eps_a &&
          a.geno_d_central == b.geno_d_central && a.geno_d_side == b.geno_d_side && a.tau_c1 == b.tau_c1 &&
-         a.tau_c2 == b.tau_c2;
+         a.tau_c2 == b.tau_c2 && a.recon_vars == b.recon_vars && a.flux_order == b.flux_order;
 }
 
 // Steps per captured batch graph (even, so that a graph keeps the parity).
 constexpr int BATCH_GRAPH_STEPS = 16;
 
 // One batched step as one launch per phase on `stream`.
-void batch_phased_step(const BArgs& a, const Consts& k, bool fp32, hipStream_t stream) {
+template <class FT, bool CHAR, bool WIDE>
+void batch_phased_step_t(const BArgs& a, const Consts& k, hipStream_t stream) {
   const dim3 blk(64, 4);
   hipLaunchKernelGGL(k_bphase_halo<1>, dim3(a.n_cfl + a.n_halo), blk, 0, stream, a, k);
-  if (fp32) {
-    hipLaunchKernelGGL((k_bphase_edges<1, float>), dim3(a.n_edge), blk, 0, stream, a, k);
-    hipLaunchKernelGGL((k_bphase_nodes<1, float>), dim3(a.n_node), blk, 0, stream, a, k);
-  } else {
-    hipLaunchKernelGGL((k_bphase_edges<1, double>), dim3(a.n_edge), blk, 0, stream, a, k);
-    hipLaunchKernelGGL((k_bphase_nodes<1, double>), dim3(a.n_node), blk, 0, stream, a, k);
-  }
-  hipLaunchKernelGGL(k_bphase_update<1>, dim3(a.n_upd), blk, 0, stream, a, k);
+  hipLaunchKernelGGL((k_bphase_edges<1, FT, CHAR>), dim3(a.n_edge), blk, 0, stream, a, k);
+  hipLaunchKernelGGL((k_bphase_nodes<1, FT, CHAR>), dim3(a.n_node), blk, 0, stream, a, k);
+  hipLaunchKernelGGL((k_bphase_update<1, WIDE>), dim3(a.n_upd), blk, 0, stream, a, k);
   hipLaunchKernelGGL(k_bphase_halo<2>, dim3(a.n_halo), blk, 0, stream, a, k);
-  if (fp32) {
-    hipLaunchKernelGGL((k_bphase_edges<2, float>), dim3(a.n_edge), blk, 0, stream, a, k);
-    hipLaunchKernelGGL((k_bphase_nodes<2, float>), dim3(a.n_node), blk, 0, stream, a, k);
-  } else {
-    hipLaunchKernelGGL((k_bphase_edges<2, double>), dim3(a.n_edge), blk, 0, stream, a, k);
-    hipLaunchKernelGGL((k_bphase_nodes<2, double>), dim3(a.n_node), blk, 0, stream, a, k);
-  }
-  hipLaunchKernelGGL(k_bphase_update<2>, dim3(a.n_upd), blk, 0, stream, a, k);
+  hipLaunchKernelGGL((k_bphase_edges<2, FT, CHAR>), dim3(a.n_edge), blk, 0, stream, a, k);
+  hipLaunchKernelGGL((k_bphase_nodes<2, FT, CHAR>), dim3(a.n_node), blk, 0, stream, a, k);
+  hipLaunchKernelGGL((k_bphase_update<2, WIDE>), dim3(a.n_upd), blk, 0, stream, a, k);
   hipLaunchKernelGGL(k_bphase_end, dim3(1), blk, 0, stream, a, k);
 }
+void batch_phased_step(const BArgs& a, const Consts& k, bool fp32, bool chr, hipStream_t stream) {
+  using Step = void (*)(const BArgs&, const Consts&, hipStream_t);
+  static const Step steps[2][2][2] = {
+      {{batch_phased_step_t<double, false, false>, batch_phased_step_t<double, false, true>},
+       {batch_phased_step_t<double, true, false>, batch_phased_step_t<double, true, true>}},
+      {{batch_phased_step_t<float, false, false>, batch_phased_step_t<float, false, true>},
+       {batch_phased_step_t<float, true, false>, batch_phased_step_t<float, true, true>}}};
+  steps[fp32][chr][k.flux_order == 8](a, k, stream);
+}
 
-template <class FT> void* batch_kernel(int stage) {
-  return stage == 1 ? reinterpret_cast<void*>(k_batch_stage<1, FT>) : reinterpret_cast<void*>(k_batch_stage<2, FT>);
+// The cooperative persistent kernel of one stage for the batch's scheme.
+template <int STAGE> void* batch_kernel_t(bool fp32, bool chr, bool wide) {
+  static void* const fns[2][2][2] = {
+      {{reinterpret_cast<void*>(k_batch_stage<STAGE, double, false, false>),
+        reinterpret_cast<void*>(k_batch_stage<STAGE, double, false, true>)},
+       {reinterpret_cast<void*>(k_batch_stage<STAGE, double, true, false>),
+        reinterpret_cast<void*>(k_batch_stage<STAGE, double, true, true>)}},
+      {{reinterpret_cast<void*>(k_batch_stage<STAGE, float, false, false>),
+        reinterpret_cast<void*>(k_batch_stage<STAGE, float, false, true>)},
+       {reinterpret_cast<void*>(k_batch_stage<STAGE, float, true, false>),
+        reinterpret_cast<void*>(k_batch_stage<STAGE, float, true, true>)}}};
+  return fns[fp32][chr][wide];
+}
+void* batch_kernel(int stage, bool fp32, bool chr, bool wide) {
+  return stage == 1 ? batch_kernel_t<1>(fp32, chr, wide) : batch_kernel_t<2>(fp32, chr, wide);
 }
 }  // namespace
 
@@ -3076,9 +3091,6 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
     fdcgks_status st = check_params(&params[m]);
     if (st) return bfail(nullptr, st, "member %d: %s", m, std::string(g_create_error).c_str());
     if (params[m].dim != 2) return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches are 2D only", m);
-    if (params[m].recon_vars != FDCGKS_RECON_CONSERVATIVE)
-      return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches reconstruct conservative variables only", m);
-    if (params[m].flux_order != 6) return bfail(nullptr, FDCGKS_EINVAL, "member %d: batches use the order-6 flux", m);
     if (!same_scheme(params[0], params[m]))
       return bfail(nullptr, FDCGKS_EINVAL, "member %d: scheme constants differ from member 0", m);
   }
@@ -3112,7 +3124,7 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
   k.r = p.geno_r;
   k.variant = p.flux_variant;
   k.grad_carried = p.grad_update == FDCGKS_GRAD_CARRIED;
-  k.flux_order = 6;
+  k.flux_order = p.flux_order;
   // per-member buffers and work lists
   std::vector<BItem> cfl, halo, edge, node, upd;
   b->mem.resize(count);
@@ -3144,9 +3156,10 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
     for (int z = 0; z < 2; ++z)
       for (int by = 0; by < ceil_div(g.ny + 3 + g.sy, 2); ++by)
         for (int bx = 0; bx < ceil_div(g.nx + 3 + g.sx, 64); ++bx) edge.push_back({m, z, bx, by});
+    const int w = node_reach(k);  // nodes beyond the grid's own that the update reads
     for (int z = 0; z < 2; ++z)
-      for (int by = 0; by < ceil_div(g.ny + 2 + g.sy, 4); ++by)
-        for (int bx = 0; bx < ceil_div(g.nx + 1 + OX, 64); ++bx) node.push_back({m, z, bx, by});  // from i = -OX
+      for (int by = 0; by < ceil_div(g.ny + 2 * w + g.sy, 4); ++by)
+        for (int bx = 0; bx < ceil_div(g.nx + w + OX, 64); ++bx) node.push_back({m, z, bx, by});  // from i = -OX
     for (int z = 0; z < 2; ++z)
       for (int by = 0; by < ceil_div(g.ny + g.sy, 4); ++by)
         for (int bx = 0; bx < ceil_div(g.nx + g.sx, 64); ++bx) upd.push_back({m, z, bx, by});
@@ -3183,12 +3196,11 @@ fdcgks_status fdcgks_batch_create(int32_t count, const fdcgks_params* params, vo
   // resident workgroups of the cooperative grid
   if (e == hipSuccess) {
     int nb1 = 0, nb2 = 0;
-    bool fp32 = p.flux_precision == FDCGKS_FP32_FLUX;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, fp32 ? batch_kernel<float>(1) : batch_kernel<double>(1),
-                                                     256, 0);
+    const bool fp32 = p.flux_precision == FDCGKS_FP32_FLUX, chr = p.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
+    const bool wide = p.flux_order == 8;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb1, batch_kernel(1, fp32, chr, wide), 256, 0);
     if (e == hipSuccess)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, fp32 ? batch_kernel<float>(2) : batch_kernel<double>(2),
-                                                       256, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, batch_kernel(2, fp32, chr, wide), 256, 0);
     b->blocks = std::max(1, std::min(nb1, nb2)) * ncu;
   }
   if (e != hipSuccess) {
@@ -3278,6 +3290,7 @@ fdcgks_status fdcgks_batch_step(fdcgks_batch* b, double cfl, int32_t nsteps, dou
   a.dt_last = b->dt_last;
   a.sc = b->sc;
   const bool fp32 = b->prm0.flux_precision == FDCGKS_FP32_FLUX;
+  const bool chr = b->prm0.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
   int s = 0;
   if (b->mode == FDCGKS_BATCH_GRAPH && nsteps >= BATCH_GRAPH_STEPS) {
     // whole graphs of BATCH_GRAPH_STEPS (even) steps leave cur and parity unchanged
@@ -3292,7 +3305,7 @@ fdcgks_status fdcgks_batch_step(fdcgks_batch* b, double cfl, int32_t nsteps, dou
       for (int q = 0; q < BATCH_GRAPH_STEPS; ++q) {
         a.cur = cur0 ^ (q & 1);
         a.parity = par0 ^ (q & 1);
-        batch_phased_step(a, b->k, fp32, b->cap);
+        batch_phased_step(a, b->k, fp32, chr, b->cap);
       }
       hipGraph_t gr = nullptr;
       hipError_t e = hipStreamEndCapture(b->cap, &gr);
@@ -3314,12 +3327,12 @@ fdcgks_status fdcgks_batch_step(fdcgks_batch* b, double cfl, int32_t nsteps, dou
     if (b->mode == FDCGKS_BATCH_PERSISTENT) {
       void* args[2] = {&a, &b->k};
       for (int stage = 1; stage <= 2; ++stage) {
-        void* fn = fp32 ? batch_kernel<float>(stage) : batch_kernel<double>(stage);
+        void* fn = batch_kernel(stage, fp32, chr, b->k.flux_order == 8);
         BHIPCHK(b, hipLaunchCooperativeKernel(fn, dim3(b->blocks), dim3(64, 4), args, 0, b->stream));
       }
       continue;
     }
-    batch_phased_step(a, b->k, fp32, b->stream);
+    batch_phased_step(a, b->k, fp32, chr, b->stream);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, FDCGKS_EHIP, "batched launch failed: %s", hipGetErrorString(e));
   }

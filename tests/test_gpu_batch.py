@@ -1,6 +1,7 @@
 """Batched 2D solves over many uneven grids, in every launch mode (one launch
 per phase, also captured as HIP graphs; one cooperative persistent launch per
-stage), with periodic and bounded members, against the single-problem HIP
+stage), with periodic and bounded members and each scheme option
+(characteristic reconstruction, order-8 flux), against the single-problem HIP
 path and the oracle (GPU)."""
 import numpy as np
 import pytest
@@ -167,6 +168,48 @@ def test_bounded_members_match_single_problems_bitwise(mode):
         assert ns == 18 and t[k] == ts, (k, t[k], ts)
         for g in (0, 1):
             assert np.array_equal(B.get_state_stacked(k, g), pb.get_state_stacked(g)), (k, g)
+
+
+SCHEMES = {"char": dict(recon_vars="characteristic"), "order8": dict(flux_order=8),
+           "char_order8": dict(recon_vars="characteristic", flux_order=8)}
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("scheme", list(SCHEMES))
+def test_scheme_options_match_single_problems_bitwise(mode, scheme):
+    """Characteristic reconstruction and the order-8 compact flux in a batch:
+    periodic and bounded members of uneven sizes advance bit for bit like the
+    same problems alone (18 steps: the graph mode replays a captured graph
+    and launches the remainder).  The single-problem path of each option is
+    held to the oracle by its own tests."""
+    from paper_2606_17772_amd import Problem
+    kw = SCHEMES[scheme]
+    mem = [(_settings(p), p.P, p.D) for p in _members([16, 37, 23], seed=21)] + _bounded_members()
+    mem = [(dict(s, **kw), P, D) for s, P, D in mem]
+    B = _batch(None, mode, [m[0] for m in mem])
+    for k, (s, P, D) in enumerate(mem):
+        B.set_state_stacked(k, 0, P)
+        B.set_state_stacked(k, 1, D)
+    t, dt, n = B.step(nsteps=18, cfl=0.4)
+    assert n == 18
+    for k, (s, P, D) in enumerate(mem):
+        pb = Problem(gpu_params(s))
+        pb.set_state_stacked(0, P)
+        pb.set_state_stacked(1, D)
+        ts, ns = pb.step(nsteps=18, cfl=0.4)
+        assert ns == 18 and t[k] == ts, (k, t[k], ts)
+        for g in (0, 1):
+            assert np.array_equal(B.get_state_stacked(k, g), pb.get_state_stacked(g)), (scheme, k, g)
+
+
+def test_scheme_options_must_agree_across_members():
+    """One batch runs one scheme: members that differ in reconstruction
+    variables or flux order are rejected at creation."""
+    from paper_2606_17772_amd import Batch, FdcgksError
+    a = _settings(WL.vortex(16, seed=1))
+    for kw in SCHEMES.values():
+        with pytest.raises(FdcgksError, match="scheme constants differ"):
+            Batch([gpu_params(a), gpu_params(dict(a, **kw))])
 
 
 def test_bounded_members_against_oracle():
