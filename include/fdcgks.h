@@ -84,7 +84,7 @@ enum { FDCGKS_FLUX_6_4 = 0, FDCGKS_FLUX_6_2 = 1, FDCGKS_FLUX_LINEAR = 2 };
  *        - 3 (F_{j-1} + F_{j+2})) / 420,
  * exact to degree 7.  The flux variant's low-order term and blend are the same
  * for both.  Order 8 is available to fdcgks_problem steps (1D and 2D, every
- * boundary) and to batches; the step adjoint rejects it with FDCGKS_EINVAL. */
+ * boundary), to batches and to the step adjoint. */
 /* Precision of the gas-kinetic solver; reconstruction and update stay FP64. */
 enum { FDCGKS_FP64 = 0, FDCGKS_FP32_FLUX = 1 };
 /* Base of the averaged-gradient update (Eq. eq-interface-update): the gradient
@@ -310,7 +310,8 @@ fdcgks_status fdcgks_autotune(fdcgks_problem* pb, int32_t reps);
 /* ---------------------------------------------------------------- adjoint
  * Vector-Jacobian product of one S2O4 step (Sec. 2.3 stages with the
  * interface and nodal solvers of Sec. 2, the compact flux of
- * Eq. fd-conservative-flux and the GENO reconstructions of Sec. 3) taken at
+ * Eq. fd-conservative-flux of order 6 or 8 and the GENO reconstructions of
+ * Sec. 3) taken at
  * the current state with the time step dt held fixed (the CFL time step is
  * not differentiated).  lam_out[grid][12][ny][nx] is the adjoint of the step
  * output (W, Wx, Wy per grid, the get_state order); on return

@@ -76,29 +76,32 @@ __global__ __launch_bounds__(256) void k_adj_update(const double* __restrict__ l
   }
 }
 
-// Partial derivatives of the compact flux CF(Fm, Fc, Fp, N0, N1, chi).
+// Partial derivatives of the compact flux CF(Fm, Fc, Fp, [Nm,] N0, N1, [Np2,]
+// chi) of order 6 (Eq. fd-conservative-flux) or 8 (wide = true: the nodal
+// fluxes Nm, Np2 one node further out), with the (6-4)/(6-2) blend.
 struct CFd {
-  double dm, dc, dp, dn, dchi_lo;  // dchi = Fbar - lo needs the values
+  double dm, dc, dp, dn, dw;  // dn: N0 and N1; dw: Nm and Np2 (order 8)
 };
-__device__ __forceinline__ CFd cf_partials(int variant, double chi) {
+__device__ __forceinline__ CFd cf_partials(int variant, double chi, bool wide) {
+  // the linear flux Fbar = (a (Fm + Fp) + b Fc + c (N0 + N1) + e (Nm + Np2)) / den
+  const double den = wide ? 420.0 : 30.0, a = wide ? 32.0 : 1.0, b = wide ? 704.0 : 46.0;
+  const double c = wide ? -171.0 : -9.0, e = wide ? -3.0 : 0.0;
+  const double x = variant == 2 ? 1.0 : chi;  // the linear variant is Fbar itself
+  const double clo = variant == 1 ? 1.0 : 8.0 / 6.0, nlo = variant == 1 ? 0.0 : -1.0 / 6.0;
   CFd d;
-  if (variant == 2) {
-    d.dm = d.dp = 1.0 / 30.0;
-    d.dc = 46.0 / 30.0;
-    d.dn = -9.0 / 30.0;
-  } else {
-    const double clo = variant == 1 ? 1.0 : 8.0 / 6.0, nlo = variant == 1 ? 0.0 : -1.0 / 6.0;
-    d.dm = d.dp = chi / 30.0;
-    d.dc = (1.0 - chi) * clo + chi * 46.0 / 30.0;
-    d.dn = (1.0 - chi) * nlo + chi * (-9.0 / 30.0);
-  }
-  d.dchi_lo = 0.0;
+  d.dm = d.dp = x * a / den;
+  d.dc = (1.0 - x) * clo + x * b / den;
+  d.dn = (1.0 - x) * nlo + x * c / den;
+  d.dw = x * e / den;
   return d;
 }
-__device__ __forceinline__ double cf_dchi(int variant, double Fm, double Fc, double Fp, double N0, double N1) {
+// d CF / d chi = Fbar - lo (0 for the linear variant).
+__device__ __forceinline__ double cf_dchi(int variant, double Fm, double Fc, double Fp, double Nm, double N0,
+                                          double N1, double Np2, bool wide) {
   if (variant == 2) return 0.0;
-  double Fb = ((Fm + 46.0 * Fc + Fp) - 9.0 * (N0 + N1)) * (1.0 / 30.0);
-  double lo = variant == 1 ? Fc : (8.0 * Fc - N0 - N1) * (1.0 / 6.0);
+  const double Fb = wide ? ((32.0 * (Fm + Fp) + 704.0 * Fc) - 171.0 * (N0 + N1) - 3.0 * (Nm + Np2)) * (1.0 / 420.0)
+                         : ((Fm + 46.0 * Fc + Fp) - 9.0 * (N0 + N1)) * (1.0 / 30.0);
+  const double lo = variant == 1 ? Fc : (8.0 * Fc - N0 - N1) * (1.0 / 6.0);
   return Fb - lo;
 }
 
@@ -123,6 +126,7 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const double* __restrict__
   double* le = lamE + ((long)fam * 50 + G * 25) * pl + o;
   const long nL = -(long)G * st, nR = (long)(1 - G) * st;         // node offsets of interface e
   const int gop = ay ? 12 : 8, gopt = ay ? 20 : 16;               // gradient planes of this axis in lam_op
+  const bool wide = k.flux_order == 8;
   double lchi = 0.0;
   for (int c = 0; c < 4; ++c) {
     for (int tpart = (STAGE == 1 ? 0 : 1); tpart < 2; ++tpart) {
@@ -135,10 +139,12 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const double* __restrict__
         const long eo = q * st;
         const double lcf = (lL[eo + nR] - lL[eo + nL]) * g.invh;
         const double chi = e[8 * pl + eo];
-        const CFd d = cf_partials(k.variant, chi);
+        const CFd d = cf_partials(k.variant, chi, wide);
         lF += (q == -1 ? d.dp : (q == 0 ? d.dc : d.dm)) * lcf;
-        if (q == 0)
-          lchi += cf_dchi(k.variant, f[-st], f[0], f[st], n[nL], n[nR]) * lcf;
+        // (the nodal fluxes of interfaces without an interior node are not computed: skip them)
+        if (q == 0 && lcf != 0.0)
+          lchi += cf_dchi(k.variant, f[-st], f[0], f[st], wide ? n[nL - st] : 0.0, n[nL], n[nR],
+                          wide ? n[nR + st] : 0.0, wide) * lcf;
       }
       le[(tpart * 4 + c) * pl] = lF;
     }
@@ -158,28 +164,41 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const double* __restrict__
 }
 
 // Lambda of the nodal fluxes: node n is the left node (N0) of its right
-// interface e_R = n + G st and the right node (N1) of e_L = e_R - st.
+// interface e_R = n + G st and the right node (N1) of e_L = e_R - st; with
+// the order-8 flux also Nm of e_R + st and Np2 of e_L - st.  Nodes i, j in
+// [-w, n - 1 + w] (w = node reach): the nodes whose fluxes the forward sweep
+// computes.  Only interfaces with an interior node carry a flux adjoint.
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_adj_nodeflux(const double* __restrict__ lam_op, const double* __restrict__ E,
                                                       double* __restrict__ lamN, Geo g, Consts k) {
-  const int G = blockIdx.z;
-  const int i = blockIdx.x * 64 + threadIdx.x - 1, j = blockIdx.y * 4 + threadIdx.y - 1;
-  if (i > g.nx || j > g.ny) return;
+  const int G = blockIdx.z, w = node_reach(k);
+  const bool wide = w == 2;
+  const int i = blockIdx.x * 64 + threadIdx.x - w, j = blockIdx.y * 4 + threadIdx.y - w;
+  if (i > g.nx - 1 + w || j > g.ny - 1 + w) return;
   const long pl = g.plane, o = at(g, j, i);
   const double* op = lam_op + (long)G * OPN * pl + o;
   double* ln = lamN + (long)G * 16 * pl + o;
   for (int a = 0; a < 2; ++a) {
     const int fam = (G == 0) ? a : 1 - a;
     const long st = a == 0 ? 1 : g.pitch;
+    const int idx = a == 0 ? i : j, nn = a == 0 ? g.nx : g.ny;  // node index along the axis, nodes per line
     const double* e = E + ((long)fam * 50 + G * 25) * pl + o;
     const long eR = (long)G * st, eL = eR - st;
-    const double dR = cf_partials(k.variant, e[8 * pl + eR]).dn, dL = cf_partials(k.variant, e[8 * pl + eL]).dn;
+    // interface between nodes idx + m and idx + m + 1 (m = -2..1): at e offset eR + m st; it has an interior
+    // node when idx + m + 1 >= 0 and idx + m <= nn - 1
+    auto has = [&](int m) { return idx + m + 1 >= 0 && idx + m <= nn - 1; };
+    const CFd dR = has(0) ? cf_partials(k.variant, e[8 * pl + eR], wide) : CFd{0, 0, 0, 0, 0};
+    const CFd dL = has(-1) ? cf_partials(k.variant, e[8 * pl + eL], wide) : CFd{0, 0, 0, 0, 0};
+    const CFd dR2 = wide && has(1) ? cf_partials(k.variant, e[8 * pl + eR + st], wide) : CFd{0, 0, 0, 0, 0};
+    const CFd dL2 = wide && has(-2) ? cf_partials(k.variant, e[8 * pl + eL - st], wide) : CFd{0, 0, 0, 0, 0};
     for (int c = 0; c < 4; ++c)
       for (int tpart = (STAGE == 1 ? 0 : 1); tpart < 2; ++tpart) {
         const double* lL = op + (tpart * 4 + c) * pl;
-        // lambda of CF at e_R (left node n, right node n + st) and e_L (n - st, n)
-        const double lR = (lL[st] - lL[0]) * g.invh, lLf = (lL[0] - lL[-st]) * g.invh;
-        ln[(a * 8 + tpart * 4 + c) * pl] = dR * lR + dL * lLf;
+        // lambda of CF at the interface between nodes idx + m and idx + m + 1
+        auto lcf = [&](int m) { return has(m) ? (lL[(m + 1) * st] - lL[m * st]) * g.invh : 0.0; };
+        double v = dR.dn * lcf(0) + dL.dn * lcf(-1);
+        if (wide) v += dR2.dw * lcf(1) + dL2.dw * lcf(-2);
+        ln[(a * 8 + tpart * 4 + c) * pl] = v;
       }
     if (STAGE == 2)
       for (int c = 0; c < 4; ++c) ln[(a * 8 + c) * pl] = 0.0;
@@ -325,9 +344,9 @@ __global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S, const double* __restrict__ lamN,
                                                    double* __restrict__ lamS, Geo g, Consts k) {
-  const int grid = blockIdx.z;
-  const int i = blockIdx.x * 64 + threadIdx.x - 1, j = blockIdx.y * 4 + threadIdx.y - 1;
-  if (i > g.nx || j > g.ny) return;
+  const int grid = blockIdx.z, w = node_reach(k);
+  const int i = blockIdx.x * 64 + threadIdx.x - w, j = blockIdx.y * 4 + threadIdx.y - w;
+  if (i > g.nx - 1 + w || j > g.ny - 1 + w) return;
   const long pl = g.plane, o = at(g, j, i);
   const double* B = S + (long)grid * 12 * pl;
   const double* ln = lamN + (long)grid * 16 * pl + o;

@@ -2280,12 +2280,12 @@ fdcgks_status adj_stage(fdcgks_problem* pb, double dt, const double* Sin, const 
                      lam_out, lam_acc, pb->Op, direct, g, pb->k, dt);
   hipLaunchKernelGGL((k_adj_assemble<STAGE>), dim3(ceil_div(g.nx + 3, 64), ceil_div(g.ny + 3, 4), 4), blk, 0,
                      pb->stream, pb->Op, E, Nb, pb->LE, g, pb->k);
-  hipLaunchKernelGGL((k_adj_nodeflux<STAGE>), dim3(ceil_div(g.nx + 2, 64), ceil_div(g.ny + 2, 4), 2), blk, 0,
-                     pb->stream, pb->Op, E, pb->LN, g, pb->k);
+  const int w = node_reach(pb->k);  // nodes whose fluxes the forward sweep computes beyond the grid's own
+  const dim3 gn(ceil_div(g.nx + 2 * w, 64), ceil_div(g.ny + 2 * w, 4), 2);
+  hipLaunchKernelGGL((k_adj_nodeflux<STAGE>), gn, blk, 0, pb->stream, pb->Op, E, pb->LN, g, pb->k);
   hipLaunchKernelGGL((k_adj_edges<STAGE>), dim3(ceil_div(g.nx + 3, 64), ceil_div(g.ny + 3, 2), 2), blk, 0,
                      pb->stream, Sin, pb->LE, scatter, g, pb->k, dt);
-  hipLaunchKernelGGL((k_adj_nodes<STAGE>), dim3(ceil_div(g.nx + 2, 64), ceil_div(g.ny + 2, 4), 2), blk, 0,
-                     pb->stream, Sin, pb->LN, scatter, g, pb->k);
+  hipLaunchKernelGGL((k_adj_nodes<STAGE>), gn, blk, 0, pb->stream, Sin, pb->LN, scatter, g, pb->k);
   adj_fold(pb, scatter);
   return launch_check(pb, "adjoint stage");
 }
@@ -2792,7 +2792,6 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   if (pb->prm.recon_vars != FDCGKS_RECON_CONSERVATIVE)
     return fail(pb, FDCGKS_EINVAL, "the step adjoint needs conservative reconstruction");
   if (pb->g.sx | pb->g.sy) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs periodic sides");
-  if (pb->prm.flux_order != 6) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs the order-6 flux");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, FDCGKS_EINVAL, "dt must be finite and > 0");
   if (!state_ready(pb)) return fail(pb, FDCGKS_ESTATE, "set_state has not been called for every grid");
   fdcgks_status st = adj_alloc(pb);

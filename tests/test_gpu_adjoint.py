@@ -45,6 +45,19 @@ def _case(name):
                                      WL.random_smooth2d(12, 12, seed=14)),
         "smooth_12_carried": lambda: (settings(dim=2, nx=12, ny=12, lx=1.0, grad_carried=1),
                                       WL.random_smooth2d(12, 12, seed=15)),
+        # the order-8 compact flux (nodal fluxes two nodes out)
+        "tiny_8_order8": lambda: (settings(dim=2, nx=8, ny=8, lx=1.0, flux_order=8),
+                                  WL.random_smooth2d(8, 8, seed=16)),
+        "smooth_67x10_order8": lambda: (settings(dim=2, nx=67, ny=10, lx=1.0, flux_order=8),
+                                        WL.random_smooth2d(67, 10, seed=17)),
+        "rough_66x9_order8": lambda: (settings(dim=2, nx=66, ny=9, lx=1.0, flux_order=8),
+                                      WL.random_rough2d(66, 9, seed=18)),
+        "smooth_ns_20_order8": lambda: (settings(dim=2, nx=20, ny=20, lx=1.0, mu=1e-3, prandtl=0.72, flux_order=8),
+                                        WL.random_smooth2d(20, 20, seed=19)),
+        "smooth_12_62_order8": lambda: (settings(dim=2, nx=12, ny=12, lx=1.0, variant="6-2", flux_order=8),
+                                        WL.random_smooth2d(12, 12, seed=20)),
+        "smooth_12_linear_order8": lambda: (settings(dim=2, nx=12, ny=12, lx=1.0, variant="linear", flux_order=8),
+                                            WL.random_smooth2d(12, 12, seed=21)),
     }[name]
     s, pr = c()
     if pr.ny != s["ny"]:
@@ -106,14 +119,15 @@ def _check_columns(oracle, par, dt, S, lam, g, ks):
     return worst, wbar
 
 
-def test_vjp_all_columns_tiny(oracle):
-    s, pr = _case("tiny_8")
+@pytest.mark.parametrize("name", ["tiny_8", "tiny_8_order8"])
+def test_vjp_all_columns_tiny(oracle, name):
+    s, pr = _case(name)
     S, lam = _inputs(pr, 0)
     dt = 0.2 * pr.h / 3.0
     par = oracle_par(oracle, s)
     g = _problem(s, S).step_vjp(dt, lam)
     worst, bar = _check_columns(oracle, par, dt, S, lam, g, range(S.size))
-    print(f"tiny_8: all {S.size} adjoint elements, worst scaled error {worst:.2e} (largest bar {bar:.1e})")
+    print(f"{name}: all {S.size} adjoint elements, worst scaled error {worst:.2e} (largest bar {bar:.1e})")
 
 
 def _sample(S, rng, n=40):
@@ -129,7 +143,9 @@ def _sample(S, rng, n=40):
 
 
 @pytest.mark.parametrize("name", ["smooth_67x10", "rough_66x9", "smooth_ns_20", "shear_ns_20_smoothmap",
-                                  "riemann_33x20", "smooth_12_62", "smooth_12_linear", "smooth_12_carried"])
+                                  "riemann_33x20", "smooth_12_62", "smooth_12_linear", "smooth_12_carried",
+                                  "smooth_67x10_order8", "rough_66x9_order8", "smooth_ns_20_order8",
+                                  "smooth_12_62_order8", "smooth_12_linear_order8"])
 def test_vjp_sampled_columns(oracle, name):
     s, pr = _case(name)
     S, lam = _inputs(pr, 1)
@@ -219,6 +235,16 @@ def test_vjp_conservation_shear_layer():
     s, pr = _case("smooth_ns_20")
     S = np.stack([pr.P, pr.D])
     _conservation_check(_problem(s, S), S, 0.2 * pr.h / 3.0)
+
+
+def test_vjp_conservation_order8():
+    """The conserved-sum invariant with the order-8 compact flux, whose
+    nodal-flux adjoints reach two nodes out and fold across the periodic
+    seam."""
+    s, pr = _case("smooth_ns_20_order8")
+    S = np.stack([pr.P, pr.D])
+    r = _conservation_check(_problem(s, S), S, 0.2 * pr.h / 3.0)
+    print(f"smooth_ns_20_order8: conserved-sum adjoints, worst deviation / bar = {r:.2e}")
 
 
 @pytest.mark.parametrize("n", [2048])

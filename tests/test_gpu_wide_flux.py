@@ -6,8 +6,8 @@ Stages element by element at the 1e-12 bar on periodic and walled 2D
 problems and on 1D lines; CFL steps against max(1e-12, 4 x the oracle's
 one-ulp sensitivity); the order of accuracy measured through the GPU path
 on the smooth 1D advection test (it must exceed 7, against about 6 with the
-order-6 flux); the graph and fused-node options; the step adjoint, which
-rejects it (batches run it: test_gpu_batch.py)."""
+order-6 flux); the graph and fused-node options.  Batches and the step
+adjoint with this flux: test_gpu_batch.py, test_gpu_adjoint.py."""
 import numpy as np
 import pytest
 
@@ -193,11 +193,3 @@ def test_order_of_accuracy_1d():
     print("L1 errors", errs, "rates", rates)
     assert all(r > 7.0 for r in rates[8]) and all(5.5 < r < 7.0 for r in rates[6])
     assert errs[8][2] < 0.2 * errs[6][2]
-
-
-def test_order8_rejected_by_adjoint():
-    from paper_2606_17772_amd import FdcgksError
-    s, P, D = CASES["rough_67x9"]()
-    pb = _problem(s, P, D)
-    with pytest.raises(FdcgksError, match="order-6 flux"):
-        pb.step_vjp(0.001, np.zeros((2, 12) + P.shape[1:]))
