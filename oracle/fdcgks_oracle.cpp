@@ -1619,15 +1619,18 @@ void orc_stage2d_sample(const Par* p, int stage, double dt, const double* P, con
 // Tangent (forward-mode) of one full step at fixed dt: given state and a
 // direction (dP, dD), returns the stepped state and its directional
 // derivative.  Ties in min/max and |0| follow the adjoint's convention.
-// Periodic problems only.
+// Any sides: along a bounded axis the dual state has one more node (as in
+// orc_step2d).
 void orc_step2d_tangent(const Par* p, double dt, const double* P, const double* D, const double* dP,
                         const double* dD, double* outP, double* outD, double* outdP, double* outdD) {
-  long n12 = 12L * p->nx * p->ny;
-  std::vector<Dual> xP(n12), xD(n12), sP(n12), sD(n12), aP(n12), aD(n12), yP(n12), yD(n12);
-  for (long k = 0; k < n12; ++k) { xP[k] = Dual(P[k], dP[k]); xD[k] = Dual(D[k], dD[k]); }
+  const long n12 = 12L * p->nx * p->ny, d12 = 12L * (p->nx + bounded(*p, 0)) * (p->ny + bounded(*p, 1));
+  std::vector<Dual> xP(n12), sP(n12), aP(n12), yP(n12), xD(d12), sD(d12), aD(d12), yD(d12);
+  for (long k = 0; k < n12; ++k) xP[k] = Dual(P[k], dP[k]);
+  for (long k = 0; k < d12; ++k) xD[k] = Dual(D[k], dD[k]);
   stage2d<Dual>(*p, 1, dt, xP.data(), xD.data(), nullptr, nullptr, sP.data(), sD.data(), aP.data(), aD.data());
   stage2d<Dual>(*p, 2, dt, sP.data(), sD.data(), aP.data(), aD.data(), yP.data(), yD.data(), nullptr, nullptr);
-  for (long k = 0; k < n12; ++k) { outP[k] = yP[k].v; outD[k] = yD[k].v; outdP[k] = yP[k].d; outdD[k] = yD[k].d; }
+  for (long k = 0; k < n12; ++k) { outP[k] = yP[k].v; outdP[k] = yP[k].d; }
+  for (long k = 0; k < d12; ++k) { outD[k] = yD[k].v; outdD[k] = yD[k].d; }
 }
 
 // --- 3D --------------------------------------------------------------------

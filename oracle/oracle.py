@@ -296,10 +296,14 @@ def stage2d_sample(par, stage, dt, P, D, grid, jj, ii, accP=None, accD=None):
 
 
 def step2d_tangent(par, dt, P, D, dP, dD):
-    if any(par.side[k] != 0 for k in range(4)):
-        raise ValueError("the tangent step is implemented for periodic problems")
+    """One step and its derivative along (dP, dD) (forward mode, dual
+    numbers through both stages).  D and dD have the dual grid's size, one
+    node more along a bounded axis."""
     P, D, dP, dD = _arr(P), _arr(D), _arr(dP), _arr(dD)
-    oP, oD, odP, odD = (np.zeros_like(P) for _ in range(4))
+    if dP.shape != P.shape or dD.shape != D.shape:
+        raise ValueError("the direction must have the state's shape")
+    oP, odP = np.zeros_like(P), np.zeros_like(P)
+    oD, odD = np.zeros_like(D), np.zeros_like(D)
     lib().orc_step2d_tangent(C.byref(par), dt, _p(P), _p(D), _p(dP), _p(dD), _p(oP), _p(oD), _p(odP), _p(odD))
     return oP, oD, odP, odD
 

@@ -69,3 +69,51 @@ def test_tangent_default_scheme_small_eps(oracle):
     assert _fd_check(oracle, par, pr, dt, 5, 1e-8) < 1e-6
     par, pr, dt = _setup(oracle, variant="6-2", grad_carried=1, seed=23)
     assert _fd_check(oracle, par, pr, dt, 3, 1e-8) < 1e-6
+
+
+def _bounded_fd_check(oracle, par, P, D, dt, seed, eps):
+    """As _fd_check for a problem with bounded axes (the dual state is larger)."""
+    rng = np.random.default_rng(seed)
+    vP = rng.standard_normal(P.shape) * np.abs(P).max(axis=(1, 2), keepdims=True)
+    vD = rng.standard_normal(D.shape) * np.abs(D).max(axis=(1, 2), keepdims=True)
+    _, _, dP, dD = oracle.step2d_tangent(par, dt, P, D, vP, vD)
+
+    def f(X, Y):
+        return oracle.step2d(par, X, Y, 1, dt=dt)[:2]
+    a, b = f(P + eps * vP, D + eps * vD), f(P - eps * vP, D - eps * vD)
+    worst = 0.0
+    for g, Jv in ((0, dP), (1, dD)):
+        fd = (a[g] - b[g]) / (2 * eps)
+        num = np.abs(fd - Jv).max(axis=(1, 2))
+        den = np.abs(Jv).max(axis=(1, 2))
+        worst = max(worst, float((num / np.maximum(den, 1e-300)).max()))
+    return worst
+
+
+def test_tangent_bounded_sides(oracle):
+    """Walls and zero-gradient sides (ghost values mirrored, copied or zeroed;
+    wall conditions on the dual boundary nodes): on the analytic
+    linear-flux map central differences converge to the tangent as eps^2,
+    and the value part is the plain step."""
+    cases = [
+        (["reflecting", "reflecting", "no_slip", "no_slip"], 14, 9),
+        (["zero_gradient", "zero_gradient", "reflecting", "zero_gradient"], 11, 12),
+        (["periodic", "periodic", "no_slip", "reflecting"], 12, 10),
+    ]
+    for sides, nx, ny in cases:
+        bx, by = int(sides[0] != "periodic"), int(sides[2] != "periodic")
+        h = 1.0 / nx
+        P, D = WL.sample_bounded(WL.mirror_flow(1.0, ny * h, bx, by), nx, ny, h, bx, by)
+        s = settings(dim=2, nx=nx, ny=ny, lx=1.0, sides=sides, variant="linear", tau_c1=0.05, tau_c2=0.0,
+                     mu=1e-3, prandtl=0.72)
+        par = oracle_par(oracle, s)
+        dt = 0.2 * h / 3.0
+        assert D.shape == (12, ny + by, nx + bx)
+        v = np.zeros_like(P), np.zeros_like(D)
+        oP, oD, dP, dD = oracle.step2d_tangent(par, dt, P, D, *v)
+        sP, sD, _, k = oracle.step2d(par, P, D, 1, dt=dt)
+        assert k == 1 and np.array_equal(oP, sP) and np.array_equal(oD, sD)
+        assert not dP.any() and not dD.any()
+        e5 = _bounded_fd_check(oracle, par, P, D, dt, 7, 1e-5)
+        e4 = _bounded_fd_check(oracle, par, P, D, dt, 7, 1e-4)
+        assert e5 < 1e-8 and e4 / e5 > 30.0, (sides, e4, e5)
