@@ -319,9 +319,12 @@ fdcgks_status fdcgks_autotune(fdcgks_problem* pb, int32_t reps);
  * step map at the current state.  The state is not advanced (the step is
  * recomputed internally; the next-state buffer is used as scratch).
  * Non-smooth points take fixed one-sided derivatives: |x| has derivative 0
- * at 0 and min/max ties select the first argument.  2D periodic problems with
- * FP64 fluxes and conservative reconstruction only (EINVAL otherwise);
- * ENONPHYS if the recomputed step is non-physical.
+ * at 0 and min/max ties select the first argument.  2D problems (any sides:
+ * the halo fill's ghost rules and the wall condition are differentiated like
+ * the rest) with FP64 fluxes and conservative reconstruction only (EINVAL
+ * otherwise); ENONPHYS if the recomputed step is non-physical.  With bounded
+ * axes grid 1's planes have the dual grid's size (as fdcgks_get_state):
+ * lam_out and lam_in hold grid 0's 12 planes, then grid 1's.
  * on_device: both arrays are device pointers (1) or host pointers (0).
  * The first call allocates an adjoint workspace of about 410 planes of
  * (nx + 16) x (ny + 6) doubles, kept until fdcgks_destroy.  Calls on one

@@ -254,8 +254,12 @@ class Problem:
     def step_vjp(self, dt, lam_out):
         """J^T lam_out for one step of size dt from the current state (the
         state is not advanced).  lam_out: (2, 12, ny, nx) numpy array or
-        torch tensor; the result has the same type and device."""
+        torch tensor; the result has the same type and device.  With bounded
+        axes the grids differ in size: lam_out is a pair of (12, ny_g, nx_g)
+        arrays (grid_shape), and so is the result."""
         p = self.params
+        if any(self.bounded):
+            return self._step_vjp_bounded(dt, lam_out)
         shape = (self.ngrid, (3 if p.dim == 2 else 2) * self.ncomp, p.ny, p.nx)
         if tuple(lam_out.shape) != shape:
             raise ValueError(f"lam_out must have shape {shape}")
@@ -269,6 +273,25 @@ class Problem:
         pi, dev2, _ = _ptr(lam_in, True)
         self._chk(self._L.fdcgks_step_vjp(self._h, dt, po, pi, dev))
         return lam_in
+
+    def _step_vjp_bounded(self, dt, lam_out):
+        shapes = [(3 * self.ncomp,) + self.grid_dims(g) for g in range(self.ngrid)]
+        if len(lam_out) != self.ngrid or any(tuple(a.shape) != sh for a, sh in zip(lam_out, shapes)):
+            raise ValueError(f"lam_out must be a pair of arrays of shapes {shapes}")
+        sizes = [int(np.prod(sh)) for sh in shapes]
+        if isinstance(lam_out[0], np.ndarray):
+            flat = np.ascontiguousarray(np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in lam_out]))
+            out = np.empty_like(flat)
+            parts = np.split(out, [sizes[0]])
+        else:
+            torch = _torch()
+            flat = torch.cat([a.reshape(-1) for a in lam_out]).contiguous()
+            out = torch.empty_like(flat)
+            parts = torch.split(out, sizes)
+        po, dev, _ = _ptr(flat)
+        pi, dev2, _ = _ptr(out, True)
+        self._chk(self._L.fdcgks_step_vjp(self._h, dt, po, pi, dev))
+        return [q.reshape(sh) for q, sh in zip(parts, shapes)]
 
     def diagnostics(self):
         """Conservation sums per grid ((ngrid, ncomp) array), smallest rho and

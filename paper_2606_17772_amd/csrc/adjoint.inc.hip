@@ -35,14 +35,20 @@ __global__ __launch_bounds__(256) void k_adj_update(const double* __restrict__ l
                                                     const double* __restrict__ lam_acc, double* __restrict__ lam_op,
                                                     double* __restrict__ lam_direct, Geo g, Consts k, double dt) {
   const int grid = blockIdx.z;
-  const int i = blockIdx.x * 64 + threadIdx.x, j = blockIdx.y * 4 + threadIdx.y;
+  // the nodes the forward update writes: the dual grid starts at -sx, -sy
+  const int i = blockIdx.x * 64 + threadIdx.x - (grid ? g.sx : 0);
+  const int j = blockIdx.y * 4 + threadIdx.y - (grid ? g.sy : 0);
   if (i >= g.nx || j >= g.ny) return;
-  const long pl = g.plane, o = at(g, j, i);
-  const double* lo = lam_out + (long)grid * 12 * pl + o;
+  const long pl = g.plane, o = at(g, j, i), so = o + (grid ? g.dshift : 0);  // state planes: shifted dual
+  const double* lo = lam_out + (long)grid * 12 * pl + so;
   double* op = lam_op + (long)grid * OPN * pl + o;
-  double* dir = lam_direct + (long)grid * 12 * pl + o;
+  double* dir = lam_direct + (long)grid * 12 * pl + so;
+  // outputs the wall condition sets to zero depend on nothing
+  const int zero = wall_mask(g, grid, i, j);
   for (int c = 0; c < 4; ++c) {
-    const double lW = lo[c * pl], lX = lo[(4 + c) * pl], lY = lo[(8 + c) * pl];
+    const double lW = zero & (1 << c) ? 0.0 : lo[c * pl];
+    const double lX = zero & (1 << (4 + c)) ? 0.0 : lo[(4 + c) * pl];
+    const double lY = zero & (1 << (8 + c)) ? 0.0 : lo[(8 + c) * pl];
     if (STAGE == 2) {
       dir[c * pl] = lW;  // acc_W
       dir[(4 + c) * pl] = lX;
@@ -54,7 +60,7 @@ __global__ __launch_bounds__(256) void k_adj_update(const double* __restrict__ l
       op[(16 + c) * pl] = dt * lX;
       op[(20 + c) * pl] = dt * lY;
     } else {
-      const double* la = lam_acc + (long)grid * 12 * pl + o;
+      const double* la = lam_acc + (long)grid * 12 * pl + so;
       const double aW = la[c * pl], aX = la[(4 + c) * pl], aY = la[(8 + c) * pl];
       dir[c * pl] = lW + aW;
       op[c * pl] = 0.5 * dt * lW + dt * aW;
@@ -115,8 +121,8 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const double* __restrict__
                                                       const double* __restrict__ Nb, double* __restrict__ lamE, Geo g,
                                                       Consts k) {
   const int fam = blockIdx.z >> 1, G = blockIdx.z & 1;
-  const int i = blockIdx.x * 64 + threadIdx.x + (fam == 0 ? -2 : -1);
-  const int j = blockIdx.y * 4 + threadIdx.y + (fam == 0 ? -1 : -2);
+  const int i = blockIdx.x * 64 + threadIdx.x + (fam == 0 ? -2 : -1 - g.sx);
+  const int j = blockIdx.y * 4 + threadIdx.y + (fam == 0 ? -1 - g.sy : -2);
   if (i > (fam == 0 ? g.nx : g.nx + 1) || j > (fam == 0 ? g.ny + 1 : g.ny)) return;
   const bool ay = (fam ^ G) != 0;
   const long pl = g.plane, st = ay ? g.pitch : 1, o = at(g, j, i);
@@ -173,7 +179,8 @@ __global__ __launch_bounds__(256) void k_adj_nodeflux(const double* __restrict__
                                                       double* __restrict__ lamN, Geo g, Consts k) {
   const int G = blockIdx.z, w = node_reach(k);
   const bool wide = w == 2;
-  const int i = blockIdx.x * 64 + threadIdx.x - w, j = blockIdx.y * 4 + threadIdx.y - w;
+  const int sx = G ? g.sx : 0, sy = G ? g.sy : 0;  // the dual grid starts at -sx, -sy
+  const int i = blockIdx.x * 64 + threadIdx.x - w - sx, j = blockIdx.y * 4 + threadIdx.y - w - sy;
   if (i > g.nx - 1 + w || j > g.ny - 1 + w) return;
   const long pl = g.plane, o = at(g, j, i);
   const double* op = lam_op + (long)G * OPN * pl + o;
@@ -181,12 +188,13 @@ __global__ __launch_bounds__(256) void k_adj_nodeflux(const double* __restrict__
   for (int a = 0; a < 2; ++a) {
     const int fam = (G == 0) ? a : 1 - a;
     const long st = a == 0 ? 1 : g.pitch;
-    const int idx = a == 0 ? i : j, nn = a == 0 ? g.nx : g.ny;  // node index along the axis, nodes per line
+    // node index along the axis; the grid's updated nodes along it are [lo, nn - 1]
+    const int idx = a == 0 ? i : j, nn = a == 0 ? g.nx : g.ny, lo = a == 0 ? -sx : -sy;
     const double* e = E + ((long)fam * 50 + G * 25) * pl + o;
     const long eR = (long)G * st, eL = eR - st;
-    // interface between nodes idx + m and idx + m + 1 (m = -2..1): at e offset eR + m st; it has an interior
-    // node when idx + m + 1 >= 0 and idx + m <= nn - 1
-    auto has = [&](int m) { return idx + m + 1 >= 0 && idx + m <= nn - 1; };
+    // interface between nodes idx + m and idx + m + 1 (m = -2..1): at e offset eR + m st; it has an updated
+    // node when idx + m + 1 >= lo and idx + m <= nn - 1
+    auto has = [&](int m) { return idx + m + 1 >= lo && idx + m <= nn - 1; };
     const CFd dR = has(0) ? cf_partials(k.variant, e[8 * pl + eR], wide) : CFd{0, 0, 0, 0, 0};
     const CFd dL = has(-1) ? cf_partials(k.variant, e[8 * pl + eL], wide) : CFd{0, 0, 0, 0, 0};
     const CFd dR2 = wide && has(1) ? cf_partials(k.variant, e[8 * pl + eR + st], wide) : CFd{0, 0, 0, 0, 0};
@@ -215,7 +223,7 @@ __device__ __forceinline__ void line_adjoint(const double* __restrict__ S, doubl
   const bool ALONG_Y = (fam ^ G) != 0;
   const int back = G == 0 ? 1 : 2;
   const long st = ALONG_Y ? g.pitch : 1;
-  const long o = ALONG_Y ? at(g, j - back, i) : at(g, j, i - back);
+  const long o = (ALONG_Y ? at(g, j - back, i) : at(g, j, i - back)) + (G ? g.dshift : 0);  // shifted dual planes
   const int f = ALONG_Y ? 2 : 1;
   const long pl = g.plane;
   for (int c = 0; c < 4; ++c) {
@@ -252,8 +260,8 @@ __global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__
   __shared__ fdk::AccB s_ab[256];
   const int fam = blockIdx.z;
   const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1, tid = ty * 64 + tx;
-  const int i = blockIdx.x * 64 + tx + (fam == 0 ? -2 : -1);
-  const int j = blockIdx.y * 2 + (ty >> 1) + (fam == 0 ? -1 : -2);
+  const int i = blockIdx.x * 64 + tx + (fam == 0 ? -2 : -1 - g.sx);
+  const int j = blockIdx.y * 2 + (ty >> 1) + (fam == 0 ? -1 - g.sy : -2);
   const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
   const bool swap = fam != G;
   fdk::SolveIO& in = s_in[tid];
@@ -345,10 +353,12 @@ template <int STAGE>
 __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S, const double* __restrict__ lamN,
                                                    double* __restrict__ lamS, Geo g, Consts k) {
   const int grid = blockIdx.z, w = node_reach(k);
-  const int i = blockIdx.x * 64 + threadIdx.x - w, j = blockIdx.y * 4 + threadIdx.y - w;
+  const int i = blockIdx.x * 64 + threadIdx.x - w - (grid ? g.sx : 0);
+  const int j = blockIdx.y * 4 + threadIdx.y - w - (grid ? g.sy : 0);
   if (i > g.nx - 1 + w || j > g.ny - 1 + w) return;
   const long pl = g.plane, o = at(g, j, i);
-  const double* B = S + (long)grid * 12 * pl;
+  const long ds = grid ? g.dshift : 0;  // state planes: shifted dual
+  const double* B = S + (long)grid * 12 * pl + ds;
   const double* ln = lamN + (long)grid * 16 * pl + o;
   double W[4], Wx[4], Wy[4];
   for (int c = 0; c < 4; ++c) {
@@ -371,7 +381,7 @@ __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S,
   if (STAGE == 2)
     for (int c = 0; c < 4; ++c) { lF[c] = 0.0; lG[c] = 0.0; }
   fdk::gks_node_b(k, W, Wx, Wy, lF, lFt, lG, lGt, Wb, Wxb, Wyb);
-  double* lS = lamS + (long)grid * 12 * pl + o;
+  double* lS = lamS + (long)grid * 12 * pl + ds + o;
   for (int c = 0; c < 4; ++c) {
     if (Wb[c] != 0.0) atomicAdd(lS + c * pl, Wb[c]);
     // derivative reconstructions along x and y
@@ -392,34 +402,46 @@ __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S,
   }
 }
 
-// Fold the periodic halo of the adjoint planes back onto their images:
-// columns first (all rows, halo rows included), then rows.
+// Transpose of the halo fill (k_halo_rows, then k_halo_cols): a ghost value
+// fac * P[src] hands its adjoint to its source, columns first (their ghost
+// rows included), then rows.  Stored node coordinates, as the state planes.
 __global__ void k_adj_fold_cols(double* __restrict__ L, int nplanes, Geo g) {
-  const int rows = g.ny + 2 * HALO;
+  const int rows = g.ny + g.sy + 2 * HALO;
   const long n = (long)nplanes * rows * 2 * HALO;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
     const int hc = (int)(t % (2 * HALO));
     const long r = t / (2 * HALO);
     const int j = (int)(r % rows) - HALO;
     const int p = (int)(r / rows);
-    const int i = hc < HALO ? hc - HALO : g.nx + (hc - HALO);
+    const PlaneInfo q = plane_info(g, p);
+    if (j >= q.my + HALO) continue;
+    const int i = hc < HALO ? hc - HALO : q.mx + (hc - HALO);
+    double fac;
+    const int is = ghost_src(i, q.mx, g.side[0], g.side[1], q.dual && g.sx, q.field == 1, q.comp == 1,
+                             q.comp == 1 || q.comp == 2, fac);
     double* P = L + p * g.plane;
-    const double v = P[at(g, j, i)];
-    if (v != 0.0) atomicAdd(&P[at(g, j, imod(i, g.nx))], v);
+    const double v = fac * P[at(g, j, i)];
+    if (v != 0.0) atomicAdd(&P[at(g, j, is)], v);
     P[at(g, j, i)] = 0.0;
   }
 }
 __global__ void k_adj_fold_rows(double* __restrict__ L, int nplanes, Geo g) {
-  const long n = (long)nplanes * 2 * HALO * g.nx;
+  const int W = g.nx + g.sx;
+  const long n = (long)nplanes * 2 * HALO * W;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    const int i = (int)(t % g.nx);
-    const long r = t / g.nx;
+    const int i = (int)(t % W);
+    const long r = t / W;
     const int hr = (int)(r % (2 * HALO));
     const int p = (int)(r / (2 * HALO));
-    const int j = hr < HALO ? hr - HALO : g.ny + (hr - HALO);
+    const PlaneInfo q = plane_info(g, p);
+    if (i >= q.mx) continue;
+    const int j = hr < HALO ? hr - HALO : q.my + (hr - HALO);
+    double fac;
+    const int js = ghost_src(j, q.my, g.side[2], g.side[3], q.dual && g.sy, q.field == 2, q.comp == 2,
+                             q.comp == 1 || q.comp == 2, fac);
     double* P = L + p * g.plane;
-    const double v = P[at(g, j, i)];
-    if (v != 0.0) atomicAdd(&P[at(g, imod(j, g.ny), i)], v);
+    const double v = fac * P[at(g, j, i)];
+    if (v != 0.0) atomicAdd(&P[at(g, js, i)], v);
     P[at(g, j, i)] = 0.0;
   }
 }

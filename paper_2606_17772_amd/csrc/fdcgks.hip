@@ -460,21 +460,11 @@ __global__ __launch_bounds__(256) void k_nodes2d(const double* __restrict__ S, d
 #ifndef FDCGKS_UPDATE_UNROLL
 #define FDCGKS_UPDATE_UNROLL 1
 #endif
-template <int STAGE, class NF, bool WIDE = false>
-__device__ __forceinline__ void update_node(const double* __restrict__ S, const double* __restrict__ E,
-                                            const NF& nf, const double* __restrict__ Ain, double* __restrict__ Out,
-                                            double* __restrict__ Aout, const Geo& g, const Consts& k, double dt,
-                                            int i, int j, int grid, Scal* sc, int member, bool want_cfl,
-                                            double& cfl_s, double& cfl_r) {
-  const long pl = g.plane, o = at(g, j, i);
-  const int r = grid;
-  const long so = o + (grid ? g.dshift : 0);  // the dual planes are shifted along bounded axes
-  const double* s = S + (long)grid * 12 * pl + so;
-  double* out = Out + (long)grid * 12 * pl + so;
-  // the wall condition of dual nodes on a reflecting / no-slip side: the
-  // normal momentum (no-slip: both momenta) and its derivative along the wall
-  // are zero; bit c of `zero` clears component c, bit 4 + c its x-derivative,
-  // bit 8 + c its y-derivative
+// The wall condition of dual node (i, j) on a reflecting / no-slip side: the
+// normal momentum (no-slip: both momenta) and its derivative along the wall
+// are zero after every stage.  Bit c clears component c, bit 4 + c its
+// x-derivative, bit 8 + c its y-derivative; 0 off the walls.
+__device__ __forceinline__ int wall_mask(const Geo& g, int grid, int i, int j) {
   int zero = 0;
   if (grid == 1 && (g.sx | g.sy)) {
 #pragma unroll
@@ -490,6 +480,21 @@ __device__ __forceinline__ void update_node(const double* __restrict__ S, const 
         if (type == FDCGKS_BC_NO_SLIP || c == 1 + a) zero |= (1 << c) | (1 << (4 * along + c));
     }
   }
+  return zero;
+}
+
+template <int STAGE, class NF, bool WIDE = false>
+__device__ __forceinline__ void update_node(const double* __restrict__ S, const double* __restrict__ E,
+                                            const NF& nf, const double* __restrict__ Ain, double* __restrict__ Out,
+                                            double* __restrict__ Aout, const Geo& g, const Consts& k, double dt,
+                                            int i, int j, int grid, Scal* sc, int member, bool want_cfl,
+                                            double& cfl_s, double& cfl_r) {
+  const long pl = g.plane, o = at(g, j, i);
+  const int r = grid;
+  const long so = o + (grid ? g.dshift : 0);  // the dual planes are shifted along bounded axes
+  const double* s = S + (long)grid * 12 * pl + so;
+  double* out = Out + (long)grid * 12 * pl + so;
+  const int zero = wall_mask(g, grid, i, j);
   double rho = 0.0, mom2 = 0.0, ener = 0.0, mU = 0.0, mV = 0.0;  // the new values
 #pragma unroll FDCGKS_UPDATE_UNROLL
   for (int c = 0; c < 4; ++c) {
@@ -2258,7 +2263,7 @@ fdcgks_status adj_alloc(fdcgks_problem* pb) {
 
 void adj_fold(fdcgks_problem* pb, double* L) {
   const Geo& g = pb->g;
-  long nc = 24L * (g.ny + 2 * HALO) * 2 * HALO, nr = 24L * 2 * HALO * g.nx;
+  long nc = 24L * (g.ny + g.sy + 2 * HALO) * 2 * HALO, nr = 24L * 2 * HALO * (g.nx + g.sx);
   hipLaunchKernelGGL(k_adj_fold_cols, dim3(std::min(ceil_div(nc, 256), 4096)), dim3(256), 0, pb->stream, L, 24, g);
   hipLaunchKernelGGL(k_adj_fold_rows, dim3(std::min(ceil_div(nr, 256), 4096)), dim3(256), 0, pb->stream, L, 24, g);
 }
@@ -2276,15 +2281,16 @@ fdcgks_status adj_stage(fdcgks_problem* pb, double dt, const double* Sin, const 
   const dim3 blk(64, 4);
   if (STAGE == 2) HIPCHK(pb, hipMemsetAsync(scatter, 0, 24 * g.plane * sizeof(double), pb->stream));
   else HIPCHK(pb, hipMemsetAsync(direct, 0, 24 * g.plane * sizeof(double), pb->stream));
-  hipLaunchKernelGGL((k_adj_update<STAGE>), dim3(ceil_div(g.nx, 64), ceil_div(g.ny, 4), 2), blk, 0, pb->stream,
-                     lam_out, lam_acc, pb->Op, direct, g, pb->k, dt);
-  hipLaunchKernelGGL((k_adj_assemble<STAGE>), dim3(ceil_div(g.nx + 3, 64), ceil_div(g.ny + 3, 4), 4), blk, 0,
-                     pb->stream, pb->Op, E, Nb, pb->LE, g, pb->k);
+  // the ranges of the forward launches (bounded axes add the dual grid's boundary nodes)
+  hipLaunchKernelGGL((k_adj_update<STAGE>), dim3(ceil_div(g.nx + g.sx, 64), ceil_div(g.ny + g.sy, 4), 2), blk, 0,
+                     pb->stream, lam_out, lam_acc, pb->Op, direct, g, pb->k, dt);
+  hipLaunchKernelGGL((k_adj_assemble<STAGE>), dim3(ceil_div(g.nx + 3 + g.sx, 64), ceil_div(g.ny + 3 + g.sy, 4), 4),
+                     blk, 0, pb->stream, pb->Op, E, Nb, pb->LE, g, pb->k);
   const int w = node_reach(pb->k);  // nodes whose fluxes the forward sweep computes beyond the grid's own
-  const dim3 gn(ceil_div(g.nx + 2 * w, 64), ceil_div(g.ny + 2 * w, 4), 2);
+  const dim3 gn(ceil_div(g.nx + 2 * w + g.sx, 64), ceil_div(g.ny + 2 * w + g.sy, 4), 2);
   hipLaunchKernelGGL((k_adj_nodeflux<STAGE>), gn, blk, 0, pb->stream, pb->Op, E, pb->LN, g, pb->k);
-  hipLaunchKernelGGL((k_adj_edges<STAGE>), dim3(ceil_div(g.nx + 3, 64), ceil_div(g.ny + 3, 2), 2), blk, 0,
-                     pb->stream, Sin, pb->LE, scatter, g, pb->k, dt);
+  hipLaunchKernelGGL((k_adj_edges<STAGE>), dim3(ceil_div(g.nx + 3 + g.sx, 64), ceil_div(g.ny + 3 + g.sy, 2), 2), blk,
+                     0, pb->stream, Sin, pb->LE, scatter, g, pb->k, dt);
   hipLaunchKernelGGL((k_adj_nodes<STAGE>), gn, blk, 0, pb->stream, Sin, pb->LN, scatter, g, pb->k);
   adj_fold(pb, scatter);
   return launch_check(pb, "adjoint stage");
@@ -2791,27 +2797,33 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   if (pb->prm.flux_precision != FDCGKS_FP64) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs FP64 fluxes");
   if (pb->prm.recon_vars != FDCGKS_RECON_CONSERVATIVE)
     return fail(pb, FDCGKS_EINVAL, "the step adjoint needs conservative reconstruction");
-  if (pb->g.sx | pb->g.sy) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs periodic sides");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, FDCGKS_EINVAL, "dt must be finite and > 0");
   if (!state_ready(pb)) return fail(pb, FDCGKS_ESTATE, "set_state has not been called for every grid");
   fdcgks_status st = adj_alloc(pb);
   if (st) return st;
   const Geo& g = pb->g;
-  const size_t row = (size_t)g.nx * sizeof(double), pitchb = (size_t)g.pitch * sizeof(double);
-  const long n = (long)g.nx * g.ny;
+  const size_t pitchb = (size_t)g.pitch * sizeof(double);
   const long interior = (long)OY * g.pitch + OX;
+  // dense layout: grid 0's 12 planes, then grid 1's (one more node along a bounded axis)
+  const int mx[2] = {g.nx, g.nx + g.sx}, my[2] = {g.ny, g.ny + g.sy};
+  const long total = 12L * ((long)mx[0] * my[0] + (long)mx[1] * my[1]);
+  auto dense_plane = [&](int p) {  // offset of plane p (grid p / 12) in the dense layout
+    return p < 12 ? (long)p * mx[0] * my[0] : 12L * mx[0] * my[0] + (long)(p - 12) * mx[1] * my[1];
+  };
   // adjoint of the step output into the padded layout (halo stays zero)
   // host input: one contiguous transfer into the interface buffer (written
   // by the forward recompute only after these copies, in stream order), then
   // device-to-device 2D copies into the padded layout
   const double* lsrc = lam_out;
   if (!on_device) {
-    HIPCHK(pb, hipMemcpyAsync(pb->E, lam_out, (size_t)24 * n * sizeof(double), hipMemcpyHostToDevice, pb->stream));
+    HIPCHK(pb, hipMemcpyAsync(pb->E, lam_out, (size_t)total * sizeof(double), hipMemcpyHostToDevice, pb->stream));
     lsrc = pb->E;
   }
-  for (int p = 0; p < 24; ++p)
-    HIPCHK(pb, hipMemcpy2DAsync(pb->Lo + p * g.plane + interior, pitchb, lsrc + p * n, row, row, g.ny,
-                                hipMemcpyDeviceToDevice, pb->stream));
+  for (int p = 0; p < 24; ++p) {
+    const size_t row = (size_t)mx[p / 12] * sizeof(double);
+    HIPCHK(pb, hipMemcpy2DAsync(pb->Lo + p * g.plane + interior, pitchb, lsrc + dense_plane(p), row, row,
+                                my[p / 12], hipMemcpyDeviceToDevice, pb->stream));
+  }
   // forward recompute at the frozen dt: stage-1 results into E1/Nb1, stage-2 into E/Nb
   std::memset(pb->sc_host, 0, sizeof(Scal));
   pb->sc_host->dt = dt;
@@ -2837,11 +2849,13 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   // host output: dense through the interface buffer (free once the reverse
   // sweeps are done), then one contiguous transfer
   double* ldst = on_device ? lam_in : pb->E;
-  for (int p = 0; p < 24; ++p)
-    HIPCHK(pb, hipMemcpy2DAsync(ldst + p * n, row, pb->LS0 + p * g.plane + interior, pitchb, row, g.ny,
-                                hipMemcpyDeviceToDevice, pb->stream));
+  for (int p = 0; p < 24; ++p) {
+    const size_t row = (size_t)mx[p / 12] * sizeof(double);
+    HIPCHK(pb, hipMemcpy2DAsync(ldst + dense_plane(p), row, pb->LS0 + p * g.plane + interior, pitchb, row,
+                                my[p / 12], hipMemcpyDeviceToDevice, pb->stream));
+  }
   if (!on_device) {
-    HIPCHK(pb, hipMemcpyAsync(lam_in, pb->E, (size_t)24 * n * sizeof(double), hipMemcpyDeviceToHost, pb->stream));
+    HIPCHK(pb, hipMemcpyAsync(lam_in, pb->E, (size_t)total * sizeof(double), hipMemcpyDeviceToHost, pb->stream));
     HIPCHK(pb, hipStreamSynchronize(pb->stream));
   }
   return FDCGKS_OK;

@@ -4,8 +4,10 @@ References:
   * the oracle's forward-mode derivative of the same step (dual numbers
     through every operation of the two stages, oracle/fdcgks_oracle.cpp):
     (J^T lam)_k = <lam, J e_k> element by element (all inputs on an 8 x 8
-    grid, sampled inputs on larger ones, boundary nodes included), and the
-    identity <lam, J v> = <J^T lam, v> for random v;
+    grid and on an 8 x 6 walled one, sampled inputs on larger ones, boundary
+    nodes included; periodic, zero-gradient, reflecting and no-slip sides,
+    order-6 and order-8 fluxes), and the identity <lam, J v> = <J^T lam, v>
+    for random v;
   * central differences of the GPU step itself (smooth data);
   * chained oracle tangents for a multi-step objective through autograd.
 Bar: |gpu_k - oracle_k| <= max(1e-11 * sum_i |lam_i (J e_k)_i|, 4 x the
@@ -340,3 +342,148 @@ def test_rollout_central_differences_smooth_map():
     fd = (Jof(eps) - Jof(-eps)) / (2 * eps)
     print(f"8-step rollout gradient: adjoint {an:.12e}, central differences {fd:.12e}")
     assert abs(an - fd) <= 1e-7 * abs(fd), (an, fd)
+
+
+# ---------------------------------------------------------------- bounded sides
+# With a bounded axis the dual grid has one more node along it, so states and
+# adjoints are handled as the flat concatenation of the two grids' planes.
+
+def _bounded_case(name):
+    def walls(nx, ny, sides, **kw):
+        # a smooth field with the walls' parities, perturbed by seeded noise of relative size 1e-3: the
+        # field's mirror symmetry about the domain's centre lines would otherwise make mirrored GENO
+        # stencils tie their smoothness indicators up to round-off, where the derivative branch (and so
+        # the adjoint) depends on the order of operations
+        bx, by = int(sides[0] != "periodic"), int(sides[2] != "periodic")
+        h = 1.0 / nx
+        P, D = WL.sample_bounded(WL.mirror_flow(1.0, ny * h, bx, by), nx, ny, h, bx, by)
+        rng = np.random.default_rng(nx * 100 + ny)
+        P, D = (A * (1.0 + 1e-3 * rng.uniform(-1.0, 1.0, size=A.shape)) for A in (P, D))
+        return settings(dim=2, nx=nx, ny=ny, lx=1.0, sides=sides, **kw), P, D
+
+    def riemann(n, **kw):
+        pr = WL.riemann2d_bounded(n, seed=6)
+        return settings(dim=2, nx=n, ny=n, lx=1.0, bc="zero_gradient", **kw), pr.P, pr.D
+
+    ns = dict(mu=1e-3, prandtl=0.72)
+    return {
+        "walls_8x6": lambda: walls(8, 6, ["reflecting", "reflecting", "no_slip", "no_slip"], **ns),
+        "walls_15x9": lambda: walls(15, 9, ["reflecting", "no_slip", "no_slip", "reflecting"], **ns),
+        "mixed_14x10": lambda: walls(14, 10, ["periodic", "periodic", "no_slip", "reflecting"], **ns),
+        "zero_gradient_11x12": lambda: walls(11, 12, ["zero_gradient", "zero_gradient", "reflecting",
+                                                      "zero_gradient"]),
+        "zero_gradient_riemann_13": lambda: riemann(13),
+        "walls_order8_12x9": lambda: walls(12, 9, ["reflecting", "reflecting", "no_slip", "reflecting"],
+                                           flux_order=8, **ns),
+    }[name]()
+
+
+def _bounded_problem(s, P, D):
+    from paper_2606_17772_amd import Problem
+    pb = Problem(gpu_params(s))
+    pb.set_state_stacked(0, P)
+    pb.set_state_stacked(1, D)
+    return pb
+
+
+def _bounded_oracle_dot(oracle, par, dt, P, D, lamP, lamD, vP, vD, trials=2):
+    """As _oracle_dot for separate grids."""
+    def dot(A, B):
+        _, _, dP, dD = oracle.step2d_tangent(par, dt, A, B, vP, vD)
+        t = np.concatenate([(lamP * dP).ravel(), (lamD * dD).ravel()])
+        return float(t.sum()), float(np.abs(t).sum())
+    o, scale = dot(P, D)
+    rng = np.random.default_rng(98)
+    eps = np.finfo(np.float64).eps
+    spread = 0.0
+    for _ in range(trials):
+        A = P * (1.0 + eps * rng.choice([-1.0, 1.0], size=P.shape))
+        B = D * (1.0 + eps * rng.choice([-1.0, 1.0], size=D.shape))
+        spread = max(spread, abs(dot(A, B)[0] - o))
+    return o, scale, spread
+
+
+def _bounded_columns(oracle, s, P, D, lamP, lamD, gP, gD, ks, dt):
+    """(J^T lam)_k against <lam, J e_k> for flat indices ks of the
+    concatenated (P, D) state; returns the worst scaled error and bar."""
+    par = oracle_par(oracle, s)
+    g = np.concatenate([gP.ravel(), gD.ravel()])
+    worst = wbar = 0.0
+    for k in ks:
+        e = np.zeros(P.size + D.size)
+        e[k] = 1.0
+        vP, vD = e[:P.size].reshape(P.shape), e[P.size:].reshape(D.shape)
+        o, scale, spread = _bounded_oracle_dot(oracle, par, dt, P, D, lamP, lamD, vP, vD)
+        bar = max(ADJ_TOL, 4.0 * spread / max(scale, 1e-300))
+        err = abs(g[k] - o) / max(scale, 1e-300)
+        worst, wbar = max(worst, err), max(wbar, bar)
+        where = ("P", np.unravel_index(k, P.shape)) if k < P.size else ("D", np.unravel_index(k - P.size, D.shape))
+        assert err <= bar, (where, g[k], o, scale, spread)
+    return worst, wbar
+
+
+def _bounded_sample(P, D, rng, n=48):
+    """Flat indices over both grids and every plane, boundary rows and
+    columns (and the dual grid's boundary nodes) favoured."""
+    ks = []
+    for q in range(n):
+        A, off = (P, 0) if q % 2 == 0 else (D, P.size)
+        F, ny, nx = A.shape
+        f = (q // 2) % F
+        j = [0, ny - 1, rng.integers(ny), 1][q % 4]
+        i = [nx - 1, 0, rng.integers(nx)][q % 3]
+        ks.append(off + np.ravel_multi_index((f, j, i), A.shape))
+    return ks
+
+
+def test_vjp_bounded_all_columns_tiny(oracle):
+    """Every element of J^T lam on an 8 x 6 problem with reflecting and
+    no-slip walls (ghost mirror images, the dual grid's wall nodes and their
+    wall condition)."""
+    s, P, D = _bounded_case("walls_8x6")
+    rng = np.random.default_rng(0)
+    lamP, lamD = rng.standard_normal(P.shape), rng.standard_normal(D.shape)
+    dt = 0.2 * (1.0 / s["nx"]) / 3.0
+    gP, gD = _bounded_problem(s, P, D).step_vjp(dt, [lamP, lamD])
+    worst, bar = _bounded_columns(oracle, s, P, D, lamP, lamD, gP, gD, range(P.size + D.size), dt)
+    print(f"walls_8x6: all {P.size + D.size} adjoint elements, worst scaled error {worst:.2e} (largest bar {bar:.1e})")
+
+
+@pytest.mark.parametrize("name", ["walls_15x9", "mixed_14x10", "zero_gradient_11x12", "zero_gradient_riemann_13",
+                                  "walls_order8_12x9"])
+def test_vjp_bounded_sampled_columns(oracle, name):
+    s, P, D = _bounded_case(name)
+    rng = np.random.default_rng(1)
+    lamP, lamD = rng.standard_normal(P.shape), rng.standard_normal(D.shape)
+    dt = 0.2 * (1.0 / s["nx"]) / 3.0
+    pb = _bounded_problem(s, P, D)
+    gP, gD = pb.step_vjp(dt, [lamP, lamD])
+    worst, bar = _bounded_columns(oracle, s, P, D, lamP, lamD, gP, gD, _bounded_sample(P, D, rng), dt)
+    # the dot-product identity with dense random directions
+    par = oracle_par(oracle, s)
+    for _ in range(2):
+        vP, vD = rng.standard_normal(P.shape), rng.standard_normal(D.shape)
+        o, scale, spread = _bounded_oracle_dot(oracle, par, dt, P, D, lamP, lamD, vP, vD)
+        b = float((gP * vP).sum() + (gD * vD).sum())
+        assert abs(o - b) <= max(ADJ_TOL * scale, 4.0 * spread), (o, b, scale, spread)
+    # the state is not advanced
+    assert np.array_equal(pb.get_state_stacked(0), P) and np.array_equal(pb.get_state_stacked(1), D)
+    print(f"{name}: sampled adjoint elements, worst scaled error {worst:.2e} (largest bar {bar:.1e})")
+
+
+def test_vjp_bounded_device_tensors():
+    """The bounded-side call through device tensors gives the host-array
+    result bit for bit."""
+    import torch
+    s, P, D = _bounded_case("walls_15x9")
+    rng = np.random.default_rng(2)
+    lamP, lamD = rng.standard_normal(P.shape), rng.standard_normal(D.shape)
+    dt = 0.01
+    pb = _bounded_problem(s, P, D)
+    hP, hD = pb.step_vjp(dt, [lamP, lamD])
+    dev = torch.device("cuda:0")
+    tP, tD = pb.step_vjp(dt, [torch.tensor(lamP, device=dev), torch.tensor(lamD, device=dev)])
+    assert tP.is_cuda and tuple(tD.shape) == D.shape
+    # atomic scatters: the last bits may differ between calls
+    assert np.allclose(tP.cpu().numpy(), hP, rtol=1e-13, atol=1e-13 * np.abs(hP).max())
+    assert np.allclose(tD.cpu().numpy(), hD, rtol=1e-13, atol=1e-13 * np.abs(hD).max())

@@ -168,12 +168,17 @@ def test_wall_nodes_hold_the_wall_condition(oracle):
         assert np.all(Dg[1:3, :, col] == 0.0) and np.all(Dg[9:11, :, col] == 0.0)
 
 
-def test_bounded_rejected_by_adjoint():
-    from paper_2606_17772_amd import FdcgksError
+def test_bounded_adjoint_takes_one_array_per_grid():
+    """The step adjoint of a walled problem takes (and returns) the two
+    grids' adjoints separately, the dual one with its boundary nodes; the
+    stacked periodic form is refused before any device work.  Its values:
+    test_gpu_adjoint.py."""
     s, P, D = CASES["reflecting_x_70x37"]()
     pb = _problem(s, P, D)
-    with pytest.raises(FdcgksError, match="periodic sides"):
+    with pytest.raises(ValueError, match="pair of arrays"):
         pb.step_vjp(0.001, np.zeros((2, 12) + P.shape[1:]))
+    gP, gD = pb.step_vjp(0.001, [np.zeros(P.shape), np.zeros(D.shape)])
+    assert gP.shape == P.shape and gD.shape == D.shape and not gP.any() and not gD.any()
 
 
 def test_full_size_sampled_walled(oracle):
