@@ -433,8 +433,8 @@ ADJ_STEPS, ADJ_EVERY, ADJ_CFL = 50, 7, 0.25
 
 def adjoint_batch_gradient(count=64):
     """Gradient workload of the batched configuration: 64 members (sides
-    seeded in [64, 512]; vortex and four-quadrant Riemann data, both
-    periodic here because the step adjoint covers periodic sides), each
+    seeded in [64, 512]; periodic vortices and four-quadrant Riemann
+    problems with zero-gradient sides), each
     advanced 50 steps at a time step frozen from its initial state (CFL 0.25;
     a member whose frozen step goes non-physical is skipped and counted);
     J = 1/2 sum over members and primary nodes of (rho(T) - rho_target)^2 h^2,
@@ -448,34 +448,39 @@ def adjoint_batch_gradient(count=64):
 
     import workloads as WL
     from paper_2606_17772_amd import FdcgksError, Problem, make_params
-    from paper_2606_17772_amd.adjoint import rollout
+    from paper_2606_17772_amd.adjoint import density, get_state_vector, rollout, set_state_vector
     dev = torch.device("cuda:0")
     skipped = []
     sizes = WL.batch_sizes(count, 64, 512, seed=0)
-    gen = lambda b, n, sd: WL.vortex(n, seed=sd) if b % 2 == 0 else WL.riemann2d(n, seed=sd)  # noqa: E731
+    gen = lambda b, n, sd: WL.vortex(n, seed=sd) if b % 2 == 0 else WL.riemann2d_bounded(n, seed=sd)  # noqa: E731
+
+    def state(pb, pr):  # the member's data in the rollout's state form (flat when the grids differ in size)
+        if any(pb.bounded):
+            return torch.from_numpy(np.concatenate([pr.P.ravel(), pr.D.ravel()])).to(dev)
+        return torch.from_numpy(np.stack([pr.P, pr.D])).to(dev)
     t_fwd = t_grad = 0.0
     J_total, gnorm2, members = 0.0, [0.0, 0.0], 0
     checks = []
     for b, n in enumerate(sizes):
         pr, tg = gen(b, n, b), gen(b, n, 5000 + b)
-        pb = Problem(make_params(dim=2, nx=n, ny=n, lx=pr.lx, ly=pr.ly))
-        S0 = torch.from_numpy(np.stack([pr.P, pr.D])).to(dev)
-        pb.set_state_all(S0)
+        pb = Problem(make_params(dim=2, nx=n, ny=n, lx=pr.lx, ly=pr.ly, bc=pr.params.get("bc", "periodic")))
+        S0 = state(pb, pr)
+        set_state_vector(pb, S0)
         dt = pb.compute_dt(ADJ_CFL)
         try:
-            for S in (np.stack([tg.P, tg.D]), np.stack([pr.P, pr.D])):
-                pb.set_state_all(torch.from_numpy(S).to(dev))
+            for S in (state(pb, tg), S0):
+                set_state_vector(pb, S)
                 pb.step(nsteps=ADJ_STEPS, dt=dt)
         except FdcgksError:
             skipped.append(b)
             del pb
             continue
-        pb.set_state_all(torch.from_numpy(np.stack([tg.P, tg.D])).to(dev))
+        set_state_vector(pb, state(pb, tg))
         pb.step(nsteps=ADJ_STEPS, dt=dt)
-        rho_t = pb.get_state_all(device=dev)[0, 0].clone()
+        rho_t = density(pb, get_state_vector(pb, dev)).clone()
         h2 = pr.h * pr.h
         # plain forward
-        pb.set_state_all(S0)
+        set_state_vector(pb, S0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         pb.step(nsteps=ADJ_STEPS, dt=dt)
@@ -486,9 +491,9 @@ def adjoint_batch_gradient(count=64):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         out = rollout(pb, X, dt, ADJ_STEPS, checkpoint_every=ADJ_EVERY)
-        J = 0.5 * ((out[0, 0] - rho_t) ** 2).sum() * h2
+        J = 0.5 * ((density(pb, out) - rho_t) ** 2).sum() * h2
         J.backward()
-        grad = X.grad[0, 0]
+        grad = density(pb, X.grad)
         torch.cuda.synchronize()
         t_grad += time.perf_counter() - t0
         J_total += float(J.detach())
@@ -497,8 +502,9 @@ def adjoint_batch_gradient(count=64):
         if b in (0, 1):  # central differences along 8 random density directions (vortex b = 0, Riemann b = 1)
             checks.append(_fd_directions(pb, S0, dt, rho_t, h2, grad, n, b))
         del pb, X, out, J
-    return {"workload": f"{members} members, sides in [64, 512], {ADJ_STEPS} steps at frozen CFL-{ADJ_CFL} dt, "
-                        f"checkpoint every {ADJ_EVERY} steps", "skipped_nonphysical_members": skipped,
+    return {"workload": f"{members} members (vortices periodic, Riemann problems with zero-gradient sides), sides in "
+                        f"[64, 512], {ADJ_STEPS} steps at frozen CFL-{ADJ_CFL} dt, checkpoint every {ADJ_EVERY} steps",
+            "skipped_nonphysical_members": skipped,
             "forward_s": round(t_fwd, 3), "gradient_s": round(t_grad, 3), "gradient_over_forward": round(t_grad / t_fwd, 2),
             "J": J_total, "grad_norm_vortex_members": gnorm2[0] ** 0.5, "fd_checks": checks}
 
@@ -512,19 +518,21 @@ def _fd_directions(pb, S0, dt, rho_t, h2, grad, n, b, ndir=8):
     indicators are ~0), so the adjoint is the derivative of a branch that a
     finite step leaves; such members are reported, not asserted."""
     import torch
+
+    from paper_2606_17772_amd.adjoint import density, get_state_vector, set_state_vector
     dev = S0.device
     gen = torch.Generator(device=dev).manual_seed(100 + b)
 
     def Jof(v, e):
         S = S0.clone()
-        S[0, 0] += e * v
-        pb.set_state_all(S)
+        density(pb, S).add_(e * v)
+        set_state_vector(pb, S)
         pb.step(nsteps=ADJ_STEPS, dt=dt)
-        return 0.5 * float(((pb.get_state_all(device=dev)[0, 0] - rho_t) ** 2).sum()) * h2
+        return 0.5 * float(((density(pb, get_state_vector(pb, dev)) - rho_t) ** 2).sum()) * h2
 
     rel = {"1e-6": [], "1e-4": []}
     an_all, fd_all = [], []
-    scale = float(S0[0, 0].abs().max())
+    scale = float(density(pb, S0).abs().max())
     for _ in range(ndir):
         v = torch.randn(grad.shape, dtype=torch.float64, device=dev, generator=gen)
         v /= float(v.abs().max())

@@ -487,3 +487,35 @@ def test_vjp_bounded_device_tensors():
     # atomic scatters: the last bits may differ between calls
     assert np.allclose(tP.cpu().numpy(), hP, rtol=1e-13, atol=1e-13 * np.abs(hP).max())
     assert np.allclose(tD.cpu().numpy(), hD, rtol=1e-13, atol=1e-13 * np.abs(hD).max())
+
+
+def test_rollout_bounded_vs_chained_oracle_tangents(oracle):
+    """The checkpointed rollout on a walled problem (flat state vector of
+    both grids): <grad J, v> after 4 fixed steps against the oracle's tangent
+    carried through the same steps."""
+    import torch
+
+    from paper_2606_17772_amd.adjoint import density, get_state_vector, rollout
+    s, P, D = _bounded_case("walls_15x9")
+    dt = 0.2 * (1.0 / s["nx"]) / 3.0
+    h = 1.0 / s["nx"]
+    nsteps = 4
+    par = oracle_par(oracle, s)
+    rng = np.random.default_rng(8)
+    target = P[0] * (1.0 + 0.01 * rng.standard_normal(P[0].shape))
+    vP = rng.standard_normal(P.shape) * np.abs(P).max(axis=(1, 2), keepdims=True)
+    vD = rng.standard_normal(D.shape) * np.abs(D).max(axis=(1, 2), keepdims=True)
+    pb = _bounded_problem(s, P, D)
+    X = get_state_vector(pb, torch.device("cuda:0")).clone().requires_grad_(True)
+    assert X.shape == (P.size + D.size,)
+    out = rollout(pb, X, dt, nsteps, checkpoint_every=3)
+    J = 0.5 * ((density(pb, out) - torch.tensor(target, device="cuda")) ** 2).sum() * h * h
+    J.backward()
+    gv = float((X.grad.cpu().numpy() * np.concatenate([vP.ravel(), vD.ravel()])).sum())
+    A, B, dA, dB = P.copy(), D.copy(), vP, vD
+    for _ in range(nsteps):
+        A, B, dA, dB = oracle.step2d_tangent(par, dt, A, B, dA, dB)
+    ov = float(((A[0] - target) * dA[0]).sum()) * h * h
+    scale = float(np.abs((A[0] - target) * dA[0]).sum()) * h * h
+    assert abs(float(density(pb, out.detach())[0, 0]) - A[0, 0, 0]) <= 1e-12 * abs(A[0, 0, 0])
+    assert abs(gv - ov) <= ADJ_TOL * scale, (gv, ov, scale)
