@@ -96,8 +96,8 @@ enum { FDCGKS_GRAD_REEVAL = 0, FDCGKS_GRAD_CARRIED = 1 };
  * the eigenvectors at the mean of the two interface-adjacent states (at the
  * node's own state for node derivatives) and the path function the smallest
  * of the acoustic fields' left and right values.  Characteristic mode is
- * available to fdcgks_problem steps (1D and 2D, either flux precision) and to
- * batches; the step adjoint rejects it with FDCGKS_EINVAL. */
+ * available to fdcgks_problem steps (1D and 2D, either flux precision), to
+ * batches and to the step adjoint. */
 enum { FDCGKS_RECON_CONSERVATIVE = 0, FDCGKS_RECON_CHARACTERISTIC = 1 };
 
 typedef struct fdcgks_params {
@@ -321,8 +321,9 @@ fdcgks_status fdcgks_autotune(fdcgks_problem* pb, int32_t reps);
  * Non-smooth points take fixed one-sided derivatives: |x| has derivative 0
  * at 0 and min/max ties select the first argument.  2D problems (any sides:
  * the halo fill's ghost rules and the wall condition are differentiated like
- * the rest) with FP64 fluxes and conservative reconstruction only (EINVAL
- * otherwise); ENONPHYS if the recomputed step is non-physical.  With bounded
+ * the rest; either reconstruction, the characteristic frame included) with
+ * FP64 fluxes only (EINVAL otherwise); ENONPHYS if the recomputed step is
+ * non-physical.  With bounded
  * axes grid 1's planes have the dual grid's size (as fdcgks_get_state):
  * lam_out and lam_in hold grid 0's 12 planes, then grid 1's.
  * on_device: both arrays are device pointers (1) or host pointers (0).

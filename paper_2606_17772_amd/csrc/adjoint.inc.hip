@@ -217,15 +217,51 @@ __global__ __launch_bounds__(256) void k_adj_nodeflux(const double* __restrict__
 // GENO^T of one line: lam of (vl, dl, cl, vr, dr, cr) per component ->
 // scatter onto the line's nodes (W plane and derivative plane).  fam and G
 // are runtime values (wave-uniform): one copy of the code serves all lines.
+// CHAR: the line was reconstructed on characteristic variables in its local
+// frame (edge_recon<true>); lv's cl, cr entries are unused and chib is the
+// adjoint of the line's single path function.
+template <bool CHAR>
 __device__ __forceinline__ void line_adjoint(const double* __restrict__ S, double* __restrict__ lamS, const Geo& g,
                                              const Consts& k, int i, int j, int fam, int G,
-                                             const double (&lv)[4][6]) {
+                                             const double (&lv)[4][6], double chib) {
   const bool ALONG_Y = (fam ^ G) != 0;
   const int back = G == 0 ? 1 : 2;
   const long st = ALONG_Y ? g.pitch : 1;
   const long o = (ALONG_Y ? at(g, j - back, i) : at(g, j, i - back)) + (G ? g.dshift : 0);  // shifted dual planes
   const int f = ALONG_Y ? 2 : 1;
   const long pl = g.plane;
+  if constexpr (CHAR) {
+    // local component c holds global component q (rho U and rho V trade places along y), as in edge_recon
+    double Q[4][4], X[4][4], rb[4][4], Qb[4][4], Xb[4][4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int q = ALONG_Y ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+      const double* w = S + (G * 12 + q) * pl + o;
+      const double* x = S + (G * 12 + f * 4 + q) * pl + o;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        Q[c][m] = w[m * st];
+        X[c][m] = x[m * st];
+        Qb[c][m] = Xb[c][m] = 0.0;
+      }
+      rb[c][0] = lv[q][0];
+      rb[c][1] = lv[q][1];
+      rb[c][2] = lv[q][3];
+      rb[c][3] = lv[q][4];
+    }
+    fdk::recon_iface_char_b(k, Q, X, g.h, g.invh, rb, chib, Qb, Xb);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int q = ALONG_Y ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+      double* lw = lamS + (G * 12 + q) * pl + o;
+      double* lx = lamS + (G * 12 + f * 4 + q) * pl + o;
+      for (int m = 0; m < 4; ++m) {
+        if (Qb[c][m] != 0.0) atomicAdd(lw + m * st, Qb[c][m]);
+        if (Xb[c][m] != 0.0) atomicAdd(lx + m * st, Xb[c][m]);
+      }
+    }
+    return;
+  }
   for (int c = 0; c < 4; ++c) {
     const double* w = S + (G * 12 + c) * pl + o;
     const double* x = S + (G * 12 + f * 4 + c) * pl + o;
@@ -252,7 +288,7 @@ __device__ __forceinline__ void line_adjoint(const double* __restrict__ S, doubl
 // The normal along y (fam != G) swaps rho U and rho V in the local frame:
 // the swap is applied to the data, so one copy of the solver adjoint serves
 // both normals.
-template <int STAGE>
+template <int STAGE, bool CHAR>
 __global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__ S, const double* __restrict__ lamE,
                                                       double* __restrict__ lamS, Geo g, Consts k, double dt) {
   __shared__ double xch[4][4][64];
@@ -270,7 +306,7 @@ __global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__
   {
     fdk::IfaceRec rec[4];
     if (valid) {
-      edge_recon<false>(S, g, k, i, j, fam, G, rec);
+      edge_recon<CHAR>(S, g, k, i, j, fam, G, rec);
     } else {
 #pragma unroll
       for (int c = 0; c < 4; ++c) rec[c] = fdk::IfaceRec{1.0, 0.0, 1.0, 1.0, 0.0, 1.0};
@@ -342,14 +378,16 @@ __global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__
       lv[c][4] = inb.nR[q] + lt;
       lv[c][5] = 0.0;
     }
-    if (chi_right) lv[0][5] = lchi; else lv[0][2] = lchi;
-    line_adjoint(S, lamS, g, k, i, j, fam, G, lv);
+    if (!CHAR) {
+      if (chi_right) lv[0][5] = lchi; else lv[0][2] = lchi;
+    }
+    line_adjoint<CHAR>(S, lamS, g, k, i, j, fam, G, lv, CHAR ? lchi : 0.0);
   }
 }
 
 // Reverse of the node sweep: lambda of the nodal fluxes -> lambda of the
 // node's W and of the 3-point lines its derivative reconstructions read.
-template <int STAGE>
+template <int STAGE, bool CHAR>
 __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S, const double* __restrict__ lamN,
                                                    double* __restrict__ lamS, Geo g, Consts k) {
   const int grid = blockIdx.z, w = node_reach(k);
@@ -361,14 +399,8 @@ __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S,
   const double* B = S + (long)grid * 12 * pl + ds;
   const double* ln = lamN + (long)grid * 16 * pl + o;
   double W[4], Wx[4], Wy[4];
-  for (int c = 0; c < 4; ++c) {
-    const double* w = B + c * pl + o;
-    const double* x = B + (4 + c) * pl + o;
-    const double* y = B + (8 + c) * pl + o;
-    W[c] = w[0];
-    Wx[c] = fdk::recon_node(k, w[-1], w[0], w[1], x[-1], x[0], x[1], g.h, g.invh);
-    Wy[c] = fdk::recon_node(k, w[-g.pitch], w[0], w[g.pitch], y[-g.pitch], y[0], y[g.pitch], g.h, g.invh);
-  }
+  for (int c = 0; c < 4; ++c) W[c] = B[c * pl + o];
+  node_derivs<CHAR, double>(B, g, k, o, Wx, Wy);
   double lF[4], lFt[4], lG[4], lGt[4];
   for (int c = 0; c < 4; ++c) {
     lF[c] = ln[c * pl];
@@ -382,6 +414,39 @@ __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S,
     for (int c = 0; c < 4; ++c) { lF[c] = 0.0; lG[c] = 0.0; }
   fdk::gks_node_b(k, W, Wx, Wy, lF, lFt, lG, lGt, Wb, Wxb, Wyb);
   double* lS = lamS + (long)grid * 12 * pl + ds + o;
+  if constexpr (CHAR) {
+    for (int c = 0; c < 4; ++c)
+      if (Wb[c] != 0.0) atomicAdd(lS + c * pl, Wb[c]);
+    // derivative reconstructions along x and y on characteristic variables (local frame of each axis: rho U
+    // and rho V trade places along y, as in node_derivs)
+    for (int a = 0; a < 2; ++a) {
+      const long st = a == 0 ? 1 : g.pitch;
+      double Q[4][3], X[4][3], db[4], Qb[4][3], Xb[4][3];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int q = a == 1 ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+        const double* w = B + q * pl + o;
+        const double* x = B + ((a + 1) * 4 + q) * pl + o;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          Q[c][m] = w[(m - 1) * st];
+          X[c][m] = x[(m - 1) * st];
+          Qb[c][m] = Xb[c][m] = 0.0;
+        }
+        db[c] = a == 0 ? Wxb[q] : Wyb[q];
+      }
+      fdk::recon_node_char_b(k, Q, X, g.h, g.invh, db, Qb, Xb);
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int q = a == 1 ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+        for (int m = 0; m < 3; ++m) {
+          if (Qb[c][m] != 0.0) atomicAdd(lS + q * pl + (m - 1) * st, Qb[c][m]);
+          if (Xb[c][m] != 0.0) atomicAdd(lS + ((a + 1) * 4 + q) * pl + (m - 1) * st, Xb[c][m]);
+        }
+      }
+    }
+    return;
+  }
   for (int c = 0; c < 4; ++c) {
     if (Wb[c] != 0.0) atomicAdd(lS + c * pl, Wb[c]);
     // derivative reconstructions along x and y

@@ -2289,9 +2289,12 @@ fdcgks_status adj_stage(fdcgks_problem* pb, double dt, const double* Sin, const 
   const int w = node_reach(pb->k);  // nodes whose fluxes the forward sweep computes beyond the grid's own
   const dim3 gn(ceil_div(g.nx + 2 * w + g.sx, 64), ceil_div(g.ny + 2 * w + g.sy, 4), 2);
   hipLaunchKernelGGL((k_adj_nodeflux<STAGE>), gn, blk, 0, pb->stream, pb->Op, E, pb->LN, g, pb->k);
-  hipLaunchKernelGGL((k_adj_edges<STAGE>), dim3(ceil_div(g.nx + 3 + g.sx, 64), ceil_div(g.ny + 3 + g.sy, 2), 2), blk,
-                     0, pb->stream, Sin, pb->LE, scatter, g, pb->k, dt);
-  hipLaunchKernelGGL((k_adj_nodes<STAGE>), gn, blk, 0, pb->stream, Sin, pb->LN, scatter, g, pb->k);
+  const bool chr = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
+  hipLaunchKernelGGL((chr ? k_adj_edges<STAGE, true> : k_adj_edges<STAGE, false>),
+                     dim3(ceil_div(g.nx + 3 + g.sx, 64), ceil_div(g.ny + 3 + g.sy, 2), 2), blk, 0, pb->stream, Sin,
+                     pb->LE, scatter, g, pb->k, dt);
+  hipLaunchKernelGGL((chr ? k_adj_nodes<STAGE, true> : k_adj_nodes<STAGE, false>), gn, blk, 0, pb->stream, Sin,
+                     pb->LN, scatter, g, pb->k);
   adj_fold(pb, scatter);
   return launch_check(pb, "adjoint stage");
 }
@@ -2795,8 +2798,6 @@ fdcgks_status fdcgks_step_vjp(fdcgks_problem* pb, double dt, const double* lam_o
   if (!pb || !lam_out || !lam_in) return fail(pb, FDCGKS_EINVAL, "NULL argument");
   if (pb->prm.dim != 2) return fail(pb, FDCGKS_EINVAL, "the step adjoint is implemented for 2D problems");
   if (pb->prm.flux_precision != FDCGKS_FP64) return fail(pb, FDCGKS_EINVAL, "the step adjoint needs FP64 fluxes");
-  if (pb->prm.recon_vars != FDCGKS_RECON_CONSERVATIVE)
-    return fail(pb, FDCGKS_EINVAL, "the step adjoint needs conservative reconstruction");
   if (!(dt > 0) || !std::isfinite(dt)) return fail(pb, FDCGKS_EINVAL, "dt must be finite and > 0");
   if (!state_ready(pb)) return fail(pb, FDCGKS_ESTATE, "set_state has not been called for every grid");
   fdcgks_status st = adj_alloc(pb);

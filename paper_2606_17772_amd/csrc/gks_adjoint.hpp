@@ -968,4 +968,205 @@ FDK_HD void recon_node_b(const Consts& k, const double q[3], const double x[3], 
   xb[2] += h * kx * PHxb;
 }
 
+// ---------------------------------------------- characteristic variables
+// Reverse of the 2D characteristic reconstructions (recon_iface_char<2>,
+// recon_node_char<2> in gks_device.hpp): the frame (eigenvectors at the mean
+// interface state, or at the node) depends on the line's values, so its
+// adjoint flows back into them as well.
+struct FrameB {
+  double u, v, c, ic, H, b1, b2, k2;
+};
+FDK_HD FrameB frameb_zero() { return FrameB{0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0}; }
+
+// q = L(f) w: adds L^T qb to wb and the frame's adjoint to fb.
+FDK_HD void to_char_b(const CharFrame& f, const double* w, const double* qb, double* wb, FrameB& fb) {
+  const double ab = 0.5 * (qb[0] + qb[3]) - qb[1];  // a = b2 w0 + s
+  const double mb = 0.5 * (qb[3] - qb[0]);           // m = ic w1 - u ic w0
+  const double sb = ab;                               // s = b1 (w3 - u w1 - v w2)
+  wb[0] += qb[1] - f.v * qb[2] + f.b2 * ab - f.u * f.ic * mb;
+  wb[1] += f.ic * mb - f.u * f.b1 * sb;
+  wb[2] += qb[2] - f.v * f.b1 * sb;
+  wb[3] += f.b1 * sb;
+  fb.b2 += w[0] * ab;
+  fb.b1 += (w[3] - f.u * w[1] - f.v * w[2]) * sb;
+  fb.ic += (w[1] - f.u * w[0]) * mb;
+  fb.u += -f.ic * w[0] * mb - f.b1 * w[1] * sb;
+  fb.v += -w[0] * qb[2] - f.b1 * w[2] * sb;
+}
+
+// w = R(f) q: adds R^T wb to qb and the frame's adjoint to fb.
+FDK_HD void from_char_b(const CharFrame& f, const double* q, const double* wb, double* qb, FrameB& fb) {
+  const double lo = q[0], en = q[1], sh = q[2], hi = q[3], sum = lo + en + hi, d = hi - lo;
+  const double sb = wb[0] + f.u * wb[1] + f.v * wb[2];
+  qb[0] += sb - f.c * wb[1] + (f.H - f.u * f.c) * wb[3];
+  qb[1] += sb + f.k2 * wb[3];
+  qb[2] += wb[2] + f.v * wb[3];
+  qb[3] += sb + f.c * wb[1] + (f.H + f.u * f.c) * wb[3];
+  fb.u += sum * wb[1] + f.c * d * wb[3];
+  fb.v += sum * wb[2] + sh * wb[3];
+  fb.c += d * wb[1] + f.u * d * wb[3];
+  fb.H += (lo + hi) * wb[3];
+  fb.k2 += en * wb[3];
+}
+
+// The frame from the state W: adds the adjoint of W.
+FDK_HD void char_frame_b(double gamma, const double* W, const CharFrame& f, FrameB fb, double* Wb) {
+  const double ir = 1.0 / W[0], gm = gamma - 1.0;
+  const double p = gm * (W[3] - W[0] * f.k2), c2 = f.c * f.c;
+  fb.b1 += f.k2 * fb.b2;  // b2 = b1 k2
+  fb.k2 += f.b1 * fb.b2;
+  double c2b = -gm / (c2 * c2) * fb.b1;                 // b1 = (gamma - 1) / c2
+  fb.c += -fb.ic / c2;                                  // ic = 1 / c
+  c2b += fb.c / (2.0 * f.c);                            // c = sqrt(c2)
+  double pb = ir * fb.H + gamma * ir * c2b;             // H = (W3 + p) ir, c2 = gamma p ir
+  double irb = (W[3] + p) * fb.H + gamma * p * c2b;
+  Wb[3] += ir * fb.H + gm * pb;                         // p = (gamma - 1)(W3 - W0 k2)
+  Wb[0] += -gm * f.k2 * pb;
+  fb.k2 += -gm * W[0] * pb;
+  fb.u += f.u * fb.k2;                                  // k2 = (u^2 + v^2) / 2
+  fb.v += f.v * fb.k2;
+  Wb[1] += ir * fb.u;                                   // u = W1 ir, v = W2 ir
+  Wb[2] += ir * fb.v;
+  irb += W[1] * fb.u + W[2] * fb.v;
+  Wb[0] += -ir * ir * irb;                              // ir = 1 / W0
+}
+
+// Reverse of recon_iface_char<2>.  rb[c]: adjoints of rec[c].vl, dl, vr, dr
+// (local frame); chib: adjoint of chi.  Adds into Qb, Xb.  chi's adjoint goes
+// to the first of chi^l(u-c), chi^r(u-c), chi^l(u+c), chi^r(u+c) that attains
+// the minimum.
+FDK_HD void recon_iface_char_b(const Consts& k, const double (&Q)[4][4], const double (&X)[4][4], double h,
+                               double invh, const double (&rb)[4][4], double chib, double (&Qb)[4][4],
+                               double (&Xb)[4][4]) {
+  double Wm[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Wm[c] = 0.5 * (Q[c][1] + Q[c][2]);
+  const CharFrame f = char_frame<2>(k.gamma, Wm);
+  double qc[4][4], xc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double a[4], b[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = Q[c][m];
+    to_char<2>(f, a, b);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { qc[c][m] = b[c]; a[c] = X[c][m]; }
+    to_char<2>(f, a, b);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xc[c][m] = b[c];
+  }
+  IfaceRec cr[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    cr[c] = recon_iface<double>(k, qc[c][0], qc[c][1], qc[c][2], qc[c][3], xc[c][0], xc[c][1], xc[c][2], xc[c][3],
+                                h, invh);
+  // adjoints of the characteristic results (vl, dl, cl, vr, dr, cr per field)
+  double crb[4][6];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int t = 0; t < 6; ++t) crb[c][t] = 0.0;
+  FrameB fb = frameb_zero();
+#pragma unroll
+  for (int slot = 0; slot < 4; ++slot) {  // vl, dl, vr, dr
+    const int t = slot < 2 ? slot : slot + 1;
+    double a[4], wb[4], ab[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      a[c] = t == 0 ? cr[c].vl : (t == 1 ? cr[c].dl : (t == 3 ? cr[c].vr : cr[c].dr));
+      wb[c] = rb[c][slot];
+    }
+    from_char_b(f, a, wb, ab, fb);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) crb[c][t] += ab[c];
+  }
+  {
+    const double cand[4] = {cr[0].cl, cr[0].cr, cr[3].cl, cr[3].cr};
+    int sel = 0;
+#pragma unroll
+    for (int a = 1; a < 4; ++a)
+      if (cand[a] < cand[sel]) sel = a;
+    crb[sel < 2 ? 0 : 3][sel % 2 == 0 ? 2 : 5] += chib;
+  }
+  double qcb[4][4], xcb[4][4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) { qcb[c][m] = 0.0; xcb[c][m] = 0.0; }
+    recon_iface_b(k, qc[c], xc[c], h, invh, crb[c], qcb[c], xcb[c]);
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    double a[4], b[4], wb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { a[c] = Q[c][m]; b[c] = qcb[c][m]; }
+    to_char_b(f, a, b, wb, fb);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { Qb[c][m] += wb[c]; wb[c] = 0.0; a[c] = X[c][m]; b[c] = xcb[c][m]; }
+    to_char_b(f, a, b, wb, fb);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Xb[c][m] += wb[c];
+  }
+  double Wmb[4] = {0.0, 0.0, 0.0, 0.0};
+  char_frame_b(k.gamma, Wm, f, fb, Wmb);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    Qb[c][1] += 0.5 * Wmb[c];
+    Qb[c][2] += 0.5 * Wmb[c];
+  }
+}
+
+// Reverse of recon_node_char<2>: db = adjoint of the node derivative d (local
+// frame).  Adds into Qb, Xb.
+FDK_HD void recon_node_char_b(const Consts& k, const double (&Q)[4][3], const double (&X)[4][3], double h,
+                              double invh, const double (&db)[4], double (&Qb)[4][3], double (&Xb)[4][3]) {
+  double Wc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Wc[c] = Q[c][1];
+  const CharFrame f = char_frame<2>(k.gamma, Wc);
+  double qc[4][3], xc[4][3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double a[4], b[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a[c] = Q[c][m];
+    to_char<2>(f, a, b);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { qc[c][m] = b[c]; a[c] = X[c][m]; }
+    to_char<2>(f, a, b);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) xc[c][m] = b[c];
+  }
+  double dc[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    dc[c] = recon_node<double>(k, qc[c][0], qc[c][1], qc[c][2], xc[c][0], xc[c][1], xc[c][2], h, invh);
+  FrameB fb = frameb_zero();
+  double dcb[4] = {0.0, 0.0, 0.0, 0.0};
+  from_char_b(f, dc, db, dcb, fb);
+  double qcb[4][3], xcb[4][3];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) { qcb[c][m] = 0.0; xcb[c][m] = 0.0; }
+    recon_node_b(k, qc[c], xc[c], h, invh, dcb[c], qcb[c], xcb[c]);
+  }
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    double a[4], b[4], wb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { a[c] = Q[c][m]; b[c] = qcb[c][m]; }
+    to_char_b(f, a, b, wb, fb);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) { Qb[c][m] += wb[c]; wb[c] = 0.0; a[c] = X[c][m]; b[c] = xcb[c][m]; }
+    to_char_b(f, a, b, wb, fb);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) Xb[c][m] += wb[c];
+  }
+  double Wcb[4] = {0.0, 0.0, 0.0, 0.0};
+  char_frame_b(k.gamma, Wc, f, fb, Wcb);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) Qb[c][1] += Wcb[c];
+}
+
 }  // namespace fdk

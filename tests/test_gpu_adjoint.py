@@ -6,8 +6,9 @@ References:
     (J^T lam)_k = <lam, J e_k> element by element (all inputs on an 8 x 8
     grid and on an 8 x 6 walled one, sampled inputs on larger ones, boundary
     nodes included; periodic, zero-gradient, reflecting and no-slip sides,
-    order-6 and order-8 fluxes), and the identity <lam, J v> = <J^T lam, v>
-    for random v;
+    order-6 and order-8 fluxes, conservative and characteristic
+    reconstruction), and the identity <lam, J v> = <J^T lam, v> for random
+    v;
   * central differences of the GPU step itself (smooth data);
   * chained oracle tangents for a multi-step objective through autograd.
 Bar: |gpu_k - oracle_k| <= max(1e-11 * sum_i |lam_i (J e_k)_i|, 4 x the
@@ -60,6 +61,18 @@ def _case(name):
                                         WL.random_smooth2d(12, 12, seed=20)),
         "smooth_12_linear_order8": lambda: (settings(dim=2, nx=12, ny=12, lx=1.0, variant="linear", flux_order=8),
                                             WL.random_smooth2d(12, 12, seed=21)),
+        # characteristic reconstruction: rough and Riemann data, where GENO blends (on smooth data chi ~ 1
+        # and the reconstruction is linear, so both variable sets give the same map)
+        "tiny_8_char": lambda: (settings(dim=2, nx=8, ny=8, lx=1.0, recon_vars="characteristic"),
+                                WL.random_rough2d(8, 8, seed=22)),
+        "rough_66x9_char": lambda: (settings(dim=2, nx=66, ny=9, lx=1.0, recon_vars="characteristic"),
+                                    WL.random_rough2d(66, 9, seed=23)),
+        "riemann_33x20_char": lambda: (settings(dim=2, nx=33, ny=20, lx=1.0, recon_vars="characteristic"),
+                                       WL.riemann2d(33, seed=24)),
+        "rough_ns_20_char_62": lambda: (settings(dim=2, nx=20, ny=20, lx=1.0, mu=1e-3, prandtl=0.72, variant="6-2",
+                                                 recon_vars="characteristic"), WL.random_rough2d(20, 20, seed=25)),
+        "rough_12_char_order8": lambda: (settings(dim=2, nx=12, ny=12, lx=1.0, recon_vars="characteristic",
+                                                  flux_order=8), WL.random_rough2d(12, 12, seed=26)),
     }[name]
     s, pr = c()
     if pr.ny != s["ny"]:
@@ -121,7 +134,7 @@ def _check_columns(oracle, par, dt, S, lam, g, ks):
     return worst, wbar
 
 
-@pytest.mark.parametrize("name", ["tiny_8", "tiny_8_order8"])
+@pytest.mark.parametrize("name", ["tiny_8", "tiny_8_order8", "tiny_8_char"])
 def test_vjp_all_columns_tiny(oracle, name):
     s, pr = _case(name)
     S, lam = _inputs(pr, 0)
@@ -147,7 +160,8 @@ def _sample(S, rng, n=40):
 @pytest.mark.parametrize("name", ["smooth_67x10", "rough_66x9", "smooth_ns_20", "shear_ns_20_smoothmap",
                                   "riemann_33x20", "smooth_12_62", "smooth_12_linear", "smooth_12_carried",
                                   "smooth_67x10_order8", "rough_66x9_order8", "smooth_ns_20_order8",
-                                  "smooth_12_62_order8", "smooth_12_linear_order8"])
+                                  "smooth_12_62_order8", "smooth_12_linear_order8", "rough_66x9_char",
+                                  "riemann_33x20_char", "rough_ns_20_char_62", "rough_12_char_order8"])
 def test_vjp_sampled_columns(oracle, name):
     s, pr = _case(name)
     S, lam = _inputs(pr, 1)
@@ -375,6 +389,7 @@ def _bounded_case(name):
         "zero_gradient_riemann_13": lambda: riemann(13),
         "walls_order8_12x9": lambda: walls(12, 9, ["reflecting", "reflecting", "no_slip", "reflecting"],
                                            flux_order=8, **ns),
+        "zero_gradient_riemann_char_13": lambda: riemann(13, recon_vars="characteristic"),
     }[name]()
 
 
@@ -450,7 +465,7 @@ def test_vjp_bounded_all_columns_tiny(oracle):
 
 
 @pytest.mark.parametrize("name", ["walls_15x9", "mixed_14x10", "zero_gradient_11x12", "zero_gradient_riemann_13",
-                                  "walls_order8_12x9"])
+                                  "walls_order8_12x9", "zero_gradient_riemann_char_13"])
 def test_vjp_bounded_sampled_columns(oracle, name):
     s, P, D = _bounded_case(name)
     rng = np.random.default_rng(1)

@@ -6,7 +6,8 @@ Same cases and bars as the conservative-variable parity tests: interface and
 node intermediates and both stages at the floored 1e-12 bar, several CFL
 steps at max(1e-12, 4 x the oracle's one-ulp sensitivity), 1D stages at
 1e-12, sampled nodes of one step at the full 2048^2 size in the benchmark's
-launch shapes.  The step adjoint rejects this mode (batches run it: test_gpu_batch.py)."""
+launch shapes.  Batches and the step adjoint in this mode: test_gpu_batch.py,
+test_gpu_adjoint.py."""
 import numpy as np
 import pytest
 
@@ -189,14 +190,3 @@ def test_long_run_1d_char(oracle, name, t_end):
     err = l1(g, oS)
     print(f"{name} characteristic: {n} steps, values L1 gpu-oracle {err:.2e}, oracle one-ulp spread {spread:.2e}")
     assert err <= max(TOL, 4 * spread)
-
-
-def test_adjoint_rejects_char():
-    from paper_2606_17772_amd import FdcgksError, Problem
-    s, pr = _case("vortex_40")
-    pb = Problem(gpu_params(s))
-    pb.set_state_stacked(0, pr.P)
-    pb.set_state_stacked(1, pr.D)
-    lam = np.zeros((2, 12, pr.ny, pr.nx))
-    with pytest.raises(FdcgksError, match="conservative reconstruction"):
-        pb.step_vjp(0.01, lam)
