@@ -774,8 +774,9 @@ struct IfaceVals {
 };
 template <int STAGE, class FT, bool CHAR>
 __device__ __forceinline__ void fused_iface(const double* __restrict__ S, const Geo& g, const Consts& k, double dt,
-                                            int i, int j, int fam, bool valid, double* xch, IfaceVals& o) {
-  const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
+                                            int i, int j, int fam, bool valid, double* xch, IfaceVals& o, int tx,
+                                            int ty) {
+  const int G = ty & 1;
   constexpr int TX = 64, TY = 4;
 #define XCH(c, r) xch[((c) * TY + (r)) * TX + tx]
   fdk::IfaceRec rec[4];
@@ -897,12 +898,36 @@ __device__ __forceinline__ void fused_grad(const double* __restrict__ S, const d
   }
 }
 
+// Copies of loop-invariant values the compiler cannot see through: formed
+// inside a loop, everything computed from them stays inside it.
+__device__ __forceinline__ Geo opaque_strides(const Geo& g) {
+  Geo q = g;
+  asm volatile("" : "+s"(q.plane), "+s"(q.pitch), "+s"(q.h), "+s"(q.invh));
+  return q;
+}
+__device__ __forceinline__ Consts opaque_consts(const Consts& k) {
+  Consts q = k;
+  asm volatile("" : "+s"(q.gamma), "+s"(q.K), "+s"(q.inv_Kd), "+s"(q.mu), "+s"(q.prfix));
+  asm volatile("" : "+s"(q.C), "+s"(q.inv_tanhC), "+s"(q.eps), "+s"(q.eps_a), "+s"(q.dc), "+s"(q.ds));
+  asm volatile("" : "+s"(q.tau_c1), "+s"(q.tau_c2));
+  return q;
+}
+__device__ __forceinline__ double opaque_uniform(double x) {
+  asm volatile("" : "+s"(x));
+  return x;
+}
+__device__ __forceinline__ int opaque_lane(int x) {
+  asm volatile("" : "+v"(x));
+  return x;
+}
+
 template <int STAGE, class FT, bool CHAR>
 __global__ __launch_bounds__(256, 2) void k_fused2d(const double* __restrict__ S, const double* __restrict__ Nb,
                                                     const double* __restrict__ Ain, double* __restrict__ Out,
-                                                    double* __restrict__ Aout, Geo g, Consts k,
+                                                    double* __restrict__ Aout, Geo g_in, Consts k_in,
                                                     Scal* __restrict__ sc, double* __restrict__ part, int nparts,
                                                     int nstrips, int nchunks, int rows) {
+  const Geo& g0 = g_in;
   if (sc->stop) return;  // grid-uniform
   int t;
   if (!xcd_tile(blockIdx.x, gridDim.x, nstrips * nchunks, t)) return;  // block-uniform
@@ -911,19 +936,26 @@ __global__ __launch_bounds__(256, 2) void k_fused2d(const double* __restrict__ S
   __shared__ LD lds;
   const int strip = t / nchunks, chunk = t % nchunks;
   const int i0 = strip * FS_W;
-  const int jlo = chunk * rows, jhi = min(g.ny, jlo + rows);
-  const int lane = threadIdx.x, ty = threadIdx.y, fam = ty >> 1;
-  const int i = fam == 0 ? i0 - 2 + lane : i0 - 1 + lane;  // the lane's interface column
-  const double dt = sc->dt;
-  const long pl = g.plane;
+  const int jlo = chunk * rows, jhi = min(g0.ny, jlo + rows);
+  const int fam = threadIdx.y >> 1;
+  const int i_lane = (fam == 0 ? i0 - 2 : i0 - 1) + threadIdx.x;  // the lane's interface column
+  const double dt_in = sc->dt;
   const bool fold = STAGE == 2 && part != nullptr;
   double cfl_s = 0.0, cfl_r = 1e300;
   for (int J = jlo - 2; J <= jhi + 1; ++J) {
+    // the strides, scheme constants, time step and lane indices as values the compiler cannot see through, so
+    // that what is computed from them is formed inside the loop: hoisted in front of it (plane offsets, dt and
+    // constant expressions), about 45 values would hold registers through the interface solve and spill
+    const Geo g = opaque_strides(g_in);
+    const Consts k = opaque_consts(k_in);
+    const double dt = opaque_uniform(dt_in);
+    const int lane = opaque_lane(threadIdx.x), i = opaque_lane(i_lane), ty = opaque_lane(threadIdx.y);
+    const long pl = g.plane;
     // X rows jlo-1 .. jhi+1, Y rows jlo-2 .. jhi (block-uniform per wave pair)
     const bool row_ok = fam == 0 ? J >= jlo - 1 : J <= jhi;
     const bool valid = row_ok && i <= (fam == 0 ? g.nx : g.nx + 1);
     IfaceVals v;
-    fused_iface<STAGE, FT, CHAR>(S, g, k, dt, i, J, fam, valid, lds.xch, v);
+    fused_iface<STAGE, FT, CHAR>(S, g, k, dt, i, J, fam, valid, lds.xch, v, lane, ty);
     if (ty == 0 || ty == 3) {
       // x-flux differences and x-gradients of row J: primary (ty 0, nodes
       // i = i0 - 2 + lane, lanes 2..62) or dual (ty 3, nodes i = i0 - 1 + lane,
