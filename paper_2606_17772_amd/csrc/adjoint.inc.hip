@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const double* __restrict__
         const double chi = e[8 * pl + eo];
         const CFd d = cf_partials(k.variant, chi, wide);
         lF += (q == -1 ? d.dp : (q == 0 ? d.dc : d.dm)) * lcf;
-        // (the nodal fluxes of interfaces without an interior node are not computed: skip them)
+        // interfaces next to no updated node have lcf = 0, and their outer nodal fluxes are not computed
         if (q == 0 && lcf != 0.0)
           lchi += cf_dchi(k.variant, f[-st], f[0], f[st], wide ? n[nL - st] : 0.0, n[nL], n[nR],
                           wide ? n[nR + st] : 0.0, wide) * lcf;
@@ -172,8 +172,9 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const double* __restrict__
 // Lambda of the nodal fluxes: node n is the left node (N0) of its right
 // interface e_R = n + G st and the right node (N1) of e_L = e_R - st; with
 // the order-8 flux also Nm of e_R + st and Np2 of e_L - st.  Nodes i, j in
-// [-w, n - 1 + w] (w = node reach): the nodes whose fluxes the forward sweep
-// computes.  Only interfaces with an interior node carry a flux adjoint.
+// [-w, n - 1 + w] (w = node reach; the dual grid's range starts one node
+// lower along a bounded axis): the nodes whose fluxes the forward sweep
+// computes.  Only interfaces next to an updated node carry a flux adjoint.
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_adj_nodeflux(const double* __restrict__ lam_op, const double* __restrict__ E,
                                                       double* __restrict__ lamN, Geo g, Consts k) {
