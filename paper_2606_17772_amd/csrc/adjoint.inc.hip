@@ -388,83 +388,126 @@ __global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__
 
 // Reverse of the node sweep: lambda of the nodal fluxes -> lambda of the
 // node's W and of the 3-point lines its derivative reconstructions read.
+// Block 64 x 4 nodes, one wave per row.  A node's reverse adds to 12 planes
+// of itself and to 8 planes of each neighbour along x and y (W and that
+// axis's derivative plane).  Each thread parks its contributions in LDS
+// slots of its own as they are produced; after a barrier every node sums
+// what it received from the adjacent lanes and rows of the block and adds
+// the 12 sums atomically (neighbouring blocks add to the same nodes), and
+// only contributions that leave the block go out one by one.
 template <int STAGE, bool CHAR>
 __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S, const double* __restrict__ lamN,
                                                    double* __restrict__ lamS, Geo g, Consts k) {
-  const int grid = blockIdx.z, w = node_reach(k);
-  const int i = blockIdx.x * 64 + threadIdx.x - w - (grid ? g.sx : 0);
-  const int j = blockIdx.y * 4 + threadIdx.y - w - (grid ? g.sy : 0);
-  if (i > g.nx - 1 + w || j > g.ny - 1 + w) return;
+  // [slot][thread]: own[p] = plane p of this node; to_xm / to_xp / to_ym / to_yp [s] = the node at i -/+ 1 or
+  // j -/+ 1, plane s for s < 4 (W), else the axis's derivative plane (4 + s along x, 8 + (s - 4) along y)
+  __shared__ double own[12][256], to_xm[8][256], to_xp[8][256], to_ym[8][256], to_yp[8][256];
+  const int grid = blockIdx.z, w = node_reach(k), tx = threadIdx.x, ty = threadIdx.y, t = ty * 64 + tx;
+  const int i = blockIdx.x * 64 + tx - w - (grid ? g.sx : 0);
+  const int j = blockIdx.y * 4 + ty - w - (grid ? g.sy : 0);
+  for (int p = 0; p < 12; ++p) own[p][t] = 0.0;
+  for (int s8 = 0; s8 < 8; ++s8) { to_xm[s8][t] = 0.0; to_xp[s8][t] = 0.0; to_ym[s8][t] = 0.0; to_yp[s8][t] = 0.0; }
   const long pl = g.plane, o = at(g, j, i);
   const long ds = grid ? g.dshift : 0;  // state planes: shifted dual
-  const double* B = S + (long)grid * 12 * pl + ds;
-  const double* ln = lamN + (long)grid * 16 * pl + o;
-  double W[4], Wx[4], Wy[4];
-  for (int c = 0; c < 4; ++c) W[c] = B[c * pl + o];
-  node_derivs<CHAR, double>(B, g, k, o, Wx, Wy);
-  double lF[4], lFt[4], lG[4], lGt[4];
-  for (int c = 0; c < 4; ++c) {
-    lF[c] = ln[c * pl];
-    lFt[c] = ln[(4 + c) * pl];
-    lG[c] = ln[(8 + c) * pl];
-    lGt[c] = ln[(12 + c) * pl];
+  // the nodes whose fluxes the forward sweep computed; the rest of the block
+  // only collects what its neighbours hand over
+  if (i <= g.nx - 1 + w && j <= g.ny - 1 + w) {
+    const double* B = S + (long)grid * 12 * pl + ds;
+    const double* ln = lamN + (long)grid * 16 * pl + o;
+    double W[4], Wx[4], Wy[4];
+    for (int c = 0; c < 4; ++c) W[c] = B[c * pl + o];
+    node_derivs<CHAR, double>(B, g, k, o, Wx, Wy);
+    double lF[4], lFt[4], lG[4], lGt[4];
+    for (int c = 0; c < 4; ++c) {
+      lF[c] = ln[c * pl];
+      lFt[c] = ln[(4 + c) * pl];
+      lG[c] = ln[(8 + c) * pl];
+      lGt[c] = ln[(12 + c) * pl];
+    }
+    // nodal solver^T (stage 2 has no F, G outputs)
+    double Wb[4] = {0, 0, 0, 0}, Wxb[4] = {0, 0, 0, 0}, Wyb[4] = {0, 0, 0, 0};
+    if (STAGE == 2)
+      for (int c = 0; c < 4; ++c) { lF[c] = 0.0; lG[c] = 0.0; }
+    fdk::gks_node_b(k, W, Wx, Wy, lF, lFt, lG, lGt, Wb, Wxb, Wyb);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) own[c][t] += Wb[c];
+    // the 3-point line of axis a, component q: adjoints of W (qb) and of the axis's derivative plane (xb) at
+    // offsets -1, 0, +1
+    auto park = [&](int a, int q, const double* qb, const double* xb) {
+      own[q][t] += qb[1];
+      own[(a + 1) * 4 + q][t] += xb[1];
+      if (a == 0) {
+        to_xm[q][t] = qb[0]; to_xm[4 + q][t] = xb[0]; to_xp[q][t] = qb[2]; to_xp[4 + q][t] = xb[2];
+      } else {
+        to_ym[q][t] = qb[0]; to_ym[4 + q][t] = xb[0]; to_yp[q][t] = qb[2]; to_yp[4 + q][t] = xb[2];
+      }
+    };
+    if constexpr (CHAR) {
+      // derivative reconstructions along x and y on characteristic variables (local frame of each axis: rho U
+      // and rho V trade places along y, as in node_derivs)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const long st = a == 0 ? 1 : g.pitch;
+        double Q[4][3], X[4][3], db[4], Qb[4][3], Xb[4][3];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int q = a == 1 ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
+          const double* wp = B + q * pl + o;
+          const double* xq = B + ((a + 1) * 4 + q) * pl + o;
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            Q[c][m] = wp[(m - 1) * st];
+            X[c][m] = xq[(m - 1) * st];
+            Qb[c][m] = Xb[c][m] = 0.0;
+          }
+          db[c] = a == 0 ? Wxb[q] : Wyb[q];
+        }
+        fdk::recon_node_char_b(k, Q, X, g.h, g.invh, db, Qb, Xb);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) park(a, a == 1 ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c, Qb[c], Xb[c]);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          // derivative reconstructions along x and y
+          const double la = a == 0 ? Wxb[c] : Wyb[c];
+          if (la == 0.0) continue;
+          const long st = a == 0 ? 1 : g.pitch;
+          const double* wp = B + c * pl + o;
+          const double* xq = B + ((a + 1) * 4 + c) * pl + o;
+          const double q[3] = {wp[-st], wp[0], wp[st]}, xv[3] = {xq[-st], xq[0], xq[st]};
+          double qb[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
+          fdk::recon_node_b(k, q, xv, g.h, g.invh, la, qb, xb);
+          park(a, c, qb, xb);
+        }
+    }
   }
-  // nodal solver^T (stage 2 has no F, G outputs)
-  double Wb[4] = {0, 0, 0, 0}, Wxb[4] = {0, 0, 0, 0}, Wyb[4] = {0, 0, 0, 0};
-  if (STAGE == 2)
-    for (int c = 0; c < 4; ++c) { lF[c] = 0.0; lG[c] = 0.0; }
-  fdk::gks_node_b(k, W, Wx, Wy, lF, lFt, lG, lGt, Wb, Wxb, Wyb);
+  __syncthreads();
   double* lS = lamS + (long)grid * 12 * pl + ds + o;
-  if constexpr (CHAR) {
-    for (int c = 0; c < 4; ++c)
-      if (Wb[c] != 0.0) atomicAdd(lS + c * pl, Wb[c]);
-    // derivative reconstructions along x and y on characteristic variables (local frame of each axis: rho U
-    // and rho V trade places along y, as in node_derivs)
-    for (int a = 0; a < 2; ++a) {
-      const long st = a == 0 ? 1 : g.pitch;
-      double Q[4][3], X[4][3], db[4], Qb[4][3], Xb[4][3];
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int q = a == 1 ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
-        const double* w = B + q * pl + o;
-        const double* x = B + ((a + 1) * 4 + q) * pl + o;
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-          Q[c][m] = w[(m - 1) * st];
-          X[c][m] = x[(m - 1) * st];
-          Qb[c][m] = Xb[c][m] = 0.0;
-        }
-        db[c] = a == 0 ? Wxb[q] : Wyb[q];
-      }
-      fdk::recon_node_char_b(k, Q, X, g.h, g.invh, db, Qb, Xb);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const int q = a == 1 ? (c == 1 ? 2 : (c == 2 ? 1 : c)) : c;
-        for (int m = 0; m < 3; ++m) {
-          if (Qb[c][m] != 0.0) atomicAdd(lS + q * pl + (m - 1) * st, Qb[c][m]);
-          if (Xb[c][m] != 0.0) atomicAdd(lS + ((a + 1) * 4 + q) * pl + (m - 1) * st, Xb[c][m]);
-        }
-      }
-    }
-    return;
+  // contributions that leave the block
+  for (int s8 = 0; s8 < 8; ++s8) {
+    const int py = s8 < 4 ? s8 : s8 + 4;
+    double v;
+    if (tx == 0 && (v = to_xm[s8][t]) != 0.0) atomicAdd(lS + s8 * pl - 1, v);
+    if (tx == 63 && (v = to_xp[s8][t]) != 0.0) atomicAdd(lS + s8 * pl + 1, v);
+    if (ty == 0 && (v = to_ym[s8][t]) != 0.0) atomicAdd(lS + py * pl - g.pitch, v);
+    if (ty == 3 && (v = to_yp[s8][t]) != 0.0) atomicAdd(lS + py * pl + g.pitch, v);
   }
-  for (int c = 0; c < 4; ++c) {
-    if (Wb[c] != 0.0) atomicAdd(lS + c * pl, Wb[c]);
-    // derivative reconstructions along x and y
-    for (int a = 0; a < 2; ++a) {
-      const double la = a == 0 ? Wxb[c] : Wyb[c];
-      if (la == 0.0) continue;
-      const long st = a == 0 ? 1 : g.pitch;
-      const double* w = B + c * pl + o;
-      const double* x = B + ((a == 0 ? 4 : 8) + c) * pl + o;
-      const double q[3] = {w[-st], w[0], w[st]}, xv[3] = {x[-st], x[0], x[st]};
-      double qb[3] = {0, 0, 0}, xb[3] = {0, 0, 0};
-      fdk::recon_node_b(k, q, xv, g.h, g.invh, la, qb, xb);
-      for (int m = 0; m < 3; ++m) {
-        if (qb[m] != 0.0) atomicAdd(lS + c * pl + (m - 1) * st, qb[m]);
-        if (xb[m] != 0.0) atomicAdd(lS + ((a == 0 ? 4 : 8) + c) * pl + (m - 1) * st, xb[m]);
-      }
+  // this node's sums (nodes beyond the computed range hold what a computed neighbour handed over, or nothing)
+  if (i > g.nx + w || j > g.ny + w) return;
+  for (int p = 0; p < 12; ++p) {
+    double v = own[p][t];
+    if (p < 8) {
+      if (tx > 0) v += to_xp[p][t - 1];
+      if (tx < 63) v += to_xm[p][t + 1];
     }
+    if (p < 4 || p >= 8) {
+      const int s8 = p < 4 ? p : p - 4;
+      if (ty > 0) v += to_yp[s8][t - 64];
+      if (ty < 3) v += to_ym[s8][t + 64];
+    }
+    if (v != 0.0) atomicAdd(lS + p * pl, v);
   }
 }
 

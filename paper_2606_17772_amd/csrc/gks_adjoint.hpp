@@ -14,6 +14,15 @@
 
 namespace fdk {
 
+// The reverse of the kinetic solvers below lets the compiler fuse any
+// multiply and add into one FMA (about 11% fewer FP64 instructions in the
+// reverse interface and node sweeps).  Its rounding then differs from the forward
+// solver's in the last bits, which no result depends on: it makes no branch
+// decision (those use the forward solver's own functions).  The GENO and
+// reconstruction reverse further down compares smoothness indicators and keeps
+// the forward code's contraction.
+#pragma clang fp contract(fast)
+
 // Adjoint of the fields of a Prim<double>.
 struct PrimB {
   double rho, irho, U, V, p, i2l, lam;
@@ -771,6 +780,8 @@ FDK_HD void gks_node_b(const Consts& k, const double* W, const double* Wx, const
   mom_common_b(s, K, m, mb, sb);
   prim_b(W, s, k.gamma, sb, Wb);
 }
+
+#pragma clang fp contract(on)
 
 // ------------------------------------------------------------------ GENO
 struct GenoIn {
