@@ -499,9 +499,11 @@ def test_vjp_bounded_device_tensors():
     dev = torch.device("cuda:0")
     tP, tD = pb.step_vjp(dt, [torch.tensor(lamP, device=dev), torch.tensor(lamD, device=dev)])
     assert tP.is_cuda and tuple(tD.shape) == D.shape
-    # atomic scatters: the last bits may differ between calls
-    assert np.allclose(tP.cpu().numpy(), hP, rtol=1e-13, atol=1e-13 * np.abs(hP).max())
-    assert np.allclose(tD.cpu().numpy(), hD, rtol=1e-13, atol=1e-13 * np.abs(hD).max())
+    # the same computation, but the atomic scatters add in a different order on every call: over six repeated
+    # host-array calls of this case the results spread by up to 3e-13 of the largest value (partial sums with
+    # cancellation), so the bar is 1e-12 of it
+    assert np.allclose(tP.cpu().numpy(), hP, rtol=0.0, atol=1e-12 * np.abs(hP).max())
+    assert np.allclose(tD.cpu().numpy(), hD, rtol=0.0, atol=1e-12 * np.abs(hD).max())
 
 
 def test_rollout_bounded_vs_chained_oracle_tangents(oracle):
