@@ -25,6 +25,21 @@ namespace {
 // Gxt[4], Gyt[4] per grid.
 constexpr int OPN = 24;
 
+// The reverse sweeps' tiles in XCD bands, as the forward sweeps': a 1D
+// launch over gx * gy * gz tiles (rounded up to a multiple of 8); tile
+// (bx, by, bz), bz slowest; false for the padding ids.
+struct Tiles3 {
+  int gx, gy, gz;
+};
+__device__ __forceinline__ bool xcd_tile3(const Tiles3& t, int& bx, int& by, int& bz) {
+  int tile;
+  if (!xcd_tile(blockIdx.x, gridDim.x, t.gx * t.gy * t.gz, tile)) return false;
+  bx = tile % t.gx;
+  by = (tile / t.gx) % t.gy;
+  bz = tile / (t.gx * t.gy);
+  return true;
+}
+
 // ---------------------------------------------------------- update^T
 // lam_out: adjoint of the stage output state (24 planes); lam_acc: adjoint
 // of the stage-1 accumulators (stage 1 only).  Writes lam_op (interior) and
@@ -33,11 +48,13 @@ constexpr int OPN = 24;
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_adj_update(const double* __restrict__ lam_out,
                                                     const double* __restrict__ lam_acc, double* __restrict__ lam_op,
-                                                    double* __restrict__ lam_direct, Geo g, Consts k, double dt) {
-  const int grid = blockIdx.z;
+                                                    double* __restrict__ lam_direct, Geo g, Consts k, double dt, Tiles3 tl) {
+  int bx, by, bz;
+  if (!xcd_tile3(tl, bx, by, bz)) return;  // block-uniform
+  const int grid = bz;
   // the nodes the forward update writes: the dual grid starts at -sx, -sy
-  const int i = blockIdx.x * 64 + threadIdx.x - (grid ? g.sx : 0);
-  const int j = blockIdx.y * 4 + threadIdx.y - (grid ? g.sy : 0);
+  const int i = bx * 64 + threadIdx.x - (grid ? g.sx : 0);
+  const int j = by * 4 + threadIdx.y - (grid ? g.sy : 0);
   if (i >= g.nx || j >= g.ny) return;
   const long pl = g.plane, o = at(g, j, i), so = o + (grid ? g.dshift : 0);  // state planes: shifted dual
   const double* lo = lam_out + (long)grid * 12 * pl + so;
@@ -119,10 +136,12 @@ __device__ __forceinline__ double cf_dchi(int variant, double Fm, double Fc, dou
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_adj_assemble(const double* __restrict__ lam_op, const double* __restrict__ E,
                                                       const double* __restrict__ Nb, double* __restrict__ lamE, Geo g,
-                                                      Consts k) {
-  const int fam = blockIdx.z >> 1, G = blockIdx.z & 1;
-  const int i = blockIdx.x * 64 + threadIdx.x + (fam == 0 ? -2 : -1 - g.sx);
-  const int j = blockIdx.y * 4 + threadIdx.y + (fam == 0 ? -1 - g.sy : -2);
+                                                      Consts k, Tiles3 tl) {
+  int bx, by, bz;
+  if (!xcd_tile3(tl, bx, by, bz)) return;  // block-uniform
+  const int fam = bz >> 1, G = bz & 1;
+  const int i = bx * 64 + threadIdx.x + (fam == 0 ? -2 : -1 - g.sx);
+  const int j = by * 4 + threadIdx.y + (fam == 0 ? -1 - g.sy : -2);
   if (i > (fam == 0 ? g.nx : g.nx + 1) || j > (fam == 0 ? g.ny + 1 : g.ny)) return;
   const bool ay = (fam ^ G) != 0;
   const long pl = g.plane, st = ay ? g.pitch : 1, o = at(g, j, i);
@@ -177,11 +196,13 @@ __global__ __launch_bounds__(256) void k_adj_assemble(const double* __restrict__
 // computes.  Only interfaces next to an updated node carry a flux adjoint.
 template <int STAGE>
 __global__ __launch_bounds__(256) void k_adj_nodeflux(const double* __restrict__ lam_op, const double* __restrict__ E,
-                                                      double* __restrict__ lamN, Geo g, Consts k) {
-  const int G = blockIdx.z, w = node_reach(k);
+                                                      double* __restrict__ lamN, Geo g, Consts k, Tiles3 tl) {
+  int bx, by, bz;
+  if (!xcd_tile3(tl, bx, by, bz)) return;  // block-uniform
+  const int G = bz, w = node_reach(k);
   const bool wide = w == 2;
   const int sx = G ? g.sx : 0, sy = G ? g.sy : 0;  // the dual grid starts at -sx, -sy
-  const int i = blockIdx.x * 64 + threadIdx.x - w - sx, j = blockIdx.y * 4 + threadIdx.y - w - sy;
+  const int i = bx * 64 + threadIdx.x - w - sx, j = by * 4 + threadIdx.y - w - sy;
   if (i > g.nx - 1 + w || j > g.ny - 1 + w) return;
   const long pl = g.plane, o = at(g, j, i);
   const double* op = lam_op + (long)G * OPN * pl + o;
@@ -291,14 +312,16 @@ __device__ __forceinline__ void line_adjoint(const double* __restrict__ S, doubl
 // both normals.
 template <int STAGE, bool CHAR>
 __global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__ S, const double* __restrict__ lamE,
-                                                      double* __restrict__ lamS, Geo g, Consts k, double dt) {
+                                                      double* __restrict__ lamS, Geo g, Consts k, double dt, Tiles3 tl) {
   __shared__ double xch[4][4][64];
   __shared__ fdk::SolveIO s_in[256], s_inb[256];
   __shared__ fdk::AccB s_ab[256];
-  const int fam = blockIdx.z;
+  int bx, by, bz;
+  if (!xcd_tile3(tl, bx, by, bz)) return;  // block-uniform
+  const int fam = bz;
   const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1, tid = ty * 64 + tx;
-  const int i = blockIdx.x * 64 + tx + (fam == 0 ? -2 : -1 - g.sx);
-  const int j = blockIdx.y * 2 + (ty >> 1) + (fam == 0 ? -1 - g.sy : -2);
+  const int i = bx * 64 + tx + (fam == 0 ? -2 : -1 - g.sx);
+  const int j = by * 2 + (ty >> 1) + (fam == 0 ? -1 - g.sy : -2);
   const bool valid = i <= (fam == 0 ? g.nx : g.nx + 1) && j <= (fam == 0 ? g.ny + 1 : g.ny);
   const bool swap = fam != G;
   fdk::SolveIO& in = s_in[tid];
@@ -397,13 +420,15 @@ __global__ __launch_bounds__(256, 1) void k_adj_edges(const double* __restrict__
 // only contributions that leave the block go out one by one.
 template <int STAGE, bool CHAR>
 __global__ __launch_bounds__(256) void k_adj_nodes(const double* __restrict__ S, const double* __restrict__ lamN,
-                                                   double* __restrict__ lamS, Geo g, Consts k) {
+                                                   double* __restrict__ lamS, Geo g, Consts k, Tiles3 tl) {
   // [slot][thread]: own[p] = plane p of this node; to_xm / to_xp / to_ym / to_yp [s] = the node at i -/+ 1 or
   // j -/+ 1, plane s for s < 4 (W), else the axis's derivative plane (4 + s along x, 8 + (s - 4) along y)
   __shared__ double own[12][256], to_xm[8][256], to_xp[8][256], to_ym[8][256], to_yp[8][256];
-  const int grid = blockIdx.z, w = node_reach(k), tx = threadIdx.x, ty = threadIdx.y, t = ty * 64 + tx;
-  const int i = blockIdx.x * 64 + tx - w - (grid ? g.sx : 0);
-  const int j = blockIdx.y * 4 + ty - w - (grid ? g.sy : 0);
+  int bx, by, bz;
+  if (!xcd_tile3(tl, bx, by, bz)) return;  // block-uniform
+  const int grid = bz, w = node_reach(k), tx = threadIdx.x, ty = threadIdx.y, t = ty * 64 + tx;
+  const int i = bx * 64 + tx - w - (grid ? g.sx : 0);
+  const int j = by * 4 + ty - w - (grid ? g.sy : 0);
   for (int p = 0; p < 12; ++p) own[p][t] = 0.0;
   for (int s8 = 0; s8 < 8; ++s8) { to_xm[s8][t] = 0.0; to_xp[s8][t] = 0.0; to_ym[s8][t] = 0.0; to_yp[s8][t] = 0.0; }
   const long pl = g.plane, o = at(g, j, i);

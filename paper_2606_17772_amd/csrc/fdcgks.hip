@@ -2313,20 +2313,23 @@ fdcgks_status adj_stage(fdcgks_problem* pb, double dt, const double* Sin, const 
   const dim3 blk(64, 4);
   if (STAGE == 2) HIPCHK(pb, hipMemsetAsync(scatter, 0, 24 * g.plane * sizeof(double), pb->stream));
   else HIPCHK(pb, hipMemsetAsync(direct, 0, 24 * g.plane * sizeof(double), pb->stream));
-  // the ranges of the forward launches (bounded axes add the dual grid's boundary nodes)
-  hipLaunchKernelGGL((k_adj_update<STAGE>), dim3(ceil_div(g.nx + g.sx, 64), ceil_div(g.ny + g.sy, 4), 2), blk, 0,
-                     pb->stream, lam_out, lam_acc, pb->Op, direct, g, pb->k, dt);
-  hipLaunchKernelGGL((k_adj_assemble<STAGE>), dim3(ceil_div(g.nx + 3 + g.sx, 64), ceil_div(g.ny + 3 + g.sy, 4), 4),
-                     blk, 0, pb->stream, pb->Op, E, Nb, pb->LE, g, pb->k);
+  // the ranges of the forward launches (bounded axes add the dual grid's boundary nodes), as tiles in XCD
+  // bands (xcd_tile3)
+  auto bands = [](const Tiles3& t) { return dim3(ceil_div(t.gx * t.gy * t.gz, NXCD) * NXCD); };
+  const Tiles3 tu{ceil_div(g.nx + g.sx, 64), ceil_div(g.ny + g.sy, 4), 2};
+  hipLaunchKernelGGL((k_adj_update<STAGE>), bands(tu), blk, 0, pb->stream, lam_out, lam_acc, pb->Op, direct, g, pb->k,
+                     dt, tu);
+  const Tiles3 ta{ceil_div(g.nx + 3 + g.sx, 64), ceil_div(g.ny + 3 + g.sy, 4), 4};
+  hipLaunchKernelGGL((k_adj_assemble<STAGE>), bands(ta), blk, 0, pb->stream, pb->Op, E, Nb, pb->LE, g, pb->k, ta);
   const int w = node_reach(pb->k);  // nodes whose fluxes the forward sweep computes beyond the grid's own
-  const dim3 gn(ceil_div(g.nx + 2 * w + g.sx, 64), ceil_div(g.ny + 2 * w + g.sy, 4), 2);
-  hipLaunchKernelGGL((k_adj_nodeflux<STAGE>), gn, blk, 0, pb->stream, pb->Op, E, pb->LN, g, pb->k);
+  const Tiles3 tn{ceil_div(g.nx + 2 * w + g.sx, 64), ceil_div(g.ny + 2 * w + g.sy, 4), 2};
+  hipLaunchKernelGGL((k_adj_nodeflux<STAGE>), bands(tn), blk, 0, pb->stream, pb->Op, E, pb->LN, g, pb->k, tn);
   const bool chr = pb->prm.recon_vars == FDCGKS_RECON_CHARACTERISTIC;
-  hipLaunchKernelGGL((chr ? k_adj_edges<STAGE, true> : k_adj_edges<STAGE, false>),
-                     dim3(ceil_div(g.nx + 3 + g.sx, 64), ceil_div(g.ny + 3 + g.sy, 2), 2), blk, 0, pb->stream, Sin,
-                     pb->LE, scatter, g, pb->k, dt);
-  hipLaunchKernelGGL((chr ? k_adj_nodes<STAGE, true> : k_adj_nodes<STAGE, false>), gn, blk, 0, pb->stream, Sin,
-                     pb->LN, scatter, g, pb->k);
+  const Tiles3 te{ceil_div(g.nx + 3 + g.sx, 64), ceil_div(g.ny + 3 + g.sy, 2), 2};
+  hipLaunchKernelGGL((chr ? k_adj_edges<STAGE, true> : k_adj_edges<STAGE, false>), bands(te), blk, 0, pb->stream,
+                     Sin, pb->LE, scatter, g, pb->k, dt, te);
+  hipLaunchKernelGGL((chr ? k_adj_nodes<STAGE, true> : k_adj_nodes<STAGE, false>), bands(tn), blk, 0, pb->stream,
+                     Sin, pb->LN, scatter, g, pb->k, tn);
   adj_fold(pb, scatter);
   return launch_check(pb, "adjoint stage");
 }
