@@ -262,13 +262,17 @@ __device__ __forceinline__ void edge_recon(const double* __restrict__ S, const G
 // family's range stay idle but join the barriers) and TY/2 in j.  The
 // partners exchange tangential slopes and blend sums through LDS.  Every
 // thread of the block must call this.
-template <int STAGE, class FT, bool CHAR = false>
+// IN_LOOP (work loops of the persistent batch kernel): the thread indices and
+// block shape as values formed at each call, so that nothing derived from
+// them is hoisted in front of the loop and held through the solve.
+template <int STAGE, class FT, bool CHAR = false, bool IN_LOOP = false>
 __device__ __forceinline__ void edge_block(const double* __restrict__ S, double* __restrict__ E, const Geo& g,
                                            const Consts& k, double dt, int bx, int by, int fam, int ix0) {
   // LDS slots per thread: 0-3 tangential slope, 4-7 Wlt + Wrt, 8-11 Wl + Wr
   __shared__ double xch[12 * 256];
-  const int tx = threadIdx.x, ty = threadIdx.y, G = ty & 1;
-  const int TX = blockDim.x, TY = blockDim.y;
+  int tx = threadIdx.x, ty = threadIdx.y, TX = blockDim.x, TY = blockDim.y;
+  if (IN_LOOP) asm volatile("" : "+v"(tx), "+v"(ty), "+s"(TX), "+s"(TY));
+  const int G = ty & 1;
 #define XCH(c, r) xch[((c) * TY + (r)) * TX + tx]
   const int i = bx * TX + tx + ix0;
   const int j = by * (TY >> 1) + (ty >> 1) + (fam == 0 ? -1 - g.sy : -2);
@@ -1691,8 +1695,11 @@ __global__ __launch_bounds__(256, 2) void k_batch_stage(BArgs a, Consts k) {
     for (int q = blockIdx.x; q < a.n_edge; q += nb) {
       const BItem& w = it[q];
       const BMember& M = a.mem[w.m];
-      edge_block<STAGE, FT, CHAR>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, k, member_dt(a, w.m, k), w.bx, w.by,
-                                  w.z, w.z == 0 ? -2 : -1 - M.g.sx);
+      // the scheme constants as values formed inside the loop (hoisted in front of it, constant expressions of
+      // them would hold registers through the interface solve)
+      const Consts kq = opaque_consts(k);
+      edge_block<STAGE, FT, CHAR, true>(STAGE == 1 ? M.S[a.cur] : M.Sstar, M.E, M.g, kq, member_dt(a, w.m, kq),
+                                        w.bx, w.by, w.z, w.z == 0 ? -2 : -1 - M.g.sx);
     }
   }
   it += a.n_edge;
