@@ -362,18 +362,26 @@ template <int P, int Q, int R, class FT> FDK_HD void muv(const Mom<FT>& m, FT o[
   o[2] = m.mu[P] * m.mv[Q + 1] * xr;
   o[3] = FT(0.5) * ((m.mu[P + 2] * m.mv[Q] + m.mu[P] * m.mv[Q + 2]) * xr + b * xr1);
 }
-// <(s.psi) u^P v^Q psi>
+// <(s.psi) u^P v^Q psi>.  With g = s.psi = s0 + s1 u + s2 v + h3 (u^2 + v^2 +
+// xi^2), h3 = s3 / 2, a moment of g splits into a u part and a v part:
+//   <g u^a v^b> = mv[b] cu(a) + mu[a] cv(b),
+//   cu(a) = (s0 + h3 x2) mu[a] + s1 mu[a+1] + h3 mu[a+2],  cv(b) = s2 mv[b+1] + h3 mv[b+2],
+// and <g u^a v^b xi^2> = x2 <g u^a v^b> + h3 mu[a] mv[b] (x4 - x2^2): six
+// one-dimensional combinations instead of the six moment vectors of psi.
 template <int P, int Q, class FT> FDK_HD void ma(const FT s[4], const Mom<FT>& m, FT o[4]) {
-  FT t0[4], t1[4], t2[4], t3[4], t4[4], t5[4];
-  muv<P, Q, 0>(m, t0);
-  muv<P + 1, Q, 0>(m, t1);
-  muv<P, Q + 1, 0>(m, t2);
-  muv<P + 2, Q, 0>(m, t3);
-  muv<P, Q + 2, 0>(m, t4);
-  muv<P, Q, 1>(m, t5);
-  FT h3 = FT(0.5) * s[3];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) o[i] = s[0] * t0[i] + s[1] * t1[i] + s[2] * t2[i] + h3 * (t3[i] + t4[i] + t5[i]);
+  const FT h3 = FT(0.5) * s[3];
+  const FT c0 = s[0] + h3 * m.x2;
+  const FT u0 = c0 * m.mu[P] + s[1] * m.mu[P + 1] + h3 * m.mu[P + 2];
+  const FT u1 = c0 * m.mu[P + 1] + s[1] * m.mu[P + 2] + h3 * m.mu[P + 3];
+  const FT u2 = c0 * m.mu[P + 2] + s[1] * m.mu[P + 3] + h3 * m.mu[P + 4];
+  const FT v0 = s[2] * m.mv[Q + 1] + h3 * m.mv[Q + 2];
+  const FT v1 = s[2] * m.mv[Q + 2] + h3 * m.mv[Q + 3];
+  const FT v2 = s[2] * m.mv[Q + 3] + h3 * m.mv[Q + 4];
+  o[0] = m.mv[Q] * u0 + m.mu[P] * v0;
+  o[1] = m.mv[Q] * u1 + m.mu[P + 1] * v0;
+  o[2] = m.mv[Q + 1] * u0 + m.mu[P] * v1;
+  const FT gx = m.x2 * o[0] + h3 * (m.mu[P] * m.mv[Q]) * (m.x4 - m.x2 * m.x2);
+  o[3] = FT(0.5) * ((m.mv[Q] * u2 + m.mu[P + 2] * v0) + (m.mv[Q + 2] * u0 + m.mu[P] * v2) + gx);
 }
 // 1D: psi = (1, u, (u^2+xi^2)/2)
 template <int P, int R, class FT> FDK_HD void mu1(const Mom<FT>& m, FT o[3]) {
