@@ -38,7 +38,7 @@ HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doub
 # wave instructions; FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 after the
 # copy-kernel calibration).  Both are None whenever the kernel has changed
 # since the counters were taken.
-FLOPS_PER_IFACE_POINT_STAGE1 = 6251
+FLOPS_PER_IFACE_POINT_STAGE1 = 5618
 TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 4.473e9
 # 3D leg: the stage-1 interface sweep k_edges3d<true,false>, unit one solve
 # (12 per cell), from profiles/k_edges3d_taylor_green128.md (same counters).

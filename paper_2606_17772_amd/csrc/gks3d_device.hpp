@@ -41,21 +41,33 @@ template <int P, int Q, int S, int R> FDK_HD void muvw(const Mom3& m, double o[5
   o[3] = m.mu[P] * m.mv[Q] * m.mw[S + 1] * xr;
   o[4] = 0.5 * ((m.mu[P + 2] * vw + m.mu[P] * m.mv[Q + 2] * m.mw[S] + m.mu[P] * m.mv[Q] * m.mw[S + 2]) * xr + b * xr1);
 }
-// <(s.psi) u^P v^Q w^S psi>
+// <(s.psi) u^P v^Q w^S psi>.  With g = s.psi = s0 + s1 u + s2 v + s3 w +
+// h4 (u^2 + v^2 + w^2 + xi^2), h4 = s4 / 2, a moment of g splits into
+// one-dimensional parts:
+//   <g u^a v^b w^c> = mv[b] mw[c] cu(a) + mu[a] mw[c] cv(b) + mu[a] mv[b] cw(c),
+//   cu(a) = (s0 + h4 x2) mu[a] + s1 mu[a+1] + h4 mu[a+2],
+//   cv(b) = s2 mv[b+1] + h4 mv[b+2],  cw(c) = s3 mw[c+1] + h4 mw[c+2],
+// and <g u^a v^b w^c xi^2> = x2 <g u^a v^b w^c> + h4 mu[a] mv[b] mw[c] (x4 - x2^2).
 template <int P, int Q, int S> FDK_HD void ma(const double s[5], const Mom3& m, double o[5]) {
-  double t0[5], t1[5], t2[5], t3[5], t4[5], t5[5], t6[5], t7[5];
-  muvw<P, Q, S, 0>(m, t0);
-  muvw<P + 1, Q, S, 0>(m, t1);
-  muvw<P, Q + 1, S, 0>(m, t2);
-  muvw<P, Q, S + 1, 0>(m, t3);
-  muvw<P + 2, Q, S, 0>(m, t4);
-  muvw<P, Q + 2, S, 0>(m, t5);
-  muvw<P, Q, S + 2, 0>(m, t6);
-  muvw<P, Q, S, 1>(m, t7);
   const double h4 = 0.5 * s[4];
+  const double c0 = s[0] + h4 * m.x2;
+  double cu[3], cv[3], cw[3];
 #pragma unroll
-  for (int i = 0; i < 5; ++i)
-    o[i] = s[0] * t0[i] + s[1] * t1[i] + s[2] * t2[i] + s[3] * t3[i] + h4 * (t4[i] + t5[i] + t6[i] + t7[i]);
+  for (int d = 0; d < 3; ++d) {
+    cu[d] = c0 * m.mu[P + d] + s[1] * m.mu[P + d + 1] + h4 * m.mu[P + d + 2];
+    cv[d] = s[2] * m.mv[Q + d + 1] + h4 * m.mv[Q + d + 2];
+    cw[d] = s[3] * m.mw[S + d + 1] + h4 * m.mw[S + d + 2];
+  }
+  // <g u^(P+a) v^(Q+b) w^(S+c)>
+  auto G = [&](int a, int b, int c) {
+    return m.mv[Q + b] * m.mw[S + c] * cu[a] + m.mu[P + a] * m.mw[S + c] * cv[b] + m.mu[P + a] * m.mv[Q + b] * cw[c];
+  };
+  o[0] = G(0, 0, 0);
+  o[1] = G(1, 0, 0);
+  o[2] = G(0, 1, 0);
+  o[3] = G(0, 0, 1);
+  const double gx = m.x2 * o[0] + h4 * (m.mu[P] * m.mv[Q] * m.mw[S]) * (m.x4 - m.x2 * m.x2);
+  o[4] = 0.5 * ((G(2, 0, 0) + G(0, 2, 0)) + (G(0, 0, 2) + gx));
 }
 
 struct Prim {

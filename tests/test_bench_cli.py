@@ -18,10 +18,11 @@ def test_roofline_constants():
     sys.path.insert(0, ROOT)
     import bench
     assert bench.PEAK_FP64_TFLOPS == 78.6
-    # counted flop per interface point, and the calibrated bytes of one launch
-    # (state read plus interface results written: at least the algorithmic
-    # 0.81 + 3.36 GB of the 2048^2 workload)
-    assert 6000 < bench.FLOPS_PER_IFACE_POINT_STAGE1 < 8000
+    # counted flop per interface point (about 5.6k since the solver's moment
+    # products are evaluated as one-dimensional combinations), and the
+    # calibrated bytes of one launch (state read plus interface results
+    # written: at least the algorithmic 0.81 + 3.36 GB of the 2048^2 workload)
+    assert 5000 < bench.FLOPS_PER_IFACE_POINT_STAGE1 < 8000
     assert 4.17e9 <= bench.TRAFFIC_BYTES_PER_LAUNCH_STAGE1 < 6e9
 
 
