@@ -42,7 +42,7 @@ FLOPS_PER_IFACE_POINT_STAGE1 = 5618
 TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 4.473e9
 # 3D leg: the stage-1 interface sweep k_edges3d<true,false>, unit one solve
 # (12 per cell), from profiles/k_edges3d_taylor_green128.md (same counters).
-FLOPS_PER_SOLVE_3D_STAGE1 = 5787
+FLOPS_PER_SOLVE_3D_STAGE1 = 4797
 
 
 # Launch shapes fdcgks_autotune picks on this workload (interface sweep,
