@@ -30,14 +30,21 @@ MU, PR = 1e-4, 0.72
 PEAK_FP64_TFLOPS = 78.6        # MI355X FP64 vector peak
 PEAK_HBM_GBS = 8000.0          # MI355X HBM3E
 HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doubles, stage 2 reads 24 / writes 12
-# Dominant kernel: the stage-1 interface sweep k_edges2d<1,double,false>.  Unit of
-# work: one interface point (two GENO line reconstructions, two gas-kinetic
-# solves, the blend); one launch processes 2 (n+3)^2 of them.  FP64 flops per
-# point and HBM bytes per launch are from the rocprofv3 counters of this
-# kernel (profiles/k_edges2d_shear2048.md: 64 x (ADD + MUL + 2 FMA + TRANS)
-# wave instructions; FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 after the
-# copy-kernel calibration).  Both are None whenever the kernel has changed
-# since the counters were taken.
+# Dominant kernel of the default stage: k_fused2d<1,double,false>, the stage-1
+# interface sweep fused with the update.  Unit of work: one node update (its
+# share of the interface points, each two GENO line reconstructions, two
+# gas-kinetic solves and the blend, plus the compact-flux assembly and the
+# S2O4 update); one launch updates 2 n^2 nodes.  FP64 flops per node and HBM
+# bytes per launch are from the rocprofv3 counters of this kernel
+# (profiles/k_fused2d_shear2048.md: 64 x (ADD + MUL + 2 FMA + TRANS) wave
+# instructions; FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 after the copy-kernel
+# calibration).  Both are None whenever the kernel has changed since the
+# counters were taken.
+FLOPS_PER_NODE_FUSED_STAGE1 = None
+TRAFFIC_BYTES_PER_LAUNCH_FUSED_STAGE1 = None
+# With --separate: the stage-1 interface sweep k_edges2d<1,double,false>, unit
+# one interface point, 2 (n+3)^2 per launch (profiles/k_edges2d_shear2048.md,
+# same counters).
 FLOPS_PER_IFACE_POINT_STAGE1 = 5618
 TRAFFIC_BYTES_PER_LAUNCH_STAGE1 = 4.473e9
 # 3D leg: the stage-1 interface sweep k_edges3d<true,false>, unit one solve
@@ -67,6 +74,8 @@ def parse():
     ap.add_argument("--tiles", default=DEFAULT_TILES,
                     help="launch shapes kernel=XxY,... (default: the autotuner's pick at 2048^2)")
     ap.add_argument("--autotune", action="store_true", help="run fdcgks_autotune instead of --tiles")
+    ap.add_argument("--separate", action="store_true",
+                    help="run the separate interface sweep, node sweep and update (no fused stage kernel)")
     ap.add_argument("--no-graph", action="store_true", help="skip the small-problem graph-replay comparison")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-flux variant comparison")
     ap.add_argument("--no-char", action="store_true",
@@ -685,6 +694,8 @@ def main():
     pr = WL.shear_layer(n, seed=0, mu=MU, prandtl=PR)
     prm = make_params(dim=2, nx=n, ny=n, lx=1.0, ly=1.0, mu=MU, prandtl=PR)
     pb = Problem(prm)
+    if args.separate:
+        pb.fuse_stage = False  # otherwise the default: the fused stage kernel at this size
     dev = torch.device("cuda:0")
     # inputs resident in HBM before timing
     for g, S in ((0, pr.P), (1, pr.D)):
@@ -717,18 +728,26 @@ def main():
     # per-kernel breakdown on the same stream (separate, untimed-for-value run)
     _, _, kms = pb.step_timed(nsteps=max(2, args.steps // 4), cfl=CFL, t=t)
     kn = max(2, args.steps // 4)
-    edge1_ms = kms["edge1"] / kn
-    iface_points = 2 * (n + 3) * (n + 3)
-    if FLOPS_PER_IFACE_POINT_STAGE1:
-        flops = FLOPS_PER_IFACE_POINT_STAGE1 * iface_points
-        achieved = flops / (edge1_ms * 1e-3) / 1e12
+    fused = kms["edge1"] == 0.0  # no separate interface sweep ran
+    if fused:
+        # the fused kernel's launches are timed under the update slot
+        launch_ms = kms["update1"] / kn
+        flops_per_unit, units, traffic = FLOPS_PER_NODE_FUSED_STAGE1, 2 * n * n, TRAFFIC_BYTES_PER_LAUNCH_FUSED_STAGE1
+        kernel = "k_fused2d<1,double,false> (stage-1 interface sweep fused with the update)"
+    else:
+        launch_ms = kms["edge1"] / kn
+        flops_per_unit, units, traffic = FLOPS_PER_IFACE_POINT_STAGE1, 2 * (n + 3) * (n + 3), \
+            TRAFFIC_BYTES_PER_LAUNCH_STAGE1
+        kernel = "k_edges2d<1,double,false> (stage-1 interface sweep)"
+    if flops_per_unit:
+        achieved = flops_per_unit * units / (launch_ms * 1e-3) / 1e12
         roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": TRAFFIC_BYTES_PER_LAUNCH_STAGE1}
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic}
     else:
         roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s", "frac": None,
                 "traffic": None}
-    roof["kernel"] = "k_edges2d<1,double,false> (stage-1 interface sweep)"
-    roof["avg_launch_ms"] = round(edge1_ms, 4)
+    roof["kernel"] = kernel
+    roof["avg_launch_ms"] = round(launch_ms, 4)
     hbm_gbs = value * HBM_BYTES_PER_NODE_STAGE / 1e9
     out = {
         "metric": "node-updates/s per stage (FP64, 1 GPU)",
@@ -745,7 +764,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"2D Navier-Stokes double shear layer {n}x{n} primary + dual, Re=1e4, Pr=0.72, "
                                "CFL 0.5, (6-4) GENO, FP64", "nodes_per_stage": nodes, "stages_per_step": 2,
-                   "launch_shapes": {k2: f"{x}x{y}" for k2, (x, y) in tiles.items()}, "step_graphs": True},
+                   "launch_shapes": {k2: f"{x}x{y}" for k2, (x, y) in tiles.items()}, "step_graphs": True,
+                   "stage": "fused" if fused else "separate"},
         "roofline": roof,
         "hbm_roofline": {"algorithmic_bytes_per_node_stage": HBM_BYTES_PER_NODE_STAGE,
                          "achieved_GBs": round(hbm_gbs, 1), "peak_GBs": PEAK_HBM_GBS,

@@ -278,13 +278,18 @@ fdcgks_status fdcgks_debug_intermediates(fdcgks_problem* pb, double dt, double* 
  * problems with flux_order 6 only: bounded problems and the order-8 flux
  * (which reads nodal fluxes two nodes away) keep the separate sweep.  The
  * diagnostics and the step adjoint always use the separate sweep.
- * FDCGKS_OPT_FUSE_STAGE (default 0): 1 makes 2D steps run the node sweep and
+ * FDCGKS_OPT_FUSE_STAGE (default 2): 1 makes 2D steps run the node sweep and
  * then one kernel that marches up strips of node columns, evaluating each
  * row of interface points (reconstruction, gas-kinetic solver, blend of
  * Eq. W-model-2d) and assembling and updating the nodes as soon as their
  * interfaces exist; interface results stay in registers and LDS (no
- * interface buffer).  Bitwise the same results.  Periodic problems with
- * flux_order 6; it takes precedence over FDCGKS_OPT_FUSE_NODES.
+ * interface buffer).  0 runs the separate interface sweep and update
+ * through the interface buffer (the interface and update launch shapes then
+ * apply).  2 chooses the fused kernel where its row chunks are tall, i.e.
+ * ny * ceil(nx / 61) >= 128 * (compute units): 2048^2 and up on MI355X.
+ * Bitwise the same results.  Periodic problems with flux_order 6 (the others
+ * always take the separate sweeps); it takes precedence over
+ * FDCGKS_OPT_FUSE_NODES.
  * FDCGKS_OPT_FUSED_ROWS (default 0): node rows per block of that kernel;
  * 0 chooses about two blocks per compute unit.
  * EINVAL for an unknown option or an invalid value. */

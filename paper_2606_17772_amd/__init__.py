@@ -350,14 +350,15 @@ class Problem:
 
     @property
     def fuse_stage(self):
-        """Interface sweep and update in one marching kernel (2D steps)."""
+        """Interface sweep and update in one marching kernel (2D steps):
+        False / 0 off, True / 1 on, 2 (the default) where it pays."""
         v = C.c_int64()
         self._chk(self._L.fdcgks_get_option(self._h, _lib.OPT_FUSE_STAGE, C.byref(v)))
-        return bool(v.value)
+        return int(v.value)
 
     @fuse_stage.setter
-    def fuse_stage(self, on):
-        self._chk(self._L.fdcgks_set_option(self._h, _lib.OPT_FUSE_STAGE, 1 if on else 0))
+    def fuse_stage(self, mode):
+        self._chk(self._L.fdcgks_set_option(self._h, _lib.OPT_FUSE_STAGE, int(mode)))
 
     @property
     def fused_rows(self):

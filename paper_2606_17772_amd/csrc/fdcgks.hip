@@ -1874,7 +1874,7 @@ struct fdcgks_problem {
   // captured whole steps (one graph per ping-pong parity), replayed by fdcgks_step
   int graph_steps = 16;  // steps per captured graph; 0: separate launches
   bool fuse_nodes = false;  // node sweep inside the update kernel
-  bool fuse_stage = false;  // interface sweep and update in one marching kernel (k_fused2d)
+  int fuse_stage = 2;       // interface sweep and update in one marching kernel (k_fused2d): 0 off, 1 on, 2 auto
   int fused_rows = 0;       // node rows per block of k_fused2d (0: from the CU count)
   int ncu = 256;            // compute units of the device
   bool cfl_fold = false;    // the stage-2 update being launched folds the CFL partials
@@ -2023,9 +2023,18 @@ void launch_fused(fdcgks_problem* pb, const double* Sin, const double* Ain, doub
 // fused with the update after the node sweep.  Both fusions need periodic
 // axes and the order-6 flux; otherwise the separate kernels run.
 enum { STAGE_SEPARATE = 0, STAGE_FUSE_NODES = 1, STAGE_FUSE_IFACE = 2 };
+// Whether the fused stage kernel beats the separate sweeps (the automatic
+// choice): its blocks march the rows of one strip of columns in lock step,
+// so it needs tall row chunks at about two blocks per compute unit, here at
+// least 64 rows each.  Measured: 2048^2 5.42 against 5.92 ms per step; 512^2
+// 0.72 against 0.52 ms (16-row chunks).
+bool fused_pays(const fdcgks_problem* pb) {
+  const long strips = ceil_div(pb->g.nx, FS_W);
+  return (long)pb->g.ny * strips >= 64L * 2 * pb->ncu;
+}
 int stage_mode(const fdcgks_problem* pb) {
   if ((pb->g.sx | pb->g.sy) || pb->k.flux_order == 8 || pb->prm.dim != 2) return STAGE_SEPARATE;
-  if (pb->fuse_stage) return STAGE_FUSE_IFACE;
+  if (pb->fuse_stage == 1 || (pb->fuse_stage == 2 && fused_pays(pb))) return STAGE_FUSE_IFACE;
   return pb->fuse_nodes ? STAGE_FUSE_NODES : STAGE_SEPARATE;
 }
 
@@ -2918,8 +2927,8 @@ fdcgks_status fdcgks_set_option(fdcgks_problem* pb, int32_t option, int64_t valu
       graph_invalidate(pb);
       return FDCGKS_OK;
     case FDCGKS_OPT_FUSE_STAGE:
-      if (value != 0 && value != 1) return fail(pb, FDCGKS_EINVAL, "stage-fusion option must be 0 or 1");
-      pb->fuse_stage = value != 0;
+      if (value < 0 || value > 2) return fail(pb, FDCGKS_EINVAL, "stage-fusion option must be 0, 1 or 2");
+      pb->fuse_stage = (int)value;
       graph_invalidate(pb);
       return FDCGKS_OK;
     case FDCGKS_OPT_FUSED_ROWS:
@@ -2955,7 +2964,7 @@ fdcgks_status fdcgks_get_option(const fdcgks_problem* cpb, int32_t option, int64
     return FDCGKS_OK;
   }
   if (option == FDCGKS_OPT_FUSE_STAGE) {
-    *value = pb->fuse_stage ? 1 : 0;
+    *value = pb->fuse_stage;
     return FDCGKS_OK;
   }
   if (option == FDCGKS_OPT_FUSED_ROWS) {

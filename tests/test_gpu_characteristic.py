@@ -114,6 +114,7 @@ def test_captured_and_fused_steps_char(oracle):
     b.step(nsteps=5, cfl=0.5)
     c = _problem(s, pr.P, pr.D)
     c.use_graph = False
+    c.fuse_stage = False  # the stage fusion takes precedence over the node fusion
     c.fuse_nodes = True
     c.step(nsteps=5, cfl=0.5)
     for g in (0, 1):

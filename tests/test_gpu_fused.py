@@ -115,3 +115,30 @@ def test_fused_option_rejected_where_it_does_not_apply():
     b.step(nsteps=2, cfl=0.4)
     for g in (0, 1):
         assert np.array_equal(a.get_state_stacked(g), b.get_state_stacked(g))
+
+
+def test_automatic_stage_choice():
+    """The default (2) takes the separate sweeps where the fused kernel's row
+    chunks would be short (a small grid: the per-kernel timing shows an
+    interface sweep) and the fused kernel where they are tall (2048^2: no
+    separate interface sweep); 1 forces the fused kernel; other values are
+    rejected."""
+    from paper_2606_17772_amd import Problem
+    s, pr = CASES["vortex_40"]()
+    pb = _problem(s, pr.P, pr.D, 2)
+    assert pb.fuse_stage == 2
+    _, _, kms = pb.step_timed(nsteps=1, cfl=0.5)
+    assert kms["edge1"] > 0.0
+    pb.fuse_stage = 1
+    _, _, kms = pb.step_timed(nsteps=1, cfl=0.5)
+    assert kms["edge1"] == 0.0 and kms["update1"] > 0.0
+    with pytest.raises(RuntimeError):
+        pb.fuse_stage = 3
+    n = 2048
+    big = Problem(gpu_params(settings(dim=2, nx=n, ny=n, lx=1.0)))
+    big.set_state_stacked(0, np.stack([np.ones((n, n)), np.zeros((n, n)), np.zeros((n, n)), 2.5 * np.ones((n, n))] +
+                                      [np.zeros((n, n))] * 8))
+    big.set_state_stacked(1, np.stack([np.ones((n, n)), np.zeros((n, n)), np.zeros((n, n)), 2.5 * np.ones((n, n))] +
+                                      [np.zeros((n, n))] * 8))
+    _, _, kms = big.step_timed(nsteps=1, cfl=0.5)
+    assert kms["edge1"] == 0.0 and kms["update1"] > 0.0

@@ -74,6 +74,7 @@ def test_fused_node_sweep_is_bitwise_equal(case):
     s, pr = _cases()[case]
     a = _problem(s, pr)
     b = _problem(s, pr)
+    a.fuse_stage = b.fuse_stage = False  # the stage fusion takes precedence over the node fusion
     b.fuse_nodes = True
     assert b.fuse_nodes and not a.fuse_nodes
     for rep in range(3):
