@@ -40,8 +40,8 @@ HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doub
 # instructions; FETCH_SIZE x 2.000 + WRITE_SIZE x 1.000 after the copy-kernel
 # calibration).  Both are None whenever the kernel has changed since the
 # counters were taken.
-FLOPS_PER_NODE_FUSED_STAGE1 = None
-TRAFFIC_BYTES_PER_LAUNCH_FUSED_STAGE1 = None
+FLOPS_PER_NODE_FUSED_STAGE1 = 6344
+TRAFFIC_BYTES_PER_LAUNCH_FUSED_STAGE1 = 5.226e9
 # With --separate: the stage-1 interface sweep k_edges2d<1,double,false>, unit
 # one interface point, 2 (n+3)^2 per launch (profiles/k_edges2d_shear2048.md,
 # same counters).

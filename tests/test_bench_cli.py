@@ -54,3 +54,19 @@ def test_3d_flop_constant_comes_from_the_committed_profile():
     cells = [c.strip() for c in rows[0].strip().strip("|").split("|")]
     assert bench.FLOPS_PER_SOLVE_3D_STAGE1 == int(cells[4])
     assert re.search(r"12 interface solves per cell", txt)
+
+
+def test_fused_roofline_constants_come_from_the_committed_profile():
+    """The default stage's dominant kernel (the fused interface sweep and
+    update): flop per node update and calibrated bytes per launch as the
+    committed rocprofv3 summary records them."""
+    sys.path.insert(0, ROOT)
+    import bench
+    txt = open(os.path.join(ROOT, "profiles", "k_fused2d_shear2048.md")).read()
+    rows = [ln for ln in txt.splitlines() if ln.startswith("| `k_fused2d<1, double, false>`") and ln.count("|") >= 8]
+    assert rows, "counter row of the stage-1 fused kernel"
+    cells = [c.strip() for c in rows[0].strip().strip("|").split("|")]
+    assert bench.FLOPS_PER_NODE_FUSED_STAGE1 == int(cells[4])
+    read_gb, written_gb = float(cells[5]), float(cells[6])
+    assert abs(bench.TRAFFIC_BYTES_PER_LAUNCH_FUSED_STAGE1 - (read_gb + written_gb) * 1e9) <= 2e6
+    assert "2 n^2" in txt
