@@ -3,7 +3,7 @@
 tests/opcount_iface.cpp runs the library's own reconstruction and
 gas-kinetic solver templates on the host with a counting scalar, for one
 interface point (two solves).  The counts put the roofline's flop figure in
-context: the benchmark divides the FP64 operations the GPU executes (6,251
+context: the benchmark divides the FP64 operations the GPU executes (5,618
 per point, hardware counters, FMA = 2) by the launch time; the source-level
 count of the same arithmetic is higher, because the compiler folds constants
 and shares subexpressions that the source repeats."""
@@ -52,5 +52,9 @@ def test_arithmetic_count(counts):
     # conversions (1/rho, 1/p), one in the collision time (the pressure-jump
     # ratio) and two in the time coefficients
     assert s["div"] == 2 * (3 * 2 + 1 + 2)
-    # above the executed FP64 count of the GPU build (6,251 flop per point)
-    assert 6251 < s["arith"] < 15000
+    # above the executed FP64 count of the GPU build (the separate interface
+    # sweep's counted flop per point, as the benchmark uses it)
+    import sys
+    sys.path.insert(0, os.path.dirname(HERE))
+    import bench
+    assert bench.FLOPS_PER_IFACE_POINT_STAGE1 < s["arith"] < 15000
