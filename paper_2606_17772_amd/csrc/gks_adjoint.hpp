@@ -143,34 +143,65 @@ FDK_HD void muv_b(const Mom<double>& m, const double ob[4], Mom<double>& mb) {
   }
 }
 
-// o = <(s.psi) u^P v^Q psi>
+// o = <(s.psi) u^P v^Q psi>: reverse of the one-dimensional combinations of
+// ma (cu, cv and the xi^2 row; see ma in gks_device.hpp).
 template <int P, int Q>
 FDK_HD void ma_b(const double s[4], const Mom<double>& m, const double ob[4], double sb[4], Mom<double>& mb) {
-  double t0[4], t1[4], t2[4], t3[4], t4[4], t5[4];
-  muv<P, Q, 0>(m, t0);
-  muv<P + 1, Q, 0>(m, t1);
-  muv<P, Q + 1, 0>(m, t2);
-  muv<P + 2, Q, 0>(m, t3);
-  muv<P, Q + 2, 0>(m, t4);
-  muv<P, Q, 1>(m, t5);
-  double o0[4], o1[4], o2[4], oh[4];
+  const double h3 = 0.5 * s[3];
+  const double c0 = s[0] + h3 * m.x2;
+  double u[3], v[3];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    sb[0] += t0[i] * ob[i];
-    sb[1] += t1[i] * ob[i];
-    sb[2] += t2[i] * ob[i];
-    sb[3] += 0.5 * (t3[i] + t4[i] + t5[i]) * ob[i];
-    o0[i] = s[0] * ob[i];
-    o1[i] = s[1] * ob[i];
-    o2[i] = s[2] * ob[i];
-    oh[i] = 0.5 * s[3] * ob[i];
+  for (int d = 0; d < 3; ++d) {
+    u[d] = c0 * m.mu[P + d] + s[1] * m.mu[P + d + 1] + h3 * m.mu[P + d + 2];
+    v[d] = s[2] * m.mv[Q + d + 1] + h3 * m.mv[Q + d + 2];
   }
-  muv_b<P, Q, 0>(m, o0, mb);
-  muv_b<P + 1, Q, 0>(m, o1, mb);
-  muv_b<P, Q + 1, 0>(m, o2, mb);
-  muv_b<P + 2, Q, 0>(m, oh, mb);
-  muv_b<P, Q + 2, 0>(m, oh, mb);
-  muv_b<P, Q, 1>(m, oh, mb);
+  const double o0 = m.mv[Q] * u[0] + m.mu[P] * v[0];
+  const double D = m.x4 - m.x2 * m.x2, muv = m.mu[P] * m.mv[Q];
+  // o3 = (mv[Q] u2 + mu[P+2] v0 + mv[Q+2] u0 + mu[P] v2 + gx) / 2,  gx = x2 o0 + h3 mu[P] mv[Q] D
+  const double t = 0.5 * ob[3];
+  double ub[3], vb[3];
+  ub[2] = t * m.mv[Q];
+  vb[2] = t * m.mu[P];
+  mb.mv[Q] += t * u[2];
+  mb.mu[P + 2] += t * v[0];
+  mb.mv[Q + 2] += t * u[0];
+  mb.mu[P] += t * v[2];
+  const double o0b = ob[0] + t * m.x2;
+  double x2b = t * o0, h3b = t * muv * D;
+  const double Db = t * h3 * muv;
+  mb.mu[P] += t * h3 * m.mv[Q] * D;
+  mb.mv[Q] += t * h3 * m.mu[P] * D;
+  mb.x4 += Db;
+  x2b -= 2.0 * m.x2 * Db;
+  // o2 = mv[Q+1] u0 + mu[P] v1;  o1 = mv[Q] u1 + mu[P+1] v0;  o0 = mv[Q] u0 + mu[P] v0
+  ub[0] = ob[2] * m.mv[Q + 1] + o0b * m.mv[Q] + t * m.mv[Q + 2];
+  vb[1] = ob[2] * m.mu[P];
+  ub[1] = ob[1] * m.mv[Q];
+  vb[0] = ob[1] * m.mu[P + 1] + o0b * m.mu[P] + t * m.mu[P + 2];
+  mb.mv[Q + 1] += ob[2] * u[0];
+  mb.mu[P] += ob[2] * v[1] + o0b * v[0];
+  mb.mv[Q] += ob[1] * u[1] + o0b * u[0];
+  mb.mu[P + 1] += ob[1] * v[0];
+  // u_d = c0 mu[P+d] + s1 mu[P+d+1] + h3 mu[P+d+2];  v_d = s2 mv[Q+d+1] + h3 mv[Q+d+2]
+  double c0b = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    c0b += ub[d] * m.mu[P + d];
+    sb[1] += ub[d] * m.mu[P + d + 1];
+    h3b += ub[d] * m.mu[P + d + 2] + vb[d] * m.mv[Q + d + 2];
+    sb[2] += vb[d] * m.mv[Q + d + 1];
+    mb.mu[P + d] += ub[d] * c0;
+    mb.mu[P + d + 1] += ub[d] * s[1];
+    mb.mu[P + d + 2] += ub[d] * h3;
+    mb.mv[Q + d + 1] += vb[d] * s[2];
+    mb.mv[Q + d + 2] += vb[d] * h3;
+  }
+  // c0 = s0 + h3 x2,  h3 = s3 / 2
+  sb[0] += c0b;
+  h3b += c0b * m.x2;
+  x2b += c0b * h3;
+  mb.x2 += x2b;
+  sb[3] += 0.5 * h3b;
 }
 
 // <psi> and <u psi>
