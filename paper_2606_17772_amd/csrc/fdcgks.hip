@@ -825,15 +825,16 @@ __device__ __forceinline__ void fused_iface(const double* __restrict__ S, const 
 
 // S2O4 update of node (i, j) of `grid` from its complete L (and Lt) per
 // component (the gradients are written by the caller), with the
-// non-physical check and the CFL contribution of update_node.
+// non-physical check and the CFL contribution of update_node.  pre[c] is the
+// node's state component c (stage 1) or its stage-1 accumulator (stage 2),
+// loaded by the caller together with the row's other operands.
 template <int STAGE>
-__device__ __forceinline__ void fused_node_update(const double* __restrict__ S, const double* __restrict__ Ain,
-                                                  double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
+__device__ __forceinline__ void fused_node_update(double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
                                                   const Consts& k, double dt, int i, int j, int grid,
-                                                  const double (&L)[4], const double (&Lt)[4], Scal* sc,
-                                                  bool want_cfl, double& cfl_s, double& cfl_r) {
+                                                  const double (&pre)[4], const double (&L)[4],
+                                                  const double (&Lt)[4], Scal* sc, bool want_cfl, double& cfl_s,
+                                                  double& cfl_r) {
   const long pl = g.plane, o = at(g, j, i);
-  const double* s = S + (long)grid * 12 * pl + o;
   double* out = Out + (long)grid * 12 * pl + o;
   double rho = 0.0, mom2 = 0.0, ener = 0.0, mU = 0.0, mV = 0.0;
 #pragma unroll
@@ -841,12 +842,11 @@ __device__ __forceinline__ void fused_node_update(const double* __restrict__ S, 
     double W;
     if (STAGE == 1) {
       double* ao = Aout + (long)grid * 12 * pl + o;
-      const double w = s[c * pl];
+      const double w = pre[c];
       W = w + 0.5 * dt * L[c] + 0.125 * dt * dt * Lt[c];
       __builtin_nontemporal_store((double)(w + dt * L[c] + dt * dt / 6.0 * Lt[c]), &ao[c * pl]);
     } else {
-      const double* ai = Ain + (long)grid * 12 * pl + o;
-      W = ai[c * pl] + dt * dt / 3.0 * Lt[c];
+      W = pre[c] + dt * dt / 3.0 * Lt[c];
     }
     __builtin_nontemporal_store((double)(W), &out[c * pl]);
     if (c == 0) rho = W;
@@ -877,11 +877,13 @@ __device__ __forceinline__ void fused_node_update(const double* __restrict__ S, 
 
 // Gradients of node (i, j) of `grid` along axis a from the Gauss differences
 // Gr (stage 1) and Grt, written to Out (and the stage-1 accumulators).
+// pre[c] is the node's carried gradient (stage 1, carried gradients only) or
+// its stage-1 accumulator (stage 2) of component c along a, loaded by the
+// caller (fused_grad_load).
 template <int STAGE>
-__device__ __forceinline__ void fused_grad(const double* __restrict__ S, const double* __restrict__ Ain,
-                                           double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
+__device__ __forceinline__ void fused_grad(double* __restrict__ Out, double* __restrict__ Aout, const Geo& g,
                                            const Consts& k, double dt, int i, int j, int grid, int a,
-                                           const double (&Gr)[4], const double (&Grt)[4]) {
+                                           const double (&pre)[4], const double (&Gr)[4], const double (&Grt)[4]) {
   const long pl = g.plane, o = at(g, j, i);
   const int f = 4 + 4 * a;  // field of the derivative along axis a
   double* out = Out + (long)grid * 12 * pl + o;
@@ -889,17 +891,30 @@ __device__ __forceinline__ void fused_grad(const double* __restrict__ S, const d
   for (int c = 0; c < 4; ++c) {
     double GA;
     if (STAGE == 1) {
-      const double* s = S + (long)grid * 12 * pl + o;
       double* ao = Aout + (long)grid * 12 * pl + o;
-      const double gx = k.grad_carried ? s[(f + c) * pl] : Gr[c];
+      const double gx = k.grad_carried ? pre[c] : Gr[c];
       GA = gx + 0.5 * dt * Grt[c];
       __builtin_nontemporal_store((double)(gx), &ao[(f + c) * pl]);
     } else {
-      const double* ai = Ain + (long)grid * 12 * pl + o;
-      GA = ai[(f + c) * pl] + dt * Grt[c];
+      GA = pre[c] + dt * Grt[c];
     }
     __builtin_nontemporal_store((double)(GA), &out[(f + c) * pl]);
   }
+}
+
+// The stored operands of fused_node_update (fields 0..3) or fused_grad (the
+// derivative fields along axis a) of node (i, j) of `grid`, read when `on`
+// (else zeros): the state at stage 1, the stage-1 accumulators at stage 2.
+// A row's loads are issued together, before any of them is used, so a wave
+// waits for memory once per row rather than once per helper.
+template <int STAGE>
+__device__ __forceinline__ void fused_pre_load(const double* __restrict__ S, const double* __restrict__ Ain,
+                                               const Geo& g, int i, int j, int grid, int field0, bool on,
+                                               double (&pre)[4]) {
+  const long pl = g.plane;
+  const double* p = (STAGE == 1 ? S : Ain) + (long)grid * 12 * pl + at(g, j, i) + field0 * pl;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) pre[c] = on ? p[c * pl] : 0.0;
 }
 
 // Copies of loop-invariant values the compiler cannot see through: formed
@@ -973,7 +988,17 @@ __global__ __launch_bounds__(256, 2) void k_fused2d(const double* __restrict__ S
         // fluxes at P(m), P(m + 1); dual F~(Y m) at D(m - 1), D(m)
         const int m = i;
         const bool need = lane >= 1 && lane <= 62 && (dual ? m <= g.nx : m <= g.nx - 1);
+        const bool upd = lane >= off && lane < off + FS_W && node < g.nx;
+        // every load of the row first: nodal fluxes, then the gradient operands
         const double* nb = Nb + (dual ? 16 * pl : 0) + at(g, J, dual ? m - 1 : m);
+        double nbl[NV], nbr[NV], gpre[4];
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const int qq = STAGE == 1 ? q : 4 + q;  // plane of F (q < 4) or Ft
+          nbl[q] = need ? nb[qq * pl] : 0.0;
+          nbr[q] = need ? nb[qq * pl + 1] : 0.0;
+        }
+        fused_pre_load<STAGE>(S, Ain, g, node, J, dual ? 1 : 0, 4, upd && (STAGE == 2 || k.grad_carried), gpre);
         double Fb[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
@@ -981,7 +1006,7 @@ __global__ __launch_bounds__(256, 2) void k_fused2d(const double* __restrict__ S
           const int c = qq & 3;
           const double f0 = qq < 4 ? v.F[c] : v.Ft[c];
           const double fm = __shfl_up(f0, 1), fp = __shfl_down(f0, 1);
-          Fb[q] = need ? fdk::compact_flux(k.variant, fm, f0, fp, nb[qq * pl], nb[qq * pl + 1], v.chi) : 0.0;
+          Fb[q] = need ? fdk::compact_flux(k.variant, fm, f0, fp, nbl[q], nbr[q], v.chi) : 0.0;
         }
         double Lx[NV];
 #pragma unroll
@@ -1008,11 +1033,11 @@ __global__ __launch_bounds__(256, 2) void k_fused2d(const double* __restrict__ S
             Gr[c] = 0.0;
           }
         }
-        if (lane >= off && lane < off + FS_W && node < g.nx) {
+        if (upd) {
           double* pp = dual ? lds.partD[J % 3] : lds.partP[J & 1];
 #pragma unroll
           for (int q = 0; q < NV; ++q) pp[q * 64 + (node - i0)] = Lx[q];
-          fused_grad<STAGE>(S, Ain, Out, Aout, g, k, dt, node, J, dual ? 1 : 0, 0, Gr, Grt);
+          fused_grad<STAGE>(Out, Aout, g, k, dt, node, J, dual ? 1 : 0, 0, gpre, Gr, Grt);
         }
       }
     } else {
@@ -1027,9 +1052,25 @@ __global__ __launch_bounds__(256, 2) void k_fused2d(const double* __restrict__ S
       // compact flux at row J - 1 of this column: primary F~(Y J-1) between
       // P(J-1), P(J); dual F~(X J-1) between D(J-2), D(J-1)
       const bool flux = dual ? (J >= jlo + 1 && J <= jhi + 1) : (J >= jlo && J <= jhi);
-      if (flux && col) {
-        const int r0 = dual ? J - 2 : J - 1;  // lower node row of the flux
+      const int r0 = dual ? J - 2 : J - 1;  // lower node row of the flux, and the row updated now
+      const int rg_row = dual ? J - 1 : J;  // the row whose y-gradients are formed now
+      const bool do_flux = flux && col, do_upd = do_flux && r0 >= jlo;
+      const bool do_grad = rg_row >= jlo && rg_row < jhi && col;
+      // every load of the row first: nodal fluxes, the update's state or
+      // accumulators, the gradient operands
+      double nbl[NV], nbu[NV], upre[4], gpre[4];
+      {
         const double* nb = Nb + (dual ? 16 * pl : 0) + at(g, r0, i);
+#pragma unroll
+        for (int q = 0; q < NV; ++q) {
+          const int qq = STAGE == 1 ? q : 4 + q;
+          nbl[q] = do_flux ? nb[(8 + qq) * pl] : 0.0;
+          nbu[q] = do_flux ? nb[(8 + qq) * pl + g.pitch] : 0.0;
+        }
+      }
+      fused_pre_load<STAGE>(S, Ain, g, i, r0, dual ? 1 : 0, 0, do_upd, upre);
+      fused_pre_load<STAGE>(S, Ain, g, i, rg_row, dual ? 1 : 0, 8, do_grad && (STAGE == 2 || k.grad_carried), gpre);
+      if (do_flux) {
         double Fb[NV];
 #pragma unroll
         for (int q = 0; q < NV; ++q) {
@@ -1037,10 +1078,9 @@ __global__ __launch_bounds__(256, 2) void k_fused2d(const double* __restrict__ S
           const int c = qq & 3;
           const double f2 = qq < 4 ? v.F[c] : v.Ft[c];
           const double f0 = RING((J & 1) * NV + q), f1 = RING(((J - 1) & 1) * NV + q);
-          Fb[q] = fdk::compact_flux(k.variant, f0, f1, f2, nb[(8 + qq) * pl], nb[(8 + qq) * pl + g.pitch],
-                                    RING(LD::CHI));
+          Fb[q] = fdk::compact_flux(k.variant, f0, f1, f2, nbl[q], nbu[q], RING(LD::CHI));
         }
-        const int ru = dual ? J - 2 : J - 1;  // the row updated now
+        const int ru = r0;
         if (ru >= jlo) {
           const double* pp = dual ? lds.partD[ru % 3] : lds.partP[ru & 1];
           double L[4] = {0, 0, 0, 0}, Lt[4];
@@ -1055,22 +1095,21 @@ __global__ __launch_bounds__(256, 2) void k_fused2d(const double* __restrict__ S
               Lt[q] = Lq;
             }
           }
-          fused_node_update<STAGE>(S, Ain, Out, Aout, g, k, dt, i, ru, dual ? 1 : 0, L, Lt, sc, fold, cfl_s, cfl_r);
+          fused_node_update<STAGE>(Out, Aout, g, k, dt, i, ru, dual ? 1 : 0, upre, L, Lt, sc, fold, cfl_s, cfl_r);
         }
 #pragma unroll
         for (int q = 0; q < NV; ++q) RING(LD::FB + q) = Fb[q];
       }
       // y-gradients of primary row J (W~l(Y J) - W~r(Y J-1)) or dual row J-1
       // (W~l(X J) - W~r(X J-1))
-      const int rg_row = dual ? J - 1 : J;
-      if (rg_row >= jlo && rg_row < jhi && col) {
+      if (do_grad) {
         double Gr[4], Grt[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           Grt[c] = (v.Wlt[c] - RING(LD::WR + (STAGE == 1 ? 4 : 0) + c)) * g.invh;
           Gr[c] = STAGE == 1 ? (v.Wl[c] - RING(LD::WR + c)) * g.invh : 0.0;
         }
-        fused_grad<STAGE>(S, Ain, Out, Aout, g, k, dt, i, rg_row, dual ? 1 : 0, 1, Gr, Grt);
+        fused_grad<STAGE>(Out, Aout, g, k, dt, i, rg_row, dual ? 1 : 0, 1, gpre, Gr, Grt);
       }
       if (valid && col) {
 #pragma unroll
