@@ -41,7 +41,7 @@ HBM_BYTES_PER_NODE_STAGE = 288  # algorithmic: stage 1 reads 12 / writes 24 doub
 # calibration).  Both are None whenever the kernel has changed since the
 # counters were taken.
 FLOPS_PER_NODE_FUSED_STAGE1 = 6344
-TRAFFIC_BYTES_PER_LAUNCH_FUSED_STAGE1 = 5.226e9
+TRAFFIC_BYTES_PER_LAUNCH_FUSED_STAGE1 = 4.981e9
 # With --separate: the stage-1 interface sweep k_edges2d<1,double,false>, unit
 # one interface point, 2 (n+3)^2 per launch (profiles/k_edges2d_shear2048.md,
 # same counters).
