@@ -182,12 +182,20 @@ __global__ __launch_bounds__(EDGE_THREADS, FDCGKS3D_EDGE_WAVES) void k_edges3d(C
     long at[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m) at[m] = cell_along(cell, A, odd_step(A.coord, 2 * m - 3, even));
+    // all 40 stencil values are loaded before the first reconstruction, so a
+    // wave waits for memory once rather than once per component
+    double Q[5][4], X[5][4];
 #pragma unroll
     for (int cc = 0; cc < 5; ++cc) {
       const double* W = Sg + (long)cc * g.n;
-      const double* X = Sg + (long)(5 * (1 + ax) + cc) * g.n;
-      fdk::IfaceRec r = fdk::recon_iface<double>(k, W[at[0]], W[at[1]], W[at[2]], W[at[3]], X[at[0]], X[at[1]],
-                                                 X[at[2]], X[at[3]], g.h, g.invh);
+      const double* Xp = Sg + (long)(5 * (1 + ax) + cc) * g.n;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) { Q[cc][m] = W[at[m]]; X[cc][m] = Xp[at[m]]; }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc) {
+      fdk::IfaceRec r = fdk::recon_iface<double>(k, Q[cc][0], Q[cc][1], Q[cc][2], Q[cc][3], X[cc][0], X[cc][1],
+                                                 X[cc][2], X[cc][3], g.h, g.invh);
       xs[cc][t] = r.vl;
       xs[5 + cc][t] = r.vr;
       xs[10 + cc][t] = r.dl;
