@@ -293,12 +293,19 @@ __global__ __launch_bounds__(NODE_BLOCK, FDCGKS3D_NODE_WAVES) void k_nodes3d(Con
       for (int cc = 0; cc < 5; ++cc) D[ax][lperm(ax, cc)] = d[cc];
       continue;
     }
+    // the axis's 25 stencil values are loaded before the first reconstruction,
+    // so a wave waits for memory once per axis rather than once per component
+    double Wm[5], Wq[5], Xm[5], X0[5], Xq[5];
 #pragma unroll
     for (int cc = 0; cc < 5; ++cc) {
       const double* Wp = Sg + (long)cc * g.n;
       const double* X = Sg + (long)(5 * (1 + ax) + cc) * g.n;
-      D[ax][cc] = fdk::recon_node<double>(k, Wp[am], W[cc], Wp[ap], X[am], X[cell], X[ap], g.h, g.invh);
+      Wm[cc] = Wp[am]; Wq[cc] = Wp[ap];
+      Xm[cc] = X[am]; X0[cc] = X[cell]; Xq[cc] = X[ap];
     }
+#pragma unroll
+    for (int cc = 0; cc < 5; ++cc)
+      D[ax][cc] = fdk::recon_node<double>(k, Wm[cc], W[cc], Wq[cc], Xm[cc], X0[cc], Xq[cc], g.h, g.invh);
   }
   double F[3][5], Ft[3][5];
   fdk3::gks_node<VALUES>(k, W, D[0], D[1], D[2], F, Ft);
